@@ -1,0 +1,188 @@
+/*
+ * emc.h -- C ABI of a gfx950 (MI355X) implementation of one Expand-Maximize-
+ * Compress (EMC) iteration for assembling a 3D Fourier intensity from randomly
+ * oriented 2D diffraction frames, Poisson noise model, covering one GPU's share
+ * of the rotation set.
+ *
+ * The method is that of Ekeberg, Engblom & Liu, "Machine learning for
+ * ultrafast X-ray diffraction patterns on large-scale GPU clusters"
+ * (arXiv:1409.4256): expansion eq. (2.9), E-step eq. (2.4), combined M- and
+ * c-step eq. (2.11)-(2.12), Algorithm 1.  The likelihood is the Poissonian one
+ * the paper names in Section 2.2 (eq. (2.5)/(2.11) with fluence phi = 1):
+ *     Q_jk = sum_{i valid} K_ik log W_ij - W_ij        (log K_ik! dropped).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array pointer is DEVICE memory owned by the caller.  The library
+ *    never allocates; emc_iterate takes a caller workspace sized by
+ *    emc_workspace_bytes.  All work is enqueued asynchronously on `stream`
+ *    (no host synchronisation inside, except emc_pack_frames in BF16 mode,
+ *    which reads back its range flag).
+ *  - Arguments are validated on the host before anything is launched: on a
+ *    negative status nothing has been launched or written, and
+ *    emc_last_error() returns a message (thread-local).  A failed launch maps
+ *    to EMC_ERR_HIP.  Array contents are not validated: any finite input has
+ *    a defined result (non-unit quaternions are normalised, grid points
+ *    outside the N^3 box contribute nothing).
+ *  - Model grid: N^3 float values, flat index l = (x*N + y)*N + z of grid
+ *    point p_l = (x, y, z); pixel coordinate q_i (voxel units) is placed at
+ *    R_j q_i + (N/2, N/2, N/2).  Interpolation weights f (eq. (2.8)) are the
+ *    trilinear tent f(d) = prod_a max(0, 1 - |d_a|), in expansion and
+ *    compression alike.
+ *  - Rotations: quaternions (w, x, y, z), Hamilton convention, active.
+ *  - Row strides: per-pixel rows are padded to emc_pix_stride(n_pix) (a
+ *    multiple of 256) and per-rotation rows to emc_rot_stride(n_rot) (a
+ *    multiple of 256); padding entries are written as zeros.
+ *  - Slices are floored at 1e-10 photons before the log and the sum; masked
+ *    pixels (mask == 0) are excluded from every sum.
+ *  - All 64-bit offsets: n_data * rot_stride and n_rot * pix_stride may
+ *    exceed 2^31.
+ *
+ * Thread safety: entry points are reentrant; calls that share output or
+ * workspace buffers must be ordered by the caller (same stream or events).
+ */
+#ifndef EMC_H
+#define EMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EMC_OK = 0,
+  EMC_ERR_INVALID_ARG = -1, /* bad size, null or misaligned pointer, bad enum */
+  EMC_ERR_RANGE = -2,       /* a photon count does not fit the packed type   */
+  EMC_ERR_WORKSPACE = -3,   /* workspace missing or smaller than required    */
+  EMC_ERR_HIP = -4,         /* a HIP runtime call or kernel launch failed    */
+  EMC_ERR_UNSUPPORTED = -5  /* valid request this build does not implement   */
+} emc_status;
+
+typedef enum {
+  EMC_PREC_FP32 = 0, /* FP32 operands and FP32 MFMA; FP64 normalisation and grid sums */
+  EMC_PREC_BF16 = 1  /* reserved: BF16 MFMA form (not in this build)                  */
+} emc_precision;
+
+typedef enum {
+  EMC_RESP_FULL = 0,     /* per-frame statistics, then P, L and rho             */
+  EMC_RESP_PARTIAL = 1,  /* only the per-frame (max, sum) statistics            */
+  EMC_RESP_FINALIZE = 2  /* P, L and rho from caller-supplied global statistics */
+} emc_resp_mode;
+
+/* Problem description (Section 2.2 notation). */
+typedef struct emc_problem {
+  int32_t grid_n;          /* N: model has N^3 grid points, 2 <= N <= 1024              */
+  int32_t n_pix;           /* Mpix: detector pixels, >= 1                               */
+  int32_t n_rot;           /* Mrot of this share: rotations, >= 1                       */
+  int32_t n_data;          /* Mdata of this call: frames, >= 0                          */
+  int32_t precision;       /* emc_precision                                             */
+  int32_t reserved;        /* must be 0                                                 */
+  const float* q;          /* [n_pix][3] pixel scattering vectors q_i, voxel units      */
+  const uint8_t* mask;     /* [n_pix] 1 = pixel used, 0 = missing or saturated          */
+  const float* quat;       /* [n_rot][4] rotation R_j as quaternion (w, x, y, z)        */
+  const double* log_w;     /* [n_rot] log prior weight log w_j (sum_j w_j = 1 over the  */
+                           /*         full rotation set, Section 2.2)                   */
+} emc_problem;
+
+/* Library version string (static storage). */
+const char* emc_version(void);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* emc_last_error(void);
+
+/* Padded row length of frames, slices and the centring vector: n_pix rounded
+ * up to a multiple of 256 (0 if n_pix < 1). */
+int64_t emc_pix_stride(int32_t n_pix);
+
+/* Padded row length of log-likelihood and responsibility rows: n_rot rounded
+ * up to a multiple of 256 (0 if n_rot < 1). */
+int64_t emc_rot_stride(int32_t n_rot);
+
+/* Bytes of workspace emc_iterate needs for this problem (written to *bytes). */
+emc_status emc_workspace_bytes(const emc_problem* pb, size_t* bytes);
+
+/* Frames K_ik (Section 2.1: photon counts of frame k) -> GEMM operand.
+ *   counts   [n_data][n_pix] uint16 photon counts
+ *   K_packed [n_data][pix_stride] float (FP32 form); masked and padding
+ *            pixels are written as 0.  Counts are exact in FP32.            */
+emc_status emc_pack_frames(const emc_problem* pb, const uint16_t* counts, void* K_packed,
+                           hipStream_t stream);
+
+/* Expansion, eq. (2.9): W_ij = sum_l f(p_l - R_j q_i) model_l, floored at
+ * 1e-10, returned as centred logs.
+ *   model [N^3] float grid values
+ *   c     [pix_stride] double out: centring c_i = mean of log W_ij over a fixed
+ *         subset of at most 64 rotations (j = floor(t*n_rot/n_c)); 0 on
+ *         masked/padding pixels.  Any c leaves the E-step unchanged (a shift
+ *         constant in j); it keeps FP32 sums small.
+ *   logW  [n_rot][pix_stride] float out: log W_ij - c_i, 0 on masked/padding
+ *   S     [n_rot] double out: S_j = sum_{i valid} W_ij                       */
+emc_status emc_expand(const emc_problem* pb, const float* model, double* c, float* logW,
+                      double* S, hipStream_t stream);
+
+/* Poisson log-likelihood, Section 2.2 / eq. (2.3) with the Poisson model, as a
+ * dense contraction over pixels (FP32 MFMA):
+ *   G [n_data][rot_stride] float out: G_kj = sum_i K_ik logW_ji (columns >= n_rot
+ *     are left untouched)
+ *   b [n_data] double out: b_k = sum_i K_ik c_i
+ * so that Q_jk = G_kj + b_k - S_j exactly.                                  */
+emc_status emc_loglik(const emc_problem* pb, const void* K_packed, const float* logW,
+                      const double* c, float* G, double* b, hipStream_t stream);
+
+/* E-step, eq. (2.4), as an FP64 log-sum-exp over rotations of
+ * a_kj = G_kj - S_j + log w_j:
+ *   stats [n_data][2] double: (m_k, s_k) with m_k = max_j a_kj and
+ *         s_k = sum_j exp(a_kj - m_k).  Written in FULL and PARTIAL mode; read
+ *         in FINALIZE mode, where the caller has combined the statistics of
+ *         several rotation shares (m = max m_r, s = sum s_r exp(m_r - m)).
+ *   P     [n_data][rot_stride] float out (FULL, FINALIZE): P_kj = exp(a_kj - m_k -
+ *         log s_k); padding columns written 0.  P may alias G (in place).
+ *   L     [n_data] double out (FULL, FINALIZE): log-evidence
+ *         L_k = m_k + log s_k + b_k (Section 2.2 objective, without log K!).
+ *   rho   [n_rot] double out (FULL, FINALIZE): rho_j = sum_k P_kj (overwritten).
+ * In PARTIAL mode P, L, rho may be NULL.                                     */
+emc_status emc_responsibilities(const emc_problem* pb, const float* G, const double* S,
+                                const double* b, int32_t mode, double* stats, float* P,
+                                double* L, double* rho, hipStream_t stream);
+
+/* Combined M- and c-step, eq. (2.11)-(2.12) with phi = 1, without the final
+ * division:
+ *   Wp  [n_rot][pix_stride] float out: W'_ji = sum_k P_kj K_ik (FP32 MFMA);
+ *       may alias logW of emc_expand (no longer needed by then)
+ *   num, den [N^3] double: num_l += sum_{j,i valid} f(p_l - R_j q_i) W'_ji,
+ *       den_l += sum_{j,i valid} f(p_l - R_j q_i) rho_j (FP64 atomics).
+ *       accumulate == 0 zeroes them first; accumulate != 0 adds, so frame
+ *       chunks (the k-direction split of Section 3.3) sum before division. */
+emc_status emc_compress(const emc_problem* pb, const float* P, const void* K_packed,
+                        const double* rho, float* Wp, double* num, double* den,
+                        int32_t accumulate, hipStream_t stream);
+
+/* Final division of eq. (2.12) and the mean log-evidence of eq. (2.1):
+ *   model_out_l = num_l / den_l where den_l > 0, else model_prev_l
+ *   loglik (device scalar) = sum_k L_k / n_L  (NaN when n_L == 0)
+ * Uses pb->grid_n only.  model_out may alias model_prev.                    */
+emc_status emc_finalize(const emc_problem* pb, const double* num, const double* den,
+                        const float* model_prev, float* model_out, const double* L,
+                        int64_t n_L, double* loglik, hipStream_t stream);
+
+/* One full iteration of Algorithm 1 over this problem's frames:
+ * expand -> log-likelihood -> E-step -> M/c-step -> division.
+ *   model_in  [N^3] float;  model_out [N^3] float (may alias model_in)
+ *   K_packed  output of emc_pack_frames
+ *   loglik    device double scalar: mean log-evidence (see emc_finalize)
+ *   P_out     optional [n_data][rot_stride] float responsibilities; NULL keeps
+ *             them in the workspace
+ *   ws        workspace of at least emc_workspace_bytes bytes, 256-byte aligned */
+emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void* K_packed,
+                       float* model_out, double* loglik, float* P_out, void* ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMC_H */

@@ -1,0 +1,101 @@
+// Device helpers and kernel launchers shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace emc {
+
+constexpr double kFloor = 1e-10;  // photons: slices are floored before log and sum
+
+// Rotation matrix of a (not necessarily unit) quaternion (w, x, y, z), Hamilton
+// convention, active rotation; dividing by |q|^2 normalises it.
+struct Rot {
+  double m[9];
+};
+
+__device__ __forceinline__ Rot quat_rot(const float* __restrict__ qv) {
+  const double w = qv[0], x = qv[1], y = qv[2], z = qv[3];
+  const double s = 2.0 / (w * w + x * x + y * y + z * z);
+  Rot r;
+  r.m[0] = 1.0 - s * (y * y + z * z);
+  r.m[1] = s * (x * y - w * z);
+  r.m[2] = s * (x * z + w * y);
+  r.m[3] = s * (x * y + w * z);
+  r.m[4] = 1.0 - s * (x * x + z * z);
+  r.m[5] = s * (y * z - w * x);
+  r.m[6] = s * (x * z - w * y);
+  r.m[7] = s * (y * z + w * x);
+  r.m[8] = 1.0 - s * (x * x + y * y);
+  return r;
+}
+
+// Trilinear stencil of grid-frame position p: the up to 8 grid points with
+// non-zero tent weight.  Points outside the N^3 box get weight 0 (index 0).
+struct Stencil {
+  int idx[8];
+  double w[8];
+};
+
+__device__ __forceinline__ Stencil stencil_at(const Rot& r, const float* __restrict__ qi, int N) {
+  const double qx = qi[0], qy = qi[1], qz = qi[2];
+  const double h = 0.5 * N;
+  const double px = r.m[0] * qx + r.m[1] * qy + r.m[2] * qz + h;
+  const double py = r.m[3] * qx + r.m[4] * qy + r.m[5] * qz + h;
+  const double pz = r.m[6] * qx + r.m[7] * qy + r.m[8] * qz + h;
+  const double fx0 = floor(px), fy0 = floor(py), fz0 = floor(pz);
+  const int bx = (int)fx0, by = (int)fy0, bz = (int)fz0;
+  const double tx = px - fx0, ty = py - fy0, tz = pz - fz0;
+  Stencil s;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int dx = t >> 2, dy = (t >> 1) & 1, dz = t & 1;
+    const int vx = bx + dx, vy = by + dy, vz = bz + dz;
+    const bool in = (unsigned)vx < (unsigned)N && (unsigned)vy < (unsigned)N && (unsigned)vz < (unsigned)N;
+    const double w = (dx ? tx : 1.0 - tx) * (dy ? ty : 1.0 - ty) * (dz ? tz : 1.0 - tz);
+    s.idx[t] = in ? (vx * N + vy) * N + vz : 0;
+    s.w[t] = in ? w : 0.0;
+  }
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---- launchers (all asynchronous on `st`; return hipGetLastError()) ----
+hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t st);
+hipError_t launch_pack_f32(const uint16_t* counts, const uint8_t* mask, int n_pix, int64_t stride,
+                           int64_t n_data, float* K, hipStream_t st);
+hipError_t launch_centre(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
+                         int n_pix, int64_t stride, int n_rot, double* c, hipStream_t st);
+hipError_t launch_expand(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
+                         int n_pix, int64_t stride, int n_rot, const double* c, float* logW, double* S,
+                         hipStream_t st);
+hipError_t launch_frame_dot(const float* K, int64_t stride, int64_t n_data, const double* c, double* b,
+                            hipStream_t st);
+// C[M][N] = sum_k A(m,k) B(n,k), FP32 MFMA.
+//  NT: A(m,k) = A[m*lda + k], B(n,k) = B[n*ldb + k]; Kd must be a multiple of 32;
+//      rows m >= M and n >= N read as zero.
+//  TN: A(m,k) = A[k*lda + m], B(n,k) = B[k*ldb + n]; rows k >= Kd read as zero;
+//      lda >= roundup(M, 256) and ldb >= roundup(N, 128) (padded columns readable).
+hipError_t launch_gemm_f32_nt(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
+                              int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st);
+hipError_t launch_gemm_f32_tn(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
+                              int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st);
+hipError_t launch_lse_stats(const float* G, int64_t ld, int n_rot, int64_t n_data, const double* log_w,
+                            const double* S, double* stats, hipStream_t st);
+hipError_t launch_lse_write(const float* G, float* P, int64_t ld, int n_rot, int64_t n_data,
+                            const double* log_w, const double* S, const double* stats, const double* b,
+                            double* L, double* rho, hipStream_t st);
+hipError_t launch_scatter(const float* Wp, int64_t stride, const double* rho, const float* q,
+                          const uint8_t* mask, const float* quat, int n_pix, int n_rot, int N, double* num,
+                          double* den, hipStream_t st);
+hipError_t launch_divide(const double* num, const double* den, const float* prev, float* out, int64_t M,
+                         hipStream_t st);
+hipError_t launch_mean(const double* L, int64_t n, double* out, hipStream_t st);
+
+}  // namespace emc

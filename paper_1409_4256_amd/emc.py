@@ -1,0 +1,276 @@
+"""ctypes binding of libemc.so: the C ABI declared in include/emc.h, same names.
+
+Argument marshalling only: tensors are checked for device, dtype, contiguity and
+size on the host, then their device pointers and the current HIP stream are
+handed to the library.  Every computation runs in the library's kernels; if
+the library is missing, loading fails loudly (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libemc.so")
+
+EMC_OK = 0
+EMC_ERR_INVALID_ARG = -1
+EMC_ERR_RANGE = -2
+EMC_ERR_WORKSPACE = -3
+EMC_ERR_HIP = -4
+EMC_ERR_UNSUPPORTED = -5
+
+EMC_PREC_FP32 = 0
+EMC_PREC_BF16 = 1
+
+EMC_RESP_FULL = 0
+EMC_RESP_PARTIAL = 1
+EMC_RESP_FINALIZE = 2
+
+EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_rot_stride", "emc_workspace_bytes",
+           "emc_pack_frames", "emc_expand", "emc_loglik", "emc_responsibilities", "emc_compress",
+           "emc_finalize", "emc_iterate")
+
+
+class EmcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"emc status {status}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("grid_n", ctypes.c_int32),
+        ("n_pix", ctypes.c_int32),
+        ("n_rot", ctypes.c_int32),
+        ("n_data", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("q", ctypes.c_void_p),
+        ("mask", ctypes.c_void_p),
+        ("quat", ctypes.c_void_p),
+        ("log_w", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_PB = ctypes.POINTER(Problem)
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load libemc.so (built in-tree by paper_1409_4256_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_1409_4256_amd.build`")
+    lib = ctypes.CDLL(p)
+    i32, i64, st = ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+    lib.emc_version.restype = ctypes.c_char_p
+    lib.emc_last_error.restype = ctypes.c_char_p
+    lib.emc_pix_stride.argtypes, lib.emc_pix_stride.restype = [i32], i64
+    lib.emc_rot_stride.argtypes, lib.emc_rot_stride.restype = [i32], i64
+    lib.emc_workspace_bytes.argtypes, lib.emc_workspace_bytes.restype = [_PB, ctypes.POINTER(ctypes.c_size_t)], st
+    lib.emc_pack_frames.argtypes, lib.emc_pack_frames.restype = [_PB, _P, _P, _P], st
+    lib.emc_expand.argtypes, lib.emc_expand.restype = [_PB, _P, _P, _P, _P, _P], st
+    lib.emc_loglik.argtypes, lib.emc_loglik.restype = [_PB, _P, _P, _P, _P, _P, _P], st
+    lib.emc_responsibilities.argtypes = [_PB, _P, _P, _P, i32, _P, _P, _P, _P, _P]
+    lib.emc_responsibilities.restype = st
+    lib.emc_compress.argtypes, lib.emc_compress.restype = [_PB, _P, _P, _P, _P, _P, _P, i32, _P], st
+    lib.emc_finalize.argtypes, lib.emc_finalize.restype = [_PB, _P, _P, _P, _P, _P, i64, _P, _P], st
+    lib.emc_iterate.argtypes = [_PB, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    lib.emc_iterate.restype = st
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != EMC_OK:
+        raise EmcError(status, load().emc_last_error().decode())
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor", allow_none=False):
+    """Device pointer of a contiguous GPU tensor (checked), or None."""
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    import torch
+
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Geometry:
+    """Device-resident problem description (keeps the tensors alive)."""
+
+    def __init__(self, grid_n, q, mask, quat, log_w, n_data, precision=EMC_PREC_FP32):
+        import torch
+
+        self.q = q.to(device="cuda", dtype=torch.float32).contiguous()
+        self.mask = mask.to(device="cuda", dtype=torch.uint8).contiguous()
+        self.quat = quat.to(device="cuda", dtype=torch.float32).contiguous()
+        self.log_w = log_w.to(device="cuda", dtype=torch.float64).contiguous()
+        self.pb = Problem(int(grid_n), int(self.q.shape[0]), int(self.quat.shape[0]), int(n_data),
+                          int(precision), 0, self.q.data_ptr(), self.mask.data_ptr(), self.quat.data_ptr(),
+                          self.log_w.data_ptr())
+
+    def with_frames(self, n_data):
+        g = object.__new__(Geometry)
+        g.q, g.mask, g.quat, g.log_w = self.q, self.mask, self.quat, self.log_w
+        g.pb = Problem(self.pb.grid_n, self.pb.n_pix, self.pb.n_rot, int(n_data), self.pb.precision, 0,
+                       self.pb.q, self.pb.mask, self.pb.quat, self.pb.log_w)
+        return g
+
+    @property
+    def n_pix(self):
+        return self.pb.n_pix
+
+    @property
+    def n_rot(self):
+        return self.pb.n_rot
+
+    @property
+    def n_data(self):
+        return self.pb.n_data
+
+    @property
+    def grid_n(self):
+        return self.pb.grid_n
+
+    @property
+    def pix_stride(self):
+        return emc_pix_stride(self.pb.n_pix)
+
+    @property
+    def rot_stride(self):
+        return emc_rot_stride(self.pb.n_rot)
+
+
+# ------------------------------------------------------------------------- entry points
+def emc_version() -> str:
+    return load().emc_version().decode()
+
+
+def emc_pix_stride(n_pix: int) -> int:
+    return int(load().emc_pix_stride(int(n_pix)))
+
+
+def emc_rot_stride(n_rot: int) -> int:
+    return int(load().emc_rot_stride(int(n_rot)))
+
+
+def emc_workspace_bytes(geo: Geometry) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().emc_workspace_bytes(ctypes.byref(geo.pb), ctypes.byref(n)))
+    return int(n.value)
+
+
+def emc_pack_frames(geo: Geometry, counts, K_packed, stream=None):
+    import torch
+
+    n = geo.n_data
+    _check(load().emc_pack_frames(ctypes.byref(geo.pb),
+                                  _ptr(counts, torch.uint16, n * geo.n_pix, "counts") if n else None,
+                                  _ptr(K_packed, torch.float32, n * geo.pix_stride, "K_packed") if n else None,
+                                  _stream(stream)))
+
+
+def emc_expand(geo: Geometry, model, c, logW, S, stream=None):
+    import torch
+
+    _check(load().emc_expand(ctypes.byref(geo.pb), _ptr(model, torch.float32, geo.grid_n ** 3, "model"),
+                             _ptr(c, torch.float64, geo.pix_stride, "c"),
+                             _ptr(logW, torch.float32, geo.n_rot * geo.pix_stride, "logW"),
+                             _ptr(S, torch.float64, geo.n_rot, "S"), _stream(stream)))
+
+
+def emc_loglik(geo: Geometry, K_packed, logW, c, G, b, stream=None):
+    import torch
+
+    n = geo.n_data
+    if n == 0:
+        return
+    _check(load().emc_loglik(ctypes.byref(geo.pb), _ptr(K_packed, torch.float32, n * geo.pix_stride, "K_packed"),
+                             _ptr(logW, torch.float32, geo.n_rot * geo.pix_stride, "logW"),
+                             _ptr(c, torch.float64, geo.pix_stride, "c"),
+                             _ptr(G, torch.float32, n * geo.rot_stride, "G"),
+                             _ptr(b, torch.float64, n, "b"), _stream(stream)))
+
+
+def emc_responsibilities(geo: Geometry, G, S, b, mode, stats, P=None, L=None, rho=None, stream=None):
+    import torch
+
+    n = geo.n_data
+    full = mode != EMC_RESP_PARTIAL
+    _check(load().emc_responsibilities(
+        ctypes.byref(geo.pb),
+        _ptr(G, torch.float32, n * geo.rot_stride, "G") if n else None,
+        _ptr(S, torch.float64, geo.n_rot, "S"),
+        _ptr(b, torch.float64, n, "b", allow_none=not full) if n else None,
+        int(mode),
+        _ptr(stats, torch.float64, 2 * n, "stats") if n else None,
+        _ptr(P, torch.float32, n * geo.rot_stride, "P", allow_none=not full) if n else None,
+        _ptr(L, torch.float64, n, "L", allow_none=not full) if n else None,
+        _ptr(rho, torch.float64, geo.n_rot, "rho", allow_none=not full),
+        _stream(stream)))
+
+
+def emc_compress(geo: Geometry, P, K_packed, rho, Wp, num, den, accumulate=False, stream=None):
+    import torch
+
+    n = geo.n_data
+    M = geo.grid_n ** 3
+    _check(load().emc_compress(
+        ctypes.byref(geo.pb),
+        _ptr(P, torch.float32, n * geo.rot_stride, "P") if n else None,
+        _ptr(K_packed, torch.float32, n * geo.pix_stride, "K_packed") if n else None,
+        _ptr(rho, torch.float64, geo.n_rot, "rho") if n else None,
+        _ptr(Wp, torch.float32, geo.n_rot * geo.pix_stride, "Wp") if n else None,
+        _ptr(num, torch.float64, M, "num"), _ptr(den, torch.float64, M, "den"), int(bool(accumulate)),
+        _stream(stream)))
+
+
+def emc_finalize(geo: Geometry, num, den, model_prev, model_out, L, n_L, loglik, stream=None):
+    import torch
+
+    M = geo.grid_n ** 3
+    _check(load().emc_finalize(ctypes.byref(geo.pb), _ptr(num, torch.float64, M, "num"),
+                               _ptr(den, torch.float64, M, "den"),
+                               _ptr(model_prev, torch.float32, M, "model_prev"),
+                               _ptr(model_out, torch.float32, M, "model_out"),
+                               _ptr(L, torch.float64, n_L, "L") if n_L else None, int(n_L),
+                               _ptr(loglik, torch.float64, 1, "loglik"), _stream(stream)))
+
+
+def emc_iterate(geo: Geometry, model_in, K_packed, model_out, loglik, P_out=None, ws=None, stream=None):
+    import torch
+
+    n = geo.n_data
+    M = geo.grid_n ** 3
+    need = emc_workspace_bytes(geo)
+    if ws is None:
+        raise ValueError("workspace tensor required (emc_workspace_bytes bytes, uint8)")
+    _check(load().emc_iterate(
+        ctypes.byref(geo.pb), _ptr(model_in, torch.float32, M, "model_in"),
+        _ptr(K_packed, torch.float32, n * geo.pix_stride, "K_packed") if n else None,
+        _ptr(model_out, torch.float32, M, "model_out"), _ptr(loglik, torch.float64, 1, "loglik"),
+        _ptr(P_out, torch.float32, n * geo.rot_stride, "P_out", allow_none=True),
+        _ptr(ws, torch.uint8, need, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream)))

@@ -1,0 +1,101 @@
+"""The C-ABI library loads, exports every entry point include/emc.h declares,
+and rejects invalid arguments on the host before launching anything (these
+calls never reach the GPU, so they run without one)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1409_4256_amd import emc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return emc.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "emc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(emc_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(emc.EXPORTS)
+
+
+def test_strides(lib):
+    assert emc.emc_pix_stride(16384) == 16384
+    assert emc.emc_pix_stride(1024) == 1024
+    assert emc.emc_pix_stride(529) == 768
+    assert emc.emc_rot_stride(25000) == 25088
+    assert emc.emc_rot_stride(0) == 0
+
+
+def _pb(**kw):
+    fake = 1 << 20  # never dereferenced: validation fails before any launch
+    d = dict(grid_n=32, n_pix=1024, n_rot=1000, n_data=1000, precision=0, reserved=0,
+             q=fake, mask=fake, quat=fake, log_w=fake)
+    d.update(kw)
+    return emc.Problem(*[d[k] for k, _ in emc.Problem._fields_])
+
+
+def test_workspace_bytes_config2(lib):
+    pb = _pb(grid_n=128, n_pix=16384, n_rot=25000, n_data=100000)
+    n = ctypes.c_size_t()
+    assert lib.emc_workspace_bytes(ctypes.byref(pb), ctypes.byref(n)) == emc.EMC_OK
+    slices = 25000 * 16384 * 4
+    gp = 100000 * 25088 * 4
+    assert slices + gp < n.value < slices + gp + 64 * 2 ** 20
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("grid_n", 1, emc.EMC_ERR_INVALID_ARG), ("grid_n", 2000, emc.EMC_ERR_INVALID_ARG),
+    ("n_pix", 0, emc.EMC_ERR_INVALID_ARG), ("n_rot", 0, emc.EMC_ERR_INVALID_ARG),
+    ("n_data", -1, emc.EMC_ERR_INVALID_ARG), ("reserved", 3, emc.EMC_ERR_INVALID_ARG),
+    ("precision", 7, emc.EMC_ERR_INVALID_ARG), ("precision", emc.EMC_PREC_BF16, emc.EMC_ERR_UNSUPPORTED),
+])
+def test_problem_validation(lib, field, value, status):
+    pb = _pb(**{field: value})
+    n = ctypes.c_size_t()
+    assert lib.emc_workspace_bytes(ctypes.byref(pb), ctypes.byref(n)) == status
+    assert len(lib.emc_last_error()) > 0
+
+
+def test_null_and_misaligned_pointers_rejected(lib):
+    pb = _pb()
+    z = ctypes.c_void_p(0)
+    a = ctypes.c_void_p(1 << 20)
+    assert lib.emc_expand(ctypes.byref(pb), z, a, a, a, z) == emc.EMC_ERR_INVALID_ARG
+    assert b"model" in lib.emc_last_error()
+    assert lib.emc_expand(ctypes.byref(pb), a, ctypes.c_void_p((1 << 20) + 4), a, a, z) == emc.EMC_ERR_INVALID_ARG
+    assert b"aligned" in lib.emc_last_error()
+    assert lib.emc_expand(ctypes.byref(_pb(quat=0)), a, a, a, a, z) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_responsibilities(ctypes.byref(pb), a, a, a, 9, a, a, a, a, z) == emc.EMC_ERR_INVALID_ARG
+
+
+def test_workspace_checks(lib):
+    pb = _pb()
+    a = ctypes.c_void_p(1 << 20)
+    need = ctypes.c_size_t()
+    lib.emc_workspace_bytes(ctypes.byref(pb), ctypes.byref(need))
+    st = lib.emc_iterate(ctypes.byref(pb), a, a, a, a, None, a, ctypes.c_size_t(need.value - 1), None)
+    assert st == emc.EMC_ERR_WORKSPACE
+    assert b"needs" in lib.emc_last_error()
+    st = lib.emc_iterate(ctypes.byref(pb), a, a, a, a, None, None, need, None)
+    assert st == emc.EMC_ERR_WORKSPACE
+    st = lib.emc_iterate(ctypes.byref(pb), a, a, a, a, None, ctypes.c_void_p((1 << 20) + 16), need, None)
+    assert st == emc.EMC_ERR_WORKSPACE
+
+
+def test_python_binding_raises_emc_error(lib):
+    with pytest.raises(emc.EmcError) as e:
+        emc._check(emc.EMC_ERR_INVALID_ARG)
+    assert e.value.status == emc.EMC_ERR_INVALID_ARG

@@ -1,0 +1,216 @@
+"""GPU (HIP, gfx950) vs FP64 oracle, element by element, through the C ABI.
+
+Tolerances of the plain FP32 path: log-likelihood relative error <= 1e-5
+(worst frame of max_j |dQ| / max_j |Q|), responsibilities max-abs <= 1e-3,
+updated model relative L2 <= 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from emc_inputs import WORKLOADS, make_inputs, tiny_problem
+
+pytestmark = pytest.mark.gpu
+
+Q_TOL, P_TOL, MODEL_TOL = 1e-5, 1e-3, 1e-5
+
+
+def _oracle(model, counts, q, mask, quat, log_w, N):
+    return O.iterate(np.asarray(model, dtype=np.float32).astype(np.float64), counts, q, mask, quat, log_w, N)
+
+
+def _inputs_f32(q, quat):
+    # the GPU receives FP32 coordinates and quaternions: the oracle gets the same values
+    return np.asarray(q, np.float32).astype(np.float64), np.asarray(quat, np.float32).astype(np.float64)
+
+
+def _check_all(g, o, mask, tag):
+    from gpu_helpers import q_rel_err, rel_l2
+
+    v = mask.astype(bool)
+    # expansion: log W (the centring is added back) and S_j
+    Wf = np.log(np.maximum(o["W"], 1e-10))
+    lw = g["logW_c"] + g["c"][None, :]
+    assert np.max(np.abs(lw[:, v] - Wf[:, v])) < 5e-6, tag
+    assert np.all(g["logW_c"][:, ~v] == 0) and np.all(g["logW_pad"] == 0), tag
+    np.testing.assert_allclose(g["S"], np.maximum(o["W"], 1e-10)[:, v].sum(1), rtol=1e-12)
+    # log-likelihood and E-step
+    assert q_rel_err(g["Q"], o["Q"]) <= Q_TOL, (tag, q_rel_err(g["Q"], o["Q"]))
+    assert np.max(np.abs(g["P"] - o["P"])) <= P_TOL, (tag, np.max(np.abs(g["P"] - o["P"])))
+    assert np.all(g["P_pad"] == 0)
+    np.testing.assert_allclose(g["L"], o["L"], rtol=1e-6)
+    np.testing.assert_allclose(g["P"].sum(0), 1.0, atol=1e-5)
+    np.testing.assert_allclose(g["rho"], o["rho"], rtol=1e-4, atol=1e-6 * o["rho"].max())
+    # M-step and compression
+    assert rel_l2(g["Wp"], o["Wp"]) <= 1e-5, (tag, rel_l2(g["Wp"], o["Wp"]))
+    assert rel_l2(g["num"], o["num"]) <= 1e-5 and rel_l2(g["den"], o["den"]) <= 1e-5, tag
+    assert np.array_equal(g["den"] > 0, o["den"] > 0) or np.all(o["den"][(g["den"] > 0) != (o["den"] > 0)] < 1e-12)
+    err = rel_l2(g["model"], o["model"])
+    assert err <= MODEL_TOL, (tag, err)
+    assert abs(g["loglik"] - o["loglik"]) <= 1e-6 * abs(o["loglik"]), tag
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return make_inputs(WORKLOADS[1])
+
+
+@pytest.mark.parametrize("start", ["random_smooth", "true_model"])
+def test_config1_full_iteration_matches_oracle(gpu_lib, cfg1, start):
+    from gpu_helpers import geometry, pack, run_steps, upload_counts
+
+    inp = cfg1
+    model = inp.model_start if start == "random_smooth" else inp.model_true
+    q, quat = _inputs_f32(inp.q, inp.quat)
+    geo = geometry(32, q, inp.mask, quat, inp.log_w, inp.wl.n_data)
+    K = pack(geo, upload_counts(inp.counts))
+    g = run_steps(geo, model, K)
+    o = _oracle(model, inp.counts, q, inp.mask, quat, inp.log_w, 32)
+    _check_all(g, o, inp.mask, start)
+
+
+@pytest.mark.parametrize("seed,N,npx,nrot,ndata", [(0, 24, 529, 300, 333), (1, 20, 257, 129, 517),
+                                                   (2, 16, 64, 1, 40), (3, 18, 300, 257, 1)])
+def test_ragged_shapes_match_oracle(gpu_lib, seed, N, npx, nrot, ndata):
+    from gpu_helpers import geometry, pack, run_steps, upload_counts
+
+    t = tiny_problem(seed, grid_n=N, n_pix=npx, n_rot=nrot, n_data=ndata, photons=200.0)
+    q, quat = _inputs_f32(t["q"], t["quat"])
+    geo = geometry(N, q, t["mask"], quat, t["log_w"], ndata)
+    K = pack(geo, upload_counts(t["counts"]))
+    g = run_steps(geo, t["model"], K)
+    o = _oracle(t["model"], t["counts"], q, t["mask"], quat, t["log_w"], N)
+    _check_all(g, o, t["mask"], f"seed{seed}")
+
+
+def test_frame_chunks_accumulate_before_division(gpu_lib):
+    from gpu_helpers import geometry, pack, rel_l2, run_steps, upload_counts
+
+    t = tiny_problem(5, grid_n=20, n_pix=400, n_rot=200, n_data=700, photons=150.0)
+    q, quat = _inputs_f32(t["q"], t["quat"])
+    geo = geometry(20, q, t["mask"], quat, t["log_w"], 700)
+    K = pack(geo, upload_counts(t["counts"]))
+    g = run_steps(geo, t["model"], K, frame_chunk=256)
+    o = _oracle(t["model"], t["counts"], q, t["mask"], quat, t["log_w"], 20)
+    assert rel_l2(g["model"], o["model"]) <= MODEL_TOL
+    assert np.max(np.abs(g["P"] - o["P"])) <= P_TOL
+
+
+def test_empty_frame_set_keeps_model(gpu_lib):
+    from gpu_helpers import geometry, pack, run_steps
+
+    t = tiny_problem(6, grid_n=12, n_pix=50, n_rot=10, n_data=0)
+    q, quat = _inputs_f32(t["q"], t["quat"])
+    geo = geometry(12, q, t["mask"], quat, t["log_w"], 0)
+    import torch
+
+    K = pack(geo, torch.zeros(1, dtype=torch.uint16, device="cuda"))
+    g = run_steps(geo, t["model"], K)
+    np.testing.assert_array_equal(g["model"], np.asarray(t["model"], np.float32).astype(np.float64))
+    assert math.isnan(g["loglik"])
+    assert np.all(g["den"] == 0)
+
+
+def test_single_rotation_mean_frame_on_gpu(gpu_lib):
+    # identity rotation, flat detector on integer voxels: the touched voxels are
+    # exactly the mean frame (closed form of the method)
+    from gpu_helpers import geometry, pack, run_steps, upload_counts
+
+    N = 16
+    u = np.arange(-4, 5)
+    X, Y = np.meshgrid(u, u, indexing="ij")
+    q = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1)
+    mask = np.ones(q.shape[0], np.uint8)
+    mask[7] = 0
+    K = np.random.default_rng(3).poisson(5.0, size=(37, q.shape[0])).astype(np.uint16)
+    K[:, mask == 0] = 0
+    geo = geometry(N, q, mask, np.array([[1.0, 0, 0, 0]]), np.array([0.0]), 37)
+    g = run_steps(geo, np.ones(N ** 3), pack(geo, upload_counts(K)))
+    l = ((X.ravel() + 8) * N + (Y.ravel() + 8)) * N + 8
+    v = mask.astype(bool)
+    np.testing.assert_allclose(g["model"][l[v]], K.mean(axis=0)[v], rtol=2e-7)
+    np.testing.assert_allclose(g["P"], 1.0)
+
+
+def test_virtual_rotation_shards_equal_unsharded(gpu_lib):
+    """Four rotation shares on one GPU, statistics combined on the host (Section 3.2)."""
+    import torch
+
+    from gpu_helpers import geometry, pack, upload_counts
+    from paper_1409_4256_amd import emc
+
+    t = tiny_problem(8, grid_n=20, n_pix=300, n_rot=400, n_data=150, photons=200.0)
+    q, quat = _inputs_f32(t["q"], t["quat"])
+    n = 150
+    geo_full = geometry(20, q, t["mask"], quat, t["log_w"], n)
+    Kd = pack(geo_full, upload_counts(t["counts"]))
+    model = torch.as_tensor(t["model"], dtype=torch.float32, device="cuda")
+
+    def shard_outputs(geo):
+        ps, rs = geo.pix_stride, geo.rot_stride
+        c = torch.empty(ps, dtype=torch.float64, device="cuda")
+        logW = torch.empty(geo.n_rot * ps, dtype=torch.float32, device="cuda")
+        S = torch.empty(geo.n_rot, dtype=torch.float64, device="cuda")
+        emc.emc_expand(geo, model, c, logW, S)
+        G = torch.empty(n * rs, dtype=torch.float32, device="cuda")
+        b = torch.empty(n, dtype=torch.float64, device="cuda")
+        emc.emc_loglik(geo, Kd, logW, c, G, b)
+        stats = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+        emc.emc_responsibilities(geo, G, S, b, emc.EMC_RESP_PARTIAL, stats)
+        return dict(G=G, S=S, b=b, stats=stats)
+
+    full = shard_outputs(geo_full)
+    P_full = torch.empty(n * geo_full.rot_stride, dtype=torch.float32, device="cuda")
+    L_full = torch.empty(n, dtype=torch.float64, device="cuda")
+    rho_full = torch.empty(400, dtype=torch.float64, device="cuda")
+    emc.emc_responsibilities(geo_full, full["G"], full["S"], full["b"], emc.EMC_RESP_FINALIZE, full["stats"],
+                             P_full, L_full, rho_full)
+    bounds = [0, 90, 200, 333, 400]
+    shards = []
+    for a, z in zip(bounds[:-1], bounds[1:]):
+        geo = geometry(20, q, t["mask"], quat[a:z], t["log_w"][a:z], n)
+        shards.append((geo, shard_outputs(geo)))
+    # host combination of the per-frame statistics (what an all-reduce would carry)
+    st = np.stack([s["stats"].cpu().numpy().reshape(n, 2) for _, s in shards])
+    m = st[:, :, 0].max(0)
+    s = (st[:, :, 1] * np.exp(st[:, :, 0] - m[None, :])).sum(0)
+    glob = torch.as_tensor(np.stack([m, s], 1).reshape(-1), device="cuda")
+    P_parts, rho_parts = [], []
+    for geo, o in shards:
+        P = torch.empty(n * geo.rot_stride, dtype=torch.float32, device="cuda")
+        L = torch.empty(n, dtype=torch.float64, device="cuda")
+        rho = torch.empty(geo.n_rot, dtype=torch.float64, device="cuda")
+        emc.emc_responsibilities(geo, o["G"], o["S"], o["b"], emc.EMC_RESP_FINALIZE, glob, P, L, rho)
+        P_parts.append(P.view(n, geo.rot_stride)[:, :geo.n_rot].cpu().numpy())
+        rho_parts.append(rho.cpu().numpy())
+        np.testing.assert_allclose(L.cpu().numpy(), L_full.cpu().numpy(), rtol=1e-12)
+    P_sh = np.concatenate(P_parts, axis=1)
+    P_un = P_full.view(n, geo_full.rot_stride)[:, :400].cpu().numpy()
+    np.testing.assert_allclose(P_sh, P_un, rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(np.concatenate(rho_parts), rho_full.cpu().numpy(), rtol=1e-6, atol=1e-12)
+
+
+def test_iterate_entry_point_equals_steps(gpu_lib, cfg1):
+    import torch
+
+    from gpu_helpers import geometry, pack, run_steps, upload_counts
+    from paper_1409_4256_amd import emc
+
+    inp = cfg1
+    q, quat = _inputs_f32(inp.q, inp.quat)
+    geo = geometry(32, q, inp.mask, quat, inp.log_w, inp.wl.n_data)
+    K = pack(geo, upload_counts(inp.counts))
+    steps = run_steps(geo, inp.model_start, K)
+    ws = torch.empty(emc.emc_workspace_bytes(geo), dtype=torch.uint8, device="cuda")
+    m_in = torch.as_tensor(inp.model_start, dtype=torch.float32, device="cuda")
+    m_out = torch.empty_like(m_in)
+    ll = torch.empty(1, dtype=torch.float64, device="cuda")
+    P = torch.empty(geo.n_data * geo.rot_stride, dtype=torch.float32, device="cuda")
+    emc.emc_iterate(geo, m_in, K, m_out, ll, P_out=P, ws=ws)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(m_out.double().cpu().numpy(), steps["model"], rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(P.view(geo.n_data, -1)[:, :geo.n_rot].T.double().cpu().numpy(), steps["P"],
+                               atol=1e-6)
+    assert abs(ll.item() - steps["loglik"]) <= 1e-9 * abs(steps["loglik"])
