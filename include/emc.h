@@ -133,8 +133,8 @@ emc_status emc_expand(const emc_problem* pb, const float* model, double* c, floa
 emc_status emc_loglik(const emc_problem* pb, const void* K_packed, const float* logW,
                       const double* c, float* G, double* b, hipStream_t stream);
 
-/* E-step, eq. (2.4), as an FP64 log-sum-exp over rotations of
- * a_kj = G_kj - S_j + log w_j:
+/* E-step, eq. (2.4), as an FP64 log-sum-exp over rotations of the log-joint
+ * a_kj = Q_jk + log w_j = G_kj + b_k - S_j + log w_j:
  *   stats [n_data][2] double: (m_k, s_k) with m_k = max_j a_kj and
  *         s_k = sum_j exp(a_kj - m_k).  Written in FULL and PARTIAL mode; read
  *         in FINALIZE mode, where the caller has combined the statistics of
@@ -142,8 +142,9 @@ emc_status emc_loglik(const emc_problem* pb, const void* K_packed, const float* 
  *   P     [n_data][rot_stride] float out (FULL, FINALIZE): P_kj = exp(a_kj - m_k -
  *         log s_k); padding columns written 0.  P may alias G (in place).
  *   L     [n_data] double out (FULL, FINALIZE): log-evidence
- *         L_k = m_k + log s_k + b_k (Section 2.2 objective, without log K!).
+ *         L_k = m_k + log s_k (eq. (2.1) objective term, without log K!).
  *   rho   [n_rot] double out (FULL, FINALIZE): rho_j = sum_k P_kj (overwritten).
+ *   b     [n_data] double: b_k from emc_loglik (all modes).
  * In PARTIAL mode P, L, rho may be NULL.                                     */
 emc_status emc_responsibilities(const emc_problem* pb, const float* G, const double* S,
                                 const double* b, int32_t mode, double* stats, float* P,

@@ -116,7 +116,7 @@ emc_status run_estep(const emc_problem* pb, const float* G, const double* S, con
                      double* stats, float* P, double* L, double* rho, hipStream_t st) {
   const int64_t rs = round_up(pb->n_rot, 256);
   if (mode != EMC_RESP_FINALIZE)
-    HIP_TRY(launch_lse_stats(G, rs, pb->n_rot, pb->n_data, pb->log_w, S, stats, st), "lse_stats");
+    HIP_TRY(launch_lse_stats(G, rs, pb->n_rot, pb->n_data, pb->log_w, S, b, stats, st), "lse_stats");
   if (mode == EMC_RESP_PARTIAL) return EMC_OK;
   HIP_TRY(launch_fill_zero_f64(rho, (size_t)pb->n_rot, st), "zero rho");
   HIP_TRY(launch_lse_write(G, P, rs, pb->n_rot, pb->n_data, pb->log_w, S, stats, b, L, rho, st), "lse_write");
@@ -209,10 +209,10 @@ emc_status emc_responsibilities(const emc_problem* pb, const float* G, const dou
   if (pb->n_data > 0) {
     CHECK(need(stats, 16, "stats"));
     CHECK(need(G, 16, "G"));
+    CHECK(need(b, 8, "b"));
     if (mode != EMC_RESP_PARTIAL) {
       CHECK(need(P, 16, "P"));
       CHECK(need(L, 8, "L"));
-      CHECK(need(b, 8, "b"));
     }
   }
   return run_estep(pb, G, S, b, mode, stats, P, L, rho, st);

@@ -87,7 +87,7 @@ hipError_t launch_gemm_f32_nt(const float* A, const float* B, float* C, int64_t 
 hipError_t launch_gemm_f32_tn(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
                               int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st);
 hipError_t launch_lse_stats(const float* G, int64_t ld, int n_rot, int64_t n_data, const double* log_w,
-                            const double* S, double* stats, hipStream_t st);
+                            const double* S, const double* b, double* stats, hipStream_t st);
 hipError_t launch_lse_write(const float* G, float* P, int64_t ld, int n_rot, int64_t n_data,
                             const double* log_w, const double* S, const double* stats, const double* b,
                             double* L, double* rho, hipStream_t st);

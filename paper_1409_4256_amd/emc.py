@@ -224,7 +224,7 @@ def emc_responsibilities(geo: Geometry, G, S, b, mode, stats, P=None, L=None, rh
         ctypes.byref(geo.pb),
         _ptr(G, torch.float32, n * geo.rot_stride, "G") if n else None,
         _ptr(S, torch.float64, geo.n_rot, "S"),
-        _ptr(b, torch.float64, n, "b", allow_none=not full) if n else None,
+        _ptr(b, torch.float64, n, "b") if n else None,
         int(mode),
         _ptr(stats, torch.float64, 2 * n, "stats") if n else None,
         _ptr(P, torch.float32, n * geo.rot_stride, "P", allow_none=not full) if n else None,
