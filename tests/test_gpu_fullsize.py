@@ -73,7 +73,8 @@ def full(gpu_lib):
     snap["loglik"] = run.loglik.item()
     counts = inp.counts
     snap["photons_total"] = float(counts.to(torch.int64).sum().item())
-    snap["K_rows"] = counts[torch.as_tensor(ks, device="cuda")].cpu().numpy()
+    # uint16 has no CUDA indexing kernel; int16 is the same bits for counts < 32768
+    snap["K_rows"] = counts.view(torch.int16)[torch.as_tensor(ks, device="cuda")].to(torch.int32).cpu().numpy()
     snap["K_all_f64"] = None
     snap["ks"] = ks
     snap["counts_dev"] = counts

@@ -185,11 +185,13 @@ def test_virtual_rotation_shards_equal_unsharded(gpu_lib):
         emc.emc_responsibilities(geo, o["G"], o["S"], o["b"], emc.EMC_RESP_FINALIZE, glob, P, L, rho)
         P_parts.append(P.view(n, geo.rot_stride)[:, :geo.n_rot].cpu().numpy())
         rho_parts.append(rho.cpu().numpy())
-        np.testing.assert_allclose(L.cpu().numpy(), L_full.cpu().numpy(), rtol=1e-12)
+        # each share centres its own slices, so the FP32 contractions round differently
+        np.testing.assert_allclose(L.cpu().numpy(), L_full.cpu().numpy(), rtol=1e-6)
     P_sh = np.concatenate(P_parts, axis=1)
     P_un = P_full.view(n, geo_full.rot_stride)[:, :400].cpu().numpy()
-    np.testing.assert_allclose(P_sh, P_un, rtol=1e-6, atol=1e-12)
-    np.testing.assert_allclose(np.concatenate(rho_parts), rho_full.cpu().numpy(), rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(P_sh, P_un, rtol=1e-4, atol=1e-5)
+    np.testing.assert_allclose(P_sh.sum(1), 1.0, atol=1e-5)
+    np.testing.assert_allclose(np.concatenate(rho_parts), rho_full.cpu().numpy(), rtol=1e-4, atol=1e-5)
 
 
 def test_iterate_entry_point_equals_steps(gpu_lib, cfg1):
