@@ -87,6 +87,23 @@ def scaled(base: Workload, **kw) -> Workload:
 # ----------------------------------------------------------------------------------------
 # geometry
 # ----------------------------------------------------------------------------------------
+TILE = 8
+
+
+def pixel_order(n: int, tile: int = TILE) -> np.ndarray:
+    """Order of the detector's pixels in the pixel list: tile x tile blocks, blocks
+    row-major, pixels row-major inside a block (partial blocks at the edges).
+    Entry p is the row-major index u*n + v of list position p.  Spatially compact
+    groups of 64 consecutive pixels let the compression accumulate locally."""
+    out = []
+    for tu in range(0, n, tile):
+        for tv in range(0, n, tile):
+            for u in range(tu, min(tu + tile, n)):
+                for v in range(tv, min(tv + tile, n)):
+                    out.append(u * n + v)
+    return np.asarray(out, dtype=np.int64)
+
+
 def detector_q(wl: Workload):
     """Pixel scattering vectors on the Ewald sphere, in voxel units.
 
@@ -94,20 +111,20 @@ def detector_q(wl: Workload):
     scattering vector is q = (x/r, y/r, D/r - 1)/lambda with r = |(x, y, D)|, so
     |q| = 2 sin(theta)/lambda.  The voxel spacing puts the detector corner at
     N/2 - 2 voxels, so every rotated pixel keeps two voxels of margin.
-    Returns (q_vox [n_pix][3] float64, dq_per_voxel_nm^-1).
+    Returns (q_vox [n_pix][3] float64 in pixel_order, dq_per_voxel_nm^-1).
     """
     n = wl.det_n
     x = (np.arange(n) - n / 2) * wl.px_m
     X, Y = np.meshgrid(x, x, indexing="ij")
     r = np.sqrt(X * X + Y * Y + wl.dist_m ** 2)
     q = np.stack([X / r, Y / r, wl.dist_m / r - 1.0], axis=-1) / wl.lam_nm
-    q = q.reshape(-1, 3)
+    q = q.reshape(-1, 3)[pixel_order(n)]
     dq = float(np.linalg.norm(q, axis=1).max() / (wl.grid_n / 2 - 2))
     return q / dq, dq
 
 
 def detector_mask(wl: Workload) -> np.ndarray:
-    """1 = pixel used, 0 = missing/saturated pixel."""
+    """1 = pixel used, 0 = missing/saturated pixel (in pixel-list order)."""
     n = wl.det_n
     m = np.ones((n, n), dtype=np.uint8)
     if wl.mask == "center3":
@@ -119,7 +136,7 @@ def detector_mask(wl: Workload) -> np.ndarray:
         m.reshape(-1)[off] = 0
     elif wl.mask != "none":
         raise ValueError(wl.mask)
-    return m.reshape(-1)
+    return m.reshape(-1)[pixel_order(n)]
 
 
 def shoemake_quaternions(g: np.random.Generator, n: int) -> np.ndarray:

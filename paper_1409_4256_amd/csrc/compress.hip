@@ -1,32 +1,99 @@
 // c-step, eq. (2.12): scatter of the M-step slices W'_ji and of the weights
 // rho_j into numerator and denominator grids through the same trilinear
 // weights as the expansion (FP64 atomics), then the division.
+#include <limits.h>
+
 #include "emc_device.h"
 
 namespace emc {
 
-// One workgroup per rotation (one slice per block, as the paper's
-// insert_slices kernel, Section 3.1).
+constexpr int kBoxCap = 1024;  // voxels of one wave's LDS accumulation box
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One workgroup per rotation j (one slice per block, like the paper's
+// insert_slices kernel, Section 3.1).  Each wave takes 64 consecutive pixels;
+// when they are spatially compact on the detector (an 8 x 8 tile) their 512
+// trilinear contributions land in a small box of voxels, which the wave
+// accumulates in LDS (FP64) and then adds to the global grids with one FP64
+// atomic per touched voxel.  Pixel groups whose box exceeds kBoxCap voxels
+// add straight to the global grids; the result is the same either way.
 __global__ __launch_bounds__(256) void scatter_kernel(const float* __restrict__ Wp, int64_t stride,
                                                       const double* __restrict__ rho, const float* __restrict__ q,
                                                       const uint8_t* __restrict__ mask,
                                                       const float* __restrict__ quat, int n_pix, int N,
                                                       double* __restrict__ num, double* __restrict__ den) {
+  __shared__ double s_num[4][kBoxCap];
+  __shared__ double s_den[4][kBoxCap];
   const int j = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Rot r = quat_rot(quat + 4 * (int64_t)j);
   const double rj = rho[j];
   const float* row = Wp + (int64_t)j * stride;
-  for (int i = threadIdx.x; i < n_pix; i += 256) {
-    if (!mask[i]) continue;
-    const Stencil s = stencil_at(r, q + 3 * (int64_t)i, N);
-    const double wv = (double)row[i];
+  double* bn = s_num[wave];
+  double* bd = s_den[wave];
+  const int n_groups = (n_pix + 63) / 64;
+  const int iters = (n_groups + 3) / 4;
+  for (int it = 0; it < iters; ++it) {
+    const int i = (it * 4 + wave) * 64 + lane;
+    const bool valid = i < n_pix && mask[i];
+    Stencil s;
+    double wv = 0.0;
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+    if (valid) {
+      s = stencil_at(r, q + 3 * (int64_t)i, N);
+      wv = (double)row[i];
+      lo[0] = hi[0] = s.bx;
+      lo[1] = hi[1] = s.by;
+      lo[2] = hi[2] = s.bz;
+    }
+    const int x0 = wave_min(lo[0]), y0 = wave_min(lo[1]), z0 = wave_min(lo[2]);
+    const int x1 = wave_max(hi[0]), y1 = wave_max(hi[1]), z1 = wave_max(hi[2]);
+    const bool any = x1 >= x0;  // at least one valid lane
+    const int DY = any ? y1 - y0 + 2 : 0, DZ = any ? z1 - z0 + 2 : 0;
+    const int64_t vol = any ? (int64_t)(x1 - x0 + 2) * DY * DZ : 0;
+    const bool boxed = any && vol <= kBoxCap;
+    if (boxed)
+      for (int e = lane; e < vol; e += 64) {
+        bn[e] = 0.0;
+        bd[e] = 0.0;
+      }
+    __syncthreads();
+    if (valid) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      if (s.w[t] != 0.0) {
-        unsafeAtomicAdd(num + s.idx[t], s.w[t] * wv);
-        unsafeAtomicAdd(den + s.idx[t], s.w[t] * rj);
+      for (int t = 0; t < 8; ++t) {
+        if (s.w[t] == 0.0) continue;  // outside the grid, or exactly on the far face
+        const double an = s.w[t] * wv, ad = s.w[t] * rj;
+        if (boxed) {
+          const int e = ((s.bx + (t >> 2) - x0) * DY + (s.by + ((t >> 1) & 1) - y0)) * DZ + (s.bz + (t & 1) - z0);
+          atomicAdd(bn + e, an);
+          atomicAdd(bd + e, ad);
+        } else {
+          unsafeAtomicAdd(num + s.idx[t], an);
+          unsafeAtomicAdd(den + s.idx[t], ad);
+        }
       }
     }
+    __syncthreads();
+    if (boxed)
+      for (int e = lane; e < vol; e += 64) {
+        const double vn = bn[e], vd = bd[e];
+        if (vn == 0.0 && vd == 0.0) continue;
+        const int ex = e / (DY * DZ), rem = e - ex * DY * DZ, ey = rem / DZ, ez = rem - ey * DZ;
+        const int l = ((x0 + ex) * N + (y0 + ey)) * N + (z0 + ez);
+        if (vn != 0.0) unsafeAtomicAdd(num + l, vn);
+        if (vd != 0.0) unsafeAtomicAdd(den + l, vd);
+      }
+    // the next iteration's zeroing touches entry e from the same lane that flushed it
   }
 }
 

@@ -35,6 +35,7 @@ __device__ __forceinline__ Rot quat_rot(const float* __restrict__ qv) {
 struct Stencil {
   int idx[8];
   double w[8];
+  int bx, by, bz;  // lowest corner of the 2 x 2 x 2 neighbourhood
 };
 
 __device__ __forceinline__ Stencil stencil_at(const Rot& r, const float* __restrict__ qi, int N) {
@@ -47,6 +48,9 @@ __device__ __forceinline__ Stencil stencil_at(const Rot& r, const float* __restr
   const int bx = (int)fx0, by = (int)fy0, bz = (int)fz0;
   const double tx = px - fx0, ty = py - fy0, tz = pz - fz0;
   Stencil s;
+  s.bx = bx;
+  s.by = by;
+  s.bz = bz;
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
     const int dx = t >> 2, dy = (t >> 1) & 1, dz = t & 1;

@@ -71,12 +71,16 @@ def test_config1_full_iteration_matches_oracle(gpu_lib, cfg1, start):
     _check_all(g, o, inp.mask, start)
 
 
-@pytest.mark.parametrize("seed,N,npx,nrot,ndata", [(0, 24, 529, 300, 333), (1, 20, 257, 129, 517),
-                                                   (2, 16, 64, 1, 40), (3, 18, 300, 257, 1)])
-def test_ragged_shapes_match_oracle(gpu_lib, seed, N, npx, nrot, ndata):
+@pytest.mark.parametrize("seed,N,npx,nrot,ndata,qr", [(0, 24, 529, 300, 333, None), (1, 20, 257, 129, 517, None),
+                                                      (2, 16, 64, 1, 40, None), (3, 18, 300, 257, 1, None),
+                                                      (4, 12, 200, 70, 90, 2.5)])
+def test_ragged_shapes_match_oracle(gpu_lib, seed, N, npx, nrot, ndata, qr):
+    # random pixel positions in a ball of radius N/2 - 2 spread each 64-pixel group
+    # beyond the compression's local box (global-atomic path); qr = 2.5 keeps them
+    # inside it (local-box path)
     from gpu_helpers import geometry, pack, run_steps, upload_counts
 
-    t = tiny_problem(seed, grid_n=N, n_pix=npx, n_rot=nrot, n_data=ndata, photons=200.0)
+    t = tiny_problem(seed, grid_n=N, n_pix=npx, n_rot=nrot, n_data=ndata, photons=200.0, q_radius=qr)
     q, quat = _inputs_f32(t["q"], t["quat"])
     geo = geometry(N, q, t["mask"], quat, t["log_w"], ndata)
     K = pack(geo, upload_counts(t["counts"]))
