@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
@@ -43,7 +44,7 @@ def parse():
 class Run:
     """Device buffers and the step sequence of one iteration through the C ABI."""
 
-    def __init__(self, inp):
+    def __init__(self, inp, precision=0, counts_dev=None):
         import torch
 
         from paper_1409_4256_amd import emc
@@ -53,22 +54,24 @@ class Run:
         self.wl = wl
         dev = "cuda"
         self.geo = emc.Geometry(wl.grid_n, torch.as_tensor(inp.q), torch.as_tensor(inp.mask),
-                                torch.as_tensor(inp.quat), torch.as_tensor(inp.log_w), wl.n_data)
+                                torch.as_tensor(inp.quat), torch.as_tensor(inp.log_w), wl.n_data, precision)
         g = self.geo
-        counts = inp.counts if isinstance(inp.counts, torch.Tensor) else torch.from_numpy(inp.counts)
-        counts = counts.to(dev)
-        self.K = torch.empty(wl.n_data * g.pix_stride, dtype=torch.float32, device=dev)
-        emc.emc_pack_frames(g, counts, self.K)
+        if counts_dev is None:
+            counts_dev = inp.counts if isinstance(inp.counts, torch.Tensor) else torch.from_numpy(inp.counts)
+            counts_dev = counts_dev.to(dev)
+        self.K = emc.frames_tensor(g)
+        emc.emc_pack_frames(g, counts_dev, self.K)
         torch.cuda.synchronize()
-        del counts
-        ps, rs, n = g.pix_stride, g.rot_stride, wl.n_data
+        ps, ds, n = g.pix_stride, g.data_stride, wl.n_data
         M = wl.grid_n ** 3
         self.model = [torch.as_tensor(inp.model_start, dtype=torch.float32, device=dev),
                       torch.empty(M, dtype=torch.float32, device=dev)]
         self.c = torch.empty(ps, dtype=torch.float64, device=dev)
-        self.slices = torch.empty(wl.n_rot * ps, dtype=torch.float32, device=dev)
+        self.slices = emc.slices_tensor(g)
         self.S = torch.empty(wl.n_rot, dtype=torch.float64, device=dev)
-        self.GP = torch.empty(n * rs, dtype=torch.float32, device=dev)
+        self.scale = torch.empty(wl.n_rot, dtype=torch.float32, device=dev)
+        self.G = torch.empty(wl.n_rot * ds, dtype=torch.float32, device=dev)
+        self.P = self.G if not g.bf16 else torch.empty(wl.n_rot * ds, dtype=torch.bfloat16, device=dev)
         self.b = torch.empty(n, dtype=torch.float64, device=dev)
         self.stats = torch.empty(2 * n, dtype=torch.float64, device=dev)
         self.L = torch.empty(n, dtype=torch.float64, device=dev)
@@ -84,14 +87,14 @@ class Run:
         rec = (lambda i: ev[i].record()) if ev else (lambda i: None)
         m_in, m_out = self.model[self.cur], self.model[1 - self.cur]
         rec(0)
-        emc.emc_expand(g, m_in, self.c, self.slices, self.S)
+        emc.emc_expand(g, m_in, self.c, self.slices, self.S, self.scale)
         rec(1)
-        emc.emc_loglik(g, self.K, self.slices, self.c, self.GP, self.b)
+        emc.emc_loglik(g, self.K, self.slices, self.scale, self.c, self.G, self.b)
         rec(2)
-        emc.emc_responsibilities(g, self.GP, self.S, self.b, emc.EMC_RESP_FULL, self.stats, self.GP, self.L,
+        emc.emc_responsibilities(g, self.G, self.S, self.b, emc.EMC_RESP_FULL, self.stats, self.P, self.L,
                                  self.rho)
         rec(3)
-        emc.emc_compress(g, self.GP, self.K, self.rho, self.slices, self.num, self.den, accumulate=False)
+        emc.emc_compress(g, self.P, self.K, self.rho, self.slices, self.num, self.den, accumulate=False)
         rec(4)
         emc.emc_finalize(g, self.num, self.den, m_in, m_out, self.L, self.wl.n_data, self.loglik)
         rec(5)
@@ -139,6 +142,49 @@ def cpu_baseline(inp, n_rot_s=600, n_data_s=2000):
             "full_iteration_s_extrapolated": full_s}
 
 
+def time_form(run, args, n_valid):
+    """Warm up, then time `args.steps` iterations with events around every step."""
+    import numpy as np
+    import torch
+
+    wl, g = run.wl, run.geo
+    for i in range(args.warmup):
+        run.step()
+        torch.cuda.synchronize()
+        log(f"{'bf16' if g.bf16 else 'fp32'} warmup {i + 1}/{args.warmup} done")
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        run.step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    names = ["expand", "loglik", "estep", "compress", "finalize"]
+    per = {nm: [evs[i][s].elapsed_time(evs[i][s + 1]) for i in range(K)] for s, nm in enumerate(names)}
+    total_ms = [evs[i][0].elapsed_time(evs[i][5]) for i in range(K)]
+    ms = evs[0][0].elapsed_time(evs[K - 1][5]) / K
+    log(f"{'bf16' if g.bf16 else 'fp32'}: {ms:.1f} ms/iteration (wall {wall:.2f} s), loglik {run.loglik.item():.4f}")
+    contraction = 2.0 * wl.n_data * wl.n_rot * n_valid           # one contraction over valid pixels
+    terms = 2 if g.bf16 else 1                                   # BF16: hi and lo slices
+    t_gemm = float(np.mean(per["loglik"])) / 1e3
+    peak = PEAK_BF16_MFMA_TFLOPS if g.bf16 else PEAK_FP32_MFMA_TFLOPS
+    achieved = terms * contraction / t_gemm / 1e12
+    kern = "gemm_bf16_kernel<DUAL> (hi+lo log-likelihood)" if g.bf16 else "gemm_f32_kernel (log-likelihood)"
+    return {
+        "value": round(1000.0 / ms, 5),
+        "ms_per_step": round(ms, 3),
+        "iteration_ms_min": round(float(np.min(total_ms)), 3),
+        "steps_ms_median": {k: round(float(np.median(v)), 3) for k, v in per.items()},
+        "loglik": run.loglik.item(),
+        "roofline": {"bound": "mfma", "kernel": kern + ", emc_loglik step", "achieved": round(achieved, 2),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "algorithmic_flops_per_launch": terms * contraction},
+        "iteration_tflops_algorithmic": round((terms + 1) * contraction / (ms / 1e3) / 1e12, 2),
+        "paper_flop_model_tflops": round(27.0 * wl.n_rot * wl.n_data * wl.n_pix / (ms / 1e3) / 1e12, 2),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -159,70 +205,54 @@ def main():
     inp = make_inputs(wl, device="cuda" if args.workload != 1 else "cpu", with_truth=False)
     torch.cuda.synchronize()
     log(f"inputs {wl.name} generated in {time.perf_counter() - t0:.1f} s")
-    run = Run(inp)
-    log("frames packed")
     n_valid = int(np.asarray(inp.mask).sum())
 
     if args.profile_once:
-        run.step()
-        torch.cuda.synchronize()
+        counts_dev = inp.counts if isinstance(inp.counts, torch.Tensor) else torch.from_numpy(inp.counts).cuda()
+        for prec in (emc.EMC_PREC_FP32, emc.EMC_PREC_BF16):
+            run = Run(inp, prec, counts_dev)
+            run.step()
+            torch.cuda.synchronize()
+            del run
+            torch.cuda.empty_cache()
         # reference copy of known size for scaling the FETCH_SIZE / WRITE_SIZE counters
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         bcopy = torch.empty_like(a)
         torch.cuda.synchronize()
         bcopy.copy_(a)
         torch.cuda.synchronize()
-        log("profile-once done: one iteration + a 1 GiB device copy")
+        log("profile-once done: one iteration per form + a 1 GiB device copy")
         return
 
-    for i in range(args.warmup):
-        run.step()
-        torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    K = args.steps
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(K)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(K):
-        run.step(evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    names = ["expand", "loglik", "estep", "compress", "finalize"]
-    per = {nm: [evs[i][s].elapsed_time(evs[i][s + 1]) for i in range(K)] for s, nm in enumerate(names)}
-    total_ms = [evs[i][0].elapsed_time(evs[i][5]) for i in range(K)]
-    span_ms = evs[0][0].elapsed_time(evs[K - 1][5])
-    ms_per_step = span_ms / K
-    log(f"timed {K} iterations: {ms_per_step:.1f} ms/iteration (wall {wall:.2f} s); loglik {run.loglik.item():.4f}")
-
-    gemm_flops = 2.0 * wl.n_data * wl.n_rot * n_valid  # log-likelihood contraction over valid pixels
-    t_gemm = float(np.mean(per["loglik"])) / 1e3
-    achieved = gemm_flops / t_gemm / 1e12
-    roofline = {"bound": "mfma", "kernel": "gemm_f32_kernel<NT> (log-likelihood, emc_loglik step)",
-                "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
-                "algorithmic_flops_per_launch": gemm_flops}
-    iter_flops = 4.0 * wl.n_data * wl.n_rot * n_valid
+    results = {}
+    counts_dev = inp.counts if isinstance(inp.counts, torch.Tensor) else torch.from_numpy(inp.counts).cuda()
+    for form, prec in (("plain-fp32", emc.EMC_PREC_FP32), ("bf16", emc.EMC_PREC_BF16)):
+        run = Run(inp, prec, counts_dev)
+        log(f"{form}: frames packed")
+        results[form] = time_form(run, args, n_valid)
+        del run
+        torch.cuda.empty_cache()
+    chosen = "bf16"
+    r = results[chosen]
+    wl_ = wl
     out = {
         "metric": "EMC iters/s (128³, 16k px, 25k rot, 100k pat); plain vs BF16+proposal",
-        "value": round(1000.0 / ms_per_step, 5),
+        "value": r["value"],
         "unit": "iters/s",
         "n_gpus": 1,
-        "steps": K,
+        "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": "bf16",
         "data": "synthetic (seeded Gaussian-atom Poisson frames, inputs resident in HBM)",
-        "config": {"workload": wl.name, "form": "plain-fp32", "grid": wl.grid_n, "n_pix": wl.n_pix,
-                   "n_pix_valid": n_valid, "n_rot": wl.n_rot, "n_data": wl.n_data,
-                   "photons_per_frame": wl.photons},
-        "roofline": roofline,
-        "steps_ms_median": {k: round(float(np.median(v)), 3) for k, v in per.items()},
-        "iteration_ms_min": round(float(np.min(total_ms)), 3),
-        "iteration_tflops_algorithmic": round(iter_flops / (ms_per_step / 1e3) / 1e12, 2),
-        "paper_flop_model_tflops": round(27.0 * wl.n_rot * wl.n_data * wl.n_pix / (ms_per_step / 1e3) / 1e12, 2),
+        "config": {"workload": wl_.name, "form": chosen, "grid": wl_.grid_n, "n_pix": wl_.n_pix,
+                   "n_pix_valid": n_valid, "n_rot": wl_.n_rot, "n_data": wl_.n_data,
+                   "photons_per_frame": wl_.photons},
+        "roofline": r["roofline"],
+        "forms": {k: {kk: vv for kk, vv in v.items()} for k, v in results.items()},
     }
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample (cpu baseline)")

@@ -16,27 +16,35 @@
  *  - Every array pointer is DEVICE memory owned by the caller.  The library
  *    never allocates; emc_iterate takes a caller workspace sized by
  *    emc_workspace_bytes.  All work is enqueued asynchronously on `stream`
- *    (no host synchronisation inside, except emc_pack_frames in BF16 mode,
- *    which reads back its range flag).
+ *    (no host synchronisation, except emc_pack_frames in BF16 form, which
+ *    reads back its range flag).
  *  - Arguments are validated on the host before anything is launched: on a
- *    negative status nothing has been launched or written, and
- *    emc_last_error() returns a message (thread-local).  A failed launch maps
- *    to EMC_ERR_HIP.  Array contents are not validated: any finite input has
- *    a defined result (non-unit quaternions are normalised, grid points
- *    outside the N^3 box contribute nothing).
+ *    negative status nothing has been launched or written (except
+ *    EMC_ERR_RANGE, see emc_pack_frames), and emc_last_error() returns a
+ *    message (thread-local).  A failed launch maps to EMC_ERR_HIP.  Array
+ *    contents are not validated: any finite input has a defined result
+ *    (non-unit quaternions are normalised, grid points outside the N^3 box
+ *    contribute nothing).
  *  - Model grid: N^3 float values, flat index l = (x*N + y)*N + z of grid
  *    point p_l = (x, y, z); pixel coordinate q_i (voxel units) is placed at
  *    R_j q_i + (N/2, N/2, N/2).  Interpolation weights f (eq. (2.8)) are the
  *    trilinear tent f(d) = prod_a max(0, 1 - |d_a|), in expansion and
  *    compression alike.
  *  - Rotations: quaternions (w, x, y, z), Hamilton convention, active.
- *  - Row strides: per-pixel rows are padded to emc_pix_stride(n_pix) (a
- *    multiple of 256) and per-rotation rows to emc_rot_stride(n_rot) (a
- *    multiple of 256); padding entries are written as zeros.
+ *  - Padded row lengths: ps = emc_pix_stride(n_pix), ds = emc_data_stride(n_data)
+ *    (multiples of 256).  Padding entries are written as zeros unless stated.
+ *  - Rotation-major storage of everything indexed (j, k): G[j][k], P[j][k]
+ *    with row length ds, frames contiguous.
  *  - Slices are floored at 1e-10 photons before the log and the sum; masked
  *    pixels (mask == 0) are excluded from every sum.
- *  - All 64-bit offsets: n_data * rot_stride and n_rot * pix_stride may
- *    exceed 2^31.
+ *  - The pixel list may be in any order (apply the same permutation to q,
+ *    mask and the counts' columns); compression is fastest when each run of
+ *    64 consecutive pixels is spatially compact on the detector (8 x 8 tiles).
+ *  - Precision: EMC_PREC_FP32 runs both contractions in FP32 MFMA;
+ *    EMC_PREC_BF16 runs them in BF16 MFMA with FP32 accumulation (counts exact,
+ *    slices split hi + lo with a per-rotation scale, responsibilities rounded
+ *    to BF16).  Both keep FP64 for S_j, b_k, the log-sum-exp, rho and the grid
+ *    accumulation.
  *
  * Thread safety: entry points are reentrant; calls that share output or
  * workspace buffers must be ordered by the caller (same stream or events).
@@ -63,8 +71,8 @@ typedef enum {
 } emc_status;
 
 typedef enum {
-  EMC_PREC_FP32 = 0, /* FP32 operands and FP32 MFMA; FP64 normalisation and grid sums */
-  EMC_PREC_BF16 = 1  /* reserved: BF16 MFMA form (not in this build)                  */
+  EMC_PREC_FP32 = 0, /* FP32 operands, FP32 MFMA                            */
+  EMC_PREC_BF16 = 1  /* BF16 operands (slices as hi + lo), BF16 MFMA, FP32 acc */
 } emc_precision;
 
 typedef enum {
@@ -94,71 +102,85 @@ const char* emc_version(void);
 /* Message describing the last non-OK status returned on this thread. */
 const char* emc_last_error(void);
 
-/* Padded row length of frames, slices and the centring vector: n_pix rounded
- * up to a multiple of 256 (0 if n_pix < 1). */
+/* ps: n_pix rounded up to a multiple of 256 (0 if n_pix < 1). */
 int64_t emc_pix_stride(int32_t n_pix);
 
-/* Padded row length of log-likelihood and responsibility rows: n_rot rounded
- * up to a multiple of 256 (0 if n_rot < 1). */
-int64_t emc_rot_stride(int32_t n_rot);
+/* ds: n_data rounded up to a multiple of 256 (0 if n_data < 1). */
+int64_t emc_data_stride(int32_t n_data);
+
+/* Bytes of the packed frames (emc_pack_frames output) for this problem. */
+emc_status emc_frames_bytes(const emc_problem* pb, size_t* bytes);
+
+/* Bytes of the slice buffer (emc_expand output, also the W' buffer). */
+emc_status emc_slices_bytes(const emc_problem* pb, size_t* bytes);
 
 /* Bytes of workspace emc_iterate needs for this problem (written to *bytes). */
 emc_status emc_workspace_bytes(const emc_problem* pb, size_t* bytes);
 
-/* Frames K_ik (Section 2.1: photon counts of frame k) -> GEMM operand.
+/* Frames K_ik (Section 2.1: photon counts of frame k) -> GEMM operands.
  *   counts   [n_data][n_pix] uint16 photon counts
- *   K_packed [n_data][pix_stride] float (FP32 form); masked and padding
- *            pixels are written as 0.  Counts are exact in FP32.            */
+ *   K_packed emc_frames_bytes bytes, 16-byte aligned: K [n_data][ps] followed by
+ *            KT [ps][ds] (element type float in FP32 form, bfloat16 in BF16
+ *            form); masked and padding pixels and padding frames are 0.
+ * BF16 form: counts above 256 are not exact in BF16 and give EMC_ERR_RANGE
+ * (the call then synchronises the stream; K_packed holds rounded values). */
 emc_status emc_pack_frames(const emc_problem* pb, const uint16_t* counts, void* K_packed,
                            hipStream_t stream);
 
 /* Expansion, eq. (2.9): W_ij = sum_l f(p_l - R_j q_i) model_l, floored at
- * 1e-10, returned as centred logs.
- *   model [N^3] float grid values
- *   c     [pix_stride] double out: centring c_i = mean of log W_ij over a fixed
- *         subset of at most 64 rotations (j = floor(t*n_rot/n_c)); 0 on
- *         masked/padding pixels.  Any c leaves the E-step unchanged (a shift
- *         constant in j); it keeps FP32 sums small.
- *   logW  [n_rot][pix_stride] float out: log W_ij - c_i, 0 on masked/padding
- *   S     [n_rot] double out: S_j = sum_{i valid} W_ij                       */
-emc_status emc_expand(const emc_problem* pb, const float* model, double* c, float* logW,
-                      double* S, hipStream_t stream);
+ * 1e-10, as centred logs A_ji = log W_ij - c_i.
+ *   model  [N^3] float grid values
+ *   c      [ps] double out: c_i = mean of log W_ij over a fixed subset of at most
+ *          64 rotations (j = floor(t*n_rot/n_c)); 0 on masked/padding pixels.
+ *          Any c leaves the E-step unchanged (a shift constant in j, added back
+ *          through b_k); it keeps the reduced-precision sums small.
+ *   slices emc_slices_bytes bytes out.  FP32: A [n_rot][ps] float.  BF16: hi
+ *          [n_rot][ps] followed by lo [n_rot][ps], bfloat16, with
+ *          A_ji ~ scale_j (hi_ji + lo_ji).  0 on masked/padding pixels.
+ *   S      [n_rot] double out: S_j = sum_{i valid} W_ij
+ *   scale  [n_rot] float out (BF16 form; may be NULL in FP32 form):
+ *          scale_j = max_i |A_ji| (1 if the row is 0)                        */
+emc_status emc_expand(const emc_problem* pb, const float* model, double* c, void* slices,
+                      double* S, float* scale, hipStream_t stream);
 
-/* Poisson log-likelihood, Section 2.2 / eq. (2.3) with the Poisson model, as a
- * dense contraction over pixels (FP32 MFMA):
- *   G [n_data][rot_stride] float out: G_kj = sum_i K_ik logW_ji (columns >= n_rot
- *     are left untouched)
- *   b [n_data] double out: b_k = sum_i K_ik c_i
- * so that Q_jk = G_kj + b_k - S_j exactly.                                  */
-emc_status emc_loglik(const emc_problem* pb, const void* K_packed, const float* logW,
-                      const double* c, float* G, double* b, hipStream_t stream);
+/* Poisson log-likelihood, Section 2.2 / eq. (2.3), as a dense contraction over
+ * pixels on the matrix cores:
+ *   G [n_rot][ds] float out: G_jk = sum_i A_ji K_ik (padding frames untouched)
+ *   b [n_data] double out:   b_k = sum_i K_ik c_i (FP64)
+ * so that Q_jk = G_jk + b_k - S_j.  `scale` is read in BF16 form only.      */
+emc_status emc_loglik(const emc_problem* pb, const void* K_packed, const void* slices,
+                      const float* scale, const double* c, float* G, double* b,
+                      hipStream_t stream);
 
 /* E-step, eq. (2.4), as an FP64 log-sum-exp over rotations of the log-joint
- * a_kj = Q_jk + log w_j = G_kj + b_k - S_j + log w_j:
- *   stats [n_data][2] double: (m_k, s_k) with m_k = max_j a_kj and
- *         s_k = sum_j exp(a_kj - m_k).  Written in FULL and PARTIAL mode; read
+ * a_jk = Q_jk + log w_j = G_jk + b_k - S_j + log w_j:
+ *   stats [n_data][2] double: (m_k, s_k) with m_k = max_j a_jk and
+ *         s_k = sum_j exp(a_jk - m_k).  Written in FULL and PARTIAL mode; read
  *         in FINALIZE mode, where the caller has combined the statistics of
- *         several rotation shares (m = max m_r, s = sum s_r exp(m_r - m)).
- *   P     [n_data][rot_stride] float out (FULL, FINALIZE): P_kj = exp(a_kj - m_k -
- *         log s_k); padding columns written 0.  P may alias G (in place).
+ *         several rotation shares (m = max_r m_r, s = sum_r s_r exp(m_r - m)),
+ *         the exchange Section 3.2 describes.
+ *   P     [n_rot][ds] out (FULL, FINALIZE): P_jk = exp(a_jk - m_k - log s_k);
+ *         float in FP32 form (may alias G), bfloat16 in BF16 form (must not
+ *         alias G); padding frames written 0.
  *   L     [n_data] double out (FULL, FINALIZE): log-evidence
  *         L_k = m_k + log s_k (eq. (2.1) objective term, without log K!).
- *   rho   [n_rot] double out (FULL, FINALIZE): rho_j = sum_k P_kj (overwritten).
+ *   rho   [n_rot] double out (FULL, FINALIZE): rho_j = sum_k P_jk of the stored
+ *         (rounded) P values.
  *   b     [n_data] double: b_k from emc_loglik (all modes).
  * In PARTIAL mode P, L, rho may be NULL.                                     */
 emc_status emc_responsibilities(const emc_problem* pb, const float* G, const double* S,
-                                const double* b, int32_t mode, double* stats, float* P,
+                                const double* b, int32_t mode, double* stats, void* P,
                                 double* L, double* rho, hipStream_t stream);
 
 /* Combined M- and c-step, eq. (2.11)-(2.12) with phi = 1, without the final
  * division:
- *   Wp  [n_rot][pix_stride] float out: W'_ji = sum_k P_kj K_ik (FP32 MFMA);
- *       may alias logW of emc_expand (no longer needed by then)
+ *   Wp  [n_rot][ps] float out: W'_ji = sum_k P_jk K_ik (matrix cores); may
+ *       alias the slices of emc_expand (no longer needed by then)
  *   num, den [N^3] double: num_l += sum_{j,i valid} f(p_l - R_j q_i) W'_ji,
- *       den_l += sum_{j,i valid} f(p_l - R_j q_i) rho_j (FP64 atomics).
+ *       den_l += sum_{j,i valid} f(p_l - R_j q_i) rho_j (FP64).
  *       accumulate == 0 zeroes them first; accumulate != 0 adds, so frame
  *       chunks (the k-direction split of Section 3.3) sum before division. */
-emc_status emc_compress(const emc_problem* pb, const float* P, const void* K_packed,
+emc_status emc_compress(const emc_problem* pb, const void* P, const void* K_packed,
                         const double* rho, float* Wp, double* num, double* den,
                         int32_t accumulate, hipStream_t stream);
 
@@ -173,13 +195,13 @@ emc_status emc_finalize(const emc_problem* pb, const double* num, const double* 
 /* One full iteration of Algorithm 1 over this problem's frames:
  * expand -> log-likelihood -> E-step -> M/c-step -> division.
  *   model_in  [N^3] float;  model_out [N^3] float (may alias model_in)
- *   K_packed  output of emc_pack_frames
+ *   K_packed  output of emc_pack_frames (same precision)
  *   loglik    device double scalar: mean log-evidence (see emc_finalize)
- *   P_out     optional [n_data][rot_stride] float responsibilities; NULL keeps
- *             them in the workspace
+ *   P_out     optional [n_rot][ds] responsibilities (float in FP32 form,
+ *             bfloat16 in BF16 form); NULL keeps them in the workspace
  *   ws        workspace of at least emc_workspace_bytes bytes, 256-byte aligned */
 emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void* K_packed,
-                       float* model_out, double* loglik, float* P_out, void* ws,
+                       float* model_out, double* loglik, void* P_out, void* ws,
                        size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus

@@ -24,15 +24,23 @@ emc_status fail(emc_status s, const char* fmt, ...) {
   return s;
 }
 
-#define HIP_TRY(expr, what)                                                      \
-  do {                                                                           \
-    hipError_t e_ = (expr);                                                      \
+#define HIP_TRY(expr, what)                                                                  \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
     if (e_ != hipSuccess) return fail(EMC_ERR_HIP, "%s: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHECK(x)                 \
+  do {                           \
+    emc_status s_ = (x);         \
+    if (s_ != EMC_OK) return s_; \
   } while (0)
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool is_bf16(const emc_problem* pb) { return pb->precision == EMC_PREC_BF16; }
 
 // Validate the scalar part of a problem and, if `geom`, its geometry pointers.
 emc_status check_problem(const emc_problem* pb, bool geom) {
@@ -42,8 +50,8 @@ emc_status check_problem(const emc_problem* pb, bool geom) {
   if (pb->n_rot < 1) return fail(EMC_ERR_INVALID_ARG, "n_rot=%d < 1", pb->n_rot);
   if (pb->n_data < 0) return fail(EMC_ERR_INVALID_ARG, "n_data=%d < 0", pb->n_data);
   if (pb->reserved != 0) return fail(EMC_ERR_INVALID_ARG, "reserved field must be 0");
-  if (pb->precision == EMC_PREC_BF16) return fail(EMC_ERR_UNSUPPORTED, "BF16 precision is not in this build");
-  if (pb->precision != EMC_PREC_FP32) return fail(EMC_ERR_INVALID_ARG, "unknown precision %d", pb->precision);
+  if (pb->precision != EMC_PREC_FP32 && pb->precision != EMC_PREC_BF16)
+    return fail(EMC_ERR_INVALID_ARG, "unknown precision %d", pb->precision);
   if (geom) {
     if (!pb->q || !pb->mask || !pb->quat || !pb->log_w) return fail(EMC_ERR_INVALID_ARG, "geometry pointer is NULL");
     if (!aligned(pb->q, 4) || !aligned(pb->quat, 16) || !aligned(pb->log_w, 8))
@@ -58,82 +66,121 @@ emc_status need(const void* p, size_t align, const char* name) {
   return EMC_OK;
 }
 
-#define CHECK(x)                   \
-  do {                             \
-    emc_status s_ = (x);           \
-    if (s_ != EMC_OK) return s_;   \
-  } while (0)
+struct Dims {
+  int64_t ps, ds, grid;
+  size_t elem;  // bytes of a packed frame / responsibility element
+};
+
+Dims dims_of(const emc_problem* pb) {
+  Dims d;
+  d.ps = round_up(pb->n_pix, 256);
+  d.ds = round_up(pb->n_data, 256);
+  d.grid = (int64_t)pb->grid_n * pb->grid_n * pb->grid_n;
+  d.elem = is_bf16(pb) ? 2 : 4;
+  return d;
+}
+
+size_t frames_bytes(const emc_problem* pb) {
+  const Dims d = dims_of(pb);
+  return ((size_t)pb->n_data * d.ps + (size_t)d.ps * d.ds) * d.elem;
+}
+
+size_t slices_bytes(const emc_problem* pb) { return (size_t)pb->n_rot * dims_of(pb).ps * sizeof(float); }
 
 struct Layout {
-  int64_t pix_stride, rot_stride, grid;
-  size_t off_slices, off_gp, off_S, off_c, off_b, off_stats, off_L, off_rho, off_num, off_den, total;
+  size_t slices, G, P, S, scale, c, b, stats, L, rho, num, den, total;
 };
 
 Layout layout_of(const emc_problem* pb) {
+  const Dims d = dims_of(pb);
   Layout L;
-  L.pix_stride = round_up(pb->n_pix, 256);
-  L.rot_stride = round_up(pb->n_rot, 256);
-  L.grid = (int64_t)pb->grid_n * pb->grid_n * pb->grid_n;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
     o += (size_t)round_up((int64_t)bytes, 256);
     return at;
   };
-  L.off_slices = take((size_t)pb->n_rot * L.pix_stride * sizeof(float));
-  L.off_gp = take((size_t)pb->n_data * L.rot_stride * sizeof(float));
-  L.off_S = take((size_t)pb->n_rot * sizeof(double));
-  L.off_c = take((size_t)L.pix_stride * sizeof(double));
-  L.off_b = take((size_t)pb->n_data * sizeof(double));
-  L.off_stats = take((size_t)pb->n_data * 2 * sizeof(double));
-  L.off_L = take((size_t)pb->n_data * sizeof(double));
-  L.off_rho = take((size_t)pb->n_rot * sizeof(double));
-  L.off_num = take((size_t)L.grid * sizeof(double));
-  L.off_den = take((size_t)L.grid * sizeof(double));
+  L.slices = take(slices_bytes(pb));  // A (or hi/lo), then W'
+  L.G = take((size_t)pb->n_rot * d.ds * sizeof(float));
+  L.P = is_bf16(pb) ? take((size_t)pb->n_rot * d.ds * 2) : L.G;  // FP32: P overwrites G in place
+  L.S = take((size_t)pb->n_rot * sizeof(double));
+  L.scale = take((size_t)pb->n_rot * sizeof(float));
+  L.c = take((size_t)d.ps * sizeof(double));
+  L.b = take((size_t)pb->n_data * sizeof(double));
+  L.stats = take((size_t)pb->n_data * 2 * sizeof(double));
+  L.L = take((size_t)pb->n_data * sizeof(double));
+  L.rho = take((size_t)pb->n_rot * sizeof(double));
+  L.num = take((size_t)d.grid * sizeof(double));
+  L.den = take((size_t)d.grid * sizeof(double));
   L.total = o;
   return L;
 }
 
-// Launch sequences shared by the step entry points and emc_iterate (no validation).
-emc_status run_expand(const emc_problem* pb, const float* model, double* c, float* logW, double* S, hipStream_t st) {
-  const int64_t ps = round_up(pb->n_pix, 256);
-  HIP_TRY(launch_centre(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, ps, pb->n_rot, c, st), "centre");
-  HIP_TRY(launch_expand(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, ps, pb->n_rot, c, logW, S, st),
-          "expand");
+// ---- launch sequences shared by the step entry points and emc_iterate (no validation) ----
+
+emc_status run_expand(const emc_problem* pb, const float* model, double* c, void* slices, double* S, float* scale,
+                      hipStream_t st) {
+  const Dims d = dims_of(pb);
+  HIP_TRY(launch_centre(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c, st), "centre");
+  if (is_bf16(pb))
+    HIP_TRY(launch_expand_bf16(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c, slices, S,
+                               scale, st),
+            "expand");
+  else
+    HIP_TRY(launch_expand(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c,
+                          (float*)slices, S, st),
+            "expand");
   return EMC_OK;
 }
 
-emc_status run_loglik(const emc_problem* pb, const void* K, const float* logW, const double* c, float* G, double* b,
-                      hipStream_t st) {
+emc_status run_loglik(const emc_problem* pb, const void* K, const void* slices, const float* scale, const double* c,
+                      float* G, double* b, hipStream_t st) {
   if (pb->n_data == 0) return EMC_OK;
-  const int64_t ps = round_up(pb->n_pix, 256), rs = round_up(pb->n_rot, 256);
-  HIP_TRY(launch_frame_dot((const float*)K, ps, pb->n_data, c, b, st), "frame_dot");
-  HIP_TRY(launch_gemm_f32_nt((const float*)K, logW, G, pb->n_data, pb->n_rot, ps, ps, ps, rs, st), "loglik gemm");
+  const Dims d = dims_of(pb);
+  HIP_TRY(launch_frame_dot(K, is_bf16(pb), d.ps, pb->n_data, c, b, st), "frame_dot");
+  if (is_bf16(pb)) {
+    const char* hi = (const char*)slices;
+    const char* lo = hi + (size_t)pb->n_rot * d.ps * 2;
+    HIP_TRY(launch_gemm_bf16_dual_nt(hi, lo, K, scale, G, pb->n_rot, pb->n_data, d.ps, d.ps, d.ps, d.ds, st),
+            "loglik gemm");
+  } else {
+    HIP_TRY(launch_gemm_f32_nt((const float*)slices, (const float*)K, G, pb->n_rot, pb->n_data, d.ps, d.ps, d.ps, d.ds,
+                               st),
+            "loglik gemm");
+  }
   return EMC_OK;
 }
 
 emc_status run_estep(const emc_problem* pb, const float* G, const double* S, const double* b, int32_t mode,
-                     double* stats, float* P, double* L, double* rho, hipStream_t st) {
-  const int64_t rs = round_up(pb->n_rot, 256);
+                     double* stats, void* P, double* L, double* rho, hipStream_t st) {
+  const Dims d = dims_of(pb);
   if (mode != EMC_RESP_FINALIZE)
-    HIP_TRY(launch_lse_stats(G, rs, pb->n_rot, pb->n_data, pb->log_w, S, b, stats, st), "lse_stats");
+    HIP_TRY(launch_lse_stats(G, d.ds, pb->n_rot, pb->n_data, pb->log_w, S, b, stats, st), "lse_stats");
   if (mode == EMC_RESP_PARTIAL) return EMC_OK;
-  HIP_TRY(launch_fill_zero_f64(rho, (size_t)pb->n_rot, st), "zero rho");
-  HIP_TRY(launch_lse_write(G, P, rs, pb->n_rot, pb->n_data, pb->log_w, S, stats, b, L, rho, st), "lse_write");
+  HIP_TRY(launch_lse_finish(stats, pb->n_data, L, st), "lse_finish");
+  if (is_bf16(pb))
+    HIP_TRY(launch_lse_write_bf16(G, d.ds, P, d.ds, pb->n_rot, pb->n_data, pb->log_w, S, b, L, rho, st), "lse_write");
+  else
+    HIP_TRY(launch_lse_write_f32(G, d.ds, (float*)P, d.ds, pb->n_rot, pb->n_data, pb->log_w, S, b, L, rho, st),
+            "lse_write");
   return EMC_OK;
 }
 
-emc_status run_compress(const emc_problem* pb, const float* P, const void* K, const double* rho, float* Wp,
+emc_status run_compress(const emc_problem* pb, const void* P, const void* K, const double* rho, float* Wp,
                         double* num, double* den, int32_t accumulate, hipStream_t st) {
-  const int64_t ps = round_up(pb->n_pix, 256), rs = round_up(pb->n_rot, 256);
-  const size_t grid = (size_t)pb->grid_n * pb->grid_n * pb->grid_n;
+  const Dims d = dims_of(pb);
   if (!accumulate) {
-    HIP_TRY(launch_fill_zero_f64(num, grid, st), "zero num");
-    HIP_TRY(launch_fill_zero_f64(den, grid, st), "zero den");
+    HIP_TRY(launch_fill_zero_f64(num, (size_t)d.grid, st), "zero num");
+    HIP_TRY(launch_fill_zero_f64(den, (size_t)d.grid, st), "zero den");
   }
   if (pb->n_data == 0) return EMC_OK;  // nothing to add: W' = 0 and rho = 0
-  HIP_TRY(launch_gemm_f32_tn(P, (const float*)K, Wp, pb->n_rot, ps, pb->n_data, rs, ps, ps, st), "mstep gemm");
-  HIP_TRY(launch_scatter(Wp, ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, st),
+  const char* KT = (const char*)K + (size_t)pb->n_data * d.ps * d.elem;
+  if (is_bf16(pb))
+    HIP_TRY(launch_gemm_bf16_nt(P, KT, Wp, pb->n_rot, d.ps, d.ds, d.ds, d.ds, d.ps, st), "mstep gemm");
+  else
+    HIP_TRY(launch_gemm_f32_nt((const float*)P, (const float*)KT, Wp, pb->n_rot, d.ps, d.ds, d.ds, d.ds, d.ps, st),
+            "mstep gemm");
+  HIP_TRY(launch_scatter(Wp, d.ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, st),
           "scatter");
   return EMC_OK;
 }
@@ -150,13 +197,27 @@ emc_status run_finalize(const emc_problem* pb, const double* num, const double* 
 
 extern "C" {
 
-const char* emc_version(void) { return "emc-gfx950 0.1 (fp32 mfma)"; }
+const char* emc_version(void) { return "emc-gfx950 0.2 (fp32 and bf16 mfma)"; }
 
 const char* emc_last_error(void) { return g_err.c_str(); }
 
 int64_t emc_pix_stride(int32_t n_pix) { return n_pix < 1 ? 0 : round_up(n_pix, 256); }
 
-int64_t emc_rot_stride(int32_t n_rot) { return n_rot < 1 ? 0 : round_up(n_rot, 256); }
+int64_t emc_data_stride(int32_t n_data) { return n_data < 1 ? 0 : round_up(n_data, 256); }
+
+emc_status emc_frames_bytes(const emc_problem* pb, size_t* bytes) {
+  CHECK(check_problem(pb, false));
+  if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = frames_bytes(pb);
+  return EMC_OK;
+}
+
+emc_status emc_slices_bytes(const emc_problem* pb, size_t* bytes) {
+  CHECK(check_problem(pb, false));
+  if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = slices_bytes(pb);
+  return EMC_OK;
+}
 
 emc_status emc_workspace_bytes(const emc_problem* pb, size_t* bytes) {
   CHECK(check_problem(pb, false));
@@ -167,39 +228,46 @@ emc_status emc_workspace_bytes(const emc_problem* pb, size_t* bytes) {
 
 emc_status emc_pack_frames(const emc_problem* pb, const uint16_t* counts, void* K_packed, hipStream_t st) {
   CHECK(check_problem(pb, true));
-  if (pb->n_data > 0) {
-    CHECK(need(counts, 2, "counts"));
-    CHECK(need(K_packed, 16, "K_packed"));
+  if (pb->n_data == 0) return EMC_OK;
+  CHECK(need(counts, 2, "counts"));
+  CHECK(need(K_packed, 16, "K_packed"));
+  const Dims d = dims_of(pb);
+  char* KT = (char*)K_packed + (size_t)pb->n_data * d.ps * d.elem;
+  HIP_TRY(launch_pack(counts, pb->mask, pb->n_pix, d.ps, pb->n_data, d.ds, K_packed, KT, is_bf16(pb), st), "pack");
+  if (is_bf16(pb)) {
+    int flag = 0;
+    HIP_TRY(read_range_flag(&flag, st), "range flag");
+    if (flag) return fail(EMC_ERR_RANGE, "a photon count exceeds 256, which BF16 cannot hold exactly");
   }
-  HIP_TRY(launch_pack_f32(counts, pb->mask, pb->n_pix, emc_pix_stride(pb->n_pix), pb->n_data, (float*)K_packed, st),
-          "pack");
   return EMC_OK;
 }
 
-emc_status emc_expand(const emc_problem* pb, const float* model, double* c, float* logW, double* S,
+emc_status emc_expand(const emc_problem* pb, const float* model, double* c, void* slices, double* S, float* scale,
                       hipStream_t st) {
   CHECK(check_problem(pb, true));
   CHECK(need(model, 4, "model"));
   CHECK(need(c, 16, "c"));
-  CHECK(need(logW, 16, "logW"));
+  CHECK(need(slices, 16, "slices"));
   CHECK(need(S, 8, "S"));
-  return run_expand(pb, model, c, logW, S, st);
+  if (is_bf16(pb)) CHECK(need(scale, 4, "scale"));
+  return run_expand(pb, model, c, slices, S, scale, st);
 }
 
-emc_status emc_loglik(const emc_problem* pb, const void* K_packed, const float* logW, const double* c, float* G,
-                      double* b, hipStream_t st) {
+emc_status emc_loglik(const emc_problem* pb, const void* K_packed, const void* slices, const float* scale,
+                      const double* c, float* G, double* b, hipStream_t st) {
   CHECK(check_problem(pb, false));
   if (pb->n_data == 0) return EMC_OK;
   CHECK(need(K_packed, 16, "K_packed"));
-  CHECK(need(logW, 16, "logW"));
+  CHECK(need(slices, 16, "slices"));
   CHECK(need(c, 16, "c"));
   CHECK(need(G, 16, "G"));
   CHECK(need(b, 8, "b"));
-  return run_loglik(pb, K_packed, logW, c, G, b, st);
+  if (is_bf16(pb)) CHECK(need(scale, 4, "scale"));
+  return run_loglik(pb, K_packed, slices, scale, c, G, b, st);
 }
 
-emc_status emc_responsibilities(const emc_problem* pb, const float* G, const double* S, const double* b,
-                                int32_t mode, double* stats, float* P, double* L, double* rho, hipStream_t st) {
+emc_status emc_responsibilities(const emc_problem* pb, const float* G, const double* S, const double* b, int32_t mode,
+                                double* stats, void* P, double* L, double* rho, hipStream_t st) {
   CHECK(check_problem(pb, false));
   if (mode != EMC_RESP_FULL && mode != EMC_RESP_PARTIAL && mode != EMC_RESP_FINALIZE)
     return fail(EMC_ERR_INVALID_ARG, "unknown mode %d", mode);
@@ -213,12 +281,14 @@ emc_status emc_responsibilities(const emc_problem* pb, const float* G, const dou
     if (mode != EMC_RESP_PARTIAL) {
       CHECK(need(P, 16, "P"));
       CHECK(need(L, 8, "L"));
+      if (is_bf16(pb) && (const void*)P == (const void*)G)
+        return fail(EMC_ERR_INVALID_ARG, "BF16 responsibilities may not alias G");
     }
   }
   return run_estep(pb, G, S, b, mode, stats, P, L, rho, st);
 }
 
-emc_status emc_compress(const emc_problem* pb, const float* P, const void* K_packed, const double* rho, float* Wp,
+emc_status emc_compress(const emc_problem* pb, const void* P, const void* K_packed, const double* rho, float* Wp,
                         double* num, double* den, int32_t accumulate, hipStream_t st) {
   CHECK(check_problem(pb, true));
   CHECK(need(num, 8, "num"));
@@ -247,7 +317,7 @@ emc_status emc_finalize(const emc_problem* pb, const double* num, const double* 
 }
 
 emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void* K_packed, float* model_out,
-                       double* loglik, float* P_out, void* ws, size_t ws_bytes, hipStream_t st) {
+                       double* loglik, void* P_out, void* ws, size_t ws_bytes, hipStream_t st) {
   CHECK(check_problem(pb, true));
   CHECK(need(model_in, 4, "model_in"));
   CHECK(need(model_out, 4, "model_out"));
@@ -259,20 +329,22 @@ emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void*
   if (!aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is not 256-byte aligned");
   if (ws_bytes < Lo.total) return fail(EMC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, Lo.total);
   char* w = (char*)ws;
-  float* slices = (float*)(w + Lo.off_slices);  // logW, then W'
-  float* GP = P_out ? P_out : (float*)(w + Lo.off_gp);
-  double* S = (double*)(w + Lo.off_S);
-  double* c = (double*)(w + Lo.off_c);
-  double* b = (double*)(w + Lo.off_b);
-  double* stats = (double*)(w + Lo.off_stats);
-  double* L = (double*)(w + Lo.off_L);
-  double* rho = (double*)(w + Lo.off_rho);
-  double* num = (double*)(w + Lo.off_num);
-  double* den = (double*)(w + Lo.off_den);
-  CHECK(run_expand(pb, model_in, c, slices, S, st));
-  CHECK(run_loglik(pb, K_packed, slices, c, GP, b, st));
-  CHECK(run_estep(pb, GP, S, b, EMC_RESP_FULL, stats, GP, L, rho, st));
-  CHECK(run_compress(pb, GP, K_packed, rho, slices, num, den, 0, st));
+  void* slices = w + Lo.slices;  // A (or hi/lo), then W'
+  float* G = (float*)(w + Lo.G);
+  void* P = P_out ? P_out : (void*)(w + Lo.P);
+  double* S = (double*)(w + Lo.S);
+  float* scale = (float*)(w + Lo.scale);
+  double* c = (double*)(w + Lo.c);
+  double* b = (double*)(w + Lo.b);
+  double* stats = (double*)(w + Lo.stats);
+  double* L = (double*)(w + Lo.L);
+  double* rho = (double*)(w + Lo.rho);
+  double* num = (double*)(w + Lo.num);
+  double* den = (double*)(w + Lo.den);
+  CHECK(run_expand(pb, model_in, c, slices, S, scale, st));
+  CHECK(run_loglik(pb, K_packed, slices, scale, c, G, b, st));
+  CHECK(run_estep(pb, G, S, b, EMC_RESP_FULL, stats, P, L, rho, st));
+  CHECK(run_compress(pb, P, K_packed, rho, (float*)slices, num, den, 0, st));
   CHECK(run_finalize(pb, num, den, model_in, model_out, L, pb->n_data, loglik, st));
   return EMC_OK;
 }

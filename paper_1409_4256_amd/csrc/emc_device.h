@@ -1,5 +1,6 @@
 // Device helpers and kernel launchers shared by the library's translation units.
 #pragma once
+#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -72,29 +73,40 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // ---- launchers (all asynchronous on `st`; return hipGetLastError()) ----
 hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t st);
-hipError_t launch_pack_f32(const uint16_t* counts, const uint8_t* mask, int n_pix, int64_t stride,
-                           int64_t n_data, float* K, hipStream_t st);
+// counts [n_data][n_pix] -> K [n_data][ps] and KT [ps][ds] (float or bf16); ds = data stride
+hipError_t launch_pack(const uint16_t* counts, const uint8_t* mask, int n_pix, int64_t ps, int64_t n_data,
+                       int64_t ds, void* K, void* KT, bool bf16, hipStream_t st);
+hipError_t read_range_flag(int* flag, hipStream_t st);  // synchronises `st`
 hipError_t launch_centre(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
                          int n_pix, int64_t stride, int n_rot, double* c, hipStream_t st);
 hipError_t launch_expand(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
                          int n_pix, int64_t stride, int n_rot, const double* c, float* logW, double* S,
                          hipStream_t st);
-hipError_t launch_frame_dot(const float* K, int64_t stride, int64_t n_data, const double* c, double* b,
+// hilo: hi plane [n_rot][stride] bf16 followed by lo plane [n_rot][stride] bf16
+hipError_t launch_expand_bf16(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
+                              int n_pix, int64_t stride, int n_rot, const double* c, void* hilo, double* S,
+                              float* scale, hipStream_t st);
+hipError_t launch_frame_dot(const void* K, bool bf16, int64_t stride, int64_t n_data, const double* c, double* b,
                             hipStream_t st);
-// C[M][N] = sum_k A(m,k) B(n,k), FP32 MFMA.
-//  NT: A(m,k) = A[m*lda + k], B(n,k) = B[n*ldb + k]; Kd must be a multiple of 32;
-//      rows m >= M and n >= N read as zero.
-//  TN: A(m,k) = A[k*lda + m], B(n,k) = B[k*ldb + n]; rows k >= Kd read as zero;
-//      lda >= roundup(M, 256) and ldb >= roundup(N, 128) (padded columns readable).
+// C[M][N] = sum_k A[m][k] B[n][k] (both operands contiguous along k), FP32 MFMA;
+// Kd must be a multiple of 32; rows m >= M and n >= N read as zero.
 hipError_t launch_gemm_f32_nt(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
                               int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st);
-hipError_t launch_gemm_f32_tn(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
-                              int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st);
+// BF16 MFMA, FP32 accumulation; Kd multiple of 32.  DUAL: C = row_scale[m] * (A_hi + A_lo) B^T.
+hipError_t launch_gemm_bf16_dual_nt(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
+                                    float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb, int64_t ldc,
+                                    hipStream_t st);
+hipError_t launch_gemm_bf16_nt(const void* A, const void* B, float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda,
+                               int64_t ldb, int64_t ldc, hipStream_t st);
 hipError_t launch_lse_stats(const float* G, int64_t ld, int n_rot, int64_t n_data, const double* log_w,
                             const double* S, const double* b, double* stats, hipStream_t st);
-hipError_t launch_lse_write(const float* G, float* P, int64_t ld, int n_rot, int64_t n_data,
-                            const double* log_w, const double* S, const double* stats, const double* b,
-                            double* L, double* rho, hipStream_t st);
+hipError_t launch_lse_finish(const double* stats, int64_t n_data, double* L, hipStream_t st);
+hipError_t launch_lse_write_f32(const float* G, int64_t ldg, float* P, int64_t ldp, int n_rot, int64_t n_data,
+                                const double* log_w, const double* S, const double* b, const double* L,
+                                double* rho, hipStream_t st);
+hipError_t launch_lse_write_bf16(const float* G, int64_t ldg, void* P, int64_t ldp, int n_rot, int64_t n_data,
+                                 const double* log_w, const double* S, const double* b, const double* L,
+                                 double* rho, hipStream_t st);
 hipError_t launch_scatter(const float* Wp, int64_t stride, const double* rho, const float* q,
                           const uint8_t* mask, const float* quat, int n_pix, int n_rot, int N, double* num,
                           double* den, hipStream_t st);

@@ -1,7 +1,8 @@
 // E-step, eq. (2.4): responsibilities as an FP64 log-sum-exp over rotations of
-// the log-joint a_kj = Q_jk + log w_j = G_kj + b_k - S_j + log w_j.  A frame's
-// normalisation needs only its maximum and the sum of exp(a - max); these two
-// statistics are also all that rotation shares must exchange (Section 3.2).
+// the log-joint a_jk = Q_jk + log w_j = G_jk + b_k - S_j + log w_j, on the
+// rotation-major layout G[j][k] (frames contiguous).  A frame's normalisation
+// needs only its maximum and the sum of exp(a - max); these two statistics are
+// also all that rotation shares must exchange (Section 3.2).
 #include "emc_device.h"
 
 namespace emc {
@@ -15,92 +16,147 @@ __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, doubl
   }
 }
 
-// One wave per frame: online (max, sum exp) in FP64 over the frame's row.
+constexpr int kStatFrames = 64;  // frames per workgroup: one per lane, 4 waves split the rotations
+
+// Per-frame (max, sum exp) of a_jk over all rotations, FP64, online.
 __global__ __launch_bounds__(256) void lse_stats_kernel(const float* __restrict__ G, int64_t ld, int n_rot,
                                                         int64_t n_data, const double* __restrict__ log_w,
                                                         const double* __restrict__ S,
                                                         const double* __restrict__ b,
                                                         double* __restrict__ stats) {
-  const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (k >= n_data) return;  // uniform per wave
-  const float* row = G + k * ld;
-  const double bk = b[k];
+  __shared__ double sm[4][kStatFrames], ss[4][kStatFrames];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t k = (int64_t)blockIdx.x * kStatFrames + lane;
+  const bool live = k < n_data;
+  const double bk = live ? b[k] : 0.0;
   double m = -INFINITY, s = 0.0;
-  for (int j = lane; j < n_rot; j += 64) {
-    const double a = ((double)row[j] + bk) + (log_w[j] - S[j]);
-    if (!(a > -INFINITY)) continue;  // zero prior weight: no contribution
-    if (a > m) {
-      s = s * exp(m - a) + 1.0;
-      m = a;
-    } else {
-      s += exp(a - m);
+  if (live) {
+    // four rotations per step so that four loads are in flight
+    for (int j0 = wave; j0 < n_rot; j0 += 16) {
+      float g[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 4 * u;
+        g[u] = j < n_rot ? G[(int64_t)j * ld + k] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + 4 * u;
+        if (j >= n_rot) break;
+        const double a = ((double)g[u] + bk) + (log_w[j] - S[j]);
+        if (!(a > -INFINITY)) continue;  // zero prior weight: no contribution
+        if (a > m) {
+          s = s * exp(m - a) + 1.0;
+          m = a;
+        } else {
+          s += exp(a - m);
+        }
+      }
     }
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const double m2 = __shfl_xor(m, o, 64), s2 = __shfl_xor(s, o, 64);
-    lse_merge(m, s, m2, s2);
-  }
-  if (lane == 0) {
+  sm[wave][lane] = m;
+  ss[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && live) {
+    for (int w = 1; w < 4; ++w) lse_merge(m, s, sm[w][lane], ss[w][lane]);
     stats[2 * k] = m;
     stats[2 * k + 1] = s;
   }
 }
 
-constexpr int kRowsPerBlock = 256;
+// L_k = m_k + log s_k.
+__global__ void lse_finish_kernel(const double* __restrict__ stats, int64_t n_data, double* __restrict__ L) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k < n_data) L[k] = stats[2 * k] + log(stats[2 * k + 1]);
+}
 
-// Workgroup = 256 consecutive rotations x 256 frames: coalesced row segments,
-// P written in place of G when they alias, rho_j accumulated per block in FP64
-// and added with one atomic per (block, rotation).  The first column of blocks
-// also writes the log-evidence L_k = m_k + log s_k.
-__global__ __launch_bounds__(256) void lse_write_kernel(const float* G, float* P, int64_t ld, int n_rot,
-                                                        int64_t n_data, const double* __restrict__ log_w,
+constexpr int kWriteRows = 8;  // rotations per workgroup of the write pass
+
+template <typename PT>
+__device__ __forceinline__ PT to_p(double v);
+template <>
+__device__ __forceinline__ float to_p<float>(double v) {
+  return (float)v;
+}
+template <>
+__device__ __forceinline__ __hip_bfloat16 to_p<__hip_bfloat16>(double v) {
+  return __float2bfloat16((float)v);
+}
+__device__ __forceinline__ double from_p(float v) { return (double)v; }
+__device__ __forceinline__ double from_p(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
+
+// P[j][k] = exp(G[j][k] + (log w_j - S_j) + (b_k - L_k)), written as PT (FP32 or
+// BF16) with zeros in the padding frames; rho_j = sum_k of the stored values,
+// reduced in the block (deterministic).  P may alias G when PT is float.
+template <typename PT>
+__global__ __launch_bounds__(256) void lse_write_kernel(const float* G, int64_t ldg, PT* P, int64_t ldp,
+                                                        int n_rot, int64_t n_data, const double* __restrict__ log_w,
                                                         const double* __restrict__ S,
-                                                        const double* __restrict__ stats,
-                                                        const double* __restrict__ b, double* __restrict__ L,
-                                                        double* __restrict__ rho) {
-  __shared__ double shift[kRowsPerBlock];  // b_k - L_k
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t k0 = (int64_t)blockIdx.y * kRowsPerBlock;
-  const int64_t k1 = (k0 + kRowsPerBlock) < n_data ? (k0 + kRowsPerBlock) : n_data;
-  {
-    const int64_t k = k0 + threadIdx.x;
-    if (k < k1) {
-      const double v = stats[2 * k] + log(stats[2 * k + 1]);
-      shift[threadIdx.x] = b[k] - v;
-      if (blockIdx.x == 0) L[k] = v;
+                                                        const double* __restrict__ b,
+                                                        const double* __restrict__ L, double* __restrict__ rho) {
+  __shared__ double red[kWriteRows][4];
+  const int j0 = blockIdx.x * kWriteRows;
+  double e[kWriteRows], acc[kWriteRows];
+#pragma unroll
+  for (int r = 0; r < kWriteRows; ++r) {
+    const int j = j0 + r;
+    e[r] = j < n_rot ? log_w[j] - S[j] : 0.0;
+    acc[r] = 0.0;
+  }
+  for (int64_t k = threadIdx.x; k < ldp; k += 256) {
+    const bool live = k < n_data;
+    const double sh = live ? b[k] - L[k] : 0.0;
+#pragma unroll
+    for (int r = 0; r < kWriteRows; ++r) {
+      const int j = j0 + r;
+      if (j >= n_rot) break;
+      PT p = to_p<PT>(0.0);
+      if (live) {
+        p = to_p<PT>(exp(((double)G[(int64_t)j * ldg + k] + sh) + e[r]));
+        acc[r] += from_p(p);
+      }
+      P[(int64_t)j * ldp + k] = p;
     }
   }
+#pragma unroll
+  for (int r = 0; r < kWriteRows; ++r) {
+    const double v = wave_sum(acc[r]);
+    if ((threadIdx.x & 63) == 0) red[r][threadIdx.x >> 6] = v;
+  }
   __syncthreads();
-  if (j >= ld) return;
-  if (j >= n_rot) {
-    for (int64_t k = k0; k < k1; ++k) P[k * ld + j] = 0.0f;
-    return;
+  if (threadIdx.x < kWriteRows) {
+    const int j = j0 + threadIdx.x;
+    if (j < n_rot) rho[j] = (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
   }
-  const double ej = log_w[j] - S[j];
-  double acc = 0.0;
-  for (int64_t k = k0; k < k1; ++k) {
-    const float p = (float)exp(((double)G[k * ld + j] + shift[k - k0]) + ej);
-    P[k * ld + j] = p;
-    acc += (double)p;
-  }
-  atomicAdd(rho + j, acc);
 }
 
 hipError_t launch_lse_stats(const float* G, int64_t ld, int n_rot, int64_t n_data, const double* log_w,
                             const double* S, const double* b, double* stats, hipStream_t st) {
   if (n_data == 0) return hipSuccess;
-  lse_stats_kernel<<<(unsigned)((n_data + 3) / 4), 256, 0, st>>>(G, ld, n_rot, n_data, log_w, S, b, stats);
+  lse_stats_kernel<<<(unsigned)((n_data + kStatFrames - 1) / kStatFrames), 256, 0, st>>>(G, ld, n_rot, n_data,
+                                                                                        log_w, S, b, stats);
   return hipGetLastError();
 }
 
-hipError_t launch_lse_write(const float* G, float* P, int64_t ld, int n_rot, int64_t n_data,
-                            const double* log_w, const double* S, const double* stats, const double* b,
-                            double* L, double* rho, hipStream_t st) {
+hipError_t launch_lse_finish(const double* stats, int64_t n_data, double* L, hipStream_t st) {
   if (n_data == 0) return hipSuccess;
-  dim3 grid((unsigned)((ld + 255) / 256), (unsigned)((n_data + kRowsPerBlock - 1) / kRowsPerBlock));
-  lse_write_kernel<<<grid, 256, 0, st>>>(G, P, ld, n_rot, n_data, log_w, S, stats, b, L, rho);
+  lse_finish_kernel<<<(unsigned)((n_data + 255) / 256), 256, 0, st>>>(stats, n_data, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_lse_write_f32(const float* G, int64_t ldg, float* P, int64_t ldp, int n_rot, int64_t n_data,
+                                const double* log_w, const double* S, const double* b, const double* L,
+                                double* rho, hipStream_t st) {
+  lse_write_kernel<float><<<(unsigned)((n_rot + kWriteRows - 1) / kWriteRows), 256, 0, st>>>(
+      G, ldg, P, ldp, n_rot, n_data, log_w, S, b, L, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_lse_write_bf16(const float* G, int64_t ldg, void* P, int64_t ldp, int n_rot, int64_t n_data,
+                                 const double* log_w, const double* S, const double* b, const double* L,
+                                 double* rho, hipStream_t st) {
+  lse_write_kernel<__hip_bfloat16><<<(unsigned)((n_rot + kWriteRows - 1) / kWriteRows), 256, 0, st>>>(
+      G, ldg, (__hip_bfloat16*)P, ldp, n_rot, n_data, log_w, S, b, L, rho);
   return hipGetLastError();
 }
 

@@ -30,6 +30,24 @@ __global__ __launch_bounds__(256) void centre_kernel(const float* __restrict__ m
   c[i] = acc / nc;
 }
 
+__device__ __forceinline__ double slice_value(const float* __restrict__ model, int N, const Rot& r,
+                                              const float* __restrict__ qi) {
+  const Stencil s = stencil_at(r, qi, N);
+  double W = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) W += s.w[k] * (double)model[s.idx[k]];
+  return fmax(W, kFloor);
+}
+
+__device__ __forceinline__ double block_sum4(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return t;
+}
+
 // One workgroup per rotation j (the paper's one-block-per-slice mapping of the
 // expansion kernel, Section 3.1): threads stride over pixels; S_j is reduced
 // in the block in FP64, so no atomics and a deterministic order.
@@ -47,34 +65,83 @@ __global__ __launch_bounds__(256) void expand_kernel(const float* __restrict__ m
   for (int64_t i = threadIdx.x; i < stride; i += 256) {
     float out = 0.0f;
     if (i < n_pix && mask[i]) {
-      const Stencil s = stencil_at(r, q + 3 * i, N);
-      double W = 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) W += s.w[k] * (double)model[s.idx[k]];
-      W = fmax(W, kFloor);
+      const double W = slice_value(model, N, r, q + 3 * i);
       sum += W;
       out = (float)(log(W) - c[i]);
     }
     row[i] = out;
   }
-  sum = wave_sum(sum);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  sum = block_sum4(sum, red);
+  if (threadIdx.x == 0) S[j] = sum;
+}
+
+// BF16 form: the centred log slice A_ji = log W_ij - c_i is written as two BF16
+// terms with a per-rotation scale, A_ji ~ scale_j (hi_ji + lo_ji), where
+// scale_j = max_i |A_ji|, hi = bf16(A / scale), lo = bf16(A / scale - hi).
+// A first pass finds the row maximum; the second recomputes the slice.
+__global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restrict__ model, int N,
+                                                          const float* __restrict__ q,
+                                                          const uint8_t* __restrict__ mask,
+                                                          const float* __restrict__ quat, int n_pix,
+                                                          int64_t stride, int64_t plane,
+                                                          const double* __restrict__ c,
+                                                          __hip_bfloat16* __restrict__ hi_all,
+                                                          double* __restrict__ S, float* __restrict__ scale) {
+  __shared__ double red[4];
+  __shared__ float redf[4];
+  const int j = blockIdx.x;
+  const Rot r = quat_rot(quat + 4 * (int64_t)j);
+  double sum = 0.0;
+  float amax = 0.0f;
+  for (int64_t i = threadIdx.x; i < n_pix; i += 256) {
+    if (!mask[i]) continue;
+    const double W = slice_value(model, N, r, q + 3 * i);
+    sum += W;
+    amax = fmaxf(amax, fabsf((float)(log(W) - c[i])));
+  }
+  sum = block_sum4(sum, red);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = amax;
   __syncthreads();
-  if (threadIdx.x == 0) S[j] = (red[0] + red[1]) + (red[2] + red[3]);
+  amax = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
+  const float sc = amax > 0.0f ? amax : 1.0f;
+  const float inv = 1.0f / sc;
+  if (threadIdx.x == 0) {
+    S[j] = sum;
+    scale[j] = sc;
+  }
+  __hip_bfloat16* hi = hi_all + (int64_t)j * stride;
+  __hip_bfloat16* lo = hi_all + plane + (int64_t)j * stride;
+  for (int64_t i = threadIdx.x; i < stride; i += 256) {
+    float h = 0.0f, l = 0.0f;
+    if (i < n_pix && mask[i]) {
+      const double W = slice_value(model, N, r, q + 3 * i);
+      const float a = (float)(log(W) - c[i]) * inv;
+      const __hip_bfloat16 hb = __float2bfloat16(a);
+      h = __bfloat162float(hb);
+      l = a - h;
+    }
+    hi[i] = __float2bfloat16(h);
+    lo[i] = __float2bfloat16(l);
+  }
 }
 
 // b_k = sum_i K_ik c_i in FP64: one wave per frame.
-__global__ __launch_bounds__(256) void frame_dot_kernel(const float* __restrict__ K, int64_t stride,
-                                                        int64_t n_data, const double* __restrict__ c,
-                                                        double* __restrict__ b) {
+__device__ __forceinline__ double as_double(float v) { return (double)v; }
+__device__ __forceinline__ double as_double(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void frame_dot_kernel(const T* __restrict__ K, int64_t stride, int64_t n_data,
+                                                        const double* __restrict__ c, double* __restrict__ b) {
   const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (k >= n_data) return;  // uniform per wave
-  const float* row = K + k * stride;
+  const T* row = K + k * stride;
   double acc = 0.0;
   for (int64_t i = 4 * lane; i < stride; i += 256) {
-    const float4 v = *reinterpret_cast<const float4*>(row + i);
-    acc += (double)v.x * c[i] + (double)v.y * c[i + 1] + (double)v.z * c[i + 2] + (double)v.w * c[i + 3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc += as_double(row[i + u]) * c[i + u];
   }
   acc = wave_sum(acc);
   if (lane == 0) b[k] = acc;
@@ -82,17 +149,6 @@ __global__ __launch_bounds__(256) void frame_dot_kernel(const float* __restrict_
 
 __global__ void fill_zero_f64_kernel(double* __restrict__ p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0.0;
-}
-
-__global__ void pack_f32_kernel(const uint16_t* __restrict__ counts, const uint8_t* __restrict__ mask,
-                                int n_pix, int64_t stride, int64_t n_data, float* __restrict__ K) {
-  const size_t total = (size_t)n_data * stride;
-  for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (size_t)gridDim.x * 256) {
-    const int64_t k = e / stride, i = e - k * stride;
-    float v = 0.0f;
-    if (i < n_pix && mask[i]) v = (float)counts[k * n_pix + i];
-    K[e] = v;
-  }
 }
 
 static inline unsigned grid_for(size_t n) {
@@ -103,14 +159,6 @@ static inline unsigned grid_for(size_t n) {
 hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t st) {
   if (n == 0) return hipSuccess;
   fill_zero_f64_kernel<<<grid_for(n), 256, 0, st>>>(p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_pack_f32(const uint16_t* counts, const uint8_t* mask, int n_pix, int64_t stride,
-                           int64_t n_data, float* K, hipStream_t st) {
-  const size_t n = (size_t)n_data * stride;
-  if (n == 0) return hipSuccess;
-  pack_f32_kernel<<<grid_for(n), 256, 0, st>>>(counts, mask, n_pix, stride, n_data, K);
   return hipGetLastError();
 }
 
@@ -128,10 +176,22 @@ hipError_t launch_expand(const float* model, int N, const float* q, const uint8_
   return hipGetLastError();
 }
 
-hipError_t launch_frame_dot(const float* K, int64_t stride, int64_t n_data, const double* c, double* b,
+hipError_t launch_expand_bf16(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
+                              int n_pix, int64_t stride, int n_rot, const double* c, void* hilo, double* S,
+                              float* scale, hipStream_t st) {
+  expand_bf16_kernel<<<(unsigned)n_rot, 256, 0, st>>>(model, N, q, mask, quat, n_pix, stride,
+                                                      (int64_t)n_rot * stride, c, (__hip_bfloat16*)hilo, S, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_frame_dot(const void* K, bool bf16, int64_t stride, int64_t n_data, const double* c, double* b,
                             hipStream_t st) {
   if (n_data == 0) return hipSuccess;
-  frame_dot_kernel<<<(unsigned)((n_data + 3) / 4), 256, 0, st>>>(K, stride, n_data, c, b);
+  if (bf16)
+    frame_dot_kernel<__hip_bfloat16><<<(unsigned)((n_data + 3) / 4), 256, 0, st>>>((const __hip_bfloat16*)K, stride,
+                                                                                  n_data, c, b);
+  else
+    frame_dot_kernel<float><<<(unsigned)((n_data + 3) / 4), 256, 0, st>>>((const float*)K, stride, n_data, c, b);
   return hipGetLastError();
 }
 

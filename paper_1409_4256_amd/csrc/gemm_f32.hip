@@ -1,6 +1,7 @@
-// FP32 MFMA GEMM for the two dense contractions of the iteration:
-//   log-likelihood  G_kj  = sum_i K_ik logW_ji    (NT: both operands pixel-contiguous)
-//   M-step          W'_ji = sum_k P_kj K_ik       (TN: both operands frame-major)
+// FP32 MFMA GEMM for the two dense contractions of the iteration, both with
+// operands contiguous along the reduction index ("NT"):
+//   log-likelihood  G_jk  = sum_i logW_ji K_ki    (reduction over pixels)
+//   M-step          W'_ji = sum_k P_jk KT_ik      (reduction over frames)
 //
 // Workgroup tile 256 x 128 x 32 (M x N x K), 4 waves in a 2 x 2 arrangement,
 // each wave 128 x 64 built from 8 x 4 v_mfma_f32_16x16x4_f32 tiles.  Operands
@@ -8,7 +9,6 @@
 // every lane reads 4 consecutive k of one row with a single 128-bit LDS read
 // and feeds them to 4 successive MFMAs (the k order inside a 16-wide chunk is
 // permuted identically for both operands, which leaves the sum unchanged).
-// TN tiles are transposed in registers on the way into LDS (4 x 4 blocks).
 #include "emc_device.h"
 
 namespace emc {
@@ -18,7 +18,6 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int BM = 256, BN = 128, BK = 32, LDK = BK + 4;
 constexpr int GROUP_M = 8;  // M tiles per schedule group: blocks sharing an M tile land on one XCD
 
-template <bool TN>
 __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ A, const float* __restrict__ B,
                                                        float* __restrict__ C, int64_t M, int64_t N, int64_t Kd,
                                                        int64_t lda, int64_t ldb, int64_t ldc) {
@@ -42,70 +41,32 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
 
   auto load_stage = [&](int64_t k0) {
-    if constexpr (!TN) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
-        const int64_t row = m0 + r;
-        ra[u] = row < M ? *reinterpret_cast<const f4*>(A + row * lda + k0 + 4 * c4) : zero;
-      }
+    for (int u = 0; u < 8; ++u) {
+      const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
+      const int64_t row = m0 + r;
+      ra[u] = row < M ? *reinterpret_cast<const f4*>(A + row * lda + k0 + 4 * c4) : zero;
+    }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
-        const int64_t row = n0 + r;
-        rb[u] = row < N ? *reinterpret_cast<const f4*>(B + row * ldb + k0 + 4 * c4) : zero;
-      }
-    } else {
-      const int mq = tid & 63;
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int kq = (tid >> 6) + 4 * u;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t k = k0 + 4 * kq + r;
-          ra[4 * u + r] = k < Kd ? *reinterpret_cast<const f4*>(A + k * lda + m0 + 4 * mq) : zero;
-        }
-      }
-      const int nq = tid & 31, kq = tid >> 5;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t k = k0 + 4 * kq + r;
-        rb[r] = k < Kd ? *reinterpret_cast<const f4*>(B + k * ldb + n0 + 4 * nq) : zero;
-      }
+    for (int u = 0; u < 4; ++u) {
+      const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
+      const int64_t row = n0 + r;
+      rb[u] = row < N ? *reinterpret_cast<const f4*>(B + row * ldb + k0 + 4 * c4) : zero;
     }
   };
 
   auto store_stage = [&](int buf) {
     float* as = As[buf];
     float* bs = Bs[buf];
-    if constexpr (!TN) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
-        *reinterpret_cast<f4*>(as + r * LDK + 4 * c4) = ra[u];
-      }
+    for (int u = 0; u < 8; ++u) {
+      const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
+      *reinterpret_cast<f4*>(as + r * LDK + 4 * c4) = ra[u];
+    }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
-        *reinterpret_cast<f4*>(bs + r * LDK + 4 * c4) = rb[u];
-      }
-    } else {
-      const int mq = tid & 63;
-#pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int kq = (tid >> 6) + 4 * u;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          f4 v = {ra[4 * u + 0][c], ra[4 * u + 1][c], ra[4 * u + 2][c], ra[4 * u + 3][c]};
-          *reinterpret_cast<f4*>(as + (4 * mq + c) * LDK + 4 * kq) = v;
-        }
-      }
-      const int nq = tid & 31, kq = tid >> 5;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        f4 v = {rb[0][c], rb[1][c], rb[2][c], rb[3][c]};
-        *reinterpret_cast<f4*>(bs + (4 * nq + c) * LDK + 4 * kq) = v;
-      }
+    for (int u = 0; u < 4; ++u) {
+      const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
+      *reinterpret_cast<f4*>(bs + r * LDK + 4 * c4) = rb[u];
     }
   };
 
@@ -162,23 +123,12 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
     }
 }
 
-template <bool TN>
-static hipError_t launch(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda,
-                         int64_t ldb, int64_t ldc, hipStream_t st) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  gemm_f32_kernel<TN><<<(unsigned)tiles, 256, 0, st>>>(A, B, C, M, N, Kd, lda, ldb, ldc);
-  return hipGetLastError();
-}
-
 hipError_t launch_gemm_f32_nt(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
                               int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st) {
-  return launch<false>(A, B, C, M, N, Kd, lda, ldb, ldc, st);
-}
-
-hipError_t launch_gemm_f32_tn(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
-                              int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st) {
-  return launch<true>(A, B, C, M, N, Kd, lda, ldb, ldc, st);
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  gemm_f32_kernel<<<(unsigned)tiles, 256, 0, st>>>(A, B, C, M, N, Kd, lda, ldb, ldc);
+  return hipGetLastError();
 }
 
 }  // namespace emc

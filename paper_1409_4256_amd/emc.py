@@ -27,9 +27,9 @@ EMC_RESP_FULL = 0
 EMC_RESP_PARTIAL = 1
 EMC_RESP_FINALIZE = 2
 
-EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_rot_stride", "emc_workspace_bytes",
-           "emc_pack_frames", "emc_expand", "emc_loglik", "emc_responsibilities", "emc_compress",
-           "emc_finalize", "emc_iterate")
+EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride", "emc_frames_bytes",
+           "emc_slices_bytes", "emc_workspace_bytes", "emc_pack_frames", "emc_expand", "emc_loglik",
+           "emc_responsibilities", "emc_compress", "emc_finalize", "emc_iterate")
 
 
 class EmcError(RuntimeError):
@@ -72,11 +72,13 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_version.restype = ctypes.c_char_p
     lib.emc_last_error.restype = ctypes.c_char_p
     lib.emc_pix_stride.argtypes, lib.emc_pix_stride.restype = [i32], i64
-    lib.emc_rot_stride.argtypes, lib.emc_rot_stride.restype = [i32], i64
-    lib.emc_workspace_bytes.argtypes, lib.emc_workspace_bytes.restype = [_PB, ctypes.POINTER(ctypes.c_size_t)], st
+    lib.emc_data_stride.argtypes, lib.emc_data_stride.restype = [i32], i64
+    szp = ctypes.POINTER(ctypes.c_size_t)
+    for fn in (lib.emc_frames_bytes, lib.emc_slices_bytes, lib.emc_workspace_bytes):
+        fn.argtypes, fn.restype = [_PB, szp], st
     lib.emc_pack_frames.argtypes, lib.emc_pack_frames.restype = [_PB, _P, _P, _P], st
-    lib.emc_expand.argtypes, lib.emc_expand.restype = [_PB, _P, _P, _P, _P, _P], st
-    lib.emc_loglik.argtypes, lib.emc_loglik.restype = [_PB, _P, _P, _P, _P, _P, _P], st
+    lib.emc_expand.argtypes, lib.emc_expand.restype = [_PB, _P, _P, _P, _P, _P, _P], st
+    lib.emc_loglik.argtypes, lib.emc_loglik.restype = [_PB, _P, _P, _P, _P, _P, _P, _P], st
     lib.emc_responsibilities.argtypes = [_PB, _P, _P, _P, i32, _P, _P, _P, _P, _P]
     lib.emc_responsibilities.restype = st
     lib.emc_compress.argtypes, lib.emc_compress.restype = [_PB, _P, _P, _P, _P, _P, _P, i32, _P], st
@@ -92,7 +94,7 @@ def _check(status: int):
         raise EmcError(status, load().emc_last_error().decode())
 
 
-def _ptr(t, dtype=None, numel=None, name="tensor", allow_none=False):
+def _ptr(t, dtype=None, numel=None, name="tensor", allow_none=False, nbytes=None):
     """Device pointer of a contiguous GPU tensor (checked), or None."""
     if t is None:
         if allow_none:
@@ -108,6 +110,8 @@ def _ptr(t, dtype=None, numel=None, name="tensor", allow_none=False):
         raise ValueError(f"{name} must be contiguous")
     if numel is not None and t.numel() < numel:
         raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} has {t.numel() * t.element_size()} bytes, needs {nbytes}")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -160,8 +164,24 @@ class Geometry:
         return emc_pix_stride(self.pb.n_pix)
 
     @property
-    def rot_stride(self):
-        return emc_rot_stride(self.pb.n_rot)
+    def data_stride(self):
+        return emc_data_stride(self.pb.n_data)
+
+    @property
+    def bf16(self):
+        return self.pb.precision == EMC_PREC_BF16
+
+    @property
+    def p_dtype(self):
+        """torch dtype of packed frames and responsibilities in this precision."""
+        import torch
+
+        return torch.bfloat16 if self.bf16 else torch.float32
+
+    def with_precision(self, precision):
+        g = self.with_frames(self.n_data)
+        g.pb.precision = int(precision)
+        return g
 
 
 # ------------------------------------------------------------------------- entry points
@@ -173,14 +193,40 @@ def emc_pix_stride(n_pix: int) -> int:
     return int(load().emc_pix_stride(int(n_pix)))
 
 
-def emc_rot_stride(n_rot: int) -> int:
-    return int(load().emc_rot_stride(int(n_rot)))
+def emc_data_stride(n_data: int) -> int:
+    return int(load().emc_data_stride(int(n_data)))
+
+
+def _size_query(fn, geo):
+    n = ctypes.c_size_t(0)
+    _check(fn(ctypes.byref(geo.pb), ctypes.byref(n)))
+    return int(n.value)
+
+
+def emc_frames_bytes(geo: Geometry) -> int:
+    return _size_query(load().emc_frames_bytes, geo)
+
+
+def emc_slices_bytes(geo: Geometry) -> int:
+    return _size_query(load().emc_slices_bytes, geo)
 
 
 def emc_workspace_bytes(geo: Geometry) -> int:
-    n = ctypes.c_size_t(0)
-    _check(load().emc_workspace_bytes(ctypes.byref(geo.pb), ctypes.byref(n)))
-    return int(n.value)
+    return _size_query(load().emc_workspace_bytes, geo)
+
+
+def frames_tensor(geo: Geometry):
+    """An uninitialised device tensor sized for emc_pack_frames' output."""
+    import torch
+
+    n = emc_frames_bytes(geo) // (2 if geo.bf16 else 4)
+    return torch.empty(max(n, 8), dtype=geo.p_dtype, device="cuda")
+
+
+def slices_tensor(geo: Geometry):
+    import torch
+
+    return torch.empty(max(emc_slices_bytes(geo) // 4, 4), dtype=torch.float32, device="cuda")
 
 
 def emc_pack_frames(geo: Geometry, counts, K_packed, stream=None):
@@ -189,29 +235,32 @@ def emc_pack_frames(geo: Geometry, counts, K_packed, stream=None):
     n = geo.n_data
     _check(load().emc_pack_frames(ctypes.byref(geo.pb),
                                   _ptr(counts, torch.uint16, n * geo.n_pix, "counts") if n else None,
-                                  _ptr(K_packed, torch.float32, n * geo.pix_stride, "K_packed") if n else None,
+                                  _ptr(K_packed, None, None, "K_packed", nbytes=emc_frames_bytes(geo)) if n else None,
                                   _stream(stream)))
 
 
-def emc_expand(geo: Geometry, model, c, logW, S, stream=None):
+def emc_expand(geo: Geometry, model, c, slices, S, scale=None, stream=None):
     import torch
 
     _check(load().emc_expand(ctypes.byref(geo.pb), _ptr(model, torch.float32, geo.grid_n ** 3, "model"),
                              _ptr(c, torch.float64, geo.pix_stride, "c"),
-                             _ptr(logW, torch.float32, geo.n_rot * geo.pix_stride, "logW"),
-                             _ptr(S, torch.float64, geo.n_rot, "S"), _stream(stream)))
+                             _ptr(slices, None, None, "slices", nbytes=emc_slices_bytes(geo)),
+                             _ptr(S, torch.float64, geo.n_rot, "S"),
+                             _ptr(scale, torch.float32, geo.n_rot, "scale", allow_none=not geo.bf16),
+                             _stream(stream)))
 
 
-def emc_loglik(geo: Geometry, K_packed, logW, c, G, b, stream=None):
+def emc_loglik(geo: Geometry, K_packed, slices, scale, c, G, b, stream=None):
     import torch
 
     n = geo.n_data
     if n == 0:
         return
-    _check(load().emc_loglik(ctypes.byref(geo.pb), _ptr(K_packed, torch.float32, n * geo.pix_stride, "K_packed"),
-                             _ptr(logW, torch.float32, geo.n_rot * geo.pix_stride, "logW"),
+    _check(load().emc_loglik(ctypes.byref(geo.pb), _ptr(K_packed, None, None, "K_packed", nbytes=emc_frames_bytes(geo)),
+                             _ptr(slices, None, None, "slices", nbytes=emc_slices_bytes(geo)),
+                             _ptr(scale, torch.float32, geo.n_rot, "scale", allow_none=not geo.bf16),
                              _ptr(c, torch.float64, geo.pix_stride, "c"),
-                             _ptr(G, torch.float32, n * geo.rot_stride, "G"),
+                             _ptr(G, torch.float32, geo.n_rot * geo.data_stride, "G"),
                              _ptr(b, torch.float64, n, "b"), _stream(stream)))
 
 
@@ -222,12 +271,12 @@ def emc_responsibilities(geo: Geometry, G, S, b, mode, stats, P=None, L=None, rh
     full = mode != EMC_RESP_PARTIAL
     _check(load().emc_responsibilities(
         ctypes.byref(geo.pb),
-        _ptr(G, torch.float32, n * geo.rot_stride, "G") if n else None,
+        _ptr(G, torch.float32, geo.n_rot * geo.data_stride, "G") if n else None,
         _ptr(S, torch.float64, geo.n_rot, "S"),
         _ptr(b, torch.float64, n, "b") if n else None,
         int(mode),
         _ptr(stats, torch.float64, 2 * n, "stats") if n else None,
-        _ptr(P, torch.float32, n * geo.rot_stride, "P", allow_none=not full) if n else None,
+        _ptr(P, geo.p_dtype, geo.n_rot * geo.data_stride, "P", allow_none=not full) if n else None,
         _ptr(L, torch.float64, n, "L", allow_none=not full) if n else None,
         _ptr(rho, torch.float64, geo.n_rot, "rho", allow_none=not full),
         _stream(stream)))
@@ -240,8 +289,8 @@ def emc_compress(geo: Geometry, P, K_packed, rho, Wp, num, den, accumulate=False
     M = geo.grid_n ** 3
     _check(load().emc_compress(
         ctypes.byref(geo.pb),
-        _ptr(P, torch.float32, n * geo.rot_stride, "P") if n else None,
-        _ptr(K_packed, torch.float32, n * geo.pix_stride, "K_packed") if n else None,
+        _ptr(P, geo.p_dtype, geo.n_rot * geo.data_stride, "P") if n else None,
+        _ptr(K_packed, None, None, "K_packed", nbytes=emc_frames_bytes(geo)) if n else None,
         _ptr(rho, torch.float64, geo.n_rot, "rho") if n else None,
         _ptr(Wp, torch.float32, geo.n_rot * geo.pix_stride, "Wp") if n else None,
         _ptr(num, torch.float64, M, "num"), _ptr(den, torch.float64, M, "den"), int(bool(accumulate)),
@@ -270,7 +319,7 @@ def emc_iterate(geo: Geometry, model_in, K_packed, model_out, loglik, P_out=None
         raise ValueError("workspace tensor required (emc_workspace_bytes bytes, uint8)")
     _check(load().emc_iterate(
         ctypes.byref(geo.pb), _ptr(model_in, torch.float32, M, "model_in"),
-        _ptr(K_packed, torch.float32, n * geo.pix_stride, "K_packed") if n else None,
+        _ptr(K_packed, None, None, "K_packed", nbytes=emc_frames_bytes(geo)) if n else None,
         _ptr(model_out, torch.float32, M, "model_out"), _ptr(loglik, torch.float64, 1, "loglik"),
-        _ptr(P_out, torch.float32, n * geo.rot_stride, "P_out", allow_none=True),
+        _ptr(P_out, geo.p_dtype, geo.n_rot * geo.data_stride, "P_out", allow_none=True),
         _ptr(ws, torch.uint8, need, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream)))

@@ -1,6 +1,6 @@
 """Helpers for the GPU parity tests: run the C-ABI entry points on device tensors
 and bring every intermediate back as float64 numpy arrays in the oracle's index
-order.  Comparison metrics follow the tolerances of the plain FP32 path."""
+order (rotation j, frame k, pixel i)."""
 from __future__ import annotations
 
 import numpy as np
@@ -9,10 +9,10 @@ import torch
 from paper_1409_4256_amd import emc
 
 
-def geometry(grid_n, q, mask, quat, log_w, n_data):
+def geometry(grid_n, q, mask, quat, log_w, n_data, precision=emc.EMC_PREC_FP32):
     t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dt)
     return emc.Geometry(grid_n, t(q, torch.float64), t(mask, torch.uint8), t(quat, torch.float64),
-                        t(log_w, torch.float64), n_data)
+                        t(log_w, torch.float64), n_data, precision)
 
 
 def upload_counts(counts):
@@ -22,73 +22,87 @@ def upload_counts(counts):
 
 
 def pack(geo, counts_dev):
-    K = torch.empty(max(1, geo.n_data * geo.pix_stride), dtype=torch.float32, device="cuda")
+    K = emc.frames_tensor(geo)
     emc.emc_pack_frames(geo, counts_dev, K)
     return K
 
 
-def run_steps(geo, model, K, frame_chunk=None):
-    """expand -> loglik -> responsibilities -> compress (optionally in frame chunks) -> finalize."""
+def _slices_f64(geo, slices, scale):
+    """Centred log slices A_ji as float64 [n_rot][ps] (hi + lo rescaled in BF16 form)."""
+    nr, ps = geo.n_rot, geo.pix_stride
+    if not geo.bf16:
+        return slices[:nr * ps].view(nr, ps).double()
+    hl = slices.view(torch.bfloat16)
+    hi = hl[:nr * ps].view(nr, ps).double()
+    lo = hl[nr * ps:2 * nr * ps].view(nr, ps).double()
+    return (hi + lo) * scale.double()[:, None]
+
+
+def run_steps(geo, model, K, frame_chunks=None):
+    """expand -> loglik -> responsibilities -> compress -> finalize.
+
+    `frame_chunks` is a list of (geometry, K_packed, offset) per chunk of frames
+    (each packed on its own); None runs the whole frame set at once."""
     dev = "cuda"
     N3 = geo.grid_n ** 3
-    ps, rs = geo.pix_stride, geo.rot_stride
-    n = geo.n_data
+    ps = geo.pix_stride
     m = torch.as_tensor(np.asarray(model, dtype=np.float32)).to(dev)
     c = torch.empty(ps, dtype=torch.float64, device=dev)
-    logW = torch.empty(geo.n_rot * ps, dtype=torch.float32, device=dev)
+    slices = emc.slices_tensor(geo)
     S = torch.empty(geo.n_rot, dtype=torch.float64, device=dev)
-    emc.emc_expand(geo, m, c, logW, S)
-    out = dict(c=c, logW=logW.clone(), S=S)
-    G = torch.full((max(1, n * rs),), float("nan"), dtype=torch.float32, device=dev)
-    b = torch.empty(max(1, n), dtype=torch.float64, device=dev)
-    stats = torch.empty(max(1, 2 * n), dtype=torch.float64, device=dev)
-    P = torch.empty_like(G)
-    L = torch.empty(max(1, n), dtype=torch.float64, device=dev)
+    scale = torch.empty(geo.n_rot, dtype=torch.float32, device=dev)
+    emc.emc_expand(geo, m, c, slices, S, scale)
+    out = dict(c=c, A=_slices_f64(geo, slices, scale), S=S, scale=scale)
+    chunks = frame_chunks or [(geo, K, 0)]
     num = torch.empty(N3, dtype=torch.float64, device=dev)
     den = torch.empty(N3, dtype=torch.float64, device=dev)
     Wp = torch.empty(geo.n_rot * ps, dtype=torch.float32, device=dev)
+    n = geo.n_data
+    Gs, Ps, bs, Ls, sts = [], [], [], [], []
     rho_tot = torch.zeros(geo.n_rot, dtype=torch.float64, device=dev)
-    chunk = n if not frame_chunk else frame_chunk
-    starts = list(range(0, n, chunk)) if n else [0]
     Wp_tot = torch.zeros(geo.n_rot * ps, dtype=torch.float64, device=dev)
-    for ci, s in enumerate(starts):
-        nc = min(chunk, n - s) if n else 0
-        g = geo.with_frames(nc)
-        Kc = K[s * ps:(s + nc) * ps] if nc else K
-        Gc = G[s * rs:(s + nc) * rs] if nc else G
-        Pc = P[s * rs:(s + nc) * rs] if nc else P
+    for ci, (g, Kc, off) in enumerate(chunks):
+        nc, ds = g.n_data, g.data_stride
+        G = torch.full((max(1, g.n_rot * ds),), float("nan"), dtype=torch.float32, device=dev)
+        b = torch.empty(max(1, nc), dtype=torch.float64, device=dev)
+        stats = torch.empty(max(1, 2 * nc), dtype=torch.float64, device=dev)
+        P = torch.empty(max(1, g.n_rot * ds), dtype=g.p_dtype, device=dev)
+        L = torch.empty(max(1, nc), dtype=torch.float64, device=dev)
         rho = torch.empty(geo.n_rot, dtype=torch.float64, device=dev)
-        emc.emc_loglik(g, Kc, logW, c, Gc, b[s:s + nc] if nc else b)
-        emc.emc_responsibilities(g, Gc, S, b[s:s + nc] if nc else b, emc.EMC_RESP_FULL,
-                                 stats[2 * s:2 * (s + nc)] if nc else stats, Pc, L[s:s + nc] if nc else L, rho)
-        emc.emc_compress(g, Pc, Kc, rho, Wp, num, den, accumulate=ci > 0)
-        rho_tot += rho
-        Wp_tot += Wp.double() if nc else 0
+        emc.emc_loglik(g, Kc, slices, scale, c, G, b)
+        Gc = G.clone()
+        emc.emc_responsibilities(g, G, S, b, emc.EMC_RESP_FULL, stats, P, L, rho)
+        emc.emc_compress(g, P, Kc, rho, Wp, num, den, accumulate=ci > 0)
+        if nc:
+            rho_tot += rho
+            Wp_tot += Wp.double()
+            Gs.append(Gc[:g.n_rot * ds].view(g.n_rot, ds)[:, :nc].double())
+            Ps.append(P[:g.n_rot * ds].view(g.n_rot, ds).double())
+            bs.append(b[:nc])
+            Ls.append(L[:nc])
+            sts.append(stats[:2 * nc].view(nc, 2))
+        # after compress the slice buffer holds W' when Wp aliases it; here it does not
     model_out = torch.empty(N3, dtype=torch.float32, device=dev)
     loglik = torch.empty(1, dtype=torch.float64, device=dev)
-    emc.emc_finalize(geo, num, den, m, model_out, L, n, loglik)
+    L_all = torch.cat(Ls) if Ls else torch.empty(1, dtype=torch.float64, device=dev)
+    emc.emc_finalize(geo, num, den, m, model_out, L_all, n, loglik)
     torch.cuda.synchronize()
-    out.update(G=G, b=b, stats=stats, P=P, L=L, rho=rho_tot, Wp=Wp_tot, num=num, den=den, model=model_out,
-               loglik=loglik)
-    return to_oracle_order(geo, out)
-
-
-def to_oracle_order(geo, out):
-    n, nr, npx, ps, rs = geo.n_data, geo.n_rot, geo.n_pix, geo.pix_stride, geo.rot_stride
-    h = {k: v.detach().double().cpu().numpy() for k, v in out.items()}
-    r = dict(c=h["c"][:npx], S=h["S"], num=h["num"], den=h["den"], model=h["model"],
-             loglik=float(h["loglik"][0]), rho=h["rho"])
-    r["logW_c"] = h["logW"].reshape(nr, ps)[:, :npx]                      # log W - c
-    r["logW_pad"] = h["logW"].reshape(nr, ps)[:, npx:]
-    r["Wp"] = h["Wp"].reshape(nr, ps)[:, :npx]
-    if n:
-        G = h["G"][:n * rs].reshape(n, rs)[:, :nr]
-        r["Q"] = (G + h["b"][:n, None] - h["S"][None, :]).T             # [j][k]
-        r["P"] = h["P"][:n * rs].reshape(n, rs)[:, :nr].T               # [j][k]
-        r["P_pad"] = h["P"][:n * rs].reshape(n, rs)[:, nr:]
-        r["L"] = h["L"][:n]
-        r["stats"] = h["stats"][:2 * n].reshape(n, 2)
-    return r
+    r = {k: v.detach().double().cpu().numpy() for k, v in out.items()}
+    res = dict(c=r["c"][:geo.n_pix], S=r["S"], scale=r["scale"], num=num.cpu().numpy(), den=den.cpu().numpy(),
+               model=model_out.double().cpu().numpy(), loglik=float(loglik.item()), rho=rho_tot.cpu().numpy())
+    res["logW_c"] = r["A"][:, :geo.n_pix]
+    res["logW_pad"] = r["A"][:, geo.n_pix:]
+    res["Wp"] = Wp_tot.view(geo.n_rot, ps)[:, :geo.n_pix].cpu().numpy()
+    if Gs:
+        S_ = S.double()
+        res["Q"] = torch.cat([G_ + b_[None, :] - S_[:, None] for G_, b_ in zip(Gs, bs)], dim=1).cpu().numpy()
+        Pfull = [P_[:, :g.n_data] for P_, (g, _, _) in zip(Ps, [ch for ch in chunks if ch[0].n_data])]
+        Ppad = [P_[:, g.n_data:] for P_, (g, _, _) in zip(Ps, [ch for ch in chunks if ch[0].n_data])]
+        res["P"] = torch.cat(Pfull, dim=1).cpu().numpy()
+        res["P_pad_max"] = max(float(x.abs().max()) if x.numel() else 0.0 for x in Ppad)
+        res["L"] = torch.cat(Ls).cpu().numpy()
+        res["stats"] = torch.cat(sts).cpu().numpy()
+    return res
 
 
 def q_rel_err(Q_gpu, Q_ref):
@@ -98,3 +112,8 @@ def q_rel_err(Q_gpu, Q_ref):
 
 def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def top1_agreement(P_gpu, P_ref):
+    """Fraction of frames whose most probable rotation agrees."""
+    return float(np.mean(np.argmax(P_gpu, axis=0) == np.argmax(P_ref, axis=0)))

@@ -35,8 +35,8 @@ def test_strides(lib):
     assert emc.emc_pix_stride(16384) == 16384
     assert emc.emc_pix_stride(1024) == 1024
     assert emc.emc_pix_stride(529) == 768
-    assert emc.emc_rot_stride(25000) == 25088
-    assert emc.emc_rot_stride(0) == 0
+    assert emc.emc_data_stride(100000) == 100096
+    assert emc.emc_data_stride(0) == 0
 
 
 def _pb(**kw):
@@ -47,20 +47,26 @@ def _pb(**kw):
     return emc.Problem(*[d[k] for k, _ in emc.Problem._fields_])
 
 
-def test_workspace_bytes_config2(lib):
-    pb = _pb(grid_n=128, n_pix=16384, n_rot=25000, n_data=100000)
+@pytest.mark.parametrize("prec,elem", [(0, 4), (1, 2)])
+def test_buffer_sizes_config2(lib, prec, elem):
+    pb = _pb(grid_n=128, n_pix=16384, n_rot=25000, n_data=100000, precision=prec)
     n = ctypes.c_size_t()
     assert lib.emc_workspace_bytes(ctypes.byref(pb), ctypes.byref(n)) == emc.EMC_OK
     slices = 25000 * 16384 * 4
-    gp = 100000 * 25088 * 4
-    assert slices + gp < n.value < slices + gp + 64 * 2 ** 20
+    g = 25000 * 100096 * 4
+    p = 0 if prec == 0 else 25000 * 100096 * 2          # FP32 responsibilities overwrite G
+    assert slices + g + p < n.value < slices + g + p + 64 * 2 ** 20
+    assert lib.emc_frames_bytes(ctypes.byref(pb), ctypes.byref(n)) == emc.EMC_OK
+    assert n.value == (100000 * 16384 + 16384 * 100096) * elem
+    assert lib.emc_slices_bytes(ctypes.byref(pb), ctypes.byref(n)) == emc.EMC_OK
+    assert n.value == slices
 
 
 @pytest.mark.parametrize("field,value,status", [
     ("grid_n", 1, emc.EMC_ERR_INVALID_ARG), ("grid_n", 2000, emc.EMC_ERR_INVALID_ARG),
     ("n_pix", 0, emc.EMC_ERR_INVALID_ARG), ("n_rot", 0, emc.EMC_ERR_INVALID_ARG),
     ("n_data", -1, emc.EMC_ERR_INVALID_ARG), ("reserved", 3, emc.EMC_ERR_INVALID_ARG),
-    ("precision", 7, emc.EMC_ERR_INVALID_ARG), ("precision", emc.EMC_PREC_BF16, emc.EMC_ERR_UNSUPPORTED),
+    ("precision", 7, emc.EMC_ERR_INVALID_ARG), ("precision", -1, emc.EMC_ERR_INVALID_ARG),
 ])
 def test_problem_validation(lib, field, value, status):
     pb = _pb(**{field: value})
@@ -73,11 +79,17 @@ def test_null_and_misaligned_pointers_rejected(lib):
     pb = _pb()
     z = ctypes.c_void_p(0)
     a = ctypes.c_void_p(1 << 20)
-    assert lib.emc_expand(ctypes.byref(pb), z, a, a, a, z) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_expand(ctypes.byref(pb), z, a, a, a, z, z) == emc.EMC_ERR_INVALID_ARG
     assert b"model" in lib.emc_last_error()
-    assert lib.emc_expand(ctypes.byref(pb), a, ctypes.c_void_p((1 << 20) + 4), a, a, z) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_expand(ctypes.byref(pb), a, ctypes.c_void_p((1 << 20) + 4), a, a, z, z) == emc.EMC_ERR_INVALID_ARG
     assert b"aligned" in lib.emc_last_error()
-    assert lib.emc_expand(ctypes.byref(_pb(quat=0)), a, a, a, a, z) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_expand(ctypes.byref(_pb(quat=0)), a, a, a, a, z, z) == emc.EMC_ERR_INVALID_ARG
+    # BF16 form needs the per-rotation scale output
+    assert lib.emc_expand(ctypes.byref(_pb(precision=1)), a, a, a, a, z, z) == emc.EMC_ERR_INVALID_ARG
+    assert b"scale" in lib.emc_last_error()
+    # BF16 responsibilities may not overwrite G
+    pb16 = _pb(precision=1)
+    assert lib.emc_responsibilities(ctypes.byref(pb16), a, a, a, 0, a, a, a, a, z) == emc.EMC_ERR_INVALID_ARG
     assert lib.emc_responsibilities(ctypes.byref(pb), a, a, a, 9, a, a, a, a, z) == emc.EMC_ERR_INVALID_ARG
 
 
