@@ -104,6 +104,18 @@ def pixel_order(n: int, tile: int = TILE) -> np.ndarray:
     return np.asarray(out, dtype=np.int64)
 
 
+def proposal_bins(n: int, mask: np.ndarray, image: int = 64) -> np.ndarray:
+    """Bin of each listed pixel in the proposal network's image (image x image,
+    row-major), -1 for masked pixels; the detector is reduced by n // image
+    along each axis (2 x 2 sum-binning for a 128 x 128 detector)."""
+    f = max(1, n // image)
+    order = pixel_order(n)
+    u, v = order // n, order % n
+    b = (u // f) * image + (v // f)
+    b = np.where((u // f < image) & (v // f < image), b, -1)
+    return np.where(np.asarray(mask) > 0, b, -1).astype(np.int32)
+
+
 def detector_q(wl: Workload):
     """Pixel scattering vectors on the Ewald sphere, in voxel units.
 
