@@ -204,6 +204,59 @@ emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void*
                        float* model_out, double* loglik, void* P_out, void* ws,
                        size_t ws_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Learned orientation proposal.  A small CNN scores the cells of a coarse
+ * rotation grid from a frame; its top-K cells restrict the E-step's search
+ * (the full search stays the fallback and the judge of recall).  This is an
+ * addition to the paper's method; its training targets are the E-step
+ * responsibilities of eq. (2.4) summed over each cell's fine rotations.
+ * Network: x = log(1 + binned frame) 1x64x64 -> 4 x [conv 3x3 stride 2 pad 1
+ * + bias + ReLU] (1->32->64->128->128) -> flatten 2048 -> linear -> n_cells
+ * logits.  Parameters are one float array (emc_cnn_param_count floats):
+ * for l = 0..3: w_l [co][ci][3][3], b_l [co]; then wf [n_cells][2048], bf
+ * [n_cells].  Activations and images are NCHW float.
+ * ------------------------------------------------------------------------ */
+
+int64_t emc_cnn_param_count(int32_t n_cells);
+
+/* Workspace bytes for emc_cnn_forward / emc_cnn_gradients at batch <= max_batch. */
+emc_status emc_cnn_workspace_bytes(int32_t n_cells, int32_t max_batch, size_t* bytes);
+
+/* Network input of B frames: x[b] = log1p(per-bin photon sums), 64x64.
+ *   K_packed  frames packed by emc_pack_frames (frame-major part is read)
+ *   bins      [n_pix] int32 bin of each pixel in [0, 4096), or -1 (ignored)
+ *   frames    [B] int32 frame indices, or NULL for frames 0..B-1
+ *   x         [B][64][64] float out                                         */
+emc_status emc_cnn_preprocess(const emc_problem* pb, const void* K_packed, const int32_t* bins,
+                              const int32_t* frames, int32_t B, float* x, hipStream_t stream);
+
+/* logits [B][n_cells] float out. */
+emc_status emc_cnn_forward(int32_t n_cells, const float* params, const float* x, int32_t B,
+                           float* logits, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Soft-target cross entropy loss = -(1/B) sum_b sum_c T[b][c] log softmax(z_b)_c
+ * (device double, overwritten) and its gradient with respect to every
+ * parameter (grads, same layout as params, overwritten).  T [B][n_cells]. */
+emc_status emc_cnn_gradients(int32_t n_cells, const float* params, const float* x, const float* T,
+                             int32_t B, float* grads, double* loss, void* ws, size_t ws_bytes,
+                             hipStream_t stream);
+
+/* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments)
+ * of params with grads; m, v moments (zero before step 1); step >= 1.      */
+emc_status emc_cnn_adam(int32_t n_cells, float* params, const float* grads, float* m, float* v,
+                        int32_t step, float lr, hipStream_t stream);
+
+/* out [rows][k] int32: indices of the k largest logits of each row, largest
+ * first, ties to the lower index (k <= n_cells <= 8192).                    */
+emc_status emc_cnn_topk(const float* logits, int64_t rows, int32_t n_cells, int32_t k,
+                        int32_t* out, hipStream_t stream);
+
+/* Training targets: T [n_data][n_cells] float out, T[k][c] = sum of P[j][k]
+ * over the fine rotations j of cell c, listed as CSR (cell_ptr [n_cells+1],
+ * cell_rot [n_rot]); P as written by emc_responsibilities (precision of pb). */
+emc_status emc_cell_targets(const emc_problem* pb, const void* P, const int32_t* cell_ptr,
+                            const int32_t* cell_rot, int32_t n_cells, float* T, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -350,3 +350,190 @@ emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void*
 }
 
 }  // extern "C"
+
+// =========================================================================== proposal network
+namespace {
+
+constexpr int kConvCI[4] = {1, 32, 64, 128};
+constexpr int kConvCO[4] = {32, 64, 128, 128};
+constexpr int kConvIH[4] = {64, 32, 16, 8};
+constexpr int kFlat = 2048;
+
+struct CnnLayout {
+  int64_t w[4], b[4], wf, bf, total;  // parameter offsets (floats)
+};
+
+CnnLayout cnn_layout(int n_cells) {
+  CnnLayout L;
+  int64_t o = 0;
+  for (int l = 0; l < 4; ++l) {
+    L.w[l] = o;
+    o += (int64_t)kConvCO[l] * kConvCI[l] * 9;
+    L.b[l] = o;
+    o += kConvCO[l];
+  }
+  L.wf = o;
+  o += (int64_t)n_cells * kFlat;
+  L.bf = o;
+  o += n_cells;
+  L.total = o;
+  return L;
+}
+
+int64_t act_size(int l) {  // floats per sample of activation l (output of conv layer l)
+  const int oh = kConvIH[l] / 2;
+  return (int64_t)kConvCO[l] * oh * oh;
+}
+
+struct CnnWs {
+  size_t act[4], dact[4], z, dz, total;
+};
+
+CnnWs cnn_ws(int n_cells, int B) {
+  CnnWs W;
+  size_t o = 0;
+  auto take = [&](size_t floats) {
+    size_t at = o;
+    o += (size_t)round_up((int64_t)(floats * 4), 256);
+    return at;
+  };
+  for (int l = 0; l < 4; ++l) W.act[l] = take((size_t)B * act_size(l));
+  for (int l = 0; l < 4; ++l) W.dact[l] = take((size_t)B * act_size(l));
+  W.z = take((size_t)B * n_cells);
+  W.dz = take((size_t)B * n_cells);
+  W.total = o;
+  return W;
+}
+
+emc_status check_cnn(int32_t n_cells, int32_t B, const void* ws, size_t ws_bytes) {
+  if (n_cells < 1 || n_cells > (1 << 20)) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d outside [1, 2^20]", n_cells);
+  if (B < 1) return fail(EMC_ERR_INVALID_ARG, "batch=%d < 1", B);
+  if (!ws) return fail(EMC_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  const size_t need_b = cnn_ws(n_cells, B).total;
+  if (ws_bytes < need_b) return fail(EMC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need_b);
+  return EMC_OK;
+}
+
+// forward into the workspace activations; logits to `z`
+emc_status run_cnn_forward(int n_cells, const float* p, const float* x, int B, float* z, char* w, hipStream_t st) {
+  const CnnLayout L = cnn_layout(n_cells);
+  const CnnWs W = cnn_ws(n_cells, B);
+  const float* in = x;
+  for (int l = 0; l < 4; ++l) {
+    float* out = (float*)(w + W.act[l]);
+    HIP_TRY(launch_conv_fwd(l, in, p + L.w[l], p + L.b[l], out, B, st), "conv forward");
+    in = out;
+  }
+  HIP_TRY(launch_gemm_f32_nt(in, p + L.wf, z, B, n_cells, kFlat, kFlat, kFlat, n_cells, st), "fc forward");
+  HIP_TRY(launch_add_bias(z, p + L.bf, B, n_cells, st), "fc bias");
+  return EMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t emc_cnn_param_count(int32_t n_cells) { return n_cells < 1 ? 0 : cnn_layout(n_cells).total; }
+
+emc_status emc_cnn_workspace_bytes(int32_t n_cells, int32_t max_batch, size_t* bytes) {
+  if (n_cells < 1 || max_batch < 1) return fail(EMC_ERR_INVALID_ARG, "n_cells and max_batch must be >= 1");
+  if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = cnn_ws(n_cells, max_batch).total;
+  return EMC_OK;
+}
+
+emc_status emc_cnn_preprocess(const emc_problem* pb, const void* K_packed, const int32_t* bins,
+                              const int32_t* frames, int32_t B, float* x, hipStream_t st) {
+  CHECK(check_problem(pb, false));
+  if (B < 0) return fail(EMC_ERR_INVALID_ARG, "batch=%d < 0", B);
+  if (B == 0) return EMC_OK;
+  if (!frames && B > pb->n_data) return fail(EMC_ERR_INVALID_ARG, "batch %d exceeds n_data %d", B, pb->n_data);
+  CHECK(need(K_packed, 16, "K_packed"));
+  CHECK(need(bins, 4, "bins"));
+  CHECK(need(x, 4, "x"));
+  if (frames) CHECK(need(frames, 4, "frames"));
+  HIP_TRY(launch_bin_log(K_packed, is_bf16(pb), dims_of(pb).ps, pb->n_pix, bins, frames, B, x, st), "bin_log");
+  return EMC_OK;
+}
+
+emc_status emc_cnn_forward(int32_t n_cells, const float* params, const float* x, int32_t B, float* logits, void* ws,
+                           size_t ws_bytes, hipStream_t st) {
+  CHECK(check_cnn(n_cells, B, ws, ws_bytes));
+  CHECK(need(params, 16, "params"));
+  CHECK(need(x, 4, "x"));
+  CHECK(need(logits, 4, "logits"));
+  return run_cnn_forward(n_cells, params, x, B, logits, (char*)ws, st);
+}
+
+emc_status emc_cnn_gradients(int32_t n_cells, const float* params, const float* x, const float* T, int32_t B,
+                             float* grads, double* loss, void* ws, size_t ws_bytes, hipStream_t st) {
+  CHECK(check_cnn(n_cells, B, ws, ws_bytes));
+  CHECK(need(params, 16, "params"));
+  CHECK(need(x, 4, "x"));
+  CHECK(need(T, 4, "T"));
+  CHECK(need(grads, 16, "grads"));
+  CHECK(need(loss, 8, "loss"));
+  char* w = (char*)ws;
+  const CnnLayout L = cnn_layout(n_cells);
+  const CnnWs W = cnn_ws(n_cells, B);
+  float* z = (float*)(w + W.z);
+  float* dz = (float*)(w + W.dz);
+  CHECK(run_cnn_forward(n_cells, params, x, B, z, w, st));
+  HIP_TRY(launch_fill_zero_f64(loss, 1, st), "zero loss");
+  HIP_TRY(launch_softmax_xent(z, T, n_cells, B, dz, loss, st), "softmax xent");
+  const float* a3 = (const float*)(w + W.act[3]);
+  // fully connected: dWf[c][m] = sum_b dz[b][c] a3[b][m]; dbf = column sums; da3 = dz Wf
+  HIP_TRY(launch_gemm_small(dz, 1, n_cells, a3, kFlat, 1, grads + L.wf, kFlat, n_cells, kFlat, B, st), "fc dW");
+  HIP_TRY(launch_col_sum(dz, B, n_cells, grads + L.bf, st), "fc db");
+  float* d3 = (float*)(w + W.dact[3]);
+  HIP_TRY(launch_gemm_small(dz, n_cells, 1, params + L.wf, kFlat, 1, d3, kFlat, B, kFlat, n_cells, st), "fc dx");
+  for (int l = 3; l >= 0; --l) {
+    float* dl = (float*)(w + W.dact[l]);
+    HIP_TRY(launch_relu_mask(dl, (const float*)(w + W.act[l]), (int64_t)B * act_size(l), st), "relu backward");
+    const float* in = l == 0 ? x : (const float*)(w + W.act[l - 1]);
+    float* din = l == 0 ? nullptr : (float*)(w + W.dact[l - 1]);
+    HIP_TRY(launch_conv_bwd(l, in, params + L.w[l], dl, din, grads + L.w[l], grads + L.b[l], B, st), "conv backward");
+  }
+  return EMC_OK;
+}
+
+emc_status emc_cnn_adam(int32_t n_cells, float* params, const float* grads, float* m, float* v, int32_t step,
+                        float lr, hipStream_t st) {
+  if (n_cells < 1) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d < 1", n_cells);
+  if (step < 1) return fail(EMC_ERR_INVALID_ARG, "step=%d < 1 (Adam steps count from 1)", step);
+  CHECK(need(params, 4, "params"));
+  CHECK(need(grads, 4, "grads"));
+  CHECK(need(m, 4, "m"));
+  CHECK(need(v, 4, "v"));
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = (float)(1.0 - pow(0.9, step)), c2 = (float)(1.0 - pow(0.999, step));
+  HIP_TRY(launch_adam(params, grads, m, v, cnn_layout(n_cells).total, lr, b1, b2, eps, c1, c2, st), "adam");
+  return EMC_OK;
+}
+
+emc_status emc_cnn_topk(const float* logits, int64_t rows, int32_t n_cells, int32_t k, int32_t* out, hipStream_t st) {
+  if (rows < 0 || n_cells < 1 || n_cells > 8192 || k < 1 || k > n_cells)
+    return fail(EMC_ERR_INVALID_ARG, "need rows >= 0, 1 <= k <= n_cells <= 8192");
+  if (rows == 0) return EMC_OK;
+  CHECK(need(logits, 4, "logits"));
+  CHECK(need(out, 4, "out"));
+  HIP_TRY(launch_topk(logits, rows, n_cells, k, out, st), "topk");
+  return EMC_OK;
+}
+
+emc_status emc_cell_targets(const emc_problem* pb, const void* P, const int32_t* cell_ptr, const int32_t* cell_rot,
+                            int32_t n_cells, float* T, hipStream_t st) {
+  CHECK(check_problem(pb, false));
+  if (n_cells < 1) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d < 1", n_cells);
+  if (pb->n_data == 0) return EMC_OK;
+  CHECK(need(P, 4, "P"));
+  CHECK(need(cell_ptr, 4, "cell_ptr"));
+  CHECK(need(cell_rot, 4, "cell_rot"));
+  CHECK(need(T, 4, "T"));
+  HIP_TRY(launch_cell_targets(P, is_bf16(pb), dims_of(pb).ds, pb->n_data, cell_ptr, cell_rot, n_cells, T, st),
+          "cell targets");
+  return EMC_OK;
+}
+
+}  // extern "C"

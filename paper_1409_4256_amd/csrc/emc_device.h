@@ -114,4 +114,24 @@ hipError_t launch_divide(const double* num, const double* den, const float* prev
                          hipStream_t st);
 hipError_t launch_mean(const double* L, int64_t n, double* out, hipStream_t st);
 
+// ---- proposal network (cnn.hip) ----
+hipError_t launch_bin_log(const void* K, bool bf16, int64_t ps, int n_pix, const int32_t* bins, const int32_t* frames,
+                          int B, float* x, hipStream_t st);
+hipError_t launch_conv_fwd(int layer, const float* in, const float* w, const float* b, float* out, int B,
+                           hipStream_t st);
+hipError_t launch_conv_bwd(int layer, const float* in, const float* w, const float* dout, float* din, float* dw,
+                           float* db, int B, hipStream_t st);
+hipError_t launch_relu_mask(float* g, const float* act, int64_t n, hipStream_t st);
+hipError_t launch_add_bias(float* z, const float* bias, int64_t rows, int cols, hipStream_t st);
+hipError_t launch_gemm_small(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn,
+                             float* C, int64_t ldc, int M, int N, int Kd, hipStream_t st);
+hipError_t launch_col_sum(const float* X, int rows, int cols, float* out, hipStream_t st);
+hipError_t launch_softmax_xent(const float* z, const float* T, int n_cells, int B, float* dz, double* loss,
+                               hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2, hipStream_t st);
+hipError_t launch_topk(const float* z, int64_t rows, int n_cells, int k, int32_t* out, hipStream_t st);
+hipError_t launch_cell_targets(const void* P, bool bf16, int64_t ldp, int64_t n_data, const int32_t* cell_ptr,
+                               const int32_t* cell_rot, int n_cells, float* T, hipStream_t st);
+
 }  // namespace emc

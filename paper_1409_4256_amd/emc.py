@@ -29,7 +29,9 @@ EMC_RESP_FINALIZE = 2
 
 EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride", "emc_frames_bytes",
            "emc_slices_bytes", "emc_workspace_bytes", "emc_pack_frames", "emc_expand", "emc_loglik",
-           "emc_responsibilities", "emc_compress", "emc_finalize", "emc_iterate")
+           "emc_responsibilities", "emc_compress", "emc_finalize", "emc_iterate",
+           "emc_cnn_param_count", "emc_cnn_workspace_bytes", "emc_cnn_preprocess", "emc_cnn_forward",
+           "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_targets")
 
 
 class EmcError(RuntimeError):
@@ -85,6 +87,17 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_finalize.argtypes, lib.emc_finalize.restype = [_PB, _P, _P, _P, _P, _P, i64, _P, _P], st
     lib.emc_iterate.argtypes = [_PB, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.emc_iterate.restype = st
+    lib.emc_cnn_param_count.argtypes, lib.emc_cnn_param_count.restype = [i32], i64
+    lib.emc_cnn_workspace_bytes.argtypes, lib.emc_cnn_workspace_bytes.restype = [i32, i32, szp], st
+    lib.emc_cnn_preprocess.argtypes, lib.emc_cnn_preprocess.restype = [_PB, _P, _P, _P, i32, _P, _P], st
+    lib.emc_cnn_forward.argtypes = [i32, _P, _P, i32, _P, _P, ctypes.c_size_t, _P]
+    lib.emc_cnn_forward.restype = st
+    lib.emc_cnn_gradients.argtypes = [i32, _P, _P, _P, i32, _P, _P, _P, ctypes.c_size_t, _P]
+    lib.emc_cnn_gradients.restype = st
+    lib.emc_cnn_adam.argtypes = [i32, _P, _P, _P, _P, i32, ctypes.c_float, _P]
+    lib.emc_cnn_adam.restype = st
+    lib.emc_cnn_topk.argtypes, lib.emc_cnn_topk.restype = [_P, i64, i32, i32, _P, _P], st
+    lib.emc_cell_targets.argtypes, lib.emc_cell_targets.restype = [_PB, _P, _P, _P, i32, _P, _P], st
     _lib = lib
     return lib
 
@@ -323,3 +336,68 @@ def emc_iterate(geo: Geometry, model_in, K_packed, model_out, loglik, P_out=None
         _ptr(model_out, torch.float32, M, "model_out"), _ptr(loglik, torch.float64, 1, "loglik"),
         _ptr(P_out, geo.p_dtype, geo.n_rot * geo.data_stride, "P_out", allow_none=True),
         _ptr(ws, torch.uint8, need, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream)))
+
+
+# ------------------------------------------------------------------------- proposal network
+def emc_cnn_param_count(n_cells: int) -> int:
+    return int(load().emc_cnn_param_count(int(n_cells)))
+
+
+def emc_cnn_workspace_bytes(n_cells: int, max_batch: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().emc_cnn_workspace_bytes(int(n_cells), int(max_batch), ctypes.byref(n)))
+    return int(n.value)
+
+
+def emc_cnn_preprocess(geo: Geometry, K_packed, bins, frames, B, x, stream=None):
+    import torch
+
+    _check(load().emc_cnn_preprocess(ctypes.byref(geo.pb), _ptr(K_packed, None, None, "K_packed"),
+                                     _ptr(bins, torch.int32, geo.n_pix, "bins"),
+                                     _ptr(frames, torch.int32, B, "frames", allow_none=True), int(B),
+                                     _ptr(x, torch.float32, B * 4096, "x"), _stream(stream)))
+
+
+def emc_cnn_forward(n_cells, params, x, B, logits, ws, stream=None):
+    import torch
+
+    _check(load().emc_cnn_forward(int(n_cells), _ptr(params, torch.float32, emc_cnn_param_count(n_cells), "params"),
+                                  _ptr(x, torch.float32, B * 4096, "x"), int(B),
+                                  _ptr(logits, torch.float32, B * n_cells, "logits"),
+                                  _ptr(ws, torch.uint8, None, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream)))
+
+
+def emc_cnn_gradients(n_cells, params, x, T, B, grads, loss, ws, stream=None):
+    import torch
+
+    n_par = emc_cnn_param_count(n_cells)
+    _check(load().emc_cnn_gradients(int(n_cells), _ptr(params, torch.float32, n_par, "params"),
+                                    _ptr(x, torch.float32, B * 4096, "x"), _ptr(T, torch.float32, B * n_cells, "T"),
+                                    int(B), _ptr(grads, torch.float32, n_par, "grads"),
+                                    _ptr(loss, torch.float64, 1, "loss"), _ptr(ws, torch.uint8, None, "ws"),
+                                    ctypes.c_size_t(ws.numel()), _stream(stream)))
+
+
+def emc_cnn_adam(n_cells, params, grads, m, v, step, lr, stream=None):
+    import torch
+
+    n_par = emc_cnn_param_count(n_cells)
+    _check(load().emc_cnn_adam(int(n_cells), _ptr(params, torch.float32, n_par, "params"),
+                               _ptr(grads, torch.float32, n_par, "grads"), _ptr(m, torch.float32, n_par, "m"),
+                               _ptr(v, torch.float32, n_par, "v"), int(step), ctypes.c_float(lr), _stream(stream)))
+
+
+def emc_cnn_topk(logits, rows, n_cells, k, out, stream=None):
+    import torch
+
+    _check(load().emc_cnn_topk(_ptr(logits, torch.float32, rows * n_cells, "logits"), int(rows), int(n_cells),
+                               int(k), _ptr(out, torch.int32, rows * k, "out"), _stream(stream)))
+
+
+def emc_cell_targets(geo: Geometry, P, cell_ptr, cell_rot, n_cells, T, stream=None):
+    import torch
+
+    _check(load().emc_cell_targets(ctypes.byref(geo.pb), _ptr(P, geo.p_dtype, geo.n_rot * geo.data_stride, "P"),
+                                   _ptr(cell_ptr, torch.int32, n_cells + 1, "cell_ptr"),
+                                   _ptr(cell_rot, torch.int32, geo.n_rot, "cell_rot"), int(n_cells),
+                                   _ptr(T, torch.float32, geo.n_data * n_cells, "T"), _stream(stream)))
