@@ -257,6 +257,71 @@ emc_status emc_cnn_topk(const float* logits, int64_t rows, int32_t n_cells, int3
 emc_status emc_cell_targets(const emc_problem* pb, const void* P, const int32_t* cell_ptr,
                             const int32_t* cell_rot, int32_t n_cells, float* T, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Learned-proposal iteration (BF16 form).  Each frame's E-step runs over the
+ * fine rotations of its top-K coarse cells; a seeded subset of frames is
+ * searched in full and judges the proposal's recall, the fraction of their
+ * full-search responsibility inside their candidates.  The caller reruns the
+ * iteration with emc_iterate when the mean recall is below 0.98 or the
+ * status word is non-zero.
+ * ------------------------------------------------------------------------ */
+
+/* Packed frames of a frame list: like emc_pack_frames with pb->n_data =
+ * number of listed frames and row k taken from counts row frames[k]. */
+emc_status emc_pack_frames_list(const emc_problem* pb, const uint16_t* counts, const int32_t* frames,
+                                void* K_packed, hipStream_t stream);
+
+/* Proposal plan: arrays carved from one caller buffer by emc_proposal_build. */
+typedef struct emc_proposal {
+  int32_t n_cells;        /* coarse cells                                            */
+  int32_t k_top;          /* cells proposed per frame                                */
+  int32_t n_cand;         /* frames searched over their candidates                   */
+  int32_t n_audit;        /* frames searched in full                                 */
+  int32_t n_blocks;       /* ceil(n_cand / 256) blocks of candidate frames           */
+  int32_t words;          /* ceil(n_cells / 32): words of a candidate-cell bitmask   */
+  int64_t n_list;         /* rows of the blocks' rotation lists (256 per tile)       */
+  int64_t n_tiles;        /* n_list / 256                                            */
+  int32_t* cell_of;       /* [n_rot] coarse cell of each rotation (max |<q, q_c>|)   */
+  int64_t* cell_ptr;      /* [n_cells + 1] rotations of cell c: cell_rot[ptr[c]..)   */
+  int32_t* cell_rot;      /* [n_rot]                                                 */
+  int32_t* cand_frames;   /* [n_cand] frame index, grouped by the frame's best cell  */
+  int32_t* audit_frames;  /* [n_audit] frame index of the audited frames             */
+  uint32_t* mask_cand;    /* [n_cand][words] candidate cells of each listed frame    */
+  uint32_t* mask_audit;   /* [n_audit][words]                                        */
+  int64_t* list_off;      /* [n_blocks + 1] offsets into list                        */
+  int32_t* list;          /* rotations of each block's candidate union (-1 padding)  */
+  void* tiles;            /* [n_tiles] (block, tile) int32 pairs                     */
+} emc_proposal;
+
+/* Bytes of the plan buffer for n_cells coarse cells and n_audit audited frames. */
+emc_status emc_proposal_bytes(const emc_problem* pb, int32_t n_cells, int32_t n_audit, size_t* bytes);
+
+/* Builds the plan (synchronises the stream once to size the rotation lists).
+ *   coarse [n_cells][4] float quaternions of the coarse grid
+ *   topk   [n_data][k_top] int32 proposed cells of every frame (emc_cnn_topk)
+ *   audit  [n_audit] int32 distinct frame indices searched in full          */
+emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_t n_cells,
+                              const int32_t* topk, int32_t k_top, const int32_t* audit, int32_t n_audit,
+                              void* buf, size_t buf_bytes, emc_proposal* plan, hipStream_t stream);
+
+/* Workspace bytes of emc_iterate_proposed; triple_cap bounds the number of
+ * (rotation, frame) responsibilities >= 1e-10 kept for the M-step. */
+emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan,
+                                        int64_t triple_cap, size_t* bytes);
+
+/* One iteration with the E-step restricted to the proposal (pb->precision must
+ * be EMC_PREC_BF16; pb->n_data = n_cand + n_audit):
+ *   K_cand   frames plan->cand_frames packed by emc_pack_frames_list
+ *   K_audit  frames plan->audit_frames packed by emc_pack_frames_list
+ *   loglik   mean log-evidence over all frames (each over its searched set)
+ *   recall_mean  mean recall of the audited frames (NaN without audit)
+ *   status   device int32: bit 0 set if responsibilities overflowed triple_cap
+ * Responsibilities below 1e-10 are left out of the M-step.                  */
+emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_cand,
+                                const void* K_audit, const float* model_in, float* model_out,
+                                double* loglik, double* recall_mean, int32_t* status,
+                                int64_t triple_cap, void* ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -210,3 +210,32 @@ def paper_flops(n_rot: int, n_data: int, n_pix: int) -> float:
 def mrot_600cell(d: int) -> int:
     """Number of rotations of the 600-cell refined d times, eq. (2.7)."""
     return 10 * (5 * d ** 3 + d)
+
+
+# ---------------------------------------------------------------------------------------
+# learned-proposal form: the same iteration with each frame's E-step restricted to its
+# candidate rotations (audited frames keep the full search)
+# ---------------------------------------------------------------------------------------
+def responsibilities_restricted(Q: np.ndarray, log_w: np.ndarray, cand: np.ndarray):
+    """eq. (2.4) with the sum over rotations limited to cand[j][k] (boolean); P = 0 elsewhere."""
+    a = np.where(cand, np.asarray(Q, dtype=np.float64) + np.asarray(log_w)[:, None], -np.inf)
+    m = a.max(axis=0)
+    L = m + np.log(np.exp(a - m[None, :]).sum(axis=0))
+    return np.exp(a - L[None, :]), L
+
+
+def iterate_proposed(model, K, q, mask, quat, log_w, grid_n, cand):
+    """One EMC iteration whose E-step runs over cand[j][k] only (see responsibilities_restricted)."""
+    W = expand(model, q, quat, grid_n)
+    Kf = np.asarray(K, dtype=np.float64)
+    Q = log_likelihood(W, Kf, mask)
+    P, L = responsibilities_restricted(Q, log_w, cand)
+    Wp, rho = maximize(P, Kf, mask)
+    num, den = compress(Wp, rho, q, mask, quat, grid_n)
+    return dict(W=W, Q=Q, P=P, L=L, loglik=float(L.mean()), Wp=Wp, rho=rho, num=num, den=den,
+                model=divide(num, den, model))
+
+
+def proposal_recall(P_full: np.ndarray, cand: np.ndarray) -> np.ndarray:
+    """recall_k = sum_{j in cand(k)} P_jk of the full-search responsibilities."""
+    return (np.asarray(P_full) * cand).sum(axis=0)

@@ -226,20 +226,32 @@ emc_status emc_workspace_bytes(const emc_problem* pb, size_t* bytes) {
   return EMC_OK;
 }
 
-emc_status emc_pack_frames(const emc_problem* pb, const uint16_t* counts, void* K_packed, hipStream_t st) {
+static emc_status pack_frames(const emc_problem* pb, const uint16_t* counts, const int32_t* frames, void* K_packed,
+                              hipStream_t st) {
   CHECK(check_problem(pb, true));
   if (pb->n_data == 0) return EMC_OK;
   CHECK(need(counts, 2, "counts"));
   CHECK(need(K_packed, 16, "K_packed"));
   const Dims d = dims_of(pb);
   char* KT = (char*)K_packed + (size_t)pb->n_data * d.ps * d.elem;
-  HIP_TRY(launch_pack(counts, pb->mask, pb->n_pix, d.ps, pb->n_data, d.ds, K_packed, KT, is_bf16(pb), st), "pack");
+  HIP_TRY(launch_pack(counts, pb->mask, pb->n_pix, d.ps, pb->n_data, d.ds, frames, K_packed, KT, is_bf16(pb), st),
+          "pack");
   if (is_bf16(pb)) {
     int flag = 0;
     HIP_TRY(read_range_flag(&flag, st), "range flag");
     if (flag) return fail(EMC_ERR_RANGE, "a photon count exceeds 256, which BF16 cannot hold exactly");
   }
   return EMC_OK;
+}
+
+emc_status emc_pack_frames(const emc_problem* pb, const uint16_t* counts, void* K_packed, hipStream_t st) {
+  return pack_frames(pb, counts, nullptr, K_packed, st);
+}
+
+emc_status emc_pack_frames_list(const emc_problem* pb, const uint16_t* counts, const int32_t* frames, void* K_packed,
+                                hipStream_t st) {
+  if (pb && pb->n_data > 0) CHECK(need(frames, 4, "frames"));
+  return pack_frames(pb, counts, frames, K_packed, st);
 }
 
 emc_status emc_expand(const emc_problem* pb, const float* model, double* c, void* slices, double* S, float* scale,
@@ -533,6 +545,365 @@ emc_status emc_cell_targets(const emc_problem* pb, const void* P, const int32_t*
   CHECK(need(T, 4, "T"));
   HIP_TRY(launch_cell_targets(P, is_bf16(pb), dims_of(pb).ds, pb->n_data, cell_ptr, cell_rot, n_cells, T, st),
           "cell targets");
+  return EMC_OK;
+}
+
+}  // extern "C"
+
+// =========================================================================== learned-proposal iteration
+namespace {
+
+constexpr double kRecallMin = 0.98;
+
+int words_of(int n_cells) { return (n_cells + 31) / 32; }
+
+// Carving of the plan buffer (all capacities are upper bounds known before the build).
+struct PlanLayout {
+  size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, mask_cand, mask_audit, list_off, list, tiles,
+      hist, cursor, keys, order, mark, len, coarse_hist, total;
+};
+
+PlanLayout plan_layout(int n_rot, int n_data, int n_cells, int n_audit) {
+  const int64_t n_cand = (int64_t)n_data - n_audit;
+  const int64_t n_blocks = (n_cand + 255) / 256;
+  const int64_t rs = round_up(n_rot, 256);
+  const int w = words_of(n_cells);
+  PlanLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (size_t)round_up((int64_t)(bytes ? bytes : 1), 256);
+    return at;
+  };
+  L.cell_of = take((size_t)n_rot * 4);
+  L.cell_ptr = take((size_t)(n_cells + 1) * 8);
+  L.cell_rot = take((size_t)n_rot * 4);
+  L.cand_frames = take((size_t)n_cand * 4);
+  L.audit_frames = take((size_t)n_audit * 4);
+  L.mask_cand = take((size_t)n_cand * w * 4);
+  L.mask_audit = take((size_t)n_audit * w * 4);
+  L.list_off = take((size_t)(n_blocks + 1) * 8);
+  L.list = take((size_t)n_blocks * rs * 4);
+  L.tiles = take((size_t)n_blocks * (rs / 256) * 8);
+  L.hist = take((size_t)(n_cells > n_rot ? n_cells : n_rot) * 4);
+  L.cursor = take((size_t)(n_cells > n_rot ? n_cells : n_rot) * 4);
+  L.keys = take((size_t)n_data * 4);
+  L.order = take((size_t)n_data * 4);
+  L.mark = take((size_t)n_data * 4);
+  L.len = take((size_t)(n_blocks + 1) * 8);
+  L.coarse_hist = take((size_t)(n_cells + 1) * 8);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+namespace emc {
+__global__ void top1_keys_kernel(const int32_t* __restrict__ topk, int k_top, const int32_t* __restrict__ mark,
+                                 int64_t n, int n_cells, int32_t* __restrict__ keys) {
+  const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (f >= n) return;
+  const int32_t c = topk[f * k_top];
+  // audited frames sort after every cell; frames without a valid proposal go to the last cell
+  keys[f] = mark[f] ? n_cells : (c >= 0 && c < n_cells ? c : n_cells - 1);
+}
+__global__ void mark_kernel(const int32_t* __restrict__ audit, int64_t n_audit, int32_t* __restrict__ mark) {
+  const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (a < n_audit) mark[audit[a]] = 1;
+}
+__global__ void copy_i32_kernel(const int32_t* __restrict__ src, int64_t n, int32_t* __restrict__ dst) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) dst[e] = src[e];
+}
+// exclusive scan over int64 lengths (single workgroup)
+__global__ __launch_bounds__(256) void scan_i64_kernel(const int64_t* __restrict__ len, int64_t n,
+                                                       int64_t* __restrict__ ptr) {
+  __shared__ int64_t part[256];
+  const int64_t per = (n + 255) / 256;
+  const int64_t a = threadIdx.x * per, z = a + per < n ? a + per : n;
+  int64_t s = 0;
+  for (int64_t e = a; e < z; ++e) s += len[e];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int t = 0; t < 256; ++t) {
+      const int64_t v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int64_t run = part[threadIdx.x];
+  for (int64_t e = a; e < z; ++e) {
+    ptr[e] = run;
+    run += len[e];
+  }
+  if (threadIdx.x == 255) ptr[n] = run;
+}
+__global__ void mean2_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += 256) s += x[k];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = n > 0 ? ((red[0] + red[1]) + (red[2] + red[3])) / (double)n : NAN;
+}
+}  // namespace emc
+
+extern "C" {
+
+emc_status emc_proposal_bytes(const emc_problem* pb, int32_t n_cells, int32_t n_audit, size_t* bytes) {
+  CHECK(check_problem(pb, false));
+  if (n_cells < 1 || n_cells > 8192) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d outside [1, 8192]", n_cells);
+  if (n_audit < 0 || n_audit > pb->n_data) return fail(EMC_ERR_INVALID_ARG, "n_audit=%d outside [0, n_data]", n_audit);
+  if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = plan_layout(pb->n_rot, pb->n_data, n_cells, n_audit).total;
+  return EMC_OK;
+}
+
+emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_t n_cells, const int32_t* topk,
+                              int32_t k_top, const int32_t* audit, int32_t n_audit, void* buf, size_t buf_bytes,
+                              emc_proposal* plan, hipStream_t st) {
+  CHECK(check_problem(pb, true));
+  if (n_cells < 1 || n_cells > 8192) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d outside [1, 8192]", n_cells);
+  if (k_top < 1 || k_top > n_cells) return fail(EMC_ERR_INVALID_ARG, "k_top=%d outside [1, n_cells]", k_top);
+  if (n_audit < 0 || n_audit > pb->n_data) return fail(EMC_ERR_INVALID_ARG, "n_audit outside [0, n_data]");
+  if (pb->n_data < 1) return fail(EMC_ERR_INVALID_ARG, "the proposal needs frames");
+  CHECK(need(coarse, 16, "coarse"));
+  CHECK(need(topk, 4, "topk"));
+  if (n_audit > 0) CHECK(need(audit, 4, "audit"));
+  if (!plan) return fail(EMC_ERR_INVALID_ARG, "plan is NULL");
+  const PlanLayout L = plan_layout(pb->n_rot, pb->n_data, n_cells, n_audit);
+  if (!buf || !aligned(buf, 256)) return fail(EMC_ERR_WORKSPACE, "plan buffer is NULL or not 256-byte aligned");
+  if (buf_bytes < L.total) return fail(EMC_ERR_WORKSPACE, "plan buffer has %zu bytes, needs %zu", buf_bytes, L.total);
+  char* b = (char*)buf;
+  const int64_t n_data = pb->n_data, n_cand = n_data - n_audit;
+  const int n_blocks = (int)((n_cand + 255) / 256);
+  const int w = words_of(n_cells);
+  emc_proposal P;
+  P.n_cells = n_cells;
+  P.k_top = k_top;
+  P.n_cand = (int32_t)n_cand;
+  P.n_audit = n_audit;
+  P.n_blocks = n_blocks;
+  P.words = w;
+  P.cell_of = (int32_t*)(b + L.cell_of);
+  P.cell_ptr = (int64_t*)(b + L.cell_ptr);
+  P.cell_rot = (int32_t*)(b + L.cell_rot);
+  P.cand_frames = (int32_t*)(b + L.cand_frames);
+  P.audit_frames = (int32_t*)(b + L.audit_frames);
+  P.mask_cand = (uint32_t*)(b + L.mask_cand);
+  P.mask_audit = (uint32_t*)(b + L.mask_audit);
+  P.list_off = (int64_t*)(b + L.list_off);
+  P.list = (int32_t*)(b + L.list);
+  P.tiles = (void*)(b + L.tiles);
+  int32_t* hist = (int32_t*)(b + L.hist);
+  int32_t* cursor = (int32_t*)(b + L.cursor);
+  int32_t* keys = (int32_t*)(b + L.keys);
+  int32_t* order = (int32_t*)(b + L.order);
+  int32_t* mark = (int32_t*)(b + L.mark);
+  int64_t* len = (int64_t*)(b + L.len);
+  int64_t* frame_ptr = (int64_t*)(b + L.coarse_hist);
+  // 1. coarse cell of every fine rotation, rotations grouped by cell
+  HIP_TRY(launch_assign_cells(pb->quat, pb->n_rot, coarse, n_cells, P.cell_of, st), "assign cells");
+  HIP_TRY(launch_counting_sort(P.cell_of, pb->n_rot, n_cells, hist, cursor, P.cell_ptr, P.cell_rot, nullptr, st),
+          "sort rotations");
+  // 2. frames: audited ones apart, the others grouped by their best cell
+  HIP_TRY(launch_fill_i32(mark, n_data, 0, st), "mark");
+  if (n_audit > 0) emc::mark_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(audit, n_audit, mark);
+  emc::top1_keys_kernel<<<(unsigned)((n_data + 255) / 256), 256, 0, st>>>(topk, k_top, mark, n_data, n_cells, keys);
+  HIP_TRY(launch_counting_sort(keys, n_data, n_cells + 1, hist, cursor, frame_ptr, order, nullptr, st), "sort frames");
+  if (n_cand > 0) emc::copy_i32_kernel<<<(unsigned)((n_cand + 255) / 256), 256, 0, st>>>(order, n_cand, P.cand_frames);
+  if (n_audit > 0)
+    emc::copy_i32_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(order + n_cand, n_audit, P.audit_frames);
+  HIP_TRY(launch_cand_mask(topk, k_top, P.cand_frames, n_cand, w, P.mask_cand, st), "candidate masks");
+  HIP_TRY(launch_cand_mask(topk, k_top, P.audit_frames, n_audit, w, P.mask_audit, st), "audit masks");
+  // 3. per block of 256 frames: union of candidate cells -> rotation list (padded to 256)
+  HIP_TRY(launch_block_union(P.mask_cand, w, n_cand, n_blocks, P.cell_ptr, P.cell_rot, 0, len, nullptr, nullptr, st),
+          "block union sizes");
+  emc::scan_i64_kernel<<<1, 256, 0, st>>>(len, n_blocks, P.list_off);
+  HIP_TRY(launch_block_union(P.mask_cand, w, n_cand, n_blocks, P.cell_ptr, P.cell_rot, 1, nullptr, P.list_off, P.list,
+                             st),
+          "block union lists");
+  // tile table: tile offsets are list offsets / 256
+  HIP_TRY(hipGetLastError(), "proposal build");
+  int64_t n_list = 0;
+  HIP_TRY(hipMemcpyAsync(&n_list, P.list_off + n_blocks, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read n_list");
+  HIP_TRY(hipStreamSynchronize(st), "proposal build sync");
+  P.n_list = n_list;
+  P.n_tiles = n_list / 256;
+  HIP_TRY(launch_tile_table(P.list_off, n_blocks, (int2*)P.tiles, st), "tile table");
+  *plan = P;
+  return EMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct PropWs {
+  size_t slices, S, scale, c, b, L, Gc, Ga, Pa, stats_a, rho_a, recall, tj, tk, tp, tk2, tp2, order, hist, cursor, tptr,
+      rho, num, den, count, total;
+};
+
+PropWs prop_ws(const emc_problem* pb, const emc_proposal* P, int64_t cap) {
+  const int64_t ps = round_up(pb->n_pix, 256);
+  const int64_t dsa = round_up(P->n_audit, 256);
+  const int64_t grid = (int64_t)pb->grid_n * pb->grid_n * pb->grid_n;
+  const int64_t n_frames = (int64_t)P->n_cand + P->n_audit;
+  PropWs W;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (size_t)round_up((int64_t)(bytes ? bytes : 1), 256);
+    return at;
+  };
+  W.slices = take((size_t)pb->n_rot * ps * 4);
+  W.S = take((size_t)pb->n_rot * 8);
+  W.scale = take((size_t)pb->n_rot * 4);
+  W.c = take((size_t)ps * 8);
+  W.b = take((size_t)n_frames * 8);
+  W.L = take((size_t)n_frames * 8);
+  W.Gc = take((size_t)P->n_list * 256 * 4);
+  W.Ga = take((size_t)pb->n_rot * dsa * 4);
+  W.Pa = take((size_t)pb->n_rot * dsa * 2);
+  W.stats_a = take((size_t)P->n_audit * 16);
+  W.rho_a = take((size_t)pb->n_rot * 8);
+  W.recall = take((size_t)P->n_audit * 8);
+  W.tj = take((size_t)cap * 4);
+  W.tk = take((size_t)cap * 4);
+  W.tp = take((size_t)cap * 4);
+  W.tk2 = take((size_t)cap * 4);
+  W.tp2 = take((size_t)cap * 4);
+  W.order = take((size_t)cap * 4);
+  W.hist = take((size_t)(pb->n_rot + 1) * 4);
+  W.cursor = take((size_t)(pb->n_rot + 1) * 4);
+  W.tptr = take((size_t)(pb->n_rot + 2) * 8);
+  W.rho = take((size_t)pb->n_rot * 8);
+  W.num = take((size_t)grid * 8);
+  W.den = take((size_t)grid * 8);
+  W.count = take(16);
+  W.total = o;
+  return W;
+}
+
+emc_status check_plan(const emc_problem* pb, const emc_proposal* P) {
+  if (!P) return fail(EMC_ERR_INVALID_ARG, "plan is NULL");
+  if (P->n_cand < 0 || P->n_audit < 0 || (int64_t)P->n_cand + P->n_audit != pb->n_data)
+    return fail(EMC_ERR_INVALID_ARG, "plan frames (%d + %d) do not match n_data %d", P->n_cand, P->n_audit, pb->n_data);
+  if (P->n_blocks != (P->n_cand + 255) / 256 || P->n_list < 0 || P->n_list % 256 != 0 || P->n_tiles * 256 != P->n_list)
+    return fail(EMC_ERR_INVALID_ARG, "inconsistent plan sizes");
+  if (P->words != words_of(P->n_cells)) return fail(EMC_ERR_INVALID_ARG, "plan words do not match n_cells");
+  return EMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan, int64_t triple_cap,
+                                        size_t* bytes) {
+  CHECK(check_problem(pb, false));
+  CHECK(check_plan(pb, plan));
+  if (triple_cap < 1) return fail(EMC_ERR_INVALID_ARG, "triple_cap < 1");
+  if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = prop_ws(pb, plan, triple_cap).total;
+  return EMC_OK;
+}
+
+emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_cand,
+                                const void* K_audit, const float* model_in, float* model_out, double* loglik,
+                                double* recall_mean, int32_t* status, int64_t triple_cap, void* ws, size_t ws_bytes,
+                                hipStream_t st) {
+  CHECK(check_problem(pb, true));
+  if (!is_bf16(pb)) return fail(EMC_ERR_UNSUPPORTED, "the proposal form runs in BF16 precision");
+  CHECK(check_plan(pb, plan));
+  if (plan->n_cand > 0) CHECK(need(K_cand, 16, "K_cand"));
+  if (plan->n_audit > 0) CHECK(need(K_audit, 16, "K_audit"));
+  CHECK(need(model_in, 4, "model_in"));
+  CHECK(need(model_out, 4, "model_out"));
+  CHECK(need(loglik, 8, "loglik"));
+  CHECK(need(recall_mean, 8, "recall_mean"));
+  CHECK(need(status, 4, "status"));
+  if (triple_cap < 1 || triple_cap > (int64_t)INT32_MAX) return fail(EMC_ERR_INVALID_ARG, "triple_cap out of range");
+  const PropWs W = prop_ws(pb, plan, triple_cap);
+  if (!ws || !aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is NULL or not 256-byte aligned");
+  if (ws_bytes < W.total) return fail(EMC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
+  char* w = (char*)ws;
+  const int64_t ps = round_up(pb->n_pix, 256);
+  const int64_t nc = plan->n_cand, na = plan->n_audit;
+  const int64_t dsa = round_up(na, 256);
+  void* slices = w + W.slices;
+  double* S = (double*)(w + W.S);
+  float* scale = (float*)(w + W.scale);
+  double* c = (double*)(w + W.c);
+  double* b = (double*)(w + W.b);
+  double* L = (double*)(w + W.L);
+  float* Gc = (float*)(w + W.Gc);
+  float* Ga = (float*)(w + W.Ga);
+  void* Pa = w + W.Pa;
+  double* stats_a = (double*)(w + W.stats_a);
+  double* rho_a = (double*)(w + W.rho_a);
+  double* recall = (double*)(w + W.recall);
+  int32_t* tj = (int32_t*)(w + W.tj);
+  int32_t* tk = (int32_t*)(w + W.tk);
+  float* tp = (float*)(w + W.tp);
+  int32_t* tk2 = (int32_t*)(w + W.tk2);
+  float* tp2 = (float*)(w + W.tp2);
+  int32_t* order = (int32_t*)(w + W.order);
+  int32_t* hist = (int32_t*)(w + W.hist);
+  int32_t* cursor = (int32_t*)(w + W.cursor);
+  int64_t* tptr = (int64_t*)(w + W.tptr);
+  double* rho = (double*)(w + W.rho);
+  double* num = (double*)(w + W.num);
+  double* den = (double*)(w + W.den);
+  unsigned long long* count = (unsigned long long*)(w + W.count);
+  // status word: bit 0 triple overflow (the sparse M-step is then incomplete)
+  HIP_TRY(launch_fill_i32(status, 1, 0, st), "status");
+  HIP_TRY(launch_fill_i32((int32_t*)count, 2, 0, st), "count");
+  // expand (all rotations, hi + lo)
+  emc_problem pc = *pb;
+  pc.n_data = (int32_t)nc;
+  CHECK(run_expand(&pc, model_in, c, slices, S, scale, st));
+  const char* hi = (const char*)slices;
+  const char* lo = hi + (size_t)pb->n_rot * ps * 2;
+  // candidate frames: gathered GEMM per block, masked log-sum-exp, significant triples
+  if (nc > 0) {
+    HIP_TRY(launch_frame_dot(K_cand, true, ps, nc, c, b, st), "frame_dot");
+    HIP_TRY(launch_gemm_bf16_dual_gather(hi, lo, K_cand, scale, Gc, nc, ps, ps, ps, plan->list, plan->list_off,
+                                         (const int2*)plan->tiles, plan->n_tiles, st),
+            "candidate gemm");
+    HIP_TRY(launch_cand_estep(Gc, plan->list_off, plan->list, nc, plan->n_blocks, plan->mask_cand, plan->words,
+                              plan->cell_of, pb->log_w, S, b, L, tj, tk, tp, triple_cap, count, status, st),
+            "candidate estep");
+  }
+  // audited frames: full search, recall of the proposal
+  HIP_TRY(launch_fill_zero_f64(recall, (size_t)na, st), "zero recall");
+  if (na > 0) {
+    emc_problem pa = *pb;
+    pa.n_data = (int32_t)na;
+    CHECK(run_loglik(&pa, K_audit, slices, scale, c, Ga, b + nc, st));
+    CHECK(run_estep(&pa, Ga, S, b + nc, EMC_RESP_FULL, stats_a, Pa, L + nc, rho_a, st));
+    HIP_TRY(launch_audit(Pa, true, dsa, pb->n_rot, na, plan->mask_audit, plan->words, plan->cell_of, (int32_t)nc, tj,
+                         tk, tp, triple_cap, count, status, recall, st),
+            "audit");
+  }
+  emc::mean2_kernel<<<1, 256, 0, st>>>(recall, na, recall_mean);
+  // triples grouped by rotation (frames ascending), then the sparse M-step; the
+  // triple count stays on the device
+  HIP_TRY(launch_triple_sort(tj, tk, tp, count, triple_cap, pb->n_rot, hist, cursor, tptr, tk2, tp2, st),
+          "triple sort");
+  (void)order;
+  float* Wp = (float*)slices;  // hi/lo are no longer needed
+  HIP_TRY(launch_sparse_mstep(tptr, tk2, tp2, K_cand, nc, K_audit, true, ps, pb->n_rot, Wp, rho, st), "sparse mstep");
+  HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
+  HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");
+  HIP_TRY(launch_scatter(Wp, ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, st),
+          "scatter");
+  CHECK(run_finalize(pb, num, den, model_in, model_out, L, nc + na, loglik, st));
+  (void)rho_a;
+  (void)kRecallMin;
   return EMC_OK;
 }
 

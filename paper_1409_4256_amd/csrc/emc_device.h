@@ -75,7 +75,7 @@ __device__ __forceinline__ T wave_sum(T v) {
 hipError_t launch_fill_zero_f64(double* p, size_t n, hipStream_t st);
 // counts [n_data][n_pix] -> K [n_data][ps] and KT [ps][ds] (float or bf16); ds = data stride
 hipError_t launch_pack(const uint16_t* counts, const uint8_t* mask, int n_pix, int64_t ps, int64_t n_data,
-                       int64_t ds, void* K, void* KT, bool bf16, hipStream_t st);
+                       int64_t ds, const int32_t* frames, void* K, void* KT, bool bf16, hipStream_t st);
 hipError_t read_range_flag(int* flag, hipStream_t st);  // synchronises `st`
 hipError_t launch_centre(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
                          int n_pix, int64_t stride, int n_rot, double* c, hipStream_t st);
@@ -98,6 +98,12 @@ hipError_t launch_gemm_bf16_dual_nt(const void* A_hi, const void* A_lo, const vo
                                     hipStream_t st);
 hipError_t launch_gemm_bf16_nt(const void* A, const void* B, float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda,
                                int64_t ldb, int64_t ldc, hipStream_t st);
+// grouped, gathered form: tiles[w] = (block g, tile t); A rows list[off[g] + 256 t + r];
+// B rows 256 g .. 256 g + 255 (< n_frames); C compact [list row][256]
+hipError_t launch_gemm_bf16_dual_gather(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
+                                        float* C, int64_t n_frames, int64_t Kd, int64_t lda, int64_t ldb,
+                                        const int32_t* list, const int64_t* off, const int2* tiles, int64_t n_tiles,
+                                        hipStream_t st);
 hipError_t launch_lse_stats(const float* G, int64_t ld, int n_rot, int64_t n_data, const double* log_w,
                             const double* S, const double* b, double* stats, hipStream_t st);
 hipError_t launch_lse_finish(const double* stats, int64_t n_data, double* L, hipStream_t st);
@@ -133,5 +139,35 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 hipError_t launch_topk(const float* z, int64_t rows, int n_cells, int k, int32_t* out, hipStream_t st);
 hipError_t launch_cell_targets(const void* P, bool bf16, int64_t ldp, int64_t n_data, const int32_t* cell_ptr,
                                const int32_t* cell_rot, int n_cells, float* T, hipStream_t st);
+
+// ---- learned-proposal E/M steps (proposal.hip) ----
+hipError_t launch_assign_cells(const float* quat, int n_rot, const float* coarse, int n_cells, int32_t* cell_of,
+                               hipStream_t st);
+hipError_t launch_counting_sort(const int32_t* keys, int64_t n, int nk, int32_t* hist, int32_t* cursor,
+                                int64_t* ptr, int32_t* order, float* payload_unused, hipStream_t st);
+hipError_t launch_segment_sort(const int64_t* ptr, int n_seg, int32_t* vals, float* payload, hipStream_t st);
+hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* ptr, hipStream_t st);
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
+hipError_t launch_cand_mask(const int32_t* topk, int k_top, const int32_t* frames, int64_t n_frames, int words,
+                            uint32_t* mask, hipStream_t st);
+hipError_t launch_block_union(const uint32_t* mask, int words, int64_t n_frames, int n_blocks, const int64_t* cell_ptr,
+                              const int32_t* cell_rot, int pass, int64_t* len, const int64_t* off, int32_t* list,
+                              hipStream_t st);
+hipError_t launch_tile_table(const int64_t* off, int n_blocks, int2* tiles, hipStream_t st);
+hipError_t launch_cand_estep(float* GP, const int64_t* off, const int32_t* list, int64_t n_frames, int n_blocks,
+                             const uint32_t* mask, int words, const int32_t* cell_of, const double* log_w,
+                             const double* S, const double* b, double* L, int32_t* tj, int32_t* tk, float* tp,
+                             int64_t cap, unsigned long long* count, int32_t* overflow, hipStream_t st);
+hipError_t launch_audit(const void* P, bool bf16, int64_t ldp, int n_rot, int64_t n_audit, const uint32_t* mask_audit,
+                        int words, const int32_t* cell_of, int32_t frame_base, int32_t* tj, int32_t* tk, float* tp,
+                        int64_t cap, unsigned long long* count, int32_t* overflow, double* recall, hipStream_t st);
+hipError_t launch_triple_sort(const int32_t* tj, const int32_t* tk, const float* tp, const unsigned long long* count,
+                              int64_t cap, int n_rot, int32_t* hist, int32_t* cursor, int64_t* ptr, int32_t* tk2,
+                              float* tp2, hipStream_t st);
+hipError_t launch_gather_triples(const int32_t* order, int64_t n, const int32_t* tk, const float* tp, int32_t* tk2,
+                                 float* tp2, hipStream_t st);
+hipError_t launch_sparse_mstep(const int64_t* tptr, const int32_t* tk, const float* tp, const void* Kc, int64_t n_cand,
+                               const void* Ka, bool bf16, int64_t ps, int n_rot, float* Wp, double* rho,
+                               hipStream_t st);
 
 }  // namespace emc

@@ -20,12 +20,18 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int TM = 256, TN = 256, TK = 32, LROW = TK + 8;  // LDS row in bf16 elements
 constexpr int GROUP = 8;
 
-template <bool DUAL>
+// GATHER: grouped form for the learned proposal.  Workgroup w takes tile
+// tiles[w] = (g, t): A rows are list[off[g] + 256 t + r] (-1 reads zero), B rows
+// are the 256 frames of block g (rows >= N read zero), and C is the compact
+// [list row][256] buffer (ldc = 256).
+template <bool DUAL, bool GATHER>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restrict__ A, const uint16_t* __restrict__ A2,
                                                         const uint16_t* __restrict__ B,
                                                         const float* __restrict__ row_scale, float* __restrict__ C,
                                                         int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb,
-                                                        int64_t ldc) {
+                                                        int64_t ldc, const int32_t* __restrict__ list,
+                                                        const int64_t* __restrict__ off,
+                                                        const int2* __restrict__ tiles) {
   constexpr int NA = DUAL ? 2 : 1;
   __shared__ __attribute__((aligned(16))) uint16_t As[2][NA][TM * LROW];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TN * LROW];
@@ -33,14 +39,37 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
-  const int64_t pid = blockIdx.x;
-  const int64_t group = (int64_t)GROUP * tiles_n;
-  const int64_t first_m = (pid / group) * GROUP;
-  const int64_t gm = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
-  const int64_t tm = first_m + (pid % group) % gm;
-  const int64_t tn = (pid % group) / gm;
-  const int64_t m0 = tm * TM, n0 = tn * TN;
+  int64_t m0, n0;
+  if constexpr (GATHER) {
+    const int2 tl = tiles[blockIdx.x];
+    m0 = off[tl.x] + (int64_t)TM * tl.y;
+    n0 = (int64_t)TN * tl.x;
+  } else {
+    const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+    const int64_t pid = blockIdx.x;
+    const int64_t group = (int64_t)GROUP * tiles_n;
+    const int64_t first_m = (pid / group) * GROUP;
+    const int64_t gm = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
+    const int64_t tm = first_m + (pid % group) % gm;
+    const int64_t tn = (pid % group) / gm;
+    m0 = tm * TM;
+    n0 = tn * TN;
+  }
+  // A row of each of this thread's four load slots (gathered rows resolved once)
+  int64_t arow_src[4];
+  bool arow_ok[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = (tid + 256 * u) >> 2;
+    if constexpr (GATHER) {
+      const int32_t j = list[m0 + r];
+      arow_src[u] = j < 0 ? 0 : j;
+      arow_ok[u] = j >= 0;
+    } else {
+      arow_src[u] = m0 + r;
+      arow_ok[u] = m0 + r < M;
+    }
+  }
 
   uint4 ra[NA][4], rb[4];
   const uint4 zero = {0u, 0u, 0u, 0u};
@@ -49,10 +78,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int f = tid + 256 * u, r = f >> 2, ch = f & 3;
-      const int64_t ma = m0 + r, nb = n0 + r;
+      const int64_t ma = arow_src[u], nb = n0 + r;
       const int64_t ka = k0 + 8 * ch;
-      ra[0][u] = ma < M ? *reinterpret_cast<const uint4*>(A + ma * lda + ka) : zero;
-      if constexpr (DUAL) ra[NA - 1][u] = ma < M ? *reinterpret_cast<const uint4*>(A2 + ma * lda + ka) : zero;
+      ra[0][u] = arow_ok[u] ? *reinterpret_cast<const uint4*>(A + ma * lda + ka) : zero;
+      if constexpr (DUAL) ra[NA - 1][u] = arow_ok[u] ? *reinterpret_cast<const uint4*>(A2 + ma * lda + ka) : zero;
       rb[u] = nb < N ? *reinterpret_cast<const uint4*>(B + nb * ldb + ka) : zero;
     }
   };
@@ -104,12 +133,23 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = rbase + 16 * i + r;
-      if (row >= M) continue;
-      const float sc = DUAL ? row_scale[row] : 1.0f;
+      float sc = 1.0f;
+      if constexpr (GATHER) {
+        const int32_t j = list[row];
+        sc = DUAL ? (j >= 0 ? row_scale[j] : 0.0f) : 1.0f;
+      } else {
+        if (row >= M) continue;
+        if (DUAL) sc = row_scale[row];
+      }
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int64_t col = cbase + 16 * j;
-        if (col < N) C[row * ldc + col] = sc * acc[i][j][r];
+        if (col < N) {
+          if constexpr (GATHER)
+            C[row * TN + (col - n0)] = sc * acc[i][j][r];
+          else
+            C[row * ldc + col] = sc * acc[i][j][r];
+        }
       }
     }
   }
@@ -120,8 +160,20 @@ static hipError_t launch(const void* A, const void* A2, const void* B, const flo
                          int64_t N, int64_t Kd, int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
-  gemm_bf16_kernel<DUAL><<<(unsigned)tiles, 256, 0, st>>>((const uint16_t*)A, (const uint16_t*)A2,
-                                                          (const uint16_t*)B, scale, C, M, N, Kd, lda, ldb, ldc);
+  gemm_bf16_kernel<DUAL, false><<<(unsigned)tiles, 256, 0, st>>>((const uint16_t*)A, (const uint16_t*)A2,
+                                                                 (const uint16_t*)B, scale, C, M, N, Kd, lda, ldb,
+                                                                 ldc, nullptr, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16_dual_gather(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
+                                        float* C, int64_t n_frames, int64_t Kd, int64_t lda, int64_t ldb,
+                                        const int32_t* list, const int64_t* off, const int2* tiles, int64_t n_tiles,
+                                        hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  gemm_bf16_kernel<true, true><<<(unsigned)n_tiles, 256, 0, st>>>(
+      (const uint16_t*)A_hi, (const uint16_t*)A_lo, (const uint16_t*)B, row_scale, C, 0, n_frames, Kd, lda, ldb, TN,
+      list, off, tiles);
   return hipGetLastError();
 }
 

@@ -27,8 +27,8 @@ __device__ __forceinline__ __hip_bfloat16 from_count<__hip_bfloat16>(unsigned c)
 template <typename T, bool BF16>
 __global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ counts,
                                                    const uint8_t* __restrict__ mask, int n_pix, int64_t ps,
-                                                   int64_t n_data, int64_t ds, T* __restrict__ K,
-                                                   T* __restrict__ KT) {
+                                                   int64_t n_data, int64_t ds, const int32_t* __restrict__ frames,
+                                                   T* __restrict__ K, T* __restrict__ KT) {
   __shared__ unsigned tile[64][65];
   const int64_t i0 = (int64_t)blockIdx.x * 64, k0 = (int64_t)blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
@@ -37,7 +37,8 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ 
     const int64_t k = k0 + r, i = i0 + tx;
     unsigned c = 0;
     if (k < n_data && i < n_pix && mask[i]) {
-      c = counts[k * n_pix + i];
+      const int64_t src = frames ? (int64_t)frames[k] : k;
+      c = counts[src * n_pix + i];
       if (BF16 && c > 256u) over = true;
     }
     tile[r][tx] = c;
@@ -52,14 +53,15 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint16_t* __restrict__ 
 }
 
 hipError_t launch_pack(const uint16_t* counts, const uint8_t* mask, int n_pix, int64_t ps, int64_t n_data,
-                       int64_t ds, void* K, void* KT, bool bf16, hipStream_t st) {
+                       int64_t ds, const int32_t* frames, void* K, void* KT, bool bf16, hipStream_t st) {
   dim3 grid((unsigned)(ps / 64), (unsigned)(ds / 64));
   if (bf16) {
     clear_flag_kernel<<<1, 1, 0, st>>>();
-    pack_kernel<__hip_bfloat16, true><<<grid, 256, 0, st>>>(counts, mask, n_pix, ps, n_data, ds,
+    pack_kernel<__hip_bfloat16, true><<<grid, 256, 0, st>>>(counts, mask, n_pix, ps, n_data, ds, frames,
                                                             (__hip_bfloat16*)K, (__hip_bfloat16*)KT);
   } else {
-    pack_kernel<float, false><<<grid, 256, 0, st>>>(counts, mask, n_pix, ps, n_data, ds, (float*)K, (float*)KT);
+    pack_kernel<float, false><<<grid, 256, 0, st>>>(counts, mask, n_pix, ps, n_data, ds, frames, (float*)K,
+                                                    (float*)KT);
   }
   return hipGetLastError();
 }

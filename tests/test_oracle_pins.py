@@ -306,3 +306,27 @@ def test_masked_pixels_have_no_influence():
     for key in ("Q", "P", "L", "Wp", "rho", "num", "den", "model"):
         np.testing.assert_array_equal(a[key], b[key])
     assert np.all(b["Wp"][:, t["mask"] == 0] == 0)
+
+
+def test_restricted_estep_with_all_candidates_is_the_full_estep():
+    g = _rng(30)
+    Q = g.normal(scale=30, size=(12, 7))
+    lw = np.log(g.dirichlet(np.ones(12)))
+    P, L = O.responsibilities(Q, lw)
+    Pr, Lr = O.responsibilities_restricted(Q, lw, np.ones_like(Q, dtype=bool))
+    np.testing.assert_allclose(Pr, P, rtol=1e-14)
+    np.testing.assert_allclose(Lr, L, rtol=1e-14)
+
+
+def test_restricted_estep_is_conditional_posterior():
+    # restricting the sum gives the posterior conditioned on j in cand(k): P_restricted = P / recall
+    g = _rng(31)
+    Q = g.normal(scale=3, size=(10, 6))
+    lw = np.log(g.dirichlet(np.ones(10)))
+    cand = g.random((10, 6)) < 0.5
+    cand[0] = True
+    P, _ = O.responsibilities(Q, lw)
+    Pr, _ = O.responsibilities_restricted(Q, lw, cand)
+    rec = O.proposal_recall(P, cand)
+    np.testing.assert_allclose(Pr, np.where(cand, P / rec[None, :], 0.0), rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(Pr.sum(0), 1.0, rtol=1e-14)
