@@ -585,13 +585,14 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_cells, int n_audit) {
   L.list_off = take((size_t)(n_blocks + 1) * 8);
   L.list = take((size_t)n_blocks * rs * 4);
   L.tiles = take((size_t)n_blocks * (rs / 256) * 8);
-  L.hist = take((size_t)(n_cells > n_rot ? n_cells : n_rot) * 4);
-  L.cursor = take((size_t)(n_cells > n_rot ? n_cells : n_rot) * 4);
+  const int64_t nkeys = (n_cells + 1 > n_rot + 1 ? n_cells + 1 : n_rot + 1);  // largest key count sorted
+  L.hist = take((size_t)nkeys * 4);
+  L.cursor = take((size_t)nkeys * 4);
   L.keys = take((size_t)n_data * 4);
   L.order = take((size_t)n_data * 4);
   L.mark = take((size_t)n_data * 4);
   L.len = take((size_t)(n_blocks + 1) * 8);
-  L.coarse_hist = take((size_t)(n_cells + 1) * 8);
+  L.coarse_hist = take((size_t)(n_cells + 2) * 8);  // frame-sort pointers: n_cells + 1 keys
   L.total = o;
   return L;
 }
@@ -607,9 +608,12 @@ __global__ void top1_keys_kernel(const int32_t* __restrict__ topk, int k_top, co
   // audited frames sort after every cell; frames without a valid proposal go to the last cell
   keys[f] = mark[f] ? n_cells : (c >= 0 && c < n_cells ? c : n_cells - 1);
 }
-__global__ void mark_kernel(const int32_t* __restrict__ audit, int64_t n_audit, int32_t* __restrict__ mark) {
+__global__ void mark_kernel(const int32_t* __restrict__ audit, int64_t n_audit, int64_t n_data,
+                            int32_t* __restrict__ mark) {
   const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (a < n_audit) mark[audit[a]] = 1;
+  if (a >= n_audit) return;
+  const int32_t f = audit[a];
+  if (f >= 0 && f < n_data) mark[f] = 1;
 }
 __global__ void copy_i32_kernel(const int32_t* __restrict__ src, int64_t n, int32_t* __restrict__ dst) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) dst[e] = src[e];
@@ -711,7 +715,8 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
           "sort rotations");
   // 2. frames: audited ones apart, the others grouped by their best cell
   HIP_TRY(launch_fill_i32(mark, n_data, 0, st), "mark");
-  if (n_audit > 0) emc::mark_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(audit, n_audit, mark);
+  if (n_audit > 0)
+    emc::mark_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(audit, n_audit, n_data, mark);
   emc::top1_keys_kernel<<<(unsigned)((n_data + 255) / 256), 256, 0, st>>>(topk, k_top, mark, n_data, n_cells, keys);
   HIP_TRY(launch_counting_sort(keys, n_data, n_cells + 1, hist, cursor, frame_ptr, order, nullptr, st), "sort frames");
   if (n_cand > 0) emc::copy_i32_kernel<<<(unsigned)((n_cand + 255) / 256), 256, 0, st>>>(order, n_cand, P.cand_frames);

@@ -31,7 +31,9 @@ EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride",
            "emc_slices_bytes", "emc_workspace_bytes", "emc_pack_frames", "emc_expand", "emc_loglik",
            "emc_responsibilities", "emc_compress", "emc_finalize", "emc_iterate",
            "emc_cnn_param_count", "emc_cnn_workspace_bytes", "emc_cnn_preprocess", "emc_cnn_forward",
-           "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_targets")
+           "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_targets",
+           "emc_pack_frames_list", "emc_proposal_bytes", "emc_proposal_build", "emc_proposed_workspace_bytes",
+           "emc_iterate_proposed")
 
 
 class EmcError(RuntimeError):
@@ -53,6 +55,18 @@ class Problem(ctypes.Structure):
         ("mask", ctypes.c_void_p),
         ("quat", ctypes.c_void_p),
         ("log_w", ctypes.c_void_p),
+    ]
+
+
+class Proposal(ctypes.Structure):
+    _fields_ = [
+        ("n_cells", ctypes.c_int32), ("k_top", ctypes.c_int32), ("n_cand", ctypes.c_int32),
+        ("n_audit", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("words", ctypes.c_int32),
+        ("n_list", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
+        ("cell_of", ctypes.c_void_p), ("cell_ptr", ctypes.c_void_p), ("cell_rot", ctypes.c_void_p),
+        ("cand_frames", ctypes.c_void_p), ("audit_frames", ctypes.c_void_p), ("mask_cand", ctypes.c_void_p),
+        ("mask_audit", ctypes.c_void_p), ("list_off", ctypes.c_void_p), ("list", ctypes.c_void_p),
+        ("tiles", ctypes.c_void_p),
     ]
 
 
@@ -98,6 +112,15 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_cnn_adam.restype = st
     lib.emc_cnn_topk.argtypes, lib.emc_cnn_topk.restype = [_P, i64, i32, i32, _P, _P], st
     lib.emc_cell_targets.argtypes, lib.emc_cell_targets.restype = [_PB, _P, _P, _P, i32, _P, _P], st
+    _PP = ctypes.POINTER(Proposal)
+    lib.emc_pack_frames_list.argtypes, lib.emc_pack_frames_list.restype = [_PB, _P, _P, _P, _P], st
+    lib.emc_proposal_bytes.argtypes, lib.emc_proposal_bytes.restype = [_PB, i32, i32, szp], st
+    lib.emc_proposal_build.argtypes = [_PB, _P, i32, _P, i32, _P, i32, _P, ctypes.c_size_t, _PP, _P]
+    lib.emc_proposal_build.restype = st
+    lib.emc_proposed_workspace_bytes.argtypes = [_PB, _PP, i64, szp]
+    lib.emc_proposed_workspace_bytes.restype = st
+    lib.emc_iterate_proposed.argtypes = [_PB, _PP, _P, _P, _P, _P, _P, _P, _P, i64, _P, ctypes.c_size_t, _P]
+    lib.emc_iterate_proposed.restype = st
     _lib = lib
     return lib
 
@@ -401,3 +424,67 @@ def emc_cell_targets(geo: Geometry, P, cell_ptr, cell_rot, n_cells, T, stream=No
                                    _ptr(cell_ptr, torch.int32, n_cells + 1, "cell_ptr"),
                                    _ptr(cell_rot, torch.int32, geo.n_rot, "cell_rot"), int(n_cells),
                                    _ptr(T, torch.float32, geo.n_data * n_cells, "T"), _stream(stream)))
+
+
+# ------------------------------------------------------------------------- learned-proposal iteration
+def emc_pack_frames_list(geo: Geometry, counts, frames, K_packed, stream=None):
+    """geo.n_data = number of listed frames; counts is the full [frames][n_pix] array."""
+    import torch
+
+    n = geo.n_data
+    _check(load().emc_pack_frames_list(ctypes.byref(geo.pb), _ptr(counts, torch.uint16, None, "counts") if n else None,
+                                       _ptr(frames, torch.int32, n, "frames") if n else None,
+                                       _ptr(K_packed, None, None, "K_packed", nbytes=emc_frames_bytes(geo)) if n else None,
+                                       _stream(stream)))
+
+
+def emc_proposal_bytes(geo: Geometry, n_cells: int, n_audit: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().emc_proposal_bytes(ctypes.byref(geo.pb), int(n_cells), int(n_audit), ctypes.byref(n)))
+    return int(n.value)
+
+
+def emc_proposal_build(geo: Geometry, coarse, n_cells, topk, k_top, audit, buf, stream=None) -> Proposal:
+    import torch
+
+    plan = Proposal()
+    n_audit = 0 if audit is None else int(audit.numel())
+    _check(load().emc_proposal_build(
+        ctypes.byref(geo.pb), _ptr(coarse, torch.float32, 4 * n_cells, "coarse"), int(n_cells),
+        _ptr(topk, torch.int32, geo.n_data * k_top, "topk"), int(k_top),
+        _ptr(audit, torch.int32, n_audit, "audit") if n_audit else None, n_audit,
+        _ptr(buf, torch.uint8, emc_proposal_bytes(geo, n_cells, n_audit), "buf"), ctypes.c_size_t(buf.numel()),
+        ctypes.byref(plan), _stream(stream)))
+    return plan
+
+
+def emc_proposed_workspace_bytes(geo: Geometry, plan: Proposal, triple_cap: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().emc_proposed_workspace_bytes(ctypes.byref(geo.pb), ctypes.byref(plan), int(triple_cap),
+                                               ctypes.byref(n)))
+    return int(n.value)
+
+
+def emc_iterate_proposed(geo: Geometry, plan: Proposal, K_cand, K_audit, model_in, model_out, loglik, recall_mean,
+                         status, triple_cap, ws, stream=None):
+    import torch
+
+    M = geo.grid_n ** 3
+    _check(load().emc_iterate_proposed(
+        ctypes.byref(geo.pb), ctypes.byref(plan),
+        _ptr(K_cand, None, None, "K_cand") if plan.n_cand else None,
+        _ptr(K_audit, None, None, "K_audit") if plan.n_audit else None,
+        _ptr(model_in, torch.float32, M, "model_in"), _ptr(model_out, torch.float32, M, "model_out"),
+        _ptr(loglik, torch.float64, 1, "loglik"), _ptr(recall_mean, torch.float64, 1, "recall_mean"),
+        _ptr(status, torch.int32, 1, "status"), int(triple_cap),
+        _ptr(ws, torch.uint8, emc_proposed_workspace_bytes(geo, plan, triple_cap), "ws"),
+        ctypes.c_size_t(ws.numel()), _stream(stream)))
+
+
+def plan_array(buf, address: int, n: int, dtype):
+    """A tensor view of n elements of a plan array (device address inside `buf`)."""
+    import torch
+
+    off = int(address) - buf.data_ptr()
+    size = torch.empty(0, dtype=dtype).element_size()
+    return buf[off:off + n * size].view(dtype)

@@ -1,0 +1,157 @@
+"""Driver of the learned orientation proposal (control flow over the C ABI only).
+
+Every computation runs in libemc.so: network preprocessing, forward, gradients,
+Adam, top-K, training targets, the proposal plan and the restricted iteration.
+This module sequences those calls: it collects training targets from full
+iterations, trains the network on them, builds the plan, and runs restricted
+iterations with the recall audit deciding the fallback to the full search.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+import torch
+
+from . import emc as E
+
+RECALL_MIN = 0.98
+
+
+def init_params(rng: np.random.Generator, n_cells: int) -> torch.Tensor:
+    """He-normal weights, zero biases, in the library's parameter layout (random numbers
+    drawn on the host and handed to the device, like every other input)."""
+    chans = (1, 32, 64, 128, 128)
+    parts = []
+    for l in range(4):
+        ci, co = chans[l], chans[l + 1]
+        parts.append(rng.standard_normal(co * ci * 9) * math.sqrt(2.0 / (ci * 9)))
+        parts.append(np.zeros(co))
+    parts.append(rng.standard_normal(n_cells * 2048) * math.sqrt(2.0 / 2048))
+    parts.append(np.zeros(n_cells))
+    v = np.concatenate(parts).astype(np.float32)
+    assert v.size == E.emc_cnn_param_count(n_cells)
+    return torch.as_tensor(v, device="cuda")
+
+
+class CellIndex:
+    """Fine rotations grouped by coarse cell (CSR), computed by the library's plan kernels."""
+
+    def __init__(self, geo: E.Geometry, coarse: torch.Tensor, n_cells: int):
+        # a plan over a single dummy frame gives the rotation grouping
+        one = geo.with_frames(1)
+        topk = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.buf = torch.empty(E.emc_proposal_bytes(one, n_cells, 0), dtype=torch.uint8, device="cuda")
+        plan = E.emc_proposal_build(one, coarse, n_cells, topk, 1, None, self.buf)
+        self.cell_of = E.plan_array(self.buf, plan.cell_of, geo.n_rot, torch.int32).clone()
+        ptr64 = E.plan_array(self.buf, plan.cell_ptr, n_cells + 1, torch.int64)
+        self.cell_ptr = ptr64.to(torch.int32).clone()
+        self.cell_rot = E.plan_array(self.buf, plan.cell_rot, geo.n_rot, torch.int32).clone()
+        del self.buf
+
+
+@dataclasses.dataclass
+class TrainLog:
+    steps: int
+    epochs: int
+    loss_first: float
+    loss_last: float
+    seconds: float
+
+
+class Network:
+    def __init__(self, n_cells: int, params: torch.Tensor, batch: int = 256):
+        self.n_cells = n_cells
+        self.params = params
+        self.batch = batch
+        self.ws = torch.empty(E.emc_cnn_workspace_bytes(n_cells, batch), dtype=torch.uint8, device="cuda")
+        n = E.emc_cnn_param_count(n_cells)
+        self.grads = torch.zeros(n, dtype=torch.float32, device="cuda")
+        self.m = torch.zeros_like(self.grads)
+        self.v = torch.zeros_like(self.grads)
+        self.step = 0
+
+    def images(self, geo: E.Geometry, K, bins: torch.Tensor) -> torch.Tensor:
+        x = torch.empty(geo.n_data * 4096, dtype=torch.float32, device="cuda")
+        E.emc_cnn_preprocess(geo, K, bins, None, geo.n_data, x)
+        return x
+
+    def train(self, x: torch.Tensor, targets: list, frames_per_set: int, epochs: int, lr: float,
+              rng: np.random.Generator) -> TrainLog:
+        """Adam on minibatches of (frame image, cell target) pairs drawn from every target set."""
+        import time
+
+        B, nc = self.batch, self.n_cells
+        n_sets = len(targets)
+        total = n_sets * frames_per_set
+        xb = torch.empty(B * 4096, dtype=torch.float32, device="cuda")
+        tb = torch.empty(B * nc, dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        first = last = float("nan")
+        t0 = time.perf_counter()
+        steps = 0
+        x2 = x.view(-1, 4096)
+        for ep in range(epochs):
+            perm = torch.as_tensor(rng.permutation(total), device="cuda")
+            for s in range(0, total - B + 1, B):
+                idx = perm[s:s + B]
+                fr = idx % frames_per_set
+                st = idx // frames_per_set
+                xb.view(B, 4096).copy_(x2[fr])
+                for si in range(n_sets):
+                    sel = st == si
+                    if bool(sel.any()):
+                        tb.view(B, nc)[sel] = targets[si].view(-1, nc)[fr[sel]]
+                E.emc_cnn_gradients(nc, self.params, xb, tb, B, self.grads, loss, self.ws)
+                self.step += 1
+                E.emc_cnn_adam(nc, self.params, self.grads, self.m, self.v, self.step, lr)
+                steps += 1
+                if steps == 1:
+                    first = loss.item()
+            last = loss.item()
+        torch.cuda.synchronize()
+        return TrainLog(steps, epochs, first, last, time.perf_counter() - t0)
+
+    def topk(self, x: torch.Tensor, n_frames: int, k: int) -> torch.Tensor:
+        B, nc = self.batch, self.n_cells
+        logits = torch.empty(B * nc, dtype=torch.float32, device="cuda")
+        out = torch.empty(n_frames * k, dtype=torch.int32, device="cuda")
+        x2 = x.view(-1, 4096)
+        for s in range(0, n_frames, B):
+            nb = min(B, n_frames - s)
+            E.emc_cnn_forward(nc, self.params, x2[s:s + nb].reshape(-1), nb, logits, self.ws)
+            E.emc_cnn_topk(logits, nb, nc, k, out[s * k:(s + nb) * k])
+        return out
+
+
+class ProposedIteration:
+    """Plan + packed frame lists + workspace for emc_iterate_proposed."""
+
+    def __init__(self, geo16: E.Geometry, counts_dev, coarse, n_cells, topk, k_top, audit, triple_cap):
+        self.geo = geo16
+        self.buf = torch.empty(E.emc_proposal_bytes(geo16, n_cells, audit.numel()), dtype=torch.uint8, device="cuda")
+        self.plan = E.emc_proposal_build(geo16, coarse, n_cells, topk, k_top, audit, self.buf)
+        p = self.plan
+        self.cand_frames = E.plan_array(self.buf, p.cand_frames, p.n_cand, torch.int32)
+        self.audit_frames = E.plan_array(self.buf, p.audit_frames, p.n_audit, torch.int32)
+        gc, ga = geo16.with_frames(p.n_cand), geo16.with_frames(p.n_audit)
+        self.Kc, self.Ka = E.frames_tensor(gc), E.frames_tensor(ga)
+        if p.n_cand:
+            E.emc_pack_frames_list(gc, counts_dev, self.cand_frames, self.Kc)
+        if p.n_audit:
+            E.emc_pack_frames_list(ga, counts_dev, self.audit_frames, self.Ka)
+        self.cap = int(triple_cap)
+        self.ws = torch.empty(E.emc_proposed_workspace_bytes(geo16, p, self.cap), dtype=torch.uint8, device="cuda")
+        self.loglik = torch.empty(1, dtype=torch.float64, device="cuda")
+        self.recall = torch.empty(1, dtype=torch.float64, device="cuda")
+        self.status = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    def step(self, model_in, model_out):
+        E.emc_iterate_proposed(self.geo, self.plan, self.Kc, self.Ka, model_in, model_out, self.loglik,
+                               self.recall, self.status, self.cap, self.ws)
+
+    def accepted(self) -> bool:
+        """The audit's verdict on the last step (synchronises)."""
+        rec = self.recall.item()
+        return self.status.item() == 0 and (math.isnan(rec) or rec >= RECALL_MIN)
