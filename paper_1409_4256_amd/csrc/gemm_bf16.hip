@@ -4,20 +4,23 @@
 // Both operands are read along the reduction index ("NT").  Photon counts are
 // exact in BF16; the slice split hi + lo keeps ~16 significant bits.
 //
-// Workgroup tile 256 x 256 x 32, 4 waves in a 2 x 2 arrangement, each wave
-// 128 x 128 from 8 x 8 v_mfma_f32_16x16x32_bf16 tiles.  Operands are staged
-// through double-buffered LDS laid out [row][k] (80-byte rows: 64 bytes of data
-// + 16 of padding, so eight lanes' 16-byte reads hit distinct banks).  A lane
-// feeds one MFMA with 8 consecutive k of one row (one 128-bit LDS read); A and
-// B use the same k assignment, so the product sums the same pairs.
+// Workgroup tile 256 x 256 x 64, 4 waves in a 2 x 2 arrangement, each wave
+// 128 x 128 from 8 x 8 v_mfma_f32_16x16x32_bf16 tiles.  One LDS stage laid out
+// [row][k] (144-byte rows: 128 bytes of data + 16 of padding, so eight lanes'
+// 16-byte reads hit distinct banks); the next stage's global loads (full
+// 128-byte row segments) are issued into registers before the current stage's
+// 4096 MFMA cycles, which hides their latency.  A lane feeds one MFMA with 8
+// consecutive k of one row (one 128-bit LDS read); A and B use the same k
+// assignment, so the product sums the same pairs.
 #include "emc_device.h"
 
 namespace emc {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));  // 16 bytes = 8 bf16
 
-constexpr int TM = 256, TN = 256, TK = 32, LROW = TK + 8;  // LDS row in bf16 elements
+constexpr int TM = 256, TN = 256, TK = 64, LROW = TK + 8;  // LDS row in bf16 elements
 constexpr int GROUP = 8;
 
 // GATHER: grouped form for the learned proposal.  Workgroup w takes tile
@@ -33,8 +36,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
                                                         const int64_t* __restrict__ off,
                                                         const int2* __restrict__ tiles) {
   constexpr int NA = DUAL ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][NA][TM * LROW];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][TN * LROW];
+  __shared__ __attribute__((aligned(16))) uint16_t As[NA][TM * LROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * LROW];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -55,45 +58,40 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
     m0 = tm * TM;
     n0 = tn * TN;
   }
-  // A row of each of this thread's four load slots (gathered rows resolved once)
-  int64_t arow_src[4];
-  bool arow_ok[4];
+  // source rows of this thread's eight load slots (row r = tid / 8 + 32 u), as
+  // element offsets of the row starts (-1: the slot reads zero)
+  constexpr int SLOTS = 8;
+  const int ch = tid & 7;
+  int64_t aoff[SLOTS], boff[SLOTS];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = (tid + 256 * u) >> 2;
+  for (int u = 0; u < SLOTS; ++u) {
+    const int r = (tid >> 3) + 32 * u;
+    int64_t src;
     if constexpr (GATHER) {
       const int32_t j = list[m0 + r];
-      arow_src[u] = j < 0 ? 0 : j;
-      arow_ok[u] = j >= 0;
+      src = j;
     } else {
-      arow_src[u] = m0 + r;
-      arow_ok[u] = m0 + r < M;
+      src = m0 + r < M ? m0 + r : -1;
     }
+    aoff[u] = src < 0 ? -1 : src * lda + 8 * ch;
+    boff[u] = n0 + r < N ? (n0 + r) * ldb + 8 * ch : -1;
   }
 
-  uint4 ra[NA][4], rb[4];
-  const uint4 zero = {0u, 0u, 0u, 0u};
-
-  auto load_stage = [&](int64_t k0) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = tid + 256 * u, r = f >> 2, ch = f & 3;
-      const int64_t ma = arow_src[u], nb = n0 + r;
-      const int64_t ka = k0 + 8 * ch;
-      ra[0][u] = arow_ok[u] ? *reinterpret_cast<const uint4*>(A + ma * lda + ka) : zero;
-      if constexpr (DUAL) ra[NA - 1][u] = arow_ok[u] ? *reinterpret_cast<const uint4*>(A2 + ma * lda + ka) : zero;
-      rb[u] = nb < N ? *reinterpret_cast<const uint4*>(B + nb * ldb + ka) : zero;
-    }
-  };
-  auto store_stage = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = tid + 256 * u, r = f >> 2, ch = f & 3;
-#pragma unroll
-      for (int a = 0; a < NA; ++a) *reinterpret_cast<uint4*>(&As[buf][a][r * LROW + 8 * ch]) = ra[a][u];
-      *reinterpret_cast<uint4*>(&Bs[buf][r * LROW + 8 * ch]) = rb[u];
-    }
-  };
+  u4 ra0[SLOTS], ra1[SLOTS], rb[SLOTS];
+  const u4 zero = {0u, 0u, 0u, 0u};
+#define EMC_LOAD_STAGE(k0)                                                                              \
+  _Pragma("unroll") for (int u = 0; u < SLOTS; ++u) {                                                 \
+    ra0[u] = aoff[u] >= 0 ? *reinterpret_cast<const u4*>(A + aoff[u] + (k0)) : zero;               \
+    if constexpr (DUAL) ra1[u] = aoff[u] >= 0 ? *reinterpret_cast<const u4*>(A2 + aoff[u] + (k0)) : zero; \
+    rb[u] = boff[u] >= 0 ? *reinterpret_cast<const u4*>(B + boff[u] + (k0)) : zero;                \
+  }
+#define EMC_STORE_STAGE()                                                                               \
+  _Pragma("unroll") for (int u = 0; u < SLOTS; ++u) {                                                 \
+    const int r = (tid >> 3) + 32 * u;                                                                  \
+    *reinterpret_cast<u4*>(&As[0][r * LROW + 8 * ch]) = ra0[u];                                    \
+    if constexpr (DUAL) *reinterpret_cast<u4*>(&As[NA - 1][r * LROW + 8 * ch]) = ra1[u];           \
+    *reinterpret_cast<u4*>(&Bs[r * LROW + 8 * ch]) = rb[u];                                        \
+  }
 
   f4 acc[8][8];
 #pragma unroll
@@ -102,29 +100,39 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
     for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   const int64_t nk = (Kd + TK - 1) / TK;
-  load_stage(0);
-  store_stage(0);
+  EMC_LOAD_STAGE(0)
+  EMC_STORE_STAGE()
   __syncthreads();
 
-  const int arow = wm * 128 + (lane & 15), brow = wn * 128 + (lane & 15), kofs = 8 * (lane >> 4);
+  const int arow_l = wm * 128 + (lane & 15), brow_l = wn * 128 + (lane & 15), kofs = 8 * (lane >> 4);
   for (int64_t s = 0; s < nk; ++s) {
-    const int buf = (int)(s & 1);
-    if (s + 1 < nk) load_stage((s + 1) * TK);
-    bf8 b[8];
+    if (s + 1 < nk) {
+      const int64_t k1 = (s + 1) * TK;
+      EMC_LOAD_STAGE(k1)
+    }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) b[j] = *reinterpret_cast<const bf8*>(&Bs[buf][(brow + 16 * j) * LROW + kofs]);
+    for (int kk = 0; kk < TK; kk += 32) {
+      bf8 b[8];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
+      for (int j = 0; j < 8; ++j) b[j] = *reinterpret_cast<const bf8*>(&Bs[(brow_l + 16 * j) * LROW + kk + kofs]);
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const bf8 av = *reinterpret_cast<const bf8*>(&As[buf][a][(arow + 16 * i) * LROW + kofs]);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[j], acc[i][j], 0, 0, 0);
+        for (int a = 0; a < NA; ++a) {
+          const bf8 av = *reinterpret_cast<const bf8*>(&As[a][(arow_l + 16 * i) * LROW + kk + kofs]);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[j], acc[i][j], 0, 0, 0);
+        }
       }
     }
-    if (s + 1 < nk) store_stage(buf ^ 1);
     __syncthreads();
+    if (s + 1 < nk) {
+      EMC_STORE_STAGE()
+      __syncthreads();
+    }
   }
+#undef EMC_LOAD_STAGE
+#undef EMC_STORE_STAGE
 
   const int64_t rbase = m0 + wm * 128 + 4 * (lane >> 4);
   const int64_t cbase = n0 + wn * 128 + (lane & 15);

@@ -234,7 +234,7 @@ def test_iterate_entry_point_equals_steps(gpu_lib, cfg1, precision):
 # ------------------------------------------------------------------------------- BF16 form
 @pytest.mark.parametrize("start", ["random_smooth", "true_model"])
 def test_bf16_config1_within_mixed_tolerance(gpu_lib, cfg1, start):
-    from gpu_helpers import geometry, pack, q_rel_err, rel_l2, run_steps, top1_agreement, upload_counts
+    from gpu_helpers import geometry, pack, q_rel_err, rel_l2, run_steps, top1_agreement, top1_strict, upload_counts
 
     inp = cfg1
     model = inp.model_start if start == "random_smooth" else inp.model_true
@@ -246,7 +246,7 @@ def test_bf16_config1_within_mixed_tolerance(gpu_lib, cfg1, start):
     _check_expand(g, o, inp.mask, 2e-4)           # hi + lo keeps ~16 significant bits of the row maximum
     errs = dict(Q=q_rel_err(g["Q"], o["Q"]), P=float(np.max(np.abs(g["P"] - o["P"]))),
                 L=abs(g["loglik"] - o["loglik"]) / abs(o["loglik"]), model=rel_l2(g["model"], o["model"]),
-                top1=top1_agreement(g["P"], o["P"]))
+                top1=top1_agreement(g["P"], o["P"]), top1_strict=top1_strict(g["P"], o["P"]))
     print(f"\n[bf16 {start}] errors vs FP64 oracle: {errs}")
     assert errs["model"] <= MIXED_MODEL_TOL, errs
     assert errs["top1"] >= MIXED_TOP1, errs

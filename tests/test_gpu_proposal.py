@@ -42,7 +42,7 @@ def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=30
         E.emc_pack_frames_list(gc, counts, cand_frames, Kc)
     if plan.n_audit:
         E.emc_pack_frames_list(ga, counts, audit_frames, Ka)
-    cap = 64 * ndata
+    cap = ndata * nrot  # every (rotation, frame) pair may be significant in these flat posteriors
     ws = torch.empty(E.emc_proposed_workspace_bytes(geo, plan, cap), dtype=torch.uint8, device=dev)
     m_in = torch.as_tensor(t["model"], dtype=torch.float32, device=dev)
     m_out = torch.empty_like(m_in)
