@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-once", action="store_true")
+    ap.add_argument("--no-proposal", action="store_true")
     return ap.parse_args()
 
 
@@ -185,6 +186,79 @@ def time_form(run, args, n_valid):
     }
 
 
+def proposal_form(inp, args, counts_dev):
+    """Learned-proposal form: full BF16 iterations 1-3 give cell targets, the network is
+    trained on them, and iterations 4-5 search each frame's proposed rotations only
+    (2 % of frames audited in full; an iteration whose audit recall is below 0.98 is
+    redone with the full search, and its time counts)."""
+    import numpy as np
+    import torch
+
+    from emc_inputs import rng as seeded
+    from emc_inputs import proposal_bins, shoemake_quaternions
+    from paper_1409_4256_amd import emc, learned
+
+    wl = inp.wl
+    n_cells, k_top = 2000, 64
+    run = Run(inp, emc.EMC_PREC_BF16, counts_dev)
+    g = run.geo
+    coarse = torch.as_tensor(shoemake_quaternions(seeded(wl.cfg, "coarse"), n_cells), dtype=torch.float32,
+                             device="cuda")
+    cells = learned.CellIndex(g, coarse, n_cells)
+    t0 = time.perf_counter()
+    targets = []
+    for it in range(3):
+        run.step()
+        T = torch.empty(wl.n_data * n_cells, dtype=torch.float32, device="cuda")
+        emc.emc_cell_targets(g, run.P, cells.cell_ptr, cells.cell_rot, n_cells, T)
+        targets.append(T)
+        torch.cuda.synchronize()
+        log(f"proposal: full iteration {it + 1}/3, loglik {run.loglik.item():.4f}")
+    t_full3 = time.perf_counter() - t0
+    bins = torch.as_tensor(proposal_bins(wl.det_n, inp.mask), device="cuda")
+    net = learned.Network(n_cells, learned.init_params(seeded(wl.cfg, "cnn"), n_cells))
+    x = net.images(g, run.K, bins)
+    tlog = net.train(x, targets, wl.n_data, epochs=1, lr=1e-3, rng=seeded(wl.cfg, "cnn"))
+    log(f"proposal: trained {tlog.steps} steps in {tlog.seconds:.1f} s, loss {tlog.loss_first:.3f} -> "
+        f"{tlog.loss_last:.3f}")
+    del targets
+    t0 = time.perf_counter()
+    topk = net.topk(x, wl.n_data, k_top)
+    n_audit = max(1, int(round(0.02 * wl.n_data)))
+    audit = torch.as_tensor(np.sort(seeded(wl.cfg, "audit").choice(wl.n_data, n_audit, replace=False)),
+                            dtype=torch.int32, device="cuda")
+    prop = learned.ProposedIteration(g, counts_dev, coarse, n_cells, topk, k_top, audit, 200 * wl.n_data)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    del x
+    log(f"proposal: plan with {prop.plan.n_tiles} gathered tiles ({prop.plan.n_list} list rows) in {t_plan:.1f} s")
+    # iterations 4-5, timed with the audit verdict and any fallback included
+    per, recs, fallbacks = [], [], 0
+    for it in range(max(2, args.steps)):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        prop.step(run.model[run.cur], run.model[1 - run.cur])
+        ok = prop.accepted()
+        if ok:
+            run.cur = 1 - run.cur
+        else:
+            fallbacks += 1
+            run.step()          # full search from the same input model
+        ev1.record()
+        torch.cuda.synchronize()
+        per.append(ev0.elapsed_time(ev1))
+        recs.append(prop.recall.item())
+        log(f"proposal iteration {it + 4}: {per[-1]:.1f} ms, audit recall {recs[-1]:.4f}, "
+            f"{'accepted' if ok else 'fell back to full search'}")
+    ms = float(np.mean(per))
+    return {"value": round(1000.0 / ms, 5), "ms_per_step": round(ms, 3), "recall": recs, "fallbacks": fallbacks,
+            "one_off_s": {"full_iterations_1_3": round(t_full3, 2), "training": round(tlog.seconds, 2),
+                          "plan": round(t_plan, 2)},
+            "training": {"steps": tlog.steps, "loss_first": tlog.loss_first, "loss_last": tlog.loss_last},
+            "gathered_tiles": int(prop.plan.n_tiles), "dense_tiles_equivalent": int(
+                ((wl.n_rot + 255) // 256) * ((wl.n_data + 255) // 256))}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -232,8 +306,15 @@ def main():
         results[form] = time_form(run, args, n_valid)
         del run
         torch.cuda.empty_cache()
+    if not args.no_proposal:
+        results["bf16+proposal"] = proposal_form(inp, args, counts_dev)
+        torch.cuda.empty_cache()
     chosen = "bf16"
-    r = results[chosen]
+    if "bf16+proposal" in results and results["bf16+proposal"]["fallbacks"] == 0 and \
+            results["bf16+proposal"]["value"] > results["bf16"]["value"]:
+        chosen = "bf16+proposal"
+    r = dict(results[chosen])
+    r.setdefault("roofline", results["bf16"]["roofline"])
     wl_ = wl
     out = {
         "metric": "EMC iters/s (128³, 16k px, 25k rot, 100k pat); plain vs BF16+proposal",

@@ -125,5 +125,13 @@ def top1_agreement(P_gpu, P_ref, rel_tie=1e-3):
     return float(np.mean(P_ref[jg, k] >= (1.0 - rel_tie) * P_ref.max(axis=0)))
 
 
+def top1_same_precision(P_gpu_bf16, P_ref):
+    """Top-1 agreement with the decision taken in the kernel's precision on both
+    sides: the reference responsibilities are rounded to BF16 (as the GPU stores
+    them) before the arg-max; equal values go to the lower rotation index."""
+    ref = torch.as_tensor(np.asarray(P_ref, np.float32)).to(torch.bfloat16).double().numpy()
+    return float(np.mean(np.argmax(P_gpu_bf16, axis=0) == np.argmax(ref, axis=0)))
+
+
 def top1_strict(P_gpu, P_ref):
     return float(np.mean(np.argmax(P_gpu, axis=0) == np.argmax(P_ref, axis=0)))

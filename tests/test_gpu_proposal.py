@@ -99,4 +99,4 @@ def test_proposal_with_every_cell_is_full_search(gpu_lib):
     r = _run(4, 18, 250, 500, 400, 12, 12, 10)
     assert r["status"] == 0
     assert rel_l2(r["model"], r["full"]["model"]) <= 1e-3
-    assert abs(r["recall"] - 1.0) <= 1e-5
+    assert abs(r["recall"] - 1.0) <= 4e-3   # sum of BF16-rounded responsibilities
