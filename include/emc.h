@@ -305,7 +305,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
                               void* buf, size_t buf_bytes, emc_proposal* plan, hipStream_t stream);
 
 /* Workspace bytes of emc_iterate_proposed; triple_cap bounds the number of
- * (rotation, frame) responsibilities >= 1e-10 kept for the M-step. */
+ * (rotation, frame) responsibilities >= 1e-7 kept for the M-step.  */
 emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan,
                                         int64_t triple_cap, size_t* bytes);
 
@@ -316,7 +316,8 @@ emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposa
  *   loglik   mean log-evidence over all frames (each over its searched set)
  *   recall_mean  mean recall of the audited frames (NaN without audit)
  *   status   device int32: bit 0 set if responsibilities overflowed triple_cap
- * Responsibilities below 1e-10 are left out of the M-step.                  */
+ * Responsibilities below 1e-7 are left out of the M-step (each frame loses
+ * at most 1e-7 x its candidate count of probability mass there).          */
 emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_cand,
                                 const void* K_audit, const float* model_in, float* model_out,
                                 double* loglik, double* recall_mean, int32_t* status,

@@ -10,7 +10,7 @@
 
 namespace emc {
 
-constexpr double kKeep = 1e-10;  // responsibilities below this are left out of the M-step
+constexpr double kKeep = 1e-7;  // responsibilities below this are left out of the M-step
 
 // ------------------------------------------------------------------ coarse cells
 // cell_of[j] = argmax_c |<q_j, q_c>| over normalised quaternions, ties -> lower c.
@@ -210,10 +210,20 @@ __global__ void tile_table_kernel(const int64_t* __restrict__ off, int n_blocks,
 }
 
 // ------------------------------------------------------------------ candidate E-step
-// One workgroup per block: thread = frame (block position).  Log-sum-exp over the
-// block's rotation list restricted to the frame's candidate cells, then P written
-// in place of G (0 outside the candidates) and the triples with P >= kKeep
-// appended (rotation, frame, P).  Overflow of the triple buffer sets *overflow.
+__device__ __forceinline__ void lse_merge2(double& m, double& s, double m2, double s2) {
+  if (m2 > m) {
+    s = s * exp(m - m2) + s2;
+    m = m2;
+  } else if (m2 > -INFINITY) {
+    s += s2 * exp(m2 - m);
+  }
+}
+
+// Workgroup = 64 frames (lanes) of one block x 4 waves splitting the block's
+// rotation list.  Log-sum-exp over the list restricted to each frame's candidate
+// cells, then P written in place of G (0 outside the candidates) and the triples
+// with P >= kKeep appended (rotation, frame, P).  Overflow of the triple buffer
+// sets *overflow.
 __global__ __launch_bounds__(256) void cand_estep_kernel(float* __restrict__ GP, const int64_t* __restrict__ off,
                                                          const int32_t* __restrict__ list, int64_t n_frames,
                                                          const uint32_t* __restrict__ mask, int words,
@@ -224,37 +234,49 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(float* __restrict__ GP,
                                                          int32_t* __restrict__ tk, float* __restrict__ tp,
                                                          int64_t cap, unsigned long long* __restrict__ count,
                                                          int32_t* __restrict__ overflow) {
-  const int g = blockIdx.x;
-  const int64_t f = (int64_t)g * 256 + threadIdx.x;
+  __shared__ double sm[4][64], ss[4][64];
+  const int g = blockIdx.x >> 2, quarter = blockIdx.x & 3;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = quarter * 64 + lane;             // frame within the block
+  const int64_t f = (int64_t)g * 256 + col;
   const bool live = f < n_frames;
   const int64_t r0 = off[g], r1 = off[g + 1];
   float* Gb = GP + r0 * 256;
   const uint32_t* m = mask + (live ? f : 0) * words;
   const double bk = live ? b[f] : 0.0;
   double mx = -INFINITY, s = 0.0;
-  for (int64_t r = r0; r < r1 && live; ++r) {
-    const int j = list[r];
-    if (j < 0) continue;
-    const int c = cell_of[j];
-    if (!((m[c >> 5] >> (c & 31)) & 1u)) continue;
-    const double a = ((double)Gb[(r - r0) * 256 + threadIdx.x] + bk) + (log_w[j] - S[j]);
-    if (!(a > -INFINITY)) continue;
-    if (a > mx) {
-      s = s * exp(mx - a) + 1.0;
-      mx = a;
-    } else {
-      s += exp(a - mx);
+  if (live) {
+    for (int64_t r = r0 + wave; r < r1; r += 4) {
+      const int j = list[r];
+      if (j < 0) continue;
+      const int c = cell_of[j];
+      if (!((m[c >> 5] >> (c & 31)) & 1u)) continue;
+      const double a = ((double)Gb[(r - r0) * 256 + col] + bk) + (log_w[j] - S[j]);
+      if (!(a > -INFINITY)) continue;
+      if (a > mx) {
+        s = s * exp(mx - a) + 1.0;
+        mx = a;
+      } else {
+        s += exp(a - mx);
+      }
     }
   }
+  sm[wave][lane] = mx;
+  ss[wave][lane] = s;
+  __syncthreads();
+  // every wave merges the four partial statistics in the same order
+  mx = sm[0][lane];
+  s = ss[0][lane];
+  for (int w = 1; w < 4; ++w) lse_merge2(mx, s, sm[w][lane], ss[w][lane]);
   const double lse = mx + log(s);
-  if (live) L[f] = lse;
-  for (int64_t r = r0; r < r1; ++r) {
+  if (live && wave == 0) L[f] = lse;
+  for (int64_t r = r0 + wave; r < r1; r += 4) {
     const int j = list[r];
     float p = 0.0f;
     if (live && j >= 0) {
       const int c = cell_of[j];
       if ((m[c >> 5] >> (c & 31)) & 1u) {
-        const double a = ((double)Gb[(r - r0) * 256 + threadIdx.x] + bk) + (log_w[j] - S[j]);
+        const double a = ((double)Gb[(r - r0) * 256 + col] + bk) + (log_w[j] - S[j]);
         const double pd = exp(a - lse);
         p = (float)pd;
         if (pd >= kKeep) {
@@ -269,7 +291,7 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(float* __restrict__ GP,
         }
       }
     }
-    Gb[(r - r0) * 256 + threadIdx.x] = p;
+    Gb[(r - r0) * 256 + col] = p;
   }
 }
 
@@ -450,8 +472,8 @@ hipError_t launch_cand_estep(float* GP, const int64_t* off, const int32_t* list,
                              const double* S, const double* b, double* L, int32_t* tj, int32_t* tk, float* tp,
                              int64_t cap, unsigned long long* count, int32_t* overflow, hipStream_t st) {
   if (n_blocks > 0)
-    cand_estep_kernel<<<(unsigned)n_blocks, 256, 0, st>>>(GP, off, list, n_frames, mask, words, cell_of, log_w, S, b, L,
-                                                          tj, tk, tp, cap, count, overflow);
+    cand_estep_kernel<<<(unsigned)n_blocks * 4, 256, 0, st>>>(GP, off, list, n_frames, mask, words, cell_of, log_w, S,
+                                                              b, L, tj, tk, tp, cap, count, overflow);
   return hipGetLastError();
 }
 
