@@ -4,8 +4,10 @@
 // Both operands are read along the reduction index ("NT").  Photon counts are
 // exact in BF16; the slice split hi + lo keeps ~16 significant bits.
 //
-// Workgroup tile 256 x 256 x 64, 4 waves in a 2 x 2 arrangement, each wave
-// 128 x 128 from 8 x 8 v_mfma_f32_16x16x32_bf16 tiles.  One LDS stage laid out
+// Workgroup tile 256 x 256 x 64 with 8 waves (two per SIMD, so that one can
+// issue MFMAs while the other waits on LDS) in a 2 x 4 arrangement, each wave
+// 128 x 64 from 8 x 4 v_mfma_f32_16x16x32_bf16 tiles (4 waves of 128 x 128 when
+// built with EMC_BF16_WAVES=4).  One LDS stage laid out
 // [row][k] (144-byte rows: 128 bytes of data + 16 of padding, so eight lanes'
 // 16-byte reads hit distinct banks); the next stage's global loads (full
 // 128-byte row segments) are issued into registers before the current stage's
@@ -27,8 +29,8 @@ constexpr int GROUP = 8;
 // tiles[w] = (g, t): A rows are list[off[g] + 256 t + r] (-1 reads zero), B rows
 // are the 256 frames of block g (rows >= N read zero), and C is the compact
 // [list row][256] buffer (ldc = 256).
-template <bool DUAL, bool GATHER>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restrict__ A, const uint16_t* __restrict__ A2,
+template <bool DUAL, bool GATHER, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* __restrict__ A, const uint16_t* __restrict__ A2,
                                                         const uint16_t* __restrict__ B,
                                                         const float* __restrict__ row_scale, float* __restrict__ C,
                                                         int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb,
@@ -39,8 +41,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
   __shared__ __attribute__((aligned(16))) uint16_t As[NA][TM * LROW];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * LROW];
 
+  // 4 waves: 2 x 2 of 128 x 128; 8 waves (two per SIMD): 2 x 4 of 128 x 64
+  constexpr int NT = 64 * WAVES;
+  constexpr int WROWS = 128;                    // rows of C per wave
+  constexpr int WCOLS = WAVES == 8 ? 64 : 128;  // columns of C per wave
+  constexpr int IT = WROWS / 16, JT = WCOLS / 16;
+  constexpr int WN = TN / WCOLS;                // waves along N
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
 
   int64_t m0, n0;
   if constexpr (GATHER) {
@@ -58,53 +66,53 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
     m0 = tm * TM;
     n0 = tn * TN;
   }
-  // source rows of this thread's eight load slots (row r = tid / 8 + 32 u), as
+  // source rows of this thread's load slots (row r = tid / 8 + (NT / 8) u), as
   // element offsets of the row starts (-1: the slot reads zero)
-  constexpr int SLOTS = 8;
+  constexpr int SLOTS = TM * 8 / NT;
   const int ch = tid & 7;
-  int64_t aoff[SLOTS], boff[SLOTS];
+  int32_t arow[SLOTS];  // A row of each slot, -1 reads zero (B rows are n0 + r)
 #pragma unroll
   for (int u = 0; u < SLOTS; ++u) {
-    const int r = (tid >> 3) + 32 * u;
-    int64_t src;
-    if constexpr (GATHER) {
-      const int32_t j = list[m0 + r];
-      src = j;
-    } else {
-      src = m0 + r < M ? m0 + r : -1;
-    }
-    aoff[u] = src < 0 ? -1 : src * lda + 8 * ch;
-    boff[u] = n0 + r < N ? (n0 + r) * ldb + 8 * ch : -1;
+    const int r = (tid >> 3) + (NT / 8) * u;
+    if constexpr (GATHER)
+      arow[u] = list[m0 + r];
+    else
+      arow[u] = m0 + r < M ? (int32_t)(m0 + r) : -1;
   }
+  const uint16_t* Ab = A + 8 * ch;
+  const uint16_t* A2b = A2 + 8 * ch;
+  const uint16_t* Bb = B + (n0 + (tid >> 3)) * ldb + 8 * ch;
+  const int64_t nvalid = N - n0 - (tid >> 3);  // slot u reads B when (NT / 8) u < nvalid
 
   u4 ra0[SLOTS], ra1[SLOTS], rb[SLOTS];
   const u4 zero = {0u, 0u, 0u, 0u};
 #define EMC_LOAD_STAGE(k0)                                                                              \
   _Pragma("unroll") for (int u = 0; u < SLOTS; ++u) {                                                 \
-    ra0[u] = aoff[u] >= 0 ? *reinterpret_cast<const u4*>(A + aoff[u] + (k0)) : zero;               \
-    if constexpr (DUAL) ra1[u] = aoff[u] >= 0 ? *reinterpret_cast<const u4*>(A2 + aoff[u] + (k0)) : zero; \
-    rb[u] = boff[u] >= 0 ? *reinterpret_cast<const u4*>(B + boff[u] + (k0)) : zero;                \
+    const int64_t ao = (int64_t)arow[u] * lda + (k0);                                                 \
+    ra0[u] = arow[u] >= 0 ? *reinterpret_cast<const u4*>(Ab + ao) : zero;                             \
+    if constexpr (DUAL) ra1[u] = arow[u] >= 0 ? *reinterpret_cast<const u4*>(A2b + ao) : zero;        \
+    rb[u] = (NT / 8) * u < nvalid ? *reinterpret_cast<const u4*>(Bb + (int64_t)(NT / 8) * u * ldb + (k0)) : zero; \
   }
 #define EMC_STORE_STAGE()                                                                               \
   _Pragma("unroll") for (int u = 0; u < SLOTS; ++u) {                                                 \
-    const int r = (tid >> 3) + 32 * u;                                                                  \
+    const int r = (tid >> 3) + (NT / 8) * u;                                                            \
     *reinterpret_cast<u4*>(&As[0][r * LROW + 8 * ch]) = ra0[u];                                    \
     if constexpr (DUAL) *reinterpret_cast<u4*>(&As[NA - 1][r * LROW + 8 * ch]) = ra1[u];           \
     *reinterpret_cast<u4*>(&Bs[r * LROW + 8 * ch]) = rb[u];                                        \
   }
 
-  f4 acc[8][8];
+  f4 acc[IT][JT];
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < IT; ++i)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < JT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   const int64_t nk = (Kd + TK - 1) / TK;
   EMC_LOAD_STAGE(0)
   EMC_STORE_STAGE()
   __syncthreads();
 
-  const int arow_l = wm * 128 + (lane & 15), brow_l = wn * 128 + (lane & 15), kofs = 8 * (lane >> 4);
+  const int arow_l = wm * WROWS + (lane & 15), brow_l = wn * WCOLS + (lane & 15), kofs = 8 * (lane >> 4);
   for (int64_t s = 0; s < nk; ++s) {
     if (s + 1 < nk) {
       const int64_t k1 = (s + 1) * TK;
@@ -112,16 +120,16 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
     }
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 32) {
-      bf8 b[8];
+      bf8 b[JT];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) b[j] = *reinterpret_cast<const bf8*>(&Bs[(brow_l + 16 * j) * LROW + kk + kofs]);
+      for (int j = 0; j < JT; ++j) b[j] = *reinterpret_cast<const bf8*>(&Bs[(brow_l + 16 * j) * LROW + kk + kofs]);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < IT; ++i) {
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
           const bf8 av = *reinterpret_cast<const bf8*>(&As[a][(arow_l + 16 * i) * LROW + kk + kofs]);
 #pragma unroll
-          for (int j = 0; j < 8; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < JT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[j], acc[i][j], 0, 0, 0);
         }
       }
     }
@@ -134,10 +142,10 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
 #undef EMC_LOAD_STAGE
 #undef EMC_STORE_STAGE
 
-  const int64_t rbase = m0 + wm * 128 + 4 * (lane >> 4);
-  const int64_t cbase = n0 + wn * 128 + (lane & 15);
+  const int64_t rbase = m0 + wm * WROWS + 4 * (lane >> 4);
+  const int64_t cbase = n0 + wn * WCOLS + (lane & 15);
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < IT; ++i) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = rbase + 16 * i + r;
@@ -150,7 +158,7 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
         if (DUAL) sc = row_scale[row];
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < JT; ++j) {
         const int64_t col = cbase + 16 * j;
         if (col < N) {
           if constexpr (GATHER)
@@ -163,14 +171,20 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(const uint16_t* __restri
   }
 }
 
+#ifndef EMC_BF16_WAVES
+#define EMC_BF16_WAVES 8
+#endif
+constexpr int kWaves = EMC_BF16_WAVES;
+static_assert(kWaves == 4 || kWaves == 8, "4 or 8 waves per workgroup");
+
 template <bool DUAL>
 static hipError_t launch(const void* A, const void* A2, const void* B, const float* scale, float* C, int64_t M,
                          int64_t N, int64_t Kd, int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
-  gemm_bf16_kernel<DUAL, false><<<(unsigned)tiles, 256, 0, st>>>((const uint16_t*)A, (const uint16_t*)A2,
-                                                                 (const uint16_t*)B, scale, C, M, N, Kd, lda, ldb,
-                                                                 ldc, nullptr, nullptr, nullptr);
+  gemm_bf16_kernel<DUAL, false, kWaves><<<(unsigned)tiles, 64 * kWaves, 0, st>>>(
+      (const uint16_t*)A, (const uint16_t*)A2, (const uint16_t*)B, scale, C, M, N, Kd, lda, ldb, ldc, nullptr,
+      nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -179,7 +193,7 @@ hipError_t launch_gemm_bf16_dual_gather(const void* A_hi, const void* A_lo, cons
                                         const int32_t* list, const int64_t* off, const int2* tiles, int64_t n_tiles,
                                         hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  gemm_bf16_kernel<true, true><<<(unsigned)n_tiles, 256, 0, st>>>(
+  gemm_bf16_kernel<true, true, kWaves><<<(unsigned)n_tiles, 64 * kWaves, 0, st>>>(
       (const uint16_t*)A_hi, (const uint16_t*)A_lo, (const uint16_t*)B, row_scale, C, 0, n_frames, Kd, lda, ldb, TN,
       list, off, tiles);
   return hipGetLastError();
