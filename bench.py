@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-once", action="store_true")
     ap.add_argument("--no-proposal", action="store_true")
+    ap.add_argument("--train-at", type=int, default=10,
+                    help="full iterations before the proposal (targets from the last three)")
     return ap.parse_args()
 
 
@@ -187,10 +189,11 @@ def time_form(run, args, n_valid):
 
 
 def proposal_form(inp, args, counts_dev):
-    """Learned-proposal form: full BF16 iterations 1-3 give cell targets, the network is
-    trained on them, and iterations 4-5 search each frame's proposed rotations only
-    (2 % of frames audited in full; an iteration whose audit recall is below 0.98 is
-    redone with the full search, and its time counts)."""
+    """Learned-proposal form: full BF16 iterations run until EMC's posteriors have
+    concentrated (iteration `args.train_at`), the last three give cell targets, the
+    network is trained on them, and the following iterations search each frame's
+    proposed rotations only (2 % of frames audited in full; an iteration whose
+    audit recall is below 0.98 is redone with the full search, and its time counts)."""
     import numpy as np
     import torch
 
@@ -207,18 +210,19 @@ def proposal_form(inp, args, counts_dev):
     cells = learned.CellIndex(g, coarse, n_cells)
     t0 = time.perf_counter()
     targets = []
-    for it in range(3):
+    for it in range(args.train_at):
         run.step()
-        T = torch.empty(wl.n_data * n_cells, dtype=torch.float32, device="cuda")
-        emc.emc_cell_targets(g, run.P, cells.cell_ptr, cells.cell_rot, n_cells, T)
-        targets.append(T)
+        if it >= args.train_at - 3:
+            T = torch.empty(wl.n_data * n_cells, dtype=torch.float32, device="cuda")
+            emc.emc_cell_targets(g, run.P, cells.cell_ptr, cells.cell_rot, n_cells, T)
+            targets.append(T)
         torch.cuda.synchronize()
-        log(f"proposal: full iteration {it + 1}/3, loglik {run.loglik.item():.4f}")
+        log(f"proposal: full iteration {it + 1}/{args.train_at}, loglik {run.loglik.item():.4f}")
     t_full3 = time.perf_counter() - t0
     bins = torch.as_tensor(proposal_bins(wl.det_n, inp.mask), device="cuda")
     net = learned.Network(n_cells, learned.init_params(seeded(wl.cfg, "cnn"), n_cells))
     x = net.images(g, run.K, bins)
-    tlog = net.train(x, targets, wl.n_data, epochs=1, lr=1e-3, rng=seeded(wl.cfg, "cnn"))
+    tlog = net.train(x, targets, wl.n_data, epochs=2, lr=1e-3, rng=seeded(wl.cfg, "cnn"))
     log(f"proposal: trained {tlog.steps} steps in {tlog.seconds:.1f} s, loss {tlog.loss_first:.3f} -> "
         f"{tlog.loss_last:.3f}")
     del targets
@@ -248,11 +252,13 @@ def proposal_form(inp, args, counts_dev):
         torch.cuda.synchronize()
         per.append(ev0.elapsed_time(ev1))
         recs.append(prop.recall.item())
-        log(f"proposal iteration {it + 4}: {per[-1]:.1f} ms, audit recall {recs[-1]:.4f}, "
+        log(f"proposal iteration {it + 1 + args.train_at}: {per[-1]:.1f} ms, audit recall {recs[-1]:.4f}, "
             f"{'accepted' if ok else 'fell back to full search'}")
     ms = float(np.mean(per))
     return {"value": round(1000.0 / ms, 5), "ms_per_step": round(ms, 3), "recall": recs, "fallbacks": fallbacks,
-            "one_off_s": {"full_iterations_1_3": round(t_full3, 2), "training": round(tlog.seconds, 2),
+            "schedule": f"full search for iterations 1-{args.train_at}, trained on iterations "
+                        f"{args.train_at - 2}-{args.train_at}, proposal from iteration {args.train_at + 1}",
+            "one_off_s": {"full_iterations": round(t_full3, 2), "training": round(tlog.seconds, 2),
                           "plan": round(t_plan, 2)},
             "training": {"steps": tlog.steps, "loss_first": tlog.loss_first, "loss_last": tlog.loss_last},
             "gathered_tiles": int(prop.plan.n_tiles), "dense_tiles_equivalent": int(
