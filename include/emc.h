@@ -271,38 +271,50 @@ emc_status emc_cell_targets(const emc_problem* pb, const void* P, const int32_t*
 emc_status emc_pack_frames_list(const emc_problem* pb, const uint16_t* counts, const int32_t* frames,
                                 void* K_packed, hipStream_t stream);
 
-/* Proposal plan: arrays carved from one caller buffer by emc_proposal_build. */
+/* Proposal plan: arrays carved from one caller buffer by emc_proposal_build.
+ * Frames are split into audited ones and candidate ones (grouped by their best
+ * cell); every (candidate frame, proposed cell) pair is a column of that cell's
+ * block of log-likelihoods G_c [rotations of c][frames that proposed c]. */
 typedef struct emc_proposal {
-  int32_t n_cells;        /* coarse cells                                            */
-  int32_t k_top;          /* cells proposed per frame                                */
-  int32_t n_cand;         /* frames searched over their candidates                   */
-  int32_t n_audit;        /* frames searched in full                                 */
-  int32_t n_blocks;       /* ceil(n_cand / 256) blocks of candidate frames           */
-  int32_t words;          /* ceil(n_cells / 32): words of a candidate-cell bitmask   */
-  int64_t n_list;         /* rows of the blocks' rotation lists (256 per tile)       */
-  int64_t n_tiles;        /* n_list / 256                                            */
-  int32_t* cell_of;       /* [n_rot] coarse cell of each rotation (max |<q, q_c>|)   */
-  int64_t* cell_ptr;      /* [n_cells + 1] rotations of cell c: cell_rot[ptr[c]..)   */
-  int32_t* cell_rot;      /* [n_rot]                                                 */
-  int32_t* cand_frames;   /* [n_cand] frame index, grouped by the frame's best cell  */
-  int32_t* audit_frames;  /* [n_audit] frame index of the audited frames             */
-  uint32_t* mask_cand;    /* [n_cand][words] candidate cells of each listed frame    */
-  uint32_t* mask_audit;   /* [n_audit][words]                                        */
-  int64_t* list_off;      /* [n_blocks + 1] offsets into list                        */
-  int32_t* list;          /* rotations of each block's candidate union (-1 padding)  */
-  void* tiles;            /* [n_tiles] (block, tile) int32 pairs                     */
+  int32_t n_cells;        /* coarse cells                                           */
+  int32_t k_top;          /* cells proposed per frame (<= 64)                       */
+  int32_t n_cand;         /* frames searched over their candidates                  */
+  int32_t n_audit;        /* frames searched in full                                */
+  int32_t words;          /* ceil(n_cells / 32): words of a cell bitmask            */
+  int32_t reserved;
+  int64_t n_tiles;        /* workgroups of the candidate log-likelihood (x 8)       */
+  int64_t n_g;            /* floats of all cells' blocks                            */
+  int64_t n_nz;           /* non-zero pixels of the candidate frames                */
+  int32_t* cell_of;       /* [n_rot] coarse cell of each rotation (max |<q, q_c>|)  */
+  int64_t* cell_ptr;      /* [n_cells + 1] rotations of cell c: cell_rot[ptr[c]..)  */
+  int32_t* cell_rot;      /* [n_rot]                                                */
+  int32_t* cand_frames;   /* [n_cand] frame index, grouped by the frame's best cell */
+  int32_t* audit_frames;  /* [n_audit] frame index of the audited frames            */
+  int32_t* cand_cells;    /* [n_cand][k_top] proposed cells of each candidate frame */
+  int32_t* pair_col;      /* [n_cand][k_top] column of the pair in its cell's block */
+  int64_t* cf_ptr;        /* [n_cells + 1] pairs of cell c: cf_frame[ptr[c]..)      */
+  int32_t* cf_frame;      /* [n_cand * k_top] candidate-frame index of each pair    */
+  int64_t* g_off;         /* [n_cells + 1] offset of cell c's block                  */
+  void* tiles;            /* [n_tiles] (cell, chunk) int32 pairs, (-1, 0) padding   */
+  uint32_t* mask_audit;   /* [n_audit][words] proposed cells of the audited frames  */
+  int64_t* nz_ptr;        /* [n_cand + 1] non-zero pixels of candidate frame f:     */
+  uint32_t* nz;           /*   nz[nz_ptr[f]..) = (pixel << 16) | count              */
 } emc_proposal;
 
-/* Bytes of the plan buffer for n_cells coarse cells and n_audit audited frames. */
-emc_status emc_proposal_bytes(const emc_problem* pb, int32_t n_cells, int32_t n_audit, size_t* bytes);
+/* Bytes of the plan buffer; nz_cap bounds the non-zero pixels of all frames. */
+emc_status emc_proposal_bytes(const emc_problem* pb, int32_t n_cells, int32_t k_top, int32_t n_audit,
+                              int64_t nz_cap, size_t* bytes);
 
-/* Builds the plan (synchronises the stream once to size the rotation lists).
+/* Builds the plan (synchronises the stream once).
  *   coarse [n_cells][4] float quaternions of the coarse grid
- *   topk   [n_data][k_top] int32 proposed cells of every frame (emc_cnn_topk)
- *   audit  [n_audit] int32 distinct frame indices searched in full          */
+ *   topk   [n_data][k_top] int32 distinct proposed cells of every frame (emc_cnn_topk)
+ *   audit  [n_audit] int32 distinct frame indices searched in full
+ *   counts [n_data][n_pix] uint16 photon counts (their non-zero unmasked pixels
+ *          are listed for the candidate frames; n_pix <= 65536)            */
 emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_t n_cells,
                               const int32_t* topk, int32_t k_top, const int32_t* audit, int32_t n_audit,
-                              void* buf, size_t buf_bytes, emc_proposal* plan, hipStream_t stream);
+                              const uint16_t* counts, int64_t nz_cap, void* buf, size_t buf_bytes,
+                              emc_proposal* plan, hipStream_t stream);
 
 /* Workspace bytes of emc_iterate_proposed; triple_cap bounds the number of
  * (rotation, frame) responsibilities >= 1e-7 kept for the M-step.  */

@@ -3,6 +3,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <string>
 
 #include "../../include/emc.h"
@@ -119,12 +120,12 @@ Layout layout_of(const emc_problem* pb) {
 // ---- launch sequences shared by the step entry points and emc_iterate (no validation) ----
 
 emc_status run_expand(const emc_problem* pb, const float* model, double* c, void* slices, double* S, float* scale,
-                      hipStream_t st) {
+                      hipStream_t st, float* A32 = nullptr) {
   const Dims d = dims_of(pb);
   HIP_TRY(launch_centre(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c, st), "centre");
   if (is_bf16(pb))
     HIP_TRY(launch_expand_bf16(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c, slices, S,
-                               scale, st),
+                               scale, A32, st),
             "expand");
   else
     HIP_TRY(launch_expand(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c,
@@ -553,20 +554,17 @@ emc_status emc_cell_targets(const emc_problem* pb, const void* P, const int32_t*
 // =========================================================================== learned-proposal iteration
 namespace {
 
-constexpr double kRecallMin = 0.98;
-
 int words_of(int n_cells) { return (n_cells + 31) / 32; }
 
-// Carving of the plan buffer (all capacities are upper bounds known before the build).
+// Carving of the plan buffer (capacities known before the build).
 struct PlanLayout {
-  size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, mask_cand, mask_audit, list_off, list, tiles,
-      hist, cursor, keys, order, mark, len, coarse_hist, total;
+  size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, g_off, tiles,
+      mask_audit, nz_ptr, nz, hist, cursor, keys, order, mark, frame_ptr, sizes, nchunk, nzcnt, scalars, total;
 };
 
-PlanLayout plan_layout(int n_rot, int n_data, int n_cells, int n_audit) {
+PlanLayout plan_layout(int n_rot, int n_data, int n_cells, int k_top, int n_audit, int64_t nz_cap) {
   const int64_t n_cand = (int64_t)n_data - n_audit;
-  const int64_t n_blocks = (n_cand + 255) / 256;
-  const int64_t rs = round_up(n_rot, 256);
+  const int64_t n_pairs = n_cand * k_top;
   const int w = words_of(n_cells);
   PlanLayout L;
   size_t o = 0;
@@ -575,24 +573,31 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_cells, int n_audit) {
     o += (size_t)round_up((int64_t)(bytes ? bytes : 1), 256);
     return at;
   };
+  const int64_t nkeys = std::max<int64_t>(n_cells + 1, std::max<int64_t>(n_rot, (int64_t)1) + 1);
   L.cell_of = take((size_t)n_rot * 4);
-  L.cell_ptr = take((size_t)(n_cells + 1) * 8);
+  L.cell_ptr = take((size_t)(n_cells + 2) * 8);
   L.cell_rot = take((size_t)n_rot * 4);
   L.cand_frames = take((size_t)n_cand * 4);
   L.audit_frames = take((size_t)n_audit * 4);
-  L.mask_cand = take((size_t)n_cand * w * 4);
+  L.cand_cells = take((size_t)n_pairs * 4);
+  L.pair_col = take((size_t)n_pairs * 4);
+  L.cf_ptr = take((size_t)(n_cells + 2) * 8);
+  L.cf_frame = take((size_t)n_pairs * 4);
+  L.g_off = take((size_t)(n_cells + 1) * 8);
+  L.tiles = take((size_t)8 * ((n_pairs + 31) / 32 + n_cells) * 8);
   L.mask_audit = take((size_t)n_audit * w * 4);
-  L.list_off = take((size_t)(n_blocks + 1) * 8);
-  L.list = take((size_t)n_blocks * rs * 4);
-  L.tiles = take((size_t)n_blocks * (rs / 256) * 8);
-  const int64_t nkeys = (n_cells + 1 > n_rot + 1 ? n_cells + 1 : n_rot + 1);  // largest key count sorted
+  L.nz_ptr = take((size_t)(n_cand + 1) * 8);
+  L.nz = take((size_t)nz_cap * 4);
   L.hist = take((size_t)nkeys * 4);
   L.cursor = take((size_t)nkeys * 4);
-  L.keys = take((size_t)n_data * 4);
-  L.order = take((size_t)n_data * 4);
+  L.keys = take((size_t)std::max<int64_t>(n_pairs, n_data) * 4);
+  L.order = take((size_t)std::max<int64_t>(n_pairs, n_data) * 4);
   L.mark = take((size_t)n_data * 4);
-  L.len = take((size_t)(n_blocks + 1) * 8);
-  L.coarse_hist = take((size_t)(n_cells + 2) * 8);  // frame-sort pointers: n_cells + 1 keys
+  L.frame_ptr = take((size_t)(n_cells + 2) * 8);
+  L.sizes = take((size_t)n_cells * 8);
+  L.nchunk = take((size_t)n_cells * 4);
+  L.nzcnt = take((size_t)n_cand * 4);
+  L.scalars = take(64);
   L.total = o;
   return L;
 }
@@ -618,32 +623,6 @@ __global__ void mark_kernel(const int32_t* __restrict__ audit, int64_t n_audit, 
 __global__ void copy_i32_kernel(const int32_t* __restrict__ src, int64_t n, int32_t* __restrict__ dst) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) dst[e] = src[e];
 }
-// exclusive scan over int64 lengths (single workgroup)
-__global__ __launch_bounds__(256) void scan_i64_kernel(const int64_t* __restrict__ len, int64_t n,
-                                                       int64_t* __restrict__ ptr) {
-  __shared__ int64_t part[256];
-  const int64_t per = (n + 255) / 256;
-  const int64_t a = threadIdx.x * per, z = a + per < n ? a + per : n;
-  int64_t s = 0;
-  for (int64_t e = a; e < z; ++e) s += len[e];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int t = 0; t < 256; ++t) {
-      const int64_t v = part[t];
-      part[t] = run;
-      run += v;
-    }
-  }
-  __syncthreads();
-  int64_t run = part[threadIdx.x];
-  for (int64_t e = a; e < z; ++e) {
-    ptr[e] = run;
-    run += len[e];
-  }
-  if (threadIdx.x == 255) ptr[n] = run;
-}
 __global__ void mean2_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ out) {
   __shared__ double red[4];
   double s = 0.0;
@@ -657,59 +636,70 @@ __global__ void mean2_kernel(const double* __restrict__ x, int64_t n, double* __
 
 extern "C" {
 
-emc_status emc_proposal_bytes(const emc_problem* pb, int32_t n_cells, int32_t n_audit, size_t* bytes) {
+emc_status emc_proposal_bytes(const emc_problem* pb, int32_t n_cells, int32_t k_top, int32_t n_audit,
+                              int64_t nz_cap, size_t* bytes) {
   CHECK(check_problem(pb, false));
   if (n_cells < 1 || n_cells > 8192) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d outside [1, 8192]", n_cells);
+  if (k_top < 1 || k_top > 64 || k_top > n_cells) return fail(EMC_ERR_INVALID_ARG, "k_top=%d outside [1, 64]", k_top);
   if (n_audit < 0 || n_audit > pb->n_data) return fail(EMC_ERR_INVALID_ARG, "n_audit=%d outside [0, n_data]", n_audit);
+  if (nz_cap < 1) return fail(EMC_ERR_INVALID_ARG, "nz_cap < 1");
   if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
-  *bytes = plan_layout(pb->n_rot, pb->n_data, n_cells, n_audit).total;
+  *bytes = plan_layout(pb->n_rot, pb->n_data, n_cells, k_top, n_audit, nz_cap).total;
   return EMC_OK;
 }
 
 emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_t n_cells, const int32_t* topk,
-                              int32_t k_top, const int32_t* audit, int32_t n_audit, void* buf, size_t buf_bytes,
-                              emc_proposal* plan, hipStream_t st) {
+                              int32_t k_top, const int32_t* audit, int32_t n_audit, const uint16_t* counts,
+                              int64_t nz_cap, void* buf, size_t buf_bytes, emc_proposal* plan, hipStream_t st) {
   CHECK(check_problem(pb, true));
   if (n_cells < 1 || n_cells > 8192) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d outside [1, 8192]", n_cells);
-  if (k_top < 1 || k_top > n_cells) return fail(EMC_ERR_INVALID_ARG, "k_top=%d outside [1, n_cells]", k_top);
+  if (k_top < 1 || k_top > 64 || k_top > n_cells) return fail(EMC_ERR_INVALID_ARG, "k_top=%d outside [1, 64]", k_top);
   if (n_audit < 0 || n_audit > pb->n_data) return fail(EMC_ERR_INVALID_ARG, "n_audit outside [0, n_data]");
   if (pb->n_data < 1) return fail(EMC_ERR_INVALID_ARG, "the proposal needs frames");
+  if (pb->n_pix > 65536) return fail(EMC_ERR_UNSUPPORTED, "the proposal form needs n_pix <= 65536");
+  if (nz_cap < 1) return fail(EMC_ERR_INVALID_ARG, "nz_cap < 1");
   CHECK(need(coarse, 16, "coarse"));
   CHECK(need(topk, 4, "topk"));
   if (n_audit > 0) CHECK(need(audit, 4, "audit"));
+  CHECK(need(counts, 2, "counts"));
   if (!plan) return fail(EMC_ERR_INVALID_ARG, "plan is NULL");
-  const PlanLayout L = plan_layout(pb->n_rot, pb->n_data, n_cells, n_audit);
+  const PlanLayout L = plan_layout(pb->n_rot, pb->n_data, n_cells, k_top, n_audit, nz_cap);
   if (!buf || !aligned(buf, 256)) return fail(EMC_ERR_WORKSPACE, "plan buffer is NULL or not 256-byte aligned");
   if (buf_bytes < L.total) return fail(EMC_ERR_WORKSPACE, "plan buffer has %zu bytes, needs %zu", buf_bytes, L.total);
   char* b = (char*)buf;
-  const int64_t n_data = pb->n_data, n_cand = n_data - n_audit;
-  const int n_blocks = (int)((n_cand + 255) / 256);
+  const int64_t n_data = pb->n_data, n_cand = n_data - n_audit, n_pairs = n_cand * k_top;
   const int w = words_of(n_cells);
-  emc_proposal P;
+  emc_proposal P{};
   P.n_cells = n_cells;
   P.k_top = k_top;
   P.n_cand = (int32_t)n_cand;
   P.n_audit = n_audit;
-  P.n_blocks = n_blocks;
   P.words = w;
   P.cell_of = (int32_t*)(b + L.cell_of);
   P.cell_ptr = (int64_t*)(b + L.cell_ptr);
   P.cell_rot = (int32_t*)(b + L.cell_rot);
   P.cand_frames = (int32_t*)(b + L.cand_frames);
   P.audit_frames = (int32_t*)(b + L.audit_frames);
-  P.mask_cand = (uint32_t*)(b + L.mask_cand);
-  P.mask_audit = (uint32_t*)(b + L.mask_audit);
-  P.list_off = (int64_t*)(b + L.list_off);
-  P.list = (int32_t*)(b + L.list);
+  P.cand_cells = (int32_t*)(b + L.cand_cells);
+  P.pair_col = (int32_t*)(b + L.pair_col);
+  P.cf_ptr = (int64_t*)(b + L.cf_ptr);
+  P.cf_frame = (int32_t*)(b + L.cf_frame);
+  P.g_off = (int64_t*)(b + L.g_off);
   P.tiles = (void*)(b + L.tiles);
+  P.mask_audit = (uint32_t*)(b + L.mask_audit);
+  P.nz_ptr = (int64_t*)(b + L.nz_ptr);
+  P.nz = (uint32_t*)(b + L.nz);
   int32_t* hist = (int32_t*)(b + L.hist);
   int32_t* cursor = (int32_t*)(b + L.cursor);
   int32_t* keys = (int32_t*)(b + L.keys);
   int32_t* order = (int32_t*)(b + L.order);
   int32_t* mark = (int32_t*)(b + L.mark);
-  int64_t* len = (int64_t*)(b + L.len);
-  int64_t* frame_ptr = (int64_t*)(b + L.coarse_hist);
-  // 1. coarse cell of every fine rotation, rotations grouped by cell
+  int64_t* frame_ptr = (int64_t*)(b + L.frame_ptr);
+  int64_t* sizes = (int64_t*)(b + L.sizes);
+  int32_t* nchunk = (int32_t*)(b + L.nchunk);
+  int32_t* nzcnt = (int32_t*)(b + L.nzcnt);
+  int64_t* scal = (int64_t*)(b + L.scalars);  // [0] n_tiles
+  // 1. coarse cell of every fine rotation; rotations grouped by cell
   HIP_TRY(launch_assign_cells(pb->quat, pb->n_rot, coarse, n_cells, P.cell_of, st), "assign cells");
   HIP_TRY(launch_counting_sort(P.cell_of, pb->n_rot, n_cells, hist, cursor, P.cell_ptr, P.cell_rot, nullptr, st),
           "sort rotations");
@@ -722,23 +712,28 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   if (n_cand > 0) emc::copy_i32_kernel<<<(unsigned)((n_cand + 255) / 256), 256, 0, st>>>(order, n_cand, P.cand_frames);
   if (n_audit > 0)
     emc::copy_i32_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(order + n_cand, n_audit, P.audit_frames);
-  HIP_TRY(launch_cand_mask(topk, k_top, P.cand_frames, n_cand, w, P.mask_cand, st), "candidate masks");
   HIP_TRY(launch_cand_mask(topk, k_top, P.audit_frames, n_audit, w, P.mask_audit, st), "audit masks");
-  // 3. per block of 256 frames: union of candidate cells -> rotation list (padded to 256)
-  HIP_TRY(launch_block_union(P.mask_cand, w, n_cand, n_blocks, P.cell_ptr, P.cell_rot, 0, len, nullptr, nullptr, st),
-          "block union sizes");
-  emc::scan_i64_kernel<<<1, 256, 0, st>>>(len, n_blocks, P.list_off);
-  HIP_TRY(launch_block_union(P.mask_cand, w, n_cand, n_blocks, P.cell_ptr, P.cell_rot, 1, nullptr, P.list_off, P.list,
-                             st),
-          "block union lists");
-  // tile table: tile offsets are list offsets / 256
-  HIP_TRY(hipGetLastError(), "proposal build");
-  int64_t n_list = 0;
-  HIP_TRY(hipMemcpyAsync(&n_list, P.list_off + n_blocks, sizeof(int64_t), hipMemcpyDeviceToHost, st), "read n_list");
+  // 3. (frame, candidate cell) pairs grouped by cell: each cell's frame list and storage
+  HIP_TRY(launch_cand_cells(topk, k_top, P.cand_frames, n_cand, n_cells, P.cand_cells, keys, st), "candidate cells");
+  HIP_TRY(launch_counting_sort(keys, n_pairs, n_cells + 1, hist, cursor, P.cf_ptr, order, nullptr, st), "sort pairs");
+  HIP_TRY(launch_pair_columns(order, n_pairs, k_top, keys, P.cf_ptr, P.cf_frame, P.pair_col, st), "pair columns");
+  HIP_TRY(launch_cell_sizes(P.cell_ptr, P.cf_ptr, n_cells, sizes, nchunk, st), "cell sizes");
+  HIP_TRY(launch_scan64(sizes, n_cells, P.g_off, st), "cell offsets");
+  HIP_TRY(launch_cell_tiles(nchunk, n_cells, (int2*)P.tiles, scal, st), "cell tiles");
+  // 4. sparse frames (non-zero pixels) of the candidate frames
+  HIP_TRY(launch_nz_count(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, nzcnt, st), "nz count");
+  HIP_TRY(launch_scan(nzcnt, n_cand, P.nz_ptr, st), "nz offsets");
+  int64_t host[3] = {0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(&host[0], scal, 8, hipMemcpyDeviceToHost, st), "read n_tiles");
+  HIP_TRY(hipMemcpyAsync(&host[1], P.g_off + n_cells, 8, hipMemcpyDeviceToHost, st), "read n_g");
+  HIP_TRY(hipMemcpyAsync(&host[2], P.nz_ptr + n_cand, 8, hipMemcpyDeviceToHost, st), "read n_nz");
   HIP_TRY(hipStreamSynchronize(st), "proposal build sync");
-  P.n_list = n_list;
-  P.n_tiles = n_list / 256;
-  HIP_TRY(launch_tile_table(P.list_off, n_blocks, (int2*)P.tiles, st), "tile table");
+  if (host[2] > nz_cap) return fail(EMC_ERR_WORKSPACE, "frames have %lld non-zero pixels, nz_cap is %lld",
+                                    (long long)host[2], (long long)nz_cap);
+  HIP_TRY(launch_nz_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.nz_ptr, P.nz, st), "nz fill");
+  P.n_tiles = host[0];
+  P.n_g = host[1];
+  P.n_nz = host[2];
   *plan = P;
   return EMC_OK;
 }
@@ -748,7 +743,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
 namespace {
 
 struct PropWs {
-  size_t slices, S, scale, c, b, L, Gc, Ga, Pa, stats_a, rho_a, recall, tj, tk, tp, tk2, tp2, order, hist, cursor, tptr,
+  size_t slices, A32, S, scale, c, b, L, G, Ga, Pa, stats_a, rho_a, recall, tj, tk, tp, tk2, tp2, hist, cursor, tptr,
       rho, num, den, count, total;
 };
 
@@ -765,12 +760,13 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P, int64_t cap) {
     return at;
   };
   W.slices = take((size_t)pb->n_rot * ps * 4);
+  W.A32 = take((size_t)pb->n_rot * ps * 4);
   W.S = take((size_t)pb->n_rot * 8);
   W.scale = take((size_t)pb->n_rot * 4);
   W.c = take((size_t)ps * 8);
   W.b = take((size_t)n_frames * 8);
   W.L = take((size_t)n_frames * 8);
-  W.Gc = take((size_t)P->n_list * 256 * 4);
+  W.G = take((size_t)P->n_g * 4);
   W.Ga = take((size_t)pb->n_rot * dsa * 4);
   W.Pa = take((size_t)pb->n_rot * dsa * 2);
   W.stats_a = take((size_t)P->n_audit * 16);
@@ -781,7 +777,6 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P, int64_t cap) {
   W.tp = take((size_t)cap * 4);
   W.tk2 = take((size_t)cap * 4);
   W.tp2 = take((size_t)cap * 4);
-  W.order = take((size_t)cap * 4);
   W.hist = take((size_t)(pb->n_rot + 1) * 4);
   W.cursor = take((size_t)(pb->n_rot + 1) * 4);
   W.tptr = take((size_t)(pb->n_rot + 2) * 8);
@@ -797,9 +792,9 @@ emc_status check_plan(const emc_problem* pb, const emc_proposal* P) {
   if (!P) return fail(EMC_ERR_INVALID_ARG, "plan is NULL");
   if (P->n_cand < 0 || P->n_audit < 0 || (int64_t)P->n_cand + P->n_audit != pb->n_data)
     return fail(EMC_ERR_INVALID_ARG, "plan frames (%d + %d) do not match n_data %d", P->n_cand, P->n_audit, pb->n_data);
-  if (P->n_blocks != (P->n_cand + 255) / 256 || P->n_list < 0 || P->n_list % 256 != 0 || P->n_tiles * 256 != P->n_list)
-    return fail(EMC_ERR_INVALID_ARG, "inconsistent plan sizes");
-  if (P->words != words_of(P->n_cells)) return fail(EMC_ERR_INVALID_ARG, "plan words do not match n_cells");
+  if (P->k_top < 1 || P->k_top > 64 || P->n_cells < 1 || P->words != words_of(P->n_cells) || P->n_g < 0 ||
+      P->n_tiles < 0 || P->n_tiles % 8 != 0)
+    return fail(EMC_ERR_INVALID_ARG, "inconsistent plan");
   return EMC_OK;
 }
 
@@ -840,12 +835,13 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   const int64_t nc = plan->n_cand, na = plan->n_audit;
   const int64_t dsa = round_up(na, 256);
   void* slices = w + W.slices;
+  float* A32 = (float*)(w + W.A32);
   double* S = (double*)(w + W.S);
   float* scale = (float*)(w + W.scale);
   double* c = (double*)(w + W.c);
   double* b = (double*)(w + W.b);
   double* L = (double*)(w + W.L);
-  float* Gc = (float*)(w + W.Gc);
+  float* G = (float*)(w + W.G);
   float* Ga = (float*)(w + W.Ga);
   void* Pa = w + W.Pa;
   double* stats_a = (double*)(w + W.stats_a);
@@ -856,7 +852,6 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   float* tp = (float*)(w + W.tp);
   int32_t* tk2 = (int32_t*)(w + W.tk2);
   float* tp2 = (float*)(w + W.tp2);
-  int32_t* order = (int32_t*)(w + W.order);
   int32_t* hist = (int32_t*)(w + W.hist);
   int32_t* cursor = (int32_t*)(w + W.cursor);
   int64_t* tptr = (int64_t*)(w + W.tptr);
@@ -864,23 +859,22 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   double* num = (double*)(w + W.num);
   double* den = (double*)(w + W.den);
   unsigned long long* count = (unsigned long long*)(w + W.count);
-  // status word: bit 0 triple overflow (the sparse M-step is then incomplete)
+  // status word: bit 0 set when the significant responsibilities overflow triple_cap
   HIP_TRY(launch_fill_i32(status, 1, 0, st), "status");
   HIP_TRY(launch_fill_i32((int32_t*)count, 2, 0, st), "count");
-  // expand (all rotations, hi + lo)
+  // expansion: BF16 hi + lo for the audit's dense contraction, FP32 A for the sparse gathers
   emc_problem pc = *pb;
   pc.n_data = (int32_t)nc;
-  CHECK(run_expand(&pc, model_in, c, slices, S, scale, st));
-  const char* hi = (const char*)slices;
-  const char* lo = hi + (size_t)pb->n_rot * ps * 2;
-  // candidate frames: gathered GEMM per block, masked log-sum-exp, significant triples
+  CHECK(run_expand(&pc, model_in, c, slices, S, scale, st, A32));
+  // candidate frames: sparse log-likelihoods per (cell, frame), E-step over each frame's candidates
   if (nc > 0) {
     HIP_TRY(launch_frame_dot(K_cand, true, ps, nc, c, b, st), "frame_dot");
-    HIP_TRY(launch_gemm_bf16_dual_gather(hi, lo, K_cand, scale, Gc, nc, ps, ps, ps, plan->list, plan->list_off,
-                                         (const int2*)plan->tiles, plan->n_tiles, st),
-            "candidate gemm");
-    HIP_TRY(launch_cand_estep(Gc, plan->list_off, plan->list, nc, plan->n_blocks, plan->mask_cand, plan->words,
-                              plan->cell_of, pb->log_w, S, b, L, tj, tk, tp, triple_cap, count, status, st),
+    HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, plan->cell_ptr, plan->cell_rot, plan->cf_ptr,
+                               plan->cf_frame, plan->g_off, plan->nz_ptr, plan->nz, A32, ps, G, st),
+            "candidate loglik");
+    HIP_TRY(launch_cand_estep(G, plan->g_off, plan->cand_cells, plan->pair_col, plan->k_top, nc, plan->cell_ptr,
+                              plan->cell_rot, plan->cf_ptr, pb->log_w, S, b, L, tj, tk, tp, triple_cap, count, status,
+                              st),
             "candidate estep");
   }
   // audited frames: full search, recall of the proposal
@@ -899,7 +893,6 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   // triple count stays on the device
   HIP_TRY(launch_triple_sort(tj, tk, tp, count, triple_cap, pb->n_rot, hist, cursor, tptr, tk2, tp2, st),
           "triple sort");
-  (void)order;
   float* Wp = (float*)slices;  // hi/lo are no longer needed
   HIP_TRY(launch_sparse_mstep(tptr, tk2, tp2, K_cand, nc, K_audit, true, ps, pb->n_rot, Wp, rho, st), "sparse mstep");
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
@@ -908,7 +901,6 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
           "scatter");
   CHECK(run_finalize(pb, num, den, model_in, model_out, L, nc + na, loglik, st));
   (void)rho_a;
-  (void)kRecallMin;
   return EMC_OK;
 }
 

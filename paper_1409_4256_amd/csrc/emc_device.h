@@ -85,7 +85,7 @@ hipError_t launch_expand(const float* model, int N, const float* q, const uint8_
 // hilo: hi plane [n_rot][stride] bf16 followed by lo plane [n_rot][stride] bf16
 hipError_t launch_expand_bf16(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
                               int n_pix, int64_t stride, int n_rot, const double* c, void* hilo, double* S,
-                              float* scale, hipStream_t st);
+                              float* scale, float* A32, hipStream_t st);
 hipError_t launch_frame_dot(const void* K, bool bf16, int64_t stride, int64_t n_data, const double* c, double* b,
                             hipStream_t st);
 // C[M][N] = sum_k A[m][k] B[n][k] (both operands contiguous along k), FP32 MFMA;
@@ -98,12 +98,6 @@ hipError_t launch_gemm_bf16_dual_nt(const void* A_hi, const void* A_lo, const vo
                                     hipStream_t st);
 hipError_t launch_gemm_bf16_nt(const void* A, const void* B, float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda,
                                int64_t ldb, int64_t ldc, hipStream_t st);
-// grouped, gathered form: tiles[w] = (block g, tile t); A rows list[off[g] + 256 t + r];
-// B rows 256 g .. 256 g + 255 (< n_frames); C compact [list row][256]
-hipError_t launch_gemm_bf16_dual_gather(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
-                                        float* C, int64_t n_frames, int64_t Kd, int64_t lda, int64_t ldb,
-                                        const int32_t* list, const int64_t* off, const int2* tiles, int64_t n_tiles,
-                                        hipStream_t st);
 hipError_t launch_lse_stats(const float* G, int64_t ld, int n_rot, int64_t n_data, const double* log_w,
                             const double* S, const double* b, double* stats, hipStream_t st);
 hipError_t launch_lse_finish(const double* stats, int64_t n_data, double* L, hipStream_t st);
@@ -150,14 +144,27 @@ hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* ptr, hipStream_t 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_cand_mask(const int32_t* topk, int k_top, const int32_t* frames, int64_t n_frames, int words,
                             uint32_t* mask, hipStream_t st);
-hipError_t launch_block_union(const uint32_t* mask, int words, int64_t n_frames, int n_blocks, const int64_t* cell_ptr,
-                              const int32_t* cell_rot, int pass, int64_t* len, const int64_t* off, int32_t* list,
+hipError_t launch_cand_cells(const int32_t* topk, int k_top, const int32_t* frames, int64_t n_frames, int n_cells,
+                             int32_t* cells, int32_t* keys, hipStream_t st);
+hipError_t launch_pair_columns(const int32_t* order, int64_t n_pairs, int k_top, const int32_t* keys,
+                               const int64_t* cf_ptr, int32_t* cf_frame, int32_t* pair_col, hipStream_t st);
+hipError_t launch_cell_sizes(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int64_t* sizes,
+                             int32_t* nchunk, hipStream_t st);
+hipError_t launch_cell_tiles(const int32_t* nchunk, int n_cells, int2* tiles, int64_t* n_tiles, hipStream_t st);
+hipError_t launch_scan64(const int64_t* cnt, int64_t n, int64_t* ptr, hipStream_t st);
+hipError_t launch_nz_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
+                           int64_t n_frames, int32_t* cnt, hipStream_t st);
+hipError_t launch_nz_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
+                          int64_t n_frames, const int64_t* ptr, uint32_t* nz, hipStream_t st);
+hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int64_t* cell_ptr, const int32_t* cell_rot,
+                              const int64_t* cf_ptr, const int32_t* cf_frame, const int64_t* g_off,
+                              const int64_t* nz_ptr, const uint32_t* nz, const float* A, int64_t ps, float* G,
                               hipStream_t st);
-hipError_t launch_tile_table(const int64_t* off, int n_blocks, int2* tiles, hipStream_t st);
-hipError_t launch_cand_estep(float* GP, const int64_t* off, const int32_t* list, int64_t n_frames, int n_blocks,
-                             const uint32_t* mask, int words, const int32_t* cell_of, const double* log_w,
-                             const double* S, const double* b, double* L, int32_t* tj, int32_t* tk, float* tp,
-                             int64_t cap, unsigned long long* count, int32_t* overflow, hipStream_t st);
+hipError_t launch_cand_estep(float* G, const int64_t* g_off, const int32_t* cells, const int32_t* pair_col, int k_top,
+                             int64_t n_frames, const int64_t* cell_ptr, const int32_t* cell_rot, const int64_t* cf_ptr,
+                             const double* log_w, const double* S, const double* b, double* L, int32_t* tj,
+                             int32_t* tk, float* tp, int64_t cap, unsigned long long* count, int32_t* overflow,
+                             hipStream_t st);
 hipError_t launch_audit(const void* P, bool bf16, int64_t ldp, int n_rot, int64_t n_audit, const uint32_t* mask_audit,
                         int words, const int32_t* cell_of, int32_t frame_base, int32_t* tj, int32_t* tk, float* tp,
                         int64_t cap, unsigned long long* count, int32_t* overflow, double* recall, hipStream_t st);

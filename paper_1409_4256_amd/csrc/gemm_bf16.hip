@@ -25,18 +25,12 @@ typedef unsigned u4 __attribute__((ext_vector_type(4)));  // 16 bytes = 8 bf16
 constexpr int TM = 256, TN = 256, TK = 64, LROW = TK + 8;  // LDS row in bf16 elements
 constexpr int GROUP = 8;
 
-// GATHER: grouped form for the learned proposal.  Workgroup w takes tile
-// tiles[w] = (g, t): A rows are list[off[g] + 256 t + r] (-1 reads zero), B rows
-// are the 256 frames of block g (rows >= N read zero), and C is the compact
-// [list row][256] buffer (ldc = 256).
-template <bool DUAL, bool GATHER, int WAVES>
+template <bool DUAL, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* __restrict__ A, const uint16_t* __restrict__ A2,
                                                         const uint16_t* __restrict__ B,
                                                         const float* __restrict__ row_scale, float* __restrict__ C,
                                                         int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb,
-                                                        int64_t ldc, const int32_t* __restrict__ list,
-                                                        const int64_t* __restrict__ off,
-                                                        const int2* __restrict__ tiles) {
+                                                        int64_t ldc) {
   constexpr int NA = DUAL ? 2 : 1;
   __shared__ __attribute__((aligned(16))) uint16_t As[NA][TM * LROW];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * LROW];
@@ -50,22 +44,14 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
 
-  int64_t m0, n0;
-  if constexpr (GATHER) {
-    const int2 tl = tiles[blockIdx.x];
-    m0 = off[tl.x] + (int64_t)TM * tl.y;
-    n0 = (int64_t)TN * tl.x;
-  } else {
-    const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
-    const int64_t pid = blockIdx.x;
-    const int64_t group = (int64_t)GROUP * tiles_n;
-    const int64_t first_m = (pid / group) * GROUP;
-    const int64_t gm = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
-    const int64_t tm = first_m + (pid % group) % gm;
-    const int64_t tn = (pid % group) / gm;
-    m0 = tm * TM;
-    n0 = tn * TN;
-  }
+  const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
+  const int64_t pid = blockIdx.x;
+  const int64_t group = (int64_t)GROUP * tiles_n;
+  const int64_t first_m = (pid / group) * GROUP;
+  const int64_t gm = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
+  const int64_t tm = first_m + (pid % group) % gm;
+  const int64_t tn = (pid % group) / gm;
+  const int64_t m0 = tm * TM, n0 = tn * TN;
   // source rows of this thread's load slots (row r = tid / 8 + (NT / 8) u), as
   // element offsets of the row starts (-1: the slot reads zero)
   constexpr int SLOTS = TM * 8 / NT;
@@ -74,10 +60,7 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
 #pragma unroll
   for (int u = 0; u < SLOTS; ++u) {
     const int r = (tid >> 3) + (NT / 8) * u;
-    if constexpr (GATHER)
-      arow[u] = list[m0 + r];
-    else
-      arow[u] = m0 + r < M ? (int32_t)(m0 + r) : -1;
+    arow[u] = m0 + r < M ? (int32_t)(m0 + r) : -1;
   }
   const uint16_t* Ab = A + 8 * ch;
   const uint16_t* A2b = A2 + 8 * ch;
@@ -149,23 +132,12 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t row = rbase + 16 * i + r;
-      float sc = 1.0f;
-      if constexpr (GATHER) {
-        const int32_t j = list[row];
-        sc = DUAL ? (j >= 0 ? row_scale[j] : 0.0f) : 1.0f;
-      } else {
-        if (row >= M) continue;
-        if (DUAL) sc = row_scale[row];
-      }
+      if (row >= M) continue;
+      const float sc = DUAL ? row_scale[row] : 1.0f;
 #pragma unroll
       for (int j = 0; j < JT; ++j) {
         const int64_t col = cbase + 16 * j;
-        if (col < N) {
-          if constexpr (GATHER)
-            C[row * TN + (col - n0)] = sc * acc[i][j][r];
-          else
-            C[row * ldc + col] = sc * acc[i][j][r];
-        }
+        if (col < N) C[row * ldc + col] = sc * acc[i][j][r];
       }
     }
   }
@@ -182,20 +154,8 @@ static hipError_t launch(const void* A, const void* A2, const void* B, const flo
                          int64_t N, int64_t Kd, int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
-  gemm_bf16_kernel<DUAL, false, kWaves><<<(unsigned)tiles, 64 * kWaves, 0, st>>>(
-      (const uint16_t*)A, (const uint16_t*)A2, (const uint16_t*)B, scale, C, M, N, Kd, lda, ldb, ldc, nullptr,
-      nullptr, nullptr);
-  return hipGetLastError();
-}
-
-hipError_t launch_gemm_bf16_dual_gather(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
-                                        float* C, int64_t n_frames, int64_t Kd, int64_t lda, int64_t ldb,
-                                        const int32_t* list, const int64_t* off, const int2* tiles, int64_t n_tiles,
-                                        hipStream_t st) {
-  if (n_tiles <= 0) return hipSuccess;
-  gemm_bf16_kernel<true, true, kWaves><<<(unsigned)n_tiles, 64 * kWaves, 0, st>>>(
-      (const uint16_t*)A_hi, (const uint16_t*)A_lo, (const uint16_t*)B, row_scale, C, 0, n_frames, Kd, lda, ldb, TN,
-      list, off, tiles);
+  gemm_bf16_kernel<DUAL, kWaves><<<(unsigned)tiles, 64 * kWaves, 0, st>>>(
+      (const uint16_t*)A, (const uint16_t*)A2, (const uint16_t*)B, scale, C, M, N, Kd, lda, ldb, ldc);
   return hipGetLastError();
 }
 

@@ -143,70 +143,143 @@ __global__ void cand_mask_kernel(const int32_t* __restrict__ topk, int k_top, co
   }
 }
 
-// one workgroup per block of 256 frames: union of the frames' candidate cells,
-// listed in ascending cell order and expanded to rotations; the list is padded to
-// a multiple of 256 with -1.  Pass 0 writes the padded length, pass 1 the list.
-__global__ __launch_bounds__(256) void block_union_kernel(const uint32_t* __restrict__ mask, int words,
-                                                          int64_t n_frames, const int64_t* __restrict__ cell_ptr,
-                                                          const int32_t* __restrict__ cell_rot, int pass,
-                                                          int64_t* __restrict__ len, const int64_t* __restrict__ off,
-                                                          int32_t* __restrict__ list) {
-  __shared__ uint32_t u[256];   // up to 8192 cells
-  __shared__ int64_t wsum[256];  // rotations per mask word, then exclusive prefix
-  const int g = blockIdx.x;
-  for (int w = threadIdx.x; w < words; w += 256) u[w] = 0u;
-  __syncthreads();
-  const int64_t f0 = (int64_t)g * 256;
-  for (int w = threadIdx.x; w < words; w += 256) {
-    uint32_t acc = 0u;
-    for (int64_t f = f0; f < f0 + 256 && f < n_frames; ++f) acc |= mask[f * words + w];
-    u[w] = acc;
-  }
-  __syncthreads();
-  for (int w = threadIdx.x; w < words; w += 256) {
-    int64_t s = 0;
-    uint32_t b = u[w];
-    while (b) {
-      const int c = (w << 5) + __builtin_ctz(b);
-      b &= b - 1;
-      s += cell_ptr[c + 1] - cell_ptr[c];
-    }
-    wsum[w] = s;
-  }
-  __syncthreads();
-  __shared__ int64_t used_len;
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int w = 0; w < words; ++w) {
-      const int64_t v = wsum[w];
-      wsum[w] = run;
-      run += v;
-    }
-    used_len = run;
-    if (pass == 0) len[g] = (run + 255) / 256 * 256;
-  }
-  __syncthreads();
-  if (pass == 0) return;
-  int32_t* out = list + off[g];
-  const int64_t padded = off[g + 1] - off[g];
-  for (int w = threadIdx.x; w < words; w += 256) {
-    int64_t at = wsum[w];
-    uint32_t b = u[w];
-    while (b) {
-      const int c = (w << 5) + __builtin_ctz(b);
-      b &= b - 1;
-      for (int64_t t = cell_ptr[c]; t < cell_ptr[c + 1]; ++t) out[at++] = cell_rot[t];
-    }
-  }
-  for (int64_t e = used_len + threadIdx.x; e < padded; e += 256) out[e] = -1;
+// candidate cells of the listed frames: cells[f][t] = topk[frames[f]][t] (-1 stays -1)
+__global__ void cand_cells_kernel(const int32_t* __restrict__ topk, int k_top, const int32_t* __restrict__ frames,
+                                  int64_t n_frames, int n_cells, int32_t* __restrict__ cells,
+                                  int32_t* __restrict__ keys) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_frames * k_top) return;
+  const int64_t f = e / k_top;
+  const int t = (int)(e - f * k_top);
+  int32_t c = topk[(int64_t)frames[f] * k_top + t];
+  if (c < 0 || c >= n_cells) c = -1;
+  cells[e] = c;
+  keys[e] = c < 0 ? n_cells : c;  // invalid picks sort after every cell
 }
 
-// tile table: for block g, tiles t = 0 .. len/256 - 1 -> (g, t), stored from off[g] / 256
-__global__ void tile_table_kernel(const int64_t* __restrict__ off, int n_blocks, int2* __restrict__ tiles) {
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  if (g >= n_blocks) return;
-  const int64_t nt = (off[g + 1] - off[g]) / 256, base = off[g] / 256;
-  for (int64_t t = 0; t < nt; ++t) tiles[base + t] = make_int2(g, (int)t);
+// pairs sorted by cell (order = pair indices): frame of each pair in cell order and
+// the column of each pair inside its cell's frame list
+__global__ void pair_columns_kernel(const int32_t* __restrict__ order, int64_t n_pairs, int k_top,
+                                    const int32_t* __restrict__ keys, const int64_t* __restrict__ cf_ptr,
+                                    int32_t* __restrict__ cf_frame, int32_t* __restrict__ pair_col) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_pairs) return;
+  const int32_t pr = order[e];
+  cf_frame[e] = pr / k_top;
+  pair_col[pr] = (int32_t)(e - cf_ptr[keys[pr]]);
+}
+
+// storage of each cell's block G_c [rotations of c][frames of c]: sizes
+__global__ void cell_sizes_kernel(const int64_t* __restrict__ cell_ptr, const int64_t* __restrict__ cf_ptr,
+                                  int n_cells, int64_t* __restrict__ sizes, int32_t* __restrict__ nchunk, int chunk) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= n_cells) return;
+  const int64_t R = cell_ptr[c + 1] - cell_ptr[c], F = cf_ptr[c + 1] - cf_ptr[c];
+  sizes[c] = R * F;
+  nchunk[c] = R > 0 ? (int32_t)((F + chunk - 1) / chunk) : 0;
+}
+
+// tile table of the candidate log-likelihood: tiles of one cell are dealt to one
+// XCD (dispatch order is round-robin over the 8 XCDs) so that the cell's slices stay
+// in that XCD's L2; slot 8 q + x holds the q-th tile of XCD x, (-1, 0) pads.
+__global__ void cell_tiles_kernel(const int32_t* __restrict__ nchunk, int n_cells, int2* __restrict__ tiles,
+                                  int64_t* __restrict__ n_tiles_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t len[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int c = 0; c < n_cells; ++c) len[c & 7] += nchunk[c];
+  int64_t q_max = 0;
+  for (int x = 0; x < 8; ++x) q_max = len[x] > q_max ? len[x] : q_max;
+  for (int x = 0; x < 8; ++x) {
+    int64_t q = 0;
+    for (int c = x; c < n_cells; c += 8)
+      for (int t = 0; t < nchunk[c]; ++t) tiles[8 * (q++) + x] = make_int2(c, t);
+    for (; q < q_max; ++q) tiles[8 * q + x] = make_int2(-1, 0);
+  }
+  *n_tiles_out = 8 * q_max;
+}
+
+// frame CSR of the listed frames: non-zero photon counts of unmasked pixels as
+// (pixel << 16) | count, pixels ascending
+__global__ __launch_bounds__(256) void nz_count_kernel(const uint16_t* __restrict__ counts,
+                                                       const uint8_t* __restrict__ mask, int n_pix,
+                                                       const int32_t* __restrict__ frames, int64_t n_frames,
+                                                       int32_t* __restrict__ cnt) {
+  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (f >= n_frames) return;
+  const uint16_t* row = counts + (int64_t)frames[f] * n_pix;
+  int n = 0;
+  for (int i = lane; i < n_pix; i += 64) n += (mask[i] && row[i] != 0);
+  n = wave_sum(n);
+  if (lane == 0) cnt[f] = n;
+}
+
+__global__ __launch_bounds__(256) void nz_fill_kernel(const uint16_t* __restrict__ counts,
+                                                      const uint8_t* __restrict__ mask, int n_pix,
+                                                      const int32_t* __restrict__ frames, int64_t n_frames,
+                                                      const int64_t* __restrict__ ptr, uint32_t* __restrict__ nz) {
+  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (f >= n_frames) return;
+  const uint16_t* row = counts + (int64_t)frames[f] * n_pix;
+  int64_t at = ptr[f];
+  for (int i0 = 0; i0 < n_pix; i0 += 64) {
+    const int i = i0 + lane;
+    const uint32_t v = i < n_pix && mask[i] ? row[i] : 0u;
+    const bool hit = v != 0u;
+    const unsigned long long bal = __ballot(hit);
+    if (hit) nz[at + __popcll(bal & ((1ull << lane) - 1ull))] = ((uint32_t)i << 16) | v;
+    at += __popcll(bal);
+  }
+}
+
+// ------------------------------------------------------------------ candidate log-likelihood
+// G_c[r][p] = sum over the non-zero pixels i of frame cf_frame[c][p] of K_i A_{rot(c, r), i}
+// (A: FP32 centred log slices).  Workgroup = one tile (cell c, chunk of kChunk frames);
+// each wave takes frames of the chunk, lanes stride over a frame's non-zero pixels and
+// accumulate all the cell's rotations (up to kRot per pass).
+constexpr int kChunk = 32, kRot = 32;
+__global__ __launch_bounds__(256) void cand_loglik_kernel(const int2* __restrict__ tiles,
+                                                          const int64_t* __restrict__ cell_ptr,
+                                                          const int32_t* __restrict__ cell_rot,
+                                                          const int64_t* __restrict__ cf_ptr,
+                                                          const int32_t* __restrict__ cf_frame,
+                                                          const int64_t* __restrict__ g_off,
+                                                          const int64_t* __restrict__ nz_ptr,
+                                                          const uint32_t* __restrict__ nz,
+                                                          const float* __restrict__ A, int64_t ps,
+                                                          float* __restrict__ G) {
+  const int2 tl = tiles[blockIdx.x];
+  const int c = tl.x;
+  if (c < 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t R = cell_ptr[c + 1] - cell_ptr[c];
+  const int64_t F = cf_ptr[c + 1] - cf_ptr[c];
+  const int32_t* rots = cell_rot + cell_ptr[c];
+  float* Gc = G + g_off[c];
+  for (int64_t p = (int64_t)tl.y * kChunk + wave; p < F && p < (int64_t)(tl.y + 1) * kChunk; p += 4) {
+    const int64_t f = cf_frame[cf_ptr[c] + p];
+    const int64_t a = nz_ptr[f], z = nz_ptr[f + 1];
+    for (int64_t r0 = 0; r0 < R; r0 += kRot) {
+      const int nr = (int)(R - r0 < kRot ? R - r0 : kRot);
+      float acc[kRot];
+#pragma unroll
+      for (int r = 0; r < kRot; ++r) acc[r] = 0.0f;
+      for (int64_t e = a + lane; e < z; e += 64) {
+        const uint32_t w = nz[e];
+        const int64_t i = w >> 16;
+        const float v = (float)(w & 0xffffu);
+#pragma unroll
+        for (int r = 0; r < kRot; ++r)
+          if (r < nr) acc[r] += v * A[(int64_t)rots[r0 + r] * ps + i];
+      }
+#pragma unroll
+      for (int r = 0; r < kRot; ++r) {
+        const float t = wave_sum(acc[r]);
+        if (lane == r && r < nr) Gc[(r0 + r) * F + p] = t;
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------------ candidate E-step
@@ -219,79 +292,65 @@ __device__ __forceinline__ void lse_merge2(double& m, double& s, double m2, doub
   }
 }
 
-// Workgroup = 64 frames (lanes) of one block x 4 waves splitting the block's
-// rotation list.  Log-sum-exp over the list restricted to each frame's candidate
-// cells, then P written in place of G (0 outside the candidates) and the triples
-// with P >= kKeep appended (rotation, frame, P).  Overflow of the triple buffer
-// sets *overflow.
-__global__ __launch_bounds__(256) void cand_estep_kernel(float* __restrict__ GP, const int64_t* __restrict__ off,
-                                                         const int32_t* __restrict__ list, int64_t n_frames,
-                                                         const uint32_t* __restrict__ mask, int words,
-                                                         const int32_t* __restrict__ cell_of,
+// One wave per frame; lane t takes the frame's t-th candidate cell (k_top <= 64).
+// Log-sum-exp over the candidates, P written in place of G, triples with P >= kKeep.
+__global__ __launch_bounds__(256) void cand_estep_kernel(float* __restrict__ G, const int64_t* __restrict__ g_off,
+                                                         const int32_t* __restrict__ cells,
+                                                         const int32_t* __restrict__ pair_col, int k_top,
+                                                         int64_t n_frames, const int64_t* __restrict__ cell_ptr,
+                                                         const int32_t* __restrict__ cell_rot,
+                                                         const int64_t* __restrict__ cf_ptr,
                                                          const double* __restrict__ log_w,
                                                          const double* __restrict__ S, const double* __restrict__ b,
                                                          double* __restrict__ L, int32_t* __restrict__ tj,
                                                          int32_t* __restrict__ tk, float* __restrict__ tp,
                                                          int64_t cap, unsigned long long* __restrict__ count,
                                                          int32_t* __restrict__ overflow) {
-  __shared__ double sm[4][64], ss[4][64];
-  const int g = blockIdx.x >> 2, quarter = blockIdx.x & 3;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = quarter * 64 + lane;             // frame within the block
-  const int64_t f = (int64_t)g * 256 + col;
-  const bool live = f < n_frames;
-  const int64_t r0 = off[g], r1 = off[g + 1];
-  float* Gb = GP + r0 * 256;
-  const uint32_t* m = mask + (live ? f : 0) * words;
-  const double bk = live ? b[f] : 0.0;
+  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (f >= n_frames) return;  // uniform per wave
+  const int c = lane < k_top ? cells[f * k_top + lane] : -1;
+  const int64_t col = c >= 0 ? pair_col[f * k_top + lane] : 0;
+  const int64_t R = c >= 0 ? cell_ptr[c + 1] - cell_ptr[c] : 0;
+  const int64_t F = c >= 0 ? cf_ptr[c + 1] - cf_ptr[c] : 0;
+  const int32_t* rots = c >= 0 ? cell_rot + cell_ptr[c] : cell_rot;
+  float* Gc = c >= 0 ? G + g_off[c] + col : G;
+  const double bk = b[f];
   double mx = -INFINITY, s = 0.0;
-  if (live) {
-    for (int64_t r = r0 + wave; r < r1; r += 4) {
-      const int j = list[r];
-      if (j < 0) continue;
-      const int c = cell_of[j];
-      if (!((m[c >> 5] >> (c & 31)) & 1u)) continue;
-      const double a = ((double)Gb[(r - r0) * 256 + col] + bk) + (log_w[j] - S[j]);
-      if (!(a > -INFINITY)) continue;
-      if (a > mx) {
-        s = s * exp(mx - a) + 1.0;
-        mx = a;
-      } else {
-        s += exp(a - mx);
-      }
+  for (int64_t r = 0; r < R; ++r) {
+    const int j = rots[r];
+    const double a = ((double)Gc[r * F] + bk) + (log_w[j] - S[j]);
+    if (!(a > -INFINITY)) continue;
+    if (a > mx) {
+      s = s * exp(mx - a) + 1.0;
+      mx = a;
+    } else {
+      s += exp(a - mx);
     }
   }
-  sm[wave][lane] = mx;
-  ss[wave][lane] = s;
-  __syncthreads();
-  // every wave merges the four partial statistics in the same order
-  mx = sm[0][lane];
-  s = ss[0][lane];
-  for (int w = 1; w < 4; ++w) lse_merge2(mx, s, sm[w][lane], ss[w][lane]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double m2 = __shfl_xor(mx, o, 64), s2 = __shfl_xor(s, o, 64);
+    lse_merge2(mx, s, m2, s2);
+  }
   const double lse = mx + log(s);
-  if (live && wave == 0) L[f] = lse;
-  for (int64_t r = r0 + wave; r < r1; r += 4) {
-    const int j = list[r];
-    float p = 0.0f;
-    if (live && j >= 0) {
-      const int c = cell_of[j];
-      if ((m[c >> 5] >> (c & 31)) & 1u) {
-        const double a = ((double)Gb[(r - r0) * 256 + col] + bk) + (log_w[j] - S[j]);
-        const double pd = exp(a - lse);
-        p = (float)pd;
-        if (pd >= kKeep) {
-          const unsigned long long at = atomicAdd(count, 1ull);
-          if ((int64_t)at < cap) {
-            tj[at] = j;
-            tk[at] = (int32_t)f;
-            tp[at] = p;
-          } else {
-            *overflow = 1;
-          }
-        }
+  if (lane == 0) L[f] = lse;
+  for (int64_t r = 0; r < R; ++r) {
+    const int j = rots[r];
+    const double a = ((double)Gc[r * F] + bk) + (log_w[j] - S[j]);
+    const double pd = exp(a - lse);
+    const float p = (float)pd;
+    Gc[r * F] = p;
+    if (pd >= kKeep) {
+      const unsigned long long at = atomicAdd(count, 1ull);
+      if ((int64_t)at < cap) {
+        tj[at] = j;
+        tk[at] = (int32_t)f;
+        tp[at] = p;
+      } else {
+        *overflow = 1;
       }
     }
-    Gb[(r - r0) * 256 + col] = p;
   }
 }
 
@@ -441,6 +500,37 @@ hipError_t launch_segment_sort(const int64_t* ptr, int n_seg, int32_t* vals, flo
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void exclusive_scan64_kernel(const int64_t* __restrict__ cnt, int64_t n,
+                                                               int64_t* __restrict__ ptr) {
+  __shared__ int64_t part[256];
+  const int64_t per = (n + 255) / 256;
+  const int64_t a = threadIdx.x * per, z = a + per < n ? a + per : n;
+  int64_t s = 0;
+  for (int64_t e = a; e < z; ++e) s += cnt[e];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int t = 0; t < 256; ++t) {
+      const int64_t v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int64_t run = part[threadIdx.x];
+  for (int64_t e = a; e < z; ++e) {
+    ptr[e] = run;
+    run += cnt[e];
+  }
+  if (threadIdx.x == 255) ptr[n] = run;
+}
+
+hipError_t launch_scan64(const int64_t* cnt, int64_t n, int64_t* ptr, hipStream_t st) {
+  exclusive_scan64_kernel<<<1, 256, 0, st>>>(cnt, n, ptr);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* ptr, hipStream_t st) {
   exclusive_scan_kernel<<<1, 256, 0, st>>>(cnt, n, ptr);
   return hipGetLastError();
@@ -453,27 +543,67 @@ hipError_t launch_cand_mask(const int32_t* topk, int k_top, const int32_t* frame
   return hipGetLastError();
 }
 
-hipError_t launch_block_union(const uint32_t* mask, int words, int64_t n_frames, int n_blocks, const int64_t* cell_ptr,
-                              const int32_t* cell_rot, int pass, int64_t* len, const int64_t* off, int32_t* list,
+hipError_t launch_cand_cells(const int32_t* topk, int k_top, const int32_t* frames, int64_t n_frames, int n_cells,
+                             int32_t* cells, int32_t* keys, hipStream_t st) {
+  const int64_t n = n_frames * k_top;
+  if (n > 0) cand_cells_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(topk, k_top, frames, n_frames, n_cells,
+                                                                             cells, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_columns(const int32_t* order, int64_t n_pairs, int k_top, const int32_t* keys,
+                               const int64_t* cf_ptr, int32_t* cf_frame, int32_t* pair_col, hipStream_t st) {
+  if (n_pairs > 0)
+    pair_columns_kernel<<<(unsigned)((n_pairs + 255) / 256), 256, 0, st>>>(order, n_pairs, k_top, keys, cf_ptr,
+                                                                           cf_frame, pair_col);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_sizes(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int64_t* sizes,
+                             int32_t* nchunk, hipStream_t st) {
+  cell_sizes_kernel<<<(unsigned)((n_cells + 255) / 256), 256, 0, st>>>(cell_ptr, cf_ptr, n_cells, sizes, nchunk,
+                                                                       kChunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_tiles(const int32_t* nchunk, int n_cells, int2* tiles, int64_t* n_tiles, hipStream_t st) {
+  cell_tiles_kernel<<<1, 64, 0, st>>>(nchunk, n_cells, tiles, n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_nz_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
+                           int64_t n_frames, int32_t* cnt, hipStream_t st) {
+  if (n_frames > 0)
+    nz_count_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_nz_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
+                          int64_t n_frames, const int64_t* ptr, uint32_t* nz, hipStream_t st) {
+  if (n_frames > 0)
+    nz_fill_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, ptr, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int64_t* cell_ptr, const int32_t* cell_rot,
+                              const int64_t* cf_ptr, const int32_t* cf_frame, const int64_t* g_off,
+                              const int64_t* nz_ptr, const uint32_t* nz, const float* A, int64_t ps, float* G,
                               hipStream_t st) {
-  if (n_blocks > 0)
-    block_union_kernel<<<(unsigned)n_blocks, 256, 0, st>>>(mask, words, n_frames, cell_ptr, cell_rot, pass, len, off,
-                                                           list);
+  if (n_tiles > 0)
+    cand_loglik_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, cell_ptr, cell_rot, cf_ptr, cf_frame, g_off, nz_ptr,
+                                                          nz, A, ps, G);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_table(const int64_t* off, int n_blocks, int2* tiles, hipStream_t st) {
-  if (n_blocks > 0) tile_table_kernel<<<(unsigned)((n_blocks + 255) / 256), 256, 0, st>>>(off, n_blocks, tiles);
-  return hipGetLastError();
-}
-
-hipError_t launch_cand_estep(float* GP, const int64_t* off, const int32_t* list, int64_t n_frames, int n_blocks,
-                             const uint32_t* mask, int words, const int32_t* cell_of, const double* log_w,
-                             const double* S, const double* b, double* L, int32_t* tj, int32_t* tk, float* tp,
-                             int64_t cap, unsigned long long* count, int32_t* overflow, hipStream_t st) {
-  if (n_blocks > 0)
-    cand_estep_kernel<<<(unsigned)n_blocks * 4, 256, 0, st>>>(GP, off, list, n_frames, mask, words, cell_of, log_w, S,
-                                                              b, L, tj, tk, tp, cap, count, overflow);
+hipError_t launch_cand_estep(float* G, const int64_t* g_off, const int32_t* cells, const int32_t* pair_col, int k_top,
+                             int64_t n_frames, const int64_t* cell_ptr, const int32_t* cell_rot, const int64_t* cf_ptr,
+                             const double* log_w, const double* S, const double* b, double* L, int32_t* tj,
+                             int32_t* tk, float* tp, int64_t cap, unsigned long long* count, int32_t* overflow,
+                             hipStream_t st) {
+  if (n_frames > 0)
+    cand_estep_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(G, g_off, cells, pair_col, k_top, n_frames,
+                                                                      cell_ptr, cell_rot, cf_ptr, log_w, S, b, L, tj,
+                                                                      tk, tp, cap, count, overflow);
   return hipGetLastError();
 }
 

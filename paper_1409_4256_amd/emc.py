@@ -61,12 +61,13 @@ class Problem(ctypes.Structure):
 class Proposal(ctypes.Structure):
     _fields_ = [
         ("n_cells", ctypes.c_int32), ("k_top", ctypes.c_int32), ("n_cand", ctypes.c_int32),
-        ("n_audit", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("words", ctypes.c_int32),
-        ("n_list", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
+        ("n_audit", ctypes.c_int32), ("words", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_tiles", ctypes.c_int64), ("n_g", ctypes.c_int64), ("n_nz", ctypes.c_int64),
         ("cell_of", ctypes.c_void_p), ("cell_ptr", ctypes.c_void_p), ("cell_rot", ctypes.c_void_p),
-        ("cand_frames", ctypes.c_void_p), ("audit_frames", ctypes.c_void_p), ("mask_cand", ctypes.c_void_p),
-        ("mask_audit", ctypes.c_void_p), ("list_off", ctypes.c_void_p), ("list", ctypes.c_void_p),
-        ("tiles", ctypes.c_void_p),
+        ("cand_frames", ctypes.c_void_p), ("audit_frames", ctypes.c_void_p), ("cand_cells", ctypes.c_void_p),
+        ("pair_col", ctypes.c_void_p), ("cf_ptr", ctypes.c_void_p), ("cf_frame", ctypes.c_void_p),
+        ("g_off", ctypes.c_void_p), ("tiles", ctypes.c_void_p), ("mask_audit", ctypes.c_void_p),
+        ("nz_ptr", ctypes.c_void_p), ("nz", ctypes.c_void_p),
     ]
 
 
@@ -114,8 +115,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_cell_targets.argtypes, lib.emc_cell_targets.restype = [_PB, _P, _P, _P, i32, _P, _P], st
     _PP = ctypes.POINTER(Proposal)
     lib.emc_pack_frames_list.argtypes, lib.emc_pack_frames_list.restype = [_PB, _P, _P, _P, _P], st
-    lib.emc_proposal_bytes.argtypes, lib.emc_proposal_bytes.restype = [_PB, i32, i32, szp], st
-    lib.emc_proposal_build.argtypes = [_PB, _P, i32, _P, i32, _P, i32, _P, ctypes.c_size_t, _PP, _P]
+    lib.emc_proposal_bytes.argtypes, lib.emc_proposal_bytes.restype = [_PB, i32, i32, i32, i64, szp], st
+    lib.emc_proposal_build.argtypes = [_PB, _P, i32, _P, i32, _P, i32, _P, i64, _P, ctypes.c_size_t, _PP, _P]
     lib.emc_proposal_build.restype = st
     lib.emc_proposed_workspace_bytes.argtypes = [_PB, _PP, i64, szp]
     lib.emc_proposed_workspace_bytes.restype = st
@@ -438,13 +439,15 @@ def emc_pack_frames_list(geo: Geometry, counts, frames, K_packed, stream=None):
                                        _stream(stream)))
 
 
-def emc_proposal_bytes(geo: Geometry, n_cells: int, n_audit: int) -> int:
+def emc_proposal_bytes(geo: Geometry, n_cells: int, k_top: int, n_audit: int, nz_cap: int) -> int:
     n = ctypes.c_size_t(0)
-    _check(load().emc_proposal_bytes(ctypes.byref(geo.pb), int(n_cells), int(n_audit), ctypes.byref(n)))
+    _check(load().emc_proposal_bytes(ctypes.byref(geo.pb), int(n_cells), int(k_top), int(n_audit), int(nz_cap),
+                                     ctypes.byref(n)))
     return int(n.value)
 
 
-def emc_proposal_build(geo: Geometry, coarse, n_cells, topk, k_top, audit, buf, stream=None) -> Proposal:
+def emc_proposal_build(geo: Geometry, coarse, n_cells, topk, k_top, audit, counts, nz_cap, buf,
+                       stream=None) -> Proposal:
     import torch
 
     plan = Proposal()
@@ -453,8 +456,9 @@ def emc_proposal_build(geo: Geometry, coarse, n_cells, topk, k_top, audit, buf, 
         ctypes.byref(geo.pb), _ptr(coarse, torch.float32, 4 * n_cells, "coarse"), int(n_cells),
         _ptr(topk, torch.int32, geo.n_data * k_top, "topk"), int(k_top),
         _ptr(audit, torch.int32, n_audit, "audit") if n_audit else None, n_audit,
-        _ptr(buf, torch.uint8, emc_proposal_bytes(geo, n_cells, n_audit), "buf"), ctypes.c_size_t(buf.numel()),
-        ctypes.byref(plan), _stream(stream)))
+        _ptr(counts, torch.uint16, geo.n_data * geo.n_pix, "counts"), int(nz_cap),
+        _ptr(buf, torch.uint8, emc_proposal_bytes(geo, n_cells, k_top, n_audit, nz_cap), "buf"),
+        ctypes.c_size_t(buf.numel()), ctypes.byref(plan), _stream(stream)))
     return plan
 
 

@@ -39,11 +39,12 @@ class CellIndex:
     """Fine rotations grouped by coarse cell (CSR), computed by the library's plan kernels."""
 
     def __init__(self, geo: E.Geometry, coarse: torch.Tensor, n_cells: int):
-        # a plan over a single dummy frame gives the rotation grouping
+        # a plan over a single empty frame gives the rotation grouping
         one = geo.with_frames(1)
         topk = torch.zeros(1, dtype=torch.int32, device="cuda")
-        self.buf = torch.empty(E.emc_proposal_bytes(one, n_cells, 0), dtype=torch.uint8, device="cuda")
-        plan = E.emc_proposal_build(one, coarse, n_cells, topk, 1, None, self.buf)
+        counts = torch.zeros(geo.n_pix, dtype=torch.uint16, device="cuda")
+        self.buf = torch.empty(E.emc_proposal_bytes(one, n_cells, 1, 0, 1), dtype=torch.uint8, device="cuda")
+        plan = E.emc_proposal_build(one, coarse, n_cells, topk, 1, None, counts, 1, self.buf)
         self.cell_of = E.plan_array(self.buf, plan.cell_of, geo.n_rot, torch.int32).clone()
         ptr64 = E.plan_array(self.buf, plan.cell_ptr, n_cells + 1, torch.int64)
         self.cell_ptr = ptr64.to(torch.int32).clone()
@@ -128,10 +129,15 @@ class Network:
 class ProposedIteration:
     """Plan + packed frame lists + workspace for emc_iterate_proposed."""
 
-    def __init__(self, geo16: E.Geometry, counts_dev, coarse, n_cells, topk, k_top, audit, triple_cap):
+    def __init__(self, geo16: E.Geometry, counts_dev, coarse, n_cells, topk, k_top, audit, triple_cap, nz_cap=None):
         self.geo = geo16
-        self.buf = torch.empty(E.emc_proposal_bytes(geo16, n_cells, audit.numel()), dtype=torch.uint8, device="cuda")
-        self.plan = E.emc_proposal_build(geo16, coarse, n_cells, topk, k_top, audit, self.buf)
+        if nz_cap is None:  # non-zero pixels of all frames (an upper bound of the candidate frames')
+            nz_cap = int((counts_dev.view(torch.int16) != 0).sum().item())
+        n_audit = 0 if audit is None else audit.numel()
+        self.buf = torch.empty(E.emc_proposal_bytes(geo16, n_cells, k_top, n_audit, max(1, nz_cap)),
+                               dtype=torch.uint8, device="cuda")
+        self.plan = E.emc_proposal_build(geo16, coarse, n_cells, topk, k_top, audit, counts_dev, max(1, nz_cap),
+                                         self.buf)
         p = self.plan
         self.cand_frames = E.plan_array(self.buf, p.cand_frames, p.n_cand, torch.int32)
         self.audit_frames = E.plan_array(self.buf, p.audit_frames, p.n_audit, torch.int32)

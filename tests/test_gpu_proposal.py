@@ -30,12 +30,13 @@ def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=30
     dev = "cuda"
     topk = torch.empty(ndata * k_top, dtype=torch.int32, device=dev)
     E.emc_cnn_topk(torch.as_tensor(logits, device=dev), ndata, n_cells, k_top, topk)
-    buf = torch.empty(E.emc_proposal_bytes(geo, n_cells, n_audit), dtype=torch.uint8, device=dev)
+    counts = upload_counts(t["counts"])
+    nz_cap = int((t["counts"] != 0).sum()) + 1
+    buf = torch.empty(E.emc_proposal_bytes(geo, n_cells, k_top, n_audit, nz_cap), dtype=torch.uint8, device=dev)
     plan = E.emc_proposal_build(geo, torch.as_tensor(coarse, device=dev), n_cells, topk, k_top,
-                                torch.as_tensor(audit, device=dev) if n_audit else None, buf)
+                                torch.as_tensor(audit, device=dev) if n_audit else None, counts, nz_cap, buf)
     cand_frames = E.plan_array(buf, plan.cand_frames, plan.n_cand, torch.int32)
     audit_frames = E.plan_array(buf, plan.audit_frames, plan.n_audit, torch.int32)
-    counts = upload_counts(t["counts"])
     gc, ga = geo.with_frames(plan.n_cand), geo.with_frames(plan.n_audit)
     Kc, Ka = E.frames_tensor(gc), E.frames_tensor(ga)
     if plan.n_cand:
