@@ -235,7 +235,8 @@ def proposal_form(inp, args, counts_dev):
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     del x
-    log(f"proposal: plan with {prop.plan.n_tiles} gathered tiles ({prop.plan.n_list} list rows) in {t_plan:.1f} s")
+    log(f"proposal: plan with {prop.plan.n_g} candidate (rotation, frame) pairs in {prop.plan.n_tiles} tiles, "
+        f"built in {t_plan:.1f} s")
     # iterations 4-5, timed with the audit verdict and any fallback included
     per, recs, fallbacks = [], [], 0
     for it in range(max(2, args.steps)):
@@ -261,8 +262,7 @@ def proposal_form(inp, args, counts_dev):
             "one_off_s": {"full_iterations": round(t_full3, 2), "training": round(tlog.seconds, 2),
                           "plan": round(t_plan, 2)},
             "training": {"steps": tlog.steps, "loss_first": tlog.loss_first, "loss_last": tlog.loss_last},
-            "gathered_tiles": int(prop.plan.n_tiles), "dense_tiles_equivalent": int(
-                ((wl.n_rot + 255) // 256) * ((wl.n_data + 255) // 256))}
+            "candidate_pairs": int(prop.plan.n_g), "dense_pairs": int(wl.n_rot) * int(wl.n_data)}
 
 
 def main():
