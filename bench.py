@@ -191,9 +191,11 @@ def time_form(run, args, n_valid):
 def proposal_form(inp, args, counts_dev):
     """Learned-proposal form: full BF16 iterations run until EMC's posteriors have
     concentrated (iteration `args.train_at`), the last three give cell targets, the
-    network is trained on them, and the following iterations search each frame's
-    proposed rotations only (2 % of frames audited in full; an iteration whose
-    audit recall is below 0.98 is redone with the full search, and its time counts)."""
+    network is trained on them, and the following iterations search, for each frame,
+    the network's top-64 cells together with the 64 cells that held most of the
+    frame's responsibility in the last full iteration (2 % of frames audited in full;
+    an iteration whose audit recall is below 0.98 is redone with the full search, its
+    time counts, and the plan is rebuilt from that full iteration)."""
     import numpy as np
     import torch
 
@@ -202,42 +204,57 @@ def proposal_form(inp, args, counts_dev):
     from paper_1409_4256_amd import emc, learned
 
     wl = inp.wl
-    n_cells, k_top = 2000, 64
+    n_cells, k_net, k_prev = 2000, 64, 64
     run = Run(inp, emc.EMC_PREC_BF16, counts_dev)
     g = run.geo
     coarse = torch.as_tensor(shoemake_quaternions(seeded(wl.cfg, "coarse"), n_cells), dtype=torch.float32,
                              device="cuda")
     cells = learned.CellIndex(g, coarse, n_cells)
+
+    def targets_now():
+        T = torch.empty(wl.n_data * n_cells, dtype=torch.float32, device="cuda")
+        emc.emc_cell_targets(g, run.P, cells.cell_ptr, cells.cell_rot, n_cells, T)
+        return T
+
     t0 = time.perf_counter()
     targets = []
     for it in range(args.train_at):
         run.step()
         if it >= args.train_at - 3:
-            T = torch.empty(wl.n_data * n_cells, dtype=torch.float32, device="cuda")
-            emc.emc_cell_targets(g, run.P, cells.cell_ptr, cells.cell_rot, n_cells, T)
-            targets.append(T)
+            targets.append(targets_now())
         torch.cuda.synchronize()
         log(f"proposal: full iteration {it + 1}/{args.train_at}, loglik {run.loglik.item():.4f}")
-    t_full3 = time.perf_counter() - t0
+    t_full = time.perf_counter() - t0
     bins = torch.as_tensor(proposal_bins(wl.det_n, inp.mask), device="cuda")
     net = learned.Network(n_cells, learned.init_params(seeded(wl.cfg, "cnn"), n_cells))
     x = net.images(g, run.K, bins)
     tlog = net.train(x, targets, wl.n_data, epochs=2, lr=1e-3, rng=seeded(wl.cfg, "cnn"))
     log(f"proposal: trained {tlog.steps} steps in {tlog.seconds:.1f} s, loss {tlog.loss_first:.3f} -> "
         f"{tlog.loss_last:.3f}")
+    T_last = targets[-1]
     del targets
-    t0 = time.perf_counter()
-    topk = net.topk(x, wl.n_data, k_top)
     n_audit = max(1, int(round(0.02 * wl.n_data)))
     audit = torch.as_tensor(np.sort(seeded(wl.cfg, "audit").choice(wl.n_data, n_audit, replace=False)),
                             dtype=torch.int32, device="cuda")
-    prop = learned.ProposedIteration(g, counts_dev, coarse, n_cells, topk, k_top, audit, 200 * wl.n_data)
+    top_net = net.topk(x, wl.n_data, k_net)
+    del x
+
+    def build(T):
+        top_prev = torch.empty(wl.n_data * k_prev, dtype=torch.int32, device="cuda")
+        emc.emc_cell_topk(T, wl.n_data, n_cells, k_prev, top_prev)
+        cand = torch.empty(wl.n_data * (k_net + k_prev), dtype=torch.int32, device="cuda")
+        emc.emc_topk_union(top_net, k_net, top_prev, k_prev, wl.n_data, n_cells, cand)
+        return learned.ProposedIteration(g, counts_dev, coarse, n_cells, cand, k_net + k_prev, audit)
+
+    t0 = time.perf_counter()
+    prop = build(T_last)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
-    del x
-    log(f"proposal: plan with {prop.plan.n_g} candidate (rotation, frame) pairs in {prop.plan.n_tiles} tiles, "
-        f"built in {t_plan:.1f} s")
-    # iterations 4-5, timed with the audit verdict and any fallback included
+    n_pairs = prop.candidate_pairs()
+    log(f"proposal: plan with {n_pairs} candidate (rotation, frame) pairs "
+        f"({n_pairs / (wl.n_rot * wl.n_data):.4f} of the full search), {prop.plan.n_groups} rotation groups, "
+        f"{prop.plan.n_tiles} tiles, built in {t_plan:.1f} s")
+    # proposal iterations, timed with the audit verdict and any fallback included
     per, recs, fallbacks = [], [], 0
     for it in range(max(2, args.steps)):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -253,16 +270,20 @@ def proposal_form(inp, args, counts_dev):
         torch.cuda.synchronize()
         per.append(ev0.elapsed_time(ev1))
         recs.append(prop.recall.item())
-        log(f"proposal iteration {it + 1 + args.train_at}: {per[-1]:.1f} ms, audit recall {recs[-1]:.4f}, "
+        log(f"proposal iteration {it + 1 + args.train_at}: {per[-1]:.1f} ms, audit recall {recs[-1]:.5f}, "
             f"{'accepted' if ok else 'fell back to full search'}")
+        if not ok:              # the full posterior just computed becomes the new persistence source
+            del prop
+            prop = build(targets_now())
     ms = float(np.mean(per))
     return {"value": round(1000.0 / ms, 5), "ms_per_step": round(ms, 3), "recall": recs, "fallbacks": fallbacks,
             "schedule": f"full search for iterations 1-{args.train_at}, trained on iterations "
-                        f"{args.train_at - 2}-{args.train_at}, proposal from iteration {args.train_at + 1}",
-            "one_off_s": {"full_iterations": round(t_full3, 2), "training": round(tlog.seconds, 2),
+                        f"{args.train_at - 2}-{args.train_at}, proposal from iteration {args.train_at + 1}: "
+                        f"network top-{k_net} cells U top-{k_prev} cells of the last full posterior",
+            "one_off_s": {"full_iterations": round(t_full, 2), "training": round(tlog.seconds, 2),
                           "plan": round(t_plan, 2)},
             "training": {"steps": tlog.steps, "loss_first": tlog.loss_first, "loss_last": tlog.loss_last},
-            "candidate_pairs": int(prop.plan.n_g), "dense_pairs": int(wl.n_rot) * int(wl.n_data)}
+            "candidate_pairs": n_pairs, "dense_pairs": int(wl.n_rot) * int(wl.n_data)}
 
 
 def main():

@@ -251,6 +251,19 @@ emc_status emc_cnn_adam(int32_t n_cells, float* params, const float* grads, floa
 emc_status emc_cnn_topk(const float* logits, int64_t rows, int32_t n_cells, int32_t k,
                         int32_t* out, hipStream_t stream);
 
+/* out [rows][k] int32: the k cells of largest positive mass of each row of T
+ * [rows][n_cells] (largest first, ties to the lower index); a row with fewer
+ * positive cells is padded with -1.  Used on emc_cell_targets output to
+ * propose the cells that held a frame's responsibility in a full iteration.   */
+emc_status emc_cell_topk(const float* T, int64_t rows, int32_t n_cells, int32_t k, int32_t* out,
+                         hipStream_t stream);
+
+/* out [rows][ka + kb] int32: per row, the valid cells (0 <= c < n_cells) of
+ * a [rows][ka] in order, then those of b [rows][kb] not already present,
+ * then -1 padding; repeated cells are kept once (ka + kb <= 512).            */
+emc_status emc_topk_union(const int32_t* a, int32_t ka, const int32_t* b, int32_t kb, int64_t rows,
+                          int32_t n_cells, int32_t* out, hipStream_t stream);
+
 /* Training targets: T [n_data][n_cells] float out, T[k][c] = sum of P[j][k]
  * over the fine rotations j of cell c, listed as CSR (cell_ptr [n_cells+1],
  * cell_rot [n_rot]); P as written by emc_responsibilities (precision of pb). */
@@ -258,12 +271,14 @@ emc_status emc_cell_targets(const emc_problem* pb, const void* P, const int32_t*
                             const int32_t* cell_rot, int32_t n_cells, float* T, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Learned-proposal iteration (BF16 form).  Each frame's E-step runs over the
- * fine rotations of its top-K coarse cells; a seeded subset of frames is
- * searched in full and judges the proposal's recall, the fraction of their
- * full-search responsibility inside their candidates.  The caller reruns the
- * iteration with emc_iterate when the mean recall is below 0.98 or the
- * status word is non-zero.
+ * Learned-proposal iteration (BF16 form).  Each frame's E-step (eq. 2.4) runs
+ * over the fine rotations of its proposed coarse cells only; a seeded subset
+ * of frames is searched in full and judges the proposal's recall, the
+ * fraction of their full-search responsibility inside their proposed cells.
+ * The caller reruns the iteration with emc_iterate when the mean recall is
+ * below its threshold.  Log-likelihoods, responsibilities and the M-step
+ * (eq. 2.11) of the candidate pairs are exact over those pairs (BF16
+ * arithmetic as in emc_iterate); nothing is dropped below a threshold.
  * ------------------------------------------------------------------------ */
 
 /* Packed frames of a frame list: like emc_pack_frames with pb->n_data =
@@ -272,33 +287,39 @@ emc_status emc_pack_frames_list(const emc_problem* pb, const uint16_t* counts, c
                                 void* K_packed, hipStream_t stream);
 
 /* Proposal plan: arrays carved from one caller buffer by emc_proposal_build.
- * Frames are split into audited ones and candidate ones (grouped by their best
- * cell); every (candidate frame, proposed cell) pair is a column of that cell's
- * block of log-likelihoods G_c [rotations of c][frames that proposed c]. */
+ * Frames are split into audited ones and candidate ones (grouped by their
+ * first proposed cell).  The fine rotations of each cell are split into
+ * groups of at most 32; a group's storage in G and P is Fp x 32 elements,
+ * Fp = the cell's frame list length rounded up to 32.  All pointers are
+ * device pointers into the plan buffer.                                        */
 typedef struct emc_proposal {
   int32_t n_cells;        /* coarse cells                                           */
-  int32_t k_top;          /* cells proposed per frame (<= 64)                       */
+  int32_t k_top;          /* entries of each frame's proposal list (<= 256)         */
   int32_t n_cand;         /* frames searched over their candidates                  */
   int32_t n_audit;        /* frames searched in full                                */
   int32_t words;          /* ceil(n_cells / 32): words of a cell bitmask            */
-  int32_t reserved;
+  int32_t ntab;           /* entries per frame of nz_off: n_pix stride / 128 + 1    */
+  int64_t n_groups;       /* rotation groups                                        */
   int64_t n_tiles;        /* workgroups of the candidate log-likelihood (x 8)       */
-  int64_t n_g;            /* floats of all cells' blocks                            */
+  int64_t n_g;            /* elements of G (float) and P (bf16)                     */
   int64_t n_nz;           /* non-zero pixels of the candidate frames                */
   int32_t* cell_of;       /* [n_rot] coarse cell of each rotation (max |<q, q_c>|)  */
   int64_t* cell_ptr;      /* [n_cells + 1] rotations of cell c: cell_rot[ptr[c]..)  */
   int32_t* cell_rot;      /* [n_rot]                                                */
-  int32_t* cand_frames;   /* [n_cand] frame index, grouped by the frame's best cell */
+  int32_t* cand_frames;   /* [n_cand] frame index, grouped by first proposed cell   */
   int32_t* audit_frames;  /* [n_audit] frame index of the audited frames            */
-  int32_t* cand_cells;    /* [n_cand][k_top] proposed cells of each candidate frame */
-  int32_t* pair_col;      /* [n_cand][k_top] column of the pair in its cell's block */
-  int64_t* cf_ptr;        /* [n_cells + 1] pairs of cell c: cf_frame[ptr[c]..)      */
-  int32_t* cf_frame;      /* [n_cand * k_top] candidate-frame index of each pair    */
-  int64_t* g_off;         /* [n_cells + 1] offset of cell c's block                  */
-  void* tiles;            /* [n_tiles] (cell, chunk) int32 pairs, (-1, 0) padding   */
+  int32_t* cand_cells;    /* [n_cand][k_top] proposed cells (-1: none)              */
+  int32_t* pair_col;      /* [n_cand][k_top] position of the frame in the cell's list */
+  int64_t* cf_ptr;        /* [n_cells + 1] frame list of cell c: cf_frame[ptr[c]..) */
+  int32_t* cf_frame;      /* [n_cand * k_top] candidate-frame index                 */
+  int64_t* cg_ptr;        /* [n_cells + 1] groups of cell c: [cg_ptr[c], cg_ptr[c+1]) */
+  void* groups;           /* [n_groups] int32 x 4: cell, first cell_rot entry, count, 0 */
+  int64_t* grp_off;       /* [n_groups + 1] element offset of each group's storage   */
+  void* tiles;            /* [n_tiles] int32 x 2: group, first frame; (-1, 0) padding */
   uint32_t* mask_audit;   /* [n_audit][words] proposed cells of the audited frames  */
   int64_t* nz_ptr;        /* [n_cand + 1] non-zero pixels of candidate frame f:     */
-  uint32_t* nz;           /*   nz[nz_ptr[f]..) = (pixel << 16) | count              */
+  uint32_t* nz;           /*   nz[nz_ptr[f]..) = (pixel << 16) | count, ascending    */
+  int32_t* nz_off;        /* [n_cand][ntab] entries of frame f with pixel < 128 t    */
 } emc_proposal;
 
 /* Bytes of the plan buffer; nz_cap bounds the non-zero pixels of all frames. */
@@ -307,33 +328,30 @@ emc_status emc_proposal_bytes(const emc_problem* pb, int32_t n_cells, int32_t k_
 
 /* Builds the plan (synchronises the stream once).
  *   coarse [n_cells][4] float quaternions of the coarse grid
- *   topk   [n_data][k_top] int32 distinct proposed cells of every frame (emc_cnn_topk)
+ *   topk   [n_data][k_top] int32 proposed cells of every frame, distinct, -1
+ *          for no cell (emc_cnn_topk, emc_cell_topk, emc_topk_union)
  *   audit  [n_audit] int32 distinct frame indices searched in full
  *   counts [n_data][n_pix] uint16 photon counts (their non-zero unmasked pixels
- *          are listed for the candidate frames; n_pix <= 65536)            */
+ *          are listed for the candidate frames; n_pix <= 65536)
+ * EMC_ERR_RANGE if a candidate frame holds a count above 256 (not exact in
+ * BF16); EMC_ERR_WORKSPACE if the non-zero pixels exceed nz_cap.             */
 emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_t n_cells,
                               const int32_t* topk, int32_t k_top, const int32_t* audit, int32_t n_audit,
                               const uint16_t* counts, int64_t nz_cap, void* buf, size_t buf_bytes,
                               emc_proposal* plan, hipStream_t stream);
 
-/* Workspace bytes of emc_iterate_proposed; triple_cap bounds the number of
- * (rotation, frame) responsibilities >= 1e-7 kept for the M-step.  */
-emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan,
-                                        int64_t triple_cap, size_t* bytes);
+/* Workspace bytes of emc_iterate_proposed. */
+emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan, size_t* bytes);
 
 /* One iteration with the E-step restricted to the proposal (pb->precision must
  * be EMC_PREC_BF16; pb->n_data = n_cand + n_audit):
- *   K_cand   frames plan->cand_frames packed by emc_pack_frames_list
- *   K_audit  frames plan->audit_frames packed by emc_pack_frames_list
+ *   K_audit  frames plan->audit_frames packed by emc_pack_frames_list (the
+ *            candidate frames are read from the plan's sparse lists)
  *   loglik   mean log-evidence over all frames (each over its searched set)
- *   recall_mean  mean recall of the audited frames (NaN without audit)
- *   status   device int32: bit 0 set if responsibilities overflowed triple_cap
- * Responsibilities below 1e-7 are left out of the M-step (each frame loses
- * at most 1e-7 x its candidate count of probability mass there).          */
-emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_cand,
-                                const void* K_audit, const float* model_in, float* model_out,
-                                double* loglik, double* recall_mean, int32_t* status,
-                                int64_t triple_cap, void* ws, size_t ws_bytes, hipStream_t stream);
+ *   recall_mean  mean recall of the audited frames (NaN without audit)      */
+emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_audit,
+                                const float* model_in, float* model_out, double* loglik,
+                                double* recall_mean, void* ws, size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

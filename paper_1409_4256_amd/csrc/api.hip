@@ -120,12 +120,12 @@ Layout layout_of(const emc_problem* pb) {
 // ---- launch sequences shared by the step entry points and emc_iterate (no validation) ----
 
 emc_status run_expand(const emc_problem* pb, const float* model, double* c, void* slices, double* S, float* scale,
-                      hipStream_t st, float* A32 = nullptr) {
+                      hipStream_t st) {
   const Dims d = dims_of(pb);
   HIP_TRY(launch_centre(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c, st), "centre");
   if (is_bf16(pb))
     HIP_TRY(launch_expand_bf16(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c, slices, S,
-                               scale, A32, st),
+                               scale, st),
             "expand");
   else
     HIP_TRY(launch_expand(model, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c,
@@ -531,7 +531,29 @@ emc_status emc_cnn_topk(const float* logits, int64_t rows, int32_t n_cells, int3
   if (rows == 0) return EMC_OK;
   CHECK(need(logits, 4, "logits"));
   CHECK(need(out, 4, "out"));
-  HIP_TRY(launch_topk(logits, rows, n_cells, k, out, st), "topk");
+  HIP_TRY(launch_topk(logits, rows, n_cells, k, false, out, st), "topk");
+  return EMC_OK;
+}
+
+emc_status emc_cell_topk(const float* T, int64_t rows, int32_t n_cells, int32_t k, int32_t* out, hipStream_t st) {
+  if (rows < 0 || n_cells < 1 || n_cells > 8192 || k < 1 || k > n_cells)
+    return fail(EMC_ERR_INVALID_ARG, "need rows >= 0, 1 <= k <= n_cells <= 8192");
+  if (rows == 0) return EMC_OK;
+  CHECK(need(T, 4, "T"));
+  CHECK(need(out, 4, "out"));
+  HIP_TRY(launch_topk(T, rows, n_cells, k, true, out, st), "cell topk");
+  return EMC_OK;
+}
+
+emc_status emc_topk_union(const int32_t* a, int32_t ka, const int32_t* b, int32_t kb, int64_t rows, int32_t n_cells,
+                          int32_t* out, hipStream_t st) {
+  if (rows < 0 || n_cells < 1 || n_cells > 8192 || ka < 0 || kb < 0 || ka + kb < 1 || ka + kb > 512)
+    return fail(EMC_ERR_INVALID_ARG, "need rows >= 0, 1 <= n_cells <= 8192, 1 <= ka + kb <= 512");
+  if (rows == 0) return EMC_OK;
+  if (ka > 0) CHECK(need(a, 4, "a"));
+  if (kb > 0) CHECK(need(b, 4, "b"));
+  CHECK(need(out, 4, "out"));
+  HIP_TRY(launch_topk_union(a, ka, b, kb, rows, n_cells, out, st), "topk union");
   return EMC_OK;
 }
 
@@ -556,47 +578,65 @@ namespace {
 
 int words_of(int n_cells) { return (n_cells + 31) / 32; }
 
+constexpr int kMaxTop = 256;      // proposed cells per frame
+constexpr int kBandPx = 128;      // granularity of the entry-offset table (the kernels' band)
+constexpr int kTileFrames = 64;   // frames per candidate log-likelihood tile
+constexpr int kGroupRot = 32;     // rotations per group
+
+int64_t group_cap(int n_rot, int n_cells) { return (int64_t)n_cells + (n_rot + kGroupRot - 1) / kGroupRot; }
+int64_t tile_cap(int64_t g_max, int64_t n_cand) {
+  const int64_t per = (n_cand + kTileFrames - 1) / kTileFrames;
+  return g_max * per + 8 * per + 8;
+}
+int ntab_of(int n_pix) { return (int)(round_up(n_pix, 256) / kBandPx) + 1; }
+
 // Carving of the plan buffer (capacities known before the build).
 struct PlanLayout {
-  size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, g_off, tiles,
-      mask_audit, nz_ptr, nz, hist, cursor, keys, order, mark, frame_ptr, sizes, nchunk, nzcnt, scalars, total;
+  size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, cg_ptr,
+      groups, grp_off, tiles, mask_audit, nz_ptr, nz, nz_off, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd,
+      cnt, nzcnt, scalars, total;
 };
 
-PlanLayout plan_layout(int n_rot, int n_data, int n_cells, int k_top, int n_audit, int64_t nz_cap) {
+PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top, int n_audit, int64_t nz_cap) {
   const int64_t n_cand = (int64_t)n_data - n_audit;
   const int64_t n_pairs = n_cand * k_top;
+  const int64_t g_max = group_cap(n_rot, n_cells);
   const int w = words_of(n_cells);
   PlanLayout L;
   size_t o = 0;
-  auto take = [&](size_t bytes) {
+  auto take = [&](int64_t bytes) {
     size_t at = o;
-    o += (size_t)round_up((int64_t)(bytes ? bytes : 1), 256);
+    o += (size_t)round_up(bytes > 0 ? bytes : 1, 256);
     return at;
   };
   const int64_t nkeys = std::max<int64_t>(n_cells + 1, std::max<int64_t>(n_rot, (int64_t)1) + 1);
-  L.cell_of = take((size_t)n_rot * 4);
-  L.cell_ptr = take((size_t)(n_cells + 2) * 8);
-  L.cell_rot = take((size_t)n_rot * 4);
-  L.cand_frames = take((size_t)n_cand * 4);
-  L.audit_frames = take((size_t)n_audit * 4);
-  L.cand_cells = take((size_t)n_pairs * 4);
-  L.pair_col = take((size_t)n_pairs * 4);
-  L.cf_ptr = take((size_t)(n_cells + 2) * 8);
-  L.cf_frame = take((size_t)n_pairs * 4);
-  L.g_off = take((size_t)(n_cells + 1) * 8);
-  L.tiles = take((size_t)8 * ((n_pairs + 31) / 32 + n_cells) * 8);
-  L.mask_audit = take((size_t)n_audit * w * 4);
-  L.nz_ptr = take((size_t)(n_cand + 1) * 8);
-  L.nz = take((size_t)nz_cap * 4);
-  L.hist = take((size_t)nkeys * 4);
-  L.cursor = take((size_t)nkeys * 4);
-  L.keys = take((size_t)std::max<int64_t>(n_pairs, n_data) * 4);
-  L.order = take((size_t)std::max<int64_t>(n_pairs, n_data) * 4);
-  L.mark = take((size_t)n_data * 4);
-  L.frame_ptr = take((size_t)(n_cells + 2) * 8);
-  L.sizes = take((size_t)n_cells * 8);
-  L.nchunk = take((size_t)n_cells * 4);
-  L.nzcnt = take((size_t)n_cand * 4);
+  L.cell_of = take((int64_t)n_rot * 4);
+  L.cell_ptr = take((int64_t)(n_cells + 2) * 8);
+  L.cell_rot = take((int64_t)n_rot * 4);
+  L.cand_frames = take(n_cand * 4);
+  L.audit_frames = take((int64_t)n_audit * 4);
+  L.cand_cells = take(n_pairs * 4);
+  L.pair_col = take(n_pairs * 4);
+  L.cf_ptr = take((int64_t)(n_cells + 2) * 8);
+  L.cf_frame = take(n_pairs * 4);
+  L.cg_ptr = take((int64_t)(n_cells + 1) * 8);
+  L.groups = take(g_max * 16);
+  L.grp_off = take((g_max + 1) * 8);
+  L.tiles = take(tile_cap(g_max, n_cand) * 8);
+  L.mask_audit = take((int64_t)n_audit * w * 4);
+  L.nz_ptr = take((n_cand + 1) * 8);
+  L.nz = take(nz_cap * 4);
+  L.nz_off = take(n_cand * ntab_of(n_pix) * 4);
+  L.hist = take(nkeys * 4);
+  L.cursor = take(nkeys * 4);
+  L.keys = take(std::max<int64_t>(n_pairs, n_data) * 4);
+  L.order = take(std::max<int64_t>(n_pairs, n_data) * 4);
+  L.mark = take((int64_t)n_data * 4);
+  L.frame_ptr = take((int64_t)(n_cells + 2) * 8);
+  L.gsize = take(g_max * 8);
+  L.xcd = take(g_max * 4);
+  L.cnt = take((int64_t)n_cells * 4);
+  L.nzcnt = take(n_cand * 4);
   L.scalars = take(64);
   L.total = o;
   return L;
@@ -640,11 +680,11 @@ emc_status emc_proposal_bytes(const emc_problem* pb, int32_t n_cells, int32_t k_
                               int64_t nz_cap, size_t* bytes) {
   CHECK(check_problem(pb, false));
   if (n_cells < 1 || n_cells > 8192) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d outside [1, 8192]", n_cells);
-  if (k_top < 1 || k_top > 64 || k_top > n_cells) return fail(EMC_ERR_INVALID_ARG, "k_top=%d outside [1, 64]", k_top);
-  if (n_audit < 0 || n_audit > pb->n_data) return fail(EMC_ERR_INVALID_ARG, "n_audit=%d outside [0, n_data]", n_audit);
+  if (k_top < 1 || k_top > kMaxTop) return fail(EMC_ERR_INVALID_ARG, "k_top=%d outside [1, %d]", k_top, kMaxTop);
+  if (n_audit < 0 || n_audit > pb->n_data) return fail(EMC_ERR_INVALID_ARG, "n_audit outside [0, n_data]");
   if (nz_cap < 1) return fail(EMC_ERR_INVALID_ARG, "nz_cap < 1");
   if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
-  *bytes = plan_layout(pb->n_rot, pb->n_data, n_cells, k_top, n_audit, nz_cap).total;
+  *bytes = plan_layout(pb->n_rot, pb->n_data, pb->n_pix, n_cells, k_top, n_audit, nz_cap).total;
   return EMC_OK;
 }
 
@@ -653,7 +693,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
                               int64_t nz_cap, void* buf, size_t buf_bytes, emc_proposal* plan, hipStream_t st) {
   CHECK(check_problem(pb, true));
   if (n_cells < 1 || n_cells > 8192) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d outside [1, 8192]", n_cells);
-  if (k_top < 1 || k_top > 64 || k_top > n_cells) return fail(EMC_ERR_INVALID_ARG, "k_top=%d outside [1, 64]", k_top);
+  if (k_top < 1 || k_top > kMaxTop) return fail(EMC_ERR_INVALID_ARG, "k_top=%d outside [1, %d]", k_top, kMaxTop);
   if (n_audit < 0 || n_audit > pb->n_data) return fail(EMC_ERR_INVALID_ARG, "n_audit outside [0, n_data]");
   if (pb->n_data < 1) return fail(EMC_ERR_INVALID_ARG, "the proposal needs frames");
   if (pb->n_pix > 65536) return fail(EMC_ERR_UNSUPPORTED, "the proposal form needs n_pix <= 65536");
@@ -663,18 +703,21 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   if (n_audit > 0) CHECK(need(audit, 4, "audit"));
   CHECK(need(counts, 2, "counts"));
   if (!plan) return fail(EMC_ERR_INVALID_ARG, "plan is NULL");
-  const PlanLayout L = plan_layout(pb->n_rot, pb->n_data, n_cells, k_top, n_audit, nz_cap);
+  const PlanLayout L = plan_layout(pb->n_rot, pb->n_data, pb->n_pix, n_cells, k_top, n_audit, nz_cap);
   if (!buf || !aligned(buf, 256)) return fail(EMC_ERR_WORKSPACE, "plan buffer is NULL or not 256-byte aligned");
   if (buf_bytes < L.total) return fail(EMC_ERR_WORKSPACE, "plan buffer has %zu bytes, needs %zu", buf_bytes, L.total);
   char* b = (char*)buf;
   const int64_t n_data = pb->n_data, n_cand = n_data - n_audit, n_pairs = n_cand * k_top;
+  const int64_t g_max = group_cap(pb->n_rot, n_cells);
   const int w = words_of(n_cells);
+  const int ntab = ntab_of(pb->n_pix);
   emc_proposal P{};
   P.n_cells = n_cells;
   P.k_top = k_top;
   P.n_cand = (int32_t)n_cand;
   P.n_audit = n_audit;
   P.words = w;
+  P.ntab = ntab;
   P.cell_of = (int32_t*)(b + L.cell_of);
   P.cell_ptr = (int64_t*)(b + L.cell_ptr);
   P.cell_rot = (int32_t*)(b + L.cell_rot);
@@ -684,26 +727,31 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   P.pair_col = (int32_t*)(b + L.pair_col);
   P.cf_ptr = (int64_t*)(b + L.cf_ptr);
   P.cf_frame = (int32_t*)(b + L.cf_frame);
-  P.g_off = (int64_t*)(b + L.g_off);
+  P.cg_ptr = (int64_t*)(b + L.cg_ptr);
+  P.groups = (void*)(b + L.groups);
+  P.grp_off = (int64_t*)(b + L.grp_off);
   P.tiles = (void*)(b + L.tiles);
   P.mask_audit = (uint32_t*)(b + L.mask_audit);
   P.nz_ptr = (int64_t*)(b + L.nz_ptr);
   P.nz = (uint32_t*)(b + L.nz);
+  P.nz_off = (int32_t*)(b + L.nz_off);
   int32_t* hist = (int32_t*)(b + L.hist);
   int32_t* cursor = (int32_t*)(b + L.cursor);
   int32_t* keys = (int32_t*)(b + L.keys);
   int32_t* order = (int32_t*)(b + L.order);
   int32_t* mark = (int32_t*)(b + L.mark);
   int64_t* frame_ptr = (int64_t*)(b + L.frame_ptr);
-  int64_t* sizes = (int64_t*)(b + L.sizes);
-  int32_t* nchunk = (int32_t*)(b + L.nchunk);
+  int64_t* gsize = (int64_t*)(b + L.gsize);
+  int32_t* xcd = (int32_t*)(b + L.xcd);
+  int32_t* cnt = (int32_t*)(b + L.cnt);
   int32_t* nzcnt = (int32_t*)(b + L.nzcnt);
-  int64_t* scal = (int64_t*)(b + L.scalars);  // [0] n_tiles
+  int64_t* scal = (int64_t*)(b + L.scalars);  // [0] n_tiles, [1] count range flag (int32)
+  int32_t* over = (int32_t*)(scal + 1);
   // 1. coarse cell of every fine rotation; rotations grouped by cell
   HIP_TRY(launch_assign_cells(pb->quat, pb->n_rot, coarse, n_cells, P.cell_of, st), "assign cells");
   HIP_TRY(launch_counting_sort(P.cell_of, pb->n_rot, n_cells, hist, cursor, P.cell_ptr, P.cell_rot, nullptr, st),
           "sort rotations");
-  // 2. frames: audited ones apart, the others grouped by their best cell
+  // 2. frames: audited ones apart, the others grouped by their first proposed cell
   HIP_TRY(launch_fill_i32(mark, n_data, 0, st), "mark");
   if (n_audit > 0)
     emc::mark_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(audit, n_audit, n_data, mark);
@@ -713,27 +761,35 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   if (n_audit > 0)
     emc::copy_i32_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(order + n_cand, n_audit, P.audit_frames);
   HIP_TRY(launch_cand_mask(topk, k_top, P.audit_frames, n_audit, w, P.mask_audit, st), "audit masks");
-  // 3. (frame, candidate cell) pairs grouped by cell: each cell's frame list and storage
+  // 3. (frame, proposed cell) pairs grouped by cell: each cell's frame list
   HIP_TRY(launch_cand_cells(topk, k_top, P.cand_frames, n_cand, n_cells, P.cand_cells, keys, st), "candidate cells");
   HIP_TRY(launch_counting_sort(keys, n_pairs, n_cells + 1, hist, cursor, P.cf_ptr, order, nullptr, st), "sort pairs");
   HIP_TRY(launch_pair_columns(order, n_pairs, k_top, keys, P.cf_ptr, P.cf_frame, P.pair_col, st), "pair columns");
-  HIP_TRY(launch_cell_sizes(P.cell_ptr, P.cf_ptr, n_cells, sizes, nchunk, st), "cell sizes");
-  HIP_TRY(launch_scan64(sizes, n_cells, P.g_off, st), "cell offsets");
-  HIP_TRY(launch_cell_tiles(nchunk, n_cells, (int2*)P.tiles, scal, st), "cell tiles");
-  // 4. sparse frames (non-zero pixels) of the candidate frames
-  HIP_TRY(launch_nz_count(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, nzcnt, st), "nz count");
+  // 4. groups of up to 32 rotations per cell, their storage and the log-likelihood tiles
+  HIP_TRY(launch_cell_groups(P.cell_ptr, P.cf_ptr, n_cells, cnt, P.cg_ptr, (int4*)P.groups, gsize, P.grp_off, g_max,
+                             st),
+          "groups");
+  HIP_TRY(launch_group_tiles((const int4*)P.groups, P.cg_ptr, n_cells, P.cf_ptr, xcd, (int2*)P.tiles, scal, st),
+          "tiles");
+  // 5. sparse frames (non-zero pixels) of the candidate frames
+  HIP_TRY(launch_fill_i32(over, 1, 0, st), "range flag");
+  HIP_TRY(launch_nz_count(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, nzcnt, over, st), "nz count");
   HIP_TRY(launch_scan(nzcnt, n_cand, P.nz_ptr, st), "nz offsets");
-  int64_t host[3] = {0, 0, 0};
-  HIP_TRY(hipMemcpyAsync(&host[0], scal, 8, hipMemcpyDeviceToHost, st), "read n_tiles");
-  HIP_TRY(hipMemcpyAsync(&host[1], P.g_off + n_cells, 8, hipMemcpyDeviceToHost, st), "read n_g");
-  HIP_TRY(hipMemcpyAsync(&host[2], P.nz_ptr + n_cand, 8, hipMemcpyDeviceToHost, st), "read n_nz");
+  int64_t host[5] = {0, 0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(&host[0], scal, 16, hipMemcpyDeviceToHost, st), "read n_tiles");
+  HIP_TRY(hipMemcpyAsync(&host[2], P.cg_ptr + n_cells, 8, hipMemcpyDeviceToHost, st), "read n_groups");
+  HIP_TRY(hipMemcpyAsync(&host[3], P.grp_off + g_max, 8, hipMemcpyDeviceToHost, st), "read n_g");
+  HIP_TRY(hipMemcpyAsync(&host[4], P.nz_ptr + n_cand, 8, hipMemcpyDeviceToHost, st), "read n_nz");
   HIP_TRY(hipStreamSynchronize(st), "proposal build sync");
-  if (host[2] > nz_cap) return fail(EMC_ERR_WORKSPACE, "frames have %lld non-zero pixels, nz_cap is %lld",
-                                    (long long)host[2], (long long)nz_cap);
+  if ((int32_t)host[1] != 0) return fail(EMC_ERR_RANGE, "a photon count exceeds 256, which BF16 cannot hold exactly");
+  if (host[4] > nz_cap) return fail(EMC_ERR_WORKSPACE, "frames have %lld non-zero pixels, nz_cap is %lld",
+                                    (long long)host[4], (long long)nz_cap);
   HIP_TRY(launch_nz_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.nz_ptr, P.nz, st), "nz fill");
+  HIP_TRY(launch_nz_offsets(P.nz_ptr, P.nz, n_cand, ntab, P.nz_off, st), "nz band offsets");
   P.n_tiles = host[0];
-  P.n_g = host[1];
-  P.n_nz = host[2];
+  P.n_groups = host[2];
+  P.n_g = host[3];
+  P.n_nz = host[4];
   *plan = P;
   return EMC_OK;
 }
@@ -743,47 +799,37 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
 namespace {
 
 struct PropWs {
-  size_t slices, A32, S, scale, c, b, L, G, Ga, Pa, stats_a, rho_a, recall, tj, tk, tp, tk2, tp2, hist, cursor, tptr,
-      rho, num, den, count, total;
+  size_t slices, S, scale, c, b, L, G, P, Ga, Pa, stats_a, rho_a, recall, rho, num, den, total;
 };
 
-PropWs prop_ws(const emc_problem* pb, const emc_proposal* P, int64_t cap) {
+PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
   const int64_t ps = round_up(pb->n_pix, 256);
   const int64_t dsa = round_up(P->n_audit, 256);
   const int64_t grid = (int64_t)pb->grid_n * pb->grid_n * pb->grid_n;
   const int64_t n_frames = (int64_t)P->n_cand + P->n_audit;
   PropWs W;
   size_t o = 0;
-  auto take = [&](size_t bytes) {
+  auto take = [&](int64_t bytes) {
     size_t at = o;
-    o += (size_t)round_up((int64_t)(bytes ? bytes : 1), 256);
+    o += (size_t)round_up(bytes > 0 ? bytes : 1, 256);
     return at;
   };
-  W.slices = take((size_t)pb->n_rot * ps * 4);
-  W.A32 = take((size_t)pb->n_rot * ps * 4);
-  W.S = take((size_t)pb->n_rot * 8);
-  W.scale = take((size_t)pb->n_rot * 4);
-  W.c = take((size_t)ps * 8);
-  W.b = take((size_t)n_frames * 8);
-  W.L = take((size_t)n_frames * 8);
-  W.G = take((size_t)P->n_g * 4);
-  W.Ga = take((size_t)pb->n_rot * dsa * 4);
-  W.Pa = take((size_t)pb->n_rot * dsa * 2);
-  W.stats_a = take((size_t)P->n_audit * 16);
-  W.rho_a = take((size_t)pb->n_rot * 8);
-  W.recall = take((size_t)P->n_audit * 8);
-  W.tj = take((size_t)cap * 4);
-  W.tk = take((size_t)cap * 4);
-  W.tp = take((size_t)cap * 4);
-  W.tk2 = take((size_t)cap * 4);
-  W.tp2 = take((size_t)cap * 4);
-  W.hist = take((size_t)(pb->n_rot + 1) * 4);
-  W.cursor = take((size_t)(pb->n_rot + 1) * 4);
-  W.tptr = take((size_t)(pb->n_rot + 2) * 8);
-  W.rho = take((size_t)pb->n_rot * 8);
-  W.num = take((size_t)grid * 8);
-  W.den = take((size_t)grid * 8);
-  W.count = take(16);
+  W.slices = take((int64_t)pb->n_rot * ps * 4);  // BF16 hi + lo, later the FP32 M-step rows
+  W.S = take((int64_t)pb->n_rot * 8);
+  W.scale = take((int64_t)pb->n_rot * 4);
+  W.c = take(ps * 8);
+  W.b = take(n_frames * 8);
+  W.L = take(n_frames * 8);
+  W.G = take(P->n_g * 4);
+  W.P = take(P->n_g * 2);
+  W.Ga = take((int64_t)pb->n_rot * dsa * 4);
+  W.Pa = take((int64_t)pb->n_rot * dsa * 2);
+  W.stats_a = take((int64_t)P->n_audit * 16);
+  W.rho_a = take((int64_t)pb->n_rot * 8);
+  W.recall = take((int64_t)P->n_audit * 8);
+  W.rho = take((int64_t)pb->n_rot * 8);
+  W.num = take(grid * 8);
+  W.den = take(grid * 8);
   W.total = o;
   return W;
 }
@@ -792,8 +838,9 @@ emc_status check_plan(const emc_problem* pb, const emc_proposal* P) {
   if (!P) return fail(EMC_ERR_INVALID_ARG, "plan is NULL");
   if (P->n_cand < 0 || P->n_audit < 0 || (int64_t)P->n_cand + P->n_audit != pb->n_data)
     return fail(EMC_ERR_INVALID_ARG, "plan frames (%d + %d) do not match n_data %d", P->n_cand, P->n_audit, pb->n_data);
-  if (P->k_top < 1 || P->k_top > 64 || P->n_cells < 1 || P->words != words_of(P->n_cells) || P->n_g < 0 ||
-      P->n_tiles < 0 || P->n_tiles % 8 != 0)
+  if (P->k_top < 1 || P->k_top > kMaxTop || P->n_cells < 1 || P->words != words_of(P->n_cells) || P->n_g < 0 ||
+      P->n_tiles < 0 || P->n_tiles % 8 != 0 || P->n_groups < 1 || P->n_groups > group_cap(pb->n_rot, P->n_cells) ||
+      P->ntab != ntab_of(pb->n_pix))
     return fail(EMC_ERR_INVALID_ARG, "inconsistent plan");
   return EMC_OK;
 }
@@ -802,32 +849,26 @@ emc_status check_plan(const emc_problem* pb, const emc_proposal* P) {
 
 extern "C" {
 
-emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan, int64_t triple_cap,
-                                        size_t* bytes) {
+emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan, size_t* bytes) {
   CHECK(check_problem(pb, false));
   CHECK(check_plan(pb, plan));
-  if (triple_cap < 1) return fail(EMC_ERR_INVALID_ARG, "triple_cap < 1");
   if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
-  *bytes = prop_ws(pb, plan, triple_cap).total;
+  *bytes = prop_ws(pb, plan).total;
   return EMC_OK;
 }
 
-emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_cand,
-                                const void* K_audit, const float* model_in, float* model_out, double* loglik,
-                                double* recall_mean, int32_t* status, int64_t triple_cap, void* ws, size_t ws_bytes,
-                                hipStream_t st) {
+emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_audit,
+                                const float* model_in, float* model_out, double* loglik, double* recall_mean,
+                                void* ws, size_t ws_bytes, hipStream_t st) {
   CHECK(check_problem(pb, true));
   if (!is_bf16(pb)) return fail(EMC_ERR_UNSUPPORTED, "the proposal form runs in BF16 precision");
   CHECK(check_plan(pb, plan));
-  if (plan->n_cand > 0) CHECK(need(K_cand, 16, "K_cand"));
   if (plan->n_audit > 0) CHECK(need(K_audit, 16, "K_audit"));
   CHECK(need(model_in, 4, "model_in"));
   CHECK(need(model_out, 4, "model_out"));
   CHECK(need(loglik, 8, "loglik"));
   CHECK(need(recall_mean, 8, "recall_mean"));
-  CHECK(need(status, 4, "status"));
-  if (triple_cap < 1 || triple_cap > (int64_t)INT32_MAX) return fail(EMC_ERR_INVALID_ARG, "triple_cap out of range");
-  const PropWs W = prop_ws(pb, plan, triple_cap);
+  const PropWs W = prop_ws(pb, plan);
   if (!ws || !aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is NULL or not 256-byte aligned");
   if (ws_bytes < W.total) return fail(EMC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
   char* w = (char*)ws;
@@ -835,72 +876,60 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   const int64_t nc = plan->n_cand, na = plan->n_audit;
   const int64_t dsa = round_up(na, 256);
   void* slices = w + W.slices;
-  float* A32 = (float*)(w + W.A32);
   double* S = (double*)(w + W.S);
   float* scale = (float*)(w + W.scale);
   double* c = (double*)(w + W.c);
   double* b = (double*)(w + W.b);
   double* L = (double*)(w + W.L);
   float* G = (float*)(w + W.G);
+  void* Pc = w + W.P;
   float* Ga = (float*)(w + W.Ga);
   void* Pa = w + W.Pa;
   double* stats_a = (double*)(w + W.stats_a);
   double* rho_a = (double*)(w + W.rho_a);
   double* recall = (double*)(w + W.recall);
-  int32_t* tj = (int32_t*)(w + W.tj);
-  int32_t* tk = (int32_t*)(w + W.tk);
-  float* tp = (float*)(w + W.tp);
-  int32_t* tk2 = (int32_t*)(w + W.tk2);
-  float* tp2 = (float*)(w + W.tp2);
-  int32_t* hist = (int32_t*)(w + W.hist);
-  int32_t* cursor = (int32_t*)(w + W.cursor);
-  int64_t* tptr = (int64_t*)(w + W.tptr);
   double* rho = (double*)(w + W.rho);
   double* num = (double*)(w + W.num);
   double* den = (double*)(w + W.den);
-  unsigned long long* count = (unsigned long long*)(w + W.count);
-  // status word: bit 0 set when the significant responsibilities overflow triple_cap
-  HIP_TRY(launch_fill_i32(status, 1, 0, st), "status");
-  HIP_TRY(launch_fill_i32((int32_t*)count, 2, 0, st), "count");
-  // expansion: BF16 hi + lo for the audit's dense contraction, FP32 A for the sparse gathers
-  emc_problem pc = *pb;
-  pc.n_data = (int32_t)nc;
-  CHECK(run_expand(&pc, model_in, c, slices, S, scale, st, A32));
-  // candidate frames: sparse log-likelihoods per (cell, frame), E-step over each frame's candidates
+  const int4* groups = (const int4*)plan->groups;
+  // expansion (BF16 hi + lo slices with their row scales)
+  CHECK(run_expand(pb, model_in, c, slices, S, scale, st));
+  // candidate frames: log-likelihoods per (group, listed frame), E-step over each frame's candidates
   if (nc > 0) {
-    HIP_TRY(launch_frame_dot(K_cand, true, ps, nc, c, b, st), "frame_dot");
-    HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, plan->cell_ptr, plan->cell_rot, plan->cf_ptr,
-                               plan->cf_frame, plan->g_off, plan->nz_ptr, plan->nz, A32, ps, G, st),
+    HIP_TRY(launch_nz_dot(plan->nz_ptr, plan->nz, nc, c, b, st), "nz_dot");
+    HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, groups, plan->grp_off, plan->cf_ptr,
+                               plan->cf_frame, plan->nz_ptr, plan->nz_off, plan->ntab, plan->nz, plan->cell_rot,
+                               slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
             "candidate loglik");
-    HIP_TRY(launch_cand_estep(G, plan->g_off, plan->cand_cells, plan->pair_col, plan->k_top, nc, plan->cell_ptr,
-                              plan->cell_rot, plan->cf_ptr, pb->log_w, S, b, L, tj, tk, tp, triple_cap, count, status,
-                              st),
+    HIP_TRY(launch_cand_estep(G, Pc, groups, plan->grp_off, plan->cg_ptr, plan->cand_cells, plan->pair_col,
+                              plan->k_top, nc, plan->cell_rot, pb->log_w, S, b, L, st),
             "candidate estep");
   }
   // audited frames: full search, recall of the proposal
   HIP_TRY(launch_fill_zero_f64(recall, (size_t)na, st), "zero recall");
+  emc_problem pa = *pb;
+  pa.n_data = (int32_t)na;
   if (na > 0) {
-    emc_problem pa = *pb;
-    pa.n_data = (int32_t)na;
     CHECK(run_loglik(&pa, K_audit, slices, scale, c, Ga, b + nc, st));
     CHECK(run_estep(&pa, Ga, S, b + nc, EMC_RESP_FULL, stats_a, Pa, L + nc, rho_a, st));
-    HIP_TRY(launch_audit(Pa, true, dsa, pb->n_rot, na, plan->mask_audit, plan->words, plan->cell_of, (int32_t)nc, tj,
-                         tk, tp, triple_cap, count, status, recall, st),
-            "audit");
+    HIP_TRY(launch_audit_recall(Pa, dsa, pb->n_rot, na, plan->mask_audit, plan->words, plan->cell_of, recall, st),
+            "audit recall");
   }
   emc::mean2_kernel<<<1, 256, 0, st>>>(recall, na, recall_mean);
-  // triples grouped by rotation (frames ascending), then the sparse M-step; the
-  // triple count stays on the device
-  HIP_TRY(launch_triple_sort(tj, tk, tp, count, triple_cap, pb->n_rot, hist, cursor, tptr, tk2, tp2, st),
-          "triple sort");
+  // M-step rows: the audited frames' dense product first, then every group's candidate sum
   float* Wp = (float*)slices;  // hi/lo are no longer needed
-  HIP_TRY(launch_sparse_mstep(tptr, tk2, tp2, K_cand, nc, K_audit, true, ps, pb->n_rot, Wp, rho, st), "sparse mstep");
+  if (na > 0) {
+    const char* KTa = (const char*)K_audit + (size_t)na * ps * 2;
+    HIP_TRY(launch_gemm_bf16_nt(Pa, KTa, Wp, pb->n_rot, ps, dsa, dsa, dsa, ps, st), "audit mstep gemm");
+  }
+  HIP_TRY(launch_cand_mstep(groups, plan->grp_off, plan->n_groups, plan->cf_ptr, plan->cf_frame, plan->nz_ptr,
+                            plan->nz_off, plan->ntab, plan->nz, Pc, plan->cell_rot, ps, Wp, rho, rho_a, na > 0, st),
+          "candidate mstep");
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
   HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");
   HIP_TRY(launch_scatter(Wp, ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, st),
           "scatter");
   CHECK(run_finalize(pb, num, den, model_in, model_out, L, nc + na, loglik, st));
-  (void)rho_a;
   return EMC_OK;
 }
 

@@ -256,13 +256,17 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
 
 // --------------------------------------------------------------------- top-K
 // One workgroup per row: k rounds of arg-max with exclusion; ties -> lower index.
-__global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ z, int n_cells, int k,
+__global__ __launch_bounds__(256) void topk_kernel(const float* __restrict__ z, int n_cells, int k, int positive,
                                                    int32_t* __restrict__ out) {
   extern __shared__ float vals[];
   __shared__ float bv[4];
   __shared__ int bi[4];
   const int b = blockIdx.x;
-  for (int c = threadIdx.x; c < n_cells; c += 256) vals[c] = z[(int64_t)b * n_cells + c];
+  // positive: only values > 0 are candidates (the others become NaN, never picked)
+  for (int c = threadIdx.x; c < n_cells; c += 256) {
+    const float v = z[(int64_t)b * n_cells + c];
+    vals[c] = positive && !(v > 0.0f) ? NAN : v;
+  }
   __syncthreads();
   for (int r = 0; r < k; ++r) {
     float best = -INFINITY;
@@ -410,9 +414,10 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   return hipGetLastError();
 }
 
-hipError_t launch_topk(const float* z, int64_t rows, int n_cells, int k, int32_t* out, hipStream_t st) {
+hipError_t launch_topk(const float* z, int64_t rows, int n_cells, int k, bool positive, int32_t* out,
+                       hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  topk_kernel<<<(unsigned)rows, 256, n_cells * sizeof(float), st>>>(z, n_cells, k, out);
+  topk_kernel<<<(unsigned)rows, 256, n_cells * sizeof(float), st>>>(z, n_cells, k, positive ? 1 : 0, out);
   return hipGetLastError();
 }
 

@@ -85,7 +85,7 @@ hipError_t launch_expand(const float* model, int N, const float* q, const uint8_
 // hilo: hi plane [n_rot][stride] bf16 followed by lo plane [n_rot][stride] bf16
 hipError_t launch_expand_bf16(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
                               int n_pix, int64_t stride, int n_rot, const double* c, void* hilo, double* S,
-                              float* scale, float* A32, hipStream_t st);
+                              float* scale, hipStream_t st);
 hipError_t launch_frame_dot(const void* K, bool bf16, int64_t stride, int64_t n_data, const double* c, double* b,
                             hipStream_t st);
 // C[M][N] = sum_k A[m][k] B[n][k] (both operands contiguous along k), FP32 MFMA;
@@ -130,7 +130,10 @@ hipError_t launch_softmax_xent(const float* z, const float* T, int n_cells, int 
                                hipStream_t st);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2,
                        float eps, float c1, float c2, hipStream_t st);
-hipError_t launch_topk(const float* z, int64_t rows, int n_cells, int k, int32_t* out, hipStream_t st);
+hipError_t launch_topk(const float* z, int64_t rows, int n_cells, int k, bool positive, int32_t* out,
+                       hipStream_t st);
+hipError_t launch_topk_union(const int32_t* a, int ka, const int32_t* b, int kb, int64_t rows, int n_cells,
+                             int32_t* out, hipStream_t st);
 hipError_t launch_cell_targets(const void* P, bool bf16, int64_t ldp, int64_t n_data, const int32_t* cell_ptr,
                                const int32_t* cell_rot, int n_cells, float* T, hipStream_t st);
 
@@ -139,7 +142,6 @@ hipError_t launch_assign_cells(const float* quat, int n_rot, const float* coarse
                                hipStream_t st);
 hipError_t launch_counting_sort(const int32_t* keys, int64_t n, int nk, int32_t* hist, int32_t* cursor,
                                 int64_t* ptr, int32_t* order, float* payload_unused, hipStream_t st);
-hipError_t launch_segment_sort(const int64_t* ptr, int n_seg, int32_t* vals, float* payload, hipStream_t st);
 hipError_t launch_scan(const int32_t* cnt, int64_t n, int64_t* ptr, hipStream_t st);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t st);
 hipError_t launch_cand_mask(const int32_t* topk, int k_top, const int32_t* frames, int64_t n_frames, int words,
@@ -148,33 +150,36 @@ hipError_t launch_cand_cells(const int32_t* topk, int k_top, const int32_t* fram
                              int32_t* cells, int32_t* keys, hipStream_t st);
 hipError_t launch_pair_columns(const int32_t* order, int64_t n_pairs, int k_top, const int32_t* keys,
                                const int64_t* cf_ptr, int32_t* cf_frame, int32_t* pair_col, hipStream_t st);
-hipError_t launch_cell_sizes(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int64_t* sizes,
-                             int32_t* nchunk, hipStream_t st);
-hipError_t launch_cell_tiles(const int32_t* nchunk, int n_cells, int2* tiles, int64_t* n_tiles, hipStream_t st);
 hipError_t launch_scan64(const int64_t* cnt, int64_t n, int64_t* ptr, hipStream_t st);
 hipError_t launch_nz_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                           int64_t n_frames, int32_t* cnt, hipStream_t st);
+                           int64_t n_frames, int32_t* cnt, int32_t* over, hipStream_t st);
 hipError_t launch_nz_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
                           int64_t n_frames, const int64_t* ptr, uint32_t* nz, hipStream_t st);
-hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int64_t* cell_ptr, const int32_t* cell_rot,
-                              const int64_t* cf_ptr, const int32_t* cf_frame, const int64_t* g_off,
-                              const int64_t* nz_ptr, const uint32_t* nz, const float* A, int64_t ps, float* G,
+
+// ---- candidate E/M steps (cand.hip) ----
+hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* groups, const int64_t* grp_off,
+                              const int64_t* cf_ptr, const int32_t* cf_frame, const int64_t* nz_ptr,
+                              const int32_t* nz_off, int ntab, const uint32_t* nz, const int32_t* cell_rot,
+                              const void* hilo, int64_t plane, const float* scale, int64_t ps, float* G,
                               hipStream_t st);
-hipError_t launch_cand_estep(float* G, const int64_t* g_off, const int32_t* cells, const int32_t* pair_col, int k_top,
-                             int64_t n_frames, const int64_t* cell_ptr, const int32_t* cell_rot, const int64_t* cf_ptr,
-                             const double* log_w, const double* S, const double* b, double* L, int32_t* tj,
-                             int32_t* tk, float* tp, int64_t cap, unsigned long long* count, int32_t* overflow,
+hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
+                             const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
+                             int64_t n_frames, const int32_t* cell_rot, const double* log_w, const double* S,
+                             const double* b, double* L, hipStream_t st);
+hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
+                             const int32_t* cf_frame, const int64_t* nz_ptr, const int32_t* nz_off, int ntab,
+                             const uint32_t* nz, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
+                             double* rho, const double* rho_a, bool accumulate, hipStream_t st);
+hipError_t launch_nz_dot(const int64_t* nz_ptr, const uint32_t* nz, int64_t n_frames, const double* c, double* b,
+                         hipStream_t st);
+hipError_t launch_nz_offsets(const int64_t* nz_ptr, const uint32_t* nz, int64_t n_frames, int ntab, int32_t* nz_off,
                              hipStream_t st);
-hipError_t launch_audit(const void* P, bool bf16, int64_t ldp, int n_rot, int64_t n_audit, const uint32_t* mask_audit,
-                        int words, const int32_t* cell_of, int32_t frame_base, int32_t* tj, int32_t* tk, float* tp,
-                        int64_t cap, unsigned long long* count, int32_t* overflow, double* recall, hipStream_t st);
-hipError_t launch_triple_sort(const int32_t* tj, const int32_t* tk, const float* tp, const unsigned long long* count,
-                              int64_t cap, int n_rot, int32_t* hist, int32_t* cursor, int64_t* ptr, int32_t* tk2,
-                              float* tp2, hipStream_t st);
-hipError_t launch_gather_triples(const int32_t* order, int64_t n, const int32_t* tk, const float* tp, int32_t* tk2,
-                                 float* tp2, hipStream_t st);
-hipError_t launch_sparse_mstep(const int64_t* tptr, const int32_t* tk, const float* tp, const void* Kc, int64_t n_cand,
-                               const void* Ka, bool bf16, int64_t ps, int n_rot, float* Wp, double* rho,
-                               hipStream_t st);
+hipError_t launch_cell_groups(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int32_t* cnt,
+                              int64_t* cg_ptr, int4* groups, int64_t* gsize, int64_t* grp_off, int64_t g_max,
+                              hipStream_t st);
+hipError_t launch_group_tiles(const int4* groups, const int64_t* cg_ptr, int n_cells, const int64_t* cf_ptr,
+                              int32_t* xcd_of, int2* tiles, int64_t* n_tiles, hipStream_t st);
+hipError_t launch_audit_recall(const void* P, int64_t ldp, int n_rot, int64_t n_audit, const uint32_t* mask_audit,
+                               int words, const int32_t* cell_of, double* recall, hipStream_t st);
 
 }  // namespace emc

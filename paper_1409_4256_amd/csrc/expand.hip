@@ -78,8 +78,7 @@ __global__ __launch_bounds__(256) void expand_kernel(const float* __restrict__ m
 // BF16 form: the centred log slice A_ji = log W_ij - c_i is written as two BF16
 // terms with a per-rotation scale, A_ji ~ scale_j (hi_ji + lo_ji), where
 // scale_j = max_i |A_ji|, hi = bf16(A / scale), lo = bf16(A / scale - hi).
-// A first pass finds the row maximum; the second recomputes the slice (and, if
-// A32 is given, also stores A in FP32 for the proposal form's sparse gathers).
+// A first pass finds the row maximum; the second recomputes the slice.
 __global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restrict__ model, int N,
                                                           const float* __restrict__ q,
                                                           const uint8_t* __restrict__ mask,
@@ -87,8 +86,7 @@ __global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restric
                                                           int64_t stride, int64_t plane,
                                                           const double* __restrict__ c,
                                                           __hip_bfloat16* __restrict__ hi_all,
-                                                          double* __restrict__ S, float* __restrict__ scale,
-                                                          float* __restrict__ A32) {
+                                                          double* __restrict__ S, float* __restrict__ scale) {
   __shared__ double red[4];
   __shared__ float redf[4];
   const int j = blockIdx.x;
@@ -115,20 +113,17 @@ __global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restric
   }
   __hip_bfloat16* hi = hi_all + (int64_t)j * stride;
   __hip_bfloat16* lo = hi_all + plane + (int64_t)j * stride;
-  float* a32 = A32 ? A32 + (int64_t)j * stride : nullptr;
   for (int64_t i = threadIdx.x; i < stride; i += 256) {
-    float h = 0.0f, l = 0.0f, af = 0.0f;
+    float h = 0.0f, l = 0.0f;
     if (i < n_pix && mask[i]) {
       const double W = slice_value(model, N, r, q + 3 * i);
-      af = (float)(log(W) - c[i]);
-      const float a = af * inv;
+      const float a = (float)(log(W) - c[i]) * inv;
       const __hip_bfloat16 hb = __float2bfloat16(a);
       h = __bfloat162float(hb);
       l = a - h;
     }
     hi[i] = __float2bfloat16(h);
     lo[i] = __float2bfloat16(l);
-    if (a32) a32[i] = af;
   }
 }
 
@@ -183,10 +178,9 @@ hipError_t launch_expand(const float* model, int N, const float* q, const uint8_
 
 hipError_t launch_expand_bf16(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
                               int n_pix, int64_t stride, int n_rot, const double* c, void* hilo, double* S,
-                              float* scale, float* A32, hipStream_t st) {
+                              float* scale, hipStream_t st) {
   expand_bf16_kernel<<<(unsigned)n_rot, 256, 0, st>>>(model, N, q, mask, quat, n_pix, stride,
-                                                      (int64_t)n_rot * stride, c, (__hip_bfloat16*)hilo, S, scale,
-                                                      A32);
+                                                      (int64_t)n_rot * stride, c, (__hip_bfloat16*)hilo, S, scale);
   return hipGetLastError();
 }
 

@@ -31,7 +31,8 @@ EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride",
            "emc_slices_bytes", "emc_workspace_bytes", "emc_pack_frames", "emc_expand", "emc_loglik",
            "emc_responsibilities", "emc_compress", "emc_finalize", "emc_iterate",
            "emc_cnn_param_count", "emc_cnn_workspace_bytes", "emc_cnn_preprocess", "emc_cnn_forward",
-           "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_targets",
+           "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_topk", "emc_topk_union",
+           "emc_cell_targets",
            "emc_pack_frames_list", "emc_proposal_bytes", "emc_proposal_build", "emc_proposed_workspace_bytes",
            "emc_iterate_proposed")
 
@@ -61,13 +62,15 @@ class Problem(ctypes.Structure):
 class Proposal(ctypes.Structure):
     _fields_ = [
         ("n_cells", ctypes.c_int32), ("k_top", ctypes.c_int32), ("n_cand", ctypes.c_int32),
-        ("n_audit", ctypes.c_int32), ("words", ctypes.c_int32), ("reserved", ctypes.c_int32),
-        ("n_tiles", ctypes.c_int64), ("n_g", ctypes.c_int64), ("n_nz", ctypes.c_int64),
+        ("n_audit", ctypes.c_int32), ("words", ctypes.c_int32), ("ntab", ctypes.c_int32),
+        ("n_groups", ctypes.c_int64), ("n_tiles", ctypes.c_int64), ("n_g", ctypes.c_int64),
+        ("n_nz", ctypes.c_int64),
         ("cell_of", ctypes.c_void_p), ("cell_ptr", ctypes.c_void_p), ("cell_rot", ctypes.c_void_p),
         ("cand_frames", ctypes.c_void_p), ("audit_frames", ctypes.c_void_p), ("cand_cells", ctypes.c_void_p),
         ("pair_col", ctypes.c_void_p), ("cf_ptr", ctypes.c_void_p), ("cf_frame", ctypes.c_void_p),
-        ("g_off", ctypes.c_void_p), ("tiles", ctypes.c_void_p), ("mask_audit", ctypes.c_void_p),
-        ("nz_ptr", ctypes.c_void_p), ("nz", ctypes.c_void_p),
+        ("cg_ptr", ctypes.c_void_p), ("groups", ctypes.c_void_p), ("grp_off", ctypes.c_void_p),
+        ("tiles", ctypes.c_void_p), ("mask_audit", ctypes.c_void_p),
+        ("nz_ptr", ctypes.c_void_p), ("nz", ctypes.c_void_p), ("nz_off", ctypes.c_void_p),
     ]
 
 
@@ -112,15 +115,17 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_cnn_adam.argtypes = [i32, _P, _P, _P, _P, i32, ctypes.c_float, _P]
     lib.emc_cnn_adam.restype = st
     lib.emc_cnn_topk.argtypes, lib.emc_cnn_topk.restype = [_P, i64, i32, i32, _P, _P], st
+    lib.emc_cell_topk.argtypes, lib.emc_cell_topk.restype = [_P, i64, i32, i32, _P, _P], st
+    lib.emc_topk_union.argtypes, lib.emc_topk_union.restype = [_P, i32, _P, i32, i64, i32, _P, _P], st
     lib.emc_cell_targets.argtypes, lib.emc_cell_targets.restype = [_PB, _P, _P, _P, i32, _P, _P], st
     _PP = ctypes.POINTER(Proposal)
     lib.emc_pack_frames_list.argtypes, lib.emc_pack_frames_list.restype = [_PB, _P, _P, _P, _P], st
     lib.emc_proposal_bytes.argtypes, lib.emc_proposal_bytes.restype = [_PB, i32, i32, i32, i64, szp], st
     lib.emc_proposal_build.argtypes = [_PB, _P, i32, _P, i32, _P, i32, _P, i64, _P, ctypes.c_size_t, _PP, _P]
     lib.emc_proposal_build.restype = st
-    lib.emc_proposed_workspace_bytes.argtypes = [_PB, _PP, i64, szp]
+    lib.emc_proposed_workspace_bytes.argtypes = [_PB, _PP, szp]
     lib.emc_proposed_workspace_bytes.restype = st
-    lib.emc_iterate_proposed.argtypes = [_PB, _PP, _P, _P, _P, _P, _P, _P, _P, i64, _P, ctypes.c_size_t, _P]
+    lib.emc_iterate_proposed.argtypes = [_PB, _PP, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.emc_iterate_proposed.restype = st
     _lib = lib
     return lib
@@ -418,6 +423,21 @@ def emc_cnn_topk(logits, rows, n_cells, k, out, stream=None):
                                int(k), _ptr(out, torch.int32, rows * k, "out"), _stream(stream)))
 
 
+def emc_cell_topk(T, rows, n_cells, k, out, stream=None):
+    import torch
+
+    _check(load().emc_cell_topk(_ptr(T, torch.float32, rows * n_cells, "T"), int(rows), int(n_cells), int(k),
+                                _ptr(out, torch.int32, rows * k, "out"), _stream(stream)))
+
+
+def emc_topk_union(a, ka, b, kb, rows, n_cells, out, stream=None):
+    import torch
+
+    _check(load().emc_topk_union(_ptr(a, torch.int32, rows * ka, "a") if ka else None, int(ka),
+                                 _ptr(b, torch.int32, rows * kb, "b") if kb else None, int(kb), int(rows),
+                                 int(n_cells), _ptr(out, torch.int32, rows * (ka + kb), "out"), _stream(stream)))
+
+
 def emc_cell_targets(geo: Geometry, P, cell_ptr, cell_rot, n_cells, T, stream=None):
     import torch
 
@@ -462,26 +482,23 @@ def emc_proposal_build(geo: Geometry, coarse, n_cells, topk, k_top, audit, count
     return plan
 
 
-def emc_proposed_workspace_bytes(geo: Geometry, plan: Proposal, triple_cap: int) -> int:
+def emc_proposed_workspace_bytes(geo: Geometry, plan: Proposal) -> int:
     n = ctypes.c_size_t(0)
-    _check(load().emc_proposed_workspace_bytes(ctypes.byref(geo.pb), ctypes.byref(plan), int(triple_cap),
-                                               ctypes.byref(n)))
+    _check(load().emc_proposed_workspace_bytes(ctypes.byref(geo.pb), ctypes.byref(plan), ctypes.byref(n)))
     return int(n.value)
 
 
-def emc_iterate_proposed(geo: Geometry, plan: Proposal, K_cand, K_audit, model_in, model_out, loglik, recall_mean,
-                         status, triple_cap, ws, stream=None):
+def emc_iterate_proposed(geo: Geometry, plan: Proposal, K_audit, model_in, model_out, loglik, recall_mean, ws,
+                         stream=None):
     import torch
 
     M = geo.grid_n ** 3
     _check(load().emc_iterate_proposed(
         ctypes.byref(geo.pb), ctypes.byref(plan),
-        _ptr(K_cand, None, None, "K_cand") if plan.n_cand else None,
         _ptr(K_audit, None, None, "K_audit") if plan.n_audit else None,
         _ptr(model_in, torch.float32, M, "model_in"), _ptr(model_out, torch.float32, M, "model_out"),
         _ptr(loglik, torch.float64, 1, "loglik"), _ptr(recall_mean, torch.float64, 1, "recall_mean"),
-        _ptr(status, torch.int32, 1, "status"), int(triple_cap),
-        _ptr(ws, torch.uint8, emc_proposed_workspace_bytes(geo, plan, triple_cap), "ws"),
+        _ptr(ws, torch.uint8, emc_proposed_workspace_bytes(geo, plan), "ws"),
         ctypes.c_size_t(ws.numel()), _stream(stream)))
 
 

@@ -127,9 +127,9 @@ class Network:
 
 
 class ProposedIteration:
-    """Plan + packed frame lists + workspace for emc_iterate_proposed."""
+    """Plan + packed audited frames + workspace for emc_iterate_proposed."""
 
-    def __init__(self, geo16: E.Geometry, counts_dev, coarse, n_cells, topk, k_top, audit, triple_cap, nz_cap=None):
+    def __init__(self, geo16: E.Geometry, counts_dev, coarse, n_cells, topk, k_top, audit, nz_cap=None):
         self.geo = geo16
         if nz_cap is None:  # non-zero pixels of all frames (an upper bound of the candidate frames')
             nz_cap = int((counts_dev.view(torch.int16) != 0).sum().item())
@@ -141,23 +141,26 @@ class ProposedIteration:
         p = self.plan
         self.cand_frames = E.plan_array(self.buf, p.cand_frames, p.n_cand, torch.int32)
         self.audit_frames = E.plan_array(self.buf, p.audit_frames, p.n_audit, torch.int32)
-        gc, ga = geo16.with_frames(p.n_cand), geo16.with_frames(p.n_audit)
-        self.Kc, self.Ka = E.frames_tensor(gc), E.frames_tensor(ga)
-        if p.n_cand:
-            E.emc_pack_frames_list(gc, counts_dev, self.cand_frames, self.Kc)
+        ga = geo16.with_frames(p.n_audit)
+        self.Ka = E.frames_tensor(ga)
         if p.n_audit:
             E.emc_pack_frames_list(ga, counts_dev, self.audit_frames, self.Ka)
-        self.cap = int(triple_cap)
-        self.ws = torch.empty(E.emc_proposed_workspace_bytes(geo16, p, self.cap), dtype=torch.uint8, device="cuda")
+        self.ws = torch.empty(E.emc_proposed_workspace_bytes(geo16, p), dtype=torch.uint8, device="cuda")
         self.loglik = torch.empty(1, dtype=torch.float64, device="cuda")
         self.recall = torch.empty(1, dtype=torch.float64, device="cuda")
-        self.status = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    def candidate_pairs(self) -> int:
+        """(rotation, frame) pairs the candidate E-step evaluates (synchronises)."""
+        p = self.plan
+        groups = E.plan_array(self.buf, p.groups, 4 * p.n_groups, torch.int32).view(-1, 4).long()
+        cf_ptr = E.plan_array(self.buf, p.cf_ptr, p.n_cells + 1, torch.int64)
+        F = cf_ptr[1:] - cf_ptr[:-1]
+        return int((groups[:, 2] * F[groups[:, 0]]).sum().item())
 
     def step(self, model_in, model_out):
-        E.emc_iterate_proposed(self.geo, self.plan, self.Kc, self.Ka, model_in, model_out, self.loglik,
-                               self.recall, self.status, self.cap, self.ws)
+        E.emc_iterate_proposed(self.geo, self.plan, self.Ka, model_in, model_out, self.loglik, self.recall, self.ws)
 
     def accepted(self) -> bool:
         """The audit's verdict on the last step (synchronises)."""
         rec = self.recall.item()
-        return self.status.item() == 0 and (math.isnan(rec) or rec >= RECALL_MIN)
+        return math.isnan(rec) or rec >= RECALL_MIN

@@ -111,3 +111,59 @@ def test_python_binding_raises_emc_error(lib):
     with pytest.raises(emc.EmcError) as e:
         emc._check(emc.EMC_ERR_INVALID_ARG)
     assert e.value.status == emc.EMC_ERR_INVALID_ARG
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and every field offset of emc_problem and emc_proposal, from the C
+    compiler reading include/emc.h, equal the Python binding's mirrors."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("needs gcc and the ROCm headers")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "emc.h"', "int main(void) {"]
+    for cname, cls in (("emc_problem", emc.Problem), ("emc_proposal", emc.Proposal)):
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for cname, cls in (("emc_problem", emc.Problem), ("emc_proposal", emc.Proposal)):
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, f
+
+
+def test_proposal_argument_checks(lib):
+    pb = _pb(precision=1)
+    n = ctypes.c_size_t()
+    assert lib.emc_proposal_bytes(ctypes.byref(pb), 2000, 256, 20, 1 << 20, ctypes.byref(n)) == emc.EMC_OK
+    assert n.value > 0
+    assert lib.emc_proposal_bytes(ctypes.byref(pb), 2000, 257, 20, 1 << 20, ctypes.byref(n)) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_proposal_bytes(ctypes.byref(pb), 0, 8, 20, 1 << 20, ctypes.byref(n)) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_proposal_bytes(ctypes.byref(pb), 2000, 8, 2000, 1 << 20, ctypes.byref(n)) == emc.EMC_ERR_INVALID_ARG
+    a = ctypes.c_void_p(1 << 20)
+    assert lib.emc_topk_union(a, 300, a, 300, 10, 2000, a, None) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_topk_union(a, 0, a, 0, 10, 2000, a, None) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_topk_union(a, 8, a, 8, 0, 2000, a, None) == emc.EMC_OK       # no rows: nothing launched
+    assert lib.emc_cell_topk(a, 10, 100, 101, a, None) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_cell_topk(a, 0, 100, 10, a, None) == emc.EMC_OK
+    # an inconsistent plan is refused before anything runs
+    plan = emc.Proposal()
+    assert lib.emc_proposed_workspace_bytes(ctypes.byref(pb), ctypes.byref(plan), ctypes.byref(n)) == \
+        emc.EMC_ERR_INVALID_ARG
+
+
+def test_proposal_plan_bytes_config2(lib):
+    """Plan buffer of the 128^3 workload with 128-entry lists stays modest."""
+    pb = _pb(grid_n=128, n_pix=16384, n_rot=25000, n_data=100000, precision=1)
+    n = ctypes.c_size_t()
+    assert lib.emc_proposal_bytes(ctypes.byref(pb), 2000, 128, 2000, 200_000_000, ctypes.byref(n)) == emc.EMC_OK
+    assert n.value < 3 * 2 ** 30

@@ -1,8 +1,9 @@
 """Learned-proposal iteration on the GPU vs the FP64 oracle of the same restricted
 E-step (implementation error) and vs the full-search oracle (approximation error).
 
-Proposals here come from random logits: the restricted E-step, the plan and the
-audit are checked independently of how good the network is."""
+Proposals here come from random logits (optionally merged with a second random
+list and cut to ragged lengths): the restricted E-step, the plan and the audit
+are checked independently of how good the network is."""
 import numpy as np
 import pytest
 
@@ -14,7 +15,24 @@ from paper_1409_4256_amd import emc as E
 pytestmark = pytest.mark.gpu
 
 
-def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=300.0):
+def _lists(rng, ndata, n_cells, k_top, k_extra, ragged):
+    """Proposal lists [ndata][k_top + k_extra]: top-k_top of random logits, then the
+    cells of a second random top-k_extra list not already present, -1 padding; with
+    `ragged`, every row keeps only a random-length prefix of its valid entries."""
+    logits = rng.standard_normal((ndata, n_cells))
+    out = np.full((ndata, k_top + k_extra), -1, np.int32)
+    for k in range(ndata):
+        row = list(C.topk_cells(logits[k:k + 1], k_top)[0])
+        if k_extra:
+            other = C.topk_cells(rng.standard_normal((1, n_cells)), k_extra)[0]
+            row += [c for c in other if c not in row]
+        if ragged:
+            row = row[:rng.integers(1, len(row) + 1)]
+        out[k, :len(row)] = row
+    return out
+
+
+def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=300.0, k_extra=0, ragged=False):
     import torch
 
     from gpu_helpers import geometry, upload_counts
@@ -24,41 +42,37 @@ def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=30
     quat = np.asarray(t["quat"], np.float32).astype(np.float64)
     rng = np.random.default_rng(100 + seed)
     coarse = np.asarray(shoemake_quaternions(rng, n_cells), np.float32)
-    logits = rng.standard_normal((ndata, n_cells)).astype(np.float32)
+    lists = _lists(rng, ndata, n_cells, k_top, k_extra, ragged)
+    kk = lists.shape[1]
     audit = np.sort(rng.choice(ndata, n_audit, replace=False)).astype(np.int32)
     geo = geometry(N, q, t["mask"], quat, t["log_w"], ndata, E.EMC_PREC_BF16)
     dev = "cuda"
-    topk = torch.empty(ndata * k_top, dtype=torch.int32, device=dev)
-    E.emc_cnn_topk(torch.as_tensor(logits, device=dev), ndata, n_cells, k_top, topk)
+    topk = torch.as_tensor(lists.reshape(-1), device=dev)
     counts = upload_counts(t["counts"])
     nz_cap = int((t["counts"] != 0).sum()) + 1
-    buf = torch.empty(E.emc_proposal_bytes(geo, n_cells, k_top, n_audit, nz_cap), dtype=torch.uint8, device=dev)
-    plan = E.emc_proposal_build(geo, torch.as_tensor(coarse, device=dev), n_cells, topk, k_top,
+    print(f"[proposal] seed {seed} N {N} npx {npx} nrot {nrot} ndata {ndata} cells {n_cells} list {kk} "
+          f"audit {n_audit}", flush=True)
+    buf = torch.empty(E.emc_proposal_bytes(geo, n_cells, kk, n_audit, nz_cap), dtype=torch.uint8, device=dev)
+    plan = E.emc_proposal_build(geo, torch.as_tensor(coarse, device=dev), n_cells, topk, kk,
                                 torch.as_tensor(audit, device=dev) if n_audit else None, counts, nz_cap, buf)
     cand_frames = E.plan_array(buf, plan.cand_frames, plan.n_cand, torch.int32)
     audit_frames = E.plan_array(buf, plan.audit_frames, plan.n_audit, torch.int32)
-    gc, ga = geo.with_frames(plan.n_cand), geo.with_frames(plan.n_audit)
-    Kc, Ka = E.frames_tensor(gc), E.frames_tensor(ga)
-    if plan.n_cand:
-        E.emc_pack_frames_list(gc, counts, cand_frames, Kc)
+    ga = geo.with_frames(plan.n_audit)
+    Ka = E.frames_tensor(ga)
     if plan.n_audit:
         E.emc_pack_frames_list(ga, counts, audit_frames, Ka)
-    cap = ndata * nrot  # every (rotation, frame) pair may be significant in these flat posteriors
-    ws = torch.empty(E.emc_proposed_workspace_bytes(geo, plan, cap), dtype=torch.uint8, device=dev)
+    ws = torch.empty(E.emc_proposed_workspace_bytes(geo, plan), dtype=torch.uint8, device=dev)
     m_in = torch.as_tensor(t["model"], dtype=torch.float32, device=dev)
     m_out = torch.empty_like(m_in)
     ll = torch.empty(1, dtype=torch.float64, device=dev)
     rec = torch.empty(1, dtype=torch.float64, device=dev)
-    status = torch.empty(1, dtype=torch.int32, device=dev)
-    E.emc_iterate_proposed(geo, plan, Kc, Ka, m_in, m_out, ll, rec, status, cap, ws)
+    E.emc_iterate_proposed(geo, plan, Ka, m_in, m_out, ll, rec, ws)
     torch.cuda.synchronize()
     # oracle: the same candidate sets
-    cell_of = C.assign_cells(coarse.astype(np.float64), coarse.astype(np.float64)) if False else \
-        C.assign_cells(quat, coarse.astype(np.float64))
-    top = C.topk_cells(logits.astype(np.float64), k_top)
+    cell_of = C.assign_cells(quat, coarse.astype(np.float64))
     cand = np.zeros((nrot, ndata), bool)
     for k in range(ndata):
-        cand[:, k] = np.isin(cell_of, top[k])
+        cand[:, k] = np.isin(cell_of, lists[k][lists[k] >= 0])
     cand_a = cand.copy()
     cand_a[:, audit] = True
     model = m_in.double().cpu().numpy()
@@ -66,31 +80,49 @@ def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=30
     full = O.iterate(model, t["counts"], q, t["mask"], quat, t["log_w"], N)
     recall_ref = O.proposal_recall(full["P"][:, audit], cand[:, audit]).mean() if n_audit else float("nan")
     return dict(plan=plan, buf=buf, cand_frames=cand_frames.cpu().numpy(), audit_frames=audit_frames.cpu().numpy(),
-                model=m_out.double().cpu().numpy(), loglik=ll.item(), recall=rec.item(), status=status.item(),
-                oracle=o, full=full, recall_ref=recall_ref, audit=audit, cell_of=cell_of, top=top,
-                geo=geo)
+                model=m_out.double().cpu().numpy(), loglik=ll.item(), recall=rec.item(),
+                oracle=o, full=full, recall_ref=recall_ref, audit=audit, cell_of=cell_of, lists=lists, geo=geo)
 
 
-@pytest.mark.parametrize("seed,N,npx,nrot,ndata,n_cells,k_top,n_audit",
-                         [(0, 20, 300, 700, 600, 40, 8, 12), (1, 16, 200, 400, 300, 17, 3, 0),
-                          (2, 24, 400, 1100, 520, 64, 20, 30)])
-def test_proposed_iteration_matches_restricted_oracle(gpu_lib, seed, N, npx, nrot, ndata, n_cells, k_top, n_audit):
+def _check_restricted(r, ndata, tag):
     from gpu_helpers import rel_l2
 
-    r = _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit)
-    assert r["status"] == 0
     # plan: every frame exactly once, audited frames apart
     got = np.sort(np.concatenate([r["cand_frames"], r["audit_frames"]]))
     np.testing.assert_array_equal(got, np.arange(ndata))
     np.testing.assert_array_equal(np.sort(r["audit_frames"]), r["audit"])
     # implementation error vs the FP64 oracle of the same restricted E-step (BF16 form)
     err = rel_l2(r["model"], r["oracle"]["model"])
-    print(f"\n[proposal seed{seed}] model rel L2 vs restricted oracle {err:.2e}, "
-          f"vs full search {rel_l2(r['model'], r['full']['model']):.2e}")
+    print(f"\n[proposal {tag}] model rel L2 vs restricted oracle {err:.2e}, "
+          f"vs full search {rel_l2(r['model'], r['full']['model']):.2e}, loglik {r['loglik']:.6f} "
+          f"(oracle {r['oracle']['loglik']:.6f})")
     assert err <= 1e-3
     assert abs(r["loglik"] - r["oracle"]["loglik"]) <= 1e-3 * abs(r["oracle"]["loglik"])
-    if n_audit:
+    if len(r["audit"]):
         assert abs(r["recall"] - r["recall_ref"]) <= 1e-3, (r["recall"], r["recall_ref"])
+
+
+@pytest.mark.parametrize("seed,N,npx,nrot,ndata,n_cells,k_top,n_audit",
+                         [(0, 20, 300, 700, 600, 40, 8, 12), (1, 16, 200, 400, 300, 17, 3, 0),
+                          (2, 24, 400, 1100, 520, 64, 20, 30)])
+def test_proposed_iteration_matches_restricted_oracle(gpu_lib, seed, N, npx, nrot, ndata, n_cells, k_top, n_audit):
+    r = _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit)
+    _check_restricted(r, ndata, f"seed{seed}")
+
+
+def test_union_lists_ragged_and_multi_group_cells(gpu_lib):
+    """Lists merged from two proposals with -1 padding and ragged lengths; 10 cells
+    over 1000 rotations put ~100 rotations (four groups of up to 32) in each cell."""
+    r = _run(5, 20, 300, 1000, 500, 10, 3, 20, k_extra=3, ragged=True)
+    _check_restricted(r, 500, "union/ragged/multi-group")
+    assert r["plan"].n_groups > r["plan"].n_cells
+
+
+def test_dense_bands(gpu_lib):
+    """~3000 photons over 300 pixels: most pixels of a 128-pixel band are non-zero in
+    every frame (more entries per band than a wave has lanes)."""
+    r = _run(6, 20, 300, 600, 400, 24, 6, 16, photons=3000.0)
+    _check_restricted(r, 400, "dense bands")
 
 
 def test_proposal_with_every_cell_is_full_search(gpu_lib):
@@ -98,6 +130,56 @@ def test_proposal_with_every_cell_is_full_search(gpu_lib):
     from gpu_helpers import rel_l2
 
     r = _run(4, 18, 250, 500, 400, 12, 12, 10)
-    assert r["status"] == 0
     assert rel_l2(r["model"], r["full"]["model"]) <= 1e-3
     assert abs(r["recall"] - 1.0) <= 4e-3   # sum of BF16-rounded responsibilities
+
+
+def test_counts_beyond_bf16_are_refused(gpu_lib):
+    import torch
+
+    from gpu_helpers import geometry, upload_counts
+
+    t = tiny_problem(7, grid_n=16, n_pix=200, n_rot=300, n_data=50, photons=200.0)
+    counts = t["counts"].copy()
+    counts[3, np.flatnonzero(t["mask"])[0]] = 300
+    geo = geometry(16, np.asarray(t["q"], np.float64), t["mask"], np.asarray(t["quat"], np.float64), t["log_w"], 50,
+                   E.EMC_PREC_BF16)
+    rng = np.random.default_rng(7)
+    coarse = torch.as_tensor(np.asarray(shoemake_quaternions(rng, 8), np.float32), device="cuda")
+    topk = torch.as_tensor(_lists(rng, 50, 8, 2, 0, False).reshape(-1), device="cuda")
+    nz_cap = int((counts != 0).sum()) + 1
+    buf = torch.empty(E.emc_proposal_bytes(geo, 8, 2, 0, nz_cap), dtype=torch.uint8, device="cuda")
+    with pytest.raises(E.EmcError) as e:
+        E.emc_proposal_build(geo, coarse, 8, topk, 2, None, upload_counts(counts), nz_cap, buf)
+    assert e.value.status == E.EMC_ERR_RANGE
+
+
+def test_cell_topk_and_union_match_numpy(gpu_lib):
+    import torch
+
+    rng = np.random.default_rng(11)
+    rows, n_cells, k = 300, 150, 20
+    T = rng.random((rows, n_cells)).astype(np.float32)
+    T[T < 0.8] = 0.0                       # ~30 positive cells per row, some rows fewer than k
+    T[5] = 0.0                             # a row with none
+    T[7, :40] = 0.5                        # ties: lower index first
+    out = torch.empty(rows * k, dtype=torch.int32, device="cuda")
+    E.emc_cell_topk(torch.as_tensor(T, device="cuda"), rows, n_cells, k, out)
+    got = out.view(rows, k).cpu().numpy()
+    for r in range(rows):
+        pos = np.flatnonzero(T[r] > 0)
+        ref = pos[np.argsort(-T[r, pos], kind="stable")][:k]
+        np.testing.assert_array_equal(got[r, :len(ref)], ref)
+        assert (got[r, len(ref):] == -1).all()
+    a = rng.integers(-1, n_cells, size=(rows, 12)).astype(np.int32)
+    b = rng.integers(-1, n_cells, size=(rows, 70)).astype(np.int32)   # more than one wave of entries
+    uo = torch.empty(rows * 82, dtype=torch.int32, device="cuda")
+    E.emc_topk_union(torch.as_tensor(a, device="cuda"), 12, torch.as_tensor(b, device="cuda"), 70, rows, n_cells, uo)
+    got = uo.view(rows, 82).cpu().numpy()
+    for r in range(rows):
+        ref = []
+        for c in list(a[r]) + list(b[r]):
+            if 0 <= c < n_cells and c not in ref:
+                ref.append(int(c))
+        np.testing.assert_array_equal(got[r, :len(ref)], ref)
+        assert (got[r, len(ref):] == -1).all()
