@@ -745,7 +745,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   int32_t* xcd = (int32_t*)(b + L.xcd);
   int32_t* cnt = (int32_t*)(b + L.cnt);
   int32_t* nzcnt = (int32_t*)(b + L.nzcnt);
-  int64_t* scal = (int64_t*)(b + L.scalars);  // [0] n_tiles, [1] count range flag (int32)
+  int64_t* scal = (int64_t*)(b + L.scalars);  // [0] n_tiles, [1] flags (int32): 1 count range, 2 repeated cell
   int32_t* over = (int32_t*)(scal + 1);
   // 1. coarse cell of every fine rotation; rotations grouped by cell
   HIP_TRY(launch_assign_cells(pb->quat, pb->n_rot, coarse, n_cells, P.cell_of, st), "assign cells");
@@ -762,17 +762,19 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
     emc::copy_i32_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(order + n_cand, n_audit, P.audit_frames);
   HIP_TRY(launch_cand_mask(topk, k_top, P.audit_frames, n_audit, w, P.mask_audit, st), "audit masks");
   // 3. (frame, proposed cell) pairs grouped by cell: each cell's frame list
+  HIP_TRY(launch_fill_i32(over, 1, 0, st), "flags");
   HIP_TRY(launch_cand_cells(topk, k_top, P.cand_frames, n_cand, n_cells, P.cand_cells, keys, st), "candidate cells");
+  HIP_TRY(launch_dup_check(P.cand_cells, k_top, n_cand, n_cells, over, st), "repeated cells");
   HIP_TRY(launch_counting_sort(keys, n_pairs, n_cells + 1, hist, cursor, P.cf_ptr, order, nullptr, st), "sort pairs");
   HIP_TRY(launch_pair_columns(order, n_pairs, k_top, keys, P.cf_ptr, P.cf_frame, P.pair_col, st), "pair columns");
   // 4. groups of up to 32 rotations per cell, their storage and the log-likelihood tiles
   HIP_TRY(launch_cell_groups(P.cell_ptr, P.cf_ptr, n_cells, cnt, P.cg_ptr, (int4*)P.groups, gsize, P.grp_off, g_max,
                              st),
           "groups");
-  HIP_TRY(launch_group_tiles((const int4*)P.groups, P.cg_ptr, n_cells, P.cf_ptr, xcd, (int2*)P.tiles, scal, st),
+  HIP_TRY(launch_group_tiles((const int4*)P.groups, P.cg_ptr, n_cells, P.cf_ptr, xcd, (int2*)P.tiles,
+                             tile_cap(g_max, n_cand), scal, st),
           "tiles");
   // 5. sparse frames (non-zero pixels) of the candidate frames
-  HIP_TRY(launch_fill_i32(over, 1, 0, st), "range flag");
   HIP_TRY(launch_nz_count(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, nzcnt, over, st), "nz count");
   HIP_TRY(launch_scan(nzcnt, n_cand, P.nz_ptr, st), "nz offsets");
   int64_t host[5] = {0, 0, 0, 0, 0};
@@ -781,7 +783,10 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   HIP_TRY(hipMemcpyAsync(&host[3], P.grp_off + g_max, 8, hipMemcpyDeviceToHost, st), "read n_g");
   HIP_TRY(hipMemcpyAsync(&host[4], P.nz_ptr + n_cand, 8, hipMemcpyDeviceToHost, st), "read n_nz");
   HIP_TRY(hipStreamSynchronize(st), "proposal build sync");
-  if ((int32_t)host[1] != 0) return fail(EMC_ERR_RANGE, "a photon count exceeds 256, which BF16 cannot hold exactly");
+  const int32_t flags = (int32_t)host[1];
+  if (flags & 2) return fail(EMC_ERR_INVALID_ARG, "a frame lists the same cell more than once");
+  if (host[0] < 0) return fail(EMC_ERR_INVALID_ARG, "inconsistent proposal lists");
+  if (flags & 1) return fail(EMC_ERR_RANGE, "a photon count exceeds 256, which BF16 cannot hold exactly");
   if (host[4] > nz_cap) return fail(EMC_ERR_WORKSPACE, "frames have %lld non-zero pixels, nz_cap is %lld",
                                     (long long)host[4], (long long)nz_cap);
   HIP_TRY(launch_nz_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.nz_ptr, P.nz, st), "nz fill");

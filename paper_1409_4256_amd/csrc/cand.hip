@@ -414,7 +414,7 @@ __global__ void cell_group_fill_kernel(const int64_t* __restrict__ cell_ptr, con
 // list's end are (-1, 0).  Single thread.
 __global__ void group_tiles_kernel(const int4* __restrict__ groups, const int64_t* __restrict__ cg_ptr, int n_cells,
                                    const int64_t* __restrict__ cf_ptr, int32_t* __restrict__ xcd_of,
-                                   int2* __restrict__ tiles, int64_t* __restrict__ n_tiles_out) {
+                                   int2* __restrict__ tiles, int64_t cap, int64_t* __restrict__ n_tiles_out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int64_t n_groups = cg_ptr[n_cells];
   int64_t len[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -428,6 +428,10 @@ __global__ void group_tiles_kernel(const int4* __restrict__ groups, const int64_
   }
   int64_t q_max = 0;
   for (int x = 0; x < 8; ++x) q_max = len[x] > q_max ? len[x] : q_max;
+  if (8 * q_max > cap) {  // only with repeated cells in a frame's list: reported, nothing written
+    *n_tiles_out = -1;
+    return;
+  }
   int64_t q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t g = 0; g < n_groups; ++g) {
     const int c = groups[g].x;
@@ -528,8 +532,8 @@ hipError_t launch_cell_groups(const int64_t* cell_ptr, const int64_t* cf_ptr, in
 }
 
 hipError_t launch_group_tiles(const int4* groups, const int64_t* cg_ptr, int n_cells, const int64_t* cf_ptr,
-                              int32_t* xcd_of, int2* tiles, int64_t* n_tiles, hipStream_t st) {
-  group_tiles_kernel<<<1, 64, 0, st>>>(groups, cg_ptr, n_cells, cf_ptr, xcd_of, tiles, n_tiles);
+                              int32_t* xcd_of, int2* tiles, int64_t cap, int64_t* n_tiles, hipStream_t st) {
+  group_tiles_kernel<<<1, 64, 0, st>>>(groups, cg_ptr, n_cells, cf_ptr, xcd_of, tiles, cap, n_tiles);
   return hipGetLastError();
 }
 

@@ -178,7 +178,9 @@ hipError_t launch_cell_groups(const int64_t* cell_ptr, const int64_t* cf_ptr, in
                               int64_t* cg_ptr, int4* groups, int64_t* gsize, int64_t* grp_off, int64_t g_max,
                               hipStream_t st);
 hipError_t launch_group_tiles(const int4* groups, const int64_t* cg_ptr, int n_cells, const int64_t* cf_ptr,
-                              int32_t* xcd_of, int2* tiles, int64_t* n_tiles, hipStream_t st);
+                              int32_t* xcd_of, int2* tiles, int64_t cap, int64_t* n_tiles, hipStream_t st);
+hipError_t launch_dup_check(const int32_t* cells, int k_top, int64_t n_frames, int n_cells, int32_t* flag,
+                            hipStream_t st);
 hipError_t launch_audit_recall(const void* P, int64_t ldp, int n_rot, int64_t n_audit, const uint32_t* mask_audit,
                                int words, const int32_t* cell_of, double* recall, hipStream_t st);
 

@@ -178,6 +178,33 @@ __global__ void cand_cells_kernel(const int32_t* __restrict__ topk, int k_top, c
   keys[e] = c < 0 ? n_cells : c;  // invalid picks sort after every cell
 }
 
+// a cell listed twice by one frame sets bit 1 of *flag; one wave per frame, the
+// frame's cells marked in an LDS bitmask in list order
+__global__ __launch_bounds__(256) void dup_check_kernel(const int32_t* __restrict__ cells, int k_top, int64_t n_frames,
+                                                        int n_cells, int32_t* __restrict__ flag) {
+  extern __shared__ uint32_t bits[];  // [4 waves][words]
+  const int words = (n_cells + 31) >> 5;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t f = (int64_t)blockIdx.x * 4 + wave;
+  if (f >= n_frames) return;  // uniform per wave; no barrier below
+  uint32_t* m = bits + wave * words;
+  for (int w = lane; w < words; w += 64) m[w] = 0u;
+  bool dup = false;
+  for (int t0 = 0; t0 < k_top; t0 += 64) {
+    const int t = t0 + lane;
+    const int c = t < k_top ? cells[f * k_top + t] : -1;  // entries are -1 or in [0, n_cells)
+    for (int l = 0; l < 64; ++l) {
+      const int cl = __shfl(c, l, 64);
+      if (cl < 0) continue;
+      const bool seen = (m[cl >> 5] >> (cl & 31)) & 1u;
+      if (lane == l) dup |= seen;
+      if (lane == 0) m[cl >> 5] |= 1u << (cl & 31);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if (__ballot(dup) != 0ull && lane == 0) atomicOr(flag, 2);
+}
+
 // pairs sorted by cell (order = pair indices): frame of each pair in cell order and
 // the column of each pair inside its cell's frame list
 __global__ void pair_columns_kernel(const int32_t* __restrict__ order, int64_t n_pairs, int k_top,
@@ -314,6 +341,14 @@ hipError_t launch_cand_cells(const int32_t* topk, int k_top, const int32_t* fram
   const int64_t n = n_frames * k_top;
   if (n > 0) cand_cells_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(topk, k_top, frames, n_frames, n_cells,
                                                                              cells, keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_dup_check(const int32_t* cells, int k_top, int64_t n_frames, int n_cells, int32_t* flag,
+                            hipStream_t st) {
+  if (n_frames <= 0) return hipSuccess;
+  const size_t shm = (size_t)4 * ((n_cells + 31) / 32) * sizeof(uint32_t);
+  dup_check_kernel<<<(unsigned)((n_frames + 3) / 4), 256, shm, st>>>(cells, k_top, n_frames, n_cells, flag);
   return hipGetLastError();
 }
 
