@@ -298,11 +298,11 @@ typedef struct emc_proposal {
   int32_t n_cand;         /* frames searched over their candidates                  */
   int32_t n_audit;        /* frames searched in full                                */
   int32_t words;          /* ceil(n_cells / 32): words of a cell bitmask            */
-  int32_t ntab;           /* entries per frame of nz_off: n_pix stride / 128 + 1    */
+  int32_t ntab;           /* entries per frame of band_chunk: n_pix stride / 128 + 1 */
   int64_t n_groups;       /* rotation groups                                        */
   int64_t n_tiles;        /* workgroups of the candidate log-likelihood (x 8)       */
   int64_t n_g;            /* elements of G (float) and P (bf16)                     */
-  int64_t n_nz;           /* non-zero pixels of the candidate frames                */
+  int64_t n_chunks;       /* 16-byte chunks of the candidate frames' band format    */
   int32_t* cell_of;       /* [n_rot] coarse cell of each rotation (max |<q, q_c>|)  */
   int64_t* cell_ptr;      /* [n_cells + 1] rotations of cell c: cell_rot[ptr[c]..)  */
   int32_t* cell_rot;      /* [n_rot]                                                */
@@ -317,12 +317,15 @@ typedef struct emc_proposal {
   int64_t* grp_off;       /* [n_groups + 1] element offset of each group's storage   */
   void* tiles;            /* [n_tiles] int32 x 2: group, first frame; (-1, 0) padding */
   uint32_t* mask_audit;   /* [n_audit][words] proposed cells of the audited frames  */
-  int64_t* nz_ptr;        /* [n_cand + 1] non-zero pixels of candidate frame f:     */
-  uint32_t* nz;           /*   nz[nz_ptr[f]..) = (pixel << 16) | count, ascending    */
-  int32_t* nz_off;        /* [n_cand][ntab] entries of frame f with pixel < 128 t    */
+  int64_t* chunk_ptr;     /* [n_cand + 1] first chunk of candidate frame f          */
+  void* chunks;           /* 16-byte chunks of 8 uint16 words: for every 128-pixel
+                             band b, the frame's non-zero pixels as
+                             (pixel - 128 b) << 9 | count, ascending, 0xffff pads  */
+  uint16_t* band_chunk;   /* [n_cand][ntab] first chunk of band b (relative), and
+                             at b = ntab - 1 the frame's chunk count               */
 } emc_proposal;
 
-/* Bytes of the plan buffer; nz_cap bounds the non-zero pixels of all frames. */
+/* Bytes of the plan buffer; nz_cap bounds the non-zero pixels of the frames. */
 emc_status emc_proposal_bytes(const emc_problem* pb, int32_t n_cells, int32_t k_top, int32_t n_audit,
                               int64_t nz_cap, size_t* bytes);
 

@@ -589,12 +589,14 @@ int64_t tile_cap(int64_t g_max, int64_t n_cand) {
   return g_max * per + 8 * per + 8;
 }
 int ntab_of(int n_pix) { return (int)(round_up(n_pix, 256) / kBandPx) + 1; }
+// 16-byte chunks of the band format: every non-empty (frame, band) pads at most one
+int64_t chunk_cap(int64_t nz_cap, int64_t n_cand, int n_pix) { return (nz_cap + 7) / 8 + n_cand * (ntab_of(n_pix) - 1); }
 
 // Carving of the plan buffer (capacities known before the build).
 struct PlanLayout {
   size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, cg_ptr,
-      groups, grp_off, tiles, mask_audit, nz_ptr, nz, nz_off, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd,
-      cnt, nzcnt, scalars, total;
+      groups, grp_off, tiles, mask_audit, chunk_ptr, chunks, band_chunk, hist, cursor, keys, order, mark, frame_ptr,
+      gsize, xcd, cnt, chunk_cnt, scalars, total;
 };
 
 PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top, int n_audit, int64_t nz_cap) {
@@ -624,9 +626,9 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.grp_off = take((g_max + 1) * 8);
   L.tiles = take(tile_cap(g_max, n_cand) * 8);
   L.mask_audit = take((int64_t)n_audit * w * 4);
-  L.nz_ptr = take((n_cand + 1) * 8);
-  L.nz = take(nz_cap * 4);
-  L.nz_off = take(n_cand * ntab_of(n_pix) * 4);
+  L.chunk_ptr = take((n_cand + 1) * 8);
+  L.chunks = take(chunk_cap(nz_cap, n_cand, n_pix) * 16);
+  L.band_chunk = take(n_cand * ntab_of(n_pix) * 2);
   L.hist = take(nkeys * 4);
   L.cursor = take(nkeys * 4);
   L.keys = take(std::max<int64_t>(n_pairs, n_data) * 4);
@@ -636,7 +638,7 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.gsize = take(g_max * 8);
   L.xcd = take(g_max * 4);
   L.cnt = take((int64_t)n_cells * 4);
-  L.nzcnt = take(n_cand * 4);
+  L.chunk_cnt = take(n_cand * 4);
   L.scalars = take(64);
   L.total = o;
   return L;
@@ -732,9 +734,9 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   P.grp_off = (int64_t*)(b + L.grp_off);
   P.tiles = (void*)(b + L.tiles);
   P.mask_audit = (uint32_t*)(b + L.mask_audit);
-  P.nz_ptr = (int64_t*)(b + L.nz_ptr);
-  P.nz = (uint32_t*)(b + L.nz);
-  P.nz_off = (int32_t*)(b + L.nz_off);
+  P.chunk_ptr = (int64_t*)(b + L.chunk_ptr);
+  P.chunks = (void*)(b + L.chunks);
+  P.band_chunk = (uint16_t*)(b + L.band_chunk);
   int32_t* hist = (int32_t*)(b + L.hist);
   int32_t* cursor = (int32_t*)(b + L.cursor);
   int32_t* keys = (int32_t*)(b + L.keys);
@@ -744,7 +746,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   int64_t* gsize = (int64_t*)(b + L.gsize);
   int32_t* xcd = (int32_t*)(b + L.xcd);
   int32_t* cnt = (int32_t*)(b + L.cnt);
-  int32_t* nzcnt = (int32_t*)(b + L.nzcnt);
+  int32_t* chunk_cnt = (int32_t*)(b + L.chunk_cnt);
   int64_t* scal = (int64_t*)(b + L.scalars);  // [0] n_tiles, [1] flags (int32): 1 count range, 2 repeated cell
   int32_t* over = (int32_t*)(scal + 1);
   // 1. coarse cell of every fine rotation; rotations grouped by cell
@@ -774,27 +776,31 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   HIP_TRY(launch_group_tiles((const int4*)P.groups, P.cg_ptr, n_cells, P.cf_ptr, xcd, (int2*)P.tiles,
                              tile_cap(g_max, n_cand), scal, st),
           "tiles");
-  // 5. sparse frames (non-zero pixels) of the candidate frames
-  HIP_TRY(launch_nz_count(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, nzcnt, over, st), "nz count");
-  HIP_TRY(launch_scan(nzcnt, n_cand, P.nz_ptr, st), "nz offsets");
+  // 5. the candidate frames in the sparse band format
+  HIP_TRY(launch_band_count(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab, P.band_chunk, chunk_cnt, over,
+                            st),
+          "band count");
+  HIP_TRY(launch_scan(chunk_cnt, n_cand, P.chunk_ptr, st), "chunk offsets");
   int64_t host[5] = {0, 0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(&host[0], scal, 16, hipMemcpyDeviceToHost, st), "read n_tiles");
   HIP_TRY(hipMemcpyAsync(&host[2], P.cg_ptr + n_cells, 8, hipMemcpyDeviceToHost, st), "read n_groups");
   HIP_TRY(hipMemcpyAsync(&host[3], P.grp_off + g_max, 8, hipMemcpyDeviceToHost, st), "read n_g");
-  HIP_TRY(hipMemcpyAsync(&host[4], P.nz_ptr + n_cand, 8, hipMemcpyDeviceToHost, st), "read n_nz");
+  HIP_TRY(hipMemcpyAsync(&host[4], P.chunk_ptr + n_cand, 8, hipMemcpyDeviceToHost, st), "read n_chunks");
   HIP_TRY(hipStreamSynchronize(st), "proposal build sync");
   const int32_t flags = (int32_t)host[1];
   if (flags & 2) return fail(EMC_ERR_INVALID_ARG, "a frame lists the same cell more than once");
   if (host[0] < 0) return fail(EMC_ERR_INVALID_ARG, "inconsistent proposal lists");
   if (flags & 1) return fail(EMC_ERR_RANGE, "a photon count exceeds 256, which BF16 cannot hold exactly");
-  if (host[4] > nz_cap) return fail(EMC_ERR_WORKSPACE, "frames have %lld non-zero pixels, nz_cap is %lld",
-                                    (long long)host[4], (long long)nz_cap);
-  HIP_TRY(launch_nz_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.nz_ptr, P.nz, st), "nz fill");
-  HIP_TRY(launch_nz_offsets(P.nz_ptr, P.nz, n_cand, ntab, P.nz_off, st), "nz band offsets");
+  if (host[4] > chunk_cap(nz_cap, n_cand, pb->n_pix))
+    return fail(EMC_ERR_WORKSPACE, "the candidate frames need %lld chunks, nz_cap %lld allows %lld", (long long)host[4],
+                (long long)nz_cap, (long long)chunk_cap(nz_cap, n_cand, pb->n_pix));
+  HIP_TRY(launch_band_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab, P.band_chunk, P.chunk_ptr,
+                           P.chunks, st),
+          "band fill");
   P.n_tiles = host[0];
   P.n_groups = host[2];
   P.n_g = host[3];
-  P.n_nz = host[4];
+  P.n_chunks = host[4];
   *plan = P;
   return EMC_OK;
 }
@@ -901,10 +907,10 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   CHECK(run_expand(pb, model_in, c, slices, S, scale, st));
   // candidate frames: log-likelihoods per (group, listed frame), E-step over each frame's candidates
   if (nc > 0) {
-    HIP_TRY(launch_nz_dot(plan->nz_ptr, plan->nz, nc, c, b, st), "nz_dot");
+    HIP_TRY(launch_band_dot(plan->chunk_ptr, plan->band_chunk, plan->ntab, plan->chunks, nc, c, b, st), "band dot");
     HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, groups, plan->grp_off, plan->cf_ptr,
-                               plan->cf_frame, plan->nz_ptr, plan->nz_off, plan->ntab, plan->nz, plan->cell_rot,
-                               slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
+                               plan->cf_frame, plan->chunk_ptr, plan->band_chunk, plan->ntab, plan->chunks,
+                               plan->cell_rot, slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
             "candidate loglik");
     HIP_TRY(launch_cand_estep(G, Pc, groups, plan->grp_off, plan->cg_ptr, plan->cand_cells, plan->pair_col,
                               plan->k_top, nc, plan->cell_rot, pb->log_w, S, b, L, st),
@@ -927,8 +933,9 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
     const char* KTa = (const char*)K_audit + (size_t)na * ps * 2;
     HIP_TRY(launch_gemm_bf16_nt(Pa, KTa, Wp, pb->n_rot, ps, dsa, dsa, dsa, ps, st), "audit mstep gemm");
   }
-  HIP_TRY(launch_cand_mstep(groups, plan->grp_off, plan->n_groups, plan->cf_ptr, plan->cf_frame, plan->nz_ptr,
-                            plan->nz_off, plan->ntab, plan->nz, Pc, plan->cell_rot, ps, Wp, rho, rho_a, na > 0, st),
+  HIP_TRY(launch_cand_mstep(groups, plan->grp_off, plan->n_groups, plan->cf_ptr, plan->cf_frame, plan->chunk_ptr,
+                            plan->band_chunk, plan->ntab, plan->chunks, Pc, plan->cell_rot, ps, Wp, rho, rho_a, na > 0,
+                            st),
           "candidate mstep");
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
   HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");

@@ -8,10 +8,14 @@
 // and, after each frame's E-step over its own candidates, the M-step of the
 // group is
 //     W'_r,i = sum_frames P[r][frame] K_i,frame                         (eq. 2.11)
-// Frames are stored sparsely (non-zero pixels, ascending); each workgroup
-// expands the frames it needs into LDS, 128-pixel band by band, and feeds the
-// dense band to v_mfma_f32_16x16x32_bf16.  A band's LDS rows are owned by one
-// wave (it writes, reads and clears them), so the band loops need no barrier.
+// Frames are stored sparsely, band-blocked: for every 128-pixel band a frame's
+// non-zero pixels are 16-bit words (pixel in band << 9 | count) packed in 16-byte
+// chunks of 8 (the last one padded with 0xffff), and a per-frame table gives each
+// band's first chunk.  Each workgroup expands the frames it needs into LDS band by
+// band and feeds the dense band to v_mfma_f32_16x16x32_bf16; the next band's
+// chunks are loaded while the current band's MFMAs run.  A band's LDS rows are
+// owned by one wave (it writes, reads and clears them), so the band loops need no
+// barrier.
 //
 // Storage of a group with frame list length F (Fp = F rounded up to 32):
 //   G  float [Fp][32]            frame-major: a frame's 32 values are contiguous
@@ -38,40 +42,47 @@ __device__ __forceinline__ uint16_t count_bf16(uint32_t e) {
   return (uint16_t)(__float_as_uint((float)(e & 0xffffu)) >> 16);
 }
 
-__device__ __forceinline__ int64_t readlane64(int64_t v, int l) {
-  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, l);
-  const int hi = __builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
-  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+constexpr uint32_t kPad = 0xffffu;  // padding word of a chunk
+constexpr int kWin = 2;              // chunks per band held in registers (16 pixels)
+
+// Writes (CLEAR = false) or zeroes one chunk's pixels: word e goes to
+// base[(e >> 9) * stride] as the BF16 count (e & 511).
+template <bool CLEAR>
+__device__ __forceinline__ void put_chunk(uint16_t* base, int stride, u4 ch) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t e = h ? (ch[u] >> 16) : (ch[u] & 0xffffu);
+      if (e != kPad) base[(int)(e >> 9) * stride] = CLEAR ? (uint16_t)0 : count_bf16(e & 511u);
+    }
+  }
 }
 
-// Writes (CLEAR = false) or zeroes (CLEAR = true) the band's entries of the frames
-// held by lanes 0..nf-1 (lane s: entry range [base + beg, base + end)).  Entry e goes
-// to rows[s * row_stride + (pixel - p0) * col_stride].
+// chunks first, first + step, ... < c1 of a band beyond the register window
+// (step 1: one lane per frame; 2: two lanes per frame taking alternate chunks),
+// loaded four at a time
 template <bool CLEAR>
-__device__ __forceinline__ void band_entries(uint16_t* __restrict__ rows, int row_stride, int col_stride,
-                                             const uint32_t* __restrict__ nz, int64_t base, int beg, int end, int nf,
-                                             int p0, int lane) {
-  for (int s = 0; s < nf; ++s) {
-    const int b = __builtin_amdgcn_readlane(beg, s);
-    const int n = __builtin_amdgcn_readlane(end, s) - b;
-    if (n <= 0) continue;  // uniform
-    const int64_t at = readlane64(base, s) + b;
-    for (int j = lane; j < n; j += 64) {
-      const uint32_t e = nz[at + j];
-      const int px = (int)(e >> 16) - p0;
-      if ((unsigned)px < (unsigned)kBand) rows[s * row_stride + px * col_stride] = CLEAR ? (uint16_t)0 : count_bf16(e);
-    }
+__device__ __forceinline__ void put_rest(uint16_t* base, int stride, const u4* __restrict__ src, int first, int c1,
+                                         int step) {
+  const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+  for (int c = first; c < c1; c += 4 * step) {
+    u4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = c + u * step < c1 ? src[c + u * step] : pad;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) put_chunk<CLEAR>(base, stride, v[u]);
   }
 }
 
 // ------------------------------------------------------------------ log-likelihood
 // One workgroup per tile (group g, frames [f0, f0 + 64) of the group's cell).  Wave w
-// takes the bands w, w + 4, ... of all 64 frames and both rotation tiles; the four
-// partial sums are added in LDS at the end.
+// takes the bands w, w + 4, ... of all 64 frames (lane s expands frame s) and both
+// rotation tiles; the four partial sums are added in LDS at the end.
 __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     const int2* __restrict__ tiles, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
-    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int64_t* __restrict__ nz_ptr,
-    const int32_t* __restrict__ nz_off, int ntab, const uint32_t* __restrict__ nz, const int32_t* __restrict__ cell_rot,
+    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int64_t* __restrict__ fb_ptr,
+    const uint16_t* __restrict__ fb_off, int ntab, const u4* __restrict__ fb, const int32_t* __restrict__ cell_rot,
     const uint16_t* __restrict__ hi, int64_t plane, const float* __restrict__ scale, int64_t ps,
     float* __restrict__ G) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kFT * kLRow];  // 69632 bytes
@@ -86,13 +97,14 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x < kGR) ssc[threadIdx.x] = threadIdx.x < nr ? scale[cell_rot[r0 + threadIdx.x]] : 0.0f;
 
-  // this lane's frame (slot = lane) and its entry range
-  int64_t base = 0;
-  const int32_t* tab = nz_off;
-  if (lane < nf) {
+  // this lane's frame (slot = lane): its chunks and band table
+  const bool has = lane < nf;
+  const u4* src = fb;
+  const uint16_t* tab = fb_off;
+  if (has) {
     const int32_t f = cf_frame[cf_ptr[c] + f0 + lane];
-    base = nz_ptr[f];
-    tab = nz_off + (int64_t)f * ntab;
+    src = fb + fb_ptr[f];
+    tab = fb_off + (int64_t)f * ntab;
   }
   // rows of the A operand: rotation (lane & 15) of each 16-row tile, -1 reads zero
   const int m = lane & 15, kq = 8 * (lane >> 4);
@@ -101,6 +113,7 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
   const bool two = nr > 16;
 
   uint16_t* rows = lds + wave * kFT * kLRow;
+  uint16_t* frow = rows + lane * kLRow;
   for (int e = lane; e < kFT * kLRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = u4{0u, 0u, 0u, 0u};
 
   f4 acc[2][4];
@@ -110,33 +123,72 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   const u4 zero = {0u, 0u, 0u, 0u};
+  const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
   const int nbands = (int)(ps / kBand);
+  // pipeline: chunks of the current band in registers, the next band's table entries
+  int lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+  if (has && wave < nbands) {
+    lo0 = tab[wave];
+    hi0 = tab[wave + 1];
+  }
+  u4 w0[kWin];
+#pragma unroll
+  for (int u = 0; u < kWin; ++u) w0[u] = lo0 + u < hi0 ? src[lo0 + u] : pad;
+  if (has && wave + 4 < nbands) {
+    lo1 = tab[wave + 4];
+    hi1 = tab[wave + 5];
+  }
   for (int band = wave; band < nbands; band += 4) {
     const int p0 = band * kBand;
-    const int beg = lane < nf ? tab[band] : 0, end = lane < nf ? tab[band + 1] : 0;
-    band_entries<false>(rows, kLRow, 1, nz, base, beg, end, nf, p0, lane);
+    // A fragments of the band first: loads complete in issue order, so the MFMAs
+    // below then need not wait for the prefetch that follows
+    u4 ah[4][2], al[4][2];
 #pragma unroll
-    for (int kk = 0; kk < kBand; kk += 32) {
-      const int64_t ko = p0 + kk + kq;
-      const u4 h0 = ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + ar0 + ko) : zero;
-      const u4 l0 = ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar0 + ko) : zero;
-      u4 h1 = zero, l1 = zero;
-      if (two) {
-        h1 = ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + ar1 + ko) : zero;
-        l1 = ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar1 + ko) : zero;
-      }
+    for (int kk = 0; kk < 4; ++kk) {
+      const int64_t ko = p0 + 32 * kk + kq;
+      ah[kk][0] = ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + ar0 + ko) : zero;
+      al[kk][0] = ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar0 + ko) : zero;
+      ah[kk][1] = ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + ar1 + ko) : zero;
+      al[kk][1] = ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar1 + ko) : zero;
+    }
+    // prefetch: the next band's chunks, the table entries of the band after
+    u4 w1[kWin];
+#pragma unroll
+    for (int u = 0; u < kWin; ++u) w1[u] = lo1 + u < hi1 ? src[lo1 + u] : pad;
+    int lo2 = 0, hi2 = 0;
+    if (has && band + 8 < nbands) {
+      lo2 = tab[band + 8];
+      hi2 = tab[band + 9];
+    }
+    if (has) {
+#pragma unroll
+      for (int u = 0; u < kWin; ++u) put_chunk<false>(frow, 1, w0[u]);
+      put_rest<false>(frow, 1, src, lo0 + kWin, hi0, 1);
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bf8 bv = *reinterpret_cast<const bf8*>(&rows[(16 * j + m) * kLRow + kk + kq]);
-        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, h0), bv, acc[0][j], 0, 0, 0);
-        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, l0), bv, acc[0][j], 0, 0, 0);
+        const bf8 bv = *reinterpret_cast<const bf8*>(&rows[(16 * j + m) * kLRow + 32 * kk + kq]);
+        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[kk][0]), bv, acc[0][j], 0, 0, 0);
+        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[kk][0]), bv, acc[0][j], 0, 0, 0);
         if (two) {
-          acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, h1), bv, acc[1][j], 0, 0, 0);
-          acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, l1), bv, acc[1][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[kk][1]), bv, acc[1][j], 0, 0, 0);
+          acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[kk][1]), bv, acc[1][j], 0, 0, 0);
         }
       }
     }
-    band_entries<true>(rows, kLRow, 1, nz, base, beg, end, nf, p0, lane);
+    if (has) {
+#pragma unroll
+      for (int u = 0; u < kWin; ++u) put_chunk<true>(frow, 1, w0[u]);
+      put_rest<true>(frow, 1, src, lo0 + kWin, hi0, 1);
+    }
+#pragma unroll
+    for (int u = 0; u < kWin; ++u) w0[u] = w1[u];
+    lo0 = lo1;
+    hi0 = hi1;
+    lo1 = lo2;
+    hi1 = hi2;
   }
 
   // sum of the four waves' partials: red[wave][slot][32] floats in the same LDS
@@ -240,16 +292,19 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
 // ------------------------------------------------------------------ M-step
 // One workgroup per (group g, 512-pixel range); it runs over the whole frame list
 // of the group's cell in blocks of 32 frames.  Wave w owns the range's band w:
-// it expands the block's frames there into LDS rows [pixel][frame], contracts them
-// with the block's P (B operand, read straight from its blocked layout) and clears
-// the rows.  W' rows are written (accumulate: added to what the audited frames'
-// dense product left there); the range-0 workgroup also sums rho = sum P.
+// it expands the block's frames there into LDS rows [pixel][frame] (lanes s and
+// s + 32 take alternate chunks of frame s), contracts them with the block's P (B
+// operand, read straight from its blocked layout) and clears the rows.  The next
+// block's chunks, the table entries of the block after and the frame indices of
+// the one after that are loaded while the current block's MFMAs run.  W' rows are
+// written (accumulate: added to what the audited frames' dense product left
+// there); the range-0 workgroup also sums rho = sum P.
 __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
     const int4* __restrict__ groups, const int64_t* __restrict__ grp_off, int nranges,
-    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int64_t* __restrict__ nz_ptr,
-    const int32_t* __restrict__ nz_off, int ntab, const uint32_t* __restrict__ nz,
-    const uint16_t* __restrict__ P, const int32_t* __restrict__ cell_rot, int64_t ps, float* __restrict__ Wp,
-    double* __restrict__ rho, const double* __restrict__ rho_a, int accumulate) {
+    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int64_t* __restrict__ fb_ptr,
+    const uint16_t* __restrict__ fb_off, int ntab, const u4* __restrict__ fb, const uint16_t* __restrict__ P,
+    const int32_t* __restrict__ cell_rot, int64_t ps, float* __restrict__ Wp, double* __restrict__ rho,
+    const double* __restrict__ rho_a, int accumulate) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kBand * kKRow];  // 40960 bytes
   const int64_t g = blockIdx.x / nranges;
   const int pr = (int)(blockIdx.x % nranges);
@@ -265,8 +320,10 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
   const bool two = nr > 16;
   const bool do_rho = pr == 0 && wave == 0;
   const int n = lane & 15, kq = 8 * (lane >> 4);
+  const int slot = lane & 31, par = lane >> 5;
 
   uint16_t* rows = lds + wave * kBand * kKRow;
+  uint16_t* fcol = rows + slot;
   for (int e = lane; e < kBand * kKRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = u4{0u, 0u, 0u, 0u};
 
   f4 acc[8][2];
@@ -274,22 +331,36 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
   for (int i = 0; i < 8; ++i) acc[i][0] = acc[i][1] = f4{0.f, 0.f, 0.f, 0.f};
   double rs0 = 0.0, rs1 = 0.0;
   const u4 zero = {0u, 0u, 0u, 0u};
+  const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+
+  // pipeline stages: block k (chunks in w0), k + 1 (table lo1/hi1), k + 2 (frame fr2)
+  auto frame_at = [&](int64_t f0) -> int32_t { return f0 + slot < F ? cf[f0 + slot] : -1; };
+  int32_t fr0 = frame_at(0), fr1 = frame_at(kFB), fr2 = frame_at(2 * kFB);
+  const u4* src0 = fr0 >= 0 ? fb + fb_ptr[fr0] : fb;
+  const u4* src1 = fr1 >= 0 ? fb + fb_ptr[fr1] : fb;
+  int lo0 = fr0 >= 0 ? fb_off[(int64_t)fr0 * ntab + band] : 0;
+  int hi0 = fr0 >= 0 ? fb_off[(int64_t)fr0 * ntab + band + 1] : 0;
+  u4 w0 = lo0 + par < hi0 ? src0[lo0 + par] : pad;
+  int lo1 = fr1 >= 0 ? fb_off[(int64_t)fr1 * ntab + band] : 0;
+  int hi1 = fr1 >= 0 ? fb_off[(int64_t)fr1 * ntab + band + 1] : 0;
 
   for (int64_t f0 = 0; f0 < F; f0 += kFB) {
     const int nf = (int)(F - f0 < kFB ? F - f0 : kFB);
-    int64_t base = 0;
-    int beg = 0, end = 0;
-    if (lane < nf) {
-      const int32_t f = cf[f0 + lane];
-      base = nz_ptr[f];
-      beg = nz_off[(int64_t)f * ntab + band];
-      end = nz_off[(int64_t)f * ntab + band + 1];
-    }
-    band_entries<false>(rows, 1, kKRow, nz, base, beg, end, nf, p0, lane);
-    // B operand: frames kq..kq+7 of the block for rotation n (and n + 16)
+    // B operand first (loads complete in issue order): frames kq..kq+7 of the block
+    // for rotation n (and n + 16)
     const uint16_t* pblk = Pg + (f0 >> 5) * (kGR * kFB);
     u4 b0 = *reinterpret_cast<const u4*>(pblk + n * kFB + kq);
     u4 b1 = two ? *reinterpret_cast<const u4*>(pblk + (16 + n) * kFB + kq) : zero;
+    // prefetch
+    const u4 w1 = lo1 + par < hi1 ? src1[lo1 + par] : pad;
+    const u4* src2 = fr2 >= 0 ? fb + fb_ptr[fr2] : fb;
+    const int lo2 = fr2 >= 0 ? fb_off[(int64_t)fr2 * ntab + band] : 0;
+    const int hi2 = fr2 >= 0 ? fb_off[(int64_t)fr2 * ntab + band + 1] : 0;
+    const int32_t fr3 = frame_at(f0 + 3 * kFB);
+    if (fr0 >= 0) {
+      put_chunk<false>(fcol, kKRow, w0);
+      put_rest<false>(fcol, kKRow, src0, lo0 + par + 2, hi0, 2);
+    }
     if (nf < kFB) {  // frames past the list end hold no responsibility
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -312,7 +383,20 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
       acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, b0), acc[i][0], 0, 0, 0);
       if (two) acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, b1), acc[i][1], 0, 0, 0);
     }
-    band_entries<true>(rows, 1, kKRow, nz, base, beg, end, nf, p0, lane);
+    if (fr0 >= 0) {
+      put_chunk<true>(fcol, kKRow, w0);
+      put_rest<true>(fcol, kKRow, src0, lo0 + par + 2, hi0, 2);
+    }
+    fr0 = fr1;
+    src0 = src1;
+    lo0 = lo1;
+    hi0 = hi1;
+    w0 = w1;
+    fr1 = fr2;
+    src1 = src2;
+    lo1 = lo2;
+    hi1 = hi2;
+    fr2 = fr3;
   }
 
   // acc[i][j][r] = W'[rotation 16 j + n][pixel p0 + 16 i + 4 (lane >> 4) + r]
@@ -347,41 +431,91 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
   }
 }
 
-// ------------------------------------------------------------------ small pieces
-// b_f = sum over the frame's entries of count * c[pixel], FP64; one wave per frame
-__global__ __launch_bounds__(256) void nz_dot_kernel(const int64_t* __restrict__ nz_ptr, const uint32_t* __restrict__ nz,
-                                                     int64_t n_frames, const double* __restrict__ cvec,
-                                                     double* __restrict__ b) {
+// ------------------------------------------------------------------ band-blocked frames
+// Chunks per band of each listed frame (one wave per frame, two pixels per lane per
+// band): band_chunk[f][b] = first chunk of band b (relative), band_chunk[f][nb] and
+// cnt[f] = the frame's chunk count; counts above 256 (not exact in BF16) set *over.
+__global__ __launch_bounds__(256) void band_count_kernel(const uint16_t* __restrict__ counts,
+                                                         const uint8_t* __restrict__ mask, int n_pix,
+                                                         const int32_t* __restrict__ frames, int64_t n_frames, int nb,
+                                                         uint16_t* __restrict__ band_chunk, int32_t* __restrict__ cnt,
+                                                         int32_t* __restrict__ over) {
+  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (f >= n_frames) return;  // uniform per wave
+  const uint16_t* row = counts + (int64_t)frames[f] * n_pix;
+  uint16_t* tab = band_chunk + f * (nb + 1);
+  int run = 0;
+  bool big = false;
+  for (int b = 0; b < nb; ++b) {
+    if (lane == 0) tab[b] = (uint16_t)run;
+    int n = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = b * kBand + 64 * h + lane;
+      const uint32_t v = i < n_pix && mask[i] ? row[i] : 0u;
+      big |= v > 256u;
+      n += __popcll(__ballot(v != 0u));
+    }
+    run += (n + 7) >> 3;
+  }
+  if (lane == 0) {
+    tab[nb] = (uint16_t)run;
+    cnt[f] = run;
+  }
+  if (__ballot(big) != 0ull && lane == 0) atomicOr(over, 1);
+}
+
+// Fill: words (pixel in band << 9 | count) in pixel order, chunk tails padded
+__global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restrict__ counts,
+                                                        const uint8_t* __restrict__ mask, int n_pix,
+                                                        const int32_t* __restrict__ frames, int64_t n_frames, int nb,
+                                                        const uint16_t* __restrict__ band_chunk,
+                                                        const int64_t* __restrict__ chunk_ptr,
+                                                        uint16_t* __restrict__ words) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= n_frames) return;
+  const uint16_t* row = counts + (int64_t)frames[f] * n_pix;
+  const uint16_t* tab = band_chunk + f * (nb + 1);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int b = 0; b < nb; ++b) {
+    const int c0 = tab[b], c1 = tab[b + 1];
+    if (c0 == c1) continue;  // uniform: empty band
+    uint16_t* out = words + (chunk_ptr[f] + c0) * 8;
+    int n = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = b * kBand + 64 * h + lane;
+      const uint32_t v = i < n_pix && mask[i] ? row[i] : 0u;
+      const unsigned long long bal = __ballot(v != 0u);
+      if (v != 0u) out[n + __popcll(bal & below)] = (uint16_t)(((uint32_t)(64 * h + lane) << 9) | v);
+      n += __popcll(bal);
+    }
+    for (int t = n + lane; t < 8 * (c1 - c0); t += 64) out[t] = (uint16_t)kPad;
+  }
+}
+
+// b_f = sum over the frame's pixels of count * c[pixel], FP64; one wave per frame
+__global__ __launch_bounds__(256) void band_dot_kernel(const int64_t* __restrict__ chunk_ptr,
+                                                       const uint16_t* __restrict__ band_chunk, int nb,
+                                                       const uint16_t* __restrict__ words, int64_t n_frames,
+                                                       const double* __restrict__ cvec, double* __restrict__ b) {
+  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (f >= n_frames) return;
+  const uint16_t* tab = band_chunk + f * (nb + 1);
+  const uint16_t* w = words + chunk_ptr[f] * 8;
   double acc = 0.0;
-  for (int64_t e = nz_ptr[f] + lane; e < nz_ptr[f + 1]; e += 64) {
-    const uint32_t v = nz[e];
-    acc += (double)(v & 0xffffu) * cvec[v >> 16];
+  for (int band = 0; band < nb; ++band) {
+    const int a = 8 * tab[band], z = 8 * tab[band + 1];
+    for (int t = a + lane; t < z; t += 64) {
+      const uint32_t e = w[t];
+      if (e != kPad) acc += (double)(e & 511u) * cvec[band * kBand + (e >> 9)];
+    }
   }
   acc = wave_sum(acc);
   if (lane == 0) b[f] = acc;
-}
-
-// nz_off[f][t] = number of entries of frame f with pixel < t * 128, t = 0 .. ntab - 1
-__global__ void nz_offsets_kernel(const int64_t* __restrict__ nz_ptr, const uint32_t* __restrict__ nz,
-                                  int64_t n_frames, int ntab, int32_t* __restrict__ nz_off) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n_frames * ntab) return;
-  const int64_t f = e / ntab;
-  const int t = (int)(e - f * ntab);
-  const int64_t a = nz_ptr[f];
-  int64_t lo = 0, hi = nz_ptr[f + 1] - a;  // first entry with pixel >= t * 128
-  const uint32_t bound = (uint32_t)t * kBand;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if ((nz[a + mid] >> 16) < bound)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  nz_off[e] = (int32_t)lo;
 }
 
 // groups of 32 rotations: count per cell
@@ -467,14 +601,14 @@ __global__ __launch_bounds__(256) void audit_recall_kernel(const __hip_bfloat16*
 
 // ===================================================================== launchers
 hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* groups, const int64_t* grp_off,
-                              const int64_t* cf_ptr, const int32_t* cf_frame, const int64_t* nz_ptr,
-                              const int32_t* nz_off, int ntab, const uint32_t* nz, const int32_t* cell_rot,
+                              const int64_t* cf_ptr, const int32_t* cf_frame, const int64_t* chunk_ptr,
+                              const uint16_t* band_chunk, int ntab, const void* chunks, const int32_t* cell_rot,
                               const void* hilo, int64_t plane, const float* scale, int64_t ps, float* G,
                               hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  cand_loglik_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, nz_ptr, nz_off,
-                                                        ntab, nz, cell_rot, (const uint16_t*)hilo, plane, scale, ps,
-                                                        G);
+  cand_loglik_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, chunk_ptr,
+                                                        band_chunk, ntab, (const u4*)chunks, cell_rot,
+                                                        (const uint16_t*)hilo, plane, scale, ps, G);
   return hipGetLastError();
 }
 
@@ -490,29 +624,40 @@ hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const 
 }
 
 hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
-                             const int32_t* cf_frame, const int64_t* nz_ptr, const int32_t* nz_off, int ntab,
-                             const uint32_t* nz, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
+                             const int32_t* cf_frame, const int64_t* chunk_ptr, const uint16_t* band_chunk, int ntab,
+                             const void* chunks, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
                              double* rho, const double* rho_a, bool accumulate, hipStream_t st) {
   if (n_groups <= 0) return hipSuccess;
   const int nranges = (int)((ps + kRange - 1) / kRange);
-  cand_mstep_kernel<<<(unsigned)(n_groups * nranges), 256, 0, st>>>(groups, grp_off, nranges, cf_ptr, cf_frame, nz_ptr,
-                                                                    nz_off, ntab, nz, (const uint16_t*)P, cell_rot,
-                                                                    ps, Wp, rho, rho_a, accumulate ? 1 : 0);
+  cand_mstep_kernel<<<(unsigned)(n_groups * nranges), 256, 0, st>>>(
+      groups, grp_off, nranges, cf_ptr, cf_frame, chunk_ptr, band_chunk, ntab, (const u4*)chunks, (const uint16_t*)P,
+      cell_rot, ps, Wp, rho, rho_a, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_nz_dot(const int64_t* nz_ptr, const uint32_t* nz, int64_t n_frames, const double* c, double* b,
-                         hipStream_t st) {
-  if (n_frames <= 0) return hipSuccess;
-  nz_dot_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(nz_ptr, nz, n_frames, c, b);
-  return hipGetLastError();
-}
-
-hipError_t launch_nz_offsets(const int64_t* nz_ptr, const uint32_t* nz, int64_t n_frames, int ntab, int32_t* nz_off,
+hipError_t launch_band_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
+                             int64_t n_frames, int ntab, uint16_t* band_chunk, int32_t* cnt, int32_t* over,
                              hipStream_t st) {
-  const int64_t n = n_frames * ntab;
-  if (n <= 0) return hipSuccess;
-  nz_offsets_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(nz_ptr, nz, n_frames, ntab, nz_off);
+  if (n_frames <= 0) return hipSuccess;
+  band_count_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, ntab - 1,
+                                                                    band_chunk, cnt, over);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
+                            int64_t n_frames, int ntab, const uint16_t* band_chunk, const int64_t* chunk_ptr,
+                            void* chunks, hipStream_t st) {
+  if (n_frames <= 0) return hipSuccess;
+  band_fill_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, ntab - 1,
+                                                                   band_chunk, chunk_ptr, (uint16_t*)chunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_dot(const int64_t* chunk_ptr, const uint16_t* band_chunk, int ntab, const void* chunks,
+                           int64_t n_frames, const double* c, double* b, hipStream_t st) {
+  if (n_frames <= 0) return hipSuccess;
+  band_dot_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(chunk_ptr, band_chunk, ntab - 1,
+                                                                  (const uint16_t*)chunks, n_frames, c, b);
   return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // Plan of the learned-proposal form: coarse cells of the fine rotations, the
-// candidate frames grouped by their best cell, the (frame, proposed cell) pairs
-// grouped by cell, and the candidate frames' photon counts as sparse lists.  The
-// candidate E- and M-steps themselves are in cand.hip.
+// candidate frames grouped by their best cell and the (frame, proposed cell)
+// pairs grouped by cell.  The candidate E- and M-steps and the candidate frames'
+// sparse band format are in cand.hip.
 #include "emc_device.h"
 
 namespace emc {
@@ -217,47 +217,6 @@ __global__ void pair_columns_kernel(const int32_t* __restrict__ order, int64_t n
   pair_col[pr] = (int32_t)(e - cf_ptr[keys[pr]]);
 }
 
-// frame CSR of the listed frames: non-zero photon counts of unmasked pixels as
-// (pixel << 16) | count, pixels ascending; counts above 256 (not exact in BF16) set *over
-__global__ __launch_bounds__(256) void nz_count_kernel(const uint16_t* __restrict__ counts,
-                                                       const uint8_t* __restrict__ mask, int n_pix,
-                                                       const int32_t* __restrict__ frames, int64_t n_frames,
-                                                       int32_t* __restrict__ cnt, int32_t* __restrict__ over) {
-  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (f >= n_frames) return;
-  const uint16_t* row = counts + (int64_t)frames[f] * n_pix;
-  int n = 0;
-  bool big = false;
-  for (int i = lane; i < n_pix; i += 64) {
-    const bool live = mask[i] && row[i] != 0;
-    n += live;
-    big |= live && row[i] > 256;
-  }
-  n = wave_sum(n);
-  if (lane == 0) cnt[f] = n;
-  if (__ballot(big) != 0ull && lane == 0) atomicOr(over, 1);
-}
-
-__global__ __launch_bounds__(256) void nz_fill_kernel(const uint16_t* __restrict__ counts,
-                                                      const uint8_t* __restrict__ mask, int n_pix,
-                                                      const int32_t* __restrict__ frames, int64_t n_frames,
-                                                      const int64_t* __restrict__ ptr, uint32_t* __restrict__ nz) {
-  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (f >= n_frames) return;
-  const uint16_t* row = counts + (int64_t)frames[f] * n_pix;
-  int64_t at = ptr[f];
-  for (int i0 = 0; i0 < n_pix; i0 += 64) {
-    const int i = i0 + lane;
-    const uint32_t v = i < n_pix && mask[i] ? row[i] : 0u;
-    const bool hit = v != 0u;
-    const unsigned long long bal = __ballot(hit);
-    if (hit) nz[at + __popcll(bal & ((1ull << lane) - 1ull))] = ((uint32_t)i << 16) | v;
-    at += __popcll(bal);
-  }
-}
-
 // ===================================================================== launchers
 static inline unsigned g256(int64_t n) {
   const int64_t g = (n + 255) / 256;
@@ -357,21 +316,6 @@ hipError_t launch_pair_columns(const int32_t* order, int64_t n_pairs, int k_top,
   if (n_pairs > 0)
     pair_columns_kernel<<<(unsigned)((n_pairs + 255) / 256), 256, 0, st>>>(order, n_pairs, k_top, keys, cf_ptr,
                                                                            cf_frame, pair_col);
-  return hipGetLastError();
-}
-
-hipError_t launch_nz_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                           int64_t n_frames, int32_t* cnt, int32_t* over, hipStream_t st) {
-  if (n_frames > 0)
-    nz_count_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, cnt,
-                                                                    over);
-  return hipGetLastError();
-}
-
-hipError_t launch_nz_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                          int64_t n_frames, const int64_t* ptr, uint32_t* nz, hipStream_t st) {
-  if (n_frames > 0)
-    nz_fill_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, ptr, nz);
   return hipGetLastError();
 }
 

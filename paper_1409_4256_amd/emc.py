@@ -64,13 +64,13 @@ class Proposal(ctypes.Structure):
         ("n_cells", ctypes.c_int32), ("k_top", ctypes.c_int32), ("n_cand", ctypes.c_int32),
         ("n_audit", ctypes.c_int32), ("words", ctypes.c_int32), ("ntab", ctypes.c_int32),
         ("n_groups", ctypes.c_int64), ("n_tiles", ctypes.c_int64), ("n_g", ctypes.c_int64),
-        ("n_nz", ctypes.c_int64),
+        ("n_chunks", ctypes.c_int64),
         ("cell_of", ctypes.c_void_p), ("cell_ptr", ctypes.c_void_p), ("cell_rot", ctypes.c_void_p),
         ("cand_frames", ctypes.c_void_p), ("audit_frames", ctypes.c_void_p), ("cand_cells", ctypes.c_void_p),
         ("pair_col", ctypes.c_void_p), ("cf_ptr", ctypes.c_void_p), ("cf_frame", ctypes.c_void_p),
         ("cg_ptr", ctypes.c_void_p), ("groups", ctypes.c_void_p), ("grp_off", ctypes.c_void_p),
         ("tiles", ctypes.c_void_p), ("mask_audit", ctypes.c_void_p),
-        ("nz_ptr", ctypes.c_void_p), ("nz", ctypes.c_void_p), ("nz_off", ctypes.c_void_p),
+        ("chunk_ptr", ctypes.c_void_p), ("chunks", ctypes.c_void_p), ("band_chunk", ctypes.c_void_p),
     ]
 
 
