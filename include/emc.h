@@ -298,7 +298,7 @@ typedef struct emc_proposal {
   int32_t n_cand;         /* frames searched over their candidates                  */
   int32_t n_audit;        /* frames searched in full                                */
   int32_t words;          /* ceil(n_cells / 32): words of a cell bitmask            */
-  int32_t ntab;           /* entries per frame of band_chunk: n_pix stride / 128 + 1 */
+  int32_t n_bands;        /* 128-pixel bands: n_pix stride / 128                     */
   int64_t n_groups;       /* rotation groups                                        */
   int64_t n_tiles;        /* workgroups of the candidate log-likelihood (x 8)       */
   int64_t n_g;            /* elements of G (float) and P (bf16)                     */
@@ -317,12 +317,12 @@ typedef struct emc_proposal {
   int64_t* grp_off;       /* [n_groups + 1] element offset of each group's storage   */
   void* tiles;            /* [n_tiles] int32 x 2: group, first frame; (-1, 0) padding */
   uint32_t* mask_audit;   /* [n_audit][words] proposed cells of the audited frames  */
-  int64_t* chunk_ptr;     /* [n_cand + 1] first chunk of candidate frame f          */
-  void* chunks;           /* 16-byte chunks of 8 uint16 words: for every 128-pixel
-                             band b, the frame's non-zero pixels as
-                             (pixel - 128 b) << 9 | count, ascending, 0xffff pads  */
-  uint16_t* band_chunk;   /* [n_cand][ntab] first chunk of band b (relative), and
-                             at b = ntab - 1 the frame's chunk count               */
+  void* chunks;           /* 16-byte chunks of 8 uint16 words: the non-zero pixels
+                             of candidate frame f in 128-pixel band b as
+                             (pixel - 128 b) << 9 | count, ascending, 0xffff pads;
+                             stored band-major (band 0 of all frames first)        */
+  int32_t* band_range;    /* [n_bands][n_cand][2] chunk range (first, end) of band
+                             b of frame f, absolute chunk indices                  */
 } emc_proposal;
 
 /* Bytes of the plan buffer; nz_cap bounds the non-zero pixels of the frames. */

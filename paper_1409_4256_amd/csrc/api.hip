@@ -595,8 +595,8 @@ int64_t chunk_cap(int64_t nz_cap, int64_t n_cand, int n_pix) { return (nz_cap + 
 // Carving of the plan buffer (capacities known before the build).
 struct PlanLayout {
   size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, cg_ptr,
-      groups, grp_off, tiles, mask_audit, chunk_ptr, chunks, band_chunk, hist, cursor, keys, order, mark, frame_ptr,
-      gsize, xcd, cnt, chunk_cnt, scalars, total;
+      groups, grp_off, tiles, mask_audit, chunks, band_range, band_cnt, band_ptr, hist, cursor, keys, order, mark,
+      frame_ptr, gsize, xcd, cnt, scalars, total;
 };
 
 PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top, int n_audit, int64_t nz_cap) {
@@ -626,9 +626,11 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.grp_off = take((g_max + 1) * 8);
   L.tiles = take(tile_cap(g_max, n_cand) * 8);
   L.mask_audit = take((int64_t)n_audit * w * 4);
-  L.chunk_ptr = take((n_cand + 1) * 8);
+  const int64_t n_fb = n_cand * (ntab_of(n_pix) - 1);  // (band, frame) entries
   L.chunks = take(chunk_cap(nz_cap, n_cand, n_pix) * 16);
-  L.band_chunk = take(n_cand * ntab_of(n_pix) * 2);
+  L.band_range = take(n_fb * 8);
+  L.band_cnt = take(n_fb * 4);
+  L.band_ptr = take((n_fb + 1) * 8);
   L.hist = take(nkeys * 4);
   L.cursor = take(nkeys * 4);
   L.keys = take(std::max<int64_t>(n_pairs, n_data) * 4);
@@ -638,7 +640,6 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.gsize = take(g_max * 8);
   L.xcd = take(g_max * 4);
   L.cnt = take((int64_t)n_cells * 4);
-  L.chunk_cnt = take(n_cand * 4);
   L.scalars = take(64);
   L.total = o;
   return L;
@@ -719,7 +720,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   P.n_cand = (int32_t)n_cand;
   P.n_audit = n_audit;
   P.words = w;
-  P.ntab = ntab;
+  P.n_bands = ntab - 1;
   P.cell_of = (int32_t*)(b + L.cell_of);
   P.cell_ptr = (int64_t*)(b + L.cell_ptr);
   P.cell_rot = (int32_t*)(b + L.cell_rot);
@@ -734,9 +735,11 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   P.grp_off = (int64_t*)(b + L.grp_off);
   P.tiles = (void*)(b + L.tiles);
   P.mask_audit = (uint32_t*)(b + L.mask_audit);
-  P.chunk_ptr = (int64_t*)(b + L.chunk_ptr);
   P.chunks = (void*)(b + L.chunks);
-  P.band_chunk = (uint16_t*)(b + L.band_chunk);
+  P.band_range = (int32_t*)(b + L.band_range);
+  int32_t* band_cnt = (int32_t*)(b + L.band_cnt);
+  int64_t* band_ptr = (int64_t*)(b + L.band_ptr);
+  const int64_t n_fb = n_cand * (ntab - 1);
   int32_t* hist = (int32_t*)(b + L.hist);
   int32_t* cursor = (int32_t*)(b + L.cursor);
   int32_t* keys = (int32_t*)(b + L.keys);
@@ -746,7 +749,6 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   int64_t* gsize = (int64_t*)(b + L.gsize);
   int32_t* xcd = (int32_t*)(b + L.xcd);
   int32_t* cnt = (int32_t*)(b + L.cnt);
-  int32_t* chunk_cnt = (int32_t*)(b + L.chunk_cnt);
   int64_t* scal = (int64_t*)(b + L.scalars);  // [0] n_tiles, [1] flags (int32): 1 count range, 2 repeated cell
   int32_t* over = (int32_t*)(scal + 1);
   // 1. coarse cell of every fine rotation; rotations grouped by cell
@@ -777,24 +779,24 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
                              tile_cap(g_max, n_cand), scal, st),
           "tiles");
   // 5. the candidate frames in the sparse band format
-  HIP_TRY(launch_band_count(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab, P.band_chunk, chunk_cnt, over,
-                            st),
+  HIP_TRY(launch_band_count(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab - 1, band_cnt, over, st),
           "band count");
-  HIP_TRY(launch_scan(chunk_cnt, n_cand, P.chunk_ptr, st), "chunk offsets");
+  HIP_TRY(launch_scan(band_cnt, n_fb, band_ptr, st), "chunk offsets");
   int64_t host[5] = {0, 0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(&host[0], scal, 16, hipMemcpyDeviceToHost, st), "read n_tiles");
   HIP_TRY(hipMemcpyAsync(&host[2], P.cg_ptr + n_cells, 8, hipMemcpyDeviceToHost, st), "read n_groups");
   HIP_TRY(hipMemcpyAsync(&host[3], P.grp_off + g_max, 8, hipMemcpyDeviceToHost, st), "read n_g");
-  HIP_TRY(hipMemcpyAsync(&host[4], P.chunk_ptr + n_cand, 8, hipMemcpyDeviceToHost, st), "read n_chunks");
+  HIP_TRY(hipMemcpyAsync(&host[4], band_ptr + n_fb, 8, hipMemcpyDeviceToHost, st), "read n_chunks");
   HIP_TRY(hipStreamSynchronize(st), "proposal build sync");
   const int32_t flags = (int32_t)host[1];
   if (flags & 2) return fail(EMC_ERR_INVALID_ARG, "a frame lists the same cell more than once");
   if (host[0] < 0) return fail(EMC_ERR_INVALID_ARG, "inconsistent proposal lists");
   if (flags & 1) return fail(EMC_ERR_RANGE, "a photon count exceeds 256, which BF16 cannot hold exactly");
-  if (host[4] > chunk_cap(nz_cap, n_cand, pb->n_pix))
+  if (host[4] > chunk_cap(nz_cap, n_cand, pb->n_pix) || host[4] > (int64_t)INT32_MAX)
     return fail(EMC_ERR_WORKSPACE, "the candidate frames need %lld chunks, nz_cap %lld allows %lld", (long long)host[4],
                 (long long)nz_cap, (long long)chunk_cap(nz_cap, n_cand, pb->n_pix));
-  HIP_TRY(launch_band_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab, P.band_chunk, P.chunk_ptr,
+  HIP_TRY(launch_band_range(band_ptr, n_fb, (int2*)P.band_range, st), "band ranges");
+  HIP_TRY(launch_band_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab - 1, (const int2*)P.band_range,
                            P.chunks, st),
           "band fill");
   P.n_tiles = host[0];
@@ -851,7 +853,7 @@ emc_status check_plan(const emc_problem* pb, const emc_proposal* P) {
     return fail(EMC_ERR_INVALID_ARG, "plan frames (%d + %d) do not match n_data %d", P->n_cand, P->n_audit, pb->n_data);
   if (P->k_top < 1 || P->k_top > kMaxTop || P->n_cells < 1 || P->words != words_of(P->n_cells) || P->n_g < 0 ||
       P->n_tiles < 0 || P->n_tiles % 8 != 0 || P->n_groups < 1 || P->n_groups > group_cap(pb->n_rot, P->n_cells) ||
-      P->ntab != ntab_of(pb->n_pix))
+      P->n_bands != ntab_of(pb->n_pix) - 1)
     return fail(EMC_ERR_INVALID_ARG, "inconsistent plan");
   return EMC_OK;
 }
@@ -907,10 +909,10 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   CHECK(run_expand(pb, model_in, c, slices, S, scale, st));
   // candidate frames: log-likelihoods per (group, listed frame), E-step over each frame's candidates
   if (nc > 0) {
-    HIP_TRY(launch_band_dot(plan->chunk_ptr, plan->band_chunk, plan->ntab, plan->chunks, nc, c, b, st), "band dot");
+    HIP_TRY(launch_band_dot((const int2*)plan->band_range, plan->n_bands, plan->chunks, nc, c, b, st), "band dot");
     HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, groups, plan->grp_off, plan->cf_ptr,
-                               plan->cf_frame, plan->chunk_ptr, plan->band_chunk, plan->ntab, plan->chunks,
-                               plan->cell_rot, slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
+                               plan->cf_frame, (const int2*)plan->band_range, nc, plan->chunks, plan->cell_rot,
+                               slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
             "candidate loglik");
     HIP_TRY(launch_cand_estep(G, Pc, groups, plan->grp_off, plan->cg_ptr, plan->cand_cells, plan->pair_col,
                               plan->k_top, nc, plan->cell_rot, pb->log_w, S, b, L, st),
@@ -933,9 +935,9 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
     const char* KTa = (const char*)K_audit + (size_t)na * ps * 2;
     HIP_TRY(launch_gemm_bf16_nt(Pa, KTa, Wp, pb->n_rot, ps, dsa, dsa, dsa, ps, st), "audit mstep gemm");
   }
-  HIP_TRY(launch_cand_mstep(groups, plan->grp_off, plan->n_groups, plan->cf_ptr, plan->cf_frame, plan->chunk_ptr,
-                            plan->band_chunk, plan->ntab, plan->chunks, Pc, plan->cell_rot, ps, Wp, rho, rho_a, na > 0,
-                            st),
+  HIP_TRY(launch_cand_mstep(groups, plan->grp_off, plan->n_groups, plan->cf_ptr, plan->cf_frame,
+                            (const int2*)plan->band_range, nc, plan->chunks, Pc, plan->cell_rot, ps, Wp, rho, rho_a,
+                            na > 0, st),
           "candidate mstep");
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
   HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");

@@ -10,8 +10,11 @@
 //     W'_r,i = sum_frames P[r][frame] K_i,frame                         (eq. 2.11)
 // Frames are stored sparsely, band-blocked: for every 128-pixel band a frame's
 // non-zero pixels are 16-bit words (pixel in band << 9 | count) packed in 16-byte
-// chunks of 8 (the last one padded with 0xffff), and a per-frame table gives each
-// band's first chunk.  Each workgroup expands the frames it needs into LDS band by
+// chunks of 8 (the last one padded with 0xffff).  Chunks are stored band-major
+// (band 0 of every frame, then band 1, ...), and frames are numbered by their best
+// cell, so the frames of a cell's list -- runs of consecutive numbers -- have their
+// chunks of one band next to each other; a table [band][frame] gives each chunk
+// range (absolute chunk indices).  Each workgroup expands the frames it needs into LDS band by
 // band and feeds the dense band to v_mfma_f32_16x16x32_bf16; the next band's
 // chunks are loaded while the current band's MFMAs run.  A band's LDS rows are
 // owned by one wave (it writes, reads and clears them), so the band loops need no
@@ -35,7 +38,6 @@ constexpr int kBand = 128;          // pixels per band (granularity of the entry
 constexpr int kLRow = kBand + 8;    // LDS row of one frame's band, bf16 (272 bytes: conflict-free 16-byte reads)
 constexpr int kFB = 32;             // frames per M-step block (one MFMA reduction step)
 constexpr int kKRow = kFB + 8;      // LDS row of one pixel's frames, bf16 (80 bytes)
-constexpr int kRange = 4 * kBand;   // pixels per M-step workgroup (one band per wave)
 
 __device__ __forceinline__ uint16_t count_bf16(uint32_t e) {
   // counts up to 256 are exact in BF16: the upper half of the FP32 pattern
@@ -62,16 +64,17 @@ __device__ __forceinline__ void put_chunk(uint16_t* base, int stride, u4 ch) {
 // chunks first, first + step, ... < c1 of a band beyond the register window
 // (step 1: one lane per frame; 2: two lanes per frame taking alternate chunks),
 // loaded four at a time
+// (chunks from `mid` on belong to the next band: their pixels go `next` further)
 template <bool CLEAR>
 __device__ __forceinline__ void put_rest(uint16_t* base, int stride, const u4* __restrict__ src, int first, int c1,
-                                         int step) {
+                                         int step, int mid = INT_MAX, int next = 0) {
   const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
   for (int c = first; c < c1; c += 4 * step) {
     u4 v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) v[u] = c + u * step < c1 ? src[c + u * step] : pad;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) put_chunk<CLEAR>(base, stride, v[u]);
+    for (int u = 0; u < 4; ++u) put_chunk<CLEAR>(base + (c + u * step >= mid ? next : 0), stride, v[u]);
   }
 }
 
@@ -81,10 +84,9 @@ __device__ __forceinline__ void put_rest(uint16_t* base, int stride, const u4* _
 // rotation tiles; the four partial sums are added in LDS at the end.
 __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     const int2* __restrict__ tiles, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
-    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int64_t* __restrict__ fb_ptr,
-    const uint16_t* __restrict__ fb_off, int ntab, const u4* __restrict__ fb, const int32_t* __restrict__ cell_rot,
-    const uint16_t* __restrict__ hi, int64_t plane, const float* __restrict__ scale, int64_t ps,
-    float* __restrict__ G) {
+    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int2* __restrict__ band_range,
+    int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ cell_rot, const uint16_t* __restrict__ hi,
+    int64_t plane, const float* __restrict__ scale, int64_t ps, float* __restrict__ G) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kFT * kLRow];  // 69632 bytes
   __shared__ float ssc[kGR];
   const int2 tl = tiles[blockIdx.x];
@@ -97,15 +99,11 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x < kGR) ssc[threadIdx.x] = threadIdx.x < nr ? scale[cell_rot[r0 + threadIdx.x]] : 0.0f;
 
-  // this lane's frame (slot = lane): its chunks and band table
+  const int nbands = (int)(ps / kBand);
+  // this lane's frame (slot = lane): its bands' chunk ranges, rng[band * n_list]
   const bool has = lane < nf;
-  const u4* src = fb;
-  const uint16_t* tab = fb_off;
-  if (has) {
-    const int32_t f = cf_frame[cf_ptr[c] + f0 + lane];
-    src = fb + fb_ptr[f];
-    tab = fb_off + (int64_t)f * ntab;
-  }
+  const int2* rng = band_range;
+  if (has) rng = band_range + cf_frame[cf_ptr[c] + f0 + lane];
   // rows of the A operand: rotation (lane & 15) of each 16-row tile, -1 reads zero
   const int m = lane & 15, kq = 8 * (lane >> 4);
   const int64_t ar0 = m < nr ? (int64_t)cell_rot[r0 + m] * ps : -1;
@@ -124,46 +122,42 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
 
   const u4 zero = {0u, 0u, 0u, 0u};
   const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
-  const int nbands = (int)(ps / kBand);
-  // pipeline: chunks of the current band in registers, the next band's table entries
-  int lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
-  if (has && wave < nbands) {
-    lo0 = tab[wave];
-    hi0 = tab[wave + 1];
-  }
+  // pipeline: chunks of the current band in registers, the next band's chunk range
+  int2 r0c = {0, 0}, r1c = {0, 0};
+  if (has && wave < nbands) r0c = rng[wave * n_list];
   u4 w0[kWin];
 #pragma unroll
-  for (int u = 0; u < kWin; ++u) w0[u] = lo0 + u < hi0 ? src[lo0 + u] : pad;
-  if (has && wave + 4 < nbands) {
-    lo1 = tab[wave + 4];
-    hi1 = tab[wave + 5];
-  }
-  for (int band = wave; band < nbands; band += 4) {
-    const int p0 = band * kBand;
-    // A fragments of the band first: loads complete in issue order, so the MFMAs
-    // below then need not wait for the prefetch that follows
-    u4 ah[4][2], al[4][2];
+  for (int u = 0; u < kWin; ++u) w0[u] = r0c.x + u < r0c.y ? fb[r0c.x + u] : pad;
+  if (has && wave + 4 < nbands) r1c = rng[(wave + 4) * n_list];
+  // A fragments (slice rows, hi and lo, both row tiles) of a band, 4 k-steps
+  auto load_a = [&](int band, u4 (&h)[4][2], u4 (&l)[4][2]) {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int64_t ko = p0 + 32 * kk + kq;
-      ah[kk][0] = ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + ar0 + ko) : zero;
-      al[kk][0] = ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar0 + ko) : zero;
-      ah[kk][1] = ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + ar1 + ko) : zero;
-      al[kk][1] = ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar1 + ko) : zero;
+      const int64_t ko = (int64_t)band * kBand + 32 * kk + kq;
+      const bool in = band < nbands;
+      h[kk][0] = in && ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + ar0 + ko) : zero;
+      l[kk][0] = in && ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar0 + ko) : zero;
+      h[kk][1] = in && ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + ar1 + ko) : zero;
+      l[kk][1] = in && ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar1 + ko) : zero;
     }
-    // prefetch: the next band's chunks, the table entries of the band after
+  };
+  u4 ah[4][2], al[4][2];
+  load_a(wave, ah, al);
+  for (int band = wave; band < nbands; band += 4) {
+    // prefetch (all issued before this band's data is waited on; loads complete in
+    // issue order): the next band's A fragments and chunks, the table entries of
+    // the band after
+    u4 ahn[4][2], aln[4][2];
+    load_a(band + 4, ahn, aln);
     u4 w1[kWin];
 #pragma unroll
-    for (int u = 0; u < kWin; ++u) w1[u] = lo1 + u < hi1 ? src[lo1 + u] : pad;
-    int lo2 = 0, hi2 = 0;
-    if (has && band + 8 < nbands) {
-      lo2 = tab[band + 8];
-      hi2 = tab[band + 9];
-    }
+    for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? fb[r1c.x + u] : pad;
+    int2 r2c = {0, 0};
+    if (has && band + 8 < nbands) r2c = rng[(band + 8) * n_list];
     if (has) {
 #pragma unroll
       for (int u = 0; u < kWin; ++u) put_chunk<false>(frow, 1, w0[u]);
-      put_rest<false>(frow, 1, src, lo0 + kWin, hi0, 1);
+      put_rest<false>(frow, 1, fb, r0c.x + kWin, r0c.y, 1);
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -178,17 +172,19 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
         }
       }
     }
-    if (has) {
-#pragma unroll
-      for (int u = 0; u < kWin; ++u) put_chunk<true>(frow, 1, w0[u]);
-      put_rest<true>(frow, 1, src, lo0 + kWin, hi0, 1);
-    }
+    // clear the band's rows (contiguous 16-byte stores: no reloads of the chunks)
+    for (int e = lane; e < kFT * kLRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = zero;
 #pragma unroll
     for (int u = 0; u < kWin; ++u) w0[u] = w1[u];
-    lo0 = lo1;
-    hi0 = hi1;
-    lo1 = lo2;
-    hi1 = hi2;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        ah[kk][t] = ahn[kk][t];
+        al[kk][t] = aln[kk][t];
+      }
+    r0c = r1c;
+    r1c = r2c;
   }
 
   // sum of the four waves' partials: red[wave][slot][32] floats in the same LDS
@@ -290,22 +286,22 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
 }
 
 // ------------------------------------------------------------------ M-step
-// One workgroup per (group g, 512-pixel range); it runs over the whole frame list
-// of the group's cell in blocks of 32 frames.  Wave w owns the range's band w:
-// it expands the block's frames there into LDS rows [pixel][frame] (lanes s and
-// s + 32 take alternate chunks of frame s), contracts them with the block's P (B
-// operand, read straight from its blocked layout) and clears the rows.  The next
-// block's chunks, the table entries of the block after and the frame indices of
-// the one after that are loaded while the current block's MFMAs run.  W' rows are
-// written (accumulate: added to what the audited frames' dense product left
-// there); the range-0 workgroup also sums rho = sum P.
+// One workgroup per (group g, 1024-pixel range); it runs over the whole frame list
+// of the group's cell in blocks of 32 frames.  Wave w owns the range's band pair
+// w (256 pixels): it expands the block's frames there into LDS rows [pixel][frame]
+// (lanes s and s + 32 take the two bands of frame s), contracts them with the
+// block's P (B operand, read straight from its blocked layout) and clears the
+// rows.  The next block's P and chunks, the chunk ranges of the block after and
+// the frame indices of the one after that are loaded while the current block's
+// MFMAs run.  W' rows are written (accumulate: added to what the audited frames'
+// dense product left there); the range-0 workgroup also sums rho = sum P.
+constexpr int kPair = 2 * kBand;    // pixels per wave in the M-step
 __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
     const int4* __restrict__ groups, const int64_t* __restrict__ grp_off, int nranges,
-    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int64_t* __restrict__ fb_ptr,
-    const uint16_t* __restrict__ fb_off, int ntab, const u4* __restrict__ fb, const uint16_t* __restrict__ P,
-    const int32_t* __restrict__ cell_rot, int64_t ps, float* __restrict__ Wp, double* __restrict__ rho,
-    const double* __restrict__ rho_a, int accumulate) {
-  __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kBand * kKRow];  // 40960 bytes
+    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int2* __restrict__ band_range,
+    int64_t n_list, const u4* __restrict__ fb, const uint16_t* __restrict__ P, const int32_t* __restrict__ cell_rot,
+    int64_t ps, float* __restrict__ Wp, double* __restrict__ rho, const double* __restrict__ rho_a, int accumulate) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kPair * kKRow];  // 81920 bytes
   const int64_t g = blockIdx.x / nranges;
   const int pr = (int)(blockIdx.x % nranges);
   const int4 gr = groups[g];
@@ -314,53 +310,63 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
   const int32_t* cf = cf_frame + cf_ptr[c];
   const uint16_t* Pg = P + grp_off[g];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int band = pr * 4 + wave;
+  const int nbands = (int)(ps / kBand);
+  const int band = 2 * (pr * 4 + wave);  // first band of this wave's pair
   const int p0 = band * kBand;
-  if ((int64_t)p0 >= ps) return;  // no band for this wave (no barrier follows)
+  if (band >= nbands) return;  // no band for this wave (no barrier follows)
   const bool two = nr > 16;
   const bool do_rho = pr == 0 && wave == 0;
   const int n = lane & 15, kq = 8 * (lane >> 4);
   const int slot = lane & 31, par = lane >> 5;
 
-  uint16_t* rows = lds + wave * kBand * kKRow;
+  uint16_t* rows = lds + wave * kPair * kKRow;
   uint16_t* fcol = rows + slot;
-  for (int e = lane; e < kBand * kKRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = u4{0u, 0u, 0u, 0u};
+  for (int e = lane; e < kPair * kKRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = u4{0u, 0u, 0u, 0u};
 
-  f4 acc[8][2];
+  f4 acc[16][2];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) acc[i][0] = acc[i][1] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < 16; ++i) acc[i][0] = acc[i][1] = f4{0.f, 0.f, 0.f, 0.f};
   double rs0 = 0.0, rs1 = 0.0;
   const u4 zero = {0u, 0u, 0u, 0u};
   const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+  constexpr int kNext = kBand * kKRow;  // LDS offset of the pair's second band
 
-  // pipeline stages: block k (chunks in w0), k + 1 (table lo1/hi1), k + 2 (frame fr2)
+  // this lane's band of the pair and its LDS rows
+  const int2* rng = band_range + (int64_t)(band + par) * n_list;
+  uint16_t* fcol_b = fcol + par * kNext;
+  auto range_of = [&](int32_t fr) -> int2 { return fr < 0 ? int2{0, 0} : rng[fr]; };
   auto frame_at = [&](int64_t f0) -> int32_t { return f0 + slot < F ? cf[f0 + slot] : -1; };
-  int32_t fr0 = frame_at(0), fr1 = frame_at(kFB), fr2 = frame_at(2 * kFB);
-  const u4* src0 = fr0 >= 0 ? fb + fb_ptr[fr0] : fb;
-  const u4* src1 = fr1 >= 0 ? fb + fb_ptr[fr1] : fb;
-  int lo0 = fr0 >= 0 ? fb_off[(int64_t)fr0 * ntab + band] : 0;
-  int hi0 = fr0 >= 0 ? fb_off[(int64_t)fr0 * ntab + band + 1] : 0;
-  u4 w0 = lo0 + par < hi0 ? src0[lo0 + par] : pad;
-  int lo1 = fr1 >= 0 ? fb_off[(int64_t)fr1 * ntab + band] : 0;
-  int hi1 = fr1 >= 0 ? fb_off[(int64_t)fr1 * ntab + band + 1] : 0;
+  // B operand of a block: frames kq..kq+7 for rotation n (and n + 16)
+  auto load_p = [&](int64_t f0, u4& x0, u4& x1) {
+    const uint16_t* pblk = Pg + (f0 >> 5) * (kGR * kFB);
+    x0 = f0 < F ? *reinterpret_cast<const u4*>(pblk + n * kFB + kq) : zero;
+    x1 = f0 < F && two ? *reinterpret_cast<const u4*>(pblk + (16 + n) * kFB + kq) : zero;
+  };
+  // pipeline stages: block k (P in b0/b1, chunks in w0), k + 1 (range q1), k + 2 (frame fr2)
+  int2 q0 = range_of(frame_at(0));
+  const int32_t fr1 = frame_at(kFB);
+  int32_t fr2 = frame_at(2 * kFB);
+  u4 w0[kWin];
+#pragma unroll
+  for (int u = 0; u < kWin; ++u) w0[u] = q0.x + u < q0.y ? fb[q0.x + u] : pad;
+  int2 q1 = range_of(fr1);
+  u4 b0, b1;
+  load_p(0, b0, b1);
 
   for (int64_t f0 = 0; f0 < F; f0 += kFB) {
     const int nf = (int)(F - f0 < kFB ? F - f0 : kFB);
-    // B operand first (loads complete in issue order): frames kq..kq+7 of the block
-    // for rotation n (and n + 16)
-    const uint16_t* pblk = Pg + (f0 >> 5) * (kGR * kFB);
-    u4 b0 = *reinterpret_cast<const u4*>(pblk + n * kFB + kq);
-    u4 b1 = two ? *reinterpret_cast<const u4*>(pblk + (16 + n) * kFB + kq) : zero;
-    // prefetch
-    const u4 w1 = lo1 + par < hi1 ? src1[lo1 + par] : pad;
-    const u4* src2 = fr2 >= 0 ? fb + fb_ptr[fr2] : fb;
-    const int lo2 = fr2 >= 0 ? fb_off[(int64_t)fr2 * ntab + band] : 0;
-    const int hi2 = fr2 >= 0 ? fb_off[(int64_t)fr2 * ntab + band + 1] : 0;
+    // prefetch (loads complete in issue order, so this block's data, loaded one
+    // block ago, is waited on without waiting for these)
+    u4 b0n, b1n;
+    load_p(f0 + kFB, b0n, b1n);
+    u4 w1[kWin];
+#pragma unroll
+    for (int u = 0; u < kWin; ++u) w1[u] = q1.x + u < q1.y ? fb[q1.x + u] : pad;
+    const int2 q2 = range_of(fr2);
     const int32_t fr3 = frame_at(f0 + 3 * kFB);
-    if (fr0 >= 0) {
-      put_chunk<false>(fcol, kKRow, w0);
-      put_rest<false>(fcol, kKRow, src0, lo0 + par + 2, hi0, 2);
-    }
+#pragma unroll
+    for (int u = 0; u < kWin; ++u) put_chunk<false>(fcol_b, kKRow, w0[u]);
+    put_rest<false>(fcol_b, kKRow, fb, q0.x + kWin, q0.y, 1);
     if (nf < kFB) {  // frames past the list end hold no responsibility
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -378,24 +384,18 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
       }
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 16; ++i) {
       const bf8 av = *reinterpret_cast<const bf8*>(&rows[(16 * i + n) * kKRow + kq]);
       acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, b0), acc[i][0], 0, 0, 0);
       if (two) acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, b1), acc[i][1], 0, 0, 0);
     }
-    if (fr0 >= 0) {
-      put_chunk<true>(fcol, kKRow, w0);
-      put_rest<true>(fcol, kKRow, src0, lo0 + par + 2, hi0, 2);
-    }
-    fr0 = fr1;
-    src0 = src1;
-    lo0 = lo1;
-    hi0 = hi1;
-    w0 = w1;
-    fr1 = fr2;
-    src1 = src2;
-    lo1 = lo2;
-    hi1 = hi2;
+    for (int e = lane; e < kPair * kKRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = zero;
+    b0 = b0n;
+    b1 = b1n;
+    q0 = q1;
+    q1 = q2;
+#pragma unroll
+    for (int u = 0; u < kWin; ++u) w0[u] = w1[u];
     fr2 = fr3;
   }
 
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
     if (mr >= nr) continue;
     float* out = Wp + (int64_t)cell_rot[r0 + mr] * ps + p0 + 4 * (lane >> 4);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 16; ++i) {
       f4 v = acc[i][j];
       if (accumulate) v += *reinterpret_cast<const f4*>(out + 16 * i);
       *reinterpret_cast<f4*>(out + 16 * i) = v;
@@ -432,23 +432,19 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
 }
 
 // ------------------------------------------------------------------ band-blocked frames
-// Chunks per band of each listed frame (one wave per frame, two pixels per lane per
-// band): band_chunk[f][b] = first chunk of band b (relative), band_chunk[f][nb] and
-// cnt[f] = the frame's chunk count; counts above 256 (not exact in BF16) set *over.
+// Chunks of every (band, listed frame), band-major: cnt[b * n_frames + f] (one wave
+// per frame, two pixels per lane per band); counts above 256 (not exact in BF16)
+// set *over.
 __global__ __launch_bounds__(256) void band_count_kernel(const uint16_t* __restrict__ counts,
                                                          const uint8_t* __restrict__ mask, int n_pix,
                                                          const int32_t* __restrict__ frames, int64_t n_frames, int nb,
-                                                         uint16_t* __restrict__ band_chunk, int32_t* __restrict__ cnt,
-                                                         int32_t* __restrict__ over) {
+                                                         int32_t* __restrict__ cnt, int32_t* __restrict__ over) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= n_frames) return;  // uniform per wave
   const uint16_t* row = counts + (int64_t)frames[f] * n_pix;
-  uint16_t* tab = band_chunk + f * (nb + 1);
-  int run = 0;
   bool big = false;
   for (int b = 0; b < nb; ++b) {
-    if (lane == 0) tab[b] = (uint16_t)run;
     int n = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -457,32 +453,32 @@ __global__ __launch_bounds__(256) void band_count_kernel(const uint16_t* __restr
       big |= v > 256u;
       n += __popcll(__ballot(v != 0u));
     }
-    run += (n + 7) >> 3;
-  }
-  if (lane == 0) {
-    tab[nb] = (uint16_t)run;
-    cnt[f] = run;
+    if (lane == 0) cnt[(int64_t)b * n_frames + f] = (n + 7) >> 3;
   }
   if (__ballot(big) != 0ull && lane == 0) atomicOr(over, 1);
+}
+
+// band_range[e] = (ptr[e], ptr[e + 1]) as int32 chunk indices
+__global__ void band_range_kernel(const int64_t* __restrict__ ptr, int64_t n, int2* __restrict__ band_range) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    band_range[e] = make_int2((int)ptr[e], (int)ptr[e + 1]);
 }
 
 // Fill: words (pixel in band << 9 | count) in pixel order, chunk tails padded
 __global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restrict__ counts,
                                                         const uint8_t* __restrict__ mask, int n_pix,
                                                         const int32_t* __restrict__ frames, int64_t n_frames, int nb,
-                                                        const uint16_t* __restrict__ band_chunk,
-                                                        const int64_t* __restrict__ chunk_ptr,
+                                                        const int2* __restrict__ band_range,
                                                         uint16_t* __restrict__ words) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= n_frames) return;
   const uint16_t* row = counts + (int64_t)frames[f] * n_pix;
-  const uint16_t* tab = band_chunk + f * (nb + 1);
   const unsigned long long below = (1ull << lane) - 1ull;
   for (int b = 0; b < nb; ++b) {
-    const int c0 = tab[b], c1 = tab[b + 1];
-    if (c0 == c1) continue;  // uniform: empty band
-    uint16_t* out = words + (chunk_ptr[f] + c0) * 8;
+    const int2 r = band_range[(int64_t)b * n_frames + f];
+    if (r.x == r.y) continue;  // uniform: empty band
+    uint16_t* out = words + (int64_t)r.x * 8;
     int n = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -492,25 +488,23 @@ __global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restri
       if (v != 0u) out[n + __popcll(bal & below)] = (uint16_t)(((uint32_t)(64 * h + lane) << 9) | v);
       n += __popcll(bal);
     }
-    for (int t = n + lane; t < 8 * (c1 - c0); t += 64) out[t] = (uint16_t)kPad;
+    for (int t = n + lane; t < 8 * (r.y - r.x); t += 64) out[t] = (uint16_t)kPad;
   }
 }
 
 // b_f = sum over the frame's pixels of count * c[pixel], FP64; one wave per frame
-__global__ __launch_bounds__(256) void band_dot_kernel(const int64_t* __restrict__ chunk_ptr,
-                                                       const uint16_t* __restrict__ band_chunk, int nb,
+__global__ __launch_bounds__(256) void band_dot_kernel(const int2* __restrict__ band_range, int nb,
                                                        const uint16_t* __restrict__ words, int64_t n_frames,
                                                        const double* __restrict__ cvec, double* __restrict__ b) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= n_frames) return;
-  const uint16_t* tab = band_chunk + f * (nb + 1);
-  const uint16_t* w = words + chunk_ptr[f] * 8;
   double acc = 0.0;
   for (int band = 0; band < nb; ++band) {
-    const int a = 8 * tab[band], z = 8 * tab[band + 1];
-    for (int t = a + lane; t < z; t += 64) {
-      const uint32_t e = w[t];
+    const int2 r = band_range[(int64_t)band * n_frames + f];
+    const int64_t a = 8 * (int64_t)r.x, z = 8 * (int64_t)r.y;
+    for (int64_t t = a + lane; t < z; t += 64) {
+      const uint32_t e = words[t];
       if (e != kPad) acc += (double)(e & 511u) * cvec[band * kBand + (e >> 9)];
     }
   }
@@ -601,14 +595,13 @@ __global__ __launch_bounds__(256) void audit_recall_kernel(const __hip_bfloat16*
 
 // ===================================================================== launchers
 hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* groups, const int64_t* grp_off,
-                              const int64_t* cf_ptr, const int32_t* cf_frame, const int64_t* chunk_ptr,
-                              const uint16_t* band_chunk, int ntab, const void* chunks, const int32_t* cell_rot,
-                              const void* hilo, int64_t plane, const float* scale, int64_t ps, float* G,
-                              hipStream_t st) {
+                              const int64_t* cf_ptr, const int32_t* cf_frame, const int2* band_range, int64_t n_list,
+                              const void* chunks, const int32_t* cell_rot, const void* hilo, int64_t plane,
+                              const float* scale, int64_t ps, float* G, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  cand_loglik_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, chunk_ptr,
-                                                        band_chunk, ntab, (const u4*)chunks, cell_rot,
-                                                        (const uint16_t*)hilo, plane, scale, ps, G);
+  cand_loglik_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, band_range, n_list,
+                                                        (const u4*)chunks, cell_rot, (const uint16_t*)hilo, plane,
+                                                        scale, ps, G);
   return hipGetLastError();
 }
 
@@ -624,40 +617,46 @@ hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const 
 }
 
 hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
-                             const int32_t* cf_frame, const int64_t* chunk_ptr, const uint16_t* band_chunk, int ntab,
-                             const void* chunks, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
-                             double* rho, const double* rho_a, bool accumulate, hipStream_t st) {
+                             const int32_t* cf_frame, const int2* band_range, int64_t n_list, const void* chunks,
+                             const void* P, const int32_t* cell_rot, int64_t ps, float* Wp, double* rho,
+                             const double* rho_a, bool accumulate, hipStream_t st) {
   if (n_groups <= 0) return hipSuccess;
-  const int nranges = (int)((ps + kRange - 1) / kRange);
-  cand_mstep_kernel<<<(unsigned)(n_groups * nranges), 256, 0, st>>>(
-      groups, grp_off, nranges, cf_ptr, cf_frame, chunk_ptr, band_chunk, ntab, (const u4*)chunks, (const uint16_t*)P,
-      cell_rot, ps, Wp, rho, rho_a, accumulate ? 1 : 0);
+  const int nranges = (int)((ps + 4 * kPair - 1) / (4 * kPair));
+  cand_mstep_kernel<<<(unsigned)(n_groups * nranges), 256, 0, st>>>(groups, grp_off, nranges, cf_ptr, cf_frame,
+                                                                    band_range, n_list, (const u4*)chunks,
+                                                                    (const uint16_t*)P, cell_rot, ps, Wp, rho, rho_a,
+                                                                    accumulate ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_band_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                             int64_t n_frames, int ntab, uint16_t* band_chunk, int32_t* cnt, int32_t* over,
-                             hipStream_t st) {
+                             int64_t n_frames, int nbands, int32_t* cnt, int32_t* over, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
-  band_count_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, ntab - 1,
-                                                                    band_chunk, cnt, over);
+  band_count_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, nbands, cnt,
+                                                                    over);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_range(const int64_t* ptr, int64_t n, int2* band_range, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t g = (n + 255) / 256;
+  band_range_kernel<<<(unsigned)(g > 65536 ? 65536 : g), 256, 0, st>>>(ptr, n, band_range);
   return hipGetLastError();
 }
 
 hipError_t launch_band_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                            int64_t n_frames, int ntab, const uint16_t* band_chunk, const int64_t* chunk_ptr,
-                            void* chunks, hipStream_t st) {
+                            int64_t n_frames, int nbands, const int2* band_range, void* chunks, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
-  band_fill_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, ntab - 1,
-                                                                   band_chunk, chunk_ptr, (uint16_t*)chunks);
+  band_fill_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, nbands,
+                                                                   band_range, (uint16_t*)chunks);
   return hipGetLastError();
 }
 
-hipError_t launch_band_dot(const int64_t* chunk_ptr, const uint16_t* band_chunk, int ntab, const void* chunks,
-                           int64_t n_frames, const double* c, double* b, hipStream_t st) {
+hipError_t launch_band_dot(const int2* band_range, int nbands, const void* chunks, int64_t n_frames, const double* c,
+                           double* b, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
-  band_dot_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(chunk_ptr, band_chunk, ntab - 1,
-                                                                  (const uint16_t*)chunks, n_frames, c, b);
+  band_dot_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(band_range, nbands, (const uint16_t*)chunks,
+                                                                  n_frames, c, b);
   return hipGetLastError();
 }
 

@@ -154,26 +154,24 @@ hipError_t launch_scan64(const int64_t* cnt, int64_t n, int64_t* ptr, hipStream_
 
 // ---- candidate E/M steps (cand.hip) ----
 hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* groups, const int64_t* grp_off,
-                              const int64_t* cf_ptr, const int32_t* cf_frame, const int64_t* chunk_ptr,
-                              const uint16_t* band_chunk, int ntab, const void* chunks, const int32_t* cell_rot,
-                              const void* hilo, int64_t plane, const float* scale, int64_t ps, float* G,
-                              hipStream_t st);
+                              const int64_t* cf_ptr, const int32_t* cf_frame, const int2* band_range, int64_t n_list,
+                              const void* chunks, const int32_t* cell_rot, const void* hilo, int64_t plane,
+                              const float* scale, int64_t ps, float* G, hipStream_t st);
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
                              int64_t n_frames, const int32_t* cell_rot, const double* log_w, const double* S,
                              const double* b, double* L, hipStream_t st);
 hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
-                             const int32_t* cf_frame, const int64_t* chunk_ptr, const uint16_t* band_chunk, int ntab,
-                             const void* chunks, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
-                             double* rho, const double* rho_a, bool accumulate, hipStream_t st);
+                             const int32_t* cf_frame, const int2* band_range, int64_t n_list, const void* chunks,
+                             const void* P, const int32_t* cell_rot, int64_t ps, float* Wp, double* rho,
+                             const double* rho_a, bool accumulate, hipStream_t st);
 hipError_t launch_band_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                             int64_t n_frames, int ntab, uint16_t* band_chunk, int32_t* cnt, int32_t* over,
-                             hipStream_t st);
+                             int64_t n_frames, int nbands, int32_t* cnt, int32_t* over, hipStream_t st);
 hipError_t launch_band_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                            int64_t n_frames, int ntab, const uint16_t* band_chunk, const int64_t* chunk_ptr,
-                            void* chunks, hipStream_t st);
-hipError_t launch_band_dot(const int64_t* chunk_ptr, const uint16_t* band_chunk, int ntab, const void* chunks,
-                           int64_t n_frames, const double* c, double* b, hipStream_t st);
+                            int64_t n_frames, int nbands, const int2* band_range, void* chunks, hipStream_t st);
+hipError_t launch_band_range(const int64_t* ptr, int64_t n, int2* band_range, hipStream_t st);
+hipError_t launch_band_dot(const int2* band_range, int nbands, const void* chunks, int64_t n_frames, const double* c,
+                           double* b, hipStream_t st);
 hipError_t launch_cell_groups(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int32_t* cnt,
                               int64_t* cg_ptr, int4* groups, int64_t* gsize, int64_t* grp_off, int64_t g_max,
                               hipStream_t st);

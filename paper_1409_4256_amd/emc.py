@@ -62,7 +62,7 @@ class Problem(ctypes.Structure):
 class Proposal(ctypes.Structure):
     _fields_ = [
         ("n_cells", ctypes.c_int32), ("k_top", ctypes.c_int32), ("n_cand", ctypes.c_int32),
-        ("n_audit", ctypes.c_int32), ("words", ctypes.c_int32), ("ntab", ctypes.c_int32),
+        ("n_audit", ctypes.c_int32), ("words", ctypes.c_int32), ("n_bands", ctypes.c_int32),
         ("n_groups", ctypes.c_int64), ("n_tiles", ctypes.c_int64), ("n_g", ctypes.c_int64),
         ("n_chunks", ctypes.c_int64),
         ("cell_of", ctypes.c_void_p), ("cell_ptr", ctypes.c_void_p), ("cell_rot", ctypes.c_void_p),
@@ -70,7 +70,7 @@ class Proposal(ctypes.Structure):
         ("pair_col", ctypes.c_void_p), ("cf_ptr", ctypes.c_void_p), ("cf_frame", ctypes.c_void_p),
         ("cg_ptr", ctypes.c_void_p), ("groups", ctypes.c_void_p), ("grp_off", ctypes.c_void_p),
         ("tiles", ctypes.c_void_p), ("mask_audit", ctypes.c_void_p),
-        ("chunk_ptr", ctypes.c_void_p), ("chunks", ctypes.c_void_p), ("band_chunk", ctypes.c_void_p),
+        ("chunks", ctypes.c_void_p), ("band_range", ctypes.c_void_p),
     ]
 
 
