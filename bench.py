@@ -254,12 +254,14 @@ def proposal_form(inp, args, counts_dev):
     log(f"proposal: plan with {n_pairs} candidate (rotation, frame) pairs "
         f"({n_pairs / (wl.n_rot * wl.n_data):.4f} of the full search), {prop.plan.n_groups} rotation groups, "
         f"{prop.plan.n_tiles} tiles, built in {t_plan:.1f} s")
-    # proposal iterations, timed with the audit verdict and any fallback included
-    per, recs, fallbacks = [], [], 0
+    # proposal iterations, timed with the audit verdict and any fallback included; the
+    # library records events at its stage boundaries (per-kernel durations)
+    per, recs, fallbacks, stages = [], [], 0, []
     for it in range(max(2, args.steps)):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        sev = [torch.cuda.Event(enable_timing=True) for _ in range(emc.EMC_PROPOSED_STAGES + 1)]
         ev0.record()
-        prop.step(run.model[run.cur], run.model[1 - run.cur])
+        prop.step(run.model[run.cur], run.model[1 - run.cur], sev)
         ok = prop.accepted()
         if ok:
             run.cur = 1 - run.cur
@@ -270,13 +272,30 @@ def proposal_form(inp, args, counts_dev):
         torch.cuda.synchronize()
         per.append(ev0.elapsed_time(ev1))
         recs.append(prop.recall.item())
+        stages.append([sev[i].elapsed_time(sev[i + 1]) for i in range(emc.EMC_PROPOSED_STAGES)])
         log(f"proposal iteration {it + 1 + args.train_at}: {per[-1]:.1f} ms, audit recall {recs[-1]:.5f}, "
             f"{'accepted' if ok else 'fell back to full search'}")
         if not ok:              # the full posterior just computed becomes the new persistence source
             del prop
             prop = build(targets_now())
+    st_med = np.median(np.asarray(stages), axis=0)
+    steps_ms = {name: round(float(v), 3) for name, v in zip(emc.PROPOSED_STAGE_NAMES, st_med)}
+    # roofline of the dominant kernel (candidate M-step): the contraction over the
+    # candidate (rotation, frame) pairs, 2 flop per pair and valid pixel (BF16 MFMA)
+    n_valid = int(np.asarray(inp.mask).sum())
+    mstep_s = float(np.mean(np.asarray(stages)[:, emc.PROPOSED_STAGE_NAMES.index("cand_mstep")])) / 1e3
+    loglik_s = float(np.mean(np.asarray(stages)[:, emc.PROPOSED_STAGE_NAMES.index("cand_loglik")])) / 1e3
+    flops = 2.0 * n_pairs * n_valid
+    roof = {"bound": "mfma", "kernel": "cand_mstep_kernel (candidate M-step), emc_iterate_proposed",
+            "achieved": round(flops / mstep_s / 1e12, 2), "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": round(flops / mstep_s / 1e12 / 2500.0, 4), "traffic": None,
+            "algorithmic_flops_per_launch": flops,
+            "second": {"kernel": "cand_loglik_kernel (candidate log-likelihood)",
+                       "achieved": round(2.0 * flops / loglik_s / 1e12, 2), "unit": "TFLOP/s",
+                       "note": "hi + lo terms: 4 flop per pair and valid pixel"}}
     ms = float(np.mean(per))
-    return {"value": round(1000.0 / ms, 5), "ms_per_step": round(ms, 3), "recall": recs, "fallbacks": fallbacks,
+    return {"value": round(1000.0 / ms, 5), "ms_per_step": round(ms, 3), "steps_ms_median": steps_ms,
+            "roofline": roof, "recall": recs, "fallbacks": fallbacks,
             "schedule": f"full search for iterations 1-{args.train_at}, trained on iterations "
                         f"{args.train_at - 2}-{args.train_at}, proposal from iteration {args.train_at + 1}: "
                         f"network top-{k_net} cells U top-{k_prev} cells of the last full posterior",

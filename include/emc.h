@@ -346,15 +346,24 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
 /* Workspace bytes of emc_iterate_proposed. */
 emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan, size_t* bytes);
 
+/* Stages of emc_iterate_proposed, in order (stage_events[i], [i + 1] bracket stage i). */
+#define EMC_PROPOSED_STAGES 6  /* expansion; candidate log-likelihood (with b); candidate
+                                  E-step; audited frames (log-likelihood, E-step, recall,
+                                  dense M-step product); candidate M-step; compression,
+                                  division and mean log-evidence                        */
+
 /* One iteration with the E-step restricted to the proposal (pb->precision must
  * be EMC_PREC_BF16; pb->n_data = n_cand + n_audit):
  *   K_audit  frames plan->audit_frames packed by emc_pack_frames_list (the
- *            candidate frames are read from the plan's sparse lists)
+ *            candidate frames are read from the plan's sparse band format)
  *   loglik   mean log-evidence over all frames (each over its searched set)
- *   recall_mean  mean recall of the audited frames (NaN without audit)      */
+ *   recall_mean  mean recall of the audited frames (NaN without audit)
+ *   stage_events NULL, or EMC_PROPOSED_STAGES + 1 events recorded on the
+ *            stream at the stage boundaries (for timing; owned by the caller) */
 emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_audit,
                                 const float* model_in, float* model_out, double* loglik,
-                                double* recall_mean, void* ws, size_t ws_bytes, hipStream_t stream);
+                                double* recall_mean, void* ws, size_t ws_bytes,
+                                hipEvent_t* stage_events, hipStream_t stream);
 
 #ifdef __cplusplus
 }

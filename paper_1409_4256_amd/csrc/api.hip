@@ -872,7 +872,7 @@ emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposa
 
 emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_audit,
                                 const float* model_in, float* model_out, double* loglik, double* recall_mean,
-                                void* ws, size_t ws_bytes, hipStream_t st) {
+                                void* ws, size_t ws_bytes, hipEvent_t* stage_events, hipStream_t st) {
   CHECK(check_problem(pb, true));
   if (!is_bf16(pb)) return fail(EMC_ERR_UNSUPPORTED, "the proposal form runs in BF16 precision");
   CHECK(check_plan(pb, plan));
@@ -905,8 +905,14 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   double* num = (double*)(w + W.num);
   double* den = (double*)(w + W.den);
   const int4* groups = (const int4*)plan->groups;
+  auto mark = [&](int i) -> emc_status {
+    if (stage_events) HIP_TRY(hipEventRecord(stage_events[i], st), "stage event");
+    return EMC_OK;
+  };
+  CHECK(mark(0));
   // expansion (BF16 hi + lo slices with their row scales)
   CHECK(run_expand(pb, model_in, c, slices, S, scale, st));
+  CHECK(mark(1));
   // candidate frames: log-likelihoods per (group, listed frame), E-step over each frame's candidates
   if (nc > 0) {
     HIP_TRY(launch_band_dot((const int2*)plan->band_range, plan->n_bands, plan->chunks, nc, c, b, st), "band dot");
@@ -914,10 +920,14 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
                                plan->cf_frame, (const int2*)plan->band_range, nc, plan->chunks, plan->cell_rot,
                                slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
             "candidate loglik");
+  }
+  CHECK(mark(2));
+  if (nc > 0) {
     HIP_TRY(launch_cand_estep(G, Pc, groups, plan->grp_off, plan->cg_ptr, plan->cand_cells, plan->pair_col,
                               plan->k_top, nc, plan->cell_rot, pb->log_w, S, b, L, st),
             "candidate estep");
   }
+  CHECK(mark(3));
   // audited frames: full search, recall of the proposal
   HIP_TRY(launch_fill_zero_f64(recall, (size_t)na, st), "zero recall");
   emc_problem pa = *pb;
@@ -935,15 +945,18 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
     const char* KTa = (const char*)K_audit + (size_t)na * ps * 2;
     HIP_TRY(launch_gemm_bf16_nt(Pa, KTa, Wp, pb->n_rot, ps, dsa, dsa, dsa, ps, st), "audit mstep gemm");
   }
+  CHECK(mark(4));
   HIP_TRY(launch_cand_mstep(groups, plan->grp_off, plan->n_groups, plan->cf_ptr, plan->cf_frame,
                             (const int2*)plan->band_range, nc, plan->chunks, Pc, plan->cell_rot, ps, Wp, rho, rho_a,
                             na > 0, st),
           "candidate mstep");
+  CHECK(mark(5));
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
   HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");
   HIP_TRY(launch_scatter(Wp, ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, st),
           "scatter");
   CHECK(run_finalize(pb, num, den, model_in, model_out, L, nc + na, loglik, st));
+  CHECK(mark(6));
   return EMC_OK;
 }
 

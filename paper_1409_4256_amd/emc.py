@@ -125,7 +125,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_proposal_build.restype = st
     lib.emc_proposed_workspace_bytes.argtypes = [_PB, _PP, szp]
     lib.emc_proposed_workspace_bytes.restype = st
-    lib.emc_iterate_proposed.argtypes = [_PB, _PP, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    lib.emc_iterate_proposed.argtypes = [_PB, _PP, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]
     lib.emc_iterate_proposed.restype = st
     _lib = lib
     return lib
@@ -488,18 +488,31 @@ def emc_proposed_workspace_bytes(geo: Geometry, plan: Proposal) -> int:
     return int(n.value)
 
 
+EMC_PROPOSED_STAGES = 6
+PROPOSED_STAGE_NAMES = ("expand", "cand_loglik", "cand_estep", "audit", "cand_mstep", "compress")
+
+
 def emc_iterate_proposed(geo: Geometry, plan: Proposal, K_audit, model_in, model_out, loglik, recall_mean, ws,
-                         stream=None):
+                         stage_events=None, stream=None):
+    """stage_events: None or EMC_PROPOSED_STAGES + 1 torch.cuda.Event(enable_timing=True) objects."""
     import torch
 
     M = geo.grid_n ** 3
+    evs = None
+    if stage_events is not None:
+        if len(stage_events) != EMC_PROPOSED_STAGES + 1:
+            raise ValueError(f"need {EMC_PROPOSED_STAGES + 1} stage events")
+        for ev in stage_events:
+            if not ev.cuda_event:            # the event is created on its first record
+                ev.record()
+        evs = (ctypes.c_void_p * len(stage_events))(*[ctypes.c_void_p(ev.cuda_event) for ev in stage_events])
     _check(load().emc_iterate_proposed(
         ctypes.byref(geo.pb), ctypes.byref(plan),
         _ptr(K_audit, None, None, "K_audit") if plan.n_audit else None,
         _ptr(model_in, torch.float32, M, "model_in"), _ptr(model_out, torch.float32, M, "model_out"),
         _ptr(loglik, torch.float64, 1, "loglik"), _ptr(recall_mean, torch.float64, 1, "recall_mean"),
         _ptr(ws, torch.uint8, emc_proposed_workspace_bytes(geo, plan), "ws"),
-        ctypes.c_size_t(ws.numel()), _stream(stream)))
+        ctypes.c_size_t(ws.numel()), evs, _stream(stream)))
 
 
 def plan_array(buf, address: int, n: int, dtype):

@@ -157,8 +157,9 @@ class ProposedIteration:
         F = cf_ptr[1:] - cf_ptr[:-1]
         return int((groups[:, 2] * F[groups[:, 0]]).sum().item())
 
-    def step(self, model_in, model_out):
-        E.emc_iterate_proposed(self.geo, self.plan, self.Ka, model_in, model_out, self.loglik, self.recall, self.ws)
+    def step(self, model_in, model_out, stage_events=None):
+        E.emc_iterate_proposed(self.geo, self.plan, self.Ka, model_in, model_out, self.loglik, self.recall, self.ws,
+                               stage_events)
 
     def accepted(self) -> bool:
         """The audit's verdict on the last step (synchronises)."""
