@@ -323,6 +323,14 @@ typedef struct emc_proposal {
                              stored band-major (band 0 of all frames first)        */
   int32_t* band_range;    /* [n_bands][n_cand][2] chunk range (first, end) of band
                              b of frame f, absolute chunk indices                  */
+  int32_t n_dense;        /* dense bands (frames average >= 3 chunks; <= 16): their
+                             M-step columns are one dense product                  */
+  int32_t reserved2;
+  int64_t ld_dense;       /* n_cand rounded up to 256                               */
+  int32_t* dense_band;    /* [n_bands] index among the dense bands, or -1           */
+  int32_t* dense_list;    /* [16] band of each dense index                          */
+  void* kt_dense;         /* [n_dense * 128][ld_dense] BF16 pixel-major counts of the
+                             dense bands' pixels over the candidate frames         */
 } emc_proposal;
 
 /* Bytes of the plan buffer; nz_cap bounds the non-zero pixels of the frames. */

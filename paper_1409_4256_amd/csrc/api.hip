@@ -582,6 +582,7 @@ constexpr int kMaxTop = 256;      // proposed cells per frame
 constexpr int kBandPx = 128;      // granularity of the entry-offset table (the kernels' band)
 constexpr int kTileFrames = 64;   // frames per candidate log-likelihood tile
 constexpr int kGroupRot = 32;     // rotations per group
+constexpr int kMaxDense = 16;     // bands handled by the M-step's dense product (at most)
 
 int64_t group_cap(int n_rot, int n_cells) { return (int64_t)n_cells + (n_rot + kGroupRot - 1) / kGroupRot; }
 int64_t tile_cap(int64_t g_max, int64_t n_cand) {
@@ -595,8 +596,8 @@ int64_t chunk_cap(int64_t nz_cap, int64_t n_cand, int n_pix) { return (nz_cap + 
 // Carving of the plan buffer (capacities known before the build).
 struct PlanLayout {
   size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, cg_ptr,
-      groups, grp_off, tiles, mask_audit, chunks, band_range, band_cnt, band_ptr, hist, cursor, keys, order, mark,
-      frame_ptr, gsize, xcd, cnt, scalars, total;
+      groups, grp_off, tiles, mask_audit, chunks, band_range, band_cnt, band_ptr, dense_band, dense_list, kt_dense,
+      band_mean, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd, cnt, scalars, total;
 };
 
 PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top, int n_audit, int64_t nz_cap) {
@@ -631,6 +632,10 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.band_range = take(n_fb * 8);
   L.band_cnt = take(n_fb * 4);
   L.band_ptr = take((n_fb + 1) * 8);
+  L.dense_band = take((int64_t)(ntab_of(n_pix) - 1) * 4);
+  L.dense_list = take(kMaxDense * 4);
+  L.kt_dense = take((int64_t)kMaxDense * kBandPx * round_up(n_cand, 256) * 2);
+  L.band_mean = take((int64_t)(ntab_of(n_pix) - 1) * 4);
   L.hist = take(nkeys * 4);
   L.cursor = take(nkeys * 4);
   L.keys = take(std::max<int64_t>(n_pairs, n_data) * 4);
@@ -740,6 +745,10 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   int32_t* band_cnt = (int32_t*)(b + L.band_cnt);
   int64_t* band_ptr = (int64_t*)(b + L.band_ptr);
   const int64_t n_fb = n_cand * (ntab - 1);
+  P.dense_band = (int32_t*)(b + L.dense_band);
+  P.dense_list = (int32_t*)(b + L.dense_list);
+  P.kt_dense = (void*)(b + L.kt_dense);
+  P.ld_dense = round_up(n_cand, 256);
   int32_t* hist = (int32_t*)(b + L.hist);
   int32_t* cursor = (int32_t*)(b + L.cursor);
   int32_t* keys = (int32_t*)(b + L.keys);
@@ -782,8 +791,13 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   HIP_TRY(launch_band_count(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab - 1, band_cnt, over, st),
           "band count");
   HIP_TRY(launch_scan(band_cnt, n_fb, band_ptr, st), "chunk offsets");
-  int64_t host[5] = {0, 0, 0, 0, 0};
+  int32_t* n_dense_dev = (int32_t*)(scal + 2);
+  HIP_TRY(launch_dense_bands(band_cnt, n_cand, ntab - 1, (float*)(b + L.band_mean), P.dense_band, P.dense_list,
+                             n_dense_dev, st),
+          "dense bands");
+  int64_t host[6] = {0, 0, 0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(&host[0], scal, 16, hipMemcpyDeviceToHost, st), "read n_tiles");
+  HIP_TRY(hipMemcpyAsync(&host[5], n_dense_dev, 4, hipMemcpyDeviceToHost, st), "read n_dense");
   HIP_TRY(hipMemcpyAsync(&host[2], P.cg_ptr + n_cells, 8, hipMemcpyDeviceToHost, st), "read n_groups");
   HIP_TRY(hipMemcpyAsync(&host[3], P.grp_off + g_max, 8, hipMemcpyDeviceToHost, st), "read n_g");
   HIP_TRY(hipMemcpyAsync(&host[4], band_ptr + n_fb, 8, hipMemcpyDeviceToHost, st), "read n_chunks");
@@ -799,6 +813,10 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   HIP_TRY(launch_band_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab - 1, (const int2*)P.band_range,
                            P.chunks, st),
           "band fill");
+  P.n_dense = (int32_t)host[5];
+  HIP_TRY(launch_dense_pack(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.ld_dense, P.n_dense, P.dense_list,
+                            P.kt_dense, st),
+          "dense pack");
   P.n_tiles = host[0];
   P.n_groups = host[2];
   P.n_g = host[3];
@@ -812,7 +830,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
 namespace {
 
 struct PropWs {
-  size_t slices, S, scale, c, b, L, G, P, Ga, Pa, stats_a, rho_a, recall, rho, num, den, total;
+  size_t slices, S, scale, c, b, L, G, P, Ga, Pa, stats_a, rho_a, recall, rho, num, den, Pd, Wd, total;
 };
 
 PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
@@ -843,6 +861,8 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
   W.rho = take((int64_t)pb->n_rot * 8);
   W.num = take(grid * 8);
   W.den = take(grid * 8);
+  W.Pd = take(P->n_dense > 0 ? (int64_t)pb->n_rot * P->ld_dense * 2 : 0);
+  W.Wd = take((int64_t)pb->n_rot * P->n_dense * kBandPx * 4);
   W.total = o;
   return W;
 }
@@ -853,7 +873,8 @@ emc_status check_plan(const emc_problem* pb, const emc_proposal* P) {
     return fail(EMC_ERR_INVALID_ARG, "plan frames (%d + %d) do not match n_data %d", P->n_cand, P->n_audit, pb->n_data);
   if (P->k_top < 1 || P->k_top > kMaxTop || P->n_cells < 1 || P->words != words_of(P->n_cells) || P->n_g < 0 ||
       P->n_tiles < 0 || P->n_tiles % 8 != 0 || P->n_groups < 1 || P->n_groups > group_cap(pb->n_rot, P->n_cells) ||
-      P->n_bands != ntab_of(pb->n_pix) - 1)
+      P->n_bands != ntab_of(pb->n_pix) - 1 || P->n_dense < 0 || P->n_dense > kMaxDense ||
+      P->ld_dense != round_up(P->n_cand, 256))
     return fail(EMC_ERR_INVALID_ARG, "inconsistent plan");
   return EMC_OK;
 }
@@ -904,6 +925,8 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   double* rho = (double*)(w + W.rho);
   double* num = (double*)(w + W.num);
   double* den = (double*)(w + W.den);
+  void* Pd = plan->n_dense > 0 ? (void*)(w + W.Pd) : nullptr;
+  float* Wd = (float*)(w + W.Wd);
   const int4* groups = (const int4*)plan->groups;
   auto mark = [&](int i) -> emc_status {
     if (stage_events) HIP_TRY(hipEventRecord(stage_events[i], st), "stage event");
@@ -923,8 +946,10 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   }
   CHECK(mark(2));
   if (nc > 0) {
+    // the dense bands' responsibility matrix is zero outside the candidate pairs
+    if (Pd) HIP_TRY(launch_fill_zero_bytes(Pd, (int64_t)pb->n_rot * plan->ld_dense * 2, st), "zero dense P");
     HIP_TRY(launch_cand_estep(G, Pc, groups, plan->grp_off, plan->cg_ptr, plan->cand_cells, plan->pair_col,
-                              plan->k_top, nc, plan->cell_rot, pb->log_w, S, b, L, st),
+                              plan->k_top, nc, plan->cell_rot, pb->log_w, S, b, L, Pd, plan->ld_dense, st),
             "candidate estep");
   }
   CHECK(mark(3));
@@ -947,9 +972,16 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   }
   CHECK(mark(4));
   HIP_TRY(launch_cand_mstep(groups, plan->grp_off, plan->n_groups, plan->cf_ptr, plan->cf_frame,
-                            (const int2*)plan->band_range, nc, plan->chunks, Pc, plan->cell_rot, ps, Wp, rho, rho_a,
-                            na > 0, st),
+                            (const int2*)plan->band_range, nc, plan->chunks, plan->dense_band, Pc, plan->cell_rot, ps,
+                            Wp, rho, rho_a, na > 0, st),
           "candidate mstep");
+  if (Pd && nc > 0) {  // dense bands: W'[:, centre] += P_dense K_centre^T over all candidate frames
+    const int64_t nd = (int64_t)plan->n_dense * kBandPx;
+    HIP_TRY(launch_gemm_bf16_nt(Pd, plan->kt_dense, Wd, pb->n_rot, nd, plan->ld_dense, plan->ld_dense,
+                                plan->ld_dense, nd, st),
+            "dense mstep gemm");
+    HIP_TRY(launch_dense_add(Wd, pb->n_rot, plan->n_dense, plan->dense_list, ps, Wp, st), "dense add");
+  }
   CHECK(mark(5));
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
   HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");

@@ -230,13 +230,15 @@ __device__ __forceinline__ void lse_push(double& mx, double& s, double a) {
 
 // One wave per candidate frame; lanes take the frame's proposed cells (slot t =
 // lane + 64 u).  a = Q + log w_j = G + b_f - S_j + log w_j, log-evidence over the
-// frame's candidates in FP64, P = exp(a - L) stored in BF16 (eq. 2.4).
+// frame's candidates in FP64, P = exp(a - L) stored in BF16 (eq. 2.4); with Pd,
+// also into the dense [rotation][frame] matrix (zero elsewhere) of the M-step's
+// dense bands.
 __global__ __launch_bounds__(256) void cand_estep_kernel(
     const float* __restrict__ G, uint16_t* __restrict__ P, const int4* __restrict__ groups,
     const int64_t* __restrict__ grp_off, const int64_t* __restrict__ cg_ptr, const int32_t* __restrict__ cells,
     const int32_t* __restrict__ pair_col, int k_top, int64_t n_frames, const int32_t* __restrict__ cell_rot,
     const double* __restrict__ log_w, const double* __restrict__ S, const double* __restrict__ b,
-    double* __restrict__ L) {
+    double* __restrict__ L, uint16_t* __restrict__ Pd, int64_t ldd) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= n_frames) return;  // uniform per wave
@@ -278,8 +280,9 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
       for (int r = 0; r < gr.z; ++r) {
         const int j = cell_rot[gr.y + r];
         const double a = ((double)row[r] + bk) + (log_w[j] - S[j]);
-        const __hip_bfloat16 p = __float2bfloat16((float)exp(a - lse));
-        pb[r * kFB] = __builtin_bit_cast(uint16_t, p);
+        const uint16_t p = __builtin_bit_cast(uint16_t, __float2bfloat16((float)exp(a - lse)));
+        pb[r * kFB] = p;
+        if (Pd) Pd[(int64_t)j * ldd + f] = p;
       }
     }
   }
@@ -293,14 +296,16 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
 // block's P (B operand, read straight from its blocked layout) and clears the
 // rows.  The next block's P and chunks, the chunk ranges of the block after and
 // the frame indices of the one after that are loaded while the current block's
-// MFMAs run.  W' rows are written (accumulate: added to what the audited frames'
+// MFMAs run.  Dense bands (the detector centre, where every frame has photons)
+// are skipped: their W' columns are one dense product over the whole frame set.  W' rows are written (accumulate: added to what the audited frames'
 // dense product left there); the range-0 workgroup also sums rho = sum P.
 constexpr int kPair = 2 * kBand;    // pixels per wave in the M-step
 __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
     const int4* __restrict__ groups, const int64_t* __restrict__ grp_off, int nranges,
     const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int2* __restrict__ band_range,
-    int64_t n_list, const u4* __restrict__ fb, const uint16_t* __restrict__ P, const int32_t* __restrict__ cell_rot,
-    int64_t ps, float* __restrict__ Wp, double* __restrict__ rho, const double* __restrict__ rho_a, int accumulate) {
+    int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ dense_band, const uint16_t* __restrict__ P,
+    const int32_t* __restrict__ cell_rot, int64_t ps, float* __restrict__ Wp, double* __restrict__ rho,
+    const double* __restrict__ rho_a, int accumulate) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kPair * kKRow];  // 81920 bytes
   const int64_t g = blockIdx.x / nranges;
   const int pr = (int)(blockIdx.x % nranges);
@@ -331,10 +336,12 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
   const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
   constexpr int kNext = kBand * kKRow;  // LDS offset of the pair's second band
 
-  // this lane's band of the pair and its LDS rows
+  // this lane's band of the pair and its LDS rows; a dense band's rows stay zero
+  // here (its pixels come from the dense product)
   const int2* rng = band_range + (int64_t)(band + par) * n_list;
+  const bool sparse = dense_band[band + par] < 0;
   uint16_t* fcol_b = fcol + par * kNext;
-  auto range_of = [&](int32_t fr) -> int2 { return fr < 0 ? int2{0, 0} : rng[fr]; };
+  auto range_of = [&](int32_t fr) -> int2 { return fr < 0 || !sparse ? int2{0, 0} : rng[fr]; };
   auto frame_at = [&](int64_t f0) -> int32_t { return f0 + slot < F ? cf[f0 + slot] : -1; };
   // B operand of a block: frames kq..kq+7 for rotation n (and n + 16)
   auto load_p = [&](int64_t f0, u4& x0, u4& x1) {
@@ -512,6 +519,74 @@ __global__ __launch_bounds__(256) void band_dot_kernel(const int2* __restrict__ 
   if (lane == 0) b[f] = acc;
 }
 
+// Dense bands: band b is dense when its frames average at least kDenseChunks
+// chunks; dense_band[b] = its index among the dense bands (ascending b, at most
+// kMaxDense) or -1, dense_list[d] = band of dense index d, *n_dense.  One
+// workgroup per band sums the chunk counts, then one thread assigns the indices.
+constexpr int kDenseChunks = 3;
+constexpr int kMaxDense = 16;
+__global__ __launch_bounds__(256) void band_mean_kernel(const int32_t* __restrict__ cnt, int64_t n_frames,
+                                                        float* __restrict__ mean) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int64_t f = threadIdx.x; f < n_frames; f += 256) s += cnt[(int64_t)b * n_frames + f];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) mean[b] = n_frames > 0 ? (float)(((red[0] + red[1]) + (red[2] + red[3])) / n_frames) : 0.0f;
+}
+__global__ void dense_pick_kernel(const float* __restrict__ mean, int nb, int32_t* __restrict__ dense_band,
+                                  int32_t* __restrict__ dense_list, int32_t* __restrict__ n_dense) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int d = 0;
+  for (int b = 0; b < nb; ++b) {
+    const bool dense = mean[b] >= (float)kDenseChunks && d < kMaxDense;
+    dense_band[b] = dense ? d : -1;
+    if (dense) dense_list[d++] = b;
+  }
+  *n_dense = d;
+}
+
+// Pixel-major counts of the dense bands: KT[d * 128 + p][f] = count of candidate
+// frame f at pixel 128 dense_list[d] + p (BF16, 0 when masked; columns past
+// n_frames are 0).  64 x 64 tiles transposed through LDS.
+__global__ __launch_bounds__(256) void dense_pack_kernel(const uint16_t* __restrict__ counts,
+                                                         const uint8_t* __restrict__ mask, int n_pix,
+                                                         const int32_t* __restrict__ frames, int64_t n_frames,
+                                                         int64_t ld, const int32_t* __restrict__ dense_list,
+                                                         uint16_t* __restrict__ KT) {
+  __shared__ uint16_t tile[64][66];
+  const int64_t r0 = (int64_t)blockIdx.x * 64, f0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {  // r: frame within tile, tx: dense pixel row within tile
+    const int64_t f = f0 + r, row = r0 + tx;
+    const int i = dense_list[row >> 7] * kBand + (int)(row & (kBand - 1));
+    uint32_t v = 0;
+    if (f < n_frames && i < n_pix && mask[i]) v = counts[(int64_t)frames[f] * n_pix + i];
+    tile[r][tx] = count_bf16(v);
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) KT[(r0 + r) * ld + f0 + tx] = tile[tx][r];  // r: row, tx: frame
+}
+
+// W'[j][128 dense_list[d] + p] += D[j][128 d + p]
+__global__ void dense_add_kernel(const float* __restrict__ D, int64_t n_rot, int n_dense,
+                                 const int32_t* __restrict__ dense_list, int64_t ps, float* __restrict__ Wp) {
+  const int64_t cols = (int64_t)n_dense * kBand;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n_rot * cols; e += (int64_t)gridDim.x * 256) {
+    const int64_t j = e / cols;
+    const int c = (int)(e - j * cols);
+    Wp[j * ps + (int64_t)dense_list[c >> 7] * kBand + (c & (kBand - 1))] += D[e];
+  }
+}
+
+// zero fill, 16 bytes per store (n16 = bytes / 16)
+__global__ void fill_zero16_kernel(u4* __restrict__ p, int64_t n16) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n16; e += (int64_t)gridDim.x * 256)
+    p[e] = u4{0u, 0u, 0u, 0u};
+}
+
 // groups of 32 rotations: count per cell
 __global__ void cell_group_count_kernel(const int64_t* __restrict__ cell_ptr, int n_cells, int32_t* __restrict__ cnt) {
   const int c = blockIdx.x * 256 + threadIdx.x;
@@ -608,22 +683,22 @@ hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* gr
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
                              int64_t n_frames, const int32_t* cell_rot, const double* log_w, const double* S,
-                             const double* b, double* L, hipStream_t st) {
+                             const double* b, double* L, void* Pd, int64_t ldd, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
   cand_estep_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(G, (uint16_t*)P, groups, grp_off, cg_ptr, cells,
                                                                     pair_col, k_top, n_frames, cell_rot, log_w, S, b,
-                                                                    L);
+                                                                    L, (uint16_t*)Pd, ldd);
   return hipGetLastError();
 }
 
 hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
                              const int32_t* cf_frame, const int2* band_range, int64_t n_list, const void* chunks,
-                             const void* P, const int32_t* cell_rot, int64_t ps, float* Wp, double* rho,
-                             const double* rho_a, bool accumulate, hipStream_t st) {
+                             const int32_t* dense_band, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
+                             double* rho, const double* rho_a, bool accumulate, hipStream_t st) {
   if (n_groups <= 0) return hipSuccess;
   const int nranges = (int)((ps + 4 * kPair - 1) / (4 * kPair));
   cand_mstep_kernel<<<(unsigned)(n_groups * nranges), 256, 0, st>>>(groups, grp_off, nranges, cf_ptr, cf_frame,
-                                                                    band_range, n_list, (const u4*)chunks,
+                                                                    band_range, n_list, (const u4*)chunks, dense_band,
                                                                     (const uint16_t*)P, cell_rot, ps, Wp, rho, rho_a,
                                                                     accumulate ? 1 : 0);
   return hipGetLastError();
@@ -657,6 +732,40 @@ hipError_t launch_band_dot(const int2* band_range, int nbands, const void* chunk
   if (n_frames <= 0) return hipSuccess;
   band_dot_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(band_range, nbands, (const uint16_t*)chunks,
                                                                   n_frames, c, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_bands(const int32_t* cnt, int64_t n_frames, int nbands, float* mean, int32_t* dense_band,
+                              int32_t* dense_list, int32_t* n_dense, hipStream_t st) {
+  if (n_frames > 0 && nbands > 0) band_mean_kernel<<<(unsigned)nbands, 256, 0, st>>>(cnt, n_frames, mean);
+  else if (nbands > 0) launch_fill_i32(reinterpret_cast<int32_t*>(mean), nbands, 0, st);
+  dense_pick_kernel<<<1, 64, 0, st>>>(mean, nbands, dense_band, dense_list, n_dense);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_pack(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
+                             int64_t n_frames, int64_t ld, int n_dense, const int32_t* dense_list, void* KT,
+                             hipStream_t st) {
+  if (n_dense <= 0 || ld <= 0) return hipSuccess;
+  const dim3 grid((unsigned)(n_dense * kBand / 64), (unsigned)(ld / 64));
+  dense_pack_kernel<<<grid, 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, ld, dense_list, (uint16_t*)KT);
+  return hipGetLastError();
+}
+
+hipError_t launch_dense_add(const float* D, int64_t n_rot, int n_dense, const int32_t* dense_list, int64_t ps,
+                            float* Wp, hipStream_t st) {
+  const int64_t n = n_rot * n_dense * kBand;
+  if (n <= 0) return hipSuccess;
+  const int64_t g = (n + 255) / 256;
+  dense_add_kernel<<<(unsigned)(g > 65536 ? 65536 : g), 256, 0, st>>>(D, n_rot, n_dense, dense_list, ps, Wp);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero_bytes(void* p, int64_t bytes, hipStream_t st) {
+  const int64_t n16 = bytes / 16;
+  if (n16 <= 0) return hipSuccess;
+  const int64_t g = (n16 + 255) / 256;
+  fill_zero16_kernel<<<(unsigned)(g > 65536 ? 65536 : g), 256, 0, st>>>((u4*)p, n16);
   return hipGetLastError();
 }
 

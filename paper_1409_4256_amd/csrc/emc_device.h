@@ -160,11 +160,19 @@ hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* gr
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
                              int64_t n_frames, const int32_t* cell_rot, const double* log_w, const double* S,
-                             const double* b, double* L, hipStream_t st);
+                             const double* b, double* L, void* Pd, int64_t ldd, hipStream_t st);
 hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
                              const int32_t* cf_frame, const int2* band_range, int64_t n_list, const void* chunks,
-                             const void* P, const int32_t* cell_rot, int64_t ps, float* Wp, double* rho,
-                             const double* rho_a, bool accumulate, hipStream_t st);
+                             const int32_t* dense_band, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
+                             double* rho, const double* rho_a, bool accumulate, hipStream_t st);
+hipError_t launch_dense_bands(const int32_t* cnt, int64_t n_frames, int nbands, float* mean, int32_t* dense_band,
+                              int32_t* dense_list, int32_t* n_dense, hipStream_t st);
+hipError_t launch_dense_pack(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
+                             int64_t n_frames, int64_t ld, int n_dense, const int32_t* dense_list, void* KT,
+                             hipStream_t st);
+hipError_t launch_dense_add(const float* D, int64_t n_rot, int n_dense, const int32_t* dense_list, int64_t ps,
+                            float* Wp, hipStream_t st);
+hipError_t launch_fill_zero_bytes(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_band_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
                              int64_t n_frames, int nbands, int32_t* cnt, int32_t* over, hipStream_t st);
 hipError_t launch_band_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,

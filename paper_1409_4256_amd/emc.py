@@ -71,6 +71,8 @@ class Proposal(ctypes.Structure):
         ("cg_ptr", ctypes.c_void_p), ("groups", ctypes.c_void_p), ("grp_off", ctypes.c_void_p),
         ("tiles", ctypes.c_void_p), ("mask_audit", ctypes.c_void_p),
         ("chunks", ctypes.c_void_p), ("band_range", ctypes.c_void_p),
+        ("n_dense", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("ld_dense", ctypes.c_int64),
+        ("dense_band", ctypes.c_void_p), ("dense_list", ctypes.c_void_p), ("kt_dense", ctypes.c_void_p),
     ]
 
 

@@ -118,10 +118,18 @@ def test_union_lists_ragged_and_multi_group_cells(gpu_lib):
     assert r["plan"].n_groups > r["plan"].n_cells
 
 
+def test_sparse_bands_only(gpu_lib):
+    """~40 photons per frame: no band is dense, the M-step is the sparse path alone."""
+    r = _run(8, 20, 300, 700, 500, 40, 8, 12, photons=40.0)
+    assert r["plan"].n_dense == 0
+    _check_restricted(r, 500, "sparse bands only")
+
+
 def test_dense_bands(gpu_lib):
     """~3000 photons over 300 pixels: most pixels of a 128-pixel band are non-zero in
     every frame (more entries per band than a wave has lanes)."""
     r = _run(6, 20, 300, 600, 400, 24, 6, 16, photons=3000.0)
+    assert r["plan"].n_dense == r["plan"].n_bands
     _check_restricted(r, 400, "dense bands")
 
 
