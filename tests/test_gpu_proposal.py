@@ -129,7 +129,7 @@ def test_dense_bands(gpu_lib):
     """~3000 photons over 300 pixels: most pixels of a 128-pixel band are non-zero in
     every frame (more entries per band than a wave has lanes)."""
     r = _run(6, 20, 300, 600, 400, 24, 6, 16, photons=3000.0)
-    assert r["plan"].n_dense == r["plan"].n_bands
+    assert 0 < r["plan"].n_dense < r["plan"].n_bands   # the padding band past n_pix stays sparse (empty)
     _check_restricted(r, 400, "dense bands")
 
 
