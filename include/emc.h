@@ -331,6 +331,8 @@ typedef struct emc_proposal {
   int32_t* dense_list;    /* [16] band of each dense index                          */
   void* kt_dense;         /* [n_dense * 128][ld_dense] BF16 pixel-major counts of the
                              dense bands' pixels over the candidate frames         */
+  void* dense_rows;       /* [n_dense][n_cand][128] BF16 frame-major counts of the
+                             dense bands (the log-likelihood's operand there)      */
 } emc_proposal;
 
 /* Bytes of the plan buffer; nz_cap bounds the non-zero pixels of the frames. */
@@ -355,10 +357,11 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
 emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan, size_t* bytes);
 
 /* Stages of emc_iterate_proposed, in order (stage_events[i], [i + 1] bracket stage i). */
-#define EMC_PROPOSED_STAGES 6  /* expansion; candidate log-likelihood (with b); candidate
+#define EMC_PROPOSED_STAGES 7  /* expansion; candidate log-likelihood (with b); candidate
                                   E-step; audited frames (log-likelihood, E-step, recall,
-                                  dense M-step product); candidate M-step; compression,
-                                  division and mean log-evidence                        */
+                                  dense M-step product); candidate M-step (sparse bands);
+                                  candidate M-step of the dense bands (one product);
+                                  compression, division and mean log-evidence           */
 
 /* One iteration with the E-step restricted to the proposal (pb->precision must
  * be EMC_PREC_BF16; pb->n_data = n_cand + n_audit):

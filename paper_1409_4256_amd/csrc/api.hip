@@ -597,7 +597,7 @@ int64_t chunk_cap(int64_t nz_cap, int64_t n_cand, int n_pix) { return (nz_cap + 
 struct PlanLayout {
   size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, cg_ptr,
       groups, grp_off, tiles, mask_audit, chunks, band_range, band_cnt, band_ptr, dense_band, dense_list, kt_dense,
-      band_mean, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd, cnt, scalars, total;
+      dense_rows, band_mean, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd, cnt, scalars, total;
 };
 
 PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top, int n_audit, int64_t nz_cap) {
@@ -635,6 +635,7 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.dense_band = take((int64_t)(ntab_of(n_pix) - 1) * 4);
   L.dense_list = take(kMaxDense * 4);
   L.kt_dense = take((int64_t)kMaxDense * kBandPx * round_up(n_cand, 256) * 2);
+  L.dense_rows = take((int64_t)kMaxDense * n_cand * kBandPx * 2);
   L.band_mean = take((int64_t)(ntab_of(n_pix) - 1) * 4);
   L.hist = take(nkeys * 4);
   L.cursor = take(nkeys * 4);
@@ -748,6 +749,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   P.dense_band = (int32_t*)(b + L.dense_band);
   P.dense_list = (int32_t*)(b + L.dense_list);
   P.kt_dense = (void*)(b + L.kt_dense);
+  P.dense_rows = (void*)(b + L.dense_rows);
   P.ld_dense = round_up(n_cand, 256);
   int32_t* hist = (int32_t*)(b + L.hist);
   int32_t* cursor = (int32_t*)(b + L.cursor);
@@ -817,6 +819,9 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   HIP_TRY(launch_dense_pack(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.ld_dense, P.n_dense, P.dense_list,
                             P.kt_dense, st),
           "dense pack");
+  HIP_TRY(launch_dense_rows(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.n_dense, P.dense_list, P.dense_rows,
+                            st),
+          "dense rows");
   P.n_tiles = host[0];
   P.n_groups = host[2];
   P.n_g = host[3];
@@ -940,8 +945,8 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   if (nc > 0) {
     HIP_TRY(launch_band_dot((const int2*)plan->band_range, plan->n_bands, plan->chunks, nc, c, b, st), "band dot");
     HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, groups, plan->grp_off, plan->cf_ptr,
-                               plan->cf_frame, (const int2*)plan->band_range, nc, plan->chunks, plan->cell_rot,
-                               slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
+                               plan->cf_frame, (const int2*)plan->band_range, nc, plan->chunks, plan->dense_band,
+                               plan->dense_rows, plan->cell_rot, slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
             "candidate loglik");
   }
   CHECK(mark(2));
@@ -975,6 +980,7 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
                             (const int2*)plan->band_range, nc, plan->chunks, plan->dense_band, Pc, plan->cell_rot, ps,
                             Wp, rho, rho_a, na > 0, st),
           "candidate mstep");
+  CHECK(mark(5));
   if (Pd && nc > 0) {  // dense bands: W'[:, centre] += P_dense K_centre^T over all candidate frames
     const int64_t nd = (int64_t)plan->n_dense * kBandPx;
     HIP_TRY(launch_gemm_bf16_nt(Pd, plan->kt_dense, Wd, pb->n_rot, nd, plan->ld_dense, plan->ld_dense,
@@ -982,13 +988,13 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
             "dense mstep gemm");
     HIP_TRY(launch_dense_add(Wd, pb->n_rot, plan->n_dense, plan->dense_list, ps, Wp, st), "dense add");
   }
-  CHECK(mark(5));
+  CHECK(mark(6));
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
   HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");
   HIP_TRY(launch_scatter(Wp, ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, st),
           "scatter");
   CHECK(run_finalize(pb, num, den, model_in, model_out, L, nc + na, loglik, st));
-  CHECK(mark(6));
+  CHECK(mark(7));
   return EMC_OK;
 }
 

@@ -73,6 +73,7 @@ class Proposal(ctypes.Structure):
         ("chunks", ctypes.c_void_p), ("band_range", ctypes.c_void_p),
         ("n_dense", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("ld_dense", ctypes.c_int64),
         ("dense_band", ctypes.c_void_p), ("dense_list", ctypes.c_void_p), ("kt_dense", ctypes.c_void_p),
+        ("dense_rows", ctypes.c_void_p),
     ]
 
 
@@ -490,8 +491,8 @@ def emc_proposed_workspace_bytes(geo: Geometry, plan: Proposal) -> int:
     return int(n.value)
 
 
-EMC_PROPOSED_STAGES = 6
-PROPOSED_STAGE_NAMES = ("expand", "cand_loglik", "cand_estep", "audit", "cand_mstep", "compress")
+EMC_PROPOSED_STAGES = 7
+PROPOSED_STAGE_NAMES = ("expand", "cand_loglik", "cand_estep", "audit", "cand_mstep", "dense_mstep", "compress")
 
 
 def emc_iterate_proposed(geo: Geometry, plan: Proposal, K_audit, model_in, model_out, loglik, recall_mean, ws,
