@@ -350,15 +350,18 @@ def main():
 
     results = {}
     counts_dev = inp.counts if isinstance(inp.counts, torch.Tensor) else torch.from_numpy(inp.counts).cuda()
+    # the proposal form first: its gathers are sensitive to how fragmented the device
+    # memory it gets is, and the dense forms' large buffers come and go before it otherwise
+    if not args.no_proposal:
+        results["bf16+proposal"] = proposal_form(inp, args, counts_dev)
+        torch.cuda.empty_cache()
     for form, prec in (("plain-fp32", emc.EMC_PREC_FP32), ("bf16", emc.EMC_PREC_BF16)):
         run = Run(inp, prec, counts_dev)
         log(f"{form}: frames packed")
         results[form] = time_form(run, args, n_valid)
         del run
         torch.cuda.empty_cache()
-    if not args.no_proposal:
-        results["bf16+proposal"] = proposal_form(inp, args, counts_dev)
-        torch.cuda.empty_cache()
+    results = {k: results[k] for k in ("plain-fp32", "bf16", "bf16+proposal") if k in results}
     chosen = "bf16"
     if "bf16+proposal" in results and results["bf16+proposal"]["fallbacks"] == 0 and \
             results["bf16+proposal"]["value"] > results["bf16"]["value"]:

@@ -331,8 +331,6 @@ typedef struct emc_proposal {
   int32_t* dense_list;    /* [16] band of each dense index                          */
   void* kt_dense;         /* [n_dense * 128][ld_dense] BF16 pixel-major counts of the
                              dense bands' pixels over the candidate frames         */
-  void* dense_rows;       /* [n_dense][n_cand][128] BF16 frame-major counts of the
-                             dense bands (the log-likelihood's operand there)      */
 } emc_proposal;
 
 /* Bytes of the plan buffer; nz_cap bounds the non-zero pixels of the frames. */

@@ -597,7 +597,7 @@ int64_t chunk_cap(int64_t nz_cap, int64_t n_cand, int n_pix) { return (nz_cap + 
 struct PlanLayout {
   size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, cg_ptr,
       groups, grp_off, tiles, mask_audit, chunks, band_range, band_cnt, band_ptr, dense_band, dense_list, kt_dense,
-      dense_rows, band_mean, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd, cnt, scalars, total;
+      band_mean, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd, cnt, scalars, total;
 };
 
 PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top, int n_audit, int64_t nz_cap) {
@@ -635,7 +635,6 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.dense_band = take((int64_t)(ntab_of(n_pix) - 1) * 4);
   L.dense_list = take(kMaxDense * 4);
   L.kt_dense = take((int64_t)kMaxDense * kBandPx * round_up(n_cand, 256) * 2);
-  L.dense_rows = take((int64_t)kMaxDense * n_cand * kBandPx * 2);
   L.band_mean = take((int64_t)(ntab_of(n_pix) - 1) * 4);
   L.hist = take(nkeys * 4);
   L.cursor = take(nkeys * 4);
@@ -749,7 +748,6 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   P.dense_band = (int32_t*)(b + L.dense_band);
   P.dense_list = (int32_t*)(b + L.dense_list);
   P.kt_dense = (void*)(b + L.kt_dense);
-  P.dense_rows = (void*)(b + L.dense_rows);
   P.ld_dense = round_up(n_cand, 256);
   int32_t* hist = (int32_t*)(b + L.hist);
   int32_t* cursor = (int32_t*)(b + L.cursor);
@@ -819,9 +817,6 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   HIP_TRY(launch_dense_pack(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.ld_dense, P.n_dense, P.dense_list,
                             P.kt_dense, st),
           "dense pack");
-  HIP_TRY(launch_dense_rows(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.n_dense, P.dense_list, P.dense_rows,
-                            st),
-          "dense rows");
   P.n_tiles = host[0];
   P.n_groups = host[2];
   P.n_g = host[3];
@@ -945,8 +940,8 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   if (nc > 0) {
     HIP_TRY(launch_band_dot((const int2*)plan->band_range, plan->n_bands, plan->chunks, nc, c, b, st), "band dot");
     HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, groups, plan->grp_off, plan->cf_ptr,
-                               plan->cf_frame, (const int2*)plan->band_range, nc, plan->chunks, plan->dense_band,
-                               plan->dense_rows, plan->cell_rot, slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
+                               plan->cf_frame, (const int2*)plan->band_range, nc, plan->chunks, plan->cell_rot,
+                               slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
             "candidate loglik");
   }
   CHECK(mark(2));

@@ -85,9 +85,8 @@ __device__ __forceinline__ void put_rest(uint16_t* base, int stride, const u4* _
 __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     const int2* __restrict__ tiles, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
     const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int2* __restrict__ band_range,
-    int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ dense_band, const u4* __restrict__ dense_rows,
-    const int32_t* __restrict__ cell_rot, const uint16_t* __restrict__ hi, int64_t plane,
-    const float* __restrict__ scale, int64_t ps, float* __restrict__ G) {
+    int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ cell_rot, const uint16_t* __restrict__ hi,
+    int64_t plane, const float* __restrict__ scale, int64_t ps, float* __restrict__ G) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kFT * kLRow];  // 69632 bytes
   __shared__ float ssc[kGR];
   const int2 tl = tiles[blockIdx.x];
@@ -155,17 +154,7 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? fb[r1c.x + u] : pad;
     int2 r2c = {0, 0};
     if (has && band + 8 < nbands) r2c = rng[(band + 8) * n_list];
-    const int db = dense_band[band];  // uniform
-    if (db >= 0) {
-      // dense band: copy the frames' BF16 rows (16 lanes per 256-byte row, 4 rows per step)
-#pragma unroll 4
-      for (int i = 0; i < kFT / 4; ++i) {
-        const int sl = 4 * i + (lane >> 4);
-        const int32_t fs = __shfl(fidx, sl, 64);
-        if (sl < nf)
-          reinterpret_cast<u4*>(rows + sl * kLRow)[lane & 15] = dense_rows[((int64_t)db * n_list + fs) * 16 + (lane & 15)];
-      }
-    } else if (has) {
+    if (has) {
 #pragma unroll
       for (int u = 0; u < kWin; ++u) put_chunk<false>(frow, 1, w0[u]);
       put_rest<false>(frow, 1, fb, r0c.x + kWin, r0c.y, 1);
@@ -581,23 +570,6 @@ __global__ __launch_bounds__(256) void dense_pack_kernel(const uint16_t* __restr
   for (int r = ty; r < 64; r += 4) KT[(r0 + r) * ld + f0 + tx] = tile[tx][r];  // r: row, tx: frame
 }
 
-// Frame-major BF16 rows of the dense bands: rows[d][f][p] = count of candidate frame
-// f at pixel 128 dense_list[d] + p (0 when masked)
-__global__ void dense_rows_kernel(const uint16_t* __restrict__ counts, const uint8_t* __restrict__ mask, int n_pix,
-                                  const int32_t* __restrict__ frames, int64_t n_frames, int n_dense,
-                                  const int32_t* __restrict__ dense_list, uint16_t* __restrict__ rows) {
-  const int64_t n = (int64_t)n_dense * n_frames * kBand;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-    const int p = (int)(e & (kBand - 1));
-    const int64_t df = e >> 7;
-    const int64_t f = df % n_frames;
-    const int d = (int)(df / n_frames);
-    const int i = dense_list[d] * kBand + p;
-    const uint32_t v = i < n_pix && mask[i] ? counts[(int64_t)frames[f] * n_pix + i] : 0u;
-    rows[e] = count_bf16(v);
-  }
-}
-
 // W'[j][128 dense_list[d] + p] += D[j][128 d + p]
 __global__ void dense_add_kernel(const float* __restrict__ D, int64_t n_rot, int n_dense,
                                  const int32_t* __restrict__ dense_list, int64_t ps, float* __restrict__ Wp) {
@@ -699,13 +671,12 @@ __global__ __launch_bounds__(256) void audit_recall_kernel(const __hip_bfloat16*
 // ===================================================================== launchers
 hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* groups, const int64_t* grp_off,
                               const int64_t* cf_ptr, const int32_t* cf_frame, const int2* band_range, int64_t n_list,
-                              const void* chunks, const int32_t* dense_band, const void* dense_rows,
-                              const int32_t* cell_rot, const void* hilo, int64_t plane, const float* scale, int64_t ps,
-                              float* G, hipStream_t st) {
+                              const void* chunks, const int32_t* cell_rot, const void* hilo, int64_t plane,
+                              const float* scale, int64_t ps, float* G, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   cand_loglik_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, band_range, n_list,
-                                                        (const u4*)chunks, dense_band, (const u4*)dense_rows,
-                                                        cell_rot, (const uint16_t*)hilo, plane, scale, ps, G);
+                                                        (const u4*)chunks, cell_rot, (const uint16_t*)hilo, plane,
+                                                        scale, ps, G);
   return hipGetLastError();
 }
 
@@ -778,16 +749,6 @@ hipError_t launch_dense_pack(const uint16_t* counts, const uint8_t* mask, int n_
   if (n_dense <= 0 || ld <= 0) return hipSuccess;
   const dim3 grid((unsigned)(n_dense * kBand / 64), (unsigned)(ld / 64));
   dense_pack_kernel<<<grid, 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, ld, dense_list, (uint16_t*)KT);
-  return hipGetLastError();
-}
-
-hipError_t launch_dense_rows(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                             int64_t n_frames, int n_dense, const int32_t* dense_list, void* rows, hipStream_t st) {
-  const int64_t n = (int64_t)n_dense * n_frames * kBand;
-  if (n <= 0) return hipSuccess;
-  const int64_t g = (n + 255) / 256;
-  dense_rows_kernel<<<(unsigned)(g > 65536 ? 65536 : g), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, n_dense,
-                                                                       dense_list, (uint16_t*)rows);
   return hipGetLastError();
 }
 

@@ -155,11 +155,8 @@ hipError_t launch_scan64(const int64_t* cnt, int64_t n, int64_t* ptr, hipStream_
 // ---- candidate E/M steps (cand.hip) ----
 hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* groups, const int64_t* grp_off,
                               const int64_t* cf_ptr, const int32_t* cf_frame, const int2* band_range, int64_t n_list,
-                              const void* chunks, const int32_t* dense_band, const void* dense_rows,
-                              const int32_t* cell_rot, const void* hilo, int64_t plane, const float* scale, int64_t ps,
-                              float* G, hipStream_t st);
-hipError_t launch_dense_rows(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                             int64_t n_frames, int n_dense, const int32_t* dense_list, void* rows, hipStream_t st);
+                              const void* chunks, const int32_t* cell_rot, const void* hilo, int64_t plane,
+                              const float* scale, int64_t ps, float* G, hipStream_t st);
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
                              int64_t n_frames, const int32_t* cell_rot, const double* log_w, const double* S,

@@ -73,7 +73,6 @@ class Proposal(ctypes.Structure):
         ("chunks", ctypes.c_void_p), ("band_range", ctypes.c_void_p),
         ("n_dense", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("ld_dense", ctypes.c_int64),
         ("dense_band", ctypes.c_void_p), ("dense_list", ctypes.c_void_p), ("kt_dense", ctypes.c_void_p),
-        ("dense_rows", ctypes.c_void_p),
     ]
 
 
