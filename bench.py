@@ -339,13 +339,17 @@ def main():
             torch.cuda.synchronize()
             del run
             torch.cuda.empty_cache()
+        if not args.no_proposal:   # one proposal iteration (after its full iterations and training)
+            args.steps = 1
+            proposal_form(inp, args, counts_dev)
+            torch.cuda.empty_cache()
         # reference copy of known size for scaling the FETCH_SIZE / WRITE_SIZE counters
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         bcopy = torch.empty_like(a)
         torch.cuda.synchronize()
         bcopy.copy_(a)
         torch.cuda.synchronize()
-        log("profile-once done: one iteration per form + a 1 GiB device copy")
+        log("profile-once done: one iteration per form (the proposal form: after its training) + a 1 GiB device copy")
         return
 
     results = {}
