@@ -82,6 +82,7 @@ class Run:
         self.num = torch.empty(M, dtype=torch.float64, device=dev)
         self.den = torch.empty(M, dtype=torch.float64, device=dev)
         self.loglik = torch.empty(1, dtype=torch.float64, device=dev)
+        self.cws = torch.empty(emc.emc_compress_workspace_bytes(g), dtype=torch.uint8, device=dev)
         self.cur = 0
 
     def step(self, ev=None):
@@ -97,7 +98,8 @@ class Run:
         emc.emc_responsibilities(g, self.G, self.S, self.b, emc.EMC_RESP_FULL, self.stats, self.P, self.L,
                                  self.rho)
         rec(3)
-        emc.emc_compress(g, self.P, self.K, self.rho, self.slices, self.num, self.den, accumulate=False)
+        emc.emc_compress(g, self.P, self.K, self.rho, self.slices, self.num, self.den, accumulate=False,
+                         ws=self.cws)
         rec(4)
         emc.emc_finalize(g, self.num, self.den, m_in, m_out, self.L, self.wl.n_data, self.loglik)
         rec(5)

@@ -179,10 +179,14 @@ emc_status emc_responsibilities(const emc_problem* pb, const float* G, const dou
  *   num, den [N^3] double: num_l += sum_{j,i valid} f(p_l - R_j q_i) W'_ji,
  *       den_l += sum_{j,i valid} f(p_l - R_j q_i) rho_j (FP64).
  *       accumulate == 0 zeroes them first; accumulate != 0 adds, so frame
- *       chunks (the k-direction split of Section 3.3) sum before division. */
+ *       chunks (the k-direction split of Section 3.3) sum before division.
+ *   ws  NULL, or emc_compress_workspace_bytes of device memory: one copy of
+ *       the two grids per XCD, whose atomics stay in that XCD's L2 (faster);
+ *       without it the atomics go to num/den directly.                       */
+emc_status emc_compress_workspace_bytes(const emc_problem* pb, size_t* bytes);
 emc_status emc_compress(const emc_problem* pb, const void* P, const void* K_packed,
                         const double* rho, float* Wp, double* num, double* den,
-                        int32_t accumulate, hipStream_t stream);
+                        int32_t accumulate, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Final division of eq. (2.12) and the mean log-evidence of eq. (2.1):
  *   model_out_l = num_l / den_l where den_l > 0, else model_prev_l

@@ -89,8 +89,11 @@ size_t frames_bytes(const emc_problem* pb) {
 size_t slices_bytes(const emc_problem* pb) { return (size_t)pb->n_rot * dims_of(pb).ps * sizeof(float); }
 
 struct Layout {
-  size_t slices, G, P, S, scale, c, b, stats, L, rho, num, den, total;
+  size_t slices, G, P, S, scale, c, b, stats, L, rho, num, den, copies, total;
 };
+
+// grid copies of the c-step's scatter: one numerator and one denominator per XCD
+size_t copies_bytes(const emc_problem* pb) { return (size_t)16 * pb->grid_n * pb->grid_n * pb->grid_n * sizeof(double); }
 
 Layout layout_of(const emc_problem* pb) {
   const Dims d = dims_of(pb);
@@ -113,6 +116,7 @@ Layout layout_of(const emc_problem* pb) {
   L.rho = take((size_t)pb->n_rot * sizeof(double));
   L.num = take((size_t)d.grid * sizeof(double));
   L.den = take((size_t)d.grid * sizeof(double));
+  L.copies = take(copies_bytes(pb));
   L.total = o;
   return L;
 }
@@ -168,7 +172,7 @@ emc_status run_estep(const emc_problem* pb, const float* G, const double* S, con
 }
 
 emc_status run_compress(const emc_problem* pb, const void* P, const void* K, const double* rho, float* Wp,
-                        double* num, double* den, int32_t accumulate, hipStream_t st) {
+                        double* num, double* den, int32_t accumulate, double* copies, hipStream_t st) {
   const Dims d = dims_of(pb);
   if (!accumulate) {
     HIP_TRY(launch_fill_zero_f64(num, (size_t)d.grid, st), "zero num");
@@ -181,7 +185,8 @@ emc_status run_compress(const emc_problem* pb, const void* P, const void* K, con
   else
     HIP_TRY(launch_gemm_f32_nt((const float*)P, (const float*)KT, Wp, pb->n_rot, d.ps, d.ds, d.ds, d.ds, d.ps, st),
             "mstep gemm");
-  HIP_TRY(launch_scatter(Wp, d.ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, st),
+  HIP_TRY(launch_scatter(Wp, d.ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, copies,
+                         st),
           "scatter");
   return EMC_OK;
 }
@@ -301,9 +306,21 @@ emc_status emc_responsibilities(const emc_problem* pb, const float* G, const dou
   return run_estep(pb, G, S, b, mode, stats, P, L, rho, st);
 }
 
+emc_status emc_compress_workspace_bytes(const emc_problem* pb, size_t* bytes) {
+  CHECK(check_problem(pb, false));
+  if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = copies_bytes(pb);
+  return EMC_OK;
+}
+
 emc_status emc_compress(const emc_problem* pb, const void* P, const void* K_packed, const double* rho, float* Wp,
-                        double* num, double* den, int32_t accumulate, hipStream_t st) {
+                        double* num, double* den, int32_t accumulate, void* ws, size_t ws_bytes, hipStream_t st) {
   CHECK(check_problem(pb, true));
+  if (ws) {
+    if (!aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    if (ws_bytes < copies_bytes(pb))
+      return fail(EMC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, copies_bytes(pb));
+  }
   CHECK(need(num, 8, "num"));
   CHECK(need(den, 8, "den"));
   if (pb->n_data > 0) {
@@ -312,7 +329,7 @@ emc_status emc_compress(const emc_problem* pb, const void* P, const void* K_pack
     CHECK(need(rho, 8, "rho"));
     CHECK(need(Wp, 16, "Wp"));
   }
-  return run_compress(pb, P, K_packed, rho, Wp, num, den, accumulate, st);
+  return run_compress(pb, P, K_packed, rho, Wp, num, den, accumulate, (double*)ws, st);
 }
 
 emc_status emc_finalize(const emc_problem* pb, const double* num, const double* den, const float* model_prev,
@@ -357,7 +374,7 @@ emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void*
   CHECK(run_expand(pb, model_in, c, slices, S, scale, st));
   CHECK(run_loglik(pb, K_packed, slices, scale, c, G, b, st));
   CHECK(run_estep(pb, G, S, b, EMC_RESP_FULL, stats, P, L, rho, st));
-  CHECK(run_compress(pb, P, K_packed, rho, (float*)slices, num, den, 0, st));
+  CHECK(run_compress(pb, P, K_packed, rho, (float*)slices, num, den, 0, (double*)(w + Lo.copies), st));
   CHECK(run_finalize(pb, num, den, model_in, model_out, L, pb->n_data, loglik, st));
   return EMC_OK;
 }
@@ -830,7 +847,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
 namespace {
 
 struct PropWs {
-  size_t slices, S, scale, c, b, L, G, P, Ga, Pa, stats_a, rho_a, recall, rho, num, den, Pd, Wd, total;
+  size_t slices, S, scale, c, b, L, G, P, Ga, Pa, stats_a, rho_a, recall, rho, num, den, Pd, Wd, copies, total;
 };
 
 PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
@@ -863,6 +880,7 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
   W.den = take(grid * 8);
   W.Pd = take(P->n_dense > 0 ? (int64_t)pb->n_rot * P->ld_dense * 2 : 0);
   W.Wd = take((int64_t)pb->n_rot * P->n_dense * kBandPx * 4);
+  W.copies = take((int64_t)copies_bytes(pb));
   W.total = o;
   return W;
 }
@@ -986,7 +1004,8 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   CHECK(mark(6));
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
   HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");
-  HIP_TRY(launch_scatter(Wp, ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, st),
+  HIP_TRY(launch_scatter(Wp, ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den,
+                         (double*)(w + W.copies), st),
           "scatter");
   CHECK(run_finalize(pb, num, den, model_in, model_out, L, nc + na, loglik, st));
   CHECK(mark(7));

@@ -1,6 +1,11 @@
 // c-step, eq. (2.12): scatter of the M-step slices W'_ji and of the weights
 // rho_j into numerator and denominator grids through the same trilinear
 // weights as the expansion (FP64 atomics), then the division.
+//
+// With a workspace, every XCD accumulates into a grid copy of its own (the wave
+// reads the id of the XCD it runs on), with atomics that complete in that XCD's
+// L2; a reduction then adds the eight copies.  Without one, the atomics go to the
+// shared grids at device scope (past the L2s).
 #include <limits.h>
 
 #include "emc_device.h"
@@ -8,6 +13,17 @@
 namespace emc {
 
 constexpr int kBoxCap = 1024;  // voxels of one wave's LDS accumulation box
+constexpr int kCopies = 8;     // grid copies: one per XCD
+
+template <bool LOCAL>
+__device__ __forceinline__ void grid_add(double* p, double v) {
+  if constexpr (LOCAL)
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  // in this XCD's L2
+  else
+    unsafeAtomicAdd(p, v);
+}
+
+__device__ __forceinline__ int xcd_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kCopies - 1); }
 
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
@@ -27,11 +43,18 @@ __device__ __forceinline__ int wave_max(int v) {
 // accumulates in LDS (FP64) and then adds to the global grids with one FP64
 // atomic per touched voxel.  Pixel groups whose box exceeds kBoxCap voxels
 // add straight to the global grids; the result is the same either way.
+template <bool LOCAL>
 __global__ __launch_bounds__(256) void scatter_kernel(const float* __restrict__ Wp, int64_t stride,
                                                       const double* __restrict__ rho, const float* __restrict__ q,
                                                       const uint8_t* __restrict__ mask,
                                                       const float* __restrict__ quat, int n_pix, int N,
-                                                      double* __restrict__ num, double* __restrict__ den) {
+                                                      double* __restrict__ num, double* __restrict__ den,
+                                                      int64_t M) {
+  if constexpr (LOCAL) {  // this XCD's copies of the two grids
+    const int64_t x = xcd_id();
+    num += x * M;
+    den += x * M;
+  }
   __shared__ double s_num[4][kBoxCap];
   __shared__ double s_den[4][kBoxCap];
   const int j = blockIdx.x;
@@ -78,8 +101,8 @@ __global__ __launch_bounds__(256) void scatter_kernel(const float* __restrict__ 
           atomicAdd(bn + e, an);
           atomicAdd(bd + e, ad);
         } else {
-          unsafeAtomicAdd(num + s.idx[t], an);
-          unsafeAtomicAdd(den + s.idx[t], ad);
+          grid_add<LOCAL>(num + s.idx[t], an);
+          grid_add<LOCAL>(den + s.idx[t], ad);
         }
       }
     }
@@ -90,11 +113,30 @@ __global__ __launch_bounds__(256) void scatter_kernel(const float* __restrict__ 
         if (vn == 0.0 && vd == 0.0) continue;
         const int ex = e / (DY * DZ), rem = e - ex * DY * DZ, ey = rem / DZ, ez = rem - ey * DZ;
         const int l = ((x0 + ex) * N + (y0 + ey)) * N + (z0 + ez);
-        if (vn != 0.0) unsafeAtomicAdd(num + l, vn);
-        if (vd != 0.0) unsafeAtomicAdd(den + l, vd);
+        if (vn != 0.0) grid_add<LOCAL>(num + l, vn);
+        if (vd != 0.0) grid_add<LOCAL>(den + l, vd);
       }
     // the next iteration's zeroing touches entry e from the same lane that flushed it
   }
+}
+
+// num_l += sum_x cn[x][l], den_l += sum_x cd[x][l] (copies in a fixed order)
+__global__ void grid_reduce_kernel(const double* __restrict__ cn, const double* __restrict__ cd, int64_t M,
+                                   double* __restrict__ num, double* __restrict__ den) {
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < M; l += (int64_t)gridDim.x * 256) {
+    double sn = 0.0, sd = 0.0;
+#pragma unroll
+    for (int x = 0; x < kCopies; ++x) {
+      sn += cn[x * M + l];
+      sd += cd[x * M + l];
+    }
+    num[l] += sn;
+    den[l] += sd;
+  }
+}
+
+__global__ void zero_f64_kernel(double* __restrict__ p, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) p[e] = 0.0;
 }
 
 __global__ void divide_kernel(const double* __restrict__ num, const double* __restrict__ den,
@@ -115,10 +157,21 @@ __global__ __launch_bounds__(256) void mean_kernel(const double* __restrict__ L,
   if (threadIdx.x == 0) *out = n > 0 ? ((red[0] + red[1]) + (red[2] + red[3])) / (double)n : NAN;
 }
 
+// num/den += the scatter of all rotations; copies: NULL or 2 * 8 * N^3 doubles
 hipError_t launch_scatter(const float* Wp, int64_t stride, const double* rho, const float* q,
                           const uint8_t* mask, const float* quat, int n_pix, int n_rot, int N, double* num,
-                          double* den, hipStream_t st) {
-  scatter_kernel<<<(unsigned)n_rot, 256, 0, st>>>(Wp, stride, rho, q, mask, quat, n_pix, N, num, den);
+                          double* den, double* copies, hipStream_t st) {
+  const int64_t M = (int64_t)N * N * N;
+  if (!copies) {
+    scatter_kernel<false><<<(unsigned)n_rot, 256, 0, st>>>(Wp, stride, rho, q, mask, quat, n_pix, N, num, den, M);
+    return hipGetLastError();
+  }
+  const int64_t nc = 2 * kCopies * M;
+  const int64_t gz = (nc + 255) / 256, gr = (M + 255) / 256;
+  zero_f64_kernel<<<(unsigned)(gz > 65536 ? 65536 : gz), 256, 0, st>>>(copies, nc);
+  scatter_kernel<true><<<(unsigned)n_rot, 256, 0, st>>>(Wp, stride, rho, q, mask, quat, n_pix, N, copies,
+                                                        copies + kCopies * M, M);
+  grid_reduce_kernel<<<(unsigned)(gr > 65536 ? 65536 : gr), 256, 0, st>>>(copies, copies + kCopies * M, M, num, den);
   return hipGetLastError();
 }
 

@@ -109,7 +109,7 @@ hipError_t launch_lse_write_bf16(const float* G, int64_t ldg, void* P, int64_t l
                                  double* rho, hipStream_t st);
 hipError_t launch_scatter(const float* Wp, int64_t stride, const double* rho, const float* q,
                           const uint8_t* mask, const float* quat, int n_pix, int n_rot, int N, double* num,
-                          double* den, hipStream_t st);
+                          double* den, double* copies, hipStream_t st);
 hipError_t launch_divide(const double* num, const double* den, const float* prev, float* out, int64_t M,
                          hipStream_t st);
 hipError_t launch_mean(const double* L, int64_t n, double* out, hipStream_t st);

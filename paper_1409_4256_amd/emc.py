@@ -29,7 +29,7 @@ EMC_RESP_FINALIZE = 2
 
 EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride", "emc_frames_bytes",
            "emc_slices_bytes", "emc_workspace_bytes", "emc_pack_frames", "emc_expand", "emc_loglik",
-           "emc_responsibilities", "emc_compress", "emc_finalize", "emc_iterate",
+           "emc_responsibilities", "emc_compress_workspace_bytes", "emc_compress", "emc_finalize", "emc_iterate",
            "emc_cnn_param_count", "emc_cnn_workspace_bytes", "emc_cnn_preprocess", "emc_cnn_forward",
            "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_topk", "emc_topk_union",
            "emc_cell_targets",
@@ -103,7 +103,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_loglik.argtypes, lib.emc_loglik.restype = [_PB, _P, _P, _P, _P, _P, _P, _P], st
     lib.emc_responsibilities.argtypes = [_PB, _P, _P, _P, i32, _P, _P, _P, _P, _P]
     lib.emc_responsibilities.restype = st
-    lib.emc_compress.argtypes, lib.emc_compress.restype = [_PB, _P, _P, _P, _P, _P, _P, i32, _P], st
+    lib.emc_compress.argtypes = [_PB, _P, _P, _P, _P, _P, _P, i32, _P, ctypes.c_size_t, _P]
+    lib.emc_compress.restype = st
+    lib.emc_compress_workspace_bytes.argtypes, lib.emc_compress_workspace_bytes.restype = [_PB, szp], st
     lib.emc_finalize.argtypes, lib.emc_finalize.restype = [_PB, _P, _P, _P, _P, _P, i64, _P, _P], st
     lib.emc_iterate.argtypes = [_PB, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.emc_iterate.restype = st
@@ -326,7 +328,14 @@ def emc_responsibilities(geo: Geometry, G, S, b, mode, stats, P=None, L=None, rh
         _stream(stream)))
 
 
-def emc_compress(geo: Geometry, P, K_packed, rho, Wp, num, den, accumulate=False, stream=None):
+def emc_compress_workspace_bytes(geo: Geometry) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().emc_compress_workspace_bytes(ctypes.byref(geo.pb), ctypes.byref(n)))
+    return int(n.value)
+
+
+def emc_compress(geo: Geometry, P, K_packed, rho, Wp, num, den, accumulate=False, ws=None, stream=None):
+    """ws: None (atomics to num/den) or a uint8 tensor of emc_compress_workspace_bytes (per-XCD grid copies)."""
     import torch
 
     n = geo.n_data
@@ -338,7 +347,8 @@ def emc_compress(geo: Geometry, P, K_packed, rho, Wp, num, den, accumulate=False
         _ptr(rho, torch.float64, geo.n_rot, "rho") if n else None,
         _ptr(Wp, torch.float32, geo.n_rot * geo.pix_stride, "Wp") if n else None,
         _ptr(num, torch.float64, M, "num"), _ptr(den, torch.float64, M, "den"), int(bool(accumulate)),
-        _stream(stream)))
+        _ptr(ws, torch.uint8, emc_compress_workspace_bytes(geo), "ws") if ws is not None else None,
+        ctypes.c_size_t(ws.numel() if ws is not None else 0), _stream(stream)))
 
 
 def emc_finalize(geo: Geometry, num, den, model_prev, model_out, L, n_L, loglik, stream=None):

@@ -38,7 +38,7 @@ def _slices_f64(geo, slices, scale):
     return (hi + lo) * scale.double()[:, None]
 
 
-def run_steps(geo, model, K, frame_chunks=None):
+def run_steps(geo, model, K, frame_chunks=None, grid_copies=True):
     """expand -> loglik -> responsibilities -> compress -> finalize.
 
     `frame_chunks` is a list of (geometry, K_packed, offset) per chunk of frames
@@ -57,6 +57,7 @@ def run_steps(geo, model, K, frame_chunks=None):
     num = torch.empty(N3, dtype=torch.float64, device=dev)
     den = torch.empty(N3, dtype=torch.float64, device=dev)
     Wp = torch.empty(geo.n_rot * ps, dtype=torch.float32, device=dev)
+    cws = torch.empty(emc.emc_compress_workspace_bytes(geo), dtype=torch.uint8, device=dev) if grid_copies else None
     n = geo.n_data
     Gs, Ps, bs, Ls, sts = [], [], [], [], []
     rho_tot = torch.zeros(geo.n_rot, dtype=torch.float64, device=dev)
@@ -72,7 +73,7 @@ def run_steps(geo, model, K, frame_chunks=None):
         emc.emc_loglik(g, Kc, slices, scale, c, G, b)
         Gc = G.clone()
         emc.emc_responsibilities(g, G, S, b, emc.EMC_RESP_FULL, stats, P, L, rho)
-        emc.emc_compress(g, P, Kc, rho, Wp, num, den, accumulate=ci > 0)
+        emc.emc_compress(g, P, Kc, rho, Wp, num, den, accumulate=ci > 0, ws=cws)
         if nc:
             rho_tot += rho
             Wp_tot += Wp.double()

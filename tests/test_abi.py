@@ -55,7 +55,10 @@ def test_buffer_sizes_config2(lib, prec, elem):
     slices = 25000 * 16384 * 4
     g = 25000 * 100096 * 4
     p = 0 if prec == 0 else 25000 * 100096 * 2          # FP32 responsibilities overwrite G
-    assert slices + g + p < n.value < slices + g + p + 64 * 2 ** 20
+    copies = 16 * 128 ** 3 * 8                           # per-XCD numerator and denominator grids
+    assert slices + g + p + copies < n.value < slices + g + p + copies + 64 * 2 ** 20
+    assert lib.emc_compress_workspace_bytes(ctypes.byref(pb), ctypes.byref(n)) == emc.EMC_OK
+    assert n.value == copies
     assert lib.emc_frames_bytes(ctypes.byref(pb), ctypes.byref(n)) == emc.EMC_OK
     assert n.value == (100000 * 16384 + 16384 * 100096) * elem
     assert lib.emc_slices_bytes(ctypes.byref(pb), ctypes.byref(n)) == emc.EMC_OK
@@ -104,6 +107,17 @@ def test_workspace_checks(lib):
     st = lib.emc_iterate(ctypes.byref(pb), a, a, a, a, None, None, need, None)
     assert st == emc.EMC_ERR_WORKSPACE
     st = lib.emc_iterate(ctypes.byref(pb), a, a, a, a, None, ctypes.c_void_p((1 << 20) + 16), need, None)
+    assert st == emc.EMC_ERR_WORKSPACE
+
+
+def test_compress_workspace_checks(lib):
+    pb = _pb()
+    a = ctypes.c_void_p(1 << 20)
+    need = ctypes.c_size_t()
+    lib.emc_compress_workspace_bytes(ctypes.byref(pb), ctypes.byref(need))
+    st = lib.emc_compress(ctypes.byref(pb), a, a, a, a, a, a, 0, a, ctypes.c_size_t(need.value - 1), None)
+    assert st == emc.EMC_ERR_WORKSPACE
+    st = lib.emc_compress(ctypes.byref(pb), a, a, a, a, a, a, 0, ctypes.c_void_p((1 << 20) + 8), need, None)
     assert st == emc.EMC_ERR_WORKSPACE
 
 

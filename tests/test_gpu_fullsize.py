@@ -76,7 +76,7 @@ def full(request, inputs, gpu_lib):
     s["L"] = run.L.cpu().numpy()
     s["rho"] = run.rho.cpu().numpy()
     print(f"[fullsize {form}] compress", flush=True)
-    emc.emc_compress(g, run.P, run.K, run.rho, run.slices, run.num, run.den, accumulate=False)
+    emc.emc_compress(g, run.P, run.K, run.rho, run.slices, run.num, run.den, accumulate=False, ws=run.cws)
     torch.cuda.synchronize()
     s["Wp"] = run.slices[:wl.n_rot * ps].view(wl.n_rot, ps)[jt[:8]].double().cpu().numpy()
     s["num_sum"] = float(run.num.sum().item())

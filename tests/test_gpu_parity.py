@@ -78,7 +78,8 @@ def test_config1_full_iteration_matches_oracle(gpu_lib, cfg1, start):
 @pytest.mark.parametrize("seed,N,npx,nrot,ndata,qr", [(0, 24, 529, 300, 333, None), (1, 20, 257, 129, 517, None),
                                                       (2, 16, 64, 1, 40, None), (3, 18, 300, 257, 1, None),
                                                       (4, 12, 200, 70, 90, 2.5)])
-def test_ragged_shapes_match_oracle(gpu_lib, seed, N, npx, nrot, ndata, qr):
+@pytest.mark.parametrize("grid_copies", [True, False])
+def test_ragged_shapes_match_oracle(gpu_lib, seed, N, npx, nrot, ndata, qr, grid_copies):
     # random pixel positions in a ball of radius N/2 - 2 spread each 64-pixel group
     # beyond the compression's local box (global-atomic path); qr = 2.5 keeps them
     # inside it (local-box path)
@@ -88,9 +89,9 @@ def test_ragged_shapes_match_oracle(gpu_lib, seed, N, npx, nrot, ndata, qr):
     q, quat = _inputs_f32(t["q"], t["quat"])
     geo = geometry(N, q, t["mask"], quat, t["log_w"], ndata)
     K = pack(geo, upload_counts(t["counts"]))
-    g = run_steps(geo, t["model"], K)
+    g = run_steps(geo, t["model"], K, grid_copies=grid_copies)
     o = _oracle(t["model"], t["counts"], q, t["mask"], quat, t["log_w"], N)
-    _check_all(g, o, t["mask"], f"seed{seed}")
+    _check_all(g, o, t["mask"], f"seed{seed} grid copies {grid_copies}")
 
 
 def test_frame_chunks_accumulate_before_division(gpu_lib):

@@ -59,6 +59,7 @@ def streamed(gpu_lib):
     frames = torch.arange(wl.n_data, dtype=torch.int32, device=dev)
     out = dict(js=js, A=A, c=c.cpu().numpy(), S=S.cpu().numpy(), G={}, b={}, ks={}, Kr={}, colsum=[])
     n_chunks = wl.n_data // CHUNK
+    cws = torch.empty(emc.emc_compress_workspace_bytes(geo), dtype=torch.uint8, device="cuda")
     for ci in range(n_chunks):
         emc.emc_pack_frames_list(gc, inp.counts, frames[ci * CHUNK:(ci + 1) * CHUNK], K)
         emc.emc_loglik(gc, K, slices, scale, c, G, b)
@@ -72,7 +73,7 @@ def streamed(gpu_lib):
             out["Kr"][ci] = inp.counts.view(torch.int16)[kt + ci * CHUNK].to(torch.int32).cpu().numpy()
         emc.emc_responsibilities(gc, G, S, b, emc.EMC_RESP_FULL, stats, P, L[ci * CHUNK:(ci + 1) * CHUNK], rho)
         out["colsum"].append(P.view(wl.n_rot, ds)[:, :CHUNK].double().sum(0).cpu().numpy())
-        emc.emc_compress(gc, P, K, rho, Wp, num, den, accumulate=ci > 0)
+        emc.emc_compress(gc, P, K, rho, Wp, num, den, accumulate=ci > 0, ws=cws)
         rho_tot += rho
         print(f"[stream160] chunk {ci + 1}/{n_chunks} done", flush=True)
     m_out = torch.empty_like(model)
