@@ -26,6 +26,25 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 
 
+TRAFFIC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                       "emc128_r25000_d100000_hbm_traffic.json")
+
+
+def hbm_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when that summary is missing or its kernel source has changed since."""
+    import hashlib
+
+    try:
+        rec = json.load(open(TRAFFIC))["kernels"][kernel]
+        src = os.path.join(os.path.dirname(os.path.abspath(__file__)), rec["source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+            return None
+        return round(rec["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -176,6 +195,7 @@ def time_form(run, args, n_valid):
     peak = PEAK_BF16_MFMA_TFLOPS if g.bf16 else PEAK_FP32_MFMA_TFLOPS
     achieved = terms * contraction / t_gemm / 1e12
     kern = "gemm_bf16_kernel<DUAL> (hi+lo log-likelihood)" if g.bf16 else "gemm_f32_kernel (log-likelihood)"
+    sym = "emc::gemm_bf16_kernel<true, 8>" if g.bf16 else "emc::gemm_f32_kernel"
     return {
         "value": round(1000.0 / ms, 5),
         "ms_per_step": round(ms, 3),
@@ -183,7 +203,9 @@ def time_form(run, args, n_valid):
         "steps_ms_median": {k: round(float(np.median(v)), 3) for k, v in per.items()},
         "loglik": run.loglik.item(),
         "roofline": {"bound": "mfma", "kernel": kern + ", emc_loglik step", "achieved": round(achieved, 2),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": hbm_traffic(sym),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "algorithmic_flops_per_launch": terms * contraction},
         "iteration_tflops_algorithmic": round((terms + 1) * contraction / (ms / 1e3) / 1e12, 2),
         "paper_flop_model_tflops": round(27.0 * wl.n_rot * wl.n_data * wl.n_pix / (ms / 1e3) / 1e12, 2),
@@ -288,14 +310,17 @@ def proposal_form(inp, args, counts_dev):
     n_valid = int(np.asarray(inp.mask).sum())
     sarr = np.asarray(stages)
     mean_s = {name: float(np.mean(sarr[:, i])) / 1e3 for i, name in enumerate(emc.PROPOSED_STAGE_NAMES)}
-    cand = {"cand_loglik": ("cand_loglik_kernel (candidate log-likelihood)", 4.0 * n_pairs * n_valid),
-            "cand_mstep": ("cand_mstep_kernel (candidate M-step, sparse bands)", 2.0 * n_pairs * n_valid)}
+    cand = {"cand_loglik": ("cand_loglik_kernel (candidate log-likelihood)", 4.0 * n_pairs * n_valid,
+                            "emc::cand_loglik_kernel"),
+            "cand_mstep": ("cand_mstep_kernel (candidate M-step, sparse bands)", 2.0 * n_pairs * n_valid,
+                           "emc::cand_mstep_kernel")}
     dom = max(cand, key=lambda k: mean_s[k])
     roofs = {}
-    for k, (kname, flops) in cand.items():
+    for k, (kname, flops, sym) in cand.items():
         roofs[k] = {"bound": "mfma", "kernel": kname + ", emc_iterate_proposed",
                     "achieved": round(flops / mean_s[k] / 1e12, 2), "peak": 2500.0, "unit": "TFLOP/s",
-                    "frac": round(flops / mean_s[k] / 1e12 / 2500.0, 4), "traffic": None,
+                    "frac": round(flops / mean_s[k] / 1e12 / 2500.0, 4), "traffic": hbm_traffic(sym),
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                     "algorithmic_flops_per_launch": flops, "ms": round(mean_s[k] * 1e3, 3)}
     roof = dict(roofs[dom])
     roof["other"] = {k: v for k, v in roofs.items() if k != dom}

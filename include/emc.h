@@ -359,7 +359,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
 emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposal* plan, size_t* bytes);
 
 /* Stages of emc_iterate_proposed, in order (stage_events[i], [i + 1] bracket stage i). */
-#define EMC_PROPOSED_STAGES 7  /* expansion; candidate log-likelihood (with b); candidate
+#define EMC_PROPOSED_STAGES 7  /* expansion (with b); candidate log-likelihood; candidate
                                   E-step; audited frames (log-likelihood, E-step, recall,
                                   dense M-step product); candidate M-step (sparse bands);
                                   candidate M-step of the dense bands (one product);

@@ -953,10 +953,11 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   CHECK(mark(0));
   // expansion (BF16 hi + lo slices with their row scales)
   CHECK(run_expand(pb, model_in, c, slices, S, scale, st));
+  if (nc > 0)
+    HIP_TRY(launch_band_dot((const int2*)plan->band_range, plan->n_bands, plan->chunks, nc, c, b, st), "band dot");
   CHECK(mark(1));
   // candidate frames: log-likelihoods per (group, listed frame), E-step over each frame's candidates
   if (nc > 0) {
-    HIP_TRY(launch_band_dot((const int2*)plan->band_range, plan->n_bands, plan->chunks, nc, c, b, st), "band dot");
     HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, groups, plan->grp_off, plan->cf_ptr,
                                plan->cf_frame, (const int2*)plan->band_range, nc, plan->chunks, plan->cell_rot,
                                slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
