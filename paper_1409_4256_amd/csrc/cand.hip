@@ -45,6 +45,17 @@ __device__ __forceinline__ uint16_t count_bf16(uint32_t e) {
 }
 
 constexpr uint32_t kPad = 0xffffu;  // padding word of a chunk
+
+// The M-step streams each chunk once: non-temporal loads keep the stream from
+// evicting the responsibilities its workgroups share in L2 (measured faster there;
+// the log-likelihood's chunk loads are faster as ordinary loads).
+template <bool NT>
+__device__ __forceinline__ u4 load_chunk(const u4* __restrict__ p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
 constexpr int kWin = 2;              // chunks per band held in registers (16 pixels)
 
 // Writes (CLEAR = false) or zeroes one chunk's pixels: word e goes to
@@ -65,14 +76,14 @@ __device__ __forceinline__ void put_chunk(uint16_t* base, int stride, u4 ch) {
 // (step 1: one lane per frame; 2: two lanes per frame taking alternate chunks),
 // loaded four at a time
 // (chunks from `mid` on belong to the next band: their pixels go `next` further)
-template <bool CLEAR>
+template <bool CLEAR, bool NT>
 __device__ __forceinline__ void put_rest(uint16_t* base, int stride, const u4* __restrict__ src, int first, int c1,
                                          int step, int mid = INT_MAX, int next = 0) {
   const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
   for (int c = first; c < c1; c += 4 * step) {
     u4 v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = c + u * step < c1 ? src[c + u * step] : pad;
+    for (int u = 0; u < 4; ++u) v[u] = c + u * step < c1 ? load_chunk<NT>(src + c + u * step) : pad;
 #pragma unroll
     for (int u = 0; u < 4; ++u) put_chunk<CLEAR>(base + (c + u * step >= mid ? next : 0), stride, v[u]);
   }
@@ -127,7 +138,7 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
   if (has && wave < nbands) r0c = rng[wave * n_list];
   u4 w0[kWin];
 #pragma unroll
-  for (int u = 0; u < kWin; ++u) w0[u] = r0c.x + u < r0c.y ? fb[r0c.x + u] : pad;
+  for (int u = 0; u < kWin; ++u) w0[u] = r0c.x + u < r0c.y ? load_chunk<false>(fb + r0c.x + u) : pad;
   if (has && wave + 4 < nbands) r1c = rng[(wave + 4) * n_list];
   // A fragments (slice rows, hi and lo, both row tiles) of a band, 4 k-steps
   auto load_a = [&](int band, u4 (&h)[4][2], u4 (&l)[4][2]) {
@@ -151,13 +162,13 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     load_a(band + 4, ahn, aln);
     u4 w1[kWin];
 #pragma unroll
-    for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? fb[r1c.x + u] : pad;
+    for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? load_chunk<false>(fb + r1c.x + u) : pad;
     int2 r2c = {0, 0};
     if (has && band + 8 < nbands) r2c = rng[(band + 8) * n_list];
     if (has) {
 #pragma unroll
       for (int u = 0; u < kWin; ++u) put_chunk<false>(frow, 1, w0[u]);
-      put_rest<false>(frow, 1, fb, r0c.x + kWin, r0c.y, 1);
+      put_rest<false, false>(frow, 1, fb, r0c.x + kWin, r0c.y, 1);
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -355,7 +366,7 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
   int32_t fr2 = frame_at(2 * kFB);
   u4 w0[kWin];
 #pragma unroll
-  for (int u = 0; u < kWin; ++u) w0[u] = q0.x + u < q0.y ? fb[q0.x + u] : pad;
+  for (int u = 0; u < kWin; ++u) w0[u] = q0.x + u < q0.y ? load_chunk<true>(fb + q0.x + u) : pad;
   int2 q1 = range_of(fr1);
   u4 b0, b1;
   load_p(0, b0, b1);
@@ -368,12 +379,12 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
     load_p(f0 + kFB, b0n, b1n);
     u4 w1[kWin];
 #pragma unroll
-    for (int u = 0; u < kWin; ++u) w1[u] = q1.x + u < q1.y ? fb[q1.x + u] : pad;
+    for (int u = 0; u < kWin; ++u) w1[u] = q1.x + u < q1.y ? load_chunk<true>(fb + q1.x + u) : pad;
     const int2 q2 = range_of(fr2);
     const int32_t fr3 = frame_at(f0 + 3 * kFB);
 #pragma unroll
     for (int u = 0; u < kWin; ++u) put_chunk<false>(fcol_b, kKRow, w0[u]);
-    put_rest<false>(fcol_b, kKRow, fb, q0.x + kWin, q0.y, 1);
+    put_rest<false, true>(fcol_b, kKRow, fb, q0.x + kWin, q0.y, 1);
     if (nf < kFB) {  // frames past the list end hold no responsibility
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
