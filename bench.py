@@ -66,7 +66,7 @@ def parse():
 class Run:
     """Device buffers and the step sequence of one iteration through the C ABI."""
 
-    def __init__(self, inp, precision=0, counts_dev=None):
+    def __init__(self, inp, precision=0, counts_dev=None, brick=True):
         import torch
 
         from paper_1409_4256_amd import emc
@@ -78,6 +78,8 @@ class Run:
         self.geo = emc.Geometry(wl.grid_n, torch.as_tensor(inp.q), torch.as_tensor(inp.mask),
                                 torch.as_tensor(inp.quat), torch.as_tensor(inp.log_w), wl.n_data, precision)
         g = self.geo
+        if brick:   # brick-major c-step: its plan depends on the geometry only, built once here
+            g.use_brick_scatter()
         if counts_dev is None:
             counts_dev = inp.counts if isinstance(inp.counts, torch.Tensor) else torch.from_numpy(inp.counts)
             counts_dev = counts_dev.to(dev)

@@ -81,6 +81,8 @@ typedef enum {
   EMC_RESP_FINALIZE = 2  /* P, L and rho from caller-supplied global statistics */
 } emc_resp_mode;
 
+struct emc_scatter_plan;
+
 /* Problem description (Section 2.2 notation). */
 typedef struct emc_problem {
   int32_t grid_n;          /* N: model has N^3 grid points, 2 <= N <= 1024              */
@@ -94,6 +96,9 @@ typedef struct emc_problem {
   const float* quat;       /* [n_rot][4] rotation R_j as quaternion (w, x, y, z)        */
   const double* log_w;     /* [n_rot] log prior weight log w_j (sum_j w_j = 1 over the  */
                            /*         full rotation set, Section 2.2)                   */
+  const struct emc_scatter_plan* scatter;  /* host struct; NULL = rotation-major c-step, */
+                           /*         else the brick-major one this plan describes      */
+                           /*         (emc_scatter_plan_build, same q, mask, quat, N)   */
 } emc_problem;
 
 /* Library version string (static storage). */
@@ -182,11 +187,62 @@ emc_status emc_responsibilities(const emc_problem* pb, const float* G, const dou
  *       chunks (the k-direction split of Section 3.3) sum before division.
  *   ws  NULL, or emc_compress_workspace_bytes of device memory: one copy of
  *       the two grids per XCD, whose atomics stay in that XCD's L2 (faster);
- *       without it the atomics go to num/den directly.                       */
+ *       without it the atomics go to num/den directly.  With pb->scatter set
+ *       the c-step is brick-major, needs no workspace (0 bytes) and ignores ws. */
 emc_status emc_compress_workspace_bytes(const emc_problem* pb, size_t* bytes);
 emc_status emc_compress(const emc_problem* pb, const void* P, const void* K_packed,
                         const double* rho, float* Wp, double* num, double* den,
                         int32_t accumulate, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Brick-major c-step (eq. (2.12), the same sums as the rotation-major
+ * scatter with the loop nest turned round).  The grid is cut into bricks of
+ * 16^3 voxels; a visit is a pair (rotation j, group t of the 64 pixels
+ * 64t .. 64t+63) listed under every brick that a trilinear corner of a used
+ * pixel of the group reaches under R_j.  Visits are grouped by brick and cut
+ * into work items of at most `chunk` visits; one workgroup per item sums its
+ * brick in LDS (FP64) and adds it to num/den with one atomic per voxel.  The
+ * plan depends only on grid_n, n_pix, n_rot, q, mask and quat, so one build
+ * serves every iteration; point pb->scatter at it and emc_compress,
+ * emc_iterate and emc_iterate_proposed run their c-step this way (and need
+ * no grid copies in their workspaces).  Results equal the rotation-major
+ * c-step's up to the order of the FP64 additions.
+ * ------------------------------------------------------------------------ */
+typedef struct emc_scatter_plan {
+  int32_t grid_n, n_pix, n_rot;  /* geometry the plan was built for                  */
+  int32_t brick;                 /* brick edge in voxels (16)                        */
+  int32_t n_bricks;              /* ceil(N / brick)^3                                */
+  int32_t n_groups;              /* ceil(n_pix / 64) pixel groups                    */
+  int32_t chunk;                 /* most visits per work item                        */
+  int32_t reserved;
+  int64_t n_visits;              /* (j, t, brick) visits                             */
+  int64_t n_items;               /* work items                                       */
+  int64_t bytes;                 /* bytes of buf the plan uses or, after             */
+                                 /* EMC_ERR_WORKSPACE, needs                         */
+  const int32_t* visits;         /* [n_visits] j * n_groups + t, grouped by brick    */
+  const int32_t* items;          /* [n_items][4] (brick, first visit, end, 0)        */
+  const double* rot;             /* [n_rot][9] R_j row-major (FP64)                  */
+  const float* q;                /* geometry pointers the plan was built from        */
+  const uint8_t* mask;
+  const float* quat;
+} emc_scatter_plan;
+
+/* Bytes of buf emc_scatter_plan_build needs before it knows the visit count
+ * (the per-brick counters and offsets, the rotation table). */
+emc_status emc_scatter_plan_min_bytes(const emc_problem* pb, size_t* bytes);
+
+/* Build the plan for pb's geometry into buf (device memory, 256-byte aligned,
+ * buf_bytes >= emc_scatter_plan_min_bytes); the plan's arrays point into buf,
+ * which must outlive every call that uses the plan.
+ *   chunk  visits per work item, 0 for the default (2048), else 64 .. 2^20.
+ * Counts the visits on the device and reads the per-brick counts back (one
+ * synchronisation of `stream`); the listing itself is enqueued on `stream`,
+ * so later calls on other streams must wait for it.  When buf_bytes is too
+ * small, returns EMC_ERR_WORKSPACE with plan->bytes set to the bytes needed
+ * and nothing else filled.  EMC_ERR_UNSUPPORTED when n_rot * n_groups or the
+ * visit count exceeds 2^31 - 1. */
+emc_status emc_scatter_plan_build(const emc_problem* pb, int32_t chunk, void* buf, size_t buf_bytes,
+                                  emc_scatter_plan* plan, hipStream_t stream);
 
 /* Final division of eq. (2.12) and the mean log-evidence of eq. (2.1):
  *   model_out_l = num_l / den_l where den_l > 0, else model_prev_l

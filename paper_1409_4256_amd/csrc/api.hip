@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "../../include/emc.h"
 #include "emc_device.h"
@@ -57,6 +58,16 @@ emc_status check_problem(const emc_problem* pb, bool geom) {
     if (!pb->q || !pb->mask || !pb->quat || !pb->log_w) return fail(EMC_ERR_INVALID_ARG, "geometry pointer is NULL");
     if (!aligned(pb->q, 4) || !aligned(pb->quat, 16) || !aligned(pb->log_w, 8))
       return fail(EMC_ERR_INVALID_ARG, "misaligned geometry pointer");
+    if (const emc_scatter_plan* S = pb->scatter) {
+      const int nb = (pb->grid_n + brick_edge() - 1) / brick_edge();
+      if (S->grid_n != pb->grid_n || S->n_pix != pb->n_pix || S->n_rot != pb->n_rot || S->q != pb->q ||
+          S->mask != pb->mask || S->quat != pb->quat)
+        return fail(EMC_ERR_INVALID_ARG, "scatter plan was built for another geometry");
+      if (S->brick != brick_edge() || S->n_bricks != nb * nb * nb || S->n_groups != (pb->n_pix + 63) / 64 ||
+          S->n_items < 0 || S->n_visits < 0 || (S->n_items > 0 && (!S->items || !S->visits || !S->rot)) ||
+          !aligned(S->items, 16) || !aligned(S->rot, 8))
+        return fail(EMC_ERR_INVALID_ARG, "inconsistent scatter plan");
+    }
   }
   return EMC_OK;
 }
@@ -92,8 +103,11 @@ struct Layout {
   size_t slices, G, P, S, scale, c, b, stats, L, rho, num, den, copies, total;
 };
 
-// grid copies of the c-step's scatter: one numerator and one denominator per XCD
-size_t copies_bytes(const emc_problem* pb) { return (size_t)16 * pb->grid_n * pb->grid_n * pb->grid_n * sizeof(double); }
+// grid copies of the rotation-major c-step: one numerator and one denominator per
+// XCD (none with a brick-major plan)
+size_t copies_bytes(const emc_problem* pb) {
+  return pb->scatter ? 0 : (size_t)16 * pb->grid_n * pb->grid_n * pb->grid_n * sizeof(double);
+}
 
 Layout layout_of(const emc_problem* pb) {
   const Dims d = dims_of(pb);
@@ -171,6 +185,23 @@ emc_status run_estep(const emc_problem* pb, const float* G, const double* S, con
   return EMC_OK;
 }
 
+// num/den += the c-step sums of W' (row stride ps) and rho: brick-major with a plan,
+// else rotation-major (with per-XCD grid copies when `copies` is given)
+emc_status run_scatter(const emc_problem* pb, const float* Wp, int64_t ps, const double* rho, double* num,
+                       double* den, double* copies, hipStream_t st) {
+  if (const emc_scatter_plan* S = pb->scatter) {
+    const int nb = (pb->grid_n + brick_edge() - 1) / brick_edge();
+    HIP_TRY(launch_brick_scatter((const int4*)S->items, S->n_items, S->visits, S->n_groups, Wp, ps, rho, pb->q,
+                                 pb->mask, S->rot, pb->n_pix, pb->grid_n, nb, num, den, st),
+            "brick scatter");
+  } else {
+    HIP_TRY(launch_scatter(Wp, ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, copies,
+                           st),
+            "scatter");
+  }
+  return EMC_OK;
+}
+
 emc_status run_compress(const emc_problem* pb, const void* P, const void* K, const double* rho, float* Wp,
                         double* num, double* den, int32_t accumulate, double* copies, hipStream_t st) {
   const Dims d = dims_of(pb);
@@ -185,10 +216,7 @@ emc_status run_compress(const emc_problem* pb, const void* P, const void* K, con
   else
     HIP_TRY(launch_gemm_f32_nt((const float*)P, (const float*)KT, Wp, pb->n_rot, d.ps, d.ds, d.ds, d.ds, d.ps, st),
             "mstep gemm");
-  HIP_TRY(launch_scatter(Wp, d.ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den, copies,
-                         st),
-          "scatter");
-  return EMC_OK;
+  return run_scatter(pb, Wp, d.ps, rho, num, den, copies, st);
 }
 
 emc_status run_finalize(const emc_problem* pb, const double* num, const double* den, const float* prev, float* out,
@@ -330,6 +358,125 @@ emc_status emc_compress(const emc_problem* pb, const void* P, const void* K_pack
     CHECK(need(Wp, 16, "Wp"));
   }
   return run_compress(pb, P, K_packed, rho, Wp, num, den, accumulate, (double*)ws, st);
+}
+
+namespace {
+
+struct ScatterLayout {
+  size_t cnt, off, rot, items, visits, total;
+};
+
+ScatterLayout scatter_layout(int64_t n_bricks, int64_t n_rot, int64_t n_items, int64_t n_visits) {
+  ScatterLayout L;
+  size_t o = 0;
+  auto take = [&](int64_t bytes) {
+    size_t at = o;
+    o += (size_t)round_up(bytes, 256);
+    return at;
+  };
+  L.cnt = take(n_bricks * 4);
+  L.off = take((n_bricks + 1) * 8);
+  L.rot = take(n_rot * 9 * 8);
+  L.items = take(n_items * 16);
+  L.visits = take(n_visits * 4);
+  L.total = o;
+  return L;
+}
+
+int64_t bricks_of(const emc_problem* pb) {
+  const int64_t nb = (pb->grid_n + brick_edge() - 1) / brick_edge();
+  return nb * nb * nb;
+}
+
+}  // namespace
+
+emc_status emc_scatter_plan_min_bytes(const emc_problem* pb, size_t* bytes) {
+  CHECK(check_problem(pb, false));
+  if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = scatter_layout(bricks_of(pb), pb->n_rot, 0, 0).total;
+  return EMC_OK;
+}
+
+emc_status emc_scatter_plan_build(const emc_problem* pb, int32_t chunk, void* buf, size_t buf_bytes,
+                                  emc_scatter_plan* plan, hipStream_t st) {
+  CHECK(check_problem(pb, true));
+  if (!plan) return fail(EMC_ERR_INVALID_ARG, "plan is NULL");
+  if (chunk == 0) chunk = 2048;
+  if (chunk < 64 || chunk > (1 << 20)) return fail(EMC_ERR_INVALID_ARG, "chunk=%d outside [64, 2^20]", chunk);
+  const int64_t n_bricks = bricks_of(pb);
+  const int nb = (pb->grid_n + brick_edge() - 1) / brick_edge();
+  const int n_groups = (pb->n_pix + 63) / 64;
+  if ((int64_t)pb->n_rot * n_groups > INT32_MAX)
+    return fail(EMC_ERR_UNSUPPORTED, "n_rot * pixel groups = %lld exceeds 2^31 - 1",
+                (long long)pb->n_rot * n_groups);
+  CHECK(need(buf, 256, "buf"));
+  const ScatterLayout L0 = scatter_layout(n_bricks, pb->n_rot, 0, 0);
+  if (buf_bytes < L0.total) {
+    plan->bytes = (int64_t)L0.total;
+    return fail(EMC_ERR_WORKSPACE, "scatter plan buffer has %zu bytes, needs at least %zu", buf_bytes, L0.total);
+  }
+  char* b = (char*)buf;
+  int* cnt = (int*)(b + L0.cnt);
+  double* rot = (double*)(b + L0.rot);
+  HIP_TRY(launch_brick_rot(pb->quat, pb->n_rot, rot, st), "rotation table");
+  HIP_TRY(launch_fill_i32(cnt, n_bricks, 0, st), "zero brick counts");
+  HIP_TRY(launch_brick_visits(pb->q, pb->mask, rot, pb->n_pix, pb->n_rot, n_groups, pb->grid_n, nb, cnt, nullptr,
+                              nullptr, st),
+          "count visits");
+  std::vector<int> h(n_bricks);
+  HIP_TRY(hipMemcpyAsync(h.data(), cnt, n_bricks * 4, hipMemcpyDeviceToHost, st), "read brick counts");
+  HIP_TRY(hipStreamSynchronize(st), "read brick counts");
+  std::vector<int64_t> off(n_bricks + 1, 0);
+  int64_t max_items = 0;
+  for (int64_t k = 0; k < n_bricks; ++k) {
+    off[k + 1] = off[k] + h[k];
+    max_items = std::max<int64_t>(max_items, (h[k] + chunk - 1) / chunk);
+  }
+  const int64_t n_visits = off[n_bricks];
+  if (n_visits > INT32_MAX) return fail(EMC_ERR_UNSUPPORTED, "%lld visits exceed 2^31 - 1", (long long)n_visits);
+  // items ordered by chunk index, then brick: a brick's items spread over the launch
+  std::vector<int4> items;
+  for (int64_t c = 0; c < max_items; ++c)
+    for (int64_t k = 0; k < n_bricks; ++k)
+      if ((int64_t)c * chunk < h[k]) {
+        const int64_t first = off[k] + c * chunk;
+        items.push_back(make_int4((int)k, (int)first, (int)std::min<int64_t>(first + chunk, off[k + 1]), 0));
+      }
+  const int64_t n_items = (int64_t)items.size();
+  const ScatterLayout L = scatter_layout(n_bricks, pb->n_rot, n_items, n_visits);
+  plan->bytes = (int64_t)L.total;
+  if (buf_bytes < L.total)
+    return fail(EMC_ERR_WORKSPACE, "scatter plan buffer has %zu bytes, needs %zu", buf_bytes, L.total);
+  int64_t* doff = (int64_t*)(b + L.off);
+  int4* ditems = (int4*)(b + L.items);
+  int* dvisits = (int*)(b + L.visits);
+  HIP_TRY(hipMemcpyAsync(doff, off.data(), (n_bricks + 1) * 8, hipMemcpyHostToDevice, st), "write offsets");
+  if (n_items > 0)
+    HIP_TRY(hipMemcpyAsync(ditems, items.data(), n_items * 16, hipMemcpyHostToDevice, st), "write items");
+  HIP_TRY(launch_fill_i32(cnt, n_bricks, 0, st), "zero brick cursors");
+  HIP_TRY(launch_brick_visits(pb->q, pb->mask, rot, pb->n_pix, pb->n_rot, n_groups, pb->grid_n, nb, cnt, doff,
+                              dvisits, st),
+          "list visits");
+  HIP_TRY(hipStreamSynchronize(st), "list visits");  // the host arrays above go out of scope
+  emc_scatter_plan P = {};
+  P.grid_n = pb->grid_n;
+  P.n_pix = pb->n_pix;
+  P.n_rot = pb->n_rot;
+  P.brick = brick_edge();
+  P.n_bricks = (int32_t)n_bricks;
+  P.n_groups = n_groups;
+  P.chunk = chunk;
+  P.n_visits = n_visits;
+  P.n_items = n_items;
+  P.bytes = (int64_t)L.total;
+  P.visits = dvisits;
+  P.items = (const int32_t*)ditems;
+  P.rot = rot;
+  P.q = pb->q;
+  P.mask = pb->mask;
+  P.quat = pb->quat;
+  *plan = P;
+  return EMC_OK;
 }
 
 emc_status emc_finalize(const emc_problem* pb, const double* num, const double* den, const float* model_prev,
@@ -1005,9 +1152,7 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   CHECK(mark(6));
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
   HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");
-  HIP_TRY(launch_scatter(Wp, ps, rho, pb->q, pb->mask, pb->quat, pb->n_pix, pb->n_rot, pb->grid_n, num, den,
-                         (double*)(w + W.copies), st),
-          "scatter");
+  CHECK(run_scatter(pb, Wp, ps, rho, num, den, (double*)(w + W.copies), st));
   CHECK(run_finalize(pb, num, den, model_in, model_out, L, nc + na, loglik, st));
   CHECK(mark(7));
   return EMC_OK;

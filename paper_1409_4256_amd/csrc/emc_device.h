@@ -110,6 +110,14 @@ hipError_t launch_lse_write_bf16(const float* G, int64_t ldg, void* P, int64_t l
 hipError_t launch_scatter(const float* Wp, int64_t stride, const double* rho, const float* q,
                           const uint8_t* mask, const float* quat, int n_pix, int n_rot, int N, double* num,
                           double* den, double* copies, hipStream_t st);
+int brick_edge();
+hipError_t launch_brick_rot(const float* quat, int n_rot, double* rot, hipStream_t st);
+hipError_t launch_brick_visits(const float* q, const uint8_t* mask, const double* rot, int n_pix, int n_rot,
+                               int n_groups, int N, int nb, int* cnt, const int64_t* off, int* visits, hipStream_t st);
+hipError_t launch_brick_scatter(const int4* items, int64_t n_items, const int* visits, int n_groups, const float* Wp,
+                                int64_t stride, const double* rho, const float* q, const uint8_t* mask,
+                                const double* rot, int n_pix, int N, int nb, double* num, double* den,
+                                hipStream_t st);
 hipError_t launch_divide(const double* num, const double* den, const float* prev, float* out, int64_t M,
                          hipStream_t st);
 hipError_t launch_mean(const double* L, int64_t n, double* out, hipStream_t st);

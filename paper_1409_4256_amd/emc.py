@@ -34,7 +34,7 @@ EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride",
            "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_topk", "emc_topk_union",
            "emc_cell_targets",
            "emc_pack_frames_list", "emc_proposal_bytes", "emc_proposal_build", "emc_proposed_workspace_bytes",
-           "emc_iterate_proposed")
+           "emc_iterate_proposed", "emc_scatter_plan_min_bytes", "emc_scatter_plan_build")
 
 
 class EmcError(RuntimeError):
@@ -56,6 +56,18 @@ class Problem(ctypes.Structure):
         ("mask", ctypes.c_void_p),
         ("quat", ctypes.c_void_p),
         ("log_w", ctypes.c_void_p),
+        ("scatter", ctypes.c_void_p),
+    ]
+
+
+class ScatterPlan(ctypes.Structure):
+    _fields_ = [
+        ("grid_n", ctypes.c_int32), ("n_pix", ctypes.c_int32), ("n_rot", ctypes.c_int32),
+        ("brick", ctypes.c_int32), ("n_bricks", ctypes.c_int32), ("n_groups", ctypes.c_int32),
+        ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_visits", ctypes.c_int64), ("n_items", ctypes.c_int64), ("bytes", ctypes.c_int64),
+        ("visits", ctypes.c_void_p), ("items", ctypes.c_void_p), ("rot", ctypes.c_void_p),
+        ("q", ctypes.c_void_p), ("mask", ctypes.c_void_p), ("quat", ctypes.c_void_p),
     ]
 
 
@@ -131,6 +143,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_proposed_workspace_bytes.restype = st
     lib.emc_iterate_proposed.argtypes = [_PB, _PP, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]
     lib.emc_iterate_proposed.restype = st
+    lib.emc_scatter_plan_min_bytes.argtypes, lib.emc_scatter_plan_min_bytes.restype = [_PB, szp], st
+    lib.emc_scatter_plan_build.argtypes = [_PB, i32, _P, ctypes.c_size_t, ctypes.POINTER(ScatterPlan), _P]
+    lib.emc_scatter_plan_build.restype = st
     _lib = lib
     return lib
 
@@ -180,14 +195,25 @@ class Geometry:
         self.log_w = log_w.to(device="cuda", dtype=torch.float64).contiguous()
         self.pb = Problem(int(grid_n), int(self.q.shape[0]), int(self.quat.shape[0]), int(n_data),
                           int(precision), 0, self.q.data_ptr(), self.mask.data_ptr(), self.quat.data_ptr(),
-                          self.log_w.data_ptr())
+                          self.log_w.data_ptr(), None)
+        self.scatter_plan = None   # (ScatterPlan, its device buffer) once built
+        self.scatter_buf = None
 
     def with_frames(self, n_data):
         g = object.__new__(Geometry)
         g.q, g.mask, g.quat, g.log_w = self.q, self.mask, self.quat, self.log_w
+        g.scatter_plan, g.scatter_buf = self.scatter_plan, self.scatter_buf
         g.pb = Problem(self.pb.grid_n, self.pb.n_pix, self.pb.n_rot, int(n_data), self.pb.precision, 0,
-                       self.pb.q, self.pb.mask, self.pb.quat, self.pb.log_w)
+                       self.pb.q, self.pb.mask, self.pb.quat, self.pb.log_w, self.pb.scatter)
         return g
+
+    def use_brick_scatter(self, chunk=0, stream=None):
+        """Build the brick-major c-step plan for this geometry and use it in every
+        later call (see emc_scatter_plan_build); returns the plan."""
+        plan, buf = emc_scatter_plan_build(self, chunk, stream)
+        self.scatter_plan, self.scatter_buf = plan, buf
+        self.pb.scatter = ctypes.cast(ctypes.pointer(plan), ctypes.c_void_p)
+        return plan
 
     @property
     def n_pix(self):
@@ -492,6 +518,31 @@ def emc_proposal_build(geo: Geometry, coarse, n_cells, topk, k_top, audit, count
         _ptr(buf, torch.uint8, emc_proposal_bytes(geo, n_cells, k_top, n_audit, nz_cap), "buf"),
         ctypes.c_size_t(buf.numel()), ctypes.byref(plan), _stream(stream)))
     return plan
+
+
+def emc_scatter_plan_min_bytes(geo: Geometry) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().emc_scatter_plan_min_bytes(ctypes.byref(geo.pb), ctypes.byref(n)))
+    return int(n.value)
+
+
+def emc_scatter_plan_build(geo: Geometry, chunk=0, stream=None):
+    """(plan, buf): the brick-major c-step plan for geo's geometry in a device
+    buffer sized by a first call that counts the visits."""
+    import torch
+
+    lib = load()
+    plan = ScatterPlan()
+    buf = torch.empty(emc_scatter_plan_min_bytes(geo), dtype=torch.uint8, device="cuda")
+    for attempt in range(2):
+        status = lib.emc_scatter_plan_build(ctypes.byref(geo.pb), int(chunk), _ptr(buf, torch.uint8, name="buf"),
+                                            ctypes.c_size_t(buf.numel()), ctypes.byref(plan), _stream(stream))
+        if status == EMC_ERR_WORKSPACE and attempt == 0 and plan.bytes > buf.numel():
+            buf = torch.empty(int(plan.bytes), dtype=torch.uint8, device="cuda")
+            continue
+        _check(status)
+        return plan, buf
+    raise AssertionError("unreachable")
 
 
 def emc_proposed_workspace_bytes(geo: Geometry, plan: Proposal) -> int:

@@ -42,7 +42,7 @@ def test_strides(lib):
 def _pb(**kw):
     fake = 1 << 20  # never dereferenced: validation fails before any launch
     d = dict(grid_n=32, n_pix=1024, n_rot=1000, n_data=1000, precision=0, reserved=0,
-             q=fake, mask=fake, quat=fake, log_w=fake)
+             q=fake, mask=fake, quat=fake, log_w=fake, scatter=None)
     d.update(kw)
     return emc.Problem(*[d[k] for k, _ in emc.Problem._fields_])
 
@@ -128,7 +128,7 @@ def test_python_binding_raises_emc_error(lib):
 
 
 def test_struct_layouts_match_the_header(tmp_path):
-    """sizeof and every field offset of emc_problem and emc_proposal, from the C
+    """sizeof and every field offset of emc_problem, emc_proposal and emc_scatter_plan, from the C
     compiler reading include/emc.h, equal the Python binding's mirrors."""
     import shutil
     import subprocess
@@ -137,7 +137,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     if gcc is None or not os.path.isdir("/opt/rocm/include"):
         pytest.skip("needs gcc and the ROCm headers")
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "emc.h"', "int main(void) {"]
-    for cname, cls in (("emc_problem", emc.Problem), ("emc_proposal", emc.Proposal)):
+    structs = (("emc_problem", emc.Problem), ("emc_proposal", emc.Proposal), ("emc_scatter_plan", emc.ScatterPlan))
+    for cname, cls in structs:
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in cls._fields_:
             lines.append(f'  printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
@@ -149,7 +150,7 @@ def test_struct_layouts_match_the_header(tmp_path):
                     str(src), "-o", str(exe)], check=True)
     got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
                                                         text=True).stdout.splitlines())
-    for cname, cls in (("emc_problem", emc.Problem), ("emc_proposal", emc.Proposal)):
+    for cname, cls in structs:
         assert int(got[cname]) == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, f
@@ -181,3 +182,44 @@ def test_proposal_plan_bytes_config2(lib):
     n = ctypes.c_size_t()
     assert lib.emc_proposal_bytes(ctypes.byref(pb), 2000, 128, 2000, 200_000_000, ctypes.byref(n)) == emc.EMC_OK
     assert n.value < 3 * 2 ** 30
+
+
+def _fake_plan(pb, **kw):
+    d = dict(grid_n=pb.grid_n, n_pix=pb.n_pix, n_rot=pb.n_rot, brick=16, n_bricks=((pb.grid_n + 15) // 16) ** 3,
+             n_groups=(pb.n_pix + 63) // 64, chunk=2048, reserved=0, n_visits=10, n_items=1, bytes=0,
+             visits=1 << 20, items=1 << 20, rot=1 << 20, q=pb.q, mask=pb.mask, quat=pb.quat)
+    d.update(kw)
+    return emc.ScatterPlan(*[d[k] for k, _ in emc.ScatterPlan._fields_])
+
+
+def test_scatter_plan_argument_checks(lib):
+    """Brick-major c-step plan: sizes, and plans that do not fit the geometry are refused."""
+    pb = _pb(grid_n=128, n_pix=16384, n_rot=25000, n_data=100000)
+    n = ctypes.c_size_t()
+    assert lib.emc_scatter_plan_min_bytes(ctypes.byref(pb), ctypes.byref(n)) == emc.EMC_OK
+    # 512 brick counters, 513 offsets, the FP64 R_j table, each rounded up to 256 bytes
+    assert n.value == 2048 + 4352 + -(-25000 * 72 // 256) * 256
+    a = ctypes.c_void_p(1 << 20)
+    plan = emc.ScatterPlan()
+    assert lib.emc_scatter_plan_build(ctypes.byref(pb), 5, a, n, ctypes.byref(plan), None) == emc.EMC_ERR_INVALID_ARG
+    assert b"chunk" in lib.emc_last_error()
+    big = _pb(n_rot=2 ** 31 - 1)
+    assert lib.emc_scatter_plan_build(ctypes.byref(big), 0, a, n, ctypes.byref(plan), None) == emc.EMC_ERR_UNSUPPORTED
+    assert lib.emc_scatter_plan_build(ctypes.byref(pb), 0, ctypes.c_void_p((1 << 20) + 8), n, ctypes.byref(plan),
+                                      None) == emc.EMC_ERR_INVALID_ARG
+    # with a plan the c-step needs no grid copies
+    good = _fake_plan(pb)
+    pbs = _pb(grid_n=128, n_pix=16384, n_rot=25000, n_data=100000, scatter=ctypes.addressof(good))
+    assert lib.emc_compress_workspace_bytes(ctypes.byref(pbs), ctypes.byref(n)) == emc.EMC_OK
+    assert n.value == 0
+    w0, w1 = ctypes.c_size_t(), ctypes.c_size_t()
+    lib.emc_workspace_bytes(ctypes.byref(pb), ctypes.byref(w0))
+    lib.emc_workspace_bytes(ctypes.byref(pbs), ctypes.byref(w1))
+    assert w0.value - w1.value == 16 * 128 ** 3 * 8
+    # a plan of another geometry, or an inconsistent one, is refused before any launch
+    for bad in (_fake_plan(pb, grid_n=64), _fake_plan(pb, n_rot=24999), _fake_plan(pb, quat=1 << 21),
+                _fake_plan(pb, brick=8), _fake_plan(pb, n_groups=3), _fake_plan(pb, items=0)):
+        pbb = _pb(grid_n=128, n_pix=16384, n_rot=25000, n_data=100000, scatter=ctypes.addressof(bad))
+        st = lib.emc_compress(ctypes.byref(pbb), a, a, a, a, a, a, 0, None, 0, None)
+        assert st == emc.EMC_ERR_INVALID_ARG
+        assert b"scatter plan" in lib.emc_last_error()

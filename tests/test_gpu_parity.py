@@ -78,28 +78,35 @@ def test_config1_full_iteration_matches_oracle(gpu_lib, cfg1, start):
 @pytest.mark.parametrize("seed,N,npx,nrot,ndata,qr", [(0, 24, 529, 300, 333, None), (1, 20, 257, 129, 517, None),
                                                       (2, 16, 64, 1, 40, None), (3, 18, 300, 257, 1, None),
                                                       (4, 12, 200, 70, 90, 2.5)])
-@pytest.mark.parametrize("grid_copies", [True, False])
-def test_ragged_shapes_match_oracle(gpu_lib, seed, N, npx, nrot, ndata, qr, grid_copies):
+@pytest.mark.parametrize("cstep", ["copies", "direct", "brick", "brick_chunk64"])
+def test_ragged_shapes_match_oracle(gpu_lib, seed, N, npx, nrot, ndata, qr, cstep):
     # random pixel positions in a ball of radius N/2 - 2 spread each 64-pixel group
-    # beyond the compression's local box (global-atomic path); qr = 2.5 keeps them
-    # inside it (local-box path)
+    # beyond the rotation-major compression's local box (global-atomic path) and over
+    # many bricks; qr = 2.5 keeps them inside one box (local-box path).  c-step forms:
+    # rotation-major with per-XCD grid copies or direct atomics, brick-major with the
+    # default work items or 64-visit ones (several items per brick).
     from gpu_helpers import geometry, pack, run_steps, upload_counts
 
     t = tiny_problem(seed, grid_n=N, n_pix=npx, n_rot=nrot, n_data=ndata, photons=200.0, q_radius=qr)
     q, quat = _inputs_f32(t["q"], t["quat"])
     geo = geometry(N, q, t["mask"], quat, t["log_w"], ndata)
+    if cstep.startswith("brick"):
+        geo.use_brick_scatter(chunk=64 if cstep == "brick_chunk64" else 0)
     K = pack(geo, upload_counts(t["counts"]))
-    g = run_steps(geo, t["model"], K, grid_copies=grid_copies)
+    g = run_steps(geo, t["model"], K, grid_copies=cstep == "copies")
     o = _oracle(t["model"], t["counts"], q, t["mask"], quat, t["log_w"], N)
-    _check_all(g, o, t["mask"], f"seed{seed} grid copies {grid_copies}")
+    _check_all(g, o, t["mask"], f"seed{seed} c-step {cstep}")
 
 
-def test_frame_chunks_accumulate_before_division(gpu_lib):
+@pytest.mark.parametrize("brick", [False, True])
+def test_frame_chunks_accumulate_before_division(gpu_lib, brick):
     from gpu_helpers import geometry, pack, rel_l2, run_steps, upload_counts
 
     t = tiny_problem(5, grid_n=20, n_pix=400, n_rot=200, n_data=700, photons=150.0)
     q, quat = _inputs_f32(t["q"], t["quat"])
     geo = geometry(20, q, t["mask"], quat, t["log_w"], 700)
+    if brick:
+        geo.use_brick_scatter()
     chunks = []
     for s in range(0, 700, 256):
         g = geo.with_frames(min(256, 700 - s))
@@ -126,7 +133,8 @@ def test_empty_frame_set_keeps_model(gpu_lib):
     assert np.all(g["den"] == 0)
 
 
-def test_single_rotation_mean_frame_on_gpu(gpu_lib):
+@pytest.mark.parametrize("brick", [False, True])
+def test_single_rotation_mean_frame_on_gpu(gpu_lib, brick):
     # identity rotation, flat detector on integer voxels: the touched voxels are
     # exactly the mean frame (closed form of the method)
     from gpu_helpers import geometry, pack, run_steps, upload_counts
@@ -140,6 +148,8 @@ def test_single_rotation_mean_frame_on_gpu(gpu_lib):
     K = np.random.default_rng(3).poisson(5.0, size=(37, q.shape[0])).astype(np.uint16)
     K[:, mask == 0] = 0
     geo = geometry(N, q, mask, np.array([[1.0, 0, 0, 0]]), np.array([0.0]), 37)
+    if brick:
+        geo.use_brick_scatter()
     g = run_steps(geo, np.ones(N ** 3), pack(geo, upload_counts(K)))
     l = ((X.ravel() + 8) * N + (Y.ravel() + 8)) * N + 8
     v = mask.astype(bool)
@@ -210,7 +220,8 @@ def test_virtual_rotation_shards_equal_unsharded(gpu_lib):
 
 
 @pytest.mark.parametrize("precision", [E.EMC_PREC_FP32, E.EMC_PREC_BF16])
-def test_iterate_entry_point_equals_steps(gpu_lib, cfg1, precision):
+@pytest.mark.parametrize("brick", [False, True])
+def test_iterate_entry_point_equals_steps(gpu_lib, cfg1, precision, brick):
     import torch
 
     from gpu_helpers import geometry, pack, run_steps, upload_counts
@@ -218,6 +229,8 @@ def test_iterate_entry_point_equals_steps(gpu_lib, cfg1, precision):
     inp = cfg1
     q, quat = _inputs_f32(inp.q, inp.quat)
     geo = geometry(32, q, inp.mask, quat, inp.log_w, inp.wl.n_data, precision)
+    if brick:
+        geo.use_brick_scatter()
     K = pack(geo, upload_counts(inp.counts))
     steps = run_steps(geo, inp.model_start, K)
     ws = torch.empty(E.emc_workspace_bytes(geo), dtype=torch.uint8, device="cuda")

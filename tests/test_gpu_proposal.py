@@ -32,7 +32,8 @@ def _lists(rng, ndata, n_cells, k_top, k_extra, ragged):
     return out
 
 
-def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=300.0, k_extra=0, ragged=False):
+def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=300.0, k_extra=0, ragged=False,
+         brick=False):
     import torch
 
     from gpu_helpers import geometry, upload_counts
@@ -46,6 +47,8 @@ def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=30
     kk = lists.shape[1]
     audit = np.sort(rng.choice(ndata, n_audit, replace=False)).astype(np.int32)
     geo = geometry(N, q, t["mask"], quat, t["log_w"], ndata, E.EMC_PREC_BF16)
+    if brick:
+        geo.use_brick_scatter(chunk=64)
     dev = "cuda"
     topk = torch.as_tensor(lists.reshape(-1), device=dev)
     counts = upload_counts(t["counts"])
@@ -116,6 +119,12 @@ def test_union_lists_ragged_and_multi_group_cells(gpu_lib):
     r = _run(5, 20, 300, 1000, 500, 10, 3, 20, k_extra=3, ragged=True)
     _check_restricted(r, 500, "union/ragged/multi-group")
     assert r["plan"].n_groups > r["plan"].n_cells
+
+
+def test_brick_major_compress(gpu_lib):
+    """The proposal iteration with the brick-major c-step."""
+    r = _run(0, 20, 300, 700, 600, 40, 8, 12, brick=True)
+    _check_restricted(r, 600, "brick-major c-step")
 
 
 def test_sparse_bands_only(gpu_lib):
