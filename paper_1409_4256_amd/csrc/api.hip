@@ -744,7 +744,7 @@ int words_of(int n_cells) { return (n_cells + 31) / 32; }
 
 constexpr int kMaxTop = 256;      // proposed cells per frame
 constexpr int kBandPx = 128;      // granularity of the entry-offset table (the kernels' band)
-constexpr int kTileFrames = 64;   // frames per candidate log-likelihood tile
+constexpr int kTileFrames = 256;  // frames per candidate log-likelihood tile
 constexpr int kGroupRot = 32;     // rotations per group
 constexpr int kMaxDense = 16;     // bands handled by the M-step's dense product (at most)
 

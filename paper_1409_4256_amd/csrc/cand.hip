@@ -33,7 +33,8 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGR = 32;             // rotations per group (two 16-row MFMA tiles)
-constexpr int kFT = 64;             // frames per log-likelihood workgroup (four 16-column tiles)
+constexpr int kFT = 64;             // frames per log-likelihood wave (four 16-column tiles)
+constexpr int kTileF = 4 * kFT;     // frames per log-likelihood workgroup (tile)
 constexpr int kBand = 128;          // pixels per band (granularity of the entry-offset table)
 constexpr int kLRow = kBand + 8;    // LDS row of one frame's band, bf16 (272 bytes: conflict-free 16-byte reads)
 constexpr int kFB = 32;             // frames per M-step block (one MFMA reduction step)
@@ -90,25 +91,26 @@ __device__ __forceinline__ void put_rest(uint16_t* base, int stride, const u4* _
 }
 
 // ------------------------------------------------------------------ log-likelihood
-// One workgroup per tile (group g, frames [f0, f0 + 64) of the group's cell).  Wave w
-// takes the bands w, w + 4, ... of all 64 frames (lane s expands frame s) and both
-// rotation tiles; the four partial sums are added in LDS at the end.
+// One workgroup per tile (group g, frames [f0, f0 + 256) of the group's cell).  Wave w
+// owns frames f0 + 64 w .. + 63 (lane s expands frame s) over every band and both
+// rotation tiles, so the four waves read the same slice rows at about the same
+// time (one fetch from L2 serves the workgroup) and each wave writes its own
+// frames' G; there is no barrier, and waves without frames leave at once.
 __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     const int2* __restrict__ tiles, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
     const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int2* __restrict__ band_range,
     int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ cell_rot, const uint16_t* __restrict__ hi,
     int64_t plane, const float* __restrict__ scale, int64_t ps, float* __restrict__ G) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kFT * kLRow];  // 69632 bytes
-  __shared__ float ssc[kGR];
   const int2 tl = tiles[blockIdx.x];
   if (tl.x < 0) return;  // padding tile (uniform)
   const int4 gr = groups[tl.x];
   const int c = gr.x, r0 = gr.y, nr = gr.z;
   const int64_t F = cf_ptr[c + 1] - cf_ptr[c];
-  const int f0 = tl.y;
-  const int nf = (int)(F - f0 < kFT ? F - f0 : kFT);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x < kGR) ssc[threadIdx.x] = threadIdx.x < nr ? scale[cell_rot[r0 + threadIdx.x]] : 0.0f;
+  const int f0 = tl.y + wave * kFT;
+  if (f0 >= F) return;  // uniform per wave
+  const int nf = (int)(F - f0 < kFT ? F - f0 : kFT);
 
   const int nbands = (int)(ps / kBand);
   // this lane's frame (slot = lane): its bands' chunk ranges, rng[band * n_list]
@@ -135,11 +137,11 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
   const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
   // pipeline: chunks of the current band in registers, the next band's chunk range
   int2 r0c = {0, 0}, r1c = {0, 0};
-  if (has && wave < nbands) r0c = rng[wave * n_list];
+  if (has) r0c = rng[0];
   u4 w0[kWin];
 #pragma unroll
   for (int u = 0; u < kWin; ++u) w0[u] = r0c.x + u < r0c.y ? load_chunk<false>(fb + r0c.x + u) : pad;
-  if (has && wave + 4 < nbands) r1c = rng[(wave + 4) * n_list];
+  if (has && 1 < nbands) r1c = rng[n_list];
   // A fragments (slice rows, hi and lo, both row tiles) of a band, 4 k-steps
   auto load_a = [&](int band, u4 (&h)[4][2], u4 (&l)[4][2]) {
 #pragma unroll
@@ -153,18 +155,18 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     }
   };
   u4 ah[4][2], al[4][2];
-  load_a(wave, ah, al);
-  for (int band = wave; band < nbands; band += 4) {
+  load_a(0, ah, al);
+  for (int band = 0; band < nbands; ++band) {
     // prefetch (all issued before this band's data is waited on; loads complete in
-    // issue order): the next band's A fragments and chunks, the table entries of
-    // the band after
+    // issue order): the next band's A fragments and chunks, the table entry of the
+    // band after
     u4 ahn[4][2], aln[4][2];
-    load_a(band + 4, ahn, aln);
+    load_a(band + 1, ahn, aln);
     u4 w1[kWin];
 #pragma unroll
     for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? load_chunk<false>(fb + r1c.x + u) : pad;
     int2 r2c = {0, 0};
-    if (has && band + 8 < nbands) r2c = rng[(band + 8) * n_list];
+    if (has && band + 2 < nbands) r2c = rng[(band + 2) * n_list];
     if (has) {
 #pragma unroll
       for (int u = 0; u < kWin; ++u) put_chunk<false>(frow, 1, w0[u]);
@@ -183,8 +185,18 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
         }
       }
     }
-    // clear the band's rows (contiguous 16-byte stores: no reloads of the chunks)
-    for (int e = lane; e < kFT * kLRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = zero;
+    // clear what this lane wrote: the words of its register window, or its whole row
+    // when the band held more chunks than the window (the wave's LDS operations run
+    // in order, so the MFMA operand reads above are done)
+    if (has) {
+      if (r0c.y - r0c.x <= kWin) {
+#pragma unroll
+        for (int u = 0; u < kWin; ++u) put_chunk<true>(frow, 1, w0[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < kLRow / 8; ++e) reinterpret_cast<u4*>(frow)[e] = zero;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < kWin; ++u) w0[u] = w1[u];
 #pragma unroll
@@ -198,33 +210,19 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     r1c = r2c;
   }
 
-  // sum of the four waves' partials: red[wave][slot][32] floats in the same LDS
-  __syncthreads();
-  float* red = reinterpret_cast<float*>(lds);
+  // G[frame][rotation] = scale_r * sum: lane holds frame 16 j + m, rotations
+  // 16 i + 4 (lane >> 4) + 0..3 of tile (i, j)
+  float* out = G + grp_off[tl.x] + (int64_t)f0 * kGR;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
+    if (i == 1 && !two) break;
+    const int rb = 16 * i + 4 * (lane >> 4);
+    f4 sc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sc[u] = rb + u < nr ? scale[cell_rot[r0 + rb + u]] : 0.0f;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      *reinterpret_cast<f4*>(&red[(wave * kFT + 16 * j + m) * kGR + 16 * i + 4 * (lane >> 4)]) = acc[i][j];
-  __syncthreads();
-  const int s = threadIdx.x >> 2, mb = 8 * (threadIdx.x & 3);
-  if (s < nf) {
-    float v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = 0.0f;
-#pragma unroll
-    for (int w = 0; w < 4; ++w)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] += red[(w * kFT + s) * kGR + mb + u];
-    float* out = G + grp_off[tl.x] + (int64_t)(f0 + s) * kGR + mb;
-    f4 o0, o1;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      o0[u] = ssc[mb + u] * v[u];
-      o1[u] = ssc[mb + 4 + u] * v[4 + u];
-    }
-    *reinterpret_cast<f4*>(out) = o0;
-    *reinterpret_cast<f4*>(out + 4) = o1;
+      if (16 * j + m < nf) *reinterpret_cast<f4*>(out + (16 * j + m) * kGR + rb) = sc * acc[i][j];
   }
 }
 
@@ -634,7 +632,7 @@ __global__ void group_tiles_kernel(const int4* __restrict__ groups, const int64_
   int64_t len[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t g = 0; g < n_groups; ++g) {
     const int c = groups[g].x;
-    const int64_t nt = (cf_ptr[c + 1] - cf_ptr[c] + kFT - 1) / kFT;
+    const int64_t nt = (cf_ptr[c + 1] - cf_ptr[c] + kTileF - 1) / kTileF;
     int x = 0;
     for (int y = 1; y < 8; ++y) x = len[y] < len[x] ? y : x;
     xcd_of[g] = x;
@@ -649,9 +647,9 @@ __global__ void group_tiles_kernel(const int4* __restrict__ groups, const int64_
   int64_t q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t g = 0; g < n_groups; ++g) {
     const int c = groups[g].x;
-    const int64_t nt = (cf_ptr[c + 1] - cf_ptr[c] + kFT - 1) / kFT;
+    const int64_t nt = (cf_ptr[c + 1] - cf_ptr[c] + kTileF - 1) / kTileF;
     const int x = xcd_of[g];
-    for (int64_t t = 0; t < nt; ++t) tiles[8 * (q[x]++) + x] = make_int2((int)g, (int)(t * kFT));
+    for (int64_t t = 0; t < nt; ++t) tiles[8 * (q[x]++) + x] = make_int2((int)g, (int)(t * kTileF));
   }
   for (int x = 0; x < 8; ++x)
     for (; q[x] < q_max; ++q[x]) tiles[8 * q[x] + x] = make_int2(-1, 0);
