@@ -1115,7 +1115,8 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
     // the dense bands' responsibility matrix is zero outside the candidate pairs
     if (Pd) HIP_TRY(launch_fill_zero_bytes(Pd, (int64_t)pb->n_rot * plan->ld_dense * 2, st), "zero dense P");
     HIP_TRY(launch_cand_estep(G, Pc, groups, plan->grp_off, plan->cg_ptr, plan->cand_cells, plan->pair_col,
-                              plan->k_top, nc, plan->cell_rot, pb->log_w, S, b, L, Pd, plan->ld_dense, st),
+                              plan->k_top, nc, plan->cell_rot, pb->log_w, S, b, L, Pd, plan->ld_dense,
+                              (const int2*)plan->tiles, plan->n_tiles, plan->cf_ptr, plan->cf_frame, st),
             "candidate estep");
   }
   CHECK(mark(3));

@@ -237,17 +237,15 @@ __device__ __forceinline__ void lse_push(double& mx, double& s, double a) {
   }
 }
 
-// One wave per candidate frame; lanes take the frame's proposed cells (slot t =
-// lane + 64 u).  a = Q + log w_j = G + b_f - S_j + log w_j, log-evidence over the
-// frame's candidates in FP64, P = exp(a - L) stored in BF16 (eq. 2.4); with Pd,
-// also into the dense [rotation][frame] matrix (zero elsewhere) of the M-step's
-// dense bands.
+// Log-evidence of each candidate frame: one wave per frame, lanes take the frame's
+// proposed cells (slot t = lane + 64 u); a = Q + log w_j = G + b_f - S_j + log w_j
+// and L_f = log sum over the frame's candidates of e^a, in FP64 (eq. 2.4's
+// denominator).
 __global__ __launch_bounds__(256) void cand_estep_kernel(
-    const float* __restrict__ G, uint16_t* __restrict__ P, const int4* __restrict__ groups,
-    const int64_t* __restrict__ grp_off, const int64_t* __restrict__ cg_ptr, const int32_t* __restrict__ cells,
-    const int32_t* __restrict__ pair_col, int k_top, int64_t n_frames, const int32_t* __restrict__ cell_rot,
-    const double* __restrict__ log_w, const double* __restrict__ S, const double* __restrict__ b,
-    double* __restrict__ L, uint16_t* __restrict__ Pd, int64_t ldd) {
+    const float* __restrict__ G, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
+    const int64_t* __restrict__ cg_ptr, const int32_t* __restrict__ cells, const int32_t* __restrict__ pair_col,
+    int k_top, int64_t n_frames, const int32_t* __restrict__ cell_rot, const double* __restrict__ log_w,
+    const double* __restrict__ S, const double* __restrict__ b, double* __restrict__ L) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= n_frames) return;  // uniform per wave
@@ -276,24 +274,37 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
       sum += s2 * exp(m2 - mx);
     }
   }
-  const double lse = mx + log(sum);
-  if (lane == 0) L[f] = lse;
-  for (int t = lane; t < k_top; t += 64) {
-    const int c = cells[f * k_top + t];
-    if (c < 0) continue;
-    const int64_t col = pair_col[f * k_top + t];
-    for (int64_t g = cg_ptr[c]; g < cg_ptr[c + 1]; ++g) {
-      const int4 gr = groups[g];
-      const float* row = G + grp_off[g] + col * kGR;
-      uint16_t* pb = P + grp_off[g] + (col >> 5) * (kGR * kFB) + (col & 31);
-      for (int r = 0; r < gr.z; ++r) {
-        const int j = cell_rot[gr.y + r];
-        const double a = ((double)row[r] + bk) + (log_w[j] - S[j]);
-        const uint16_t p = __builtin_bit_cast(uint16_t, __float2bfloat16((float)exp(a - lse)));
-        pb[r * kFB] = p;
-        if (Pd) Pd[(int64_t)j * ldd + f] = p;
-      }
-    }
+  if (lane == 0) L[f] = mx + log(sum);
+}
+
+// Responsibilities of the candidate pairs, group-major over the log-likelihood's
+// tiles (group g, list positions f0 .. f0 + 255; wave w, lane s: position
+// f0 + 64 w + s): P = exp(a - L_f) in BF16 (eq. 2.4) into the group's blocked P,
+// where 32 consecutive lanes fill one 64-byte row of a [32 rot][32 frames] block,
+// and, with Pd, into the dense [rotation][frame] matrix of the M-step's dense
+// bands (a list's frames come in runs of consecutive numbers).
+__global__ __launch_bounds__(256) void cand_pwrite_kernel(
+    const int2* __restrict__ tiles, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
+    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const float* __restrict__ G,
+    const int32_t* __restrict__ cell_rot, const double* __restrict__ log_w, const double* __restrict__ S,
+    const double* __restrict__ b, const double* __restrict__ L, uint16_t* __restrict__ P,
+    uint16_t* __restrict__ Pd, int64_t ldd) {
+  const int2 tl = tiles[blockIdx.x];
+  if (tl.x < 0) return;  // padding tile (uniform)
+  const int4 gr = groups[tl.x];
+  const int64_t F = cf_ptr[gr.x + 1] - cf_ptr[gr.x];
+  const int64_t col = tl.y + (threadIdx.x >> 6) * 64 + (threadIdx.x & 63);
+  if (col >= F) return;
+  const int32_t f = cf_frame[cf_ptr[gr.x] + col];
+  const double bk = b[f], lse = L[f];
+  const float* row = G + grp_off[tl.x] + col * kGR;
+  uint16_t* pb = P + grp_off[tl.x] + (col >> 5) * (kGR * kFB) + (col & 31);
+  for (int r = 0; r < gr.z; ++r) {
+    const int j = cell_rot[gr.y + r];
+    const double a = ((double)row[r] + bk) + (log_w[j] - S[j]);
+    const uint16_t p = __builtin_bit_cast(uint16_t, __float2bfloat16((float)exp(a - lse)));
+    pb[r * kFB] = p;
+    if (Pd) Pd[(int64_t)j * ldd + f] = p;
   }
 }
 
@@ -692,11 +703,14 @@ hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* gr
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
                              int64_t n_frames, const int32_t* cell_rot, const double* log_w, const double* S,
-                             const double* b, double* L, void* Pd, int64_t ldd, hipStream_t st) {
+                             const double* b, double* L, void* Pd, int64_t ldd, const int2* tiles, int64_t n_tiles,
+                             const int64_t* cf_ptr, const int32_t* cf_frame, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
-  cand_estep_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(G, (uint16_t*)P, groups, grp_off, cg_ptr, cells,
-                                                                    pair_col, k_top, n_frames, cell_rot, log_w, S, b,
-                                                                    L, (uint16_t*)Pd, ldd);
+  cand_estep_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(G, groups, grp_off, cg_ptr, cells, pair_col, k_top,
+                                                                    n_frames, cell_rot, log_w, S, b, L);
+  if (n_tiles > 0)
+    cand_pwrite_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, G, cell_rot, log_w,
+                                                          S, b, L, (uint16_t*)P, (uint16_t*)Pd, ldd);
   return hipGetLastError();
 }
 
