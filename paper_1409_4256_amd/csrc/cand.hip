@@ -416,7 +416,15 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
       acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, b0), acc[i][0], 0, 0, 0);
       if (two) acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, b1), acc[i][1], 0, 0, 0);
     }
-    for (int e = lane; e < kPair * kKRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = zero;
+    // clear the rows: when every lane's band fit its register window, only the words
+    // written (the wave's LDS operations run in order, so the reads above are done);
+    // otherwise all of them with contiguous 16-byte stores
+    if (__ballot(q0.y - q0.x > kWin) == 0) {
+#pragma unroll
+      for (int u = 0; u < kWin; ++u) put_chunk<true>(fcol_b, kKRow, w0[u]);
+    } else {
+      for (int e = lane; e < kPair * kKRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = zero;
+    }
     b0 = b0n;
     b1 = b1n;
     q0 = q1;
