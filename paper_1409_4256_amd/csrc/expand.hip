@@ -78,7 +78,14 @@ __global__ __launch_bounds__(256) void expand_kernel(const float* __restrict__ m
 // BF16 form: the centred log slice A_ji = log W_ij - c_i is written as two BF16
 // terms with a per-rotation scale, A_ji ~ scale_j (hi_ji + lo_ji), where
 // scale_j = max_i |A_ji|, hi = bf16(A / scale), lo = bf16(A / scale - hi).
-// A first pass finds the row maximum; the second recomputes the slice.
+// A first pass finds the row maximum; the second writes hi and lo.
+// STASH: detectors of at most kStashPx pixels keep the first pass's values
+// a_i = log W_ji - c_i (FP32) in LDS, so the interpolation and the FP64 log run
+// once per pixel; larger ones recompute them in the second pass.  Both give the
+// same bits.
+constexpr int kStashPx = 16384;  // 64 KB of LDS
+
+template <bool STASH>
 __global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restrict__ model, int N,
                                                           const float* __restrict__ q,
                                                           const uint8_t* __restrict__ mask,
@@ -89,6 +96,7 @@ __global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restric
                                                           double* __restrict__ S, float* __restrict__ scale) {
   __shared__ double red[4];
   __shared__ float redf[4];
+  __shared__ float stash[STASH ? kStashPx : 1];
   const int j = blockIdx.x;
   const Rot r = quat_rot(quat + 4 * (int64_t)j);
   double sum = 0.0;
@@ -97,13 +105,15 @@ __global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restric
     if (!mask[i]) continue;
     const double W = slice_value(model, N, r, q + 3 * i);
     sum += W;
-    amax = fmaxf(amax, fabsf((float)(log(W) - c[i])));
+    const float a = (float)(log(W) - c[i]);
+    if constexpr (STASH) stash[i] = a;
+    amax = fmaxf(amax, fabsf(a));
   }
   sum = block_sum4(sum, red);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
   if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = amax;
-  __syncthreads();
+  __syncthreads();  // also orders the stash writes before the reads below
   amax = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
   const float sc = amax > 0.0f ? amax : 1.0f;
   const float inv = 1.0f / sc;
@@ -116,8 +126,12 @@ __global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restric
   for (int64_t i = threadIdx.x; i < stride; i += 256) {
     float h = 0.0f, l = 0.0f;
     if (i < n_pix && mask[i]) {
-      const double W = slice_value(model, N, r, q + 3 * i);
-      const float a = (float)(log(W) - c[i]) * inv;
+      float v;
+      if constexpr (STASH)
+        v = stash[i];
+      else
+        v = (float)(log(slice_value(model, N, r, q + 3 * i)) - c[i]);
+      const float a = v * inv;
       const __hip_bfloat16 hb = __float2bfloat16(a);
       h = __bfloat162float(hb);
       l = a - h;
@@ -179,8 +193,14 @@ hipError_t launch_expand(const float* model, int N, const float* q, const uint8_
 hipError_t launch_expand_bf16(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
                               int n_pix, int64_t stride, int n_rot, const double* c, void* hilo, double* S,
                               float* scale, hipStream_t st) {
-  expand_bf16_kernel<<<(unsigned)n_rot, 256, 0, st>>>(model, N, q, mask, quat, n_pix, stride,
-                                                      (int64_t)n_rot * stride, c, (__hip_bfloat16*)hilo, S, scale);
+  if (n_pix <= kStashPx)
+    expand_bf16_kernel<true><<<(unsigned)n_rot, 256, 0, st>>>(model, N, q, mask, quat, n_pix, stride,
+                                                            (int64_t)n_rot * stride, c, (__hip_bfloat16*)hilo, S,
+                                                            scale);
+  else
+    expand_bf16_kernel<false><<<(unsigned)n_rot, 256, 0, st>>>(model, N, q, mask, quat, n_pix, stride,
+                                                             (int64_t)n_rot * stride, c, (__hip_bfloat16*)hilo, S,
+                                                             scale);
   return hipGetLastError();
 }
 
