@@ -171,10 +171,10 @@ emc_status run_loglik(const emc_problem* pb, const void* K, const void* slices, 
 }
 
 emc_status run_estep(const emc_problem* pb, const float* G, const double* S, const double* b, int32_t mode,
-                     double* stats, void* P, double* L, double* rho, hipStream_t st) {
+                     double* stats, void* P, double* L, double* rho, hipStream_t st, double* part = nullptr) {
   const Dims d = dims_of(pb);
   if (mode != EMC_RESP_FINALIZE)
-    HIP_TRY(launch_lse_stats(G, d.ds, pb->n_rot, pb->n_data, pb->log_w, S, b, stats, st), "lse_stats");
+    HIP_TRY(launch_lse_stats(G, d.ds, pb->n_rot, pb->n_data, pb->log_w, S, b, stats, part, st), "lse_stats");
   if (mode == EMC_RESP_PARTIAL) return EMC_OK;
   HIP_TRY(launch_lse_finish(stats, pb->n_data, L, st), "lse_finish");
   if (is_bf16(pb))
@@ -994,7 +994,8 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
 namespace {
 
 struct PropWs {
-  size_t slices, S, scale, c, b, L, G, P, Ga, Pa, stats_a, rho_a, recall, rho, num, den, Pd, Wd, copies, total;
+  size_t slices, S, scale, c, b, L, G, P, Ga, Pa, stats_a, stats_p, rho_a, recall, rho, num, den, Pd, Wd, copies,
+      total;
 };
 
 PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
@@ -1020,6 +1021,7 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
   W.Ga = take((int64_t)pb->n_rot * dsa * 4);
   W.Pa = take((int64_t)pb->n_rot * dsa * 2);
   W.stats_a = take((int64_t)P->n_audit * 16);
+  W.stats_p = take((int64_t)kMaxLseChunks * P->n_audit * 16);  // rotation-chunk partials of the audit's E-step
   W.rho_a = take((int64_t)pb->n_rot * 8);
   W.recall = take((int64_t)P->n_audit * 8);
   W.rho = take((int64_t)pb->n_rot * 8);
@@ -1126,7 +1128,8 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   pa.n_data = (int32_t)na;
   if (na > 0) {
     CHECK(run_loglik(&pa, K_audit, slices, scale, c, Ga, b + nc, st));
-    CHECK(run_estep(&pa, Ga, S, b + nc, EMC_RESP_FULL, stats_a, Pa, L + nc, rho_a, st));
+    CHECK(run_estep(&pa, Ga, S, b + nc, EMC_RESP_FULL, stats_a, Pa, L + nc, rho_a, st,
+                    (double*)(w + W.stats_p)));
     HIP_TRY(launch_audit_recall(Pa, dsa, pb->n_rot, na, plan->mask_audit, plan->words, plan->cell_of, recall, st),
             "audit recall");
   }

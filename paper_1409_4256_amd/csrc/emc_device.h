@@ -98,8 +98,11 @@ hipError_t launch_gemm_bf16_dual_nt(const void* A_hi, const void* A_lo, const vo
                                     hipStream_t st);
 hipError_t launch_gemm_bf16_nt(const void* A, const void* B, float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda,
                                int64_t ldb, int64_t ldc, hipStream_t st);
+// part: NULL, or kMaxLseChunks * 2 * n_data doubles of scratch that lets few frames
+// split the rotations over more workgroups
+constexpr int kMaxLseChunks = 64;
 hipError_t launch_lse_stats(const float* G, int64_t ld, int n_rot, int64_t n_data, const double* log_w,
-                            const double* S, const double* b, double* stats, hipStream_t st);
+                            const double* S, const double* b, double* stats, double* part, hipStream_t st);
 hipError_t launch_lse_finish(const double* stats, int64_t n_data, double* L, hipStream_t st);
 hipError_t launch_lse_write_f32(const float* G, int64_t ldg, float* P, int64_t ldp, int n_rot, int64_t n_data,
                                 const double* log_w, const double* S, const double* b, const double* L,

@@ -18,31 +18,35 @@ __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, doubl
 
 constexpr int kStatFrames = 64;  // frames per workgroup: one per lane, 4 waves split the rotations
 
-// Per-frame (max, sum exp) of a_jk over all rotations, FP64, online.
+// Per-frame (max, sum exp) of a_jk over rotations [j_begin, j_end), FP64, online;
+// blockIdx.y picks the rotation chunk when the rotations are split (out: the
+// chunk's partials at out + 2 * n_data * blockIdx.y).
 __global__ __launch_bounds__(256) void lse_stats_kernel(const float* __restrict__ G, int64_t ld, int n_rot,
                                                         int64_t n_data, const double* __restrict__ log_w,
                                                         const double* __restrict__ S,
-                                                        const double* __restrict__ b,
-                                                        double* __restrict__ stats) {
+                                                        const double* __restrict__ b, int per_chunk,
+                                                        double* __restrict__ out) {
   __shared__ double sm[4][kStatFrames], ss[4][kStatFrames];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t k = (int64_t)blockIdx.x * kStatFrames + lane;
   const bool live = k < n_data;
+  const int jb = blockIdx.y * per_chunk;
+  const int je = jb + per_chunk < n_rot ? jb + per_chunk : n_rot;
   const double bk = live ? b[k] : 0.0;
   double m = -INFINITY, s = 0.0;
   if (live) {
     // four rotations per step so that four loads are in flight
-    for (int j0 = wave; j0 < n_rot; j0 += 16) {
+    for (int j0 = jb + wave; j0 < je; j0 += 16) {
       float g[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + 4 * u;
-        g[u] = j < n_rot ? G[(int64_t)j * ld + k] : 0.0f;
+        g[u] = j < je ? G[(int64_t)j * ld + k] : 0.0f;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + 4 * u;
-        if (j >= n_rot) break;
+        if (j >= je) break;
         const double a = ((double)g[u] + bk) + (log_w[j] - S[j]);
         if (!(a > -INFINITY)) continue;  // zero prior weight: no contribution
         if (a > m) {
@@ -59,9 +63,21 @@ __global__ __launch_bounds__(256) void lse_stats_kernel(const float* __restrict_
   __syncthreads();
   if (wave == 0 && live) {
     for (int w = 1; w < 4; ++w) lse_merge(m, s, sm[w][lane], ss[w][lane]);
-    stats[2 * k] = m;
-    stats[2 * k + 1] = s;
+    double* o = out + 2 * n_data * blockIdx.y;
+    o[2 * k] = m;
+    o[2 * k + 1] = s;
   }
+}
+
+// stats_k = the chunks' partials of frame k merged in chunk order (deterministic)
+__global__ void lse_chunks_kernel(const double* __restrict__ part, int n_chunks, int64_t n_data,
+                                  double* __restrict__ stats) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= n_data) return;
+  double m = part[2 * k], s = part[2 * k + 1];
+  for (int c = 1; c < n_chunks; ++c) lse_merge(m, s, part[2 * n_data * c + 2 * k], part[2 * n_data * c + 2 * k + 1]);
+  stats[2 * k] = m;
+  stats[2 * k + 1] = s;
 }
 
 // L_k = m_k + log s_k.
@@ -130,11 +146,24 @@ __global__ __launch_bounds__(256) void lse_write_kernel(const float* G, int64_t 
   }
 }
 
+int lse_chunks(int n_rot, int64_t n_data) {
+  // few frames: split the rotations so that the grid has ~2048 workgroups, each
+  // chunk at least 256 rotations
+  const int64_t fblocks = (n_data + kStatFrames - 1) / kStatFrames;
+  int64_t c = (2048 + fblocks - 1) / fblocks;
+  c = c < n_rot / 256 ? c : n_rot / 256;
+  c = c < kMaxLseChunks ? c : kMaxLseChunks;
+  return c > 1 ? (int)c : 1;
+}
+
 hipError_t launch_lse_stats(const float* G, int64_t ld, int n_rot, int64_t n_data, const double* log_w,
-                            const double* S, const double* b, double* stats, hipStream_t st) {
+                            const double* S, const double* b, double* stats, double* part, hipStream_t st) {
   if (n_data == 0) return hipSuccess;
-  lse_stats_kernel<<<(unsigned)((n_data + kStatFrames - 1) / kStatFrames), 256, 0, st>>>(G, ld, n_rot, n_data,
-                                                                                        log_w, S, b, stats);
+  const int nc = part ? lse_chunks(n_rot, n_data) : 1;
+  const int per = (n_rot + nc - 1) / nc;
+  const dim3 grid((unsigned)((n_data + kStatFrames - 1) / kStatFrames), (unsigned)nc);
+  lse_stats_kernel<<<grid, 256, 0, st>>>(G, ld, n_rot, n_data, log_w, S, b, per, nc > 1 ? part : stats);
+  if (nc > 1) lse_chunks_kernel<<<(unsigned)((n_data + 255) / 256), 256, 0, st>>>(part, nc, n_data, stats);
   return hipGetLastError();
 }
 
