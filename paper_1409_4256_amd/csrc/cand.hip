@@ -167,10 +167,16 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? load_chunk<false>(fb + r1c.x + u) : pad;
     int2 r2c = {0, 0};
     if (has && band + 2 < nbands) r2c = rng[(band + 2) * n_list];
+    // window chunks past the first only when some lane of the wave has them (most
+    // bands hold at most 8 photon pixels per frame)
+    const bool more = __ballot(r0c.y - r0c.x > 1) != 0;
     if (has) {
+      put_chunk<false>(frow, 1, w0[0]);
+      if (more) {
 #pragma unroll
-      for (int u = 0; u < kWin; ++u) put_chunk<false>(frow, 1, w0[u]);
-      put_rest<false, false>(frow, 1, fb, r0c.x + kWin, r0c.y, 1);
+        for (int u = 1; u < kWin; ++u) put_chunk<false>(frow, 1, w0[u]);
+        put_rest<false, false>(frow, 1, fb, r0c.x + kWin, r0c.y, 1);
+      }
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -190,8 +196,11 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     // in order, so the MFMA operand reads above are done)
     if (has) {
       if (r0c.y - r0c.x <= kWin) {
+        put_chunk<true>(frow, 1, w0[0]);
+        if (more) {
 #pragma unroll
-        for (int u = 0; u < kWin; ++u) put_chunk<true>(frow, 1, w0[u]);
+          for (int u = 1; u < kWin; ++u) put_chunk<true>(frow, 1, w0[u]);
+        }
       } else {
 #pragma unroll
         for (int e = 0; e < kLRow / 8; ++e) reinterpret_cast<u4*>(frow)[e] = zero;
