@@ -265,6 +265,34 @@ emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void*
                        size_t ws_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Gaussian noise model with photon fluence (Section 2.2, the paper's own
+ * likelihood), FP32 form:
+ *   Q_jk = -sum_{i valid} (K_ik / phi_jk - W_ij)^2 / (2 sigma^2)     eq. (2.2)-(2.3)
+ *   P_jk = w_j e^{Q_jk} / sum_j' w_j' e^{Q_j'k}                       eq. (2.4)
+ *   W'_ji = sum_k P_jk K_ik / phi_jk,  rho_j = sum_k P_jk              eq. (2.11)
+ *   num/den and the division as in the Poisson form                   eq. (2.12)
+ *   phi'_jk = sum_i K_ik^2 / sum_i W_ij K_ik  (1 when that sum is 0)  eq. (2.6)
+ * One iteration uses the fluence phi^(n) in its E-step and M-step and returns
+ * phi^(n+1), the update evaluated on its own slices W^(n).
+ *   sigma          noise parameter, > 0 and finite
+ *   phi            [n_rot][ds] float, in/out: phi^(n) in (unless
+ *                  phi_from_model != 0), phi^(n+1) out; padding frames get 1
+ *   phi_from_model nonzero: phi^(n) is the update of this iteration's own
+ *                  slices (the first iteration has no previous fluence)
+ *   K_packed       emc_pack_frames output of an FP32 problem
+ *   loglik         device double: mean over frames of log sum_j w_j e^{Q_jk}
+ *   P_out          optional [n_rot][ds] float responsibilities
+ *   ws             emc_gaussian_workspace_bytes bytes, 256-byte aligned
+ * EMC_ERR_UNSUPPORTED for the BF16 form.  The c-step is brick-major when
+ * pb->scatter is set.
+ * ------------------------------------------------------------------------ */
+emc_status emc_gaussian_workspace_bytes(const emc_problem* pb, size_t* bytes);
+emc_status emc_iterate_gaussian(const emc_problem* pb, double sigma, const float* model_in,
+                                const void* K_packed, float* phi, int32_t phi_from_model,
+                                float* model_out, double* loglik, float* P_out, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Learned orientation proposal.  A small CNN scores the cells of a coarse
  * rotation grid from a frame; its top-K cells restrict the E-step's search
  * (the full search stays the fallback and the judge of recall).  This is an

@@ -526,6 +526,106 @@ emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void*
   return EMC_OK;
 }
 
+// ---- Gaussian noise model with fluence ----
+namespace {
+
+struct GaussLayout {
+  size_t A, G, P, s2, c, b, k2, stats, L, rho, num, den, copies, total;
+};
+
+GaussLayout gauss_layout(const emc_problem* pb) {
+  const Dims d = dims_of(pb);
+  GaussLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += (size_t)round_up((int64_t)bytes, 256);
+    return at;
+  };
+  L.A = take((size_t)pb->n_rot * d.ps * sizeof(float));  // A = W - c, then W'
+  L.G = take((size_t)pb->n_rot * d.ds * sizeof(float));  // G, then P / phi
+  L.P = take((size_t)pb->n_rot * d.ds * sizeof(float));  // used when P_out is NULL
+  L.s2 = take((size_t)pb->n_rot * sizeof(double));
+  L.c = take((size_t)d.ps * sizeof(double));
+  L.b = take((size_t)pb->n_data * sizeof(double));
+  L.k2 = take((size_t)pb->n_data * sizeof(double));
+  L.stats = take((size_t)pb->n_data * 2 * sizeof(double));
+  L.L = take((size_t)pb->n_data * sizeof(double));
+  L.rho = take((size_t)pb->n_rot * sizeof(double));
+  L.num = take((size_t)d.grid * sizeof(double));
+  L.den = take((size_t)d.grid * sizeof(double));
+  L.copies = take(copies_bytes(pb));
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+emc_status emc_gaussian_workspace_bytes(const emc_problem* pb, size_t* bytes) {
+  CHECK(check_problem(pb, false));
+  if (!bytes) return fail(EMC_ERR_INVALID_ARG, "bytes is NULL");
+  *bytes = gauss_layout(pb).total;
+  return EMC_OK;
+}
+
+emc_status emc_iterate_gaussian(const emc_problem* pb, double sigma, const float* model_in, const void* K_packed,
+                                float* phi, int32_t phi_from_model, float* model_out, double* loglik, float* P_out,
+                                void* ws, size_t ws_bytes, hipStream_t st) {
+  CHECK(check_problem(pb, true));
+  if (pb->precision != EMC_PREC_FP32)
+    return fail(EMC_ERR_UNSUPPORTED, "the Gaussian model runs in the FP32 form only");
+  if (!(sigma > 0.0) || !(sigma < INFINITY)) return fail(EMC_ERR_INVALID_ARG, "sigma must be positive and finite");
+  CHECK(need(model_in, 4, "model_in"));
+  CHECK(need(model_out, 4, "model_out"));
+  CHECK(need(loglik, 8, "loglik"));
+  if (pb->n_data > 0) {
+    CHECK(need(K_packed, 16, "K_packed"));
+    CHECK(need(phi, 4, "phi"));
+  }
+  if (P_out) CHECK(need(P_out, 16, "P_out"));
+  const GaussLayout Lo = gauss_layout(pb);
+  if (!ws) return fail(EMC_ERR_WORKSPACE, "workspace is NULL");
+  if (!aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+  if (ws_bytes < Lo.total) return fail(EMC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, Lo.total);
+  const Dims d = dims_of(pb);
+  char* w = (char*)ws;
+  float* A = (float*)(w + Lo.A);
+  float* G = (float*)(w + Lo.G);
+  float* P = P_out ? P_out : (float*)(w + Lo.P);
+  double* s2 = (double*)(w + Lo.s2);
+  double* c = (double*)(w + Lo.c);
+  double* b = (double*)(w + Lo.b);
+  double* k2 = (double*)(w + Lo.k2);
+  double* stats = (double*)(w + Lo.stats);
+  double* L = (double*)(w + Lo.L);
+  double* rho = (double*)(w + Lo.rho);
+  double* num = (double*)(w + Lo.num);
+  double* den = (double*)(w + Lo.den);
+  HIP_TRY(launch_fill_zero_f64(num, (size_t)d.grid, st), "zero num");
+  HIP_TRY(launch_fill_zero_f64(den, (size_t)d.grid, st), "zero den");
+  if (pb->n_data > 0) {
+    // expansion (eq. (2.9)), centred slices and the per-rotation sum of squares
+    HIP_TRY(launch_gauss_expand(model_in, pb->grid_n, pb->q, pb->mask, pb->quat, pb->n_pix, d.ps, pb->n_rot, c, A, s2,
+                                st),
+            "gaussian expand");
+    const float* K = (const float*)K_packed;
+    const float* KT = K + (size_t)pb->n_data * d.ps;
+    HIP_TRY(launch_frame_dot(K, false, d.ps, pb->n_data, c, b, st), "frame_dot");
+    HIP_TRY(launch_frame_sq(K, d.ps, pb->n_data, k2, st), "frame_sq");
+    // G_jk = sum_i (W_ij - c_i) K_ik (FP32 MFMA); b_k is added in the E-step
+    HIP_TRY(launch_gemm_f32_nt(A, K, G, pb->n_rot, pb->n_data, d.ps, d.ps, d.ps, d.ds, st), "gaussian gemm");
+    // E-step (eq. (2.4) with eq. (2.3)), M-step operand P / phi, fluence update (eq. (2.6)), rho
+    HIP_TRY(launch_gauss_estep(G, phi, P, d.ds, pb->n_rot, pb->n_data, pb->log_w, s2, b, k2, phi_from_model != 0,
+                               sigma, stats, L, rho, st),
+            "gaussian estep");
+    // M-step numerator (eq. (2.11)): W'_ji = sum_k (P_jk / phi_jk) K_ik, then the c-step (eq. (2.12))
+    HIP_TRY(launch_gemm_f32_nt(G, KT, A, pb->n_rot, d.ps, d.ds, d.ds, d.ds, d.ps, st), "gaussian mstep gemm");
+    CHECK(run_scatter(pb, A, d.ps, rho, num, den, (double*)(w + Lo.copies), st));
+  }
+  CHECK(run_finalize(pb, num, den, model_in, model_out, L, pb->n_data, loglik, st));
+  return EMC_OK;
+}
+
 }  // extern "C"
 
 // =========================================================================== proposal network

@@ -113,6 +113,14 @@ hipError_t launch_lse_write_bf16(const float* G, int64_t ldg, void* P, int64_t l
 hipError_t launch_scatter(const float* Wp, int64_t stride, const double* rho, const float* q,
                           const uint8_t* mask, const float* quat, int n_pix, int n_rot, int N, double* num,
                           double* den, double* copies, hipStream_t st);
+// ---- Gaussian noise model with fluence (gauss.hip) ----
+hipError_t launch_gauss_expand(const float* model, int N, const float* q, const uint8_t* mask, const float* quat,
+                               int n_pix, int64_t stride, int n_rot, double* c, float* A, double* s2, hipStream_t st);
+hipError_t launch_frame_sq(const float* K, int64_t stride, int64_t n_data, double* k2, hipStream_t st);
+hipError_t launch_gauss_estep(float* Gd, float* phi, float* P, int64_t ld, int n_rot, int64_t n_data,
+                              const double* log_w, const double* s2, const double* b, const double* k2, int own,
+                              double sigma, double* stats, double* L, double* rho, hipStream_t st);
+
 int brick_edge();
 hipError_t launch_brick_rot(const float* quat, int n_rot, double* rot, hipStream_t st);
 hipError_t launch_brick_visits(const float* q, const uint8_t* mask, const double* rot, int n_pix, int n_rot,

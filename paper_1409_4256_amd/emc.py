@@ -34,7 +34,8 @@ EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride",
            "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_topk", "emc_topk_union",
            "emc_cell_targets",
            "emc_pack_frames_list", "emc_proposal_bytes", "emc_proposal_build", "emc_proposed_workspace_bytes",
-           "emc_iterate_proposed", "emc_scatter_plan_min_bytes", "emc_scatter_plan_build")
+           "emc_iterate_proposed", "emc_scatter_plan_min_bytes", "emc_scatter_plan_build",
+           "emc_gaussian_workspace_bytes", "emc_iterate_gaussian")
 
 
 class EmcError(RuntimeError):
@@ -144,6 +145,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_iterate_proposed.argtypes = [_PB, _PP, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]
     lib.emc_iterate_proposed.restype = st
     lib.emc_scatter_plan_min_bytes.argtypes, lib.emc_scatter_plan_min_bytes.restype = [_PB, szp], st
+    lib.emc_gaussian_workspace_bytes.argtypes, lib.emc_gaussian_workspace_bytes.restype = [_PB, szp], st
+    lib.emc_iterate_gaussian.argtypes = [_PB, ctypes.c_double, _P, _P, _P, i32, _P, _P, _P, _P, ctypes.c_size_t, _P]
+    lib.emc_iterate_gaussian.restype = st
     lib.emc_scatter_plan_build.argtypes = [_PB, i32, _P, ctypes.c_size_t, ctypes.POINTER(ScatterPlan), _P]
     lib.emc_scatter_plan_build.restype = st
     _lib = lib
@@ -518,6 +522,32 @@ def emc_proposal_build(geo: Geometry, coarse, n_cells, topk, k_top, audit, count
         _ptr(buf, torch.uint8, emc_proposal_bytes(geo, n_cells, k_top, n_audit, nz_cap), "buf"),
         ctypes.c_size_t(buf.numel()), ctypes.byref(plan), _stream(stream)))
     return plan
+
+
+def emc_gaussian_workspace_bytes(geo: Geometry) -> int:
+    n = ctypes.c_size_t(0)
+    _check(load().emc_gaussian_workspace_bytes(ctypes.byref(geo.pb), ctypes.byref(n)))
+    return int(n.value)
+
+
+def emc_iterate_gaussian(geo: Geometry, sigma, model_in, K_packed, phi, phi_from_model, model_out, loglik,
+                         P_out=None, ws=None, stream=None):
+    """One iteration under the Gaussian model with fluence (FP32 form).  phi: float
+    [n_rot * data_stride], read as phi^(n) unless phi_from_model, overwritten with
+    phi^(n+1)."""
+    import torch
+
+    n = geo.n_data
+    M = geo.grid_n ** 3
+    nrd = geo.n_rot * geo.data_stride
+    _check(load().emc_iterate_gaussian(
+        ctypes.byref(geo.pb), ctypes.c_double(float(sigma)), _ptr(model_in, torch.float32, M, "model_in"),
+        _ptr(K_packed, None, None, "K_packed", nbytes=emc_frames_bytes(geo)) if n else None,
+        _ptr(phi, torch.float32, nrd, "phi") if n else None, int(bool(phi_from_model)),
+        _ptr(model_out, torch.float32, M, "model_out"), _ptr(loglik, torch.float64, 1, "loglik"),
+        _ptr(P_out, torch.float32, nrd, "P_out", allow_none=True),
+        _ptr(ws, torch.uint8, emc_gaussian_workspace_bytes(geo), "ws"), ctypes.c_size_t(ws.numel()),
+        _stream(stream)))
 
 
 def emc_scatter_plan_min_bytes(geo: Geometry) -> int:

@@ -223,3 +223,26 @@ def test_scatter_plan_argument_checks(lib):
         st = lib.emc_compress(ctypes.byref(pbb), a, a, a, a, a, a, 0, None, 0, None)
         assert st == emc.EMC_ERR_INVALID_ARG
         assert b"scatter plan" in lib.emc_last_error()
+
+
+def test_gaussian_argument_checks(lib):
+    """Gaussian-model iteration: sizes, sigma, form and workspace are checked before any launch."""
+    pb = _pb(grid_n=128, n_pix=16384, n_rot=25000, n_data=100000)
+    n = ctypes.c_size_t()
+    assert lib.emc_gaussian_workspace_bytes(ctypes.byref(pb), ctypes.byref(n)) == emc.EMC_OK
+    slices, g = 25000 * 16384 * 4, 25000 * 100096 * 4
+    assert slices + 2 * g < n.value < slices + 2 * g + 16 * 128 ** 3 * 8 + 64 * 2 ** 20
+    a = ctypes.c_void_p(1 << 20)
+    small = _pb()
+    lib.emc_gaussian_workspace_bytes(ctypes.byref(small), ctypes.byref(n))
+    for sigma in (0.0, -1.0, float("inf"), float("nan")):
+        st = lib.emc_iterate_gaussian(ctypes.byref(small), sigma, a, a, a, 1, a, a, None, a, n, None)
+        assert st == emc.EMC_ERR_INVALID_ARG
+        assert b"sigma" in lib.emc_last_error()
+    st = lib.emc_iterate_gaussian(ctypes.byref(_pb(precision=1)), 1.0, a, a, a, 1, a, a, None, a, n, None)
+    assert st == emc.EMC_ERR_UNSUPPORTED
+    st = lib.emc_iterate_gaussian(ctypes.byref(small), 1.0, a, a, a, 1, a, a, None, a,
+                                  ctypes.c_size_t(n.value - 1), None)
+    assert st == emc.EMC_ERR_WORKSPACE
+    st = lib.emc_iterate_gaussian(ctypes.byref(small), 1.0, a, a, None, 1, a, a, None, a, n, None)
+    assert st == emc.EMC_ERR_INVALID_ARG and b"phi" in lib.emc_last_error()
