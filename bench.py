@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-once", action="store_true")
     ap.add_argument("--no-proposal", action="store_true")
+    ap.add_argument("--no-gaussian", action="store_true", help="skip the Gaussian-model form")
     ap.add_argument("--train-at", type=int, default=10,
                     help="full iterations before the proposal (targets from the last three)")
     return ap.parse_args()
@@ -211,6 +212,55 @@ def time_form(run, args, n_valid):
                      "algorithmic_flops_per_launch": terms * contraction},
         "iteration_tflops_algorithmic": round((terms + 1) * contraction / (ms / 1e3) / 1e12, 2),
         "paper_flop_model_tflops": round(27.0 * wl.n_rot * wl.n_data * wl.n_pix / (ms / 1e3) / 1e12, 2),
+    }
+
+
+def gaussian_form(run, args, n_valid, sigma=2.0):
+    """The Gaussian noise model with fluence (FP32 form) on the plain form's geometry and
+    packed frames: the first call takes the fluence from its own slices, every later one
+    the fluence the previous iteration returned."""
+    import numpy as np
+    import torch
+
+    emc, g, wl = run.emc, run.geo, run.wl
+    dev = "cuda"
+    ws = torch.empty(emc.emc_gaussian_workspace_bytes(g), dtype=torch.uint8, device=dev)
+    phi = torch.empty(wl.n_rot * g.data_stride, dtype=torch.float32, device=dev)
+    models = [run.model[0].clone(), torch.empty_like(run.model[0])]
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    cur = [0]
+
+    def step(first):
+        emc.emc_iterate_gaussian(g, sigma, models[cur[0]], run.K, phi, first, models[1 - cur[0]], ll, ws=ws)
+        cur[0] = 1 - cur[0]
+
+    for i in range(max(1, args.warmup)):
+        step(i == 0)
+        torch.cuda.synchronize()
+        log(f"gaussian-fp32 warmup {i + 1} done")
+    K = args.steps
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    evs[0].record()
+    for i in range(K):
+        step(False)
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(K)]
+    ms = evs[0].elapsed_time(evs[K]) / K
+    log(f"gaussian-fp32: {ms:.1f} ms/iteration, loglik {ll.item():.4f}")
+    contraction = 2.0 * wl.n_data * wl.n_rot * n_valid
+    achieved = 2 * contraction / (ms / 1e3) / 1e12
+    return {
+        "value": round(1000.0 / ms, 5),
+        "ms_per_step": round(ms, 3),
+        "iteration_ms_min": round(float(np.min(per)), 3),
+        "sigma": sigma,
+        "loglik": ll.item(),
+        "roofline": {"bound": "mfma", "kernel": "gemm_f32_kernel (likelihood and M-step contractions), "
+                     "whole emc_iterate_gaussian iteration", "achieved": round(achieved, 2),
+                     "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+                     "algorithmic_flops_per_iteration": 2 * contraction},
     }
 
 
@@ -392,9 +442,12 @@ def main():
         run = Run(inp, prec, counts_dev)
         log(f"{form}: frames packed")
         results[form] = time_form(run, args, n_valid)
+        if form == "plain-fp32" and not args.no_gaussian:
+            torch.cuda.empty_cache()
+            results["gaussian-fp32"] = gaussian_form(run, args, n_valid)
         del run
         torch.cuda.empty_cache()
-    results = {k: results[k] for k in ("plain-fp32", "bf16", "bf16+proposal") if k in results}
+    results = {k: results[k] for k in ("plain-fp32", "gaussian-fp32", "bf16", "bf16+proposal") if k in results}
     chosen = "bf16"
     if "bf16+proposal" in results and results["bf16+proposal"]["fallbacks"] == 0 and \
             results["bf16+proposal"]["value"] > results["bf16"]["value"]:

@@ -46,7 +46,8 @@ def _check(g, o, tag):
     dP = np.max(np.abs(g["P"] - o["P"]))
     em = rel_l2(g["model"], o["model"])
     ephi = np.max(np.abs(g["phi"] - o["phi"]) / np.abs(o["phi"]))
-    print(f"\n[gaussian {tag}] P max-abs {dP:.2e}, model rel L2 {em:.2e}, phi max rel {ephi:.2e}, "
+    print(f"\n[gaussian {tag}] mean max_j P {o['P'].max(axis=0).mean():.3f}; "
+          f"P max-abs {dP:.2e}, model rel L2 {em:.2e}, phi max rel {ephi:.2e}, "
           f"loglik {g['loglik']:.6f} (oracle {o['loglik']:.6f})")
     assert dP <= P_TOL, (tag, dP)
     assert em <= REL_TOL, (tag, em)
@@ -59,6 +60,7 @@ def _check(g, o, tag):
     (0, 20, 300, 200, 300, 1.0, False),
     (1, 16, 257, 129, 517, 2.0, False),      # ragged pixel and frame counts
     (2, 24, 400, 300, 200, 1.5, True),       # brick-major c-step
+    (3, 20, 300, 200, 300, 8.0, False),      # broad posteriors (large sigma)
 ])
 def test_two_iterations_match_oracle(gpu_lib, seed, N, npx, nrot, ndata, sigma, brick):
     from gpu_helpers import geometry, pack, upload_counts
