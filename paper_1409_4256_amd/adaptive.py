@@ -32,7 +32,7 @@ class AdaptiveEMC:
         emc.emc_pack_frames(self.geo, counts_dev, self.K)
         self.loglik = torch.empty(1, dtype=torch.float64, device="cuda")
         self.L_prev = None
-        self.history = []   # (iteration, d, n_rot, mean log-evidence, ms)
+        self.history = []   # (iteration, d, n_rot, mean log-evidence, GPU ms, wall ms incl. any rebuild)
 
     def _build(self, d):
         import torch
@@ -48,18 +48,21 @@ class AdaptiveEMC:
         """One EMC iteration at the current d, then the refinement rule."""
         import torch
 
+        t0 = time.perf_counter()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         emc.emc_iterate(self.geo, model_in, self.K, model_out, self.loglik, ws=self.ws)
         e1.record()
         torch.cuda.synchronize()
         L = self.loglik.item()
-        self.history.append((len(self.history) + 1, self.d, self.geo.n_rot, L, e0.elapsed_time(e1)))
+        rec = [len(self.history) + 1, self.d, self.geo.n_rot, L, e0.elapsed_time(e1)]
         d_next = next_refinement(self.L_prev, L, self.d, self.d_max, self.tol)
         self.L_prev = L
         if d_next != self.d:
             self.d = d_next
             self._build(d_next)
+            torch.cuda.synchronize()
+        self.history.append(tuple(rec + [(time.perf_counter() - t0) * 1e3]))
         return L
 
     def run(self, model, n_iter):

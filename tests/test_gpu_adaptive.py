@@ -52,10 +52,10 @@ def test_driver_follows_the_refinement_rule(gpu_lib, small_inputs, tol, d_start,
     model = torch.as_tensor(inp.model_start, dtype=torch.float32, device="cuda")
     out = run.run(model, 8)
     h = run.history
-    print("\n[adaptive] " + "; ".join(f"it {i}: d {d} ({n} rot) L {L:.3f} {ms:.1f} ms" for i, d, n, L, ms in h))
+    print("\n[adaptive] " + "; ".join(f"it {i}: d {d} ({n} rot) L {L:.3f} {ms:.1f} ms" for i, d, n, L, ms, _ in h))
     assert len(h) == 8 and torch.isfinite(out).all().item()
     d, L_prev = d_start, None
-    for i, d_i, n_i, L_i, _ in h:
+    for i, d_i, n_i, L_i, _, _ in h:
         assert d_i == d and n_i == R.mrot(d)
         assert np.isfinite(L_i)
         d = R.next_refinement(L_prev, L_i, d, d_max, tol)
