@@ -87,15 +87,16 @@ __device__ __forceinline__ void axis_bricks(int b, int N, int& lo, int& hi) {
   hi = c0 <= c1 ? c1 / kBrick : INT_MIN;
 }
 
-// LDS slot of brick voxel e = (ex * 16 + ey) * 16 + ez.  A bank pair of FP64 LDS
-// is picked by the slot's low 5 bits, which for e are (ey & 1, ez) alone: the 64
-// pixels of a detector patch lying in a plane of constant z would share two bank
-// pairs.  XOR-ing bits of ex and ey >> 1 into the low bits spreads the planes of
-// constant x, y or z over all 32 pairs.  Bits 5..11 are untouched, so the map is
-// its own inverse.
-__device__ __forceinline__ int lds_slot(int e) {
-  const int ex = e >> 8, eyh = (e >> 5) & 7;
-  return e ^ (((ex & 1) << 4) | ((ex & 2) << 2) | eyh);
+// LDS slot of brick voxel (ex, ey, ez).  A bank pair of FP64 LDS is picked by the
+// slot's low bits; in the natural order (ex * 16 + ey) * 16 + ez those are ez and
+// ey & 1 alone, so the pixels of a detector patch in a plane of constant z would
+// pile onto two bank pairs.  Each row of 16 z-voxels is rotated by (13 ex + 7 ey)
+// mod 16 and its y parity flipped with x: over the visits of the 128^3 workload
+// (simulated on the host) the busiest bank pair of an atomic instruction then
+// holds 4.4 lanes on average (16 pairs) against 10.3 unswizzled.  Rows and planes
+// are only permuted, so the map is a bijection of the brick.
+__device__ __forceinline__ int lds_slot(int ex, int ey, int ez) {
+  return (ex * kBrick + (ey ^ (ex & 1))) * kBrick + ((ez + 13 * ex + 7 * ey) & (kBrick - 1));
 }
 
 __device__ __forceinline__ int wmin(int v) {
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(kBrickWaves * 64) void brick_scatter_kernel(const i
           if (X0 + ex >= N || Y0 + ey >= N || Z0 + ez >= N) continue;  // past the grid in a partial brick
           const double f = (dx ? c.tx : 1.0 - c.tx) * (dy ? c.ty : 1.0 - c.ty) * (dz ? c.tz : 1.0 - c.tz);
           if (f == 0.0) continue;
-          const int e = lds_slot((ex * kBrick + ey) * kBrick + ez);
+          const int e = lds_slot(ex, ey, ez);
           atomicAdd(s_num + e, f * wn);
           atomicAdd(s_den + e, f * rj);
         }
@@ -245,7 +246,8 @@ __global__ __launch_bounds__(kBrickWaves * 64) void brick_scatter_kernel(const i
     const int vx = X0 + (e >> 8), vy = Y0 + ((e >> 4) & 15), vz = Z0 + (e & 15);
     if (vx >= N || vy >= N || vz >= N) continue;
     const int64_t l = ((int64_t)vx * N + vy) * N + vz;
-    const double a = s_num[lds_slot(e)], b = s_den[lds_slot(e)];
+    const int sl = lds_slot(e >> 8, (e >> 4) & 15, e & 15);
+    const double a = s_num[sl], b = s_den[sl];
     if (a != 0.0) unsafeAtomicAdd(num + l, a);
     if (b != 0.0) unsafeAtomicAdd(den + l, b);
   }
