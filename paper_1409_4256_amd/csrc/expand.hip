@@ -84,24 +84,29 @@ __global__ __launch_bounds__(256) void expand_kernel(const float* __restrict__ m
 // once per pixel; larger ones recompute them in the second pass.  Both give the
 // same bits.
 constexpr int kStashPx = 16384;  // 64 KB of LDS
+// 8 waves per workgroup: the stash allows two workgroups per CU, and the
+// gathers need many waves in flight to cover their latency (two workgroups of 8
+// waves fit the registers: 4 waves per SIMD).
+constexpr int kExpThreads = 512;
+constexpr int kExpWaves = kExpThreads / 64;
 
 template <bool STASH>
-__global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restrict__ model, int N,
-                                                          const float* __restrict__ q,
-                                                          const uint8_t* __restrict__ mask,
-                                                          const float* __restrict__ quat, int n_pix,
-                                                          int64_t stride, int64_t plane,
-                                                          const double* __restrict__ c,
-                                                          __hip_bfloat16* __restrict__ hi_all,
-                                                          double* __restrict__ S, float* __restrict__ scale) {
-  __shared__ double red[4];
-  __shared__ float redf[4];
+__global__ __launch_bounds__(kExpThreads) void expand_bf16_kernel(const float* __restrict__ model, int N,
+                                                                  const float* __restrict__ q,
+                                                                  const uint8_t* __restrict__ mask,
+                                                                  const float* __restrict__ quat, int n_pix,
+                                                                  int64_t stride, int64_t plane,
+                                                                  const double* __restrict__ c,
+                                                                  __hip_bfloat16* __restrict__ hi_all,
+                                                                  double* __restrict__ S, float* __restrict__ scale) {
+  __shared__ double red[kExpWaves];
+  __shared__ float redf[kExpWaves];
   __shared__ float stash[STASH ? kStashPx : 1];
   const int j = blockIdx.x;
   const Rot r = quat_rot(quat + 4 * (int64_t)j);
   double sum = 0.0;
   float amax = 0.0f;
-  for (int64_t i = threadIdx.x; i < n_pix; i += 256) {
+  for (int64_t i = threadIdx.x; i < n_pix; i += kExpThreads) {
     if (!mask[i]) continue;
     const double W = slice_value(model, N, r, q + 3 * i);
     sum += W;
@@ -109,21 +114,28 @@ __global__ __launch_bounds__(256) void expand_bf16_kernel(const float* __restric
     if constexpr (STASH) stash[i] = a;
     amax = fmaxf(amax, fabsf(a));
   }
-  sum = block_sum4(sum, red);
+  sum = wave_sum(sum);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
-  if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = amax;
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = sum;
+    redf[threadIdx.x >> 6] = amax;
+  }
   __syncthreads();  // also orders the stash writes before the reads below
-  amax = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
+  amax = redf[0];
+#pragma unroll
+  for (int w = 1; w < kExpWaves; ++w) amax = fmaxf(amax, redf[w]);
   const float sc = amax > 0.0f ? amax : 1.0f;
   const float inv = 1.0f / sc;
   if (threadIdx.x == 0) {
-    S[j] = sum;
+    double t = 0.0;
+    for (int w = 0; w < kExpWaves; ++w) t += red[w];
+    S[j] = t;
     scale[j] = sc;
   }
   __hip_bfloat16* hi = hi_all + (int64_t)j * stride;
   __hip_bfloat16* lo = hi_all + plane + (int64_t)j * stride;
-  for (int64_t i = threadIdx.x; i < stride; i += 256) {
+  for (int64_t i = threadIdx.x; i < stride; i += kExpThreads) {
     float h = 0.0f, l = 0.0f;
     if (i < n_pix && mask[i]) {
       float v;
@@ -194,11 +206,11 @@ hipError_t launch_expand_bf16(const float* model, int N, const float* q, const u
                               int n_pix, int64_t stride, int n_rot, const double* c, void* hilo, double* S,
                               float* scale, hipStream_t st) {
   if (n_pix <= kStashPx)
-    expand_bf16_kernel<true><<<(unsigned)n_rot, 256, 0, st>>>(model, N, q, mask, quat, n_pix, stride,
+    expand_bf16_kernel<true><<<(unsigned)n_rot, kExpThreads, 0, st>>>(model, N, q, mask, quat, n_pix, stride,
                                                             (int64_t)n_rot * stride, c, (__hip_bfloat16*)hilo, S,
                                                             scale);
   else
-    expand_bf16_kernel<false><<<(unsigned)n_rot, 256, 0, st>>>(model, N, q, mask, quat, n_pix, stride,
+    expand_bf16_kernel<false><<<(unsigned)n_rot, kExpThreads, 0, st>>>(model, N, q, mask, quat, n_pix, stride,
                                                              (int64_t)n_rot * stride, c, (__hip_bfloat16*)hilo, S,
                                                              scale);
   return hipGetLastError();
