@@ -1098,6 +1098,14 @@ struct PropWs {
       total;
 };
 
+// k-range parts of the dense-band M-step product (its partial products are summed
+// by the dense add)
+constexpr int kMaxDenseSplits = 4;
+int dense_splits(const emc_problem* pb, const emc_proposal* P) {
+  if (P->n_dense <= 0) return 1;
+  return gemm_bf16_splits(pb->n_rot, (int64_t)P->n_dense * kBandPx, P->ld_dense, kMaxDenseSplits);
+}
+
 PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
   const int64_t ps = round_up(pb->n_pix, 256);
   const int64_t dsa = round_up(P->n_audit, 256);
@@ -1128,7 +1136,7 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
   W.num = take(grid * 8);
   W.den = take(grid * 8);
   W.Pd = take(P->n_dense > 0 ? (int64_t)pb->n_rot * P->ld_dense * 2 : 0);
-  W.Wd = take((int64_t)pb->n_rot * P->n_dense * kBandPx * 4);
+  W.Wd = take((int64_t)pb->n_rot * P->n_dense * kBandPx * 4 * dense_splits(pb, P));
   W.copies = take((int64_t)copies_bytes(pb));
   W.total = o;
   return W;
@@ -1248,10 +1256,11 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   CHECK(mark(5));
   if (Pd && nc > 0) {  // dense bands: W'[:, centre] += P_dense K_centre^T over all candidate frames
     const int64_t nd = (int64_t)plan->n_dense * kBandPx;
-    HIP_TRY(launch_gemm_bf16_nt(Pd, plan->kt_dense, Wd, pb->n_rot, nd, plan->ld_dense, plan->ld_dense,
-                                plan->ld_dense, nd, st),
+    const int splits = dense_splits(pb, plan);  // few output tiles, long reduction: split it
+    HIP_TRY(launch_gemm_bf16_nt_split(Pd, plan->kt_dense, Wd, pb->n_rot, nd, plan->ld_dense, plan->ld_dense,
+                                      plan->ld_dense, nd, splits, st),
             "dense mstep gemm");
-    HIP_TRY(launch_dense_add(Wd, pb->n_rot, plan->n_dense, plan->dense_list, ps, Wp, st), "dense add");
+    HIP_TRY(launch_dense_add(Wd, splits, pb->n_rot, plan->n_dense, plan->dense_list, ps, Wp, st), "dense add");
   }
   CHECK(mark(6));
   HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");

@@ -608,13 +608,15 @@ __global__ __launch_bounds__(256) void dense_pack_kernel(const uint16_t* __restr
 }
 
 // W'[j][128 dense_list[d] + p] += D[j][128 d + p]
-__global__ void dense_add_kernel(const float* __restrict__ D, int64_t n_rot, int n_dense,
+__global__ void dense_add_kernel(const float* __restrict__ D, int parts, int64_t n_rot, int n_dense,
                                  const int32_t* __restrict__ dense_list, int64_t ps, float* __restrict__ Wp) {
-  const int64_t cols = (int64_t)n_dense * kBand;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n_rot * cols; e += (int64_t)gridDim.x * 256) {
+  const int64_t cols = (int64_t)n_dense * kBand, slab = n_rot * cols;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < slab; e += (int64_t)gridDim.x * 256) {
     const int64_t j = e / cols;
     const int c = (int)(e - j * cols);
-    Wp[j * ps + (int64_t)dense_list[c >> 7] * kBand + (c & (kBand - 1))] += D[e];
+    float v = D[e];
+    for (int s = 1; s < parts; ++s) v += D[e + s * slab];
+    Wp[j * ps + (int64_t)dense_list[c >> 7] * kBand + (c & (kBand - 1))] += v;
   }
 }
 
@@ -792,12 +794,14 @@ hipError_t launch_dense_pack(const uint16_t* counts, const uint8_t* mask, int n_
   return hipGetLastError();
 }
 
-hipError_t launch_dense_add(const float* D, int64_t n_rot, int n_dense, const int32_t* dense_list, int64_t ps,
-                            float* Wp, hipStream_t st) {
+hipError_t launch_dense_add(const float* D, int parts, int64_t n_rot, int n_dense, const int32_t* dense_list,
+                            int64_t ps, float* Wp, hipStream_t st) {
   const int64_t n = n_rot * n_dense * kBand;
   if (n <= 0) return hipSuccess;
+  if (parts < 1) return hipErrorInvalidValue;
   const int64_t g = (n + 255) / 256;
-  dense_add_kernel<<<(unsigned)(g > 65536 ? 65536 : g), 256, 0, st>>>(D, n_rot, n_dense, dense_list, ps, Wp);
+  dense_add_kernel<<<(unsigned)(g > 65536 ? 65536 : g), 256, 0, st>>>(D, parts, n_rot, n_dense, dense_list, ps,
+                                                                      Wp);
   return hipGetLastError();
 }
 

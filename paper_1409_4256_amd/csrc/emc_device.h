@@ -98,6 +98,11 @@ hipError_t launch_gemm_bf16_dual_nt(const void* A_hi, const void* A_lo, const vo
                                     hipStream_t st);
 hipError_t launch_gemm_bf16_nt(const void* A, const void* B, float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda,
                                int64_t ldb, int64_t ldc, hipStream_t st);
+// The same product with its k range cut in `splits` parts: part s writes its
+// partial product to C + s * M * ldc.  `splits` must come from gemm_bf16_splits.
+int gemm_bf16_splits(int64_t M, int64_t N, int64_t Kd, int max_splits);
+hipError_t launch_gemm_bf16_nt_split(const void* A, const void* B, float* C, int64_t M, int64_t N, int64_t Kd,
+                                     int64_t lda, int64_t ldb, int64_t ldc, int splits, hipStream_t st);
 // part: NULL, or kMaxLseChunks * 2 * n_data doubles of scratch that lets few frames
 // split the rotations over more workgroups
 constexpr int kMaxLseChunks = 64;
@@ -190,8 +195,9 @@ hipError_t launch_dense_bands(const int32_t* cnt, int64_t n_frames, int nbands, 
 hipError_t launch_dense_pack(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
                              int64_t n_frames, int64_t ld, int n_dense, const int32_t* dense_list, void* KT,
                              hipStream_t st);
-hipError_t launch_dense_add(const float* D, int64_t n_rot, int n_dense, const int32_t* dense_list, int64_t ps,
-                            float* Wp, hipStream_t st);
+// Wp[j][dense pixels] += sum over the `parts` slabs of D (n_rot x n_dense*128 each), in slab order
+hipError_t launch_dense_add(const float* D, int parts, int64_t n_rot, int n_dense, const int32_t* dense_list,
+                            int64_t ps, float* Wp, hipStream_t st);
 hipError_t launch_fill_zero_bytes(void* p, int64_t bytes, hipStream_t st);
 hipError_t launch_band_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
                              int64_t n_frames, int nbands, int32_t* cnt, int32_t* over, hipStream_t st);

@@ -14,6 +14,11 @@
 // 4096 MFMA cycles, which hides their latency.  A lane feeds one MFMA with 8
 // consecutive k of one row (one 128-bit LDS read); A and B use the same k
 // assignment, so the product sums the same pairs.
+//
+// Split reduction: with `stages` < ceil(Kd / 64) the grid holds every output tile
+// once per k range of `stages` x 64; range s writes its partial product to the
+// slab C + s * c_split (the caller adds the slabs).  Products with few output
+// tiles (fewer than a few per CU) use it to fill the chip.
 #include "emc_device.h"
 
 namespace emc {
@@ -30,7 +35,7 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
                                                         const uint16_t* __restrict__ B,
                                                         const float* __restrict__ row_scale, float* __restrict__ C,
                                                         int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb,
-                                                        int64_t ldc) {
+                                                        int64_t ldc, int64_t stages, int64_t c_split) {
   constexpr int NA = DUAL ? 2 : 1;
   __shared__ __attribute__((aligned(16))) uint16_t As[NA][TM * LROW];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * LROW];
@@ -45,7 +50,9 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
   const int wm = wave / WN, wn = wave % WN;
 
   const int64_t tiles_m = (M + TM - 1) / TM, tiles_n = (N + TN - 1) / TN;
-  const int64_t pid = blockIdx.x;
+  const int64_t split = blockIdx.x / (tiles_m * tiles_n);
+  const int64_t pid = blockIdx.x - split * (tiles_m * tiles_n);
+  C += split * c_split;
   const int64_t group = (int64_t)GROUP * tiles_n;
   const int64_t first_m = (pid / group) * GROUP;
   const int64_t gm = (tiles_m - first_m) < GROUP ? (tiles_m - first_m) : GROUP;
@@ -90,14 +97,16 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
 #pragma unroll
     for (int j = 0; j < JT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // this workgroup's k stages [s0, s1); the host gives every split at least one
   const int64_t nk = (Kd + TK - 1) / TK;
-  EMC_LOAD_STAGE(0)
+  const int64_t s0 = split * stages, s1 = s0 + stages < nk ? s0 + stages : nk;
+  EMC_LOAD_STAGE(s0 * TK)
   EMC_STORE_STAGE()
   __syncthreads();
 
   const int arow_l = wm * WROWS + (lane & 15), brow_l = wn * WCOLS + (lane & 15), kofs = 8 * (lane >> 4);
-  for (int64_t s = 0; s < nk; ++s) {
-    if (s + 1 < nk) {
+  for (int64_t s = s0; s < s1; ++s) {
+    if (s + 1 < s1) {
       const int64_t k1 = (s + 1) * TK;
       EMC_LOAD_STAGE(k1)
     }
@@ -117,7 +126,7 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
       }
     }
     __syncthreads();
-    if (s + 1 < nk) {
+    if (s + 1 < s1) {
       EMC_STORE_STAGE()
       __syncthreads();
     }
@@ -151,12 +160,48 @@ static_assert(kWaves == 4 || kWaves == 8, "4 or 8 waves per workgroup");
 
 template <bool DUAL>
 static hipError_t launch(const void* A, const void* A2, const void* B, const float* scale, float* C, int64_t M,
-                         int64_t N, int64_t Kd, int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st) {
+                         int64_t N, int64_t Kd, int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st,
+                         int splits = 1) {
   if (M <= 0 || N <= 0) return hipSuccess;
   const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
-  gemm_bf16_kernel<DUAL, kWaves><<<(unsigned)tiles, 64 * kWaves, 0, st>>>(
-      (const uint16_t*)A, (const uint16_t*)A2, (const uint16_t*)B, scale, C, M, N, Kd, lda, ldb, ldc);
+  const int64_t nk = (Kd + TK - 1) / TK;
+  const int64_t stages = splits > 1 ? (nk + splits - 1) / splits : (nk > 0 ? nk : 1);
+  // every split must own at least one stage (gemm_bf16_splits returns such counts)
+  if (splits < 1 || (splits > 1 && (splits - 1) * stages >= nk)) return hipErrorInvalidValue;
+  gemm_bf16_kernel<DUAL, kWaves><<<(unsigned)(tiles * splits), 64 * kWaves, 0, st>>>(
+      (const uint16_t*)A, (const uint16_t*)A2, (const uint16_t*)B, scale, C, M, N, Kd, lda, ldb, ldc, stages,
+      M * ldc);
   return hipGetLastError();
+}
+
+// Split count for a product on a chip of kChipCUs CUs (one workgroup per CU):
+// the count of at most max_splits, each split at least kMinSplitStages stages,
+// that minimises (rounds of workgroups) x (stages per split), kept only when it
+// saves 5 % against the best smaller count.  Every split it returns owns at least
+// one stage.
+constexpr int64_t kChipCUs = 256;
+constexpr int64_t kMinSplitStages = 4;
+int gemm_bf16_splits(int64_t M, int64_t N, int64_t Kd, int max_splits) {
+  if (M <= 0 || N <= 0 || Kd <= 0) return 1;
+  const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN), nk = (Kd + TK - 1) / TK;
+  int best = 1;
+  double best_t = (double)((tiles + kChipCUs - 1) / kChipCUs);
+  for (int s = 2; s <= max_splits; ++s) {
+    const int64_t per = (nk + s - 1) / s;
+    if (per < kMinSplitStages) break;
+    const int64_t eff = (nk + per - 1) / per;
+    const double t = (double)((tiles * eff + kChipCUs - 1) / kChipCUs) * (double)per / (double)nk;
+    if (t < 0.95 * best_t) {
+      best = (int)eff;
+      best_t = t;
+    }
+  }
+  return best;
+}
+
+hipError_t launch_gemm_bf16_nt_split(const void* A, const void* B, float* C, int64_t M, int64_t N, int64_t Kd,
+                                     int64_t lda, int64_t ldb, int64_t ldc, int splits, hipStream_t st) {
+  return launch<false>(A, nullptr, B, nullptr, C, M, N, Kd, lda, ldb, ldc, st, splits);
 }
 
 hipError_t launch_gemm_bf16_dual_nt(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
