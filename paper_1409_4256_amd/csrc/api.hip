@@ -1095,7 +1095,7 @@ namespace {
 
 struct PropWs {
   size_t slices, S, scale, c, b, L, G, P, Ga, Pa, stats_a, stats_p, rho_a, recall, rho, num, den, Pd, Wd, copies,
-      total;
+      cst, total;
 };
 
 // k-range parts of the dense-band M-step product (its partial products are summed
@@ -1138,6 +1138,7 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
   W.Pd = take(P->n_dense > 0 ? (int64_t)pb->n_rot * P->ld_dense * 2 : 0);
   W.Wd = take((int64_t)pb->n_rot * P->n_dense * kBandPx * 4 * dense_splits(pb, P));
   W.copies = take((int64_t)copies_bytes(pb));
+  W.cst = take((int64_t)pb->n_rot * 8);  // log w_j - S_j in the cells' rotation order
   W.total = o;
   return W;
 }
@@ -1225,7 +1226,8 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
     // the dense bands' responsibility matrix is zero outside the candidate pairs
     if (Pd) HIP_TRY(launch_fill_zero_bytes(Pd, (int64_t)pb->n_rot * plan->ld_dense * 2, st), "zero dense P");
     HIP_TRY(launch_cand_estep(G, Pc, groups, plan->grp_off, plan->cg_ptr, plan->cand_cells, plan->pair_col,
-                              plan->k_top, nc, plan->cell_rot, pb->log_w, S, b, L, Pd, plan->ld_dense,
+                              plan->k_top, nc, plan->cell_rot, pb->n_rot, pb->log_w, S, (double*)(w + W.cst), b, L,
+                              Pd, plan->ld_dense,
                               (const int2*)plan->tiles, plan->n_tiles, plan->cf_ptr, plan->cf_frame, st),
             "candidate estep");
   }

@@ -246,6 +246,24 @@ __device__ __forceinline__ void lse_push(double& mx, double& s, double a) {
   }
 }
 
+// The rotation term of a, log w_j - S_j, in the cells' rotation order (entry t
+// belongs to rotation cell_rot[t]), so that a group's terms are contiguous.
+__global__ void cell_const_kernel(const int32_t* __restrict__ cell_rot, int64_t n_rot,
+                                  const double* __restrict__ log_w, const double* __restrict__ S,
+                                  double* __restrict__ cst) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_rot) return;
+  const int j = cell_rot[t];
+  cst[t] = log_w[j] - S[j];
+}
+
+// A frame's G row of a group (32 floats, 128-byte aligned), rotations < nr loaded
+__device__ __forceinline__ void load_grow(const float* __restrict__ row, int nr, f4 (&v)[kGR / 4]) {
+#pragma unroll
+  for (int q = 0; q < kGR / 4; ++q)
+    v[q] = 4 * q < nr ? *reinterpret_cast<const f4*>(row + 4 * q) : f4{0.f, 0.f, 0.f, 0.f};
+}
+
 // Log-evidence of each candidate frame: one wave per frame, lanes take the frame's
 // proposed cells (slot t = lane + 64 u); a = Q + log w_j = G + b_f - S_j + log w_j
 // and L_f = log sum over the frame's candidates of e^a, in FP64 (eq. 2.4's
@@ -253,8 +271,8 @@ __device__ __forceinline__ void lse_push(double& mx, double& s, double a) {
 __global__ __launch_bounds__(256) void cand_estep_kernel(
     const float* __restrict__ G, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
     const int64_t* __restrict__ cg_ptr, const int32_t* __restrict__ cells, const int32_t* __restrict__ pair_col,
-    int k_top, int64_t n_frames, const int32_t* __restrict__ cell_rot, const double* __restrict__ log_w,
-    const double* __restrict__ S, const double* __restrict__ b, double* __restrict__ L) {
+    int k_top, int64_t n_frames, const double* __restrict__ cst, const double* __restrict__ b,
+    double* __restrict__ L) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= n_frames) return;  // uniform per wave
@@ -266,11 +284,14 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
     const int64_t col = pair_col[f * k_top + t];
     for (int64_t g = cg_ptr[c]; g < cg_ptr[c + 1]; ++g) {
       const int4 gr = groups[g];
-      const float* row = G + grp_off[g] + col * kGR;
-      for (int r = 0; r < gr.z; ++r) {
-        const int j = cell_rot[gr.y + r];
-        lse_push(mx, sum, ((double)row[r] + bk) + (log_w[j] - S[j]));
-      }
+      f4 v[kGR / 4];
+      load_grow(G + grp_off[g] + col * kGR, gr.z, v);
+      const double* cr = cst + gr.y;
+#pragma unroll
+      for (int q = 0; q < kGR / 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (4 * q + u < gr.z) lse_push(mx, sum, ((double)v[q][u] + bk) + cr[4 * q + u]);
     }
   }
 #pragma unroll
@@ -295,9 +316,8 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
 __global__ __launch_bounds__(256) void cand_pwrite_kernel(
     const int2* __restrict__ tiles, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
     const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const float* __restrict__ G,
-    const int32_t* __restrict__ cell_rot, const double* __restrict__ log_w, const double* __restrict__ S,
-    const double* __restrict__ b, const double* __restrict__ L, uint16_t* __restrict__ P,
-    uint16_t* __restrict__ Pd, int64_t ldd) {
+    const int32_t* __restrict__ cell_rot, const double* __restrict__ cst, const double* __restrict__ b,
+    const double* __restrict__ L, uint16_t* __restrict__ P, uint16_t* __restrict__ Pd, int64_t ldd) {
   const int2 tl = tiles[blockIdx.x];
   if (tl.x < 0) return;  // padding tile (uniform)
   const int4 gr = groups[tl.x];
@@ -306,15 +326,21 @@ __global__ __launch_bounds__(256) void cand_pwrite_kernel(
   if (col >= F) return;
   const int32_t f = cf_frame[cf_ptr[gr.x] + col];
   const double bk = b[f], lse = L[f];
-  const float* row = G + grp_off[tl.x] + col * kGR;
+  f4 v[kGR / 4];
+  load_grow(G + grp_off[tl.x] + col * kGR, gr.z, v);
+  const double* cr = cst + gr.y;
   uint16_t* pb = P + grp_off[tl.x] + (col >> 5) * (kGR * kFB) + (col & 31);
-  for (int r = 0; r < gr.z; ++r) {
-    const int j = cell_rot[gr.y + r];
-    const double a = ((double)row[r] + bk) + (log_w[j] - S[j]);
-    const uint16_t p = __builtin_bit_cast(uint16_t, __float2bfloat16((float)exp(a - lse)));
-    pb[r * kFB] = p;
-    if (Pd) Pd[(int64_t)j * ldd + f] = p;
-  }
+#pragma unroll
+  for (int q = 0; q < kGR / 4; ++q)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = 4 * q + u;
+      if (r >= gr.z) break;  // uniform: one group per workgroup
+      const double a = ((double)v[q][u] + bk) + cr[r];
+      const uint16_t p = __builtin_bit_cast(uint16_t, __float2bfloat16((float)exp(a - lse)));
+      pb[r * kFB] = p;
+      if (Pd) Pd[(int64_t)cell_rot[gr.y + r] * ldd + f] = p;
+    }
 }
 
 // ------------------------------------------------------------------ M-step
@@ -721,15 +747,18 @@ hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* gr
 
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
-                             int64_t n_frames, const int32_t* cell_rot, const double* log_w, const double* S,
-                             const double* b, double* L, void* Pd, int64_t ldd, const int2* tiles, int64_t n_tiles,
-                             const int64_t* cf_ptr, const int32_t* cf_frame, hipStream_t st) {
+                             int64_t n_frames, const int32_t* cell_rot, int64_t n_rot, const double* log_w,
+                             const double* S, double* cst, const double* b, double* L, void* Pd, int64_t ldd,
+                             const int2* tiles, int64_t n_tiles, const int64_t* cf_ptr, const int32_t* cf_frame,
+                             hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
+  if (n_rot > 0)
+    cell_const_kernel<<<(unsigned)((n_rot + 255) / 256), 256, 0, st>>>(cell_rot, n_rot, log_w, S, cst);
   cand_estep_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(G, groups, grp_off, cg_ptr, cells, pair_col, k_top,
-                                                                    n_frames, cell_rot, log_w, S, b, L);
+                                                                    n_frames, cst, b, L);
   if (n_tiles > 0)
-    cand_pwrite_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, G, cell_rot, log_w,
-                                                          S, b, L, (uint16_t*)P, (uint16_t*)Pd, ldd);
+    cand_pwrite_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, G, cell_rot, cst,
+                                                          b, L, (uint16_t*)P, (uint16_t*)Pd, ldd);
   return hipGetLastError();
 }
 
@@ -779,8 +808,12 @@ hipError_t launch_band_dot(const int2* band_range, int nbands, const void* chunk
 
 hipError_t launch_dense_bands(const int32_t* cnt, int64_t n_frames, int nbands, float* mean, int32_t* dense_band,
                               int32_t* dense_list, int32_t* n_dense, hipStream_t st) {
-  if (n_frames > 0 && nbands > 0) band_mean_kernel<<<(unsigned)nbands, 256, 0, st>>>(cnt, n_frames, mean);
-  else if (nbands > 0) launch_fill_i32(reinterpret_cast<int32_t*>(mean), nbands, 0, st);
+  if (n_frames > 0 && nbands > 0) {
+    band_mean_kernel<<<(unsigned)nbands, 256, 0, st>>>(cnt, n_frames, mean);
+  } else if (nbands > 0) {  // no frames: every band's mean is zero (the bits of 0.0f)
+    const hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(mean), nbands, 0, st);
+    if (e != hipSuccess) return e;
+  }
   dense_pick_kernel<<<1, 64, 0, st>>>(mean, nbands, dense_band, dense_list, n_dense);
   return hipGetLastError();
 }

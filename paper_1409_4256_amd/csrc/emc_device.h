@@ -183,9 +183,10 @@ hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* gr
                               const float* scale, int64_t ps, float* G, hipStream_t st);
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
-                             int64_t n_frames, const int32_t* cell_rot, const double* log_w, const double* S,
-                             const double* b, double* L, void* Pd, int64_t ldd, const int2* tiles, int64_t n_tiles,
-                             const int64_t* cf_ptr, const int32_t* cf_frame, hipStream_t st);
+                             int64_t n_frames, const int32_t* cell_rot, int64_t n_rot, const double* log_w,
+                             const double* S, double* cst, const double* b, double* L, void* Pd, int64_t ldd,
+                             const int2* tiles, int64_t n_tiles, const int64_t* cf_ptr, const int32_t* cf_frame,
+                             hipStream_t st);
 hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
                              const int32_t* cf_frame, const int2* band_range, int64_t n_list, const void* chunks,
                              const int32_t* dense_band, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
