@@ -562,20 +562,28 @@ __global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restri
   }
 }
 
-// b_f = sum over the frame's pixels of count * c[pixel], FP64; one wave per frame
+// b_f = sum over the frame's pixels of count * c[pixel], FP64; one wave per frame,
+// lane l takes bands l, l + 64, ... and reads their chunks whole
 __global__ __launch_bounds__(256) void band_dot_kernel(const int2* __restrict__ band_range, int nb,
-                                                       const uint16_t* __restrict__ words, int64_t n_frames,
+                                                       const u4* __restrict__ chunks, int64_t n_frames,
                                                        const double* __restrict__ cvec, double* __restrict__ b) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= n_frames) return;
   double acc = 0.0;
-  for (int band = 0; band < nb; ++band) {
+  for (int band = lane; band < nb; band += 64) {
     const int2 r = band_range[(int64_t)band * n_frames + f];
-    const int64_t a = 8 * (int64_t)r.x, z = 8 * (int64_t)r.y;
-    for (int64_t t = a + lane; t < z; t += 64) {
-      const uint32_t e = words[t];
-      if (e != kPad) acc += (double)(e & 511u) * cvec[band * kBand + (e >> 9)];
+    const double* cb = cvec + band * kBand;
+    for (int ch = r.x; ch < r.y; ++ch) {
+      const u4 w = chunks[ch];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t e = h ? (w[u] >> 16) : (w[u] & 0xffffu);
+          if (e != kPad) acc += (double)(e & 511u) * cb[e >> 9];
+        }
+      }
     }
   }
   acc = wave_sum(acc);
@@ -801,8 +809,8 @@ hipError_t launch_band_fill(const uint16_t* counts, const uint8_t* mask, int n_p
 hipError_t launch_band_dot(const int2* band_range, int nbands, const void* chunks, int64_t n_frames, const double* c,
                            double* b, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
-  band_dot_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(band_range, nbands, (const uint16_t*)chunks,
-                                                                  n_frames, c, b);
+  band_dot_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(band_range, nbands, (const u4*)chunks, n_frames,
+                                                                  c, b);
   return hipGetLastError();
 }
 

@@ -7,11 +7,13 @@
 // Workgroup tile 256 x 256 x 64 with 8 waves (two per SIMD, so that one can
 // issue MFMAs while the other waits on LDS) in a 2 x 4 arrangement, each wave
 // 128 x 64 from 8 x 4 v_mfma_f32_16x16x32_bf16 tiles (4 waves of 128 x 128 when
-// built with EMC_BF16_WAVES=4).  One LDS stage laid out
+// built with EMC_BF16_WAVES=4).  LDS stages laid out
 // [row][k] (144-byte rows: 128 bytes of data + 16 of padding, so eight lanes'
 // 16-byte reads hit distinct banks); the next stage's global loads (full
 // 128-byte row segments) are issued into registers before the current stage's
-// 4096 MFMA cycles, which hides their latency.  A lane feeds one MFMA with 8
+// 4096 MFMA cycles, which hides their latency.  The single-term product holds two
+// stages and stores the next one while the current one is read (one barrier per
+// stage); the two-term one holds one stage (two barriers per stage).  A lane feeds one MFMA with 8
 // consecutive k of one row (one 128-bit LDS read); A and B use the same k
 // assignment, so the product sums the same pairs.
 //
@@ -37,8 +39,11 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
                                                         int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb,
                                                         int64_t ldc, int64_t stages, int64_t c_split) {
   constexpr int NA = DUAL ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) uint16_t As[NA][TM * LROW];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[TN * LROW];
+  // single-term products keep two stages in LDS (144 KB), so that one barrier per
+  // stage suffices; the two-term one has room for one stage
+  constexpr int NB = DUAL ? 1 : 2;
+  __shared__ __attribute__((aligned(16))) uint16_t As[NB][NA][TM * LROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[NB][TN * LROW];
 
   // 4 waves: 2 x 2 of 128 x 128; 8 waves (two per SIMD): 2 x 4 of 128 x 64
   constexpr int NT = 64 * WAVES;
@@ -83,12 +88,12 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
     if constexpr (DUAL) ra1[u] = arow[u] >= 0 ? *reinterpret_cast<const u4*>(A2b + ao) : zero;        \
     rb[u] = (NT / 8) * u < nvalid ? *reinterpret_cast<const u4*>(Bb + (int64_t)(NT / 8) * u * ldb + (k0)) : zero; \
   }
-#define EMC_STORE_STAGE()                                                                               \
+#define EMC_STORE_STAGE(buf)                                                                            \
   _Pragma("unroll") for (int u = 0; u < SLOTS; ++u) {                                                 \
     const int r = (tid >> 3) + (NT / 8) * u;                                                            \
-    *reinterpret_cast<u4*>(&As[0][r * LROW + 8 * ch]) = ra0[u];                                    \
-    if constexpr (DUAL) *reinterpret_cast<u4*>(&As[NA - 1][r * LROW + 8 * ch]) = ra1[u];           \
-    *reinterpret_cast<u4*>(&Bs[r * LROW + 8 * ch]) = rb[u];                                        \
+    *reinterpret_cast<u4*>(&As[buf][0][r * LROW + 8 * ch]) = ra0[u];                               \
+    if constexpr (DUAL) *reinterpret_cast<u4*>(&As[buf][NA - 1][r * LROW + 8 * ch]) = ra1[u];      \
+    *reinterpret_cast<u4*>(&Bs[buf][r * LROW + 8 * ch]) = rb[u];                                   \
   }
 
   f4 acc[IT][JT];
@@ -101,11 +106,12 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
   const int64_t nk = (Kd + TK - 1) / TK;
   const int64_t s0 = split * stages, s1 = s0 + stages < nk ? s0 + stages : nk;
   EMC_LOAD_STAGE(s0 * TK)
-  EMC_STORE_STAGE()
+  EMC_STORE_STAGE(0)
   __syncthreads();
 
   const int arow_l = wm * WROWS + (lane & 15), brow_l = wn * WCOLS + (lane & 15), kofs = 8 * (lane >> 4);
   for (int64_t s = s0; s < s1; ++s) {
+    const int cur = NB == 2 ? (int)((s - s0) & 1) : 0;
     if (s + 1 < s1) {
       const int64_t k1 = (s + 1) * TK;
       EMC_LOAD_STAGE(k1)
@@ -114,21 +120,31 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
     for (int kk = 0; kk < TK; kk += 32) {
       bf8 b[JT];
 #pragma unroll
-      for (int j = 0; j < JT; ++j) b[j] = *reinterpret_cast<const bf8*>(&Bs[(brow_l + 16 * j) * LROW + kk + kofs]);
+      for (int j = 0; j < JT; ++j)
+        b[j] = *reinterpret_cast<const bf8*>(&Bs[cur][(brow_l + 16 * j) * LROW + kk + kofs]);
 #pragma unroll
       for (int i = 0; i < IT; ++i) {
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
-          const bf8 av = *reinterpret_cast<const bf8*>(&As[a][(arow_l + 16 * i) * LROW + kk + kofs]);
+          const bf8 av = *reinterpret_cast<const bf8*>(&As[cur][a][(arow_l + 16 * i) * LROW + kk + kofs]);
 #pragma unroll
           for (int j = 0; j < JT; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b[j], acc[i][j], 0, 0, 0);
         }
       }
     }
-    __syncthreads();
-    if (s + 1 < s1) {
-      EMC_STORE_STAGE()
+    if constexpr (NB == 2) {
+      // the other stage was last read in the previous step, which every wave has
+      // left (barrier below); the barrier then publishes this store for the next step
+      if (s + 1 < s1) {
+        EMC_STORE_STAGE(cur ^ 1)
+      }
       __syncthreads();
+    } else {
+      __syncthreads();
+      if (s + 1 < s1) {
+        EMC_STORE_STAGE(0)
+        __syncthreads();
+      }
     }
   }
 #undef EMC_LOAD_STAGE
