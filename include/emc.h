@@ -295,7 +295,7 @@ emc_status emc_iterate_gaussian(const emc_problem* pb, double sigma, const float
 /* ------------------------------------------------------------------------
  * Learned orientation proposal.  A small CNN scores the cells of a coarse
  * rotation grid from a frame; its top-K cells restrict the E-step's search
- * (the full search stays the fallback and the judge of recall).  This is an
+ * (the full search stays the fallback and the measure of recall).  This is an
  * addition to the paper's method; its training targets are the E-step
  * responsibilities of eq. (2.4) summed over each cell's fine rotations.
  * Network: x = log(1 + binned frame) 1x64x64 -> 4 x [conv 3x3 stride 2 pad 1

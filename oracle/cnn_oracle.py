@@ -3,7 +3,7 @@
 The proposal network reads a frame and scores the cells of a coarse rotation
 grid; it is trained on the responsibilities of full EMC iterations (summed
 over the fine rotations of each cell) and only narrows the E-step's search,
-whose full form stays the fallback and the judge of recall.  The paper has no
+whose full form stays the fallback and the measure of recall.  The paper has no
 such network: this oracle fixes the network the GPU path implements.
 
 Network (NCHW, float64 here):
