@@ -356,14 +356,19 @@ __global__ __launch_bounds__(256) void cand_pwrite_kernel(
 // dense product left there); the range-0 workgroup also sums rho = sum P.
 constexpr int kPair = 2 * kBand;    // pixels per wave in the M-step
 __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
-    const int4* __restrict__ groups, const int64_t* __restrict__ grp_off, int nranges,
+    const int4* __restrict__ groups, const int64_t* __restrict__ grp_off, int64_t n_groups, int nranges,
     const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int2* __restrict__ band_range,
     int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ dense_band, const uint16_t* __restrict__ P,
     const int32_t* __restrict__ cell_rot, int64_t ps, float* __restrict__ Wp, double* __restrict__ rho,
     const double* __restrict__ rho_a, int accumulate) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kPair * kKRow];  // 81920 bytes
-  const int64_t g = blockIdx.x / nranges;
-  const int pr = (int)(blockIdx.x % nranges);
+  // workgroup 8 q + x (dispatch is round-robin over the 8 XCDs: it runs on XCD x)
+  // takes range q mod nranges of group 8 (q / nranges) + x, so a group's ranges run
+  // one after another on one XCD and share its P in that XCD's L2
+  const int64_t q = blockIdx.x >> 3;
+  const int64_t g = 8 * (q / nranges) + (blockIdx.x & 7);
+  const int pr = (int)(q % nranges);
+  if (g >= n_groups) return;  // padding of the group count to a multiple of 8 (uniform)
   const int4 gr = groups[g];
   const int c = gr.x, r0 = gr.y, nr = gr.z;
   const int64_t F = cf_ptr[c + 1] - cf_ptr[c];
@@ -776,7 +781,8 @@ hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t
                              double* rho, const double* rho_a, bool accumulate, hipStream_t st) {
   if (n_groups <= 0) return hipSuccess;
   const int nranges = (int)((ps + 4 * kPair - 1) / (4 * kPair));
-  cand_mstep_kernel<<<(unsigned)(n_groups * nranges), 256, 0, st>>>(groups, grp_off, nranges, cf_ptr, cf_frame,
+  const int64_t g8 = (n_groups + 7) / 8 * 8;
+  cand_mstep_kernel<<<(unsigned)(g8 * nranges), 256, 0, st>>>(groups, grp_off, n_groups, nranges, cf_ptr, cf_frame,
                                                                     band_range, n_list, (const u4*)chunks, dense_band,
                                                                     (const uint16_t*)P, cell_rot, ps, Wp, rho, rho_a,
                                                                     accumulate ? 1 : 0);
