@@ -152,16 +152,26 @@ emc_status run_expand(const emc_problem* pb, const float* model, double* c, void
   return EMC_OK;
 }
 
+// splits > 1 (BF16 only; from gemm_bf16_splits): the product's k range is cut in
+// `splits` parts whose partial products go to `part` (splits x n_rot x ds floats)
+// and are summed into G
 emc_status run_loglik(const emc_problem* pb, const void* K, const void* slices, const float* scale, const double* c,
-                      float* G, double* b, hipStream_t st) {
+                      float* G, double* b, hipStream_t st, int splits = 1, float* part = nullptr) {
   if (pb->n_data == 0) return EMC_OK;
   const Dims d = dims_of(pb);
   HIP_TRY(launch_frame_dot(K, is_bf16(pb), d.ps, pb->n_data, c, b, st), "frame_dot");
   if (is_bf16(pb)) {
     const char* hi = (const char*)slices;
     const char* lo = hi + (size_t)pb->n_rot * d.ps * 2;
-    HIP_TRY(launch_gemm_bf16_dual_nt(hi, lo, K, scale, G, pb->n_rot, pb->n_data, d.ps, d.ps, d.ps, d.ds, st),
-            "loglik gemm");
+    if (splits > 1) {
+      HIP_TRY(launch_gemm_bf16_dual_nt_split(hi, lo, K, scale, part, pb->n_rot, pb->n_data, d.ps, d.ps, d.ps, d.ds,
+                                             splits, st),
+              "loglik gemm");
+      HIP_TRY(launch_sum_slabs(part, splits, (int64_t)pb->n_rot * d.ds, G, st), "loglik partial sums");
+    } else {
+      HIP_TRY(launch_gemm_bf16_dual_nt(hi, lo, K, scale, G, pb->n_rot, pb->n_data, d.ps, d.ps, d.ps, d.ds, st),
+              "loglik gemm");
+    }
   } else {
     HIP_TRY(launch_gemm_f32_nt((const float*)slices, (const float*)K, G, pb->n_rot, pb->n_data, d.ps, d.ps, d.ps, d.ds,
                                st),
@@ -1095,7 +1105,7 @@ namespace {
 
 struct PropWs {
   size_t slices, S, scale, c, b, L, G, P, Ga, Pa, stats_a, stats_p, rho_a, recall, rho, num, den, Pd, Wd, copies,
-      cst, total;
+      cst, Ga_part, total;
 };
 
 // k-range parts of the dense-band M-step product (its partial products are summed
@@ -1104,6 +1114,13 @@ constexpr int kMaxDenseSplits = 4;
 int dense_splits(const emc_problem* pb, const emc_proposal* P) {
   if (P->n_dense <= 0) return 1;
   return gemm_bf16_splits(pb->n_rot, (int64_t)P->n_dense * kBandPx, P->ld_dense, kMaxDenseSplits);
+}
+
+// k-range parts of the audited frames' log-likelihood product (few frames: few
+// output tiles over a full-detector reduction)
+int audit_splits(const emc_problem* pb, const emc_proposal* P) {
+  if (P->n_audit <= 0) return 1;
+  return gemm_bf16_splits(pb->n_rot, P->n_audit, round_up(pb->n_pix, 256), kMaxDenseSplits);
 }
 
 PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
@@ -1139,6 +1156,9 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
   W.Wd = take((int64_t)pb->n_rot * P->n_dense * kBandPx * 4 * dense_splits(pb, P));
   W.copies = take((int64_t)copies_bytes(pb));
   W.cst = take((int64_t)pb->n_rot * 8);  // log w_j - S_j in the cells' rotation order
+  // partial products of the audit's split log-likelihood product
+  const int as = audit_splits(pb, P);
+  W.Ga_part = take(as > 1 ? (int64_t)as * pb->n_rot * dsa * 4 : 0);
   W.total = o;
   return W;
 }
@@ -1237,7 +1257,8 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   emc_problem pa = *pb;
   pa.n_data = (int32_t)na;
   if (na > 0) {
-    CHECK(run_loglik(&pa, K_audit, slices, scale, c, Ga, b + nc, st));
+    CHECK(run_loglik(&pa, K_audit, slices, scale, c, Ga, b + nc, st, audit_splits(pb, plan),
+                     (float*)(w + W.Ga_part)));
     CHECK(run_estep(&pa, Ga, S, b + nc, EMC_RESP_FULL, stats_a, Pa, L + nc, rho_a, st,
                     (double*)(w + W.stats_p)));
     HIP_TRY(launch_audit_recall(Pa, dsa, pb->n_rot, na, plan->mask_audit, plan->words, plan->cell_of, recall, st),

@@ -103,6 +103,11 @@ hipError_t launch_gemm_bf16_nt(const void* A, const void* B, float* C, int64_t M
 int gemm_bf16_splits(int64_t M, int64_t N, int64_t Kd, int max_splits);
 hipError_t launch_gemm_bf16_nt_split(const void* A, const void* B, float* C, int64_t M, int64_t N, int64_t Kd,
                                      int64_t lda, int64_t ldb, int64_t ldc, int splits, hipStream_t st);
+hipError_t launch_gemm_bf16_dual_nt_split(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
+                                          float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb,
+                                          int64_t ldc, int splits, hipStream_t st);
+// out[e] = sum over s < parts of part[s * n + e], in order of s
+hipError_t launch_sum_slabs(const float* part, int parts, int64_t n, float* out, hipStream_t st);
 // part: NULL, or kMaxLseChunks * 2 * n_data doubles of scratch that lets few frames
 // split the rotations over more workgroups
 constexpr int kMaxLseChunks = 64;

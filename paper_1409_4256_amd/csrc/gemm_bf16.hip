@@ -220,6 +220,29 @@ hipError_t launch_gemm_bf16_nt_split(const void* A, const void* B, float* C, int
   return launch<false>(A, nullptr, B, nullptr, C, M, N, Kd, lda, ldb, ldc, st, splits);
 }
 
+hipError_t launch_gemm_bf16_dual_nt_split(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
+                                          float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb,
+                                          int64_t ldc, int splits, hipStream_t st) {
+  return launch<true>(A_hi, A_lo, B, row_scale, C, M, N, Kd, lda, ldb, ldc, st, splits);
+}
+
+// out[e] = sum of the parts' slabs part[s * n + e], s = 0, 1, ... in order
+__global__ void sum_slabs_kernel(const float* __restrict__ part, int parts, int64_t n, float* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    float v = part[e];
+    for (int s = 1; s < parts; ++s) v += part[e + s * n];
+    out[e] = v;
+  }
+}
+
+hipError_t launch_sum_slabs(const float* part, int parts, int64_t n, float* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (parts < 1) return hipErrorInvalidValue;
+  const int64_t g = (n + 255) / 256;
+  sum_slabs_kernel<<<(unsigned)(g > 65536 ? 65536 : g), 256, 0, st>>>(part, parts, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_bf16_dual_nt(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
                                     float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb, int64_t ldc,
                                     hipStream_t st) {
