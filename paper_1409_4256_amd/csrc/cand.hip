@@ -567,32 +567,37 @@ __global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restri
   }
 }
 
-// b_f = sum over the frame's pixels of count * c[pixel], FP64; one wave per frame,
-// lane l takes bands l, l + 64, ... and reads their chunks whole
+// b_f = sum over the frame's pixels of count * c[pixel], FP64.  One workgroup per
+// 64 consecutive frames, lane = frame, so a band's table entries and chunks are read
+// contiguously and a dense band keeps every lane busy; wave w takes bands w, w + 4,
+// ..., and the four partial sums are added in a fixed order.
 __global__ __launch_bounds__(256) void band_dot_kernel(const int2* __restrict__ band_range, int nb,
                                                        const u4* __restrict__ chunks, int64_t n_frames,
                                                        const double* __restrict__ cvec, double* __restrict__ b) {
-  const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (f >= n_frames) return;
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t f = (int64_t)blockIdx.x * 64 + lane;
   double acc = 0.0;
-  for (int band = lane; band < nb; band += 64) {
-    const int2 r = band_range[(int64_t)band * n_frames + f];
-    const double* cb = cvec + band * kBand;
-    for (int ch = r.x; ch < r.y; ++ch) {
-      const u4 w = chunks[ch];
+  if (f < n_frames) {
+    for (int band = wave; band < nb; band += 4) {
+      const int2 r = band_range[(int64_t)band * n_frames + f];
+      const double* cb = cvec + band * kBand;
+      for (int ch = r.x; ch < r.y; ++ch) {
+        const u4 w = chunks[ch];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const uint32_t e = h ? (w[u] >> 16) : (w[u] & 0xffffu);
-          if (e != kPad) acc += (double)(e & 511u) * cb[e >> 9];
+          for (int h = 0; h < 2; ++h) {
+            const uint32_t e = h ? (w[u] >> 16) : (w[u] & 0xffffu);
+            if (e != kPad) acc += (double)(e & 511u) * cb[e >> 9];
+          }
         }
       }
     }
   }
-  acc = wave_sum(acc);
-  if (lane == 0) b[f] = acc;
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && f < n_frames) b[f] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 // Dense bands: band b is dense when its frames average at least kDenseChunks
@@ -815,8 +820,8 @@ hipError_t launch_band_fill(const uint16_t* counts, const uint8_t* mask, int n_p
 hipError_t launch_band_dot(const int2* band_range, int nbands, const void* chunks, int64_t n_frames, const double* c,
                            double* b, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
-  band_dot_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(band_range, nbands, (const u4*)chunks, n_frames,
-                                                                  c, b);
+  band_dot_kernel<<<(unsigned)((n_frames + 63) / 64), 256, 0, st>>>(band_range, nbands, (const u4*)chunks, n_frames,
+                                                                   c, b);
   return hipGetLastError();
 }
 
