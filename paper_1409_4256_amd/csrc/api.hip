@@ -164,6 +164,7 @@ emc_status run_loglik(const emc_problem* pb, const void* K, const void* slices, 
     const char* hi = (const char*)slices;
     const char* lo = hi + (size_t)pb->n_rot * d.ps * 2;
     if (splits > 1) {
+      if (!part) return fail(EMC_ERR_INVALID_ARG, "split log-likelihood product without a partial-product buffer");
       HIP_TRY(launch_gemm_bf16_dual_nt_split(hi, lo, K, scale, part, pb->n_rot, pb->n_data, d.ps, d.ps, d.ps, d.ds,
                                              splits, st),
               "loglik gemm");
