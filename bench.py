@@ -351,7 +351,6 @@ def proposal_form(inp, args, counts_dev):
     tlog = net.train(x, targets, wl.n_data, epochs=2, lr=1e-3, rng=seeded(wl.cfg, "cnn"))
     log(f"proposal: trained {tlog.steps} steps in {tlog.seconds:.1f} s, loss {tlog.loss_first:.3f} -> "
         f"{tlog.loss_last:.3f}")
-    T_last = targets[-1]
     del targets
     n_audit = max(1, int(round(0.02 * wl.n_data)))
     audit = torch.as_tensor(np.sort(seeded(wl.cfg, "audit").choice(wl.n_data, n_audit, replace=False)),
@@ -359,15 +358,12 @@ def proposal_form(inp, args, counts_dev):
     top_net = net.topk(x, wl.n_data, k_net)
     del x
 
-    def build(T):
-        top_prev = torch.empty(wl.n_data * k_prev, dtype=torch.int32, device="cuda")
-        emc.emc_cell_topk(T, wl.n_data, n_cells, k_prev, top_prev)
-        cand = torch.empty(wl.n_data * (k_net + k_prev), dtype=torch.int32, device="cuda")
-        emc.emc_topk_union(top_net, k_net, top_prev, k_prev, wl.n_data, n_cells, cand)
-        return learned.ProposedIteration(g, counts_dev, coarse, n_cells, cand, k_net + k_prev, audit)
+    def build():   # lists from the last full search's posterior (run.P) and the network
+        lists, k = learned.proposal_lists(g, run.P, cells, n_cells, top_net, k_net, k_prev)
+        return learned.ProposedIteration(g, counts_dev, coarse, n_cells, lists, k, audit)
 
     t0 = time.perf_counter()
-    prop = build(T_last)
+    prop = build()
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     n_pairs = prop.candidate_pairs()
@@ -381,13 +377,14 @@ def proposal_form(inp, args, counts_dev):
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         sev = [torch.cuda.Event(enable_timing=True) for _ in range(emc.EMC_PROPOSED_STAGES + 1)]
         ev0.record()
-        prop.step(run.model[run.cur], run.model[1 - run.cur], sev)
-        ok = prop.accepted()
+        # the full search from the same input model replaces a rejected iteration
+        # (run.step reads run.model[run.cur], writes the other and flips run.cur)
+        ok = learned.proposed_or_full(prop, lambda a, b: run.step(), run.model[run.cur], run.model[1 - run.cur],
+                                      sev)
         if ok:
             run.cur = 1 - run.cur
         else:
             fallbacks += 1
-            run.step()          # full search from the same input model
         ev1.record()
         torch.cuda.synchronize()
         per.append(ev0.elapsed_time(ev1))
@@ -397,7 +394,7 @@ def proposal_form(inp, args, counts_dev):
             f"{'accepted' if ok else 'fell back to full search'}")
         if not ok:              # the full posterior just computed becomes the new persistence source
             del prop
-            prop = build(targets_now())
+            prop = build()
     st_med = np.median(np.asarray(stages), axis=0)
     steps_ms = {name: round(float(v), 3) for name, v in zip(emc.PROPOSED_STAGE_NAMES, st_med)}
     # roofline of the dominant candidate kernel: the contractions over the candidate

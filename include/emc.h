@@ -419,6 +419,9 @@ typedef struct emc_proposal {
   int32_t* dense_list;    /* [16] band of each dense index                          */
   void* kt_dense;         /* [n_dense * 128][ld_dense] BF16 pixel-major counts of the
                              dense bands' pixels over the candidate frames         */
+  int32_t n_rot, n_pix;   /* problem the plan was built for: the iteration refuses a */
+  const float* quat;      /* problem with other sizes, rotations or mask            */
+  const uint8_t* mask;
 } emc_proposal;
 
 /* Bytes of the plan buffer; nz_cap bounds the non-zero pixels of the frames. */
@@ -449,8 +452,52 @@ emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposa
                                   candidate M-step of the dense bands (one product);
                                   compression, division and mean log-evidence           */
 
+/* One frame chunk of a learned-proposal iteration, without the division: the
+ * k-direction split of Section 3.3 applied to the restricted iteration, so that
+ * the frame chunks of one iteration, each with its own plan and audit, sum into
+ * one numerator and denominator before emc_finalize divides them.
+ * pb->precision must be EMC_PREC_BF16; pb->n_data = n_cand + n_audit.
+ *   K_audit     frames plan->audit_frames packed by emc_pack_frames_list
+ *   num, den    [N^3] double: accumulate == 0 zeroes them first.  The chunk's
+ *               c-step sums (eq. 2.12) are then added when its audit accepts it
+ *               (recall_mean >= recall_min, or no audited frames: recall NaN) and
+ *               skipped otherwise, decided on the device without synchronising,
+ *               so that the caller can add the chunk's full search instead
+ *               (emc_loglik, emc_responsibilities, emc_compress with accumulate).
+ *   L           [n_data] double out: log-evidence of each frame over its searched
+ *               set, candidate frames in plan->cand_frames order, then audited
+ *               frames in plan->audit_frames order
+ *   recall_mean device double out: mean recall of the audited frames (NaN without)
+ *   ws          emc_proposed_workspace_bytes bytes, 256-byte aligned
+ *   stage_events NULL, or EMC_PROPOSED_STAGES + 1 events (see below); the last
+ *               stage holds the c-step only                                      */
+emc_status emc_proposed_accumulate(const emc_problem* pb, const emc_proposal* plan, const void* K_audit,
+                                   const float* model_in, double* num, double* den, int32_t accumulate,
+                                   double recall_min, double* L, double* recall_mean, void* ws, size_t ws_bytes,
+                                   hipEvent_t* stage_events, hipStream_t stream);
+
+/* Where the intermediate results of the last emc_iterate_proposed or
+ * emc_proposed_accumulate call on a workspace lie in it (byte offsets), for
+ * inspection; valid until the workspace is used again.
+ *   G   float: candidate log-likelihood sums of eq. (2.3), group g's list position
+ *       f and rotation slot r (rotation cell_rot[groups[g].first + r]) at element
+ *       grp_off[g] + 32 f + r; Q = G + b_f - S_j
+ *   P   bfloat16: responsibilities of eq. (2.4) over the candidate pairs, group g's
+ *       storage at element grp_off[g] as blocks [Fp/32][32 rotations][32 frames]
+ *   b   double [n_data]: b_f = sum_i K_if c_i (candidate frames, then audited ones)
+ *   L   double [n_data]: log-evidence, same order (emc_iterate_proposed only)
+ *   S   double [n_rot]: S_j = sum_i W_ij
+ *   Ga  float [n_rot][round_up(n_audit, 256)]: audited frames' G (full search)
+ *   Pa  bfloat16, same shape: audited frames' responsibilities                   */
+typedef struct emc_proposed_view {
+  int64_t G, P, b, L, S, Ga, Pa;
+} emc_proposed_view;
+emc_status emc_proposed_workspace_view(const emc_problem* pb, const emc_proposal* plan, emc_proposed_view* view);
+
 /* One iteration with the E-step restricted to the proposal (pb->precision must
- * be EMC_PREC_BF16; pb->n_data = n_cand + n_audit):
+ * be EMC_PREC_BF16; pb->n_data = n_cand + n_audit): emc_proposed_accumulate
+ * into workspace grids (accumulate 0, every chunk's sums added), then the
+ * division and the mean log-evidence of emc_finalize.
  *   K_audit  frames plan->audit_frames packed by emc_pack_frames_list (the
  *            candidate frames are read from the plan's sparse band format)
  *   loglik   mean log-evidence over all frames (each over its searched set)

@@ -1096,6 +1096,10 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   P.n_groups = host[2];
   P.n_g = host[3];
   P.n_chunks = host[4];
+  P.n_rot = pb->n_rot;
+  P.n_pix = pb->n_pix;
+  P.quat = pb->quat;
+  P.mask = pb->mask;
   *plan = P;
   return EMC_OK;
 }
@@ -1166,6 +1170,9 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
 
 emc_status check_plan(const emc_problem* pb, const emc_proposal* P) {
   if (!P) return fail(EMC_ERR_INVALID_ARG, "plan is NULL");
+  // the plan's rotation lists and frame bands index this problem's slices and pixels
+  if (P->n_rot != pb->n_rot || P->n_pix != pb->n_pix || P->quat != pb->quat || P->mask != pb->mask)
+    return fail(EMC_ERR_INVALID_ARG, "proposal plan was built for another rotation set or detector");
   if (P->n_cand < 0 || P->n_audit < 0 || (int64_t)P->n_cand + P->n_audit != pb->n_data)
     return fail(EMC_ERR_INVALID_ARG, "plan frames (%d + %d) do not match n_data %d", P->n_cand, P->n_audit, pb->n_data);
   if (P->k_top < 1 || P->k_top > kMaxTop || P->n_cells < 1 || P->words != words_of(P->n_cells) || P->n_g < 0 ||
@@ -1188,21 +1195,18 @@ emc_status emc_proposed_workspace_bytes(const emc_problem* pb, const emc_proposa
   return EMC_OK;
 }
 
-emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_audit,
-                                const float* model_in, float* model_out, double* loglik, double* recall_mean,
-                                void* ws, size_t ws_bytes, hipEvent_t* stage_events, hipStream_t st) {
-  CHECK(check_problem(pb, true));
-  if (!is_bf16(pb)) return fail(EMC_ERR_UNSUPPORTED, "the proposal form runs in BF16 precision");
-  CHECK(check_plan(pb, plan));
-  if (plan->n_audit > 0) CHECK(need(K_audit, 16, "K_audit"));
-  CHECK(need(model_in, 4, "model_in"));
-  CHECK(need(model_out, 4, "model_out"));
-  CHECK(need(loglik, 8, "loglik"));
-  CHECK(need(recall_mean, 8, "recall_mean"));
+}  // extern "C"
+
+namespace {
+
+// The restricted iteration up to the c-step sums (no division): expansion, candidate
+// and audited log-likelihoods, E-steps, M-steps and the c-step into num/den (zeroed
+// first unless `accumulate`; with `gated`, the sums are added only when the audit's
+// recall reaches recall_min).  L [n_cand + n_audit]: log-evidence per frame.
+emc_status run_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_audit, const float* model_in,
+                        double* num, double* den, int32_t accumulate, bool gated, double recall_min, double* L,
+                        double* recall_mean, char* w, hipEvent_t* stage_events, hipStream_t st) {
   const PropWs W = prop_ws(pb, plan);
-  if (!ws || !aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is NULL or not 256-byte aligned");
-  if (ws_bytes < W.total) return fail(EMC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
-  char* w = (char*)ws;
   const int64_t ps = round_up(pb->n_pix, 256);
   const int64_t nc = plan->n_cand, na = plan->n_audit;
   const int64_t dsa = round_up(na, 256);
@@ -1211,7 +1215,6 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   float* scale = (float*)(w + W.scale);
   double* c = (double*)(w + W.c);
   double* b = (double*)(w + W.b);
-  double* L = (double*)(w + W.L);
   float* G = (float*)(w + W.G);
   void* Pc = w + W.P;
   float* Ga = (float*)(w + W.Ga);
@@ -1220,8 +1223,6 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
   double* rho_a = (double*)(w + W.rho_a);
   double* recall = (double*)(w + W.recall);
   double* rho = (double*)(w + W.rho);
-  double* num = (double*)(w + W.num);
-  double* den = (double*)(w + W.den);
   void* Pd = plan->n_dense > 0 ? (void*)(w + W.Pd) : nullptr;
   float* Wd = (float*)(w + W.Wd);
   const int4* groups = (const int4*)plan->groups;
@@ -1287,11 +1288,78 @@ emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan,
     HIP_TRY(launch_dense_add(Wd, splits, pb->n_rot, plan->n_dense, plan->dense_list, ps, Wp, st), "dense add");
   }
   CHECK(mark(6));
-  HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
-  HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");
+  if (!accumulate) {
+    HIP_TRY(launch_fill_zero_f64(num, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero num");
+    HIP_TRY(launch_fill_zero_f64(den, (size_t)pb->grid_n * pb->grid_n * pb->grid_n, st), "zero den");
+  }
+  // a chunk the audit rejects adds exact zeros: its W' rows and rho are cleared on the device
+  if (gated) HIP_TRY(launch_gate_zero(recall_mean, recall_min, Wp, (int64_t)pb->n_rot * ps, rho, pb->n_rot, st), "gate");
   CHECK(run_scatter(pb, Wp, ps, rho, num, den, (double*)(w + W.copies), st));
-  CHECK(run_finalize(pb, num, den, model_in, model_out, L, nc + na, loglik, st));
-  CHECK(mark(7));
+  return EMC_OK;
+}
+
+emc_status check_proposed_call(const emc_problem* pb, const emc_proposal* plan, const void* K_audit,
+                               const float* model_in, const double* recall_mean, const void* ws, size_t ws_bytes) {
+  CHECK(check_problem(pb, true));
+  if (!is_bf16(pb)) return fail(EMC_ERR_UNSUPPORTED, "the proposal form runs in BF16 precision");
+  CHECK(check_plan(pb, plan));
+  if (plan->n_audit > 0) CHECK(need(K_audit, 16, "K_audit"));
+  CHECK(need(model_in, 4, "model_in"));
+  CHECK(need(recall_mean, 8, "recall_mean"));
+  const PropWs W = prop_ws(pb, plan);
+  if (!ws || !aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is NULL or not 256-byte aligned");
+  if (ws_bytes < W.total) return fail(EMC_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, W.total);
+  return EMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+emc_status emc_proposed_accumulate(const emc_problem* pb, const emc_proposal* plan, const void* K_audit,
+                                   const float* model_in, double* num, double* den, int32_t accumulate,
+                                   double recall_min, double* L, double* recall_mean, void* ws, size_t ws_bytes,
+                                   hipEvent_t* stage_events, hipStream_t st) {
+  CHECK(check_proposed_call(pb, plan, K_audit, model_in, recall_mean, ws, ws_bytes));
+  CHECK(need(num, 8, "num"));
+  CHECK(need(den, 8, "den"));
+  CHECK(need(L, 8, "L"));
+  if (std::isnan(recall_min)) return fail(EMC_ERR_INVALID_ARG, "recall_min is NaN");
+  CHECK(run_proposed(pb, plan, K_audit, model_in, num, den, accumulate, true, recall_min, L, recall_mean, (char*)ws,
+                     stage_events, st));
+  if (stage_events) HIP_TRY(hipEventRecord(stage_events[EMC_PROPOSED_STAGES], st), "stage event");
+  return EMC_OK;
+}
+
+emc_status emc_proposed_workspace_view(const emc_problem* pb, const emc_proposal* plan, emc_proposed_view* view) {
+  CHECK(check_problem(pb, false));
+  CHECK(check_plan(pb, plan));
+  if (!view) return fail(EMC_ERR_INVALID_ARG, "view is NULL");
+  const PropWs W = prop_ws(pb, plan);
+  view->G = (int64_t)W.G;
+  view->P = (int64_t)W.P;
+  view->b = (int64_t)W.b;
+  view->L = (int64_t)W.L;
+  view->S = (int64_t)W.S;
+  view->Ga = (int64_t)W.Ga;
+  view->Pa = (int64_t)W.Pa;
+  return EMC_OK;
+}
+
+emc_status emc_iterate_proposed(const emc_problem* pb, const emc_proposal* plan, const void* K_audit,
+                                const float* model_in, float* model_out, double* loglik, double* recall_mean,
+                                void* ws, size_t ws_bytes, hipEvent_t* stage_events, hipStream_t st) {
+  CHECK(check_proposed_call(pb, plan, K_audit, model_in, recall_mean, ws, ws_bytes));
+  CHECK(need(model_out, 4, "model_out"));
+  CHECK(need(loglik, 8, "loglik"));
+  const PropWs W = prop_ws(pb, plan);
+  char* w = (char*)ws;
+  double* L = (double*)(w + W.L);
+  double* num = (double*)(w + W.num);
+  double* den = (double*)(w + W.den);
+  CHECK(run_proposed(pb, plan, K_audit, model_in, num, den, 0, false, 0.0, L, recall_mean, w, stage_events, st));
+  CHECK(run_finalize(pb, num, den, model_in, model_out, L, (int64_t)plan->n_cand + plan->n_audit, loglik, st));
+  if (stage_events) HIP_TRY(hipEventRecord(stage_events[EMC_PROPOSED_STAGES], st), "stage event");
   return EMC_OK;
 }
 

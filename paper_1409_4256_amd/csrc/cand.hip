@@ -857,6 +857,23 @@ hipError_t launch_dense_add(const float* D, int parts, int64_t n_rot, int n_dens
   return hipGetLastError();
 }
 
+// A frame chunk the audit rejects (mean recall below recall_min; NaN, no audit,
+// accepts) contributes nothing to the grids: its W' rows and rho are cleared.
+__global__ void gate_zero_kernel(const double* __restrict__ recall, double recall_min, f4* __restrict__ Wp,
+                                 int64_t n4, double* __restrict__ rho, int64_t n_rot) {
+  if (!(*recall < recall_min)) return;  // uniform: accepted
+  const f4 z = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256) Wp[e] = z;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n_rot; e += (int64_t)gridDim.x * 256) rho[e] = 0.0;
+}
+
+hipError_t launch_gate_zero(const double* recall, double recall_min, float* Wp, int64_t n, double* rho, int64_t n_rot,
+                            hipStream_t st) {
+  if (n % 4 != 0) return hipErrorInvalidValue;
+  gate_zero_kernel<<<2048, 256, 0, st>>>(recall, recall_min, (f4*)Wp, n / 4, rho, n_rot);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_zero_bytes(void* p, int64_t bytes, hipStream_t st) {
   const int64_t n16 = bytes / 16;
   if (n16 <= 0) return hipSuccess;

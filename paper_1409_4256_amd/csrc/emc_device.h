@@ -205,6 +205,9 @@ hipError_t launch_dense_pack(const uint16_t* counts, const uint8_t* mask, int n_
 hipError_t launch_dense_add(const float* D, int parts, int64_t n_rot, int n_dense, const int32_t* dense_list,
                             int64_t ps, float* Wp, hipStream_t st);
 hipError_t launch_fill_zero_bytes(void* p, int64_t bytes, hipStream_t st);
+// when *recall < recall_min: Wp[0..n) = 0 and rho[0..n_rot) = 0 (n a multiple of 4)
+hipError_t launch_gate_zero(const double* recall, double recall_min, float* Wp, int64_t n, double* rho, int64_t n_rot,
+                            hipStream_t st);
 hipError_t launch_band_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
                              int64_t n_frames, int nbands, int32_t* cnt, int32_t* over, hipStream_t st);
 hipError_t launch_band_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,

@@ -34,7 +34,8 @@ EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride",
            "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_topk", "emc_topk_union",
            "emc_cell_targets",
            "emc_pack_frames_list", "emc_proposal_bytes", "emc_proposal_build", "emc_proposed_workspace_bytes",
-           "emc_iterate_proposed", "emc_scatter_plan_min_bytes", "emc_scatter_plan_build",
+           "emc_iterate_proposed", "emc_proposed_accumulate", "emc_proposed_workspace_view",
+           "emc_scatter_plan_min_bytes", "emc_scatter_plan_build",
            "emc_gaussian_workspace_bytes", "emc_iterate_gaussian")
 
 
@@ -86,7 +87,12 @@ class Proposal(ctypes.Structure):
         ("chunks", ctypes.c_void_p), ("band_range", ctypes.c_void_p),
         ("n_dense", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("ld_dense", ctypes.c_int64),
         ("dense_band", ctypes.c_void_p), ("dense_list", ctypes.c_void_p), ("kt_dense", ctypes.c_void_p),
+        ("n_rot", ctypes.c_int32), ("n_pix", ctypes.c_int32), ("quat", ctypes.c_void_p), ("mask", ctypes.c_void_p),
     ]
+
+
+class ProposedView(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in ("G", "P", "b", "L", "S", "Ga", "Pa")]
 
 
 _lib = None
@@ -144,6 +150,11 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_proposed_workspace_bytes.restype = st
     lib.emc_iterate_proposed.argtypes = [_PB, _PP, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, _P]
     lib.emc_iterate_proposed.restype = st
+    lib.emc_proposed_accumulate.argtypes = [_PB, _PP, _P, _P, _P, _P, i32, ctypes.c_double, _P, _P, _P,
+                                            ctypes.c_size_t, _P, _P]
+    lib.emc_proposed_accumulate.restype = st
+    lib.emc_proposed_workspace_view.argtypes = [_PB, _PP, ctypes.POINTER(ProposedView)]
+    lib.emc_proposed_workspace_view.restype = st
     lib.emc_scatter_plan_min_bytes.argtypes, lib.emc_scatter_plan_min_bytes.restype = [_PB, szp], st
     lib.emc_gaussian_workspace_bytes.argtypes, lib.emc_gaussian_workspace_bytes.restype = [_PB, szp], st
     lib.emc_iterate_gaussian.argtypes = [_PB, ctypes.c_double, _P, _P, _P, i32, _P, _P, _P, _P, ctypes.c_size_t, _P]
@@ -591,14 +602,7 @@ def emc_iterate_proposed(geo: Geometry, plan: Proposal, K_audit, model_in, model
     import torch
 
     M = geo.grid_n ** 3
-    evs = None
-    if stage_events is not None:
-        if len(stage_events) != EMC_PROPOSED_STAGES + 1:
-            raise ValueError(f"need {EMC_PROPOSED_STAGES + 1} stage events")
-        for ev in stage_events:
-            if not ev.cuda_event:            # the event is created on its first record
-                ev.record()
-        evs = (ctypes.c_void_p * len(stage_events))(*[ctypes.c_void_p(ev.cuda_event) for ev in stage_events])
+    evs = _events(stage_events)
     _check(load().emc_iterate_proposed(
         ctypes.byref(geo.pb), ctypes.byref(plan),
         _ptr(K_audit, None, None, "K_audit") if plan.n_audit else None,
@@ -606,6 +610,40 @@ def emc_iterate_proposed(geo: Geometry, plan: Proposal, K_audit, model_in, model
         _ptr(loglik, torch.float64, 1, "loglik"), _ptr(recall_mean, torch.float64, 1, "recall_mean"),
         _ptr(ws, torch.uint8, emc_proposed_workspace_bytes(geo, plan), "ws"),
         ctypes.c_size_t(ws.numel()), evs, _stream(stream)))
+
+
+def _events(stage_events):
+    if stage_events is None:
+        return None
+    if len(stage_events) != EMC_PROPOSED_STAGES + 1:
+        raise ValueError(f"need {EMC_PROPOSED_STAGES + 1} stage events")
+    for ev in stage_events:
+        if not ev.cuda_event:            # the event is created on its first record
+            ev.record()
+    return (ctypes.c_void_p * len(stage_events))(*[ctypes.c_void_p(ev.cuda_event) for ev in stage_events])
+
+
+def emc_proposed_accumulate(geo: Geometry, plan: Proposal, K_audit, model_in, num, den, accumulate, recall_min, L,
+                            recall_mean, ws, stage_events=None, stream=None):
+    """One frame chunk of the restricted iteration into num/den (added only when the
+    chunk's audit recall reaches recall_min); L [n_data] per-frame log-evidence."""
+    import torch
+
+    M = geo.grid_n ** 3
+    _check(load().emc_proposed_accumulate(
+        ctypes.byref(geo.pb), ctypes.byref(plan),
+        _ptr(K_audit, None, None, "K_audit") if plan.n_audit else None,
+        _ptr(model_in, torch.float32, M, "model_in"), _ptr(num, torch.float64, M, "num"),
+        _ptr(den, torch.float64, M, "den"), int(bool(accumulate)), ctypes.c_double(float(recall_min)),
+        _ptr(L, torch.float64, geo.n_data, "L"), _ptr(recall_mean, torch.float64, 1, "recall_mean"),
+        _ptr(ws, torch.uint8, emc_proposed_workspace_bytes(geo, plan), "ws"), ctypes.c_size_t(ws.numel()),
+        _events(stage_events), _stream(stream)))
+
+
+def emc_proposed_workspace_view(geo: Geometry, plan: Proposal) -> ProposedView:
+    v = ProposedView()
+    _check(load().emc_proposed_workspace_view(ctypes.byref(geo.pb), ctypes.byref(plan), ctypes.byref(v)))
+    return v
 
 
 def plan_array(buf, address: int, n: int, dtype):

@@ -162,6 +162,43 @@ class ProposedIteration:
                                stage_events)
 
     def accepted(self) -> bool:
-        """The audit's verdict on the last step (synchronises)."""
+        """The audit's verdict on the last step (synchronises).  Without audited
+        frames there is no verdict (accepted); with them, a recall that is not a
+        number (a broken iteration) rejects."""
         rec = self.recall.item()
-        return math.isnan(rec) or rec >= RECALL_MIN
+        if self.plan.n_audit == 0:
+            return True
+        return math.isfinite(rec) and rec >= RECALL_MIN
+
+    def view(self):
+        """Workspace offsets of the last step's candidate G, P, b, L, S (see
+        emc_proposed_workspace_view)."""
+        return E.emc_proposed_workspace_view(self.geo, self.plan)
+
+
+def proposal_lists(geo: E.Geometry, P, cells: CellIndex, n_cells: int, top_net, k_net: int, k_prev: int):
+    """Each frame's proposal: the network's top-k_net cells (top_net [n_data][k_net], or
+    None) followed by those of the k_prev cells holding most of the frame's mass in the
+    full-search responsibilities P (emc_cell_targets, emc_cell_topk, emc_topk_union).
+    Returns (lists [n_data * k], k)."""
+    n = geo.n_data
+    T = torch.empty(n * n_cells, dtype=torch.float32, device="cuda")
+    E.emc_cell_targets(geo, P, cells.cell_ptr, cells.cell_rot, n_cells, T)
+    top_prev = torch.empty(n * k_prev, dtype=torch.int32, device="cuda")
+    E.emc_cell_topk(T, n, n_cells, k_prev, top_prev)
+    if top_net is None:
+        return top_prev, k_prev
+    out = torch.empty(n * (k_net + k_prev), dtype=torch.int32, device="cuda")
+    E.emc_topk_union(top_net, k_net, top_prev, k_prev, n, n_cells, out)
+    return out, k_net + k_prev
+
+
+def proposed_or_full(prop: ProposedIteration, full_step, model_in, model_out, stage_events=None) -> bool:
+    """One iteration: the restricted one, judged by its audit; when the audit rejects
+    it, the full search from the same model replaces its result
+    (full_step(model_in, model_out) writes model_out).  Returns the verdict."""
+    prop.step(model_in, model_out, stage_events)
+    if prop.accepted():
+        return True
+    full_step(model_in, model_out)
+    return False

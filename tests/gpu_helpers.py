@@ -136,3 +136,46 @@ def top1_same_precision(P_gpu_bf16, P_ref):
 
 def top1_strict(P_gpu, P_ref):
     return float(np.mean(np.argmax(P_gpu, axis=0) == np.argmax(P_ref, axis=0)))
+
+
+def candidate_pairs(buf, plan, n_rot, frames=None):
+    """Every candidate (rotation, frame) pair of a proposal plan, with the element
+    offsets of its log-likelihood sum in the G array and of its responsibility in
+    the blocked P array (layouts of emc_proposed_workspace_view); only frames in
+    `frames` when given.  Returns int64 numpy arrays (j, frame, g_off, p_off)."""
+    pa = lambda addr, n, dt: emc.plan_array(buf, addr, n, dt).cpu().numpy()
+    groups = pa(plan.groups, 4 * plan.n_groups, torch.int32).reshape(-1, 4).astype(np.int64)
+    grp_off = pa(plan.grp_off, plan.n_groups + 1, torch.int64)
+    cf_ptr = pa(plan.cf_ptr, plan.n_cells + 1, torch.int64)
+    cf_frame = pa(plan.cf_frame, int(cf_ptr[-1]), torch.int32).astype(np.int64)
+    cand_frames = pa(plan.cand_frames, plan.n_cand, torch.int32).astype(np.int64)
+    cell_rot = pa(plan.cell_rot, n_rot, torch.int32).astype(np.int64)
+    keep = None if frames is None else set(int(f) for f in frames)
+    js, ks, go, po = [], [], [], []
+    for g in range(plan.n_groups):
+        c, first, cnt = groups[g, 0], groups[g, 1], groups[g, 2]
+        fr = cand_frames[cf_frame[cf_ptr[c]:cf_ptr[c + 1]]]
+        f = np.arange(fr.size)
+        if keep is not None:
+            sel = np.fromiter((int(x) in keep for x in fr), bool, fr.size)
+            f, fr = f[sel], fr[sel]
+        if f.size == 0:
+            continue
+        r = np.arange(cnt)
+        F, R = np.meshgrid(f, r, indexing="ij")
+        js.append(cell_rot[first + R].ravel())
+        ks.append(np.broadcast_to(fr[:, None], F.shape).ravel())
+        go.append((grp_off[g] + 32 * F + R).ravel())
+        po.append((grp_off[g] + (F >> 5) * 1024 + R * 32 + (F & 31)).ravel())
+    cat = lambda a: np.concatenate(a) if a else np.zeros(0, np.int64)
+    return cat(js), cat(ks), cat(go), cat(po)
+
+
+def proposed_pairs_values(prop_ws, view, pairs):
+    """(G, P) of the given pairs read from the workspace of the last proposed step."""
+    _, _, go, po = pairs
+    G = prop_ws[view.G:].view(torch.float32)
+    P = prop_ws[view.P:view.P + 2 * (int(po.max()) + 1 if po.size else 1)].view(torch.bfloat16)
+    gi = torch.as_tensor(go, device=prop_ws.device)
+    pi = torch.as_tensor(po, device=prop_ws.device)
+    return G[gi].double().cpu().numpy(), P[pi].double().cpu().numpy()

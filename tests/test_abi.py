@@ -137,7 +137,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     if gcc is None or not os.path.isdir("/opt/rocm/include"):
         pytest.skip("needs gcc and the ROCm headers")
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "emc.h"', "int main(void) {"]
-    structs = (("emc_problem", emc.Problem), ("emc_proposal", emc.Proposal), ("emc_scatter_plan", emc.ScatterPlan))
+    structs = (("emc_problem", emc.Problem), ("emc_proposal", emc.Proposal), ("emc_scatter_plan", emc.ScatterPlan),
+               ("emc_proposed_view", emc.ProposedView))
     for cname, cls in structs:
         lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
         for f, _ in cls._fields_:
@@ -174,6 +175,47 @@ def test_proposal_argument_checks(lib):
     plan = emc.Proposal()
     assert lib.emc_proposed_workspace_bytes(ctypes.byref(pb), ctypes.byref(plan), ctypes.byref(n)) == \
         emc.EMC_ERR_INVALID_ARG
+
+
+def _consistent_plan(pb, n_audit=20, **kw):
+    fake = 1 << 20  # never dereferenced
+    n_cand = pb.n_data - n_audit
+    d = dict(n_cells=2000, k_top=128, n_cand=n_cand, n_audit=n_audit, words=63, n_bands=pb.n_pix // 128 if
+             pb.n_pix % 256 == 0 else (pb.n_pix + 255) // 256 * 2, n_groups=2000, n_tiles=8 * 100, n_g=1 << 20,
+             n_chunks=1 << 16, n_dense=4, reserved2=0, ld_dense=(n_cand + 255) // 256 * 256,
+             n_rot=pb.n_rot, n_pix=pb.n_pix, quat=pb.quat, mask=pb.mask)
+    d.update(kw)
+    plan = emc.Proposal()
+    for f, _ in emc.Proposal._fields_:
+        setattr(plan, f, d.get(f, fake))
+    return plan
+
+
+def test_proposal_plan_must_match_the_problem(lib):
+    """A plan whose sizes are consistent but which was built for another rotation set
+    or detector is refused before any launch (its rotation lists would index outside
+    this problem's slices)."""
+    pb = _pb(grid_n=128, n_pix=16384, n_rot=25000, n_data=100000, precision=1)
+    n = ctypes.c_size_t()
+    good = _consistent_plan(pb)
+    assert lib.emc_proposed_workspace_bytes(ctypes.byref(pb), ctypes.byref(good), ctypes.byref(n)) == emc.EMC_OK
+    v = emc.ProposedView()
+    assert lib.emc_proposed_workspace_view(ctypes.byref(pb), ctypes.byref(good), ctypes.byref(v)) == emc.EMC_OK
+    assert 0 <= v.S < v.G < v.P < v.Ga < v.Pa < n.value
+    a = ctypes.c_void_p(1 << 20)
+    for field, value in (("n_rot", 30000), ("n_rot", 20000), ("n_pix", 8192), ("quat", (1 << 20) + 4096),
+                         ("mask", (1 << 20) + 4096)):
+        bad = _consistent_plan(pb, **{field: value})
+        assert lib.emc_proposed_workspace_bytes(ctypes.byref(pb), ctypes.byref(bad), ctypes.byref(n)) == \
+            emc.EMC_ERR_INVALID_ARG, field
+        assert "another rotation set" in lib.emc_last_error().decode()
+        assert lib.emc_iterate_proposed(ctypes.byref(pb), ctypes.byref(bad), a, a, a, a, a, a, ctypes.c_size_t(1 << 40),
+                                        None, None) == emc.EMC_ERR_INVALID_ARG, field
+        assert lib.emc_proposed_accumulate(ctypes.byref(pb), ctypes.byref(bad), a, a, a, a, 0, 0.98, a, a, a,
+                                           ctypes.c_size_t(1 << 40), None, None) == emc.EMC_ERR_INVALID_ARG, field
+    # a NaN acceptance threshold is refused
+    assert lib.emc_proposed_accumulate(ctypes.byref(pb), ctypes.byref(good), a, a, a, a, 0, float("nan"), a, a, a,
+                                       ctypes.c_size_t(1 << 40), None, None) == emc.EMC_ERR_INVALID_ARG
 
 
 def test_proposal_plan_bytes_config2(lib):

@@ -15,6 +15,9 @@ import pytest
 
 import oracle as O
 from emc_inputs import WORKLOADS, make_inputs
+from oracle import native as ON
+
+N_ORACLE_FRAMES = 48
 
 pytestmark = pytest.mark.gpu
 
@@ -28,8 +31,31 @@ def inputs(gpu_lib):
     return make_inputs(WORKLOADS[2], device="cuda", with_truth=False)
 
 
+@pytest.fixture(scope="module")
+def oracle_columns(inputs):
+    """The FP64 oracle's log-likelihoods over all 25000 rotations (eq. 2.3) and its
+    responsibilities and log-evidence (eq. 2.4) for 48 sampled frames, from the
+    starting model (C expansion of the oracle, a chunk of rotations at a time)."""
+    import time
+
+    import torch
+
+    wl = inputs.wl
+    ks = np.sort(np.random.default_rng(11).choice(wl.n_data, N_ORACLE_FRAMES, replace=False))
+    K = inputs.counts.view(torch.int16)[torch.as_tensor(ks, device="cuda")].to(torch.int32).cpu().numpy()
+    q = np.asarray(inputs.q, np.float32).astype(np.float64)
+    quat = np.asarray(inputs.quat, np.float32).astype(np.float64)
+    model = np.asarray(inputs.model_start, np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    print(f"\n[fullsize] oracle: Q over {wl.n_rot} rotations for {ks.size} frames", flush=True)
+    Q = ON.loglik_all_rotations(model, K, q, inputs.mask, quat, wl.grid_n)
+    P, L = O.responsibilities(Q, inputs.log_w)
+    print(f"[fullsize] oracle done in {time.perf_counter() - t0:.1f} s", flush=True)
+    return dict(ks=ks, Q=Q, P=P, L=L)
+
+
 @pytest.fixture(scope="module", params=list(FORMS))
-def full(request, inputs, gpu_lib):
+def full(request, inputs, oracle_columns, gpu_lib):
     import torch
 
     import bench
@@ -73,6 +99,9 @@ def full(request, inputs, gpu_lib):
     s["P_colsum"] = P[:, :n].double().sum(0).cpu().numpy()
     s["P_pad_max"] = float(P[:, n:].abs().max().item()) if ds > n else 0.0
     s["P_rows"] = P[jt[:8], :n].double()                                                 # [8][n] on device
+    ko = torch.as_tensor(oracle_columns["ks"], device="cuda")
+    s["P_cols"] = P[:, ko].double().cpu().numpy()                                       # [n_rot][48]
+    s["L_cols"] = run.L[ko].cpu().numpy()
     s["L"] = run.L.cpu().numpy()
     s["rho"] = run.rho.cpu().numpy()
     print(f"[fullsize {form}] compress", flush=True)
@@ -159,3 +188,24 @@ def test_fullsize_mstep_gemm_and_grid_identities(full):
     assert np.all(np.isfinite(m))
     assert np.all(m[s["den_pos"]] >= 0)
     np.testing.assert_array_equal(m[~s["den_pos"]], s["model_in"][~s["den_pos"]])
+
+
+def test_fullsize_responsibilities_match_oracle_over_all_rotations(full, oracle_columns):
+    """Sampled frames, every rotation: P (eq. 2.4) and the log-evidence against the
+    FP64 oracle.  FP32 form: P max-abs <= 1e-3.  BF16 form: P is stored rounded to
+    BF16, so the bound is 1e-3 beyond that rounding (2^-9 of the value)."""
+    from gpu_helpers import top1_agreement, top1_strict
+
+    inp, s = full
+    o = oracle_columns
+    err = np.abs(s["P_cols"] - o["P"])
+    excess = float(np.max(err - (2.0 ** -8 * o["P"] if s["form"] == "bf16" else 0.0)))
+    lerr = float(np.max(np.abs(s["L_cols"] - o["L"]) / np.abs(o["L"])))
+    strict, tied = top1_strict(s["P_cols"], o["P"]), top1_agreement(s["P_cols"], o["P"])
+    print(f"\n[fullsize {s['form']}] {o['ks'].size} frames x {o['P'].shape[0]} rotations vs oracle: P max-abs "
+          f"{float(err.max()):.2e} (beyond BF16 storage rounding {excess:.2e}), log-evidence rel {lerr:.2e}, "
+          f"top-1 strict {strict:.3f}, tie-aware {tied:.3f}, oracle max P median {np.median(o['P'].max(0)):.3f}")
+    assert excess <= 1e-3
+    assert lerr <= (1e-5 if s["form"] == "fp32" else 2e-4)
+    if s["form"] == "fp32":
+        assert tied >= 0.99

@@ -71,6 +71,22 @@ def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=30
     rec = torch.empty(1, dtype=torch.float64, device=dev)
     E.emc_iterate_proposed(geo, plan, Ka, m_in, m_out, ll, rec, ws)
     torch.cuda.synchronize()
+    # candidate pairs' log-likelihood sums and responsibilities, read from the workspace
+    from gpu_helpers import candidate_pairs, proposed_pairs_values
+
+    view = E.emc_proposed_workspace_view(geo, plan)
+    pairs = candidate_pairs(buf, plan, nrot)
+    Gv, Pv = proposed_pairs_values(ws, view, pairs)
+    f64 = lambda off, n: ws[off:off + 8 * n].view(torch.float64).cpu().numpy()
+    order = np.concatenate([cand_frames.cpu().numpy(), audit_frames.cpu().numpy()]).astype(np.int64)
+    b_frame = np.empty(ndata)
+    b_frame[order] = f64(view.b, ndata)
+    L_frame = np.empty(ndata)
+    L_frame[order] = f64(view.L, ndata)
+    S_dev = f64(view.S, nrot)
+    na, dsa = plan.n_audit, E.emc_data_stride(plan.n_audit)
+    Pa = ws[view.Pa:view.Pa + 2 * nrot * dsa].view(torch.bfloat16).view(nrot, dsa)[:, :na].double().cpu().numpy() \
+        if na else np.zeros((nrot, 0))
     # oracle: the same candidate sets
     cell_of = C.assign_cells(quat, coarse.astype(np.float64))
     cand = np.zeros((nrot, ndata), bool)
@@ -82,9 +98,11 @@ def _run(seed, N, npx, nrot, ndata, n_cells, k_top, n_audit, qr=None, photons=30
     o = O.iterate_proposed(model, t["counts"], q, t["mask"], quat, t["log_w"], N, cand_a)
     full = O.iterate(model, t["counts"], q, t["mask"], quat, t["log_w"], N)
     recall_ref = O.proposal_recall(full["P"][:, audit], cand[:, audit]).mean() if n_audit else float("nan")
+    j, k = pairs[0], pairs[1]
     return dict(plan=plan, buf=buf, cand_frames=cand_frames.cpu().numpy(), audit_frames=audit_frames.cpu().numpy(),
                 model=m_out.double().cpu().numpy(), loglik=ll.item(), recall=rec.item(),
-                oracle=o, full=full, recall_ref=recall_ref, audit=audit, cell_of=cell_of, lists=lists, geo=geo)
+                oracle=o, full=full, recall_ref=recall_ref, audit=audit, cell_of=cell_of, lists=lists, geo=geo,
+                cand=cand, pair_j=j, pair_k=k, pair_Q=Gv + b_frame[k] - S_dev[j], pair_P=Pv, L_frame=L_frame, Pa=Pa)
 
 
 def _check_restricted(r, ndata, tag):
@@ -103,6 +121,38 @@ def _check_restricted(r, ndata, tag):
     assert abs(r["loglik"] - r["oracle"]["loglik"]) <= 1e-3 * abs(r["oracle"]["loglik"])
     if len(r["audit"]):
         assert abs(r["recall"] - r["recall_ref"]) <= 1e-3, (r["recall"], r["recall_ref"])
+    _check_pairs(r, tag)
+
+
+def _check_pairs(r, tag):
+    """Element by element: every candidate pair's log-likelihood Q_jk = G + b_k - S_j
+    (eq. 2.3) and responsibility (eq. 2.4 restricted to the candidates) against the
+    oracle's, the pair set against the oracle's candidate matrix, and the audited
+    frames' full-search responsibilities and every frame's log-evidence."""
+    o = r["oracle"]
+    j, k = r["pair_j"], r["pair_k"]
+    cf = r["cand_frames"]
+    # the candidate pairs are exactly the oracle's candidate set of the candidate frames
+    assert j.size == int(r["cand"][:, cf].sum())
+    assert np.all(r["cand"][j, k])
+    assert np.unique(j * 10 ** 7 + k).size == j.size
+    Qref = o["Q"][j, k]
+    qscale = np.max(np.abs(o["Q"]), axis=0)[k]
+    qerr = float(np.max(np.abs(r["pair_Q"] - Qref) / qscale)) if j.size else 0.0
+    Pref = o["P"][j, k]
+    perr = np.abs(r["pair_P"] - Pref)
+    pexcess = float(np.max(perr - 2.0 ** -8 * Pref)) if j.size else 0.0
+    Lerr = float(np.max(np.abs(r["L_frame"] - o["L"]) / np.abs(o["L"])))
+    print(f"[proposal {tag}] {j.size} candidate pairs: Q rel err {qerr:.2e}, P max-abs err "
+          f"{float(perr.max()) if j.size else 0.0:.2e} (beyond BF16 rounding {pexcess:.2e}), L rel err {Lerr:.2e}")
+    assert qerr <= 2e-4
+    # P is stored in BF16: its rounding (2^-9 relative) plus 1e-3
+    assert pexcess <= 1e-3
+    assert Lerr <= 2e-4
+    a = r["audit_frames"]
+    if a.size:
+        pa = np.abs(r["Pa"] - o["P"][:, a])
+        assert float(np.max(pa - 2.0 ** -8 * o["P"][:, a])) <= 1e-3
 
 
 @pytest.mark.parametrize("seed,N,npx,nrot,ndata,n_cells,k_top,n_audit",
@@ -200,3 +250,82 @@ def test_cell_topk_and_union_match_numpy(gpu_lib):
                 ref.append(int(c))
         np.testing.assert_array_equal(got[r, :len(ref)], ref)
         assert (got[r, len(ref):] == -1).all()
+
+
+def test_audit_rejects_poor_proposal_and_full_search_replaces_it(gpu_lib):
+    """Random two-cell proposals out of 40 hold far less than 0.98 of the audited
+    frames' posterior mass: the audit rejects the restricted iteration, the full
+    search from the same model replaces its result (equal to the FP64 oracle's full
+    iteration within the BF16 tolerance), and the plan rebuilt from that full
+    posterior proposes the cells of largest posterior mass and passes its audit."""
+    import torch
+
+    from gpu_helpers import geometry, rel_l2, upload_counts
+    from paper_1409_4256_amd import learned
+
+    N, npx, nrot, ndata, n_cells, n_audit = 20, 300, 700, 400, 40, 20
+    t = tiny_problem(9, grid_n=N, n_pix=npx, n_rot=nrot, n_data=ndata, photons=3000.0)
+    q = np.asarray(t["q"], np.float32).astype(np.float64)
+    quat = np.asarray(t["quat"], np.float32).astype(np.float64)
+    rng = np.random.default_rng(109)
+    coarse = np.asarray(shoemake_quaternions(rng, n_cells), np.float32)
+    lists = _lists(rng, ndata, n_cells, 2, 0, False)
+    audit = np.sort(rng.choice(ndata, n_audit, replace=False)).astype(np.int32)
+    geo = geometry(N, q, t["mask"], quat, t["log_w"], ndata, E.EMC_PREC_BF16)
+    dev = "cuda"
+    counts = upload_counts(t["counts"])
+    coarse_d = torch.as_tensor(coarse, device=dev)
+    audit_d = torch.as_tensor(audit, device=dev)
+    print(f"[fallback] N {N} npx {npx} nrot {nrot} ndata {ndata} cells {n_cells}", flush=True)
+    prop = learned.ProposedIteration(geo, counts, coarse_d, n_cells, torch.as_tensor(lists.reshape(-1), device=dev),
+                                     2, audit_d)
+    K = E.frames_tensor(geo)
+    E.emc_pack_frames(geo, counts, K)
+    ws_full = torch.empty(E.emc_workspace_bytes(geo), dtype=torch.uint8, device=dev)
+    P_full = torch.empty(nrot * geo.data_stride, dtype=torch.bfloat16, device=dev)
+    ll_full = torch.empty(1, dtype=torch.float64, device=dev)
+    calls = []
+
+    def full(a, b):
+        calls.append(1)
+        E.emc_iterate(geo, a, K, b, ll_full, P_out=P_full, ws=ws_full)
+
+    m_in = torch.as_tensor(t["model"], dtype=torch.float32, device=dev)
+    m_out = torch.empty_like(m_in)
+    ok = learned.proposed_or_full(prop, full, m_in, m_out)
+    torch.cuda.synchronize()
+    model = m_in.double().cpu().numpy()
+    o = O.iterate(model, t["counts"], q, t["mask"], quat, t["log_w"], N)
+    cell_of = C.assign_cells(quat, coarse.astype(np.float64))
+    cand = np.zeros((nrot, ndata), bool)
+    for k in range(ndata):
+        cand[:, k] = np.isin(cell_of, lists[k][lists[k] >= 0])
+    rec_ref = O.proposal_recall(o["P"][:, audit], cand[:, audit]).mean()
+    err = rel_l2(m_out.double().cpu().numpy(), o["model"])
+    print(f"[fallback] audit recall {prop.recall.item():.4f} (oracle {rec_ref:.4f}), verdict {ok}; "
+          f"model after the full search: rel L2 vs oracle {err:.2e}", flush=True)
+    assert rec_ref < 0.98 and abs(prop.recall.item() - rec_ref) <= 1e-3
+    assert not ok and len(calls) == 1
+    assert err <= 1e-3
+    # the plan rebuilt from the full posterior: the 8 cells of largest mass per frame
+    cells = learned.CellIndex(geo, coarse_d, n_cells)
+    new_lists, kk = learned.proposal_lists(geo, P_full, cells, n_cells, None, 0, 8)
+    nl = new_lists.view(ndata, kk).cpu().numpy()
+    T_ref = np.stack([o["P"][cell_of == c].sum(0) for c in range(n_cells)], axis=1)    # [frame][cell]
+    best = np.sort(T_ref, axis=1)[:, ::-1][:, :8].sum(1)
+    got = np.array([T_ref[f, nl[f][nl[f] >= 0]].sum() for f in range(ndata)])
+    print(f"[fallback] rebuilt lists hold {got.mean():.5f} of the oracle posterior (best 8 cells: "
+          f"{best.mean():.5f})", flush=True)
+    assert np.all(got >= best - 2e-3)
+    prop2 = learned.ProposedIteration(geo, counts, coarse_d, n_cells, new_lists, kk, audit_d)
+    calls.clear()
+    ok2 = learned.proposed_or_full(prop2, full, m_in, m_out)
+    cand2 = np.zeros((nrot, ndata), bool)
+    for k in range(ndata):
+        cand2[:, k] = np.isin(cell_of, nl[k][nl[k] >= 0])
+    rec2 = O.proposal_recall(o["P"][:, audit], cand2[:, audit]).mean()
+    print(f"[fallback] rebuilt plan: audit recall {prop2.recall.item():.5f} (oracle {rec2:.5f}), verdict {ok2}",
+          flush=True)
+    assert abs(prop2.recall.item() - rec2) <= 1e-3
+    assert rec2 >= 0.98 and ok2 and not calls
+

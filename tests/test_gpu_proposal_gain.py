@@ -27,6 +27,90 @@ pytestmark = pytest.mark.gpu
 N_CELLS, K_NET, K_PREV, TRAIN_AT = 2000, 64, 64, 10
 
 
+def ORACLE_FRAMES(wl, n=40):
+    """Frames whose iteration-11 results are checked against the FP64 oracle."""
+    return np.sort(np.random.default_rng(13).choice(wl.n_data, n, replace=False))
+
+
+_dense = {}
+
+
+def oracle_parity(inp, g, m_in, coarse, prop, lists, cells):
+    """Iteration 11 against the FP64 oracle on sampled frames (eq. 2.3, 2.4): the
+    oracle's log-likelihoods over all 25000 rotations from the same input model give
+    the full-search posterior and, restricted to each frame's proposed cells, the
+    learned form's.  Checked: every candidate pair's Q (relative 2e-4 of the frame's
+    max |Q|) and P (1e-3 beyond BF16 rounding), and the most probable rotation of the
+    learned form and of the BF16 full search against the oracle's, strict and
+    tie-aware (>= 99 %)."""
+    import time
+
+    import torch
+
+    import oracle as O
+    from gpu_helpers import candidate_pairs, proposed_pairs_values, top1_agreement, top1_strict
+    from oracle import cnn_oracle as C
+    from oracle import native as ON
+
+    wl = inp.wl
+    ks = ORACLE_FRAMES(wl)
+    audited = set(prop.audit_frames.cpu().numpy().tolist())
+    K = inp.counts.view(torch.int16)[torch.as_tensor(ks, device="cuda")].to(torch.int32).cpu().numpy()
+    q = np.asarray(inp.q, np.float32).astype(np.float64)
+    quat = np.asarray(inp.quat, np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    Q = ON.loglik_all_rotations(m_in.double().cpu().numpy(), K, q, inp.mask, quat, wl.grid_n)
+    P, L = O.responsibilities(Q, inp.log_w)
+    print(f"[gain] oracle Q over {wl.n_rot} rotations for {ks.size} frames in {time.perf_counter() - t0:.1f} s",
+          flush=True)
+    # the plan's cells (the GPU decides them in FP32): the oracle's FP64 assignment agrees
+    # except where two cells are tied to within FP32 resolution
+    cell_of = cells.cell_of.cpu().numpy()
+    qn = quat / np.linalg.norm(quat, axis=1, keepdims=True)
+    cn = coarse.double().cpu().numpy()
+    cn /= np.linalg.norm(cn, axis=1, keepdims=True)
+    dots = np.abs(qn @ cn.T)
+    ref = C.assign_cells(quat, coarse.double().cpu().numpy())
+    off = np.flatnonzero(ref != cell_of)
+    assert np.all(dots[off, ref[off]] - dots[off, cell_of[off]] <= 1e-6), off
+    cand = np.zeros((wl.n_rot, ks.size), bool)
+    for c, k in enumerate(ks):
+        row = lists[k]
+        cand[:, c] = np.isin(cell_of, row[row >= 0]) if k not in audited else True
+    Pr, _ = O.responsibilities_restricted(Q, inp.log_w, cand)
+    # the learned form's pairs of the sampled (candidate) frames, read from its workspace
+    pairs = candidate_pairs(prop.buf, prop.plan, wl.n_rot, frames=ks)
+    Gv, Pv = proposed_pairs_values(prop.ws, prop.view(), pairs)
+    view = prop.view()
+    f64 = lambda off, n: prop.ws[off:off + 8 * n].view(torch.float64).cpu().numpy()
+    order = np.concatenate([prop.cand_frames.cpu().numpy(), prop.audit_frames.cpu().numpy()]).astype(np.int64)
+    b = np.empty(wl.n_data)
+    b[order] = f64(view.b, wl.n_data)
+    S = f64(view.S, wl.n_rot)
+    j, k = pairs[0], pairs[1]
+    col = np.searchsorted(ks, k)
+    qerr = np.abs(Gv + b[k] - S[j] - Q[j, col]) / np.max(np.abs(Q), axis=0)[col]
+    perr = np.abs(Pv - Pr[j, col]) - 2.0 ** -8 * Pr[j, col]
+    n_cand_frames = len([x for x in ks if x not in audited])
+    assert j.size == int(cand[:, [c for c, x in enumerate(ks) if x not in audited]].sum())
+    # the learned form's most probable rotation per sampled candidate frame
+    P_learned = np.zeros((wl.n_rot, ks.size))
+    P_learned[j, col] = Pv
+    sel = np.array([x not in audited for x in ks])
+    strict, tied = top1_strict(P_learned[:, sel], P[:, sel]), top1_agreement(P_learned[:, sel], P[:, sel])
+    d_strict = top1_strict(_dense["P"], P)
+    d_tied = top1_agreement(_dense["P"], P)
+    print(f"[gain] oracle parity, iteration 11, {n_cand_frames} sampled candidate frames ({j.size} pairs): "
+          f"Q rel err {qerr.max():.2e}, restricted P err beyond BF16 rounding {perr.max():.2e}; top-1 vs the "
+          f"oracle's full search: learned form strict {strict:.3f} tie-aware {tied:.3f}, BF16 full search "
+          f"strict {d_strict:.3f} tie-aware {d_tied:.3f} (oracle max P median {np.median(P.max(0)):.3f})",
+          flush=True)
+    assert qerr.max() <= 2e-4
+    assert perr.max() <= 1e-3
+    assert tied >= 0.99 and strict >= 0.99
+    assert d_tied >= 0.99 and d_strict >= 0.99
+
+
 def test_trained_proposal_gain(gpu_lib):
     import torch
 
@@ -74,6 +158,7 @@ def test_trained_proposal_gain(gpu_lib):
     T11 = targets_now().view(wl.n_data, N_CELLS)
     m_full = run.model[run.cur].double()
     best_full = run.P.view(wl.n_rot, -1)[:, :wl.n_data].float().argmax(0)
+    _dense["P"] = run.P.view(wl.n_rot, -1)[:, torch.as_tensor(ORACLE_FRAMES(wl), device="cuda")].double().cpu().numpy()
     r_t = torch.gather(T11, 1, top_t.view(-1, K_NET).long()).sum(1).mean().item()
     r_u = torch.gather(T11, 1, top_u.view(-1, K_NET).long()).sum(1).mean().item()
     del T11
@@ -90,10 +175,12 @@ def test_trained_proposal_gain(gpu_lib):
         prop.step(m_in, out)                                 # iteration 11 with the proposal
         torch.cuda.synchronize()
         err = (torch.linalg.norm(out.double() - m_full) / torch.linalg.norm(m_full)).item()
-        return err, prop.recall.item(), prop.accepted(), prop.candidate_pairs()
+        return err, prop.recall.item(), prop.accepted(), prop.candidate_pairs(), prop
 
-    err, rec, ok, pairs = iterate(union, K_NET + K_PREV)
-    err_p, rec_p, _, pairs_p = iterate(top_prev, K_PREV)
+    err, rec, ok, pairs, prop = iterate(union, K_NET + K_PREV)
+    oracle_parity(inp, g, m_in, coarse, prop, union.view(-1, K_NET + K_PREV).cpu().numpy(), cells)
+    del prop
+    err_p, rec_p, _, pairs_p, _ = iterate(top_prev, K_PREV)
     dense = wl.n_rot * wl.n_data
     print(f"[gain] recall of top-{K_NET}/{N_CELLS} cells: trained {r_t:.4f}, untrained {r_u:.4f}\n"
           f"[gain] learned form: model rel L2 vs full search {err:.2e}, top-1 {top1:.4f}, audit recall {rec:.5f}, "

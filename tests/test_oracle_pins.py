@@ -330,3 +330,61 @@ def test_restricted_estep_is_conditional_posterior():
     rec = O.proposal_recall(P, cand)
     np.testing.assert_allclose(Pr, np.where(cand, P / rec[None, :], 0.0), rtol=1e-12, atol=1e-300)
     np.testing.assert_allclose(Pr.sum(0), 1.0, rtol=1e-14)
+
+
+def test_iterate_proposed_with_every_rotation_a_candidate_is_the_full_iteration():
+    t = tiny_problem(32, grid_n=12, n_pix=60, n_rot=15, n_data=9)
+    a = O.iterate(t["model"], t["counts"], t["q"], t["mask"], t["quat"], t["log_w"], 12)
+    b = O.iterate_proposed(t["model"], t["counts"], t["q"], t["mask"], t["quat"], t["log_w"], 12,
+                           np.ones((15, 9), bool))
+    for key in ("Q", "P", "L", "Wp", "rho", "num", "den", "model"):
+        np.testing.assert_allclose(b[key], a[key], rtol=1e-13, atol=1e-300)
+
+
+def test_iterate_proposed_with_one_candidate_reproduces_the_mean_frame():
+    # every frame's single candidate is the identity rotation (the other rotations are
+    # never proposed): its responsibility is 1, so with a flat detector on integer
+    # voxels the touched voxels hold the mean frame exactly, whatever the other
+    # rotations' likelihoods; the unrestricted posterior would spread the frames
+    N = 10
+    u = np.arange(-3, 4)
+    X, Y = np.meshgrid(u, u, indexing="ij")
+    q = np.stack([X.ravel(), Y.ravel(), np.zeros(X.size)], axis=1).astype(np.float64)
+    mask = np.ones(q.shape[0], np.uint8)
+    mask[7] = 0
+    K = _rng(33).poisson(4.0, size=(11, q.shape[0])).astype(np.float64)
+    quat = np.concatenate([[[1.0, 0, 0, 0]], shoemake_quaternions(_rng(34), 5)])
+    log_w = np.log(np.full(6, 1.0 / 6))
+    cand = np.zeros((6, 11), bool)
+    cand[0] = True
+    model = _rng(35).random(N ** 3) + 0.5
+    r = O.iterate_proposed(model, K, q, mask, quat, log_w, N, cand)
+    np.testing.assert_array_equal(r["P"][1:], 0.0)
+    np.testing.assert_allclose(r["P"][0], 1.0, rtol=1e-15)
+    np.testing.assert_allclose(r["rho"], [11.0, 0, 0, 0, 0, 0])
+    l = ((X.ravel() + 5) * N + (Y.ravel() + 5)) * N + 5
+    v = mask.astype(bool)
+    np.testing.assert_allclose(r["model"][l[v]], K.mean(axis=0)[v], rtol=1e-14)
+    untouched = np.ones(N ** 3, bool)
+    untouched[l[v]] = False
+    np.testing.assert_array_equal(r["model"][untouched], model[untouched])
+    # the same frames searched over every rotation do not give the mean frame
+    full = O.iterate(model, K, q, mask, quat, log_w, N)
+    assert np.max(np.abs(full["model"][l[v]] - K.mean(axis=0)[v])) > 1e-3
+
+
+def test_iterate_proposed_log_evidence_is_over_the_candidates():
+    # L_k = log sum_{j in cand(k)} w_j e^{Q_jk}: restricting can only lower it, and the
+    # reported mean is the mean of those restricted values (eq. 2.1 over the searched set)
+    t = tiny_problem(36, grid_n=12, n_pix=50, n_rot=12, n_data=8)
+    g = _rng(37)
+    cand = g.random((12, 8)) < 0.4
+    cand[g.integers(0, 12, 8), np.arange(8)] = True
+    a = O.iterate(t["model"], t["counts"], t["q"], t["mask"], t["quat"], t["log_w"], 12)
+    b = O.iterate_proposed(t["model"], t["counts"], t["q"], t["mask"], t["quat"], t["log_w"], 12, cand)
+    assert np.all(b["L"] <= a["L"] + 1e-12)
+    for k in range(8):
+        terms = [mpmath.mpf(float(a["Q"][j, k])) + mpmath.mpf(float(t["log_w"][j])) for j in range(12) if cand[j, k]]
+        assert float(b["L"][k]) == pytest.approx(float(mpmath.log(mpmath.fsum(mpmath.exp(x) for x in terms))),
+                                                 rel=1e-13)
+    assert b["loglik"] == pytest.approx(float(np.mean(b["L"])), rel=1e-15)
