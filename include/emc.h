@@ -15,7 +15,8 @@
  * ---------------------------------------
  *  - Every array pointer is DEVICE memory owned by the caller.  The library
  *    never allocates; emc_iterate takes a caller workspace sized by
- *    emc_workspace_bytes.  All work is enqueued asynchronously on `stream`
+ *    emc_workspace_bytes (emc_iterate_noalloc uses a static device buffer of
+ *    the library's own instead).  All work is enqueued asynchronously on `stream`
  *    (no host synchronisation, except emc_pack_frames in BF16 form, which
  *    reads back its range flag).
  *  - Arguments are validated on the host before anything is launched: on a
@@ -263,6 +264,25 @@ emc_status emc_finalize(const emc_problem* pb, const double* num, const double* 
 emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void* K_packed,
                        float* model_out, double* loglik, void* P_out, void* ws,
                        size_t ws_bytes, hipStream_t stream);
+
+/* Allocation-free emc_iterate, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as emc_iterate, without ws:
+ * the workspace is the library's own static device buffer of
+ * EMC_SCRATCH_MAX_BYTES, one per GPU, held from the library's load until the
+ * process ends.  Its address on the current device is looked up on the first
+ * call made with that device current.  The call allocates and frees nothing.
+ *  - Problems whose emc_workspace_bytes exceeds EMC_SCRATCH_MAX_BYTES are
+ *    refused with EMC_ERR_WORKSPACE before anything is launched.
+ *  - Every call on one GPU uses that GPU's single buffer: calls that overlap
+ *    on one GPU (concurrent streams, threads) race and must be serialised by
+ *    the caller.  Nothing in the buffer carries over between calls (every sum
+ *    the iteration needs zeroed is cleared by its own kernels first).
+ * Rotation-major c-step grid copies count towards the workspace; a brick-major
+ * plan (pb->scatter) keeps them out. */
+#define EMC_SCRATCH_MAX_BYTES ((size_t)64 << 20)
+emc_status emc_iterate_noalloc(const emc_problem* pb, const float* model_in, const void* K_packed,
+                               float* model_out, double* loglik, void* P_out, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Gaussian noise model with photon fluence (Section 2.2, the paper's own

@@ -4,6 +4,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -504,14 +505,28 @@ emc_status emc_finalize(const emc_problem* pb, const double* num, const double* 
   return run_finalize(pb, num, den, model_prev, model_out, L, n_L, loglik, st);
 }
 
-emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void* K_packed, float* model_out,
-                       double* loglik, void* P_out, void* ws, size_t ws_bytes, hipStream_t st) {
+}  // extern "C"
+
+namespace {
+
+emc_status check_iterate(const emc_problem* pb, const float* model_in, const void* K_packed, const float* model_out,
+                         const double* loglik, const void* P_out) {
   CHECK(check_problem(pb, true));
   CHECK(need(model_in, 4, "model_in"));
   CHECK(need(model_out, 4, "model_out"));
   CHECK(need(loglik, 8, "loglik"));
   if (pb->n_data > 0) CHECK(need(K_packed, 16, "K_packed"));
   if (P_out) CHECK(need(P_out, 16, "P_out"));
+  return EMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void* K_packed, float* model_out,
+                       double* loglik, void* P_out, void* ws, size_t ws_bytes, hipStream_t st) {
+  CHECK(check_iterate(pb, model_in, K_packed, model_out, loglik, P_out));
   const Layout Lo = layout_of(pb);
   if (!ws) return fail(EMC_ERR_WORKSPACE, "workspace is NULL");
   if (!aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is not 256-byte aligned");
@@ -535,6 +550,52 @@ emc_status emc_iterate(const emc_problem* pb, const float* model_in, const void*
   CHECK(run_compress(pb, P, K_packed, rho, (float*)slices, num, den, 0, (double*)(w + Lo.copies), st));
   CHECK(run_finalize(pb, num, den, model_in, model_out, L, pb->n_data, loglik, st));
   return EMC_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free iteration: the workspace is a static device array ----
+// One array per GPU (each device holds its own copy of a __device__ variable),
+// 64 MiB, kept from module load until the process ends.  Host code never uses the
+// array's name as an address: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and kept here.
+namespace {
+
+static __device__ __align__(256) unsigned char scratch[EMC_SCRATCH_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+emc_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(EMC_ERR_UNSUPPORTED, "device %d beyond %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p || !aligned(p, 256)) return fail(EMC_ERR_HIP, "scratch buffer address %p is not 256-byte aligned", p);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return EMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+emc_status emc_iterate_noalloc(const emc_problem* pb, const float* model_in, const void* K_packed, float* model_out,
+                               double* loglik, void* P_out, hipStream_t st) {
+  CHECK(check_iterate(pb, model_in, K_packed, model_out, loglik, P_out));
+  const size_t need_bytes = layout_of(pb).total;
+  if (need_bytes > EMC_SCRATCH_MAX_BYTES)
+    return fail(EMC_ERR_WORKSPACE, "problem needs %zu bytes of workspace, above the %zu-byte static scratch buffer",
+                need_bytes, (size_t)EMC_SCRATCH_MAX_BYTES);
+  void* ws = nullptr;
+  CHECK(scratch_of_current_device(&ws));
+  return emc_iterate(pb, model_in, K_packed, model_out, loglik, P_out, ws, EMC_SCRATCH_MAX_BYTES, st);
 }
 
 // ---- Gaussian noise model with fluence ----

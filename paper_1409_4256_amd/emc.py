@@ -30,6 +30,7 @@ EMC_RESP_FINALIZE = 2
 EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride", "emc_frames_bytes",
            "emc_slices_bytes", "emc_workspace_bytes", "emc_pack_frames", "emc_expand", "emc_loglik",
            "emc_responsibilities", "emc_compress_workspace_bytes", "emc_compress", "emc_finalize", "emc_iterate",
+           "emc_iterate_noalloc",
            "emc_cnn_param_count", "emc_cnn_workspace_bytes", "emc_cnn_preprocess", "emc_cnn_forward",
            "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_topk", "emc_topk_union",
            "emc_cell_targets",
@@ -128,6 +129,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_finalize.argtypes, lib.emc_finalize.restype = [_PB, _P, _P, _P, _P, _P, i64, _P, _P], st
     lib.emc_iterate.argtypes = [_PB, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
     lib.emc_iterate.restype = st
+    lib.emc_iterate_noalloc.argtypes = [_PB, _P, _P, _P, _P, _P, _P]
+    lib.emc_iterate_noalloc.restype = st
     lib.emc_cnn_param_count.argtypes, lib.emc_cnn_param_count.restype = [i32], i64
     lib.emc_cnn_workspace_bytes.argtypes, lib.emc_cnn_workspace_bytes.restype = [i32, i32, szp], st
     lib.emc_cnn_preprocess.argtypes, lib.emc_cnn_preprocess.restype = [_PB, _P, _P, _P, i32, _P, _P], st
@@ -418,6 +421,22 @@ def emc_iterate(geo: Geometry, model_in, K_packed, model_out, loglik, P_out=None
         _ptr(model_out, torch.float32, M, "model_out"), _ptr(loglik, torch.float64, 1, "loglik"),
         _ptr(P_out, geo.p_dtype, geo.n_rot * geo.data_stride, "P_out", allow_none=True),
         _ptr(ws, torch.uint8, need, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream)))
+
+
+EMC_SCRATCH_MAX_BYTES = 64 << 20    # the static device buffer of emc_iterate_noalloc
+
+
+def emc_iterate_noalloc(geo: Geometry, model_in, K_packed, model_out, loglik, P_out=None, stream=None):
+    """emc_iterate with the library's static device buffer as workspace (no allocation)."""
+    import torch
+
+    n = geo.n_data
+    M = geo.grid_n ** 3
+    _check(load().emc_iterate_noalloc(
+        ctypes.byref(geo.pb), _ptr(model_in, torch.float32, M, "model_in"),
+        _ptr(K_packed, None, None, "K_packed", nbytes=emc_frames_bytes(geo)) if n else None,
+        _ptr(model_out, torch.float32, M, "model_out"), _ptr(loglik, torch.float64, 1, "loglik"),
+        _ptr(P_out, geo.p_dtype, geo.n_rot * geo.data_stride, "P_out", allow_none=True), _stream(stream)))
 
 
 # ------------------------------------------------------------------------- proposal network

@@ -110,6 +110,19 @@ def test_workspace_checks(lib):
     assert st == emc.EMC_ERR_WORKSPACE
 
 
+def test_noalloc_refuses_problems_beyond_its_static_buffer(lib):
+    """emc_iterate_noalloc checks the problem's workspace against its fixed buffer
+    before looking the buffer up or launching anything."""
+    a = ctypes.c_void_p(1 << 20)
+    big = _pb(grid_n=64, n_pix=4096, n_rot=4000, n_data=4000)
+    need = ctypes.c_size_t()
+    assert lib.emc_workspace_bytes(ctypes.byref(big), ctypes.byref(need)) == emc.EMC_OK
+    assert need.value > emc.EMC_SCRATCH_MAX_BYTES
+    assert lib.emc_iterate_noalloc(ctypes.byref(big), a, a, a, a, None, None) == emc.EMC_ERR_WORKSPACE
+    assert b"static scratch" in lib.emc_last_error()
+    assert lib.emc_iterate_noalloc(ctypes.byref(_pb()), None, a, a, a, None, None) == emc.EMC_ERR_INVALID_ARG
+
+
 def test_compress_workspace_checks(lib):
     pb = _pb()
     a = ctypes.c_void_p(1 << 20)
