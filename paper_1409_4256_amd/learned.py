@@ -202,3 +202,73 @@ def proposed_or_full(prop: ProposedIteration, full_step, model_in, model_out, st
         return True
     full_step(model_in, model_out)
     return False
+
+
+class FullSearchChunks:
+    """The full BF16 search over frame chunks of one problem (the fallback of a chunk
+    whose audit rejects its proposal): one expansion per iteration, then for a chunk
+    its frames packed, log-likelihoods, E-step and M/c-step added into num/den."""
+
+    def __init__(self, geo16: E.Geometry, counts_dev, chunk: int):
+        self.geo, self.counts, self.chunk = geo16, counts_dev, int(chunk)
+        dev = "cuda"
+        g = geo16.with_frames(self.chunk)
+        ps, ds, nr = g.pix_stride, g.data_stride, g.n_rot
+        self.frames = torch.arange(geo16.n_data, dtype=torch.int32, device=dev)
+        self.K = E.frames_tensor(g)
+        self.slices = E.slices_tensor(g)
+        self.c = torch.empty(ps, dtype=torch.float64, device=dev)
+        self.S = torch.empty(nr, dtype=torch.float64, device=dev)
+        self.scale = torch.empty(nr, dtype=torch.float32, device=dev)
+        self.G = torch.empty(nr * ds, dtype=torch.float32, device=dev)
+        self.P = torch.empty(nr * ds, dtype=torch.bfloat16, device=dev)
+        self.b = torch.empty(self.chunk, dtype=torch.float64, device=dev)
+        self.stats = torch.empty(2 * self.chunk, dtype=torch.float64, device=dev)
+        self.rho = torch.empty(nr, dtype=torch.float64, device=dev)
+        self.Wp = torch.empty(nr * ps, dtype=torch.float32, device=dev)   # W' apart: the slices serve every chunk
+        self.cws = torch.empty(E.emc_compress_workspace_bytes(g), dtype=torch.uint8, device=dev)
+        self.expanded = None
+
+    def bounds(self, ci: int):
+        s = ci * self.chunk
+        return s, min(self.geo.n_data, s + self.chunk)
+
+    def expand(self, model):
+        E.emc_expand(self.geo, model, self.c, self.slices, self.S, self.scale)
+        self.expanded = model
+
+    def add_chunk(self, ci: int, model, num, den, L, accumulate: bool):
+        """Chunk ci's full search into num/den (zeroed first unless accumulate); its
+        frames' log-evidence into L [chunk frames]; P of the chunk stays in self.P."""
+        if self.expanded is not model:
+            self.expand(model)
+        s, e = self.bounds(ci)
+        g = self.geo.with_frames(e - s)
+        E.emc_pack_frames_list(g, self.counts, self.frames[s:e], self.K)
+        E.emc_loglik(g, self.K, self.slices, self.scale, self.c, self.G, self.b)
+        E.emc_responsibilities(g, self.G, self.S, self.b, E.EMC_RESP_FULL, self.stats, self.P, L, self.rho)
+        E.emc_compress(g, self.P, self.K, self.rho, self.Wp, num, den, accumulate=accumulate, ws=self.cws)
+
+
+def proposed_chunks(chunks, full: FullSearchChunks, model_in, model_out, loglik, L, num, den, make_plan,
+                    recall_min: float = RECALL_MIN):
+    """One iteration over frame chunks, the k-direction split of Section 3.3 applied to the
+    restricted iteration: chunk ci's proposal (plan and audit from make_plan(ci), a
+    ProposedIteration over that chunk's frames) adds its c-step sums into num/den when its
+    audit accepts it; a rejected chunk adds the full search's sums instead.  One division
+    (eq. 2.12) and the mean log-evidence (eq. 2.1) over every frame follow.
+    Returns the audit recall of each chunk and whether it was accepted."""
+    out = []
+    for ci in range(chunks):
+        s, e = full.bounds(ci)
+        prop = make_plan(ci)
+        E.emc_proposed_accumulate(prop.geo, prop.plan, prop.Ka, model_in, num, den, ci > 0, recall_min, L[s:e],
+                                  prop.recall, prop.ws)
+        ok = prop.accepted()          # synchronises: the host decides the redo
+        rec = prop.recall.item()
+        if not ok:                    # the device gate added nothing for this chunk
+            full.add_chunk(ci, model_in, num, den, L[s:e], accumulate=True)
+        out.append((rec, ok))
+        del prop
+    E.emc_finalize(full.geo, num, den, model_in, model_out, L, full.geo.n_data, loglik)
+    return out

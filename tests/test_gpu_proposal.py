@@ -329,3 +329,90 @@ def test_audit_rejects_poor_proposal_and_full_search_replaces_it(gpu_lib):
     assert abs(prop2.recall.item() - rec2) <= 1e-3
     assert rec2 >= 0.98 and ok2 and not calls
 
+
+
+def test_streamed_chunks_with_audit_gate_match_oracle(gpu_lib):
+    """Frame chunks of one restricted iteration (the k-direction split of Section 3.3),
+    each with its own plan and audit, summed into one numerator and denominator before
+    the division: chunks 0 and 2 propose each frame's 8 cells of largest oracle
+    posterior mass and pass their audits; chunk 1 proposes 2 random cells, its audit
+    rejects it, the device gate adds nothing for it and its full search is added
+    instead.  The oracle: the restricted iteration's sums of the accepted chunks plus
+    the full iteration's sums of the rejected one, divided once (eq. 2.4, 2.11-2.12)."""
+    import torch
+
+    from gpu_helpers import geometry, rel_l2, upload_counts
+    from paper_1409_4256_amd import learned
+
+    N, npx, nrot, n_cells, k_top = 20, 300, 700, 40, 8
+    bounds = [(0, 250), (250, 500), (500, 600)]        # ragged last chunk
+    ndata = bounds[-1][1]
+    t = tiny_problem(12, grid_n=N, n_pix=npx, n_rot=nrot, n_data=ndata, photons=3000.0)
+    q = np.asarray(t["q"], np.float32).astype(np.float64)
+    quat = np.asarray(t["quat"], np.float32).astype(np.float64)
+    rng = np.random.default_rng(112)
+    coarse = np.asarray(shoemake_quaternions(rng, n_cells), np.float32)
+    model = np.asarray(t["model"], np.float32).astype(np.float64)
+    full = O.iterate(model, t["counts"], q, t["mask"], quat, t["log_w"], N)
+    cell_of = C.assign_cells(quat, coarse.astype(np.float64))
+    T = np.stack([full["P"][cell_of == c].sum(0) for c in range(n_cells)], axis=1)      # [frame][cell]
+    good = np.argsort(-T, axis=1, kind="stable")[:, :k_top].astype(np.int32)
+    lists = good.copy()
+    lists[250:500] = -1
+    lists[250:500, :2] = _lists(rng, 250, n_cells, 2, 0, False)
+    audits = [np.sort(rng.choice(e - s, 10, replace=False)).astype(np.int32) for s, e in bounds]
+    dev = "cuda"
+    geo = geometry(N, q, t["mask"], quat, t["log_w"], ndata, E.EMC_PREC_BF16)
+    counts = upload_counts(t["counts"])
+    coarse_d = torch.as_tensor(coarse, device=dev)
+    print(f"[streamed proposal] N {N} npx {npx} nrot {nrot} chunks {bounds}", flush=True)
+
+    class Chunks(learned.FullSearchChunks):
+        def bounds(self, ci):
+            return bounds[ci]
+
+    fc = Chunks(geo, counts, 250)
+
+    def make_plan(ci):
+        s, e = bounds[ci]
+        return learned.ProposedIteration(geo.with_frames(e - s), counts[s:e], coarse_d, n_cells,
+                                         torch.as_tensor(lists[s:e].reshape(-1), device=dev), k_top,
+                                         torch.as_tensor(audits[ci], device=dev))
+
+    M = N ** 3
+    num = torch.full((M,), float("nan"), dtype=torch.float64, device=dev)   # the first chunk zeroes them
+    den = torch.full((M,), float("nan"), dtype=torch.float64, device=dev)
+    L = torch.empty(ndata, dtype=torch.float64, device=dev)
+    m_in = torch.as_tensor(t["model"], dtype=torch.float32, device=dev)
+    m_out = torch.empty_like(m_in)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    verdicts = learned.proposed_chunks(len(bounds), fc, m_in, m_out, ll, L, num, den, make_plan)
+    torch.cuda.synchronize()
+    # oracle, chunk by chunk
+    num_o, den_o, L_o, rec_o = np.zeros(M), np.zeros(M), [], []
+    for ci, (s, e) in enumerate(bounds):
+        cand = np.zeros((nrot, e - s), bool)
+        for k in range(e - s):
+            row = lists[s + k]
+            cand[:, k] = np.isin(cell_of, row[row >= 0])
+        rec_o.append(float(O.proposal_recall(full["P"][:, s:e][:, audits[ci]], cand[:, audits[ci]]).mean()))
+        if rec_o[-1] >= learned.RECALL_MIN:
+            cand[:, audits[ci]] = True
+            o = O.iterate_proposed(model, t["counts"][s:e], q, t["mask"], quat, t["log_w"], N, cand)
+        else:
+            o = O.iterate(model, t["counts"][s:e], q, t["mask"], quat, t["log_w"], N)
+        num_o += o["num"]
+        den_o += o["den"]
+        L_o.append(o["L"])
+    m_ref = O.divide(num_o, den_o, model)
+    ll_ref = float(np.concatenate(L_o).mean())
+    err = rel_l2(m_out.double().cpu().numpy(), m_ref)
+    print(f"[streamed proposal] verdicts {verdicts}, oracle recalls {[round(r, 5) for r in rec_o]}; "
+          f"model rel L2 vs oracle {err:.2e}, loglik {ll.item():.6f} (oracle {ll_ref:.6f})", flush=True)
+    assert [ok for _, ok in verdicts] == [True, False, True]
+    assert rec_o[0] >= 0.99 and rec_o[2] >= 0.99 and rec_o[1] < 0.9     # verdicts far from the bar
+    for (rec, _), r in zip(verdicts, rec_o):
+        assert abs(rec - r) <= 1e-3
+    assert err <= 1e-3
+    assert abs(ll.item() - ll_ref) <= 1e-3 * abs(ll_ref)
+    assert torch.isfinite(num).all() and torch.isfinite(den).all()
