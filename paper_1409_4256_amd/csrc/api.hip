@@ -734,8 +734,21 @@ int64_t act_size(int l) {  // floats per sample of activation l (output of conv 
   return (int64_t)kConvCO[l] * oh * oh;
 }
 
+int64_t pix_of(int l) { return (int64_t)(kConvIH[l] / 2) * (kConvIH[l] / 2); }  // output pixels per sample
+
+// split count of layer l's weight-gradient contraction (reduction over the batch's
+// output pixels): about 512 workgroups over its few output tiles
+int wgrad_splits(int l, int B) {
+  const int64_t tiles = ((kConvCO[l] + 127) / 128) * ((kConvCI[l] * 9 + 127) / 128);
+  const int64_t K = (int64_t)B * pix_of(l);
+  int64_t s = 512 / tiles;
+  if (s > K / 256) s = K / 256;
+  return (int)(s < 1 ? 1 : s);
+}
+
+// Activations and their gradients are channel-major over the batch: act[c][n * P + p]
 struct CnnWs {
-  size_t act[4], dact[4], z, dz, total;
+  size_t act[4], dact[4], col[4], dcol, part, flat, dflat, z, dz, total;
 };
 
 CnnWs cnn_ws(int n_cells, int B) {
@@ -746,8 +759,18 @@ CnnWs cnn_ws(int n_cells, int B) {
     o += (size_t)round_up((int64_t)(floats * 4), 256);
     return at;
   };
-  for (int l = 0; l < 4; ++l) W.act[l] = take((size_t)B * act_size(l));
-  for (int l = 0; l < 4; ++l) W.dact[l] = take((size_t)B * act_size(l));
+  size_t dcol = 0, part = 0;
+  for (int l = 0; l < 4; ++l) {
+    W.act[l] = take((size_t)B * act_size(l));
+    W.dact[l] = take((size_t)B * act_size(l));
+    W.col[l] = take((size_t)kConvCI[l] * 9 * B * pix_of(l));
+    if (l > 0) dcol = std::max(dcol, (size_t)kConvCI[l] * 9 * B * pix_of(l));
+    part = std::max(part, (size_t)wgrad_splits(l, B) * kConvCO[l] * kConvCI[l] * 9);
+  }
+  W.dcol = take(dcol);
+  W.part = take(part);
+  W.flat = take((size_t)B * kFlat);
+  W.dflat = take((size_t)B * kFlat);
   W.z = take((size_t)B * n_cells);
   W.dz = take((size_t)B * n_cells);
   W.total = o;
@@ -756,7 +779,7 @@ CnnWs cnn_ws(int n_cells, int B) {
 
 emc_status check_cnn(int32_t n_cells, int32_t B, const void* ws, size_t ws_bytes) {
   if (n_cells < 1 || n_cells > (1 << 20)) return fail(EMC_ERR_INVALID_ARG, "n_cells=%d outside [1, 2^20]", n_cells);
-  if (B < 1) return fail(EMC_ERR_INVALID_ARG, "batch=%d < 1", B);
+  if (B < 1 || B > (1 << 16)) return fail(EMC_ERR_INVALID_ARG, "batch=%d outside [1, 65536]", B);
   if (!ws) return fail(EMC_ERR_WORKSPACE, "workspace is NULL");
   if (!aligned(ws, 256)) return fail(EMC_ERR_WORKSPACE, "workspace is not 256-byte aligned");
   const size_t need_b = cnn_ws(n_cells, B).total;
@@ -764,17 +787,26 @@ emc_status check_cnn(int32_t n_cells, int32_t B, const void* ws, size_t ws_bytes
   return EMC_OK;
 }
 
-// forward into the workspace activations; logits to `z`
+// forward into the workspace activations (and the layers' im2col operands); logits to `z`
 emc_status run_cnn_forward(int n_cells, const float* p, const float* x, int B, float* z, char* w, hipStream_t st) {
   const CnnLayout L = cnn_layout(n_cells);
   const CnnWs W = cnn_ws(n_cells, B);
-  const float* in = x;
+  const float* in = x;  // [1][n][64][64] is channel-major already
   for (int l = 0; l < 4; ++l) {
+    const int64_t M = (int64_t)B * pix_of(l);
+    const int Kc = kConvCI[l] * 9;
+    float* col = (float*)(w + W.col[l]);
     float* out = (float*)(w + W.act[l]);
-    HIP_TRY(launch_conv_fwd(l, in, p + L.w[l], p + L.b[l], out, B, st), "conv forward");
+    HIP_TRY(launch_im2col(in, kConvCI[l], kConvIH[l], M, col, st), "im2col");
+    // out[o][m] = relu(b[o] + sum_kc W[o][kc] col[kc][m])
+    HIP_TRY(launch_gemm_str(true, p + L.w[l], Kc, false, col, M, out, M, kConvCO[l], (int)M, Kc, 1, nullptr,
+                            p + L.b[l], true, st),
+            "conv forward");
     in = out;
   }
-  HIP_TRY(launch_gemm_f32_nt(in, p + L.wf, z, B, n_cells, kFlat, kFlat, kFlat, n_cells, st), "fc forward");
+  float* flat = (float*)(w + W.flat);
+  HIP_TRY(launch_flatten(in, kConvCO[3], (int)pix_of(3), B, flat, true, st), "flatten");
+  HIP_TRY(launch_gemm_f32_nt(flat, p + L.wf, z, B, n_cells, kFlat, kFlat, kFlat, n_cells, st, true), "fc forward");
   HIP_TRY(launch_add_bias(z, p + L.bf, B, n_cells, st), "fc bias");
   return EMC_OK;
 }
@@ -831,18 +863,38 @@ emc_status emc_cnn_gradients(int32_t n_cells, const float* params, const float* 
   CHECK(run_cnn_forward(n_cells, params, x, B, z, w, st));
   HIP_TRY(launch_fill_zero_f64(loss, 1, st), "zero loss");
   HIP_TRY(launch_softmax_xent(z, T, n_cells, B, dz, loss, st), "softmax xent");
-  const float* a3 = (const float*)(w + W.act[3]);
-  // fully connected: dWf[c][m] = sum_b dz[b][c] a3[b][m]; dbf = column sums; da3 = dz Wf
-  HIP_TRY(launch_gemm_small(dz, 1, n_cells, a3, kFlat, 1, grads + L.wf, kFlat, n_cells, kFlat, B, st), "fc dW");
+  const float* flat = (const float*)(w + W.flat);
+  float* dflat = (float*)(w + W.dflat);
+  float* part = (float*)(w + W.part);
+  // fully connected: dWf[c][j] = sum_b dz[b][c] flat[b][j]; dbf = column sums of dz;
+  // dflat[b][j] = sum_c dz[b][c] Wf[c][j]
+  HIP_TRY(launch_gemm_str(false, dz, n_cells, false, flat, kFlat, grads + L.wf, kFlat, n_cells, kFlat, B, 1, nullptr,
+                          nullptr, false, st),
+          "fc dW");
   HIP_TRY(launch_col_sum(dz, B, n_cells, grads + L.bf, st), "fc db");
-  float* d3 = (float*)(w + W.dact[3]);
-  HIP_TRY(launch_gemm_small(dz, n_cells, 1, params + L.wf, kFlat, 1, d3, kFlat, B, kFlat, n_cells, st), "fc dx");
+  HIP_TRY(launch_gemm_str(true, dz, n_cells, false, params + L.wf, kFlat, dflat, kFlat, B, kFlat, n_cells, 1, nullptr,
+                          nullptr, false, st),
+          "fc dx");
+  HIP_TRY(launch_flatten(dflat, kConvCO[3], (int)pix_of(3), B, (float*)(w + W.dact[3]), false, st), "unflatten");
   for (int l = 3; l >= 0; --l) {
+    const int64_t M = (int64_t)B * pix_of(l);
+    const int Kc = kConvCI[l] * 9;
     float* dl = (float*)(w + W.dact[l]);
+    const float* col = (const float*)(w + W.col[l]);
     HIP_TRY(launch_relu_mask(dl, (const float*)(w + W.act[l]), (int64_t)B * act_size(l), st), "relu backward");
-    const float* in = l == 0 ? x : (const float*)(w + W.act[l - 1]);
-    float* din = l == 0 ? nullptr : (float*)(w + W.dact[l - 1]);
-    HIP_TRY(launch_conv_bwd(l, in, params + L.w[l], dl, din, grads + L.w[l], grads + L.b[l], B, st), "conv backward");
+    // dW[o][kc] = sum_m dout[o][m] col[kc][m] (split over m); db[o] = sum_m dout[o][m]
+    HIP_TRY(launch_gemm_str(true, dl, M, true, col, M, grads + L.w[l], Kc, kConvCO[l], Kc, M, wgrad_splits(l, B), part,
+                            nullptr, false, st),
+            "conv weight gradient");
+    HIP_TRY(launch_row_sum(dl, kConvCO[l], M, grads + L.b[l], st), "conv bias gradient");
+    if (l > 0) {
+      // dcol[kc][m] = sum_o W[o][kc] dout[o][m], then summed over the taps that read each input
+      float* dcol = (float*)(w + W.dcol);
+      HIP_TRY(launch_gemm_str(false, params + L.w[l], Kc, false, dl, M, dcol, M, Kc, (int)M, kConvCO[l], 1, nullptr,
+                              nullptr, false, st),
+              "conv data gradient");
+      HIP_TRY(launch_col2im(dcol, kConvCI[l], kConvIH[l], B, (float*)(w + W.dact[l - 1]), st), "col2im");
+    }
   }
   return EMC_OK;
 }

@@ -3,11 +3,15 @@
 //   x = log1p(binned frame) 1x64x64 -> 4 x [conv3x3 s2 p1 + bias + ReLU]
 //   (1->32->64->128->128 channels) -> flatten 2048 -> linear -> n_cells logits
 // Forward, backward (data and weight gradients), soft-target cross entropy,
-// Adam and top-K selection are all kernels here; the fully connected layer
-// uses the FP32 MFMA GEMM forward and a small LDS-tiled GEMM backward.
+// Adam and top-K selection are all kernels here.  Every contraction of the
+// network (the convolutions as im2col products, the linear layer's backward)
+// runs on one strided FP32 MFMA GEMM; the linear layer's forward uses the
+// iteration's FP32 MFMA GEMM.
 #include "emc_device.h"
 
 namespace emc {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int kImg = 64;
 
@@ -33,156 +37,217 @@ __global__ __launch_bounds__(256) void bin_log_kernel(const T* __restrict__ K, i
 }
 
 // --------------------------------------------------------------------- convolutions
-// out[n][o][y][x] = relu(b[o] + sum_{c,dy,dx} w[o][c][dy][dx] in[n][c][2y-1+dy][2x-1+dx])
-template <int CI, int CO, int IH>
-__global__ __launch_bounds__(256) void conv_fwd_kernel(const float* __restrict__ in, const float* __restrict__ w,
-                                                       const float* __restrict__ bias, float* __restrict__ out,
-                                                       int B) {
-  constexpr int OH = IH / 2;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)B * CO * OH * OH) return;
-  const int ox = e % OH, oy = (e / OH) % OH, o = (e / (OH * OH)) % CO;
-  const int64_t n = e / ((int64_t)CO * OH * OH);
-  float acc = bias[o];
-  const float* ib = in + n * CI * IH * IH;
-  const float* wo = w + o * CI * 9;
-  for (int c = 0; c < CI; ++c) {
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy) {
-      const int iy = 2 * oy - 1 + dy;
-      if (iy < 0 || iy >= IH) continue;
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int ix = 2 * ox - 1 + dx;
-        if (ix < 0 || ix >= IH) continue;
-        acc += wo[c * 9 + dy * 3 + dx] * ib[(c * IH + iy) * IH + ix];
-      }
-    }
+// Activations are channel-major ("CNHW"): act[c][m] with m = (n * H + y) * W + x over
+// the batch, so that every convolution pass is one contraction with a long
+// contiguous index:
+//   forward      out[o][m]  = sum_kc W[o][kc] colT[kc][m]          kc = c * 9 + dy * 3 + dx
+//   data grad    dcolT[kc][m] = sum_o W[o][kc] dout[o][m], then summed back over taps (col2im)
+//   weight grad  dW[o][kc] = sum_m dout[o][m] colT[kc][m]           (split over m)
+// where colT[kc][m] = in[c][n][2y - 1 + dy][2x - 1 + dx] (0 outside: stride 2, padding 1).
+// All three run on gemm_str_kernel (FP32 MFMA).
+
+// colT[kc][m] of a stride-2, padding-1 3x3 convolution over in[c][n][IH][IH]
+__global__ void im2col_kernel(const float* __restrict__ in, int CI, int IH, int64_t M, float* __restrict__ colT) {
+  const int OH = IH / 2;
+  const int64_t total = (int64_t)CI * 9 * M;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t m = e % M, kc = e / M;
+    const int c = (int)(kc / 9), t = (int)(kc % 9), dy = t / 3, dx = t % 3;
+    const int x = (int)(m % OH), y = (int)((m / OH) % OH);
+    const int64_t n = m / ((int64_t)OH * OH);
+    const int iy = 2 * y - 1 + dy, ix = 2 * x - 1 + dx;
+    colT[e] = (iy >= 0 && iy < IH && ix >= 0 && ix < IH) ? in[((int64_t)c * (M / ((int64_t)OH * OH)) + n) * IH * IH +
+                                                             (int64_t)iy * IH + ix]
+                                                       : 0.0f;
   }
-  out[e] = fmaxf(acc, 0.0f);
 }
 
-// dIn[n][c][iy][ix] = sum_{o,dy,dx : 2y-1+dy = iy, 2x-1+dx = ix} w[o][c][dy][dx] dOut[n][o][y][x]
-template <int CI, int CO, int IH>
-__global__ __launch_bounds__(256) void conv_bwd_data_kernel(const float* __restrict__ dout,
-                                                            const float* __restrict__ w, float* __restrict__ din,
-                                                            int B) {
-  constexpr int OH = IH / 2;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)B * CI * IH * IH) return;
-  const int ix = e % IH, iy = (e / IH) % IH, c = (e / (IH * IH)) % CI;
-  const int64_t n = e / ((int64_t)CI * IH * IH);
-  float acc = 0.0f;
-  const float* db = dout + n * CO * OH * OH;
-#pragma unroll
-  for (int dy = 0; dy < 3; ++dy) {
-    const int ty = iy + 1 - dy;
-    if (ty < 0 || (ty & 1) || (ty >> 1) >= OH) continue;
-    const int y = ty >> 1;
-#pragma unroll
-    for (int dx = 0; dx < 3; ++dx) {
-      const int tx = ix + 1 - dx;
-      if (tx < 0 || (tx & 1) || (tx >> 1) >= OH) continue;
-      const int xx = tx >> 1;
-      for (int o = 0; o < CO; ++o) acc += w[(o * CI + c) * 9 + dy * 3 + dx] * db[(o * OH + y) * OH + xx];
-    }
-  }
-  din[e] = acc;
-}
-
-// dW[o][c][dy][dx] = sum_{n,y,x} dOut[n][o][y][x] in[n][c][2y-1+dy][2x-1+dx]; one workgroup per (o, c).
-// The workgroup with c == 0 also reduces dBias[o].
-template <int CI, int CO, int IH>
-__global__ __launch_bounds__(256) void conv_bwd_weight_kernel(const float* __restrict__ in,
-                                                              const float* __restrict__ dout,
-                                                              float* __restrict__ dw, float* __restrict__ db, int B) {
-  constexpr int OH = IH / 2;
-  __shared__ float red[10][4];
-  const int o = blockIdx.x / CI, c = blockIdx.x % CI;
-  float acc[10];
-#pragma unroll
-  for (int t = 0; t < 10; ++t) acc[t] = 0.0f;
-  const int64_t total = (int64_t)B * OH * OH;
-  for (int64_t e = threadIdx.x; e < total; e += 256) {
-    const int x = e % OH, y = (e / OH) % OH;
-    const int64_t n = e / (OH * OH);
-    const float g = dout[((n * CO + o) * OH + y) * OH + x];
-    if (g == 0.0f) continue;
-    const float* ib = in + (n * CI + c) * IH * IH;
+// din[c][n][iy][ix] = sum of dcolT[c * 9 + t][m] over the taps t that read (iy, ix)
+__global__ void col2im_kernel(const float* __restrict__ dcolT, int CI, int IH, int64_t nB, float* __restrict__ din) {
+  const int OH = IH / 2;
+  const int64_t M = nB * OH * OH, total = (int64_t)CI * nB * IH * IH;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int ix = (int)(e % IH), iy = (int)((e / IH) % IH);
+    const int64_t n = (e / ((int64_t)IH * IH)) % nB, c = e / ((int64_t)IH * IH * nB);
+    float acc = 0.0f;
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy) {
-      const int iy = 2 * y - 1 + dy;
-      if (iy < 0 || iy >= IH) continue;
+      const int ty = iy + 1 - dy;
+      if (ty < 0 || (ty & 1) || (ty >> 1) >= OH) continue;
 #pragma unroll
       for (int dx = 0; dx < 3; ++dx) {
-        const int ix = 2 * x - 1 + dx;
-        if (ix < 0 || ix >= IH) continue;
-        acc[dy * 3 + dx] += g * ib[iy * IH + ix];
+        const int tx = ix + 1 - dx;
+        if (tx < 0 || (tx & 1) || (tx >> 1) >= OH) continue;
+        acc += dcolT[(c * 9 + dy * 3 + dx) * M + (n * OH + (ty >> 1)) * OH + (tx >> 1)];
       }
     }
-    acc[9] += g;
+    din[e] = acc;
   }
-#pragma unroll
-  for (int t = 0; t < 10; ++t) {
-    float v = wave_sum(acc[t]);
-    if ((threadIdx.x & 63) == 0) red[t][threadIdx.x >> 6] = v;
+}
+
+// flat[b][c * P + p] = act[c][b * P + p] (the linear layer's input, per frame), or back
+__global__ void flatten_kernel(const float* __restrict__ src, int C, int P, int64_t nB, float* __restrict__ dst,
+                               int to_flat) {
+  const int64_t total = (int64_t)C * P * nB;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int p = (int)(e % P);
+    const int64_t b = (e / P) % nB, c = e / ((int64_t)P * nB);  // e indexes act[c][b][p]
+    const int64_t f = b * C * P + c * P + p;
+    if (to_flat)
+      dst[f] = src[e];
+    else
+      dst[e] = src[f];
   }
+}
+
+// row sums: out[r] = sum_m X[r][m] (bias gradients of the convolutions); one workgroup per row
+__global__ __launch_bounds__(256) void row_sum_kernel(const float* __restrict__ X, int64_t cols, float* __restrict__ out) {
+  __shared__ float red[4];
+  const float* row = X + (int64_t)blockIdx.x * cols;
+  float s = 0.0f;
+  for (int64_t m = threadIdx.x; m < cols; m += 256) s += row[m];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x < 9) dw[(o * CI + c) * 9 + threadIdx.x] = (red[threadIdx.x][0] + red[threadIdx.x][1]) +
-                                                          (red[threadIdx.x][2] + red[threadIdx.x][3]);
-  if (threadIdx.x == 9 && c == 0) db[o] = (red[9][0] + red[9][1]) + (red[9][2] + red[9][3]);
+  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// g *= (act > 0)
+// ReLU of the forward pass and of its gradient: g *= (act > 0)
 __global__ void relu_mask_kernel(float* __restrict__ g, const float* __restrict__ act, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
     if (!(act[e] > 0.0f)) g[e] = 0.0f;
+}
+
+// --------------------------------------------------------------------- strided FP32 MFMA GEMM
+// C[m][n] = sum_k A(m, k) B(k, n) for the network's contractions, with
+//   A(m, k) = A[m * lda + k] (AK) or A[k * lda + m];  B(k, n) = B[n * ldb + k] (BK) or B[k * ldb + n],
+// so that transposed operands need no copies.  Workgroup tile 128 x 128 x 16, 4 waves
+// of 64 x 64 from v_mfma_f32_16x16x4_f32, LDS [row][k] double-buffered.  Bounds are
+// checked in m, n and k.  Split reduction: gridDim.z ranges of `kper` k each write
+// their partial product to C + z * c_split (summed by gemm_reduce_kernel); without a
+// split the epilogue adds bias[m] and applies ReLU when asked.
+constexpr int GBM = 128, GBN = 128, GBK = 16, GLK = GBK + 4;
+
+template <bool AK, bool BKC>
+__global__ __launch_bounds__(256) void gemm_str_kernel(const float* __restrict__ A, int64_t lda,
+                                                       const float* __restrict__ B, int64_t ldb, float* __restrict__ C,
+                                                       int64_t ldc, int M, int N, int64_t K, int64_t kper,
+                                                       int64_t c_split, const float* __restrict__ bias, int relu) {
+  __shared__ __attribute__((aligned(16))) float As[2][GBM * GLK];
+  __shared__ __attribute__((aligned(16))) float Bs[2][GBN * GLK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * GBM, n0 = (int64_t)blockIdx.x * GBN;
+  const int64_t kb = (int64_t)blockIdx.z * kper, ke = kb + kper < K ? kb + kper : K;
+  C += (int64_t)blockIdx.z * c_split;
+
+  float ra[8], rb[8];
+  // element u of this thread's share of a 128 x 16 stage: (row, k) inside the tile;
+  // lanes run along the operand's contiguous index
+  auto slot = [&](bool kcontig, int u, int& r, int& c) {
+    const int e = tid + 256 * u;
+    if (kcontig) {
+      r = e >> 4;
+      c = e & 15;
+    } else {
+      r = e & 127;
+      c = e >> 7;
+    }
+  };
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int r, c;
+      slot(AK, u, r, c);
+      const int64_t m = m0 + r, k = k0 + c;
+      ra[u] = (m < M && k < ke) ? (AK ? A[m * lda + k] : A[k * lda + m]) : 0.0f;
+      slot(BKC, u, r, c);
+      const int64_t n = n0 + r, kk = k0 + c;
+      rb[u] = (n < N && kk < ke) ? (BKC ? B[n * ldb + kk] : B[kk * ldb + n]) : 0.0f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int r, c;
+      slot(AK, u, r, c);
+      As[buf][r * GLK + c] = ra[u];
+      slot(BKC, u, r, c);
+      Bs[buf][r * GLK + c] = rb[u];
+    }
+  };
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nk = ke > kb ? (ke - kb + GBK - 1) / GBK : 0;
+  if (nk > 0) {
+    load(kb);
+    store(0);
+  }
+  __syncthreads();
+  const int arow = wm * 64 + (lane & 15), brow = wn * 64 + (lane & 15), kofs = 4 * (lane >> 4);
+  for (int64_t s = 0; s < nk; ++s) {
+    const int buf = (int)(s & 1);
+    if (s + 1 < nk) load(kb + (s + 1) * GBK);
+    f4 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const f4*>(&As[buf][(arow + 16 * i) * GLK + kofs]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const f4*>(&Bs[buf][(brow + 16 * j) * GLK + kofs]);
+    // lane (row, kofs) holds k = kofs .. kofs + 3 of its row in both operands: MFMA t
+    // multiplies the pairs at k = kofs + t (the k order inside the stage is permuted
+    // alike for A and B, which leaves the sum unchanged)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][t], b[j][t], acc[i][j], 0, 0, 0);
+    if (s + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  // lane holds rows 4 (lane / 16) + r, column lane % 16 of each 16 x 16 tile
+  const int64_t rbase = m0 + wm * 64 + 4 * (lane >> 4), cbase = n0 + wn * 64 + (lane & 15);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = rbase + 16 * i + r;
+      if (row >= M) continue;
+      const float bv = bias ? bias[row] : 0.0f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = cbase + 16 * j;
+        if (col >= N) continue;
+        float v = acc[i][j][r] + bv;
+        if (relu) v = fmaxf(v, 0.0f);
+        C[row * ldc + col] = v;
+      }
+    }
+}
+
+// C[m][n] = sum over splits z (in order) of part[z][m][n]
+__global__ void gemm_reduce_kernel(const float* __restrict__ part, int splits, int64_t c_split, int M, int N,
+                                   float* __restrict__ C, int64_t ldc) {
+  const int64_t total = (int64_t)M * N;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t m = e / N, n = e % N;
+    float v = 0.0f;
+    for (int z = 0; z < splits; ++z) v += part[z * c_split + m * ldc + n];
+    C[m * ldc + n] = v;
+  }
 }
 
 // z[b][c] += bias[c]
 __global__ void add_bias_kernel(float* __restrict__ z, const float* __restrict__ bias, int64_t rows, int cols) {
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < rows * cols; e += (int64_t)gridDim.x * 256)
     z[e] += bias[e % cols];
-}
-
-// --------------------------------------------------------------------- small strided GEMM
-// C[m][n] = sum_k A[m*sam + k*sak] B[k*sbk + n*sbn]; 64 x 64 tiles, 4 x 4 per thread.
-__global__ __launch_bounds__(256) void gemm_small_kernel(const float* __restrict__ A, int64_t sam, int64_t sak,
-                                                         const float* __restrict__ B, int64_t sbk, int64_t sbn,
-                                                         float* __restrict__ C, int64_t ldc, int M, int N, int Kd) {
-  __shared__ float As[16][64 + 1], Bs[16][64 + 1];
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < Kd; k0 += 16) {
-    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int kk = e / 64, r = e % 64;
-      const int m = m0 + r, n = n0 + r, k = k0 + kk;
-      As[kk][r] = (m < M && k < Kd) ? A[m * sam + k * sak] : 0.0f;
-      Bs[kk][r] = (n < N && k < Kd) ? B[k * sbk + n * sbn] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
-      if (m < M && n < N) C[m * ldc + n] = acc[i][j];
-    }
 }
 
 // column sums: out[c] = sum_r X[r][c]
@@ -344,55 +409,68 @@ hipError_t launch_bin_log(const void* K, bool bf16, int64_t ps, int n_pix, const
   return hipGetLastError();
 }
 
-#define CONV_LAYERS(X) X(0, 1, 32, 64) X(1, 32, 64, 32) X(2, 64, 128, 16) X(3, 128, 128, 8)
+static inline unsigned grid_of(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return (unsigned)(b > 65536 ? 65536 : (b < 1 ? 1 : b));
+}
 
-hipError_t launch_conv_fwd(int layer, const float* in, const float* w, const float* b, float* out, int B,
-                           hipStream_t st) {
-  switch (layer) {
-#define F(L, CI, CO, IH) \
-  case L:                \
-    conv_fwd_kernel<CI, CO, IH><<<nblk((int64_t)B * CO * (IH / 2) * (IH / 2)), 256, 0, st>>>(in, w, b, out, B); \
-    break;
-    CONV_LAYERS(F)
-#undef F
-    default:
-      return hipErrorInvalidValue;
-  }
+hipError_t launch_im2col(const float* in, int CI, int IH, int64_t M, float* colT, hipStream_t st) {
+  im2col_kernel<<<grid_of((int64_t)CI * 9 * M), 256, 0, st>>>(in, CI, IH, M, colT);
   return hipGetLastError();
 }
 
-hipError_t launch_conv_bwd(int layer, const float* in, const float* w, const float* dout, float* din, float* dw,
-                           float* db, int B, hipStream_t st) {
-  switch (layer) {
-#define F(L, CI, CO, IH)                                                                                   \
-  case L:                                                                                                  \
-    conv_bwd_weight_kernel<CI, CO, IH><<<CO * CI, 256, 0, st>>>(in, dout, dw, db, B);                     \
-    if (din) conv_bwd_data_kernel<CI, CO, IH><<<nblk((int64_t)B * CI * IH * IH), 256, 0, st>>>(dout, w, din, B); \
-    break;
-    CONV_LAYERS(F)
-#undef F
-    default:
-      return hipErrorInvalidValue;
+hipError_t launch_col2im(const float* dcolT, int CI, int IH, int64_t nB, float* din, hipStream_t st) {
+  col2im_kernel<<<grid_of((int64_t)CI * nB * IH * IH), 256, 0, st>>>(dcolT, CI, IH, nB, din);
+  return hipGetLastError();
+}
+
+hipError_t launch_flatten(const float* src, int C, int P, int64_t nB, float* dst, bool to_flat, hipStream_t st) {
+  flatten_kernel<<<grid_of((int64_t)C * P * nB), 256, 0, st>>>(src, C, P, nB, dst, to_flat ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_sum(const float* X, int rows, int64_t cols, float* out, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  row_sum_kernel<<<rows, 256, 0, st>>>(X, cols, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_str(bool a_kcontig, const float* A, int64_t lda, bool b_kcontig, const float* B, int64_t ldb,
+                           float* C, int64_t ldc, int M, int N, int64_t K, int splits, float* part,
+                           const float* bias, bool relu, hipStream_t st) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (splits < 1 || (splits > 1 && (!part || bias || relu))) return hipErrorInvalidValue;
+  const int64_t kper = splits > 1 ? ((K + splits - 1) / splits + GBK - 1) / GBK * GBK : K;
+  const int z = splits > 1 ? (int)((K + kper - 1) / kper) : 1;
+  dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), (unsigned)z);
+  float* out = z > 1 ? part : C;
+  const int64_t c_split = z > 1 ? (int64_t)M * ldc : 0;
+#define G(AK, BKC) gemm_str_kernel<AK, BKC><<<grid, 256, 0, st>>>(A, lda, B, ldb, out, ldc, M, N, K, kper, c_split, \
+                                                                 bias, relu ? 1 : 0)
+  if (a_kcontig && b_kcontig)
+    G(true, true);
+  else if (a_kcontig)
+    G(true, false);
+  else if (b_kcontig)
+    G(false, true);
+  else
+    G(false, false);
+#undef G
+  if (z > 1) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    gemm_reduce_kernel<<<grid_of((int64_t)M * N), 256, 0, st>>>(part, z, c_split, M, N, C, ldc);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_relu_mask(float* g, const float* act, int64_t n, hipStream_t st) {
-  int64_t blocks = (n + 255) / 256;
-  relu_mask_kernel<<<(unsigned)(blocks > 65536 ? 65536 : blocks), 256, 0, st>>>(g, act, n);
+  relu_mask_kernel<<<grid_of(n), 256, 0, st>>>(g, act, n);
   return hipGetLastError();
 }
 
 hipError_t launch_add_bias(float* z, const float* bias, int64_t rows, int cols, hipStream_t st) {
-  int64_t blocks = (rows * cols + 255) / 256;
-  add_bias_kernel<<<(unsigned)(blocks > 65536 ? 65536 : blocks), 256, 0, st>>>(z, bias, rows, cols);
-  return hipGetLastError();
-}
-
-hipError_t launch_gemm_small(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn,
-                             float* C, int64_t ldc, int M, int N, int Kd, hipStream_t st) {
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((M + 63) / 64));
-  gemm_small_kernel<<<grid, 256, 0, st>>>(A, sam, sak, B, sbk, sbn, C, ldc, M, N, Kd);
+  add_bias_kernel<<<grid_of(rows * cols), 256, 0, st>>>(z, bias, rows, cols);
   return hipGetLastError();
 }
 

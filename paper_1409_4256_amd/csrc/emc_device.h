@@ -91,7 +91,7 @@ hipError_t launch_frame_dot(const void* K, bool bf16, int64_t stride, int64_t n_
 // C[M][N] = sum_k A[m][k] B[n][k] (both operands contiguous along k), FP32 MFMA;
 // Kd must be a multiple of 32; rows m >= M and n >= N read as zero.
 hipError_t launch_gemm_f32_nt(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
-                              int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st);
+                              int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st, bool network = false);
 // BF16 MFMA, FP32 accumulation; Kd multiple of 32.  DUAL: C = row_scale[m] * (A_hi + A_lo) B^T.
 hipError_t launch_gemm_bf16_dual_nt(const void* A_hi, const void* A_lo, const void* B, const float* row_scale,
                                     float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda, int64_t ldb, int64_t ldc,
@@ -146,14 +146,15 @@ hipError_t launch_mean(const double* L, int64_t n, double* out, hipStream_t st);
 // ---- proposal network (cnn.hip) ----
 hipError_t launch_bin_log(const void* K, bool bf16, int64_t ps, int n_pix, const int32_t* bins, const int32_t* frames,
                           int B, float* x, hipStream_t st);
-hipError_t launch_conv_fwd(int layer, const float* in, const float* w, const float* b, float* out, int B,
-                           hipStream_t st);
-hipError_t launch_conv_bwd(int layer, const float* in, const float* w, const float* dout, float* din, float* dw,
-                           float* db, int B, hipStream_t st);
+hipError_t launch_im2col(const float* in, int CI, int IH, int64_t M, float* colT, hipStream_t st);
+hipError_t launch_col2im(const float* dcolT, int CI, int IH, int64_t nB, float* din, hipStream_t st);
+hipError_t launch_flatten(const float* src, int C, int P, int64_t nB, float* dst, bool to_flat, hipStream_t st);
+hipError_t launch_row_sum(const float* X, int rows, int64_t cols, float* out, hipStream_t st);
+hipError_t launch_gemm_str(bool a_kcontig, const float* A, int64_t lda, bool b_kcontig, const float* B, int64_t ldb,
+                           float* C, int64_t ldc, int M, int N, int64_t K, int splits, float* part,
+                           const float* bias, bool relu, hipStream_t st);
 hipError_t launch_relu_mask(float* g, const float* act, int64_t n, hipStream_t st);
 hipError_t launch_add_bias(float* z, const float* bias, int64_t rows, int cols, hipStream_t st);
-hipError_t launch_gemm_small(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn,
-                             float* C, int64_t ldc, int M, int N, int Kd, hipStream_t st);
 hipError_t launch_col_sum(const float* X, int rows, int cols, float* out, hipStream_t st);
 hipError_t launch_softmax_xent(const float* z, const float* T, int n_cells, int B, float* dz, double* loss,
                                hipStream_t st);

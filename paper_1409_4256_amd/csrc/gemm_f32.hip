@@ -15,17 +15,25 @@ namespace emc {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 256, BN = 128, BK = 32, LDK = BK + 4;
+constexpr int BM = 256, BK = 32, LDK = BK + 4;
 constexpr int GROUP_M = 8;  // M tiles per schedule group: blocks sharing an M tile land on one XCD
 
-__global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__ A, const float* __restrict__ B,
-                                                       float* __restrict__ C, int64_t M, int64_t N, int64_t Kd,
-                                                       int64_t lda, int64_t ldb, int64_t ldc) {
+// USE only names the instantiation (0: the iteration's contractions, 1: the proposal
+// network's linear layer), so that kernel traces list the two apart.  NWN: waves
+// along N; the workgroup has 2 x NWN waves of 128 x 64 and a tile BM x 64 NWN.
+template <int USE, int NWN>
+__global__ __launch_bounds__(128 * NWN) void gemm_f32_kernel(const float* __restrict__ A, const float* __restrict__ B,
+                                                              float* __restrict__ C, int64_t M, int64_t N, int64_t Kd,
+                                                              int64_t lda, int64_t ldb, int64_t ldc) {
+  constexpr int BN = 64 * NWN, NT = 128 * NWN;
+  constexpr int LA = BM * BK / 4 / NT, LB = BN * BK / 4 / NT;  // 16-byte loads per thread and stage
+  // two waves per SIMD (NWN = 4) fit their 256 registers only with one 16-deep k step live
+  constexpr int KU = NWN == 2 ? 2 : 1;
   __shared__ __attribute__((aligned(16))) float As[2][BM * LDK];
   __shared__ __attribute__((aligned(16))) float Bs[2][BN * LDK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / NWN, wn = wave % NWN;
 
   // grouped tile order: GROUP_M consecutive M tiles sweep all N tiles together
   const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
@@ -37,19 +45,19 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
   const int64_t tn = (pid % group) / gm;
   const int64_t m0 = tm * BM, n0 = tn * BN;
 
-  f4 ra[8], rb[4];
+  f4 ra[LA], rb[LB];
   const f4 zero = {0.f, 0.f, 0.f, 0.f};
 
   auto load_stage = [&](int64_t k0) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
+    for (int u = 0; u < LA; ++u) {
+      const int f = tid + NT * u, r = f >> 3, c4 = f & 7;
       const int64_t row = m0 + r;
       ra[u] = row < M ? *reinterpret_cast<const f4*>(A + row * lda + k0 + 4 * c4) : zero;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
+    for (int u = 0; u < LB; ++u) {
+      const int f = tid + NT * u, r = f >> 3, c4 = f & 7;
       const int64_t row = n0 + r;
       rb[u] = row < N ? *reinterpret_cast<const f4*>(B + row * ldb + k0 + 4 * c4) : zero;
     }
@@ -59,13 +67,13 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
     float* as = As[buf];
     float* bs = Bs[buf];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
+    for (int u = 0; u < LA; ++u) {
+      const int f = tid + NT * u, r = f >> 3, c4 = f & 7;
       *reinterpret_cast<f4*>(as + r * LDK + 4 * c4) = ra[u];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int f = tid + 256 * u, r = f >> 3, c4 = f & 7;
+    for (int u = 0; u < LB; ++u) {
+      const int f = tid + NT * u, r = f >> 3, c4 = f & 7;
       *reinterpret_cast<f4*>(bs + r * LDK + 4 * c4) = rb[u];
     }
   };
@@ -87,7 +95,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
     if (s + 1 < nk) load_stage((s + 1) * BK);
     const float* as = As[buf] + arow * LDK + kofs;
     const float* bs = Bs[buf] + brow * LDK + kofs;
-#pragma unroll
+#pragma unroll KU
     for (int kk = 0; kk < BK; kk += 16) {
       f4 a[8], b[4];
 #pragma unroll
@@ -123,12 +131,22 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(const float* __restrict__
     }
 }
 
-hipError_t launch_gemm_f32_nt(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
-                              int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
-  gemm_f32_kernel<<<(unsigned)tiles, 256, 0, st>>>(A, B, C, M, N, Kd, lda, ldb, ldc);
+template <int USE, int NWN>
+hipError_t launch_nt(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd, int64_t lda,
+                     int64_t ldb, int64_t ldc, hipStream_t st) {
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + 64 * NWN - 1) / (64 * NWN));
+  gemm_f32_kernel<USE, NWN><<<(unsigned)tiles, 128 * NWN, 0, st>>>(A, B, C, M, N, Kd, lda, ldb, ldc);
   return hipGetLastError();
+}
+
+int g_f32_nwn = 4;   // waves along N of the iteration's GEMM (2 or 4)
+
+hipError_t launch_gemm_f32_nt(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
+                              int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st, bool network) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (network) return launch_nt<1, 2>(A, B, C, M, N, Kd, lda, ldb, ldc, st);
+  if (g_f32_nwn == 2) return launch_nt<0, 2>(A, B, C, M, N, Kd, lda, ldb, ldc, st);
+  return launch_nt<0, 4>(A, B, C, M, N, Kd, lda, ldb, ldc, st);
 }
 
 }  // namespace emc

@@ -80,14 +80,17 @@ class Network:
 
     def train(self, x: torch.Tensor, targets: list, frames_per_set: int, epochs: int, lr: float,
               rng: np.random.Generator) -> TrainLog:
-        """Adam on minibatches of (frame image, cell target) pairs drawn from every target set."""
+        """Adam on minibatches of (frame image, cell target) pairs drawn from every target
+        set (the minibatches are gathered on the device; nothing waits for the GPU
+        between steps)."""
         import time
 
         B, nc = self.batch, self.n_cells
         n_sets = len(targets)
         total = n_sets * frames_per_set
-        xb = torch.empty(B * 4096, dtype=torch.float32, device="cuda")
-        tb = torch.empty(B * nc, dtype=torch.float32, device="cuda")
+        T_all = torch.cat([t.view(-1, nc) for t in targets])      # [set * frames + frame][cell]
+        xb = torch.empty(B, 4096, dtype=torch.float32, device="cuda")
+        tb = torch.empty(B, nc, dtype=torch.float32, device="cuda")
         loss = torch.empty(1, dtype=torch.float64, device="cuda")
         first = last = float("nan")
         t0 = time.perf_counter()
@@ -97,21 +100,17 @@ class Network:
             perm = torch.as_tensor(rng.permutation(total), device="cuda")
             for s in range(0, total - B + 1, B):
                 idx = perm[s:s + B]
-                fr = idx % frames_per_set
-                st = idx // frames_per_set
-                xb.view(B, 4096).copy_(x2[fr])
-                for si in range(n_sets):
-                    sel = st == si
-                    if bool(sel.any()):
-                        tb.view(B, nc)[sel] = targets[si].view(-1, nc)[fr[sel]]
+                torch.index_select(x2, 0, idx % frames_per_set, out=xb)
+                torch.index_select(T_all, 0, idx, out=tb)
                 E.emc_cnn_gradients(nc, self.params, xb, tb, B, self.grads, loss, self.ws)
                 self.step += 1
                 E.emc_cnn_adam(nc, self.params, self.grads, self.m, self.v, self.step, lr)
                 steps += 1
                 if steps == 1:
                     first = loss.item()
-            last = loss.item()
+        last = loss.item()
         torch.cuda.synchronize()
+        del T_all
         return TrainLog(steps, epochs, first, last, time.perf_counter() - t0)
 
     def topk(self, x: torch.Tensor, n_frames: int, k: int) -> torch.Tensor:

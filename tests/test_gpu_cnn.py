@@ -83,6 +83,40 @@ def test_cnn_gradients_match_oracle(setup):
         assert _rel(gg[k], gr[k]) <= 1e-4, (k, _rel(gg[k], gr[k]))
 
 
+@pytest.mark.parametrize("B", [40, 70])
+def test_cnn_gradients_match_oracle_larger_batches(gpu_lib, B):
+    """Batches that split every weight-gradient reduction over several ranges and
+    leave ragged output tiles in the contractions, against the FP64 oracle's
+    gradients."""
+    import torch
+
+    emc = gpu_lib
+    n_cells = 150
+    rng = np.random.default_rng(21 + B)
+    p = C.init_params(rng, n_cells)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.05
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    x = np.log1p(rng.poisson(1.0, size=(B, 1, 64, 64))).astype(np.float32).astype(np.float64)
+    T = rng.dirichlet(np.ones(n_cells) * 0.3, size=B).astype(np.float32).astype(np.float64)
+    dp = torch.as_tensor(_flat(p, n_cells), dtype=torch.float32, device="cuda")
+    ws = torch.empty(emc.emc_cnn_workspace_bytes(n_cells, B), dtype=torch.uint8, device="cuda")
+    g = torch.empty_like(dp)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    emc.emc_cnn_gradients(n_cells, dp, torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous(),
+                          torch.as_tensor(T, dtype=torch.float32, device="cuda").contiguous(), B, g, loss, ws)
+    z, acts = C.forward(p, x)
+    gr = C.backward(p, acts, z, T)
+    gg = _unflat(g.double().cpu().numpy(), n_cells)
+    errs = {k: _rel(gg[k], gr[k]) for k in gr}
+    print(f"\n[cnn B={B}] loss {loss.item():.6f} (oracle {C.loss(z, T):.6f}); gradient rel errors "
+          + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+    assert abs(loss.item() - C.loss(z, T)) <= 1e-5 * abs(C.loss(z, T))
+    for k, e in errs.items():
+        assert e <= 1e-4, (k, e)
+
+
 def test_cnn_adam_matches_oracle(setup):
     import torch
 
