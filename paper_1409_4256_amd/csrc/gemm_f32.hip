@@ -3,8 +3,10 @@
 //   log-likelihood  G_jk  = sum_i logW_ji K_ki    (reduction over pixels)
 //   M-step          W'_ji = sum_k P_jk KT_ik      (reduction over frames)
 //
-// Workgroup tile 256 x 128 x 32 (M x N x K), 4 waves in a 2 x 2 arrangement,
-// each wave 128 x 64 built from 8 x 4 v_mfma_f32_16x16x4_f32 tiles.  Operands
+// Workgroup tile 256 x 256 x 32 (M x N x K), 8 waves in a 2 x 4 arrangement (two
+// per SIMD, so that one issues MFMAs while the other waits at the stage barrier or
+// on LDS), each wave 128 x 64 built from 8 x 4 v_mfma_f32_16x16x4_f32 tiles
+// (the proposal network's small products: 256 x 128 with 4 waves).  Operands
 // are staged through double-buffered LDS laid out [row][k] with a 4-float pad;
 // every lane reads 4 consecutive k of one row with a single 128-bit LDS read
 // and feeds them to 4 successive MFMAs (the k order inside a 16-wide chunk is
@@ -139,13 +141,11 @@ hipError_t launch_nt(const float* A, const float* B, float* C, int64_t M, int64_
   return hipGetLastError();
 }
 
-int g_f32_nwn = 4;   // waves along N of the iteration's GEMM (2 or 4)
-
 hipError_t launch_gemm_f32_nt(const float* A, const float* B, float* C, int64_t M, int64_t N, int64_t Kd,
                               int64_t lda, int64_t ldb, int64_t ldc, hipStream_t st, bool network) {
   if (M <= 0 || N <= 0) return hipSuccess;
+  // the network's linear layer (few output tiles) keeps 256 x 128 tiles
   if (network) return launch_nt<1, 2>(A, B, C, M, N, Kd, lda, ldb, ldc, st);
-  if (g_f32_nwn == 2) return launch_nt<0, 2>(A, B, C, M, N, Kd, lda, ldb, ldc, st);
   return launch_nt<0, 4>(A, B, C, M, N, Kd, lda, ldb, ldc, st);
 }
 
