@@ -200,7 +200,8 @@ def time_form(run, args, n_valid):
     peak = PEAK_BF16_MFMA_TFLOPS if g.bf16 else PEAK_FP32_MFMA_TFLOPS
     achieved = terms * contraction / t_gemm / 1e12
     kern = "gemm_bf16_kernel<DUAL> (hi+lo log-likelihood)" if g.bf16 else "gemm_f32_kernel (log-likelihood)"
-    sym = "emc::gemm_bf16_kernel<true, 8>" if g.bf16 else "emc::gemm_f32_kernel<0>"
+    sym = ("emc::gemm_bf16_kernel<true, 8> (log-likelihood, full size)" if g.bf16
+           else "emc::gemm_f32_kernel<0, 4> (log-likelihood)")
     return {
         "value": round(1000.0 / ms, 5),
         "ms_per_step": round(ms, 3),
@@ -212,9 +213,32 @@ def time_form(run, args, n_valid):
                      "traffic": hbm_traffic(sym),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "algorithmic_flops_per_launch": terms * contraction},
+        "hbm_stages": hbm_stages(wl, g, per),
         "iteration_tflops_algorithmic": round((terms + 1) * contraction / (ms / 1e3) / 1e12, 2),
         "paper_flop_model_tflops": round(27.0 * wl.n_rot * wl.n_data * wl.n_pix / (ms / 1e3) / 1e12, 2),
     }
+
+
+def hbm_stages(wl, g, per):
+    """Achieved bandwidth of the memory-bound steps: bytes each step must move (below)
+    over its median duration, against the 8 TB/s HBM peak.
+      expand: the slices written (log W - c, FP32 or hi + lo BF16: 4 bytes per rotation
+              and padded pixel), the model read once;
+      E-step: G read twice (the statistics pass and the write pass) and P written once
+              (FP32 or BF16), the per-frame and per-rotation vectors."""
+    import numpy as np
+
+    ps, ds = g.pix_stride, g.data_stride
+    nrot, n = wl.n_rot, wl.n_data
+    p_bytes = 2 if g.bf16 else 4
+    moved = {"expand": nrot * ps * 4 + 4 * wl.grid_n ** 3 + 12 * nrot,
+             "estep": 2 * nrot * ds * 4 + nrot * ds * p_bytes + 8 * (4 * n + 2 * nrot)}
+    out = {}
+    for stage, b in moved.items():
+        t = float(np.median(per[stage])) / 1e3
+        out[stage] = {"bytes": int(b), "ms": round(t * 1e3, 3), "achieved_GBs": round(b / t / 1e9, 1),
+                      "peak_GBs": PEAK_HBM_GBS, "frac": round(b / t / 1e9 / PEAK_HBM_GBS, 4)}
+    return out
 
 
 def gaussian_form(run, args, n_valid, sigma=2.0):
