@@ -117,10 +117,11 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
   const bool has = lane < nf;
   const int32_t fidx = has ? cf_frame[cf_ptr[c] + f0 + lane] : 0;
   const int2* rng = band_range + fidx;
-  // rows of the A operand: rotation (lane & 15) of each 16-row tile, -1 reads zero
+  // rows of the A operand: rotation (lane & 15) of each 16-row tile; rows past the
+  // group read its last rotation again (their sums are multiplied by a zero scale)
   const int m = lane & 15, kq = 8 * (lane >> 4);
-  const int64_t ar0 = m < nr ? (int64_t)cell_rot[r0 + m] * ps : -1;
-  const int64_t ar1 = 16 + m < nr ? (int64_t)cell_rot[r0 + 16 + m] * ps : -1;
+  const int64_t ar0 = (int64_t)cell_rot[r0 + (m < nr ? m : nr - 1)] * ps;
+  const int64_t ar1 = (int64_t)cell_rot[r0 + (16 + m < nr ? 16 + m : nr - 1)] * ps;
   const bool two = nr > 16;
 
   uint16_t* rows = lds + wave * kFT * kLRow;
@@ -142,26 +143,30 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
 #pragma unroll
   for (int u = 0; u < kWin; ++u) w0[u] = r0c.x + u < r0c.y ? load_chunk<false>(fb + r0c.x + u) : pad;
   if (has && 1 < nbands) r1c = rng[n_list];
-  // A fragments (slice rows, hi and lo, both row tiles) of a band, 4 k-steps
+  // A fragments (slice rows, hi and lo, both row tiles) of a band, 4 k-steps; the
+  // second row tile only when the group has one (uniform)
   auto load_a = [&](int band, u4 (&h)[4][2], u4 (&l)[4][2]) {
+    const int64_t kb = (int64_t)(band < nbands ? band : nbands - 1) * kBand + kq;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int64_t ko = (int64_t)band * kBand + 32 * kk + kq;
-      const bool in = band < nbands;
-      h[kk][0] = in && ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + ar0 + ko) : zero;
-      l[kk][0] = in && ar0 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar0 + ko) : zero;
-      h[kk][1] = in && ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + ar1 + ko) : zero;
-      l[kk][1] = in && ar1 >= 0 ? *reinterpret_cast<const u4*>(hi + plane + ar1 + ko) : zero;
+      h[kk][0] = *reinterpret_cast<const u4*>(hi + ar0 + kb + 32 * kk);
+      l[kk][0] = *reinterpret_cast<const u4*>(hi + plane + ar0 + kb + 32 * kk);
+    }
+    if (two) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        h[kk][1] = *reinterpret_cast<const u4*>(hi + ar1 + kb + 32 * kk);
+        l[kk][1] = *reinterpret_cast<const u4*>(hi + plane + ar1 + kb + 32 * kk);
+      }
     }
   };
   u4 ah[4][2], al[4][2];
   load_a(0, ah, al);
   for (int band = 0; band < nbands; ++band) {
-    // prefetch (all issued before this band's data is waited on; loads complete in
-    // issue order): the next band's A fragments and chunks, the table entry of the
-    // band after
-    u4 ahn[4][2], aln[4][2];
-    load_a(band + 1, ahn, aln);
+    // prefetch (issued before this band's data is waited on; loads complete in issue
+    // order): the next band's chunks and the table entry of the band after; the next
+    // band's A fragments are loaded into the same registers once this band's MFMAs
+    // have been issued
     u4 w1[kWin];
 #pragma unroll
     for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? load_chunk<false>(fb + r1c.x + u) : pad;
@@ -206,15 +211,9 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
         for (int e = 0; e < kLRow / 8; ++e) reinterpret_cast<u4*>(frow)[e] = zero;
       }
     }
+    load_a(band + 1, ah, al);
 #pragma unroll
     for (int u = 0; u < kWin; ++u) w0[u] = w1[u];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        ah[kk][t] = ahn[kk][t];
-        al[kk][t] = aln[kk][t];
-      }
     r0c = r1c;
     r1c = r2c;
   }
