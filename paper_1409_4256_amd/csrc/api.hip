@@ -736,20 +736,16 @@ int64_t act_size(int l) {  // floats per sample of activation l (output of conv 
 
 int64_t pix_of(int l) { return (int64_t)(kConvIH[l] / 2) * (kConvIH[l] / 2); }  // output pixels per sample
 
-// split count of layer l's weight-gradient contraction (reduction over the batch's
-// output pixels): about 512 workgroups over its few output tiles
-int wgrad_splits(int l, int B) {
-  const int64_t tiles = ((kConvCO[l] + 127) / 128) * ((kConvCI[l] * 9 + 127) / 128);
-  const int64_t K = (int64_t)B * pix_of(l);
-  int64_t s = 512 / tiles;
-  if (s > K / 256) s = K / 256;
-  return (int)(s < 1 ? 1 : s);
-}
-
 // Activations and their gradients are channel-major over the batch: act[c][n * P + p]
 struct CnnWs {
-  size_t act[4], dact[4], col[4], dcol, part, flat, dflat, z, dz, total;
+  size_t act[4], dact[4], col[4], dcol, part, rpart, flat, dflat, z, dz, total;
 };
+
+// floats of split partial products a contraction of M x N over K needs (0 when unsplit)
+size_t split_floats(int M, int N, int64_t K) {
+  const int s = gemm_str_splits(M, N, K);
+  return s > 1 ? (size_t)s * M * N : 0;
+}
 
 CnnWs cnn_ws(int n_cells, int B) {
   CnnWs W;
@@ -761,14 +757,20 @@ CnnWs cnn_ws(int n_cells, int B) {
   };
   size_t dcol = 0, part = 0;
   for (int l = 0; l < 4; ++l) {
+    const int64_t M = (int64_t)B * pix_of(l);
+    const int Kc = kConvCI[l] * 9;
     W.act[l] = take((size_t)B * act_size(l));
     W.dact[l] = take((size_t)B * act_size(l));
-    W.col[l] = take((size_t)kConvCI[l] * 9 * B * pix_of(l));
-    if (l > 0) dcol = std::max(dcol, (size_t)kConvCI[l] * 9 * B * pix_of(l));
-    part = std::max(part, (size_t)wgrad_splits(l, B) * kConvCO[l] * kConvCI[l] * 9);
+    W.col[l] = take((size_t)Kc * M);
+    if (l > 0) dcol = std::max(dcol, (size_t)Kc * M);
+    part = std::max({part, split_floats(kConvCO[l], (int)M, Kc), split_floats(kConvCO[l], Kc, M),
+                     split_floats(Kc, (int)M, kConvCO[l])});
   }
+  part = std::max({part, split_floats(B, n_cells, kFlat), split_floats(n_cells, kFlat, B),
+                   split_floats(B, kFlat, n_cells)});
   W.dcol = take(dcol);
   W.part = take(part);
+  W.rpart = take((size_t)128 * 64);  // row sums: rows (channels) x 64 parts
   W.flat = take((size_t)B * kFlat);
   W.dflat = take((size_t)B * kFlat);
   W.z = take((size_t)B * n_cells);
@@ -799,14 +801,17 @@ emc_status run_cnn_forward(int n_cells, const float* p, const float* x, int B, f
     float* out = (float*)(w + W.act[l]);
     HIP_TRY(launch_im2col(in, kConvCI[l], kConvIH[l], M, col, st), "im2col");
     // out[o][m] = relu(b[o] + sum_kc W[o][kc] col[kc][m])
-    HIP_TRY(launch_gemm_str(true, p + L.w[l], Kc, false, col, M, out, M, kConvCO[l], (int)M, Kc, 1, nullptr,
-                            p + L.b[l], true, st),
+    HIP_TRY(launch_gemm_str(true, p + L.w[l], Kc, false, col, M, out, M, kConvCO[l], (int)M, Kc,
+                            gemm_str_splits(kConvCO[l], (int)M, Kc), (float*)(w + W.part), p + L.b[l], true, st),
             "conv forward");
     in = out;
   }
   float* flat = (float*)(w + W.flat);
   HIP_TRY(launch_flatten(in, kConvCO[3], (int)pix_of(3), B, flat, true, st), "flatten");
-  HIP_TRY(launch_gemm_f32_nt(flat, p + L.wf, z, B, n_cells, kFlat, kFlat, kFlat, n_cells, st, true), "fc forward");
+  // z[b][c] = sum_j flat[b][j] Wf[c][j]
+  HIP_TRY(launch_gemm_str(true, flat, kFlat, true, p + L.wf, kFlat, z, n_cells, B, n_cells, kFlat,
+                          gemm_str_splits(B, n_cells, kFlat), (float*)(w + W.part), nullptr, false, st),
+          "fc forward");
   HIP_TRY(launch_add_bias(z, p + L.bf, B, n_cells, st), "fc bias");
   return EMC_OK;
 }
@@ -868,12 +873,12 @@ emc_status emc_cnn_gradients(int32_t n_cells, const float* params, const float* 
   float* part = (float*)(w + W.part);
   // fully connected: dWf[c][j] = sum_b dz[b][c] flat[b][j]; dbf = column sums of dz;
   // dflat[b][j] = sum_c dz[b][c] Wf[c][j]
-  HIP_TRY(launch_gemm_str(false, dz, n_cells, false, flat, kFlat, grads + L.wf, kFlat, n_cells, kFlat, B, 1, nullptr,
-                          nullptr, false, st),
+  HIP_TRY(launch_gemm_str(false, dz, n_cells, false, flat, kFlat, grads + L.wf, kFlat, n_cells, kFlat, B,
+                          gemm_str_splits(n_cells, kFlat, B), part, nullptr, false, st),
           "fc dW");
   HIP_TRY(launch_col_sum(dz, B, n_cells, grads + L.bf, st), "fc db");
-  HIP_TRY(launch_gemm_str(true, dz, n_cells, false, params + L.wf, kFlat, dflat, kFlat, B, kFlat, n_cells, 1, nullptr,
-                          nullptr, false, st),
+  HIP_TRY(launch_gemm_str(true, dz, n_cells, false, params + L.wf, kFlat, dflat, kFlat, B, kFlat, n_cells,
+                          gemm_str_splits(B, kFlat, n_cells), part, nullptr, false, st),
           "fc dx");
   HIP_TRY(launch_flatten(dflat, kConvCO[3], (int)pix_of(3), B, (float*)(w + W.dact[3]), false, st), "unflatten");
   for (int l = 3; l >= 0; --l) {
@@ -883,15 +888,15 @@ emc_status emc_cnn_gradients(int32_t n_cells, const float* params, const float* 
     const float* col = (const float*)(w + W.col[l]);
     HIP_TRY(launch_relu_mask(dl, (const float*)(w + W.act[l]), (int64_t)B * act_size(l), st), "relu backward");
     // dW[o][kc] = sum_m dout[o][m] col[kc][m] (split over m); db[o] = sum_m dout[o][m]
-    HIP_TRY(launch_gemm_str(true, dl, M, true, col, M, grads + L.w[l], Kc, kConvCO[l], Kc, M, wgrad_splits(l, B), part,
-                            nullptr, false, st),
+    HIP_TRY(launch_gemm_str(true, dl, M, true, col, M, grads + L.w[l], Kc, kConvCO[l], Kc, M,
+                            gemm_str_splits(kConvCO[l], Kc, M), part, nullptr, false, st),
             "conv weight gradient");
-    HIP_TRY(launch_row_sum(dl, kConvCO[l], M, grads + L.b[l], st), "conv bias gradient");
+    HIP_TRY(launch_row_sum(dl, kConvCO[l], M, (float*)(w + W.rpart), grads + L.b[l], st), "conv bias gradient");
     if (l > 0) {
       // dcol[kc][m] = sum_o W[o][kc] dout[o][m], then summed over the taps that read each input
       float* dcol = (float*)(w + W.dcol);
-      HIP_TRY(launch_gemm_str(false, params + L.w[l], Kc, false, dl, M, dcol, M, Kc, (int)M, kConvCO[l], 1, nullptr,
-                              nullptr, false, st),
+      HIP_TRY(launch_gemm_str(false, params + L.w[l], Kc, false, dl, M, dcol, M, Kc, (int)M, kConvCO[l],
+                              gemm_str_splits(Kc, (int)M, kConvCO[l]), part, nullptr, false, st),
               "conv data gradient");
       HIP_TRY(launch_col2im(dcol, kConvCI[l], kConvIH[l], B, (float*)(w + W.dact[l - 1]), st), "col2im");
     }

@@ -100,16 +100,29 @@ __global__ void flatten_kernel(const float* __restrict__ src, int C, int P, int6
   }
 }
 
-// row sums: out[r] = sum_m X[r][m] (bias gradients of the convolutions); one workgroup per row
-__global__ __launch_bounds__(256) void row_sum_kernel(const float* __restrict__ X, int64_t cols, float* __restrict__ out) {
+// row sums: out[r] = sum_m X[r][m] (bias gradients of the convolutions) in two passes:
+// workgroup (r, q) sums columns [q * span, (q + 1) * span) into part[r][q], then the
+// parts of a row are added in order
+constexpr int kRowParts = 64;
+__global__ __launch_bounds__(256) void row_part_kernel(const float* __restrict__ X, int64_t cols, int64_t span,
+                                                       float* __restrict__ part) {
   __shared__ float red[4];
-  const float* row = X + (int64_t)blockIdx.x * cols;
+  const int r = blockIdx.y, q = blockIdx.x;
+  const float* row = X + (int64_t)r * cols;
+  const int64_t c1 = (q + 1) * span < cols ? (q + 1) * span : cols;
   float s = 0.0f;
-  for (int64_t m = threadIdx.x; m < cols; m += 256) s += row[m];
+  for (int64_t m = q * span + threadIdx.x; m < c1; m += 256) s += row[m];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) part[(int64_t)r * kRowParts + q] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+__global__ void row_finish_kernel(const float* __restrict__ part, int rows, float* __restrict__ out) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  float s = 0.0f;
+  for (int q = 0; q < kRowParts; ++q) s += part[(int64_t)r * kRowParts + q];
+  out[r] = s;
 }
 
 // ReLU of the forward pass and of its gradient: g *= (act > 0)
@@ -232,14 +245,16 @@ __global__ __launch_bounds__(256) void gemm_str_kernel(const float* __restrict__
     }
 }
 
-// C[m][n] = sum over splits z (in order) of part[z][m][n]
+// C[m][n] = sum over splits z (in order) of part[z][m][n] (+ bias[m], ReLU when asked)
 __global__ void gemm_reduce_kernel(const float* __restrict__ part, int splits, int64_t c_split, int M, int N,
-                                   float* __restrict__ C, int64_t ldc) {
+                                   float* __restrict__ C, int64_t ldc, const float* __restrict__ bias, int relu) {
   const int64_t total = (int64_t)M * N;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     const int64_t m = e / N, n = e % N;
     float v = 0.0f;
     for (int z = 0; z < splits; ++z) v += part[z * c_split + m * ldc + n];
+    if (bias) v += bias[m];
+    if (relu) v = fmaxf(v, 0.0f);
     C[m * ldc + n] = v;
   }
 }
@@ -429,24 +444,37 @@ hipError_t launch_flatten(const float* src, int C, int P, int64_t nB, float* dst
   return hipGetLastError();
 }
 
-hipError_t launch_row_sum(const float* X, int rows, int64_t cols, float* out, hipStream_t st) {
+hipError_t launch_row_sum(const float* X, int rows, int64_t cols, float* part, float* out, hipStream_t st) {
   if (rows <= 0) return hipSuccess;
-  row_sum_kernel<<<rows, 256, 0, st>>>(X, cols, out);
+  const int64_t span = (cols + kRowParts - 1) / kRowParts;
+  row_part_kernel<<<dim3(kRowParts, (unsigned)rows), 256, 0, st>>>(X, cols, span, part);
+  row_finish_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(part, rows, out);
   return hipGetLastError();
+}
+
+int gemm_str_splits(int M, int N, int64_t K) {
+  // about 256 workgroups when the product has fewer output tiles, each range >= 256 k
+  const int64_t tiles = ((int64_t)(M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
+  if (tiles >= 192) return 1;
+  int64_t s = 256 / tiles;
+  if (s > K / 256) s = K / 256;
+  return (int)(s < 1 ? 1 : s);
 }
 
 hipError_t launch_gemm_str(bool a_kcontig, const float* A, int64_t lda, bool b_kcontig, const float* B, int64_t ldb,
                            float* C, int64_t ldc, int M, int N, int64_t K, int splits, float* part,
                            const float* bias, bool relu, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  if (splits < 1 || (splits > 1 && (!part || bias || relu))) return hipErrorInvalidValue;
+  if (splits < 1 || (splits > 1 && !part)) return hipErrorInvalidValue;
   const int64_t kper = splits > 1 ? ((K + splits - 1) / splits + GBK - 1) / GBK * GBK : K;
   const int z = splits > 1 ? (int)((K + kper - 1) / kper) : 1;
   dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), (unsigned)z);
   float* out = z > 1 ? part : C;
   const int64_t c_split = z > 1 ? (int64_t)M * ldc : 0;
+  const float* eb = z > 1 ? nullptr : bias;  // the epilogue runs in the reduction when split
+  const int er = z > 1 ? 0 : (relu ? 1 : 0);
 #define G(AK, BKC) gemm_str_kernel<AK, BKC><<<grid, 256, 0, st>>>(A, lda, B, ldb, out, ldc, M, N, K, kper, c_split, \
-                                                                 bias, relu ? 1 : 0)
+                                                                 eb, er)
   if (a_kcontig && b_kcontig)
     G(true, true);
   else if (a_kcontig)
@@ -459,7 +487,7 @@ hipError_t launch_gemm_str(bool a_kcontig, const float* A, int64_t lda, bool b_k
   if (z > 1) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    gemm_reduce_kernel<<<grid_of((int64_t)M * N), 256, 0, st>>>(part, z, c_split, M, N, C, ldc);
+    gemm_reduce_kernel<<<grid_of((int64_t)M * N), 256, 0, st>>>(part, z, c_split, M, N, C, ldc, bias, relu ? 1 : 0);
   }
   return hipGetLastError();
 }

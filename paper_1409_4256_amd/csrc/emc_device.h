@@ -149,7 +149,8 @@ hipError_t launch_bin_log(const void* K, bool bf16, int64_t ps, int n_pix, const
 hipError_t launch_im2col(const float* in, int CI, int IH, int64_t M, float* colT, hipStream_t st);
 hipError_t launch_col2im(const float* dcolT, int CI, int IH, int64_t nB, float* din, hipStream_t st);
 hipError_t launch_flatten(const float* src, int C, int P, int64_t nB, float* dst, bool to_flat, hipStream_t st);
-hipError_t launch_row_sum(const float* X, int rows, int64_t cols, float* out, hipStream_t st);
+hipError_t launch_row_sum(const float* X, int rows, int64_t cols, float* part, float* out, hipStream_t st);
+int gemm_str_splits(int M, int N, int64_t K);
 hipError_t launch_gemm_str(bool a_kcontig, const float* A, int64_t lda, bool b_kcontig, const float* B, int64_t ldb,
                            float* C, int64_t ldc, int M, int N, int64_t K, int splits, float* part,
                            const float* bias, bool relu, hipStream_t st);
