@@ -111,13 +111,18 @@ def oracle_parity(inp, g, m_in, coarse, prop, lists, cells):
     assert d_tied >= 0.99 and d_strict >= 0.99
 
 
-def test_trained_proposal_gain(gpu_lib):
+@pytest.mark.parametrize("pool", [4096, 100000])
+def test_trained_proposal_gain(gpu_lib, pool):
+    """pool: distinct true orientations of the 100000 frames (4096: each shared by ~24
+    frames with their own noise; 100000: every frame its own orientation)."""
+    import dataclasses
+
     import torch
 
     import bench
     from paper_1409_4256_amd import emc, learned
 
-    wl = WORKLOADS[2]
+    wl = dataclasses.replace(WORKLOADS[2], pool=pool)
     inp = make_inputs(wl, device="cuda", with_truth=False)
     run = bench.Run(inp, emc.EMC_PREC_BF16, inp.counts)
     g = run.geo
@@ -135,7 +140,7 @@ def test_trained_proposal_gain(gpu_lib):
         run.step()
         if it >= TRAIN_AT - 3:
             targets.append(targets_now())
-    print(f"\n[gain] {TRAIN_AT} full iterations done", flush=True)
+    print(f"\n[gain] pool {pool}: {TRAIN_AT} full iterations done", flush=True)
     bins = torch.as_tensor(proposal_bins(wl.det_n, inp.mask), device="cuda")
     init = learned.init_params(seeded(wl.cfg, "cnn"), N_CELLS)
     trained = learned.Network(N_CELLS, init.clone())
@@ -173,23 +178,37 @@ def test_trained_proposal_gain(gpu_lib):
         prop = learned.ProposedIteration(g, inp.counts, coarse, N_CELLS, lists, k, audit)
         out = torch.empty_like(m_in)
         prop.step(m_in, out)                                 # iteration 11 with the proposal
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        prop.step(m_in, out)                                 # the same step again, timed
+        ev[1].record()
         torch.cuda.synchronize()
         err = (torch.linalg.norm(out.double() - m_full) / torch.linalg.norm(m_full)).item()
-        return err, prop.recall.item(), prop.accepted(), prop.candidate_pairs(), prop
+        return err, prop.recall.item(), prop.accepted(), prop.candidate_pairs(), prop, ev[0].elapsed_time(ev[1])
 
-    err, rec, ok, pairs, prop = iterate(union, K_NET + K_PREV)
+    err, rec, ok, pairs, prop, ms = iterate(union, K_NET + K_PREV)
     oracle_parity(inp, g, m_in, coarse, prop, union.view(-1, K_NET + K_PREV).cpu().numpy(), cells)
     del prop
-    err_p, rec_p, _, pairs_p, _ = iterate(top_prev, K_PREV)
+    err_p, rec_p, _, pairs_p, _, ms_p = iterate(top_prev, K_PREV)
+    # the previous posterior's cells alone with as many cells as the learned lists hold
+    k_match = int(round(float((union.view(-1, K_NET + K_PREV) >= 0).sum(1).float().mean().item())))
+    T10 = T_prev.view(wl.n_data, N_CELLS)
+    top_match = torch.empty(wl.n_data * k_match, dtype=torch.int32, device="cuda")
+    emc.emc_cell_topk(T10, wl.n_data, N_CELLS, k_match, top_match)
+    err_m, rec_m, _, pairs_m, _, ms_m = iterate(top_match, k_match)
     dense = wl.n_rot * wl.n_data
     print(f"[gain] recall of top-{K_NET}/{N_CELLS} cells: trained {r_t:.4f}, untrained {r_u:.4f}\n"
           f"[gain] learned form: model rel L2 vs full search {err:.2e}, top-1 {top1:.4f}, audit recall {rec:.5f}, "
-          f"candidate pairs {pairs / dense:.4f} of dense\n"
-          f"[gain] previous posterior's cells alone: model rel L2 {err_p:.2e}, audit recall {rec_p:.5f}, "
-          f"pairs {pairs_p / dense:.4f} of dense", flush=True)
+          f"candidate pairs {pairs / dense:.4f} of dense, {ms:.1f} ms per iteration\n"
+          f"[gain] previous posterior's top-{K_PREV} cells alone: model rel L2 {err_p:.2e}, audit recall "
+          f"{rec_p:.5f}, pairs {pairs_p / dense:.4f} of dense, {ms_p:.1f} ms per iteration\n"
+          f"[gain] previous posterior's top-{k_match} cells alone (the learned lists' mean size): model rel L2 "
+          f"{err_m:.2e}, audit recall {rec_m:.5f}, pairs {pairs_m / dense:.4f} of dense, {ms_m:.1f} ms per "
+          f"iteration", flush=True)
     assert r_t >= 0.98
     assert r_u <= 0.2
     assert ok
     assert err <= 1e-3
     assert top1 >= 0.99
-    assert err < err_p
+    if pool == 4096:   # the network's cells shrink the model error of the 64 previous-posterior cells
+        assert err < err_p
