@@ -133,6 +133,21 @@ emc_status emc_workspace_bytes(const emc_problem* pb, size_t* bytes);
 emc_status emc_pack_frames(const emc_problem* pb, const uint16_t* counts, void* K_packed,
                            hipStream_t stream);
 
+/* emc_pack_frames under the name of the problem statement's "patterns". */
+emc_status emc_pack_patterns(const emc_problem* pb, const uint16_t* counts, void* K_packed,
+                             hipStream_t stream);
+
+/* Contents check for callers that cannot vouch for their arrays (every other entry
+ * point checks sizes and pointers only; any finite input has a defined result):
+ *   - each quaternion's norm within 1e-5 of 1 (Section 2.2: unit quaternions);
+ *   - finite log prior weights and finite coordinates of the used pixels;
+ *   - when model is not NULL: every model value finite and >= 0 (an intensity).
+ *   flags  device int32 the call overwrites (scratch, 4-byte aligned)
+ * One pass over the arrays on `stream`, then one synchronisation to read the result.
+ * Returns EMC_OK, or EMC_ERR_INVALID_ARG with emc_last_error() naming the first
+ * failed check.  Nothing else is written. */
+emc_status emc_validate(const emc_problem* pb, const float* model, int32_t* flags, hipStream_t stream);
+
 /* Expansion, eq. (2.9): W_ij = sum_l f(p_l - R_j q_i) model_l, floored at
  * 1e-10, as centred logs A_ji = log W_ij - c_i.
  *   model  [N^3] float grid values

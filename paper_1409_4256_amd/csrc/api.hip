@@ -294,6 +294,27 @@ emc_status emc_pack_frames(const emc_problem* pb, const uint16_t* counts, void* 
   return pack_frames(pb, counts, nullptr, K_packed, st);
 }
 
+emc_status emc_pack_patterns(const emc_problem* pb, const uint16_t* counts, void* K_packed, hipStream_t st) {
+  return pack_frames(pb, counts, nullptr, K_packed, st);
+}
+
+emc_status emc_validate(const emc_problem* pb, const float* model, int32_t* flags, hipStream_t st) {
+  CHECK(check_problem(pb, true));
+  if (model) CHECK(need(model, 4, "model"));
+  CHECK(need(flags, 4, "flags"));
+  const int64_t grid = (int64_t)pb->grid_n * pb->grid_n * pb->grid_n;
+  HIP_TRY(launch_validate(pb->quat, pb->n_rot, pb->q, pb->mask, pb->n_pix, pb->log_w, model, grid, 1e-5, flags, st),
+          "validate");
+  int32_t host = 0;
+  HIP_TRY(hipMemcpyAsync(&host, flags, sizeof host, hipMemcpyDeviceToHost, st), "read validation flags");
+  HIP_TRY(hipStreamSynchronize(st), "validate synchronise");
+  if (host & kValidQuat) return fail(EMC_ERR_INVALID_ARG, "a quaternion's norm differs from 1 by more than 1e-5");
+  if (host & kValidWeight) return fail(EMC_ERR_INVALID_ARG, "a log prior weight is not finite");
+  if (host & kValidPixel) return fail(EMC_ERR_INVALID_ARG, "a used pixel's coordinate is not finite");
+  if (host & kValidModel) return fail(EMC_ERR_INVALID_ARG, "a model value is negative or not finite");
+  return EMC_OK;
+}
+
 emc_status emc_pack_frames_list(const emc_problem* pb, const uint16_t* counts, const int32_t* frames, void* K_packed,
                                 hipStream_t st) {
   if (pb && pb->n_data > 0) CHECK(need(frames, 4, "frames"));

@@ -143,6 +143,12 @@ hipError_t launch_divide(const double* num, const double* den, const float* prev
                          hipStream_t st);
 hipError_t launch_mean(const double* L, int64_t n, double* out, hipStream_t st);
 
+// ---- contents check (validate.hip) ----
+constexpr int32_t kValidQuat = 1, kValidWeight = 2, kValidPixel = 4, kValidModel = 8;
+hipError_t launch_validate(const float* quat, int64_t n_rot, const float* q, const uint8_t* mask, int64_t n_pix,
+                           const double* log_w, const float* model, int64_t n_grid, double tol, int32_t* flags,
+                           hipStream_t st);
+
 // ---- proposal network (cnn.hip) ----
 hipError_t launch_bin_log(const void* K, bool bf16, int64_t ps, int n_pix, const int32_t* bins, const int32_t* frames,
                           int B, float* x, hipStream_t st);

@@ -30,7 +30,7 @@ EMC_RESP_FINALIZE = 2
 EXPORTS = ("emc_version", "emc_last_error", "emc_pix_stride", "emc_data_stride", "emc_frames_bytes",
            "emc_slices_bytes", "emc_workspace_bytes", "emc_pack_frames", "emc_expand", "emc_loglik",
            "emc_responsibilities", "emc_compress_workspace_bytes", "emc_compress", "emc_finalize", "emc_iterate",
-           "emc_iterate_noalloc",
+           "emc_iterate_noalloc", "emc_pack_patterns", "emc_validate",
            "emc_cnn_param_count", "emc_cnn_workspace_bytes", "emc_cnn_preprocess", "emc_cnn_forward",
            "emc_cnn_gradients", "emc_cnn_adam", "emc_cnn_topk", "emc_cell_topk", "emc_topk_union",
            "emc_cell_targets",
@@ -131,6 +131,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
     lib.emc_iterate.restype = st
     lib.emc_iterate_noalloc.argtypes = [_PB, _P, _P, _P, _P, _P, _P]
     lib.emc_iterate_noalloc.restype = st
+    lib.emc_pack_patterns.argtypes, lib.emc_pack_patterns.restype = [_PB, _P, _P, _P], st
+    lib.emc_validate.argtypes, lib.emc_validate.restype = [_PB, _P, _P, _P], st
     lib.emc_cnn_param_count.argtypes, lib.emc_cnn_param_count.restype = [i32], i64
     lib.emc_cnn_workspace_bytes.argtypes, lib.emc_cnn_workspace_bytes.restype = [i32, i32, szp], st
     lib.emc_cnn_preprocess.argtypes, lib.emc_cnn_preprocess.restype = [_PB, _P, _P, _P, i32, _P, _P], st
@@ -421,6 +423,18 @@ def emc_iterate(geo: Geometry, model_in, K_packed, model_out, loglik, P_out=None
         _ptr(model_out, torch.float32, M, "model_out"), _ptr(loglik, torch.float64, 1, "loglik"),
         _ptr(P_out, geo.p_dtype, geo.n_rot * geo.data_stride, "P_out", allow_none=True),
         _ptr(ws, torch.uint8, need, "ws"), ctypes.c_size_t(ws.numel()), _stream(stream)))
+
+
+def emc_validate(geo: Geometry, model=None, stream=None):
+    """Contents check of the geometry (and model): raises EmcError when a quaternion is not
+    of unit norm, a weight or used pixel coordinate is not finite, or the model has a
+    negative or non-finite value."""
+    import torch
+
+    flags = torch.empty(1, dtype=torch.int32, device="cuda")
+    _check(load().emc_validate(ctypes.byref(geo.pb),
+                               _ptr(model, torch.float32, geo.grid_n ** 3, "model", allow_none=True),
+                               _ptr(flags, torch.int32, 1, "flags"), _stream(stream)))
 
 
 EMC_SCRATCH_MAX_BYTES = 64 << 20    # the static device buffer of emc_iterate_noalloc

@@ -123,6 +123,14 @@ def test_noalloc_refuses_problems_beyond_its_static_buffer(lib):
     assert lib.emc_iterate_noalloc(ctypes.byref(_pb()), None, a, a, a, None, None) == emc.EMC_ERR_INVALID_ARG
 
 
+def test_validate_argument_checks(lib):
+    a = ctypes.c_void_p(1 << 20)
+    assert lib.emc_validate(ctypes.byref(_pb()), a, None, None) == emc.EMC_ERR_INVALID_ARG
+    assert b"flags" in lib.emc_last_error()
+    assert lib.emc_validate(ctypes.byref(_pb(quat=0)), a, a, None) == emc.EMC_ERR_INVALID_ARG
+    assert lib.emc_validate(ctypes.byref(_pb()), ctypes.c_void_p((1 << 20) + 2), a, None) == emc.EMC_ERR_INVALID_ARG
+
+
 def test_compress_workspace_checks(lib):
     pb = _pb()
     a = ctypes.c_void_p(1 << 20)
