@@ -83,7 +83,7 @@ def test_cnn_gradients_match_oracle(setup):
         assert _rel(gg[k], gr[k]) <= 1e-4, (k, _rel(gg[k], gr[k]))
 
 
-@pytest.mark.parametrize("B", [40, 70])
+@pytest.mark.parametrize("B", [1, 40, 70])
 def test_cnn_gradients_match_oracle_larger_batches(gpu_lib, B):
     """Batches that split every weight-gradient reduction over several ranges and
     leave ragged output tiles in the contractions, against the FP64 oracle's
