@@ -238,7 +238,10 @@ class FullSearchChunks:
 
     def add_chunk(self, ci: int, model, num, den, L, accumulate: bool):
         """Chunk ci's full search into num/den (zeroed first unless accumulate); its
-        frames' log-evidence into L [chunk frames]; P of the chunk stays in self.P."""
+        frames' log-evidence into L [chunk frames]; P of the chunk stays in self.P.
+        The slices of the last expand() are reused while `model` is the same tensor:
+        a caller that rewrites a model tensor in place calls expand() (or sets
+        `expanded` to None) before the next chunk."""
         if self.expanded is not model:
             self.expand(model)
         s, e = self.bounds(ci)
@@ -258,6 +261,7 @@ def proposed_chunks(chunks, full: FullSearchChunks, model_in, model_out, loglik,
     (eq. 2.12) and the mean log-evidence (eq. 2.1) over every frame follow.
     Returns the audit recall of each chunk and whether it was accepted."""
     out = []
+    full.expanded = None          # the first full-search chunk expands this iteration's model
     for ci in range(chunks):
         s, e = full.bounds(ci)
         prop = make_plan(ci)
