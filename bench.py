@@ -374,7 +374,11 @@ def proposal_form(inp, args, counts_dev, compare=True):
     t_full = time.perf_counter() - t0
     bins = torch.as_tensor(proposal_bins(wl.det_n, inp.mask), device="cuda")
     net = learned.Network(n_cells, learned.init_params(seeded(wl.cfg, "cnn"), n_cells))
-    x = net.images(g, run.K, bins)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = net.images(g, run.K, bins)                 # binned log images of every frame
+    torch.cuda.synchronize()
+    t_images = time.perf_counter() - t0
     tlog = net.train(x, targets, wl.n_data, epochs=2, lr=1e-3, rng=seeded(wl.cfg, "cnn"))
     log(f"proposal: trained {tlog.steps} steps in {tlog.seconds:.1f} s, loss {tlog.loss_first:.3f} -> "
         f"{tlog.loss_last:.3f}")
@@ -472,8 +476,9 @@ def proposal_form(inp, args, counts_dev, compare=True):
             "schedule": f"full search for iterations 1-{args.train_at}, trained on iterations "
                         f"{args.train_at - 2}-{args.train_at}, proposal from iteration {args.train_at + 1}: "
                         f"network top-{k_net} cells U top-{k_prev} cells of the last full posterior",
-            "one_off_s": {"full_iterations": round(t_full, 2), "training": round(tlog.seconds, 2),
-                          "network_topk": round(t_infer, 2), "plan": round(t_plan, 2)},
+            "one_off_s": {"full_iterations": round(t_full, 2), "network_images": round(t_images, 3),
+                          "training": round(tlog.seconds, 2), "network_topk": round(t_infer, 2),
+                          "plan": round(t_plan, 2)},
             "training": {"steps": tlog.steps, "loss_first": tlog.loss_first, "loss_last": tlog.loss_last},
             "candidate_pairs": n_pairs, "dense_pairs": int(wl.n_rot) * int(wl.n_data),
             "previous_posterior_only": {
