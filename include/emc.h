@@ -443,9 +443,15 @@ typedef struct emc_proposal {
   void* chunks;           /* 16-byte chunks of 8 uint16 words: the non-zero pixels
                              of candidate frame f in 128-pixel band b as
                              (pixel - 128 b) << 9 | count, ascending, 0xffff pads;
-                             stored band-major (band 0 of all frames first)        */
-  int32_t* band_range;    /* [n_bands][n_cand][2] chunk range (first, end) of band
-                             b of frame f, absolute chunk indices                  */
+                             bands in runs of 8 (r = b / 8): run 0 of every frame,
+                             then run 1, ...; inside a run frame f's chunks of its
+                             bands are contiguous, band after band                 */
+  void* runs;             /* [n_cand][ceil(n_bands / 8)] uint32 x 4 per (frame, run):
+                             first chunk (absolute index); the offsets of bands
+                             0-3 and of bands 4-7 from it, one byte each, lowest
+                             byte first (a band past n_bands: the run's count);
+                             the run's chunk count; followed by the same records
+                             run-major, [ceil(n_bands / 8)][n_cand]                */
   int32_t n_dense;        /* dense bands (frames average >= 3 chunks; <= 16): their
                              M-step columns are one dense product                  */
   int32_t reserved2;

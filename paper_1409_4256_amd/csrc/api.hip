@@ -1010,7 +1010,7 @@ int64_t chunk_cap(int64_t nz_cap, int64_t n_cand, int n_pix) { return (nz_cap + 
 // Carving of the plan buffer (capacities known before the build).
 struct PlanLayout {
   size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, cg_ptr,
-      groups, grp_off, tiles, mask_audit, chunks, band_range, band_cnt, band_ptr, dense_band, dense_list, kt_dense,
+      groups, grp_off, tiles, mask_audit, chunks, runs, band_cnt, band_ptr, dense_band, dense_list, kt_dense,
       band_mean, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd, cnt, scalars, total;
 };
 
@@ -1043,7 +1043,7 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.mask_audit = take((int64_t)n_audit * w * 4);
   const int64_t n_fb = n_cand * (ntab_of(n_pix) - 1);  // (band, frame) entries
   L.chunks = take(chunk_cap(nz_cap, n_cand, n_pix) * 16);
-  L.band_range = take(n_fb * 8);
+  L.runs = take(2 * n_cand * run_count(ntab_of(n_pix) - 1) * 16);
   L.band_cnt = take(n_fb * 4);
   L.band_ptr = take((n_fb + 1) * 8);
   L.dense_band = take((int64_t)(ntab_of(n_pix) - 1) * 4);
@@ -1155,7 +1155,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   P.tiles = (void*)(b + L.tiles);
   P.mask_audit = (uint32_t*)(b + L.mask_audit);
   P.chunks = (void*)(b + L.chunks);
-  P.band_range = (int32_t*)(b + L.band_range);
+  P.runs = b + L.runs;
   int32_t* band_cnt = (int32_t*)(b + L.band_cnt);
   int64_t* band_ptr = (int64_t*)(b + L.band_ptr);
   const int64_t n_fb = n_cand * (ntab - 1);
@@ -1223,8 +1223,8 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   if (host[4] > chunk_cap(nz_cap, n_cand, pb->n_pix) || host[4] > (int64_t)INT32_MAX)
     return fail(EMC_ERR_WORKSPACE, "the candidate frames need %lld chunks, nz_cap %lld allows %lld", (long long)host[4],
                 (long long)nz_cap, (long long)chunk_cap(nz_cap, n_cand, pb->n_pix));
-  HIP_TRY(launch_band_range(band_ptr, n_fb, (int2*)P.band_range, st), "band ranges");
-  HIP_TRY(launch_band_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab - 1, (const int2*)P.band_range,
+  HIP_TRY(launch_run_table(band_ptr, n_cand, ntab - 1, P.runs, st), "run records");
+  HIP_TRY(launch_band_fill(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, ntab - 1, P.runs,
                            P.chunks, st),
           "band fill");
   P.n_dense = (int32_t)host[5];
@@ -1373,12 +1373,12 @@ emc_status run_proposed(const emc_problem* pb, const emc_proposal* plan, const v
   // expansion (BF16 hi + lo slices with their row scales)
   CHECK(run_expand(pb, model_in, c, slices, S, scale, st));
   if (nc > 0)
-    HIP_TRY(launch_band_dot((const int2*)plan->band_range, plan->n_bands, plan->chunks, nc, c, b, st), "band dot");
+    HIP_TRY(launch_band_dot(plan->runs, plan->n_bands, plan->chunks, nc, c, b, st), "band dot");
   CHECK(mark(1));
   // candidate frames: log-likelihoods per (group, listed frame), E-step over each frame's candidates
   if (nc > 0) {
     HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, groups, plan->grp_off, plan->cf_ptr,
-                               plan->cf_frame, (const int2*)plan->band_range, nc, plan->chunks, plan->cell_rot,
+                               plan->cf_frame, plan->runs, plan->chunks, plan->cell_rot,
                                slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
             "candidate loglik");
   }
@@ -1414,7 +1414,7 @@ emc_status run_proposed(const emc_problem* pb, const emc_proposal* plan, const v
   }
   CHECK(mark(4));
   HIP_TRY(launch_cand_mstep(groups, plan->grp_off, plan->n_groups, plan->cf_ptr, plan->cf_frame,
-                            (const int2*)plan->band_range, nc, plan->chunks, plan->dense_band, Pc, plan->cell_rot, ps,
+                            plan->runs, nc, plan->chunks, plan->dense_band, Pc, plan->cell_rot, ps,
                             Wp, rho, rho_a, na > 0, st),
           "candidate mstep");
   CHECK(mark(5));

@@ -10,11 +10,15 @@
 //     W'_r,i = sum_frames P[r][frame] K_i,frame                         (eq. 2.11)
 // Frames are stored sparsely, band-blocked: for every 128-pixel band a frame's
 // non-zero pixels are 16-bit words (pixel in band << 9 | count) packed in 16-byte
-// chunks of 8 (the last one padded with 0xffff).  Chunks are stored band-major
-// (band 0 of every frame, then band 1, ...), and frames are numbered by their best
-// cell, so the frames of a cell's list -- runs of consecutive numbers -- have their
-// chunks of one band next to each other; a table [band][frame] gives each chunk
-// range (absolute chunk indices).  Each workgroup expands the frames it needs into LDS band by
+// chunks of 8 (the last one padded with 0xffff).  Bands come in runs of 8 (1024
+// pixels, the M-step's pixel range); inside a run a frame's chunks of the 8 bands
+// are contiguous, frame after frame (run 0 of every frame, then run 1, ...).  A
+// lane that streams one frame band after band thus reads whole cache lines of its
+// own frame, whichever other frames a cell's list holds, and an M-step workgroup's
+// four waves read the same lines.  A 16-byte record per (frame, run), frame-major,
+// locates the chunks: the run's first chunk (absolute index), the offsets of its
+// bands' first chunks (one byte each) and its chunk count -- one load per frame
+// and run instead of a table entry per band.  Each workgroup expands the frames it needs into LDS band by
 // band and feeds the dense band to v_mfma_f32_16x16x32_bf16; the next band's
 // chunks are loaded while the current band's MFMAs run.  A band's LDS rows are
 // owned by one wave (it writes, reads and clears them), so the band loops need no
@@ -46,6 +50,17 @@ __device__ __forceinline__ uint16_t count_bf16(uint32_t e) {
 }
 
 constexpr uint32_t kPad = 0xffffu;  // padding word of a chunk
+constexpr int kRun = 8;             // bands per run of the chunk layout (the M-step's 1024-pixel range)
+
+// Chunks [x, y) of band i (0..kRun-1) of a run record {first chunk, offsets of
+// bands 0-3, offsets of bands 4-7 (bytes, ascending), chunks in the run}; bands
+// past a short last run have offset = chunk count (empty).
+__device__ __forceinline__ int2 run_band(u4 rec, int i) {
+  const uint32_t lo = i < 4 ? rec.y : rec.z, hi = i + 1 < 4 ? rec.y : rec.z;
+  const int x = (int)((lo >> (8 * (i & 3))) & 0xffu);
+  const int y = i + 1 < kRun ? (int)((hi >> (8 * ((i + 1) & 3))) & 0xffu) : (int)rec.w;
+  return make_int2((int)rec.x + x, (int)rec.x + y);
+}
 
 // The M-step streams each chunk once: non-temporal loads keep the stream from
 // evicting the responsibilities its workgroups share in L2 (measured faster there;
@@ -95,15 +110,18 @@ __device__ __forceinline__ void put_rest(uint16_t* base, int stride, const u4* _
 // owns frames f0 + 64 w .. + 63 (lane s expands frame s) over every band and both
 // rotation tiles, so the four waves read the same slice rows at about the same
 // time (one fetch from L2 serves the workgroup) and each wave writes its own
-// frames' G; there is no barrier, and waves without frames leave at once.
-__global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
-    const int2* __restrict__ tiles, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
-    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int2* __restrict__ band_range,
-    int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ cell_rot, const uint16_t* __restrict__ hi,
+// frames' G; there is no barrier, and waves without frames leave at once.  TWO:
+// the group has a second rotation tile (more than 16 rotations); the kernel picks
+// the variant once per workgroup, so the MFMA sequence has no branch.  Per 32-pixel
+// step the wave reads its four B fragments together and issues the hi products of
+// every accumulator before the lo ones, so no MFMA waits on the one before it.
+template <bool TWO>
+__device__ __forceinline__ void cand_loglik_tile(
+    uint16_t* __restrict__ lds, const int2 tl, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
+    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const u4* __restrict__ runs,
+    const u4* __restrict__ fb, const int32_t* __restrict__ cell_rot, const uint16_t* __restrict__ hi,
     int64_t plane, const float* __restrict__ scale, int64_t ps, float* __restrict__ G) {
-  __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kFT * kLRow];  // 69632 bytes
-  const int2 tl = tiles[blockIdx.x];
-  if (tl.x < 0) return;  // padding tile (uniform)
+  constexpr int NT = TWO ? 2 : 1;  // rotation tiles
   const int4 gr = groups[tl.x];
   const int c = gr.x, r0 = gr.y, nr = gr.z;
   const int64_t F = cf_ptr[c + 1] - cf_ptr[c];
@@ -112,55 +130,56 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
   if (f0 >= F) return;  // uniform per wave
   const int nf = (int)(F - f0 < kFT ? F - f0 : kFT);
 
-  const int nbands = (int)(ps / kBand);
-  // this lane's frame (slot = lane): its bands' chunk ranges, rng[band * n_list]
+  const int nbands = (int)(ps / kBand), n_runs = (nbands + kRun - 1) / kRun;
+  // this lane's frame (slot = lane) and its run records
   const bool has = lane < nf;
   const int32_t fidx = has ? cf_frame[cf_ptr[c] + f0 + lane] : 0;
-  const int2* rng = band_range + fidx;
+  const u4* rec_of = runs + (int64_t)fidx * n_runs;
   // rows of the A operand: rotation (lane & 15) of each 16-row tile; rows past the
   // group read its last rotation again (their sums are multiplied by a zero scale)
   const int m = lane & 15, kq = 8 * (lane >> 4);
   const int64_t ar0 = (int64_t)cell_rot[r0 + (m < nr ? m : nr - 1)] * ps;
-  const int64_t ar1 = (int64_t)cell_rot[r0 + (16 + m < nr ? 16 + m : nr - 1)] * ps;
-  const bool two = nr > 16;
+  const int64_t ar1 = TWO ? (int64_t)cell_rot[r0 + (16 + m < nr ? 16 + m : nr - 1)] * ps : 0;
 
   uint16_t* rows = lds + wave * kFT * kLRow;
   uint16_t* frow = rows + lane * kLRow;
   for (int e = lane; e < kFT * kLRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = u4{0u, 0u, 0u, 0u};
 
-  f4 acc[2][4];
+  f4 acc[NT][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NT; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   const u4 zero = {0u, 0u, 0u, 0u};
   const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
-  // pipeline: chunks of the current band in registers, the next band's chunk range
+  // pipeline: chunks of the current band in registers, the next band's chunk range;
+  // the records of the current run and the next one (loaded on entering a run)
+  u4 rc = zero, rcn = zero;
+  if (has) {
+    rc = rec_of[0];
+    if (n_runs > 1) rcn = rec_of[1];
+  }
   int2 r0c = {0, 0}, r1c = {0, 0};
-  if (has) r0c = rng[0];
+  if (has) r0c = run_band(rc, 0);
   u4 w0[kWin];
 #pragma unroll
   for (int u = 0; u < kWin; ++u) w0[u] = r0c.x + u < r0c.y ? load_chunk<false>(fb + r0c.x + u) : pad;
-  if (has && 1 < nbands) r1c = rng[n_list];
-  // A fragments (slice rows, hi and lo, both row tiles) of a band, 4 k-steps; the
-  // second row tile only when the group has one (uniform)
-  auto load_a = [&](int band, u4 (&h)[4][2], u4 (&l)[4][2]) {
+  if (has && 1 < nbands) r1c = run_band(rc, 1);
+  // A fragments (slice rows, hi and lo, of each row tile) of a band, 4 k-steps
+  auto load_a = [&](int band, u4 (&h)[4][NT], u4 (&l)[4][NT]) {
     const int64_t kb = (int64_t)(band < nbands ? band : nbands - 1) * kBand + kq;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      h[kk][0] = *reinterpret_cast<const u4*>(hi + ar0 + kb + 32 * kk);
-      l[kk][0] = *reinterpret_cast<const u4*>(hi + plane + ar0 + kb + 32 * kk);
-    }
-    if (two) {
+    for (int t = 0; t < NT; ++t) {
+      const int64_t ar = t ? ar1 : ar0;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        h[kk][1] = *reinterpret_cast<const u4*>(hi + ar1 + kb + 32 * kk);
-        l[kk][1] = *reinterpret_cast<const u4*>(hi + plane + ar1 + kb + 32 * kk);
+        h[kk][t] = *reinterpret_cast<const u4*>(hi + ar + kb + 32 * kk);
+        l[kk][t] = *reinterpret_cast<const u4*>(hi + plane + ar + kb + 32 * kk);
       }
     }
   };
-  u4 ah[4][2], al[4][2];
+  u4 ah[4][NT], al[4][NT];
   load_a(0, ah, al);
   for (int band = 0; band < nbands; ++band) {
     // prefetch (issued before this band's data is waited on; loads complete in issue
@@ -170,8 +189,12 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     u4 w1[kWin];
 #pragma unroll
     for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? load_chunk<false>(fb + r1c.x + u) : pad;
+    if (band > 0 && band % kRun == 0) {  // entering run band / kRun (uniform)
+      rc = rcn;
+      rcn = has && band / kRun + 1 < n_runs ? rec_of[band / kRun + 1] : zero;
+    }
     int2 r2c = {0, 0};
-    if (has && band + 2 < nbands) r2c = rng[(band + 2) * n_list];
+    if (has && band + 2 < nbands) r2c = run_band((band + 2) / kRun == band / kRun ? rc : rcn, (band + 2) % kRun);
     // window chunks past the first only when some lane of the wave has them (most
     // bands hold at most 8 photon pixels per frame)
     const bool more = __ballot(r0c.y - r0c.x > 1) != 0;
@@ -185,16 +208,19 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
+      bf8 bv[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bf8 bv = *reinterpret_cast<const bf8*>(&rows[(16 * j + m) * kLRow + 32 * kk + kq]);
-        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[kk][0]), bv, acc[0][j], 0, 0, 0);
-        acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[kk][0]), bv, acc[0][j], 0, 0, 0);
-        if (two) {
-          acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[kk][1]), bv, acc[1][j], 0, 0, 0);
-          acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[kk][1]), bv, acc[1][j], 0, 0, 0);
-        }
-      }
+      for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const bf8*>(&rows[(16 * j + m) * kLRow + 32 * kk + kq]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ah[kk][t]), bv[j], acc[t][j], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[t][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, al[kk][t]), bv[j], acc[t][j], 0, 0, 0);
     }
     // clear what this lane wrote: the words of its register window, or its whole row
     // when the band held more chunks than the window (the wave's LDS operations run
@@ -222,8 +248,7 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
   // 16 i + 4 (lane >> 4) + 0..3 of tile (i, j)
   float* out = G + grp_off[tl.x] + (int64_t)f0 * kGR;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    if (i == 1 && !two) break;
+  for (int i = 0; i < NT; ++i) {
     const int rb = 16 * i + 4 * (lane >> 4);
     f4 sc;
 #pragma unroll
@@ -232,6 +257,20 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
     for (int j = 0; j < 4; ++j)
       if (16 * j + m < nf) *reinterpret_cast<f4*>(out + (16 * j + m) * kGR + rb) = sc * acc[i][j];
   }
+}
+
+__global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
+    const int2* __restrict__ tiles, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
+    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const u4* __restrict__ runs,
+    const u4* __restrict__ fb, const int32_t* __restrict__ cell_rot, const uint16_t* __restrict__ hi,
+    int64_t plane, const float* __restrict__ scale, int64_t ps, float* __restrict__ G) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kFT * kLRow];  // 69632 bytes
+  const int2 tl = tiles[blockIdx.x];
+  if (tl.x < 0) return;  // padding tile (uniform)
+  if (groups[tl.x].z > 16)
+    cand_loglik_tile<true>(lds, tl, groups, grp_off, cf_ptr, cf_frame, runs, fb, cell_rot, hi, plane, scale, ps, G);
+  else
+    cand_loglik_tile<false>(lds, tl, groups, grp_off, cf_ptr, cf_frame, runs, fb, cell_rot, hi, plane, scale, ps, G);
 }
 
 // ------------------------------------------------------------------ E-step
@@ -354,20 +393,19 @@ __global__ __launch_bounds__(256) void cand_pwrite_kernel(
 // are skipped: their W' columns are one dense product over the whole frame set.  W' rows are written (accumulate: added to what the audited frames'
 // dense product left there); the range-0 workgroup also sums rho = sum P.
 constexpr int kPair = 2 * kBand;    // pixels per wave in the M-step
-__global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
-    const int4* __restrict__ groups, const int64_t* __restrict__ grp_off, int64_t n_groups, int nranges,
-    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const int2* __restrict__ band_range,
-    int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ dense_band, const uint16_t* __restrict__ P,
-    const int32_t* __restrict__ cell_rot, int64_t ps, float* __restrict__ Wp, double* __restrict__ rho,
-    const double* __restrict__ rho_a, int accumulate) {
-  __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kPair * kKRow];  // 81920 bytes
-  // workgroup 8 q + x (dispatch is round-robin over the 8 XCDs: it runs on XCD x)
-  // takes range q mod nranges of group 8 (q / nranges) + x, so a group's ranges run
-  // one after another on one XCD and share its P in that XCD's L2
-  const int64_t q = blockIdx.x >> 3;
-  const int64_t g = 8 * (q / nranges) + (blockIdx.x & 7);
-  const int pr = (int)(q % nranges);
-  if (g >= n_groups) return;  // padding of the group count to a multiple of 8 (uniform)
+static_assert(4 * kPair == kRun * kBand, "an M-step workgroup's pixel range is one run of the chunk layout");
+// TWO: the group has a second rotation tile (picked once per workgroup, so the MFMA
+// sequence has no branch); the A fragments of a block are read from LDS in batches
+// and each feeds MFMAs on independent accumulators.
+template <bool TWO>
+__device__ __forceinline__ void cand_mstep_range(
+    uint16_t* __restrict__ lds, int64_t g, int pr, const int4* __restrict__ groups,
+    const int64_t* __restrict__ grp_off, const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame,
+    const u4* __restrict__ runs, int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ dense_band,
+    const uint16_t* __restrict__ P, const int32_t* __restrict__ cell_rot, int64_t ps, float* __restrict__ Wp,
+    double* __restrict__ rho, const double* __restrict__ rho_a, int accumulate) {
+  constexpr int NT = TWO ? 2 : 1;        // rotation tiles
+  constexpr int NB = TWO ? 4 : 8;        // A fragments read per batch
   const int4 gr = groups[g];
   const int c = gr.x, r0 = gr.y, nr = gr.z;
   const int64_t F = cf_ptr[c + 1] - cf_ptr[c];
@@ -378,7 +416,6 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
   const int band = 2 * (pr * 4 + wave);  // first band of this wave's pair
   const int p0 = band * kBand;
   if (band >= nbands) return;  // no band for this wave (no barrier follows)
-  const bool two = nr > 16;
   const bool do_rho = pr == 0 && wave == 0;
   const int n = lane & 15, kq = 8 * (lane >> 4);
   const int slot = lane & 31, par = lane >> 5;
@@ -387,35 +424,40 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
   uint16_t* fcol = rows + slot;
   for (int e = lane; e < kPair * kKRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = u4{0u, 0u, 0u, 0u};
 
-  f4 acc[16][2];
+  f4 acc[16][NT];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i][0] = acc[i][1] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < 16; ++i)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[i][t] = f4{0.f, 0.f, 0.f, 0.f};
   double rs0 = 0.0, rs1 = 0.0;
   const u4 zero = {0u, 0u, 0u, 0u};
   const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
   constexpr int kNext = kBand * kKRow;  // LDS offset of the pair's second band
 
-  // this lane's band of the pair and its LDS rows; a dense band's rows stay zero
-  // here (its pixels come from the dense product)
-  const int2* rng = band_range + (int64_t)(band + par) * n_list;
+  // this lane's band of the pair (band 2 w + par of run pr, the workgroup's pixel
+  // range) and its LDS rows; a dense band's rows stay zero here (its pixels come
+  // from the dense product).  Records of run pr, run-major copy.
+  const int n_runs = (nbands + kRun - 1) / kRun, bi = band + par - pr * kRun;
+  const u4* run_pr = runs + (int64_t)n_list * n_runs + (int64_t)pr * n_list;
   const bool sparse = dense_band[band + par] < 0;
   uint16_t* fcol_b = fcol + par * kNext;
-  auto range_of = [&](int32_t fr) -> int2 { return fr < 0 || !sparse ? int2{0, 0} : rng[fr]; };
+  // a frame's record (a zero record: no chunks); decoded one block after its load
+  auto record_of = [&](int32_t fr) -> u4 { return fr < 0 || !sparse ? u4{0u, 0u, 0u, 0u} : run_pr[fr]; };
   auto frame_at = [&](int64_t f0) -> int32_t { return f0 + slot < F ? cf[f0 + slot] : -1; };
   // B operand of a block: frames kq..kq+7 for rotation n (and n + 16)
   auto load_p = [&](int64_t f0, u4& x0, u4& x1) {
     const uint16_t* pblk = Pg + (f0 >> 5) * (kGR * kFB);
     x0 = f0 < F ? *reinterpret_cast<const u4*>(pblk + n * kFB + kq) : zero;
-    x1 = f0 < F && two ? *reinterpret_cast<const u4*>(pblk + (16 + n) * kFB + kq) : zero;
+    x1 = TWO && f0 < F ? *reinterpret_cast<const u4*>(pblk + (16 + n) * kFB + kq) : zero;
   };
-  // pipeline stages: block k (P in b0/b1, chunks in w0), k + 1 (range q1), k + 2 (frame fr2)
-  int2 q0 = range_of(frame_at(0));
+  // pipeline stages: block k (P in b0/b1, chunks in w0), k + 1 (record e1), k + 2 (frame fr2)
+  int2 q0 = run_band(record_of(frame_at(0)), bi);
   const int32_t fr1 = frame_at(kFB);
   int32_t fr2 = frame_at(2 * kFB);
   u4 w0[kWin];
 #pragma unroll
   for (int u = 0; u < kWin; ++u) w0[u] = q0.x + u < q0.y ? load_chunk<true>(fb + q0.x + u) : pad;
-  int2 q1 = range_of(fr1);
+  u4 e1 = record_of(fr1);
   u4 b0, b1;
   load_p(0, b0, b1);
 
@@ -425,10 +467,11 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
     // block ago, is waited on without waiting for these)
     u4 b0n, b1n;
     load_p(f0 + kFB, b0n, b1n);
+    const int2 q1 = run_band(e1, bi);
     u4 w1[kWin];
 #pragma unroll
     for (int u = 0; u < kWin; ++u) w1[u] = q1.x + u < q1.y ? load_chunk<true>(fb + q1.x + u) : pad;
-    const int2 q2 = range_of(fr2);
+    const u4 e2 = record_of(fr2);
     const int32_t fr3 = frame_at(f0 + 3 * kFB);
 #pragma unroll
     for (int u = 0; u < kWin; ++u) put_chunk<false>(fcol_b, kKRow, w0[u]);
@@ -450,10 +493,19 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
       }
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const bf8 av = *reinterpret_cast<const bf8*>(&rows[(16 * i + n) * kKRow + kq]);
-      acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, b0), acc[i][0], 0, 0, 0);
-      if (two) acc[i][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf8, b1), acc[i][1], 0, 0, 0);
+    for (int h = 0; h < 16; h += NB) {
+      bf8 av[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) av[i] = *reinterpret_cast<const bf8*>(&rows[(16 * (h + i) + n) * kKRow + kq]);
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        acc[h + i][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], __builtin_bit_cast(bf8, b0), acc[h + i][0], 0, 0, 0);
+      if constexpr (TWO) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          acc[h + i][NT - 1] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], __builtin_bit_cast(bf8, b1), acc[h + i][NT - 1], 0, 0, 0);
+      }
     }
     // clear the rows: when every lane's band fit its register window, only the words
     // written (the wave's LDS operations run in order, so the reads above are done);
@@ -467,7 +519,7 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
     b0 = b0n;
     b1 = b1n;
     q0 = q1;
-    q1 = q2;
+    e1 = e2;
 #pragma unroll
     for (int u = 0; u < kWin; ++u) w0[u] = w1[u];
     fr2 = fr3;
@@ -475,7 +527,7 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
 
   // acc[i][j][r] = W'[rotation 16 j + n][pixel p0 + 16 i + 4 (lane >> 4) + r]
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < NT; ++j) {
     const int mr = 16 * j + n;
     if (mr >= nr) continue;
     float* out = Wp + (int64_t)cell_rot[r0 + mr] * ps + p0 + 4 * (lane >> 4);
@@ -505,10 +557,41 @@ __global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
   }
 }
 
+__global__ __launch_bounds__(256, 2) void cand_mstep_kernel(
+    const int4* __restrict__ groups, const int64_t* __restrict__ grp_off, int64_t n_groups, int nranges,
+    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const u4* __restrict__ runs,
+    int64_t n_list, const u4* __restrict__ fb, const int32_t* __restrict__ dense_band, const uint16_t* __restrict__ P,
+    const int32_t* __restrict__ cell_rot, int64_t ps, float* __restrict__ Wp, double* __restrict__ rho,
+    const double* __restrict__ rho_a, int accumulate) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[4 * kPair * kKRow];  // 81920 bytes
+  // workgroup 8 q + x (dispatch is round-robin over the 8 XCDs: it runs on XCD x)
+  // takes range q mod nranges of group 8 (q / nranges) + x, so a group's ranges run
+  // one after another on one XCD and share its P in that XCD's L2
+  const int64_t q = blockIdx.x >> 3;
+  const int64_t g = 8 * (q / nranges) + (blockIdx.x & 7);
+  const int pr = (int)(q % nranges);
+  if (g >= n_groups) return;  // padding of the group count to a multiple of 8 (uniform)
+  if (groups[g].z > 16)
+    cand_mstep_range<true>(lds, g, pr, groups, grp_off, cf_ptr, cf_frame, runs, n_list, fb, dense_band, P, cell_rot,
+                           ps, Wp, rho, rho_a, accumulate);
+  else
+    cand_mstep_range<false>(lds, g, pr, groups, grp_off, cf_ptr, cf_frame, runs, n_list, fb, dense_band, P, cell_rot,
+                            ps, Wp, rho, rho_a, accumulate);
+}
+
 // ------------------------------------------------------------------ band-blocked frames
-// Chunks of every (band, listed frame), band-major: cnt[b * n_frames + f] (one wave
-// per frame, two pixels per lane per band); counts above 256 (not exact in BF16)
-// set *over.
+
+// Position of (band b, frame f) in the chunk order: runs of kRun bands, frame-major
+// inside a run (the last run may hold fewer bands).
+__device__ __forceinline__ int64_t band_slot(int b, int64_t f, int64_t n_frames, int nb) {
+  const int r0 = b - b % kRun;
+  const int q = nb - r0 < kRun ? nb - r0 : kRun;
+  return (int64_t)r0 * n_frames + f * q + (b - r0);
+}
+
+// Chunks of every (band, listed frame) in the chunk order: cnt[band_slot(b, f)]
+// (one wave per frame, two pixels per lane per band); counts above 256 (not exact
+// in BF16) set *over.
 __global__ __launch_bounds__(256) void band_count_kernel(const uint16_t* __restrict__ counts,
                                                          const uint8_t* __restrict__ mask, int n_pix,
                                                          const int32_t* __restrict__ frames, int64_t n_frames, int nb,
@@ -527,30 +610,51 @@ __global__ __launch_bounds__(256) void band_count_kernel(const uint16_t* __restr
       big |= v > 256u;
       n += __popcll(__ballot(v != 0u));
     }
-    if (lane == 0) cnt[(int64_t)b * n_frames + f] = (n + 7) >> 3;
+    if (lane == 0) cnt[band_slot(b, f, n_frames, nb)] = (n + 7) >> 3;
   }
   if (__ballot(big) != 0ull && lane == 0) atomicOr(over, 1);
 }
 
-// band_range[e] = (ptr[e], ptr[e + 1]) as int32 chunk indices
-__global__ void band_range_kernel(const int64_t* __restrict__ ptr, int64_t n, int2* __restrict__ band_range) {
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
-    band_range[e] = make_int2((int)ptr[e], (int)ptr[e + 1]);
+// Run records from the chunk offsets ptr (exclusive scan of the counts in band_slot
+// order; a run's bands are consecutive there): runs[f * n_runs + r] (frame-major,
+// for kernels that stream one frame per lane) and the run-major copy
+// runs[n_frames * n_runs + r * n_frames + f] (for the M-step, whose workgroup reads
+// one run of many frames)
+__global__ void run_table_kernel(const int64_t* __restrict__ ptr, int64_t n_frames, int nb, u4* __restrict__ runs) {
+  const int n_runs = (nb + kRun - 1) / kRun;
+  const int64_t n = n_frames * n_runs;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const int64_t f = e / n_runs;
+    const int b0 = (int)(e - f * n_runs) * kRun;
+    const int q = nb - b0 < kRun ? nb - b0 : kRun;
+    const int64_t s = band_slot(b0, f, n_frames, nb);
+    const int64_t first = ptr[s];
+    const uint32_t total = (uint32_t)(ptr[s + q] - first);
+    uint32_t off[kRun];
+#pragma unroll
+    for (int i = 0; i < kRun; ++i) off[i] = i < q ? (uint32_t)(ptr[s + i] - first) : total;
+    const u4 rec = {(uint32_t)first, off[0] | off[1] << 8 | off[2] << 16 | off[3] << 24,
+                    off[4] | off[5] << 8 | off[6] << 16 | off[7] << 24, total};
+    runs[e] = rec;
+    runs[n + (e - f * n_runs) * n_frames + f] = rec;
+  }
 }
 
 // Fill: words (pixel in band << 9 | count) in pixel order, chunk tails padded
 __global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restrict__ counts,
                                                         const uint8_t* __restrict__ mask, int n_pix,
                                                         const int32_t* __restrict__ frames, int64_t n_frames, int nb,
-                                                        const int2* __restrict__ band_range,
-                                                        uint16_t* __restrict__ words) {
+                                                        const u4* __restrict__ runs, uint16_t* __restrict__ words) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (f >= n_frames) return;
   const uint16_t* row = counts + (int64_t)frames[f] * n_pix;
   const unsigned long long below = (1ull << lane) - 1ull;
+  const int n_runs = (nb + kRun - 1) / kRun;
+  u4 rec = {0u, 0u, 0u, 0u};
   for (int b = 0; b < nb; ++b) {
-    const int2 r = band_range[(int64_t)b * n_frames + f];
+    if (b % kRun == 0) rec = runs[f * n_runs + b / kRun];
+    const int2 r = run_band(rec, b % kRun);
     if (r.x == r.y) continue;  // uniform: empty band
     uint16_t* out = words + (int64_t)r.x * 8;
     int n = 0;
@@ -570,7 +674,7 @@ __global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restri
 // 64 consecutive frames, lane = frame, so a band's table entries and chunks are read
 // contiguously and a dense band keeps every lane busy; wave w takes bands w, w + 4,
 // ..., and the four partial sums are added in a fixed order.
-__global__ __launch_bounds__(256) void band_dot_kernel(const int2* __restrict__ band_range, int nb,
+__global__ __launch_bounds__(256) void band_dot_kernel(const u4* __restrict__ runs, int nb,
                                                        const u4* __restrict__ chunks, int64_t n_frames,
                                                        const double* __restrict__ cvec, double* __restrict__ b) {
   __shared__ double part[4][64];
@@ -579,7 +683,7 @@ __global__ __launch_bounds__(256) void band_dot_kernel(const int2* __restrict__ 
   double acc = 0.0;
   if (f < n_frames) {
     for (int band = wave; band < nb; band += 4) {
-      const int2 r = band_range[(int64_t)band * n_frames + f];
+      const int2 r = run_band(runs[f * ((nb + kRun - 1) / kRun) + band / kRun], band % kRun);
       const double* cb = cvec + band * kBand;
       for (int ch = r.x; ch < r.y; ++ch) {
         const u4 w = chunks[ch];
@@ -605,12 +709,12 @@ __global__ __launch_bounds__(256) void band_dot_kernel(const int2* __restrict__ 
 // workgroup per band sums the chunk counts, then one thread assigns the indices.
 constexpr int kDenseChunks = 3;
 constexpr int kMaxDense = 16;
-__global__ __launch_bounds__(256) void band_mean_kernel(const int32_t* __restrict__ cnt, int64_t n_frames,
+__global__ __launch_bounds__(256) void band_mean_kernel(const int32_t* __restrict__ cnt, int64_t n_frames, int nb,
                                                         float* __restrict__ mean) {
   __shared__ double red[4];
   const int b = blockIdx.x;
   double s = 0.0;
-  for (int64_t f = threadIdx.x; f < n_frames; f += 256) s += cnt[(int64_t)b * n_frames + f];
+  for (int64_t f = threadIdx.x; f < n_frames; f += 256) s += cnt[band_slot(b, f, n_frames, nb)];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -752,11 +856,11 @@ __global__ __launch_bounds__(256) void audit_recall_kernel(const __hip_bfloat16*
 
 // ===================================================================== launchers
 hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* groups, const int64_t* grp_off,
-                              const int64_t* cf_ptr, const int32_t* cf_frame, const int2* band_range, int64_t n_list,
-                              const void* chunks, const int32_t* cell_rot, const void* hilo, int64_t plane,
-                              const float* scale, int64_t ps, float* G, hipStream_t st) {
+                              const int64_t* cf_ptr, const int32_t* cf_frame, const void* runs, const void* chunks,
+                              const int32_t* cell_rot, const void* hilo, int64_t plane, const float* scale, int64_t ps,
+                              float* G, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  cand_loglik_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, band_range, n_list,
+  cand_loglik_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, (const u4*)runs,
                                                         (const u4*)chunks, cell_rot, (const uint16_t*)hilo, plane,
                                                         scale, ps, G);
   return hipGetLastError();
@@ -780,14 +884,14 @@ hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const 
 }
 
 hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
-                             const int32_t* cf_frame, const int2* band_range, int64_t n_list, const void* chunks,
+                             const int32_t* cf_frame, const void* runs, int64_t n_list, const void* chunks,
                              const int32_t* dense_band, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
                              double* rho, const double* rho_a, bool accumulate, hipStream_t st) {
   if (n_groups <= 0) return hipSuccess;
   const int nranges = (int)((ps + 4 * kPair - 1) / (4 * kPair));
   const int64_t g8 = (n_groups + 7) / 8 * 8;
   cand_mstep_kernel<<<(unsigned)(g8 * nranges), 256, 0, st>>>(groups, grp_off, n_groups, nranges, cf_ptr, cf_frame,
-                                                                    band_range, n_list, (const u4*)chunks, dense_band,
+                                                                    (const u4*)runs, n_list, (const u4*)chunks, dense_band,
                                                                     (const uint16_t*)P, cell_rot, ps, Wp, rho, rho_a,
                                                                     accumulate ? 1 : 0);
   return hipGetLastError();
@@ -801,25 +905,28 @@ hipError_t launch_band_count(const uint16_t* counts, const uint8_t* mask, int n_
   return hipGetLastError();
 }
 
-hipError_t launch_band_range(const int64_t* ptr, int64_t n, int2* band_range, hipStream_t st) {
+int run_count(int nbands) { return (nbands + kRun - 1) / kRun; }
+
+hipError_t launch_run_table(const int64_t* ptr, int64_t n_frames, int nbands, void* runs, hipStream_t st) {
+  const int64_t n = n_frames * run_count(nbands);
   if (n <= 0) return hipSuccess;
   const int64_t g = (n + 255) / 256;
-  band_range_kernel<<<(unsigned)(g > 65536 ? 65536 : g), 256, 0, st>>>(ptr, n, band_range);
+  run_table_kernel<<<(unsigned)(g > 65536 ? 65536 : g), 256, 0, st>>>(ptr, n_frames, nbands, (u4*)runs);
   return hipGetLastError();
 }
 
 hipError_t launch_band_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                            int64_t n_frames, int nbands, const int2* band_range, void* chunks, hipStream_t st) {
+                            int64_t n_frames, int nbands, const void* runs, void* chunks, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
   band_fill_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(counts, mask, n_pix, frames, n_frames, nbands,
-                                                                   band_range, (uint16_t*)chunks);
+                                                                   (const u4*)runs, (uint16_t*)chunks);
   return hipGetLastError();
 }
 
-hipError_t launch_band_dot(const int2* band_range, int nbands, const void* chunks, int64_t n_frames, const double* c,
+hipError_t launch_band_dot(const void* runs, int nbands, const void* chunks, int64_t n_frames, const double* c,
                            double* b, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
-  band_dot_kernel<<<(unsigned)((n_frames + 63) / 64), 256, 0, st>>>(band_range, nbands, (const u4*)chunks, n_frames,
+  band_dot_kernel<<<(unsigned)((n_frames + 63) / 64), 256, 0, st>>>((const u4*)runs, nbands, (const u4*)chunks, n_frames,
                                                                    c, b);
   return hipGetLastError();
 }
@@ -827,7 +934,7 @@ hipError_t launch_band_dot(const int2* band_range, int nbands, const void* chunk
 hipError_t launch_dense_bands(const int32_t* cnt, int64_t n_frames, int nbands, float* mean, int32_t* dense_band,
                               int32_t* dense_list, int32_t* n_dense, hipStream_t st) {
   if (n_frames > 0 && nbands > 0) {
-    band_mean_kernel<<<(unsigned)nbands, 256, 0, st>>>(cnt, n_frames, mean);
+    band_mean_kernel<<<(unsigned)nbands, 256, 0, st>>>(cnt, n_frames, nbands, mean);
   } else if (nbands > 0) {  // no frames: every band's mean is zero (the bits of 0.0f)
     const hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(mean), nbands, 0, st);
     if (e != hipSuccess) return e;

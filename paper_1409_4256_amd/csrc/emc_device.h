@@ -191,9 +191,9 @@ hipError_t launch_scan64(const int64_t* cnt, int64_t n, int64_t* ptr, hipStream_
 
 // ---- candidate E/M steps (cand.hip) ----
 hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* groups, const int64_t* grp_off,
-                              const int64_t* cf_ptr, const int32_t* cf_frame, const int2* band_range, int64_t n_list,
-                              const void* chunks, const int32_t* cell_rot, const void* hilo, int64_t plane,
-                              const float* scale, int64_t ps, float* G, hipStream_t st);
+                              const int64_t* cf_ptr, const int32_t* cf_frame, const void* runs, const void* chunks,
+                              const int32_t* cell_rot, const void* hilo, int64_t plane, const float* scale, int64_t ps,
+                              float* G, hipStream_t st);
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
                              int64_t n_frames, const int32_t* cell_rot, int64_t n_rot, const double* log_w,
@@ -201,7 +201,7 @@ hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const 
                              const int2* tiles, int64_t n_tiles, const int64_t* cf_ptr, const int32_t* cf_frame,
                              hipStream_t st);
 hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
-                             const int32_t* cf_frame, const int2* band_range, int64_t n_list, const void* chunks,
+                             const int32_t* cf_frame, const void* runs, int64_t n_list, const void* chunks,
                              const int32_t* dense_band, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,
                              double* rho, const double* rho_a, bool accumulate, hipStream_t st);
 hipError_t launch_dense_bands(const int32_t* cnt, int64_t n_frames, int nbands, float* mean, int32_t* dense_band,
@@ -219,9 +219,12 @@ hipError_t launch_gate_zero(const double* recall, double recall_min, float* Wp, 
 hipError_t launch_band_count(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
                              int64_t n_frames, int nbands, int32_t* cnt, int32_t* over, hipStream_t st);
 hipError_t launch_band_fill(const uint16_t* counts, const uint8_t* mask, int n_pix, const int32_t* frames,
-                            int64_t n_frames, int nbands, const int2* band_range, void* chunks, hipStream_t st);
-hipError_t launch_band_range(const int64_t* ptr, int64_t n, int2* band_range, hipStream_t st);
-hipError_t launch_band_dot(const int2* band_range, int nbands, const void* chunks, int64_t n_frames, const double* c,
+                            int64_t n_frames, int nbands, const void* runs, void* chunks, hipStream_t st);
+// run records of the chunk layout: 16 bytes per (frame, run of 8 bands), run_count(nbands) per frame,
+// frame-major, then a run-major copy
+int run_count(int nbands);
+hipError_t launch_run_table(const int64_t* ptr, int64_t n_frames, int nbands, void* runs, hipStream_t st);
+hipError_t launch_band_dot(const void* runs, int nbands, const void* chunks, int64_t n_frames, const double* c,
                            double* b, hipStream_t st);
 hipError_t launch_cell_groups(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int32_t* cnt,
                               int64_t* cg_ptr, int4* groups, int64_t* gsize, int64_t* grp_off, int64_t g_max,

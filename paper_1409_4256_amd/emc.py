@@ -85,7 +85,7 @@ class Proposal(ctypes.Structure):
         ("pair_col", ctypes.c_void_p), ("cf_ptr", ctypes.c_void_p), ("cf_frame", ctypes.c_void_p),
         ("cg_ptr", ctypes.c_void_p), ("groups", ctypes.c_void_p), ("grp_off", ctypes.c_void_p),
         ("tiles", ctypes.c_void_p), ("mask_audit", ctypes.c_void_p),
-        ("chunks", ctypes.c_void_p), ("band_range", ctypes.c_void_p),
+        ("chunks", ctypes.c_void_p), ("runs", ctypes.c_void_p),
         ("n_dense", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("ld_dense", ctypes.c_int64),
         ("dense_band", ctypes.c_void_p), ("dense_list", ctypes.c_void_p), ("kt_dense", ctypes.c_void_p),
         ("n_rot", ctypes.c_int32), ("n_pix", ctypes.c_int32), ("quat", ctypes.c_void_p), ("mask", ctypes.c_void_p),
