@@ -410,9 +410,11 @@ def proposal_form(inp, args, counts_dev, compare=True):
         torch.cuda.synchronize()
         t_plan = time.perf_counter() - t0
         n_pairs = prop.candidate_pairs()
+        n_comp = prop.computed_pairs()
         log(f"{name}: plan with {n_pairs} candidate (rotation, frame) pairs "
-            f"({n_pairs / (wl.n_rot * wl.n_data):.4f} of the full search), {prop.plan.n_groups} rotation groups, "
-            f"{prop.plan.n_tiles} tiles, built in {t_plan:.1f} s")
+            f"({n_pairs / (wl.n_rot * wl.n_data):.4f} of the full search; {n_comp} computed over {prop.plan.n_packs} "
+            f"packs of cells), {prop.plan.n_groups} rotation groups, {prop.plan.n_tiles} tiles, built in "
+            f"{t_plan:.1f} s")
         # proposal iterations, timed with the audit verdict and any fallback included; the
         # library records events at its stage boundaries (per-kernel durations)
         per, recs, fallbacks, stages = [], [], 0, []

@@ -410,11 +410,15 @@ emc_status emc_pack_frames_list(const emc_problem* pb, const uint16_t* counts, c
                                 void* K_packed, hipStream_t stream);
 
 /* Proposal plan: arrays carved from one caller buffer by emc_proposal_build.
- * Frames are split into audited ones and candidate ones (grouped by their
- * first proposed cell).  The fine rotations of each cell are split into
- * groups of at most 32; a group's storage in G and P is Fp x 32 elements,
- * Fp = the cell's frame list length rounded up to 32.  All pointers are
- * device pointers into the plan buffer.                                        */
+ * Frames are split into audited ones and candidate ones (grouped by the pack of
+ * their first proposed cell).  Neighbouring coarse cells are gathered into
+ * packs of at most 16 fine rotations in all, one 16-row MFMA tile (nearest
+ * neighbours first; a cell with more rotations is a pack of its own); a pack is searched over the union
+ * of its cells' frame lists, and only the pairs whose cell the frame proposes
+ * enter the E-step.  A pack's rotations are split into groups of at most 32;
+ * a group's storage in G and P is Fp x 32 elements, Fp = the pack's frame list
+ * length rounded up to 32.  All pointers are device pointers into the plan
+ * buffer.                                                                      */
 typedef struct emc_proposal {
   int32_t n_cells;        /* coarse cells                                           */
   int32_t k_top;          /* entries of each frame's proposal list (<= 256)         */
@@ -429,14 +433,25 @@ typedef struct emc_proposal {
   int32_t* cell_of;       /* [n_rot] coarse cell of each rotation (max |<q, q_c>|)  */
   int64_t* cell_ptr;      /* [n_cells + 1] rotations of cell c: cell_rot[ptr[c]..)  */
   int32_t* cell_rot;      /* [n_rot]                                                */
-  int32_t* cand_frames;   /* [n_cand] frame index, grouped by first proposed cell   */
+  int32_t* pack_of;       /* [n_cells] pack of each cell                            */
+  int32_t* cell_first;    /* [n_cells] position of cell c's first rotation in
+                             pack_rot (its count: cell_ptr[c + 1] - cell_ptr[c])   */
+  int32_t* pack_rot;      /* [n_rot] rotations in pack order, cell by cell          */
+  int32_t* rot_local;     /* [n_rot] index inside its pack of the cell of
+                             pack_rot[t] (< 32)                                     */
+  int32_t* cand_frames;   /* [n_cand] frame index, grouped by the pack of the
+                             frame's first proposed cell                           */
   int32_t* audit_frames;  /* [n_audit] frame index of the audited frames            */
   int32_t* cand_cells;    /* [n_cand][k_top] proposed cells (-1: none)              */
-  int32_t* pair_col;      /* [n_cand][k_top] position of the frame in the cell's list */
-  int64_t* cf_ptr;        /* [n_cells + 1] frame list of cell c: cf_frame[ptr[c]..) */
+  int32_t* pair_col;      /* [n_cand][k_top] position of the frame in the list of
+                             its cell's pack                                        */
+  int64_t* cf_ptr;        /* [n_cells + 1] frame list of pack p: cf_frame[ptr[p]..)
+                             (packs n_packs.. are empty)                            */
   int32_t* cf_frame;      /* [n_cand * k_top] candidate-frame index                 */
-  int64_t* cg_ptr;        /* [n_cells + 1] groups of cell c: [cg_ptr[c], cg_ptr[c+1]) */
-  void* groups;           /* [n_groups] int32 x 4: cell, first cell_rot entry, count, 0 */
+  uint32_t* cf_mask;      /* [n_cand * k_top] per pack-list entry: bit i set when
+                             the frame proposes the pack's i-th cell               */
+  int64_t* cg_ptr;        /* [n_cells + 1] groups of pack p: [cg_ptr[p], cg_ptr[p+1]) */
+  void* groups;           /* [n_groups] int32 x 4: pack, first pack_rot entry, count, 0 */
   int64_t* grp_off;       /* [n_groups + 1] element offset of each group's storage   */
   void* tiles;            /* [n_tiles] int32 x 2: group, first frame; (-1, 0) padding */
   uint32_t* mask_audit;   /* [n_audit][words] proposed cells of the audited frames  */
@@ -454,7 +469,7 @@ typedef struct emc_proposal {
                              run-major, [ceil(n_bands / 8)][n_cand]                */
   int32_t n_dense;        /* dense bands (frames average >= 3 chunks; <= 16): their
                              M-step columns are one dense product                  */
-  int32_t reserved2;
+  int32_t n_packs;        /* packs of cells                                         */
   int64_t ld_dense;       /* n_cand rounded up to 256                               */
   int32_t* dense_band;    /* [n_bands] index among the dense bands, or -1           */
   int32_t* dense_list;    /* [16] band of each dense index                          */

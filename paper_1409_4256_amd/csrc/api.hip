@@ -1009,9 +1009,10 @@ int64_t chunk_cap(int64_t nz_cap, int64_t n_cand, int n_pix) { return (nz_cap + 
 
 // Carving of the plan buffer (capacities known before the build).
 struct PlanLayout {
-  size_t cell_of, cell_ptr, cell_rot, cand_frames, audit_frames, cand_cells, pair_col, cf_ptr, cf_frame, cg_ptr,
-      groups, grp_off, tiles, mask_audit, chunks, runs, band_cnt, band_ptr, dense_band, dense_list, kt_dense,
-      band_mean, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd, cnt, scalars, total;
+  size_t cell_of, cell_ptr, cell_rot, pack_of, cell_first, pack_rot, rot_local, cand_frames, audit_frames, cand_cells,
+      pair_col, cf_ptr, cf_frame, cf_mask, cg_ptr, groups, grp_off, tiles, mask_audit, chunks, runs, band_cnt,
+      band_ptr, dense_band, dense_list, kt_dense, band_mean, hist, cursor, keys, order, mark, frame_ptr, gsize, xcd,
+      cnt, nn, slot_cell, pack_slot, slot_cnt, slot_ptr, cell_slot, pack_ptr, bits, prim, scalars, total;
 };
 
 PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top, int n_audit, int64_t nz_cap) {
@@ -1030,12 +1031,17 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.cell_of = take((int64_t)n_rot * 4);
   L.cell_ptr = take((int64_t)(n_cells + 2) * 8);
   L.cell_rot = take((int64_t)n_rot * 4);
+  L.pack_of = take((int64_t)n_cells * 4);
+  L.cell_first = take((int64_t)n_cells * 4);
+  L.pack_rot = take((int64_t)n_rot * 4);
+  L.rot_local = take((int64_t)n_rot * 4);
   L.cand_frames = take(n_cand * 4);
   L.audit_frames = take((int64_t)n_audit * 4);
   L.cand_cells = take(n_pairs * 4);
   L.pair_col = take(n_pairs * 4);
   L.cf_ptr = take((int64_t)(n_cells + 2) * 8);
   L.cf_frame = take(n_pairs * 4);
+  L.cf_mask = take(n_pairs * 4);
   L.cg_ptr = take((int64_t)(n_cells + 1) * 8);
   L.groups = take(g_max * 16);
   L.grp_off = take((g_max + 1) * 8);
@@ -1059,6 +1065,15 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
   L.gsize = take(g_max * 8);
   L.xcd = take(g_max * 4);
   L.cnt = take((int64_t)n_cells * 4);
+  L.nn = take((int64_t)n_cells * 16 * 4);
+  L.slot_cell = take((int64_t)n_cells * 4);
+  L.pack_slot = take((int64_t)(n_cells + 1) * 4);
+  L.slot_cnt = take((int64_t)n_cells * 4);
+  L.slot_ptr = take((int64_t)(n_cells + 1) * 8);
+  L.cell_slot = take((int64_t)n_cells * 4);
+  L.pack_ptr = take((int64_t)(n_cells + 1) * 8);
+  L.bits = take(n_pairs * 4);
+  L.prim = take(n_pairs * 4);
   L.scalars = take(64);
   L.total = o;
   return L;
@@ -1068,12 +1083,14 @@ PlanLayout plan_layout(int n_rot, int n_data, int n_pix, int n_cells, int k_top,
 
 namespace emc {
 __global__ void top1_keys_kernel(const int32_t* __restrict__ topk, int k_top, const int32_t* __restrict__ mark,
-                                 int64_t n, int n_cells, int32_t* __restrict__ keys) {
+                                 const int32_t* __restrict__ pack_of, int64_t n, int n_cells,
+                                 int32_t* __restrict__ keys) {
   const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (f >= n) return;
   const int32_t c = topk[f * k_top];
-  // audited frames sort after every cell; frames without a valid proposal go to the last cell
-  keys[f] = mark[f] ? n_cells : (c >= 0 && c < n_cells ? c : n_cells - 1);
+  // the pack of the first proposed cell; audited frames sort after every pack,
+  // frames without a valid proposal go to the last key below them
+  keys[f] = mark[f] ? n_cells : (c >= 0 && c < n_cells ? pack_of[c] : n_cells - 1);
 }
 __global__ void mark_kernel(const int32_t* __restrict__ audit, int64_t n_audit, int64_t n_data,
                             int32_t* __restrict__ mark) {
@@ -1143,12 +1160,17 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   P.cell_of = (int32_t*)(b + L.cell_of);
   P.cell_ptr = (int64_t*)(b + L.cell_ptr);
   P.cell_rot = (int32_t*)(b + L.cell_rot);
+  P.pack_of = (int32_t*)(b + L.pack_of);
+  P.cell_first = (int32_t*)(b + L.cell_first);
+  P.pack_rot = (int32_t*)(b + L.pack_rot);
+  P.rot_local = (int32_t*)(b + L.rot_local);
   P.cand_frames = (int32_t*)(b + L.cand_frames);
   P.audit_frames = (int32_t*)(b + L.audit_frames);
   P.cand_cells = (int32_t*)(b + L.cand_cells);
   P.pair_col = (int32_t*)(b + L.pair_col);
   P.cf_ptr = (int64_t*)(b + L.cf_ptr);
   P.cf_frame = (int32_t*)(b + L.cf_frame);
+  P.cf_mask = (uint32_t*)(b + L.cf_mask);
   P.cg_ptr = (int64_t*)(b + L.cg_ptr);
   P.groups = (void*)(b + L.groups);
   P.grp_off = (int64_t*)(b + L.grp_off);
@@ -1174,29 +1196,46 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   int32_t* cnt = (int32_t*)(b + L.cnt);
   int64_t* scal = (int64_t*)(b + L.scalars);  // [0] n_tiles, [1] flags (int32): 1 count range, 2 repeated cell
   int32_t* over = (int32_t*)(scal + 1);
-  // 1. coarse cell of every fine rotation; rotations grouped by cell
+  // 1. coarse cell of every fine rotation; rotations grouped by cell; packs of
+  // neighbouring cells and the rotations in pack order
   HIP_TRY(launch_assign_cells(pb->quat, pb->n_rot, coarse, n_cells, P.cell_of, st), "assign cells");
   HIP_TRY(launch_counting_sort(P.cell_of, pb->n_rot, n_cells, hist, cursor, P.cell_ptr, P.cell_rot, nullptr, st),
           "sort rotations");
+  int32_t* cell_slot = (int32_t*)(b + L.cell_slot);
+  int32_t* pack_slot = (int32_t*)(b + L.pack_slot);
+  int64_t* pack_ptr = (int64_t*)(b + L.pack_ptr);
+  int32_t* n_packs_dev = (int32_t*)(scal + 3);
+  HIP_TRY(launch_packs(coarse, n_cells, P.cell_ptr, P.cell_of, P.cell_rot, pb->n_rot, (int32_t*)(b + L.nn), P.pack_of,
+                       (int32_t*)(b + L.slot_cell), pack_slot, n_packs_dev, (int32_t*)(b + L.slot_cnt),
+                       (int64_t*)(b + L.slot_ptr), cell_slot, P.cell_first, pack_ptr, P.pack_rot, P.rot_local, st),
+          "packs");
   // 2. frames: audited ones apart, the others grouped by their first proposed cell
   HIP_TRY(launch_fill_i32(mark, n_data, 0, st), "mark");
   if (n_audit > 0)
     emc::mark_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(audit, n_audit, n_data, mark);
-  emc::top1_keys_kernel<<<(unsigned)((n_data + 255) / 256), 256, 0, st>>>(topk, k_top, mark, n_data, n_cells, keys);
+  emc::top1_keys_kernel<<<(unsigned)((n_data + 255) / 256), 256, 0, st>>>(topk, k_top, mark, P.pack_of, n_data,
+                                                                           n_cells, keys);
   HIP_TRY(launch_counting_sort(keys, n_data, n_cells + 1, hist, cursor, frame_ptr, order, nullptr, st), "sort frames");
   if (n_cand > 0) emc::copy_i32_kernel<<<(unsigned)((n_cand + 255) / 256), 256, 0, st>>>(order, n_cand, P.cand_frames);
   if (n_audit > 0)
     emc::copy_i32_kernel<<<(unsigned)((n_audit + 255) / 256), 256, 0, st>>>(order + n_cand, n_audit, P.audit_frames);
   HIP_TRY(launch_cand_mask(topk, k_top, P.audit_frames, n_audit, w, P.mask_audit, st), "audit masks");
-  // 3. (frame, proposed cell) pairs grouped by cell: each cell's frame list
+  // 3. (frame, proposed cell) pairs: each pack's frame list, every frame once with
+  // the bits of the pack's cells it proposes
   HIP_TRY(launch_fill_i32(over, 1, 0, st), "flags");
   HIP_TRY(launch_cand_cells(topk, k_top, P.cand_frames, n_cand, n_cells, P.cand_cells, keys, st), "candidate cells");
   HIP_TRY(launch_dup_check(P.cand_cells, k_top, n_cand, n_cells, over, st), "repeated cells");
+  uint32_t* bits = (uint32_t*)(b + L.bits);
+  int32_t* prim = (int32_t*)(b + L.prim);
+  HIP_TRY(launch_pack_pairs(P.cand_cells, k_top, n_cand, P.pack_of, cell_slot, pack_slot, n_cells, keys, bits, prim,
+                            st),
+          "pack pairs");
   HIP_TRY(launch_counting_sort(keys, n_pairs, n_cells + 1, hist, cursor, P.cf_ptr, order, nullptr, st), "sort pairs");
-  HIP_TRY(launch_pair_columns(order, n_pairs, k_top, keys, P.cf_ptr, P.cf_frame, P.pair_col, st), "pair columns");
-  // 4. groups of up to 32 rotations per cell, their storage and the log-likelihood tiles
-  HIP_TRY(launch_cell_groups(P.cell_ptr, P.cf_ptr, n_cells, cnt, P.cg_ptr, (int4*)P.groups, gsize, P.grp_off, g_max,
-                             st),
+  HIP_TRY(launch_pack_columns(order, P.cf_ptr, n_cells, n_pairs, k_top, keys, bits, prim, P.cf_frame, P.cf_mask,
+                              P.pair_col, st),
+          "pair columns");
+  // 4. groups of up to 32 rotations per pack, their storage and the log-likelihood tiles
+  HIP_TRY(launch_cell_groups(pack_ptr, P.cf_ptr, n_cells, cnt, P.cg_ptr, (int4*)P.groups, gsize, P.grp_off, g_max, st),
           "groups");
   HIP_TRY(launch_group_tiles((const int4*)P.groups, P.cg_ptr, n_cells, P.cf_ptr, xcd, (int2*)P.tiles,
                              tile_cap(g_max, n_cand), scal, st),
@@ -1209,9 +1248,10 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
   HIP_TRY(launch_dense_bands(band_cnt, n_cand, ntab - 1, (float*)(b + L.band_mean), P.dense_band, P.dense_list,
                              n_dense_dev, st),
           "dense bands");
-  int64_t host[6] = {0, 0, 0, 0, 0, 0};
+  int64_t host[7] = {0, 0, 0, 0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(&host[0], scal, 16, hipMemcpyDeviceToHost, st), "read n_tiles");
   HIP_TRY(hipMemcpyAsync(&host[5], n_dense_dev, 4, hipMemcpyDeviceToHost, st), "read n_dense");
+  HIP_TRY(hipMemcpyAsync(&host[6], n_packs_dev, 4, hipMemcpyDeviceToHost, st), "read n_packs");
   HIP_TRY(hipMemcpyAsync(&host[2], P.cg_ptr + n_cells, 8, hipMemcpyDeviceToHost, st), "read n_groups");
   HIP_TRY(hipMemcpyAsync(&host[3], P.grp_off + g_max, 8, hipMemcpyDeviceToHost, st), "read n_g");
   HIP_TRY(hipMemcpyAsync(&host[4], band_ptr + n_fb, 8, hipMemcpyDeviceToHost, st), "read n_chunks");
@@ -1228,6 +1268,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
                            P.chunks, st),
           "band fill");
   P.n_dense = (int32_t)host[5];
+  P.n_packs = (int32_t)host[6];
   HIP_TRY(launch_dense_pack(counts, pb->mask, pb->n_pix, P.cand_frames, n_cand, P.ld_dense, P.n_dense, P.dense_list,
                             P.kt_dense, st),
           "dense pack");
@@ -1299,7 +1340,7 @@ PropWs prop_ws(const emc_problem* pb, const emc_proposal* P) {
   W.Pd = take(P->n_dense > 0 ? (int64_t)pb->n_rot * P->ld_dense * 2 : 0);
   W.Wd = take((int64_t)pb->n_rot * P->n_dense * kBandPx * 4 * dense_splits(pb, P));
   W.copies = take((int64_t)copies_bytes(pb));
-  W.cst = take((int64_t)pb->n_rot * 8);  // log w_j - S_j in the cells' rotation order
+  W.cst = take((int64_t)pb->n_rot * 8);  // log w_j - S_j in the packs' rotation order
   // partial products of the audit's split log-likelihood product
   const int as = audit_splits(pb, P);
   W.Ga_part = take(as > 1 ? (int64_t)as * pb->n_rot * dsa * 4 : 0);
@@ -1316,6 +1357,7 @@ emc_status check_plan(const emc_problem* pb, const emc_proposal* P) {
     return fail(EMC_ERR_INVALID_ARG, "plan frames (%d + %d) do not match n_data %d", P->n_cand, P->n_audit, pb->n_data);
   if (P->k_top < 1 || P->k_top > kMaxTop || P->n_cells < 1 || P->words != words_of(P->n_cells) || P->n_g < 0 ||
       P->n_tiles < 0 || P->n_tiles % 8 != 0 || P->n_groups < 1 || P->n_groups > group_cap(pb->n_rot, P->n_cells) ||
+      P->n_packs < 1 || P->n_packs > P->n_cells ||
       P->n_bands != ntab_of(pb->n_pix) - 1 || P->n_dense < 0 || P->n_dense > kMaxDense ||
       P->ld_dense != round_up(P->n_cand, 256))
     return fail(EMC_ERR_INVALID_ARG, "inconsistent plan");
@@ -1378,7 +1420,7 @@ emc_status run_proposed(const emc_problem* pb, const emc_proposal* plan, const v
   // candidate frames: log-likelihoods per (group, listed frame), E-step over each frame's candidates
   if (nc > 0) {
     HIP_TRY(launch_cand_loglik((const int2*)plan->tiles, plan->n_tiles, groups, plan->grp_off, plan->cf_ptr,
-                               plan->cf_frame, plan->runs, plan->chunks, plan->cell_rot,
+                               plan->cf_frame, plan->runs, plan->chunks, plan->pack_rot,
                                slices, (int64_t)pb->n_rot * ps, scale, ps, G, st),
             "candidate loglik");
   }
@@ -1387,9 +1429,11 @@ emc_status run_proposed(const emc_problem* pb, const emc_proposal* plan, const v
     // the dense bands' responsibility matrix is zero outside the candidate pairs
     if (Pd) HIP_TRY(launch_fill_zero_bytes(Pd, (int64_t)pb->n_rot * plan->ld_dense * 2, st), "zero dense P");
     HIP_TRY(launch_cand_estep(G, Pc, groups, plan->grp_off, plan->cg_ptr, plan->cand_cells, plan->pair_col,
-                              plan->k_top, nc, plan->cell_rot, pb->n_rot, pb->log_w, S, (double*)(w + W.cst), b, L,
+                              plan->k_top, nc, plan->pack_of, plan->cell_first, plan->cell_ptr, plan->pack_rot,
+                              plan->rot_local, pb->n_rot, pb->log_w, S, (double*)(w + W.cst), b, L,
                               Pd, plan->ld_dense,
-                              (const int2*)plan->tiles, plan->n_tiles, plan->cf_ptr, plan->cf_frame, st),
+                              (const int2*)plan->tiles, plan->n_tiles, plan->cf_ptr, plan->cf_frame, plan->cf_mask,
+                              st),
             "candidate estep");
   }
   CHECK(mark(3));
@@ -1414,7 +1458,7 @@ emc_status run_proposed(const emc_problem* pb, const emc_proposal* plan, const v
   }
   CHECK(mark(4));
   HIP_TRY(launch_cand_mstep(groups, plan->grp_off, plan->n_groups, plan->cf_ptr, plan->cf_frame,
-                            plan->runs, nc, plan->chunks, plan->dense_band, Pc, plan->cell_rot, ps,
+                            plan->runs, nc, plan->chunks, plan->dense_band, Pc, plan->pack_rot, ps,
                             Wp, rho, rho_a, na > 0, st),
           "candidate mstep");
   CHECK(mark(5));

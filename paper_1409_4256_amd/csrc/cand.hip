@@ -37,6 +37,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGR = 32;             // rotations per group (two 16-row MFMA tiles)
+static_assert(kPackRot <= kGR, "a pack of cells fits one group");
 constexpr int kFT = 64;             // frames per log-likelihood wave (four 16-column tiles)
 constexpr int kTileF = 4 * kFT;     // frames per log-likelihood workgroup (tile)
 constexpr int kBand = 128;          // pixels per band (granularity of the entry-offset table)
@@ -274,8 +275,13 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
 }
 
 // ------------------------------------------------------------------ E-step
+// The log-evidence does not evaluate a term more than kLseDrop below the running
+// maximum (below e^-64 of it: the frame's candidates together stay far below the
+// FP64 rounding of the sum).  Responsibilities keep every term; a - L is formed in
+// FP64 and its exponential evaluated in FP32 (P is stored in BF16).
+constexpr double kLseDrop = 64.0;
 __device__ __forceinline__ void lse_push(double& mx, double& s, double a) {
-  if (!(a > -INFINITY)) return;
+  if (!(a > mx - kLseDrop)) return;  // zero prior weight, or negligible against the maximum
   if (a > mx) {
     s = s * exp(mx - a) + 1.0;
     mx = a;
@@ -284,8 +290,8 @@ __device__ __forceinline__ void lse_push(double& mx, double& s, double a) {
   }
 }
 
-// The rotation term of a, log w_j - S_j, in the cells' rotation order (entry t
-// belongs to rotation cell_rot[t]), so that a group's terms are contiguous.
+// The rotation term of a, log w_j - S_j, in the packs' rotation order (entry t
+// belongs to rotation pack_rot[t]), so that a group's terms are contiguous.
 __global__ void cell_const_kernel(const int32_t* __restrict__ cell_rot, int64_t n_rot,
                                   const double* __restrict__ log_w, const double* __restrict__ S,
                                   double* __restrict__ cst) {
@@ -305,11 +311,13 @@ __device__ __forceinline__ void load_grow(const float* __restrict__ row, int nr,
 // Log-evidence of each candidate frame: one wave per frame, lanes take the frame's
 // proposed cells (slot t = lane + 64 u); a = Q + log w_j = G + b_f - S_j + log w_j
 // and L_f = log sum over the frame's candidates of e^a, in FP64 (eq. 2.4's
-// denominator).
+// denominator).  A cell's values sit in its pack's groups, at the frame's column
+// of the pack's list, over the cell's own rotations [cell_first, + its count).
 __global__ __launch_bounds__(256) void cand_estep_kernel(
     const float* __restrict__ G, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
     const int64_t* __restrict__ cg_ptr, const int32_t* __restrict__ cells, const int32_t* __restrict__ pair_col,
-    int k_top, int64_t n_frames, const double* __restrict__ cst, const double* __restrict__ b,
+    int k_top, int64_t n_frames, const int32_t* __restrict__ pack_of, const int32_t* __restrict__ cell_first,
+    const int64_t* __restrict__ cell_ptr, const double* __restrict__ cst, const double* __restrict__ b,
     double* __restrict__ L) {
   const int64_t f = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -319,9 +327,13 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
   for (int t = lane; t < k_top; t += 64) {
     const int c = cells[f * k_top + t];
     if (c < 0) continue;
+    const int p = pack_of[c];
+    const int lo = cell_first[c], hi = lo + (int)(cell_ptr[c + 1] - cell_ptr[c]);
     const int64_t col = pair_col[f * k_top + t];
-    for (int64_t g = cg_ptr[c]; g < cg_ptr[c + 1]; ++g) {
+    for (int64_t g = cg_ptr[p]; g < cg_ptr[p + 1]; ++g) {
       const int4 gr = groups[g];
+      const int a = (lo > gr.y ? lo : gr.y) - gr.y, z = (hi < gr.y + gr.z ? hi : gr.y + gr.z) - gr.y;
+      if (a >= z) continue;
       f4 v[kGR / 4];
       load_grow(G + grp_off[g] + col * kGR, gr.z, v);
       const double* cr = cst + gr.y;
@@ -329,7 +341,7 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
       for (int q = 0; q < kGR / 4; ++q)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (4 * q + u < gr.z) lse_push(mx, sum, ((double)v[q][u] + bk) + cr[4 * q + u]);
+          if (4 * q + u >= a && 4 * q + u < z) lse_push(mx, sum, ((double)v[q][u] + bk) + cr[4 * q + u]);
     }
   }
 #pragma unroll
@@ -345,17 +357,20 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
   if (lane == 0) L[f] = mx + log(sum);
 }
 
-// Responsibilities of the candidate pairs, group-major over the log-likelihood's
-// tiles (group g, list positions f0 .. f0 + 255; wave w, lane s: position
-// f0 + 64 w + s): P = exp(a - L_f) in BF16 (eq. 2.4) into the group's blocked P,
-// where 32 consecutive lanes fill one 64-byte row of a [32 rot][32 frames] block,
-// and, with Pd, into the dense [rotation][frame] matrix of the M-step's dense
-// bands (a list's frames come in runs of consecutive numbers).
+// Responsibilities of the group's (rotation, listed frame) pairs, group-major over
+// the log-likelihood's tiles (group g, list positions f0 .. f0 + 255; wave w, lane
+// s: position f0 + 64 w + s): P = exp(a - L_f) in BF16 (eq. 2.4) for a rotation
+// whose cell the frame proposes, 0 for the pack's other cells, into the group's
+// blocked P, where 32 consecutive lanes fill one 64-byte row of a [32 rot][32
+// frames] block, and, with Pd, the proposed pairs into the dense [rotation][frame]
+// matrix of the M-step's dense bands (a list's frames come in runs of consecutive
+// numbers).
 __global__ __launch_bounds__(256) void cand_pwrite_kernel(
     const int2* __restrict__ tiles, const int4* __restrict__ groups, const int64_t* __restrict__ grp_off,
-    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const float* __restrict__ G,
-    const int32_t* __restrict__ cell_rot, const double* __restrict__ cst, const double* __restrict__ b,
-    const double* __restrict__ L, uint16_t* __restrict__ P, uint16_t* __restrict__ Pd, int64_t ldd) {
+    const int64_t* __restrict__ cf_ptr, const int32_t* __restrict__ cf_frame, const uint32_t* __restrict__ cf_mask,
+    const float* __restrict__ G, const int32_t* __restrict__ pack_rot, const int32_t* __restrict__ rot_local,
+    const double* __restrict__ cst, const double* __restrict__ b, const double* __restrict__ L,
+    uint16_t* __restrict__ P, uint16_t* __restrict__ Pd, int64_t ldd) {
   const int2 tl = tiles[blockIdx.x];
   if (tl.x < 0) return;  // padding tile (uniform)
   const int4 gr = groups[tl.x];
@@ -363,6 +378,7 @@ __global__ __launch_bounds__(256) void cand_pwrite_kernel(
   const int64_t col = tl.y + (threadIdx.x >> 6) * 64 + (threadIdx.x & 63);
   if (col >= F) return;
   const int32_t f = cf_frame[cf_ptr[gr.x] + col];
+  const uint32_t listed = cf_mask[cf_ptr[gr.x] + col];
   const double bk = b[f], lse = L[f];
   f4 v[kGR / 4];
   load_grow(G + grp_off[tl.x] + col * kGR, gr.z, v);
@@ -374,10 +390,14 @@ __global__ __launch_bounds__(256) void cand_pwrite_kernel(
     for (int u = 0; u < 4; ++u) {
       const int r = 4 * q + u;
       if (r >= gr.z) break;  // uniform: one group per workgroup
-      const double a = ((double)v[q][u] + bk) + cr[r];
-      const uint16_t p = __builtin_bit_cast(uint16_t, __float2bfloat16((float)exp(a - lse)));
-      pb[r * kFB] = p;
-      if (Pd) Pd[(int64_t)cell_rot[gr.y + r] * ldd + f] = p;
+      if ((listed >> rot_local[gr.y + r]) & 1u) {
+        const double x = (((double)v[q][u] + bk) + cr[r]) - lse;
+        const uint16_t p = __builtin_bit_cast(uint16_t, __float2bfloat16(expf((float)x)));
+        pb[r * kFB] = p;
+        if (Pd) Pd[(int64_t)pack_rot[gr.y + r] * ldd + f] = p;
+      } else {
+        pb[r * kFB] = 0;
+      }
     }
 }
 
@@ -868,18 +888,20 @@ hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* gr
 
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
-                             int64_t n_frames, const int32_t* cell_rot, int64_t n_rot, const double* log_w,
-                             const double* S, double* cst, const double* b, double* L, void* Pd, int64_t ldd,
-                             const int2* tiles, int64_t n_tiles, const int64_t* cf_ptr, const int32_t* cf_frame,
-                             hipStream_t st) {
+                             int64_t n_frames, const int32_t* pack_of, const int32_t* cell_first,
+                             const int64_t* cell_ptr, const int32_t* pack_rot, const int32_t* rot_local, int64_t n_rot,
+                             const double* log_w, const double* S, double* cst, const double* b, double* L, void* Pd,
+                             int64_t ldd, const int2* tiles, int64_t n_tiles, const int64_t* cf_ptr,
+                             const int32_t* cf_frame, const uint32_t* cf_mask, hipStream_t st) {
   if (n_frames <= 0) return hipSuccess;
   if (n_rot > 0)
-    cell_const_kernel<<<(unsigned)((n_rot + 255) / 256), 256, 0, st>>>(cell_rot, n_rot, log_w, S, cst);
+    cell_const_kernel<<<(unsigned)((n_rot + 255) / 256), 256, 0, st>>>(pack_rot, n_rot, log_w, S, cst);
   cand_estep_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(G, groups, grp_off, cg_ptr, cells, pair_col, k_top,
-                                                                    n_frames, cst, b, L);
+                                                                    n_frames, pack_of, cell_first, cell_ptr, cst, b, L);
   if (n_tiles > 0)
-    cand_pwrite_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, G, cell_rot, cst,
-                                                          b, L, (uint16_t*)P, (uint16_t*)Pd, ldd);
+    cand_pwrite_kernel<<<(unsigned)n_tiles, 256, 0, st>>>(tiles, groups, grp_off, cf_ptr, cf_frame, cf_mask, G,
+                                                          pack_rot, rot_local, cst, b, L, (uint16_t*)P,
+                                                          (uint16_t*)Pd, ldd);
   return hipGetLastError();
 }
 

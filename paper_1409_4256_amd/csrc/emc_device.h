@@ -187,6 +187,19 @@ hipError_t launch_cand_cells(const int32_t* topk, int k_top, const int32_t* fram
                              int32_t* cells, int32_t* keys, hipStream_t st);
 hipError_t launch_pair_columns(const int32_t* order, int64_t n_pairs, int k_top, const int32_t* keys,
                                const int64_t* cf_ptr, int32_t* cf_frame, int32_t* pair_col, hipStream_t st);
+// packs of neighbouring cells (at most kPackRot rotations in all; a cell with more is a pack of its own)
+constexpr int kPackRot = 16;  // the packing cap: one 16-row MFMA tile (<= the candidate kernels' group of 32)
+hipError_t launch_packs(const float* coarse, int n_cells, const int64_t* cell_ptr, const int32_t* cell_of,
+                        const int32_t* cell_rot, int n_rot, int32_t* nn, int32_t* pack_of, int32_t* slot_cell,
+                        int32_t* pack_slot, int32_t* n_packs, int32_t* slot_cnt, int64_t* slot_ptr, int32_t* cell_slot,
+                        int32_t* cell_first, int64_t* pack_ptr, int32_t* pack_rot, int32_t* rot_local,
+                        hipStream_t st);
+hipError_t launch_pack_pairs(const int32_t* cells, int k_top, int64_t n_frames, const int32_t* pack_of,
+                             const int32_t* cell_slot, const int32_t* pack_slot, int n_cells, int32_t* keys,
+                             uint32_t* bits, int32_t* prim, hipStream_t st);
+hipError_t launch_pack_columns(const int32_t* order, const int64_t* cf_ptr, int n_cells, int64_t n_pairs, int k_top,
+                               const int32_t* keys, const uint32_t* bits, const int32_t* prim, int32_t* cf_frame,
+                               uint32_t* cf_mask, int32_t* pair_col, hipStream_t st);
 hipError_t launch_scan64(const int64_t* cnt, int64_t n, int64_t* ptr, hipStream_t st);
 
 // ---- candidate E/M steps (cand.hip) ----
@@ -196,10 +209,11 @@ hipError_t launch_cand_loglik(const int2* tiles, int64_t n_tiles, const int4* gr
                               float* G, hipStream_t st);
 hipError_t launch_cand_estep(const float* G, void* P, const int4* groups, const int64_t* grp_off,
                              const int64_t* cg_ptr, const int32_t* cells, const int32_t* pair_col, int k_top,
-                             int64_t n_frames, const int32_t* cell_rot, int64_t n_rot, const double* log_w,
-                             const double* S, double* cst, const double* b, double* L, void* Pd, int64_t ldd,
-                             const int2* tiles, int64_t n_tiles, const int64_t* cf_ptr, const int32_t* cf_frame,
-                             hipStream_t st);
+                             int64_t n_frames, const int32_t* pack_of, const int32_t* cell_first,
+                             const int64_t* cell_ptr, const int32_t* pack_rot, const int32_t* rot_local, int64_t n_rot,
+                             const double* log_w, const double* S, double* cst, const double* b, double* L, void* Pd,
+                             int64_t ldd, const int2* tiles, int64_t n_tiles, const int64_t* cf_ptr,
+                             const int32_t* cf_frame, const uint32_t* cf_mask, hipStream_t st);
 hipError_t launch_cand_mstep(const int4* groups, const int64_t* grp_off, int64_t n_groups, const int64_t* cf_ptr,
                              const int32_t* cf_frame, const void* runs, int64_t n_list, const void* chunks,
                              const int32_t* dense_band, const void* P, const int32_t* cell_rot, int64_t ps, float* Wp,

@@ -3,9 +3,21 @@
 // rotation-major layout G[j][k] (frames contiguous).  A frame's normalisation
 // needs only its maximum and the sum of exp(a - max); these two statistics are
 // also all that rotation shares must exchange (Section 3.2).
+//
+// The statistics pass does not evaluate terms more than kLseDrop below the
+// running maximum: each is below e^-64 = 1.6e-28 of the maximum term, so all of
+// them together (25000 rotations: < 4e-24) stay far below the FP64 rounding of a
+// sum that is at least 1.  Once the posteriors have concentrated, most terms fall
+// there and the pass is bound by reading G instead of by FP64 exp.  The write pass
+// keeps every responsibility, however small (the c-step's ratio is scale-free: a
+// voxel reached only by improbable rotations still takes their weighted mean); it
+// forms a - L_k in FP64 and evaluates the exponential in FP32, the precision P is
+// stored in (or finer).
 #include "emc_device.h"
 
 namespace emc {
+
+constexpr double kLseDrop = 64.0;
 
 __device__ __forceinline__ void lse_merge(double& m, double& s, double m2, double s2) {
   if (m2 > m) {
@@ -48,7 +60,7 @@ __global__ __launch_bounds__(256) void lse_stats_kernel(const float* __restrict_
         const int j = j0 + 4 * u;
         if (j >= je) break;
         const double a = ((double)g[u] + bk) + (log_w[j] - S[j]);
-        if (!(a > -INFINITY)) continue;  // zero prior weight: no contribution
+        if (!(a > m - kLseDrop)) continue;  // zero prior weight, or negligible against the maximum
         if (a > m) {
           s = s * exp(m - a) + 1.0;
           m = a;
@@ -89,14 +101,14 @@ __global__ void lse_finish_kernel(const double* __restrict__ stats, int64_t n_da
 constexpr int kWriteRows = 8;  // rotations per workgroup of the write pass
 
 template <typename PT>
-__device__ __forceinline__ PT to_p(double v);
+__device__ __forceinline__ PT to_p(float v);
 template <>
-__device__ __forceinline__ float to_p<float>(double v) {
-  return (float)v;
+__device__ __forceinline__ float to_p<float>(float v) {
+  return v;
 }
 template <>
-__device__ __forceinline__ __hip_bfloat16 to_p<__hip_bfloat16>(double v) {
-  return __float2bfloat16((float)v);
+__device__ __forceinline__ __hip_bfloat16 to_p<__hip_bfloat16>(float v) {
+  return __float2bfloat16(v);
 }
 __device__ __forceinline__ double from_p(float v) { return (double)v; }
 __device__ __forceinline__ double from_p(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
@@ -126,9 +138,9 @@ __global__ __launch_bounds__(256) void lse_write_kernel(const float* G, int64_t 
     for (int r = 0; r < kWriteRows; ++r) {
       const int j = j0 + r;
       if (j >= n_rot) break;
-      PT p = to_p<PT>(0.0);
+      PT p = to_p<PT>(0.0f);
       if (live) {
-        p = to_p<PT>(exp(((double)G[(int64_t)j * ldg + k] + sh) + e[r]));
+        p = to_p<PT>(expf((float)(((double)G[(int64_t)j * ldg + k] + sh) + e[r])));  // exp(a - L_k)
         acc[r] += from_p(p);
       }
       P[(int64_t)j * ldp + k] = p;

@@ -217,6 +217,213 @@ __global__ void pair_columns_kernel(const int32_t* __restrict__ order, int64_t n
   pair_col[pr] = (int32_t)(e - cf_ptr[keys[pr]]);
 }
 
+// ------------------------------------------------------------------ packs of cells
+constexpr int kNbr = 16;        // neighbours a cell's pack is filled from
+constexpr int kMaxList = 256;   // entries of a frame's proposal list (at most)
+// The cells' rotation groups are formed over packs: neighbouring cells whose rotation
+// counts add up to at most kPackRot (one 16-row MFMA tile), searched
+// over the union of their frame lists.  A frame then has its bands expanded once per
+// pack instead of once per cell, and small cells share MFMA tiles.
+
+// nn[c][k]: the kNbr cells nearest to cell c (largest |<q_c, q_d>|, d != c; ties to
+// the lower index), -1 past n_cells - 1.  One thread per cell.
+__global__ void cell_neighbours_kernel(const float* __restrict__ coarse, int n_cells, int32_t* __restrict__ nn) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= n_cells) return;
+  const float4 qc = reinterpret_cast<const float4*>(coarse)[c];
+  const float nc = rsqrtf(qc.x * qc.x + qc.y * qc.y + qc.z * qc.z + qc.w * qc.w);
+  float best[kNbr];
+  int idx[kNbr];
+#pragma unroll
+  for (int k = 0; k < kNbr; ++k) {
+    best[k] = -1.0f;
+    idx[k] = -1;
+  }
+  for (int d = 0; d < n_cells; ++d) {
+    if (d == c) continue;
+    const float4 qd = reinterpret_cast<const float4*>(coarse)[d];
+    const float nd = rsqrtf(qd.x * qd.x + qd.y * qd.y + qd.z * qd.z + qd.w * qd.w);
+    float v = fabsf(qc.x * qd.x + qc.y * qd.y + qc.z * qd.z + qc.w * qd.w) * nc * nd;
+    int id = d;
+    if (!(v > best[kNbr - 1])) continue;  // d ascending: an equal value keeps the lower index
+#pragma unroll
+    for (int k = 0; k < kNbr; ++k) {  // insertion: the entry carried down is the smaller one
+      if (v > best[k]) {
+        const float tv = best[k];
+        const int ti = idx[k];
+        best[k] = v;
+        idx[k] = id;
+        v = tv;
+        id = ti;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kNbr; ++k) nn[(int64_t)c * kNbr + k] = idx[k];
+}
+
+// Greedy packing: cells in index order; an unpacked cell opens a pack and takes its
+// unpacked neighbours, nearest first, while the pack's rotations stay within
+// kPackRot (a cell with more rotations stays alone).  pack_of[c], slot_cell[s]
+// (cells in pack order), pack_slot[p] (first slot of pack p, p <= n_packs),
+// *n_packs.  One workgroup: the cells' sizes and packs are kept in LDS (dynamic,
+// 8 bytes per cell) and thread 0 runs the greedy pass.
+__global__ __launch_bounds__(256) void pack_cells_kernel(const int64_t* __restrict__ cell_ptr,
+                                                         const int32_t* __restrict__ nn, int n_cells,
+                                                         int32_t* __restrict__ pack_of, int32_t* __restrict__ slot_cell,
+                                                         int32_t* __restrict__ pack_slot,
+                                                         int32_t* __restrict__ n_packs) {
+  extern __shared__ int32_t sh[];
+  int32_t* size = sh;           // [n_cells] rotations per cell (clamped to kPackRot + 1)
+  int32_t* pk = sh + n_cells;   // [n_cells] pack of each cell, -1: none yet
+  for (int c = threadIdx.x; c < n_cells; c += 256) {
+    const int64_t r = cell_ptr[c + 1] - cell_ptr[c];
+    size[c] = (int32_t)(r > kPackRot ? kPackRot + 1 : r);
+    pk[c] = -1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int slot = 0, np = 0;
+    int32_t nb[kNbr];
+#pragma unroll
+    for (int k = 0; k < kNbr; ++k) nb[k] = n_cells > 0 ? nn[k] : -1;
+    for (int c = 0; c < n_cells; ++c) {
+      int32_t cur[kNbr];
+#pragma unroll
+      for (int k = 0; k < kNbr; ++k) cur[k] = nb[k];
+      if (c + 1 < n_cells) {  // the next cell's neighbours, loaded while this one is packed
+#pragma unroll
+        for (int k = 0; k < kNbr; ++k) nb[k] = nn[(int64_t)(c + 1) * kNbr + k];
+      }
+      if (pk[c] >= 0) continue;
+      pack_slot[np] = slot;
+      pk[c] = np;
+      slot_cell[slot++] = c;
+      int r = size[c];
+      if (r <= kPackRot) {
+#pragma unroll
+        for (int k = 0; k < kNbr; ++k) {
+          const int d = cur[k];
+          if (d < 0 || pk[d] >= 0 || r + size[d] > kPackRot) continue;
+          pk[d] = np;
+          slot_cell[slot++] = d;
+          r += size[d];
+        }
+      }
+      ++np;
+    }
+    pack_slot[np] = slot;
+    *n_packs = np;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n_cells; c += 256) pack_of[c] = pk[c];
+}
+
+// slot_cnt[s] = rotations of the cell in slot s; cell_slot[c] = slot of cell c
+__global__ void slot_sizes_kernel(const int32_t* __restrict__ slot_cell, const int64_t* __restrict__ cell_ptr,
+                                  int n_cells, int32_t* __restrict__ slot_cnt, int32_t* __restrict__ cell_slot) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= n_cells) return;
+  const int c = slot_cell[s];
+  slot_cnt[s] = (int32_t)(cell_ptr[c + 1] - cell_ptr[c]);
+  cell_slot[c] = s;
+}
+
+// cell_first[c] = first pack_rot position of cell c; pack_ptr[p] = first pack_rot
+// position of pack p (p <= n_cells; packs past the last one are empty at n_rot)
+__global__ void pack_offsets_kernel(const int64_t* __restrict__ slot_ptr, const int32_t* __restrict__ cell_slot,
+                                    const int32_t* __restrict__ pack_slot, const int32_t* __restrict__ n_packs,
+                                    int n_cells, int32_t* __restrict__ cell_first, int64_t* __restrict__ pack_ptr) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < n_cells) cell_first[e] = (int32_t)slot_ptr[cell_slot[e]];
+  if (e <= n_cells) pack_ptr[e] = e <= *n_packs ? slot_ptr[pack_slot[e]] : slot_ptr[n_cells];
+}
+
+// pack_rot: the rotations in pack order (cell by cell, each cell's in cell_rot
+// order); rot_local: index of each rotation's cell inside its pack
+__global__ void pack_rotations_kernel(const int32_t* __restrict__ cell_rot, const int32_t* __restrict__ cell_of,
+                                      const int64_t* __restrict__ cell_ptr, int n_rot,
+                                      const int32_t* __restrict__ cell_first, const int32_t* __restrict__ cell_slot,
+                                      const int32_t* __restrict__ pack_of, const int32_t* __restrict__ pack_slot,
+                                      int32_t* __restrict__ pack_rot, int32_t* __restrict__ rot_local) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_rot) return;
+  const int32_t j = cell_rot[t];
+  const int c = cell_of[j];
+  const int64_t pos = cell_first[c] + (t - cell_ptr[c]);
+  pack_rot[pos] = j;
+  rot_local[pos] = cell_slot[c] - pack_slot[pack_of[c]];
+}
+
+// Per candidate frame (one wave): the first list entry of each pack the frame
+// proposes is that pack's primary entry.  keys[e] = the pack for a primary entry,
+// n_cells otherwise (sorted after every pack); bits[e] (primary entries) = the
+// pack-local indices of every cell of the pack the frame lists; prim[e] = the
+// frame's primary entry of the pack of entry e (-1: no cell).
+__global__ __launch_bounds__(256) void pack_pairs_kernel(const int32_t* __restrict__ cells, int k_top, int64_t n_frames,
+                                                         const int32_t* __restrict__ pack_of,
+                                                         const int32_t* __restrict__ cell_slot,
+                                                         const int32_t* __restrict__ pack_slot, int n_cells,
+                                                         int32_t* __restrict__ keys, uint32_t* __restrict__ bits,
+                                                         int32_t* __restrict__ prim) {
+  __shared__ int32_t spk[4][kMaxList];  // pack of each entry of the wave's frame (-1: no cell)
+  __shared__ int32_t sbit[4][kMaxList]; // its cell's index inside the pack
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t f = (int64_t)blockIdx.x * 4 + wave;
+  if (f >= n_frames) return;  // uniform per wave; no barrier below
+  const int32_t* row = cells + f * k_top;
+  for (int t = lane; t < k_top; t += 64) {
+    const int c = row[t];
+    const int p = c < 0 ? -1 : pack_of[c];
+    spk[wave][t] = p;
+    sbit[wave][t] = c < 0 ? 0 : cell_slot[c] - pack_slot[p];
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (int t = lane; t < k_top; t += 64) {
+    const int p = spk[wave][t];
+    const int64_t e = f * k_top + t;
+    if (p < 0) {
+      keys[e] = n_cells;
+      prim[e] = -1;
+      continue;
+    }
+    int first = t;
+    uint32_t m = 0u;
+    for (int u = 0; u < k_top; ++u) {  // the frame's entries of the same pack
+      if (spk[wave][u] != p) continue;
+      if (u < first) first = u;
+      m |= 1u << sbit[wave][u];
+    }
+    keys[e] = first == t ? p : n_cells;
+    bits[e] = m;
+    prim[e] = first;
+  }
+}
+
+// Primary entries sorted by pack (order = entry indices, segments cf_ptr): the
+// union list of each pack (frame, cell bits) and the entries' columns in it
+__global__ void pack_columns_kernel(const int32_t* __restrict__ order, int64_t n_prim, int k_top,
+                                    const int32_t* __restrict__ keys, const int64_t* __restrict__ cf_ptr,
+                                    const uint32_t* __restrict__ bits, int32_t* __restrict__ cf_frame,
+                                    uint32_t* __restrict__ cf_mask, int32_t* __restrict__ pair_col) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_prim) return;
+  const int32_t e = order[i];
+  cf_frame[i] = e / k_top;
+  cf_mask[i] = bits[e];
+  pair_col[e] = (int32_t)(i - cf_ptr[keys[e]]);
+}
+
+// the other entries take their primary entry's column
+__global__ void pack_columns_rest_kernel(const int32_t* __restrict__ prim, int64_t n_pairs, int k_top,
+                                         int32_t* __restrict__ pair_col) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_pairs) return;
+  const int t0 = prim[e];
+  const int64_t f = e / k_top;
+  if (t0 >= 0 && f * k_top + t0 != e) pair_col[e] = pair_col[f * k_top + t0];
+}
+
 // ===================================================================== launchers
 static inline unsigned g256(int64_t n) {
   const int64_t g = (n + 255) / 256;
@@ -316,6 +523,44 @@ hipError_t launch_pair_columns(const int32_t* order, int64_t n_pairs, int k_top,
   if (n_pairs > 0)
     pair_columns_kernel<<<(unsigned)((n_pairs + 255) / 256), 256, 0, st>>>(order, n_pairs, k_top, keys, cf_ptr,
                                                                            cf_frame, pair_col);
+  return hipGetLastError();
+}
+
+hipError_t launch_packs(const float* coarse, int n_cells, const int64_t* cell_ptr, const int32_t* cell_of,
+                        const int32_t* cell_rot, int n_rot, int32_t* nn, int32_t* pack_of, int32_t* slot_cell,
+                        int32_t* pack_slot, int32_t* n_packs, int32_t* slot_cnt, int64_t* slot_ptr, int32_t* cell_slot,
+                        int32_t* cell_first, int64_t* pack_ptr, int32_t* pack_rot, int32_t* rot_local,
+                        hipStream_t st) {
+  cell_neighbours_kernel<<<g256(n_cells), 256, 0, st>>>(coarse, n_cells, nn);
+  pack_cells_kernel<<<1, 256, (size_t)n_cells * 8, st>>>(cell_ptr, nn, n_cells, pack_of, slot_cell, pack_slot, n_packs);
+  slot_sizes_kernel<<<g256(n_cells), 256, 0, st>>>(slot_cell, cell_ptr, n_cells, slot_cnt, cell_slot);
+  exclusive_scan_kernel<<<1, 256, 0, st>>>(slot_cnt, n_cells, slot_ptr);
+  pack_offsets_kernel<<<g256(n_cells + 1), 256, 0, st>>>(slot_ptr, cell_slot, pack_slot, n_packs, n_cells, cell_first,
+                                                          pack_ptr);
+  if (n_rot > 0)
+    pack_rotations_kernel<<<g256(n_rot), 256, 0, st>>>(cell_rot, cell_of, cell_ptr, n_rot, cell_first, cell_slot,
+                                                        pack_of, pack_slot, pack_rot, rot_local);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_pairs(const int32_t* cells, int k_top, int64_t n_frames, const int32_t* pack_of,
+                             const int32_t* cell_slot, const int32_t* pack_slot, int n_cells, int32_t* keys,
+                             uint32_t* bits, int32_t* prim, hipStream_t st) {
+  if (n_frames > 0)
+    pack_pairs_kernel<<<(unsigned)((n_frames + 3) / 4), 256, 0, st>>>(cells, k_top, n_frames, pack_of, cell_slot,
+                                                                       pack_slot, n_cells, keys, bits, prim);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_columns(const int32_t* order, const int64_t* cf_ptr, int n_cells, int64_t n_pairs, int k_top,
+                               const int32_t* keys, const uint32_t* bits, const int32_t* prim, int32_t* cf_frame,
+                               uint32_t* cf_mask, int32_t* pair_col, hipStream_t st) {
+  // primary entries are the first cf_ptr[n_cells] of the sorted order (the others
+  // have key n_cells); the count is read on the device
+  if (n_pairs <= 0) return hipSuccess;
+  pack_columns_kernel<<<g256(n_pairs), 256, 0, st>>>(order, n_pairs, k_top, keys, cf_ptr, bits, cf_frame, cf_mask,
+                                                      pair_col);
+  pack_columns_rest_kernel<<<g256(n_pairs), 256, 0, st>>>(prim, n_pairs, k_top, pair_col);
   return hipGetLastError();
 }
 

@@ -81,12 +81,14 @@ class Proposal(ctypes.Structure):
         ("n_groups", ctypes.c_int64), ("n_tiles", ctypes.c_int64), ("n_g", ctypes.c_int64),
         ("n_chunks", ctypes.c_int64),
         ("cell_of", ctypes.c_void_p), ("cell_ptr", ctypes.c_void_p), ("cell_rot", ctypes.c_void_p),
+        ("pack_of", ctypes.c_void_p), ("cell_first", ctypes.c_void_p), ("pack_rot", ctypes.c_void_p),
+        ("rot_local", ctypes.c_void_p),
         ("cand_frames", ctypes.c_void_p), ("audit_frames", ctypes.c_void_p), ("cand_cells", ctypes.c_void_p),
         ("pair_col", ctypes.c_void_p), ("cf_ptr", ctypes.c_void_p), ("cf_frame", ctypes.c_void_p),
-        ("cg_ptr", ctypes.c_void_p), ("groups", ctypes.c_void_p), ("grp_off", ctypes.c_void_p),
+        ("cf_mask", ctypes.c_void_p), ("cg_ptr", ctypes.c_void_p), ("groups", ctypes.c_void_p), ("grp_off", ctypes.c_void_p),
         ("tiles", ctypes.c_void_p), ("mask_audit", ctypes.c_void_p),
         ("chunks", ctypes.c_void_p), ("runs", ctypes.c_void_p),
-        ("n_dense", ctypes.c_int32), ("reserved2", ctypes.c_int32), ("ld_dense", ctypes.c_int64),
+        ("n_dense", ctypes.c_int32), ("n_packs", ctypes.c_int32), ("ld_dense", ctypes.c_int64),
         ("dense_band", ctypes.c_void_p), ("dense_list", ctypes.c_void_p), ("kt_dense", ctypes.c_void_p),
         ("n_rot", ctypes.c_int32), ("n_pix", ctypes.c_int32), ("quat", ctypes.c_void_p), ("mask", ctypes.c_void_p),
     ]

@@ -149,7 +149,16 @@ class ProposedIteration:
         self.recall = torch.empty(1, dtype=torch.float64, device="cuda")
 
     def candidate_pairs(self) -> int:
-        """(rotation, frame) pairs the candidate E-step evaluates (synchronises)."""
+        """(rotation, frame) pairs the candidate E-step evaluates: the rotations of every
+        proposed cell of every candidate frame (synchronises)."""
+        p = self.plan
+        cells = E.plan_array(self.buf, p.cand_cells, p.n_cand * p.k_top, torch.int32).long()
+        ptr = E.plan_array(self.buf, p.cell_ptr, p.n_cells + 1, torch.int64)
+        return int((ptr[1:] - ptr[:-1])[cells[cells >= 0]].sum().item())
+
+    def computed_pairs(self) -> int:
+        """(rotation, frame) pairs the candidate log-likelihood and M-step compute: every
+        rotation of a pack of cells over the union of its cells' frame lists (synchronises)."""
         p = self.plan
         groups = E.plan_array(self.buf, p.groups, 4 * p.n_groups, torch.int32).view(-1, 4).long()
         cf_ptr = E.plan_array(self.buf, p.cf_ptr, p.n_cells + 1, torch.int64)

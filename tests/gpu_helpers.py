@@ -148,25 +148,32 @@ def candidate_pairs(buf, plan, n_rot, frames=None):
     grp_off = pa(plan.grp_off, plan.n_groups + 1, torch.int64)
     cf_ptr = pa(plan.cf_ptr, plan.n_cells + 1, torch.int64)
     cf_frame = pa(plan.cf_frame, int(cf_ptr[-1]), torch.int32).astype(np.int64)
+    cf_mask = pa(plan.cf_mask, int(cf_ptr[-1]), torch.int32).astype(np.int64) & 0xffffffff
     cand_frames = pa(plan.cand_frames, plan.n_cand, torch.int32).astype(np.int64)
-    cell_rot = pa(plan.cell_rot, n_rot, torch.int32).astype(np.int64)
+    pack_rot = pa(plan.pack_rot, n_rot, torch.int32).astype(np.int64)
+    rot_local = pa(plan.rot_local, n_rot, torch.int32).astype(np.int64)
     keep = None if frames is None else set(int(f) for f in frames)
     js, ks, go, po = [], [], [], []
     for g in range(plan.n_groups):
         c, first, cnt = groups[g, 0], groups[g, 1], groups[g, 2]
         fr = cand_frames[cf_frame[cf_ptr[c]:cf_ptr[c + 1]]]
+        msk = cf_mask[cf_ptr[c]:cf_ptr[c + 1]]
         f = np.arange(fr.size)
         if keep is not None:
             sel = np.fromiter((int(x) in keep for x in fr), bool, fr.size)
-            f, fr = f[sel], fr[sel]
+            f, fr, msk = f[sel], fr[sel], msk[sel]
         if f.size == 0:
             continue
         r = np.arange(cnt)
         F, R = np.meshgrid(f, r, indexing="ij")
-        js.append(cell_rot[first + R].ravel())
-        ks.append(np.broadcast_to(fr[:, None], F.shape).ravel())
-        go.append((grp_off[g] + 32 * F + R).ravel())
-        po.append((grp_off[g] + (F >> 5) * 1024 + R * 32 + (F & 31)).ravel())
+        # a pack's list holds the union of its cells' lists: only the pairs whose cell
+        # the frame proposes are candidates
+        cand = ((msk[:, None] >> rot_local[first + R]) & 1).astype(bool)
+        F, R = F[cand], R[cand]
+        js.append(pack_rot[first + R])
+        ks.append(np.broadcast_to(fr[:, None], cand.shape)[cand])
+        go.append(grp_off[g] + 32 * F + R)
+        po.append(grp_off[g] + (F >> 5) * 1024 + R * 32 + (F & 31))
     cat = lambda a: np.concatenate(a) if a else np.zeros(0, np.int64)
     return cat(js), cat(ks), cat(go), cat(po)
 

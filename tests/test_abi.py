@@ -203,7 +203,7 @@ def _consistent_plan(pb, n_audit=20, **kw):
     n_cand = pb.n_data - n_audit
     d = dict(n_cells=2000, k_top=128, n_cand=n_cand, n_audit=n_audit, words=63, n_bands=pb.n_pix // 128 if
              pb.n_pix % 256 == 0 else (pb.n_pix + 255) // 256 * 2, n_groups=2000, n_tiles=8 * 100, n_g=1 << 20,
-             n_chunks=1 << 16, n_dense=4, reserved2=0, ld_dense=(n_cand + 255) // 256 * 256,
+             n_chunks=1 << 16, n_dense=4, n_packs=1, ld_dense=(n_cand + 255) // 256 * 256,
              n_rot=pb.n_rot, n_pix=pb.n_pix, quat=pb.quat, mask=pb.mask)
     d.update(kw)
     plan = emc.Proposal()
