@@ -76,15 +76,17 @@ __device__ __forceinline__ u4 load_chunk(const u4* __restrict__ p) {
 constexpr int kWin = 2;              // chunks per band held in registers (16 pixels)
 
 // Writes (CLEAR = false) or zeroes one chunk's pixels: word e goes to
-// base[(e >> 9) * stride] as the BF16 count (e & 511).
+// base[(e >> 9) * stride] as the BF16 count (e & 511); a padding word goes to
+// base[junk], a slot of the lane's own that no MFMA reads (a select, not a branch).
 template <bool CLEAR>
-__device__ __forceinline__ void put_chunk(uint16_t* base, int stride, u4 ch) {
+__device__ __forceinline__ void put_chunk(uint16_t* base, int stride, int junk, u4 ch) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const uint32_t e = h ? (ch[u] >> 16) : (ch[u] & 0xffffu);
-      if (e != kPad) base[(int)(e >> 9) * stride] = CLEAR ? (uint16_t)0 : count_bf16(e & 511u);
+      const int off = e == kPad ? junk : (int)(e >> 9) * stride;
+      base[off] = CLEAR ? (uint16_t)0 : count_bf16(e & 511u);
     }
   }
 }
@@ -94,15 +96,15 @@ __device__ __forceinline__ void put_chunk(uint16_t* base, int stride, u4 ch) {
 // loaded four at a time
 // (chunks from `mid` on belong to the next band: their pixels go `next` further)
 template <bool CLEAR, bool NT>
-__device__ __forceinline__ void put_rest(uint16_t* base, int stride, const u4* __restrict__ src, int first, int c1,
-                                         int step, int mid = INT_MAX, int next = 0) {
+__device__ __forceinline__ void put_rest(uint16_t* base, int stride, int junk, const u4* __restrict__ src, int first,
+                                         int c1, int step, int mid = INT_MAX, int next = 0) {
   const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
   for (int c = first; c < c1; c += 4 * step) {
     u4 v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) v[u] = c + u * step < c1 ? load_chunk<NT>(src + c + u * step) : pad;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) put_chunk<CLEAR>(base + (c + u * step >= mid ? next : 0), stride, v[u]);
+    for (int u = 0; u < 4; ++u) put_chunk<CLEAR>(base + (c + u * step >= mid ? next : 0), stride, junk, v[u]);
   }
 }
 
@@ -200,11 +202,11 @@ __device__ __forceinline__ void cand_loglik_tile(
     // bands hold at most 8 photon pixels per frame)
     const bool more = __ballot(r0c.y - r0c.x > 1) != 0;
     if (has) {
-      put_chunk<false>(frow, 1, w0[0]);
+      put_chunk<false>(frow, 1, kBand, w0[0]);
       if (more) {
 #pragma unroll
-        for (int u = 1; u < kWin; ++u) put_chunk<false>(frow, 1, w0[u]);
-        put_rest<false, false>(frow, 1, fb, r0c.x + kWin, r0c.y, 1);
+        for (int u = 1; u < kWin; ++u) put_chunk<false>(frow, 1, kBand, w0[u]);
+        put_rest<false, false>(frow, 1, kBand, fb, r0c.x + kWin, r0c.y, 1);
       }
     }
 #pragma unroll
@@ -228,10 +230,10 @@ __device__ __forceinline__ void cand_loglik_tile(
     // in order, so the MFMA operand reads above are done)
     if (has) {
       if (r0c.y - r0c.x <= kWin) {
-        put_chunk<true>(frow, 1, w0[0]);
+        put_chunk<true>(frow, 1, kBand, w0[0]);
         if (more) {
 #pragma unroll
-          for (int u = 1; u < kWin; ++u) put_chunk<true>(frow, 1, w0[u]);
+          for (int u = 1; u < kWin; ++u) put_chunk<true>(frow, 1, kBand, w0[u]);
         }
       } else {
 #pragma unroll
@@ -461,6 +463,8 @@ __device__ __forceinline__ void cand_mstep_range(
   const u4* run_pr = runs + (int64_t)n_list * n_runs + (int64_t)pr * n_list;
   const bool sparse = dense_band[band + par] < 0;
   uint16_t* fcol_b = fcol + par * kNext;
+  // padding words go to column kFB + par of pixel row `slot` (never an MFMA operand)
+  const int junk = slot * kKRow + kFB + par - slot - par * kNext;
   // a frame's record (a zero record: no chunks); decoded one block after its load
   auto record_of = [&](int32_t fr) -> u4 { return fr < 0 || !sparse ? u4{0u, 0u, 0u, 0u} : run_pr[fr]; };
   auto frame_at = [&](int64_t f0) -> int32_t { return f0 + slot < F ? cf[f0 + slot] : -1; };
@@ -494,8 +498,8 @@ __device__ __forceinline__ void cand_mstep_range(
     const u4 e2 = record_of(fr2);
     const int32_t fr3 = frame_at(f0 + 3 * kFB);
 #pragma unroll
-    for (int u = 0; u < kWin; ++u) put_chunk<false>(fcol_b, kKRow, w0[u]);
-    put_rest<false, true>(fcol_b, kKRow, fb, q0.x + kWin, q0.y, 1);
+    for (int u = 0; u < kWin; ++u) put_chunk<false>(fcol_b, kKRow, junk, w0[u]);
+    put_rest<false, true>(fcol_b, kKRow, junk, fb, q0.x + kWin, q0.y, 1);
     if (nf < kFB) {  // frames past the list end hold no responsibility
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -532,7 +536,7 @@ __device__ __forceinline__ void cand_mstep_range(
     // otherwise all of them with contiguous 16-byte stores
     if (__ballot(q0.y - q0.x > kWin) == 0) {
 #pragma unroll
-      for (int u = 0; u < kWin; ++u) put_chunk<true>(fcol_b, kKRow, w0[u]);
+      for (int u = 0; u < kWin; ++u) put_chunk<true>(fcol_b, kKRow, junk, w0[u]);
     } else {
       for (int e = lane; e < kPair * kKRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = zero;
     }
