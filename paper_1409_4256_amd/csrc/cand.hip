@@ -280,7 +280,8 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
 // The log-evidence does not evaluate a term more than kLseDrop below the running
 // maximum (below e^-64 of it: the frame's candidates together stay far below the
 // FP64 rounding of the sum).  Responsibilities keep every term; a - L is formed in
-// FP64 and its exponential evaluated in FP32 (P is stored in BF16).
+// FP64 and its exponential evaluated in FP32 (P is stored in BF16), skipped only
+// below -110, where its FP32 value is 0.
 constexpr double kLseDrop = 64.0;
 __device__ __forceinline__ void lse_push(double& mx, double& s, double a) {
   if (!(a > mx - kLseDrop)) return;  // zero prior weight, or negligible against the maximum
@@ -393,8 +394,8 @@ __global__ __launch_bounds__(256) void cand_pwrite_kernel(
       const int r = 4 * q + u;
       if (r >= gr.z) break;  // uniform: one group per workgroup
       if ((listed >> rot_local[gr.y + r]) & 1u) {
-        const double x = (((double)v[q][u] + bk) + cr[r]) - lse;
-        const uint16_t p = __builtin_bit_cast(uint16_t, __float2bfloat16(expf((float)x)));
+        const float x = (float)((((double)v[q][u] + bk) + cr[r]) - lse);
+        const uint16_t p = x > -110.0f ? __builtin_bit_cast(uint16_t, __float2bfloat16(expf(x))) : 0;
         pb[r * kFB] = p;
         if (Pd) Pd[(int64_t)pack_rot[gr.y + r] * ldd + f] = p;
       } else {

@@ -12,7 +12,10 @@
 // keeps every responsibility, however small (the c-step's ratio is scale-free: a
 // voxel reached only by improbable rotations still takes their weighted mean); it
 // forms a - L_k in FP64 and evaluates the exponential in FP32, the precision P is
-// stored in (or finer).
+// stored in (or finer), skipping only exponents below -110, whose FP32 value is 0.
+// (A first pass for each frame's maximum, so that whole waves could skip, was
+// measured slower: in the early iterations most terms are near their frame's
+// maximum and the extra read of G costs more than it saves.)
 #include "emc_device.h"
 
 namespace emc {
@@ -140,8 +143,11 @@ __global__ __launch_bounds__(256) void lse_write_kernel(const float* G, int64_t 
       if (j >= n_rot) break;
       PT p = to_p<PT>(0.0f);
       if (live) {
-        p = to_p<PT>(expf((float)(((double)G[(int64_t)j * ldg + k] + sh) + e[r])));  // exp(a - L_k)
-        acc[r] += from_p(p);
+        const float x = (float)(((double)G[(int64_t)j * ldg + k] + sh) + e[r]);  // a - L_k
+        if (x > -110.0f) {  // below, exp(x) rounds to 0 in FP32: skipping changes nothing
+          p = to_p<PT>(expf(x));
+          acc[r] += from_p(p);
+        }
       }
       P[(int64_t)j * ldp + k] = p;
     }
