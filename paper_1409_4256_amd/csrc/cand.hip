@@ -146,6 +146,9 @@ __device__ __forceinline__ void cand_loglik_tile(
 
   uint16_t* rows = lds + wave * kFT * kLRow;
   uint16_t* frow = rows + lane * kLRow;
+  // padding words go to column kBand + 2 (lane / 16) of the lane's row: past the
+  // MFMA's 128 columns, and in a different bank for each lane of the wave
+  const int junk = kBand + 2 * (lane >> 4);
   for (int e = lane; e < kFT * kLRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = u4{0u, 0u, 0u, 0u};
 
   f4 acc[NT][4];
@@ -202,11 +205,11 @@ __device__ __forceinline__ void cand_loglik_tile(
     // bands hold at most 8 photon pixels per frame)
     const bool more = __ballot(r0c.y - r0c.x > 1) != 0;
     if (has) {
-      put_chunk<false>(frow, 1, kBand, w0[0]);
+      put_chunk<false>(frow, 1, junk, w0[0]);
       if (more) {
 #pragma unroll
-        for (int u = 1; u < kWin; ++u) put_chunk<false>(frow, 1, kBand, w0[u]);
-        put_rest<false, false>(frow, 1, kBand, fb, r0c.x + kWin, r0c.y, 1);
+        for (int u = 1; u < kWin; ++u) put_chunk<false>(frow, 1, junk, w0[u]);
+        put_rest<false, false>(frow, 1, junk, fb, r0c.x + kWin, r0c.y, 1);
       }
     }
 #pragma unroll
@@ -230,10 +233,10 @@ __device__ __forceinline__ void cand_loglik_tile(
     // in order, so the MFMA operand reads above are done)
     if (has) {
       if (r0c.y - r0c.x <= kWin) {
-        put_chunk<true>(frow, 1, kBand, w0[0]);
+        put_chunk<true>(frow, 1, junk, w0[0]);
         if (more) {
 #pragma unroll
-          for (int u = 1; u < kWin; ++u) put_chunk<true>(frow, 1, kBand, w0[u]);
+          for (int u = 1; u < kWin; ++u) put_chunk<true>(frow, 1, junk, w0[u]);
         }
       } else {
 #pragma unroll
@@ -464,8 +467,9 @@ __device__ __forceinline__ void cand_mstep_range(
   const u4* run_pr = runs + (int64_t)n_list * n_runs + (int64_t)pr * n_list;
   const bool sparse = dense_band[band + par] < 0;
   uint16_t* fcol_b = fcol + par * kNext;
-  // padding words go to column kFB + par of pixel row `slot` (never an MFMA operand)
-  const int junk = slot * kKRow + kFB + par - slot - par * kNext;
+  // padding words go to column kFB + 2 (lane / 16) of pixel row `slot` (never an
+  // MFMA operand; a different bank for each lane of the wave)
+  const int junk = slot * kKRow + kFB + 2 * (lane >> 4) - slot - par * kNext;
   // a frame's record (a zero record: no chunks); decoded one block after its load
   auto record_of = [&](int32_t fr) -> u4 { return fr < 0 || !sparse ? u4{0u, 0u, 0u, 0u} : run_pr[fr]; };
   auto frame_at = [&](int64_t f0) -> int32_t { return f0 + slot < F ? cf[f0 + slot] : -1; };
