@@ -5,9 +5,11 @@
 // exact in BF16; the slice split hi + lo keeps ~16 significant bits.
 //
 // Workgroup tile 256 x 256 x 64 with 8 waves (two per SIMD, so that one can
-// issue MFMAs while the other waits on LDS) in a 2 x 4 arrangement, each wave
-// 128 x 64 from 8 x 4 v_mfma_f32_16x16x32_bf16 tiles (4 waves of 128 x 128 when
-// built with EMC_BF16_WAVES=4).  LDS stages laid out
+// issue MFMAs while the other waits on LDS): the two-term product in a 2 x 4
+// arrangement of 128 x 64 per wave (8 x 4 v_mfma_f32_16x16x32_bf16 tiles), the
+// single-term one in 4 x 2 of 64 x 128 (4 x 8 tiles: 16 KB of LDS reads per wave
+// and 32-deep step instead of 20; the two-term product would not fit its
+// registers so); 4 waves of 128 x 128 when built with EMC_BF16_WAVES=4.  LDS stages laid out
 // [row][k] (144-byte rows: 128 bytes of data + 16 of padding, so eight lanes'
 // 16-byte reads hit distinct banks); the next stage's global loads (full
 // 128-byte row segments) are issued into registers before the current stage's
@@ -47,8 +49,10 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_bf16_kernel(const uint16_t* _
 
   // 4 waves: 2 x 2 of 128 x 128; 8 waves (two per SIMD): 2 x 4 of 128 x 64
   constexpr int NT = 64 * WAVES;
-  constexpr int WROWS = 128;                    // rows of C per wave
-  constexpr int WCOLS = WAVES == 8 ? 64 : 128;  // columns of C per wave
+  // the single-term product takes 64 x 128 per wave (fewer LDS bytes per MFMA); the
+  // two-term one keeps 128 x 64 (64 x 128 would not fit its registers)
+  constexpr int WROWS = WAVES == 8 && !DUAL ? 64 : 128;   // rows of C per wave
+  constexpr int WCOLS = WAVES == 8 && DUAL ? 64 : 128;    // columns of C per wave
   constexpr int IT = WROWS / 16, JT = WCOLS / 16;
   constexpr int WN = TN / WCOLS;                // waves along N
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
