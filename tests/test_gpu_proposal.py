@@ -192,6 +192,105 @@ def test_dense_bands(gpu_lib):
     _check_restricted(r, 400, "dense bands")
 
 
+@pytest.mark.parametrize("seed,nrot,n_cells,k_top", [(11, 700, 40, 8), (12, 1000, 10, 3), (13, 300, 120, 12)])
+def test_plan_packs_and_lists_are_consistent(gpu_lib, seed, nrot, n_cells, k_top):
+    """The plan's packs of cells, against numpy: every cell in exactly one pack, a
+    pack holding at most 16 rotations unless it is a single cell; the pack-order
+    rotation list a permutation holding each cell's rotations at cell_first, with
+    the cell's index inside its pack; the groups tiling each pack's rotations in
+    runs of at most 32; each pack's list holding exactly the candidate frames that
+    propose one of its cells, each once, with the bits of those cells; and every
+    list entry's column pointing at its frame in its cell's pack list.  The three
+    cases have about 17, 100 (groups of 32 in one-cell packs) and 2.5 rotations per
+    cell (many cells without a rotation)."""
+    import torch
+
+    from gpu_helpers import geometry, upload_counts
+
+    t = tiny_problem(seed, grid_n=16, n_pix=200, n_rot=nrot, n_data=300, photons=200.0)
+    q = np.asarray(t["q"], np.float32).astype(np.float64)
+    quat = np.asarray(t["quat"], np.float32).astype(np.float64)
+    rng = np.random.default_rng(200 + seed)
+    coarse = np.asarray(shoemake_quaternions(rng, n_cells), np.float32)
+    lists = _lists(rng, 300, n_cells, k_top, 2, True)
+    kk = lists.shape[1]
+    audit = np.sort(rng.choice(300, 9, replace=False)).astype(np.int32)
+    geo = geometry(16, q, t["mask"], quat, t["log_w"], 300, E.EMC_PREC_BF16)
+    counts = upload_counts(t["counts"])
+    nz_cap = int((t["counts"] != 0).sum()) + 1
+    buf = torch.empty(E.emc_proposal_bytes(geo, n_cells, kk, 9, nz_cap), dtype=torch.uint8, device="cuda")
+    plan = E.emc_proposal_build(geo, torch.as_tensor(coarse, device="cuda"), n_cells,
+                                torch.as_tensor(lists.reshape(-1), device="cuda"), kk,
+                                torch.as_tensor(audit, device="cuda"), counts, nz_cap, buf)
+    pa = lambda addr, n, dt=torch.int32: E.plan_array(buf, addr, n, dt).cpu().numpy().astype(np.int64)
+    n_packs, nc = plan.n_packs, plan.n_cand
+    cell_of = pa(plan.cell_of, nrot)
+    # the GPU assigns cells in FP32: any cell within FP32 rounding of the best is a tie
+    qn = quat / np.linalg.norm(quat, axis=1, keepdims=True)
+    cn = coarse.astype(np.float64) / np.linalg.norm(coarse.astype(np.float64), axis=1, keepdims=True)
+    dots = np.abs(qn @ cn.T)
+    assert np.all(dots.max(axis=1) - dots[np.arange(nrot), cell_of] <= 1e-6)
+    R = np.bincount(cell_of, minlength=n_cells)
+    pack_of = pa(plan.pack_of, n_cells)
+    cell_first = pa(plan.cell_first, n_cells)
+    pack_rot = pa(plan.pack_rot, nrot)
+    rot_local = pa(plan.rot_local, nrot)
+    assert 1 <= n_packs <= n_cells and pack_of.min() == 0 and pack_of.max() == n_packs - 1
+    assert np.all(np.bincount(pack_of, minlength=n_packs) > 0)
+    np.testing.assert_array_equal(np.sort(pack_rot), np.arange(nrot))
+    members = [np.flatnonzero(pack_of == p) for p in range(n_packs)]
+    pack_start = np.zeros(n_packs, np.int64)
+    local = np.full(n_cells, -1, np.int64)  # index inside the pack (known for cells with rotations)
+    for p, cs in enumerate(members):
+        assert cs.size == 1 or R[cs].sum() <= 16, (p, cs, R[cs])
+        full = cs[R[cs] > 0]
+        if full.size == 0:
+            continue
+        order = full[np.argsort(cell_first[full])]       # the pack's cells in their rotation order
+        pack_start[p] = pos = cell_first[order[0]]
+        for c in order:
+            assert cell_first[c] == pos
+            seg = pack_rot[pos:pos + R[c]]
+            np.testing.assert_array_equal(np.sort(seg), np.flatnonzero(cell_of == c))
+            li = rot_local[pos:pos + R[c]]
+            assert np.all(li == li[0]) and 0 <= li[0] < cs.size
+            local[c] = li[0]
+            pos += R[c]
+        assert np.unique(local[full]).size == full.size
+    # groups: each pack's rotations in runs of at most 32, in order
+    groups = pa(plan.groups, 4 * plan.n_groups).reshape(-1, 4)
+    cg_ptr = pa(plan.cg_ptr, n_cells + 1, torch.int64)
+    for p in range(n_packs):
+        gs = groups[cg_ptr[p]:cg_ptr[p + 1]]
+        total = R[members[p]].sum()
+        assert np.all(gs[:, 0] == p) and np.all(gs[:, 2] <= 32) and gs[:, 2].sum() == total
+        if total:
+            np.testing.assert_array_equal(gs[:, 1], pack_start[p] + np.concatenate([[0], np.cumsum(gs[:-1, 2])]))
+    # lists: exactly the frames proposing a cell of the pack, once, with that cell's bit
+    cand_frames = pa(plan.cand_frames, nc)
+    cells = pa(plan.cand_cells, nc * kk).reshape(nc, kk)
+    np.testing.assert_array_equal(cells, lists[cand_frames])
+    cf_ptr = pa(plan.cf_ptr, n_cells + 1, torch.int64)
+    cf_frame = pa(plan.cf_frame, int(cf_ptr[n_packs]))
+    cf_mask = pa(plan.cf_mask, int(cf_ptr[n_packs])) & 0xffffffff
+    pair_col = pa(plan.pair_col, nc * kk).reshape(nc, kk)
+    for p, cs in enumerate(members):
+        fr = cf_frame[cf_ptr[p]:cf_ptr[p + 1]]
+        want = np.flatnonzero(np.isin(cells, cs).any(axis=1))
+        np.testing.assert_array_equal(np.sort(fr), want)
+        m = cf_mask[cf_ptr[p]:cf_ptr[p + 1]]
+        # one bit per proposed cell of the pack; a cell with rotations at its own index
+        npro = np.isin(cells[fr], cs).sum(axis=1)
+        np.testing.assert_array_equal(np.array([bin(int(x)).count("1") for x in m]), npro)
+        for c in cs[R[cs] > 0]:
+            np.testing.assert_array_equal((m >> local[c]) & 1, (cells[fr] == c).any(axis=1).astype(np.int64))
+    f_idx, t_idx = np.nonzero(cells >= 0)
+    p_of = pack_of[cells[f_idx, t_idx]]
+    np.testing.assert_array_equal(cf_frame[cf_ptr[p_of] + pair_col[f_idx, t_idx]], f_idx)
+    print(f"\n[proposal plan] {n_cells} cells in {n_packs} packs, {plan.n_groups} groups, "
+          f"{int(cf_ptr[n_packs])} list entries for {int((cells >= 0).sum())} proposed (frame, cell) pairs")
+
+
 def test_proposal_with_every_cell_is_full_search(gpu_lib):
     """k_top = n_cells makes every rotation a candidate: the result is the full search."""
     from gpu_helpers import rel_l2
