@@ -38,7 +38,7 @@ W_FLOOR = 1e-10
 
 
 # ---------------------------------------------------------------------------------------
-# rotations (Section 2.2: quaternions encode rotations; rotation R_j with prior weight w_j)
+# rotations (Section 2.2: each rotation R_j given as a unit quaternion, with prior weight w_j)
 # ---------------------------------------------------------------------------------------
 def rotation_matrix(quat: np.ndarray) -> np.ndarray:
     """Rotation matrices [..., 3, 3] of quaternions [..., 4] = (w, x, y, z), normalised first."""

@@ -10,7 +10,7 @@ passage it follows.
 
 Readings of points the paper leaves open:
   * sigma is a caller parameter, fixed within an iteration (the paper keeps it at
-    conservative values or lowers it slowly between iterations).
+    a cautious level or decreases it gradually from one iteration to the next).
   * The E-step and the M-step numerator of iteration n use the fluence phi^(n);
     the iteration also returns phi^(n+1), the fixed-point update (eq. (2.6))
     evaluated on its own slices W^(n).  The paper gives no phi^(0): the first
