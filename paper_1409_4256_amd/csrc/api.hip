@@ -1235,7 +1235,7 @@ emc_status emc_proposal_build(const emc_problem* pb, const float* coarse, int32_
                               P.pair_col, st),
           "pair columns");
   // 4. groups of up to 32 rotations per pack, their storage and the log-likelihood tiles
-  HIP_TRY(launch_cell_groups(pack_ptr, P.cf_ptr, n_cells, cnt, P.cg_ptr, (int4*)P.groups, gsize, P.grp_off, g_max, st),
+  HIP_TRY(launch_pack_groups(pack_ptr, P.cf_ptr, n_cells, cnt, P.cg_ptr, (int4*)P.groups, gsize, P.grp_off, g_max, st),
           "groups");
   HIP_TRY(launch_group_tiles((const int4*)P.groups, P.cg_ptr, n_cells, P.cf_ptr, xcd, (int2*)P.tiles,
                              tile_cap(g_max, n_cand), scal, st),

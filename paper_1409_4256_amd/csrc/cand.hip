@@ -1,12 +1,13 @@
-// Candidate (learned-proposal) E- and M-steps as cell-major MFMA contractions.
+// Candidate (learned-proposal) E- and M-steps as pack-major MFMA contractions.
 //
-// The fine rotations of a coarse cell are split into groups of at most 32; the
-// frames that propose the cell form its frame list.  For every group the
-// log-likelihoods of all (rotation, listed frame) pairs are one small dense
-// product
+// Neighbouring coarse cells are gathered into packs (proposal.hip); a pack's fine
+// rotations are split into groups of at most 32, and the frames that propose any
+// of its cells form its frame list (each frame once, with a bitmask of the cells
+// it proposes).  For every group the log-likelihoods of all (rotation, listed
+// frame) pairs are one small dense product
 //     G[frame][r] = scale_r * sum_i (hi_ri + lo_ri) K_i,frame          (eq. 2.4's Q)
-// and, after each frame's E-step over its own candidates, the M-step of the
-// group is
+// and, after each frame's E-step over its own candidates (the rotations of the
+// cells it proposes; the group's other pairs get P = 0), the M-step of the group is
 //     W'_r,i = sum_frames P[r][frame] K_i,frame                         (eq. 2.11)
 // Frames are stored sparsely, band-blocked: for every 128-pixel band a frame's
 // non-zero pixels are 16-bit words (pixel in band << 9 | count) packed in 16-byte
@@ -14,7 +15,7 @@
 // pixels, the M-step's pixel range); inside a run a frame's chunks of the 8 bands
 // are contiguous, frame after frame (run 0 of every frame, then run 1, ...).  A
 // lane that streams one frame band after band thus reads whole cache lines of its
-// own frame, whichever other frames a cell's list holds, and an M-step workgroup's
+// own frame, whichever other frames a pack's list holds, and an M-step workgroup's
 // four waves read the same lines.  A 16-byte record per (frame, run), frame-major,
 // locates the chunks: the run's first chunk (absolute index), the offsets of its
 // bands' first chunks (one byte each) and its chunk count -- one load per frame
@@ -109,7 +110,7 @@ __device__ __forceinline__ void put_rest(uint16_t* base, int stride, int junk, c
 }
 
 // ------------------------------------------------------------------ log-likelihood
-// One workgroup per tile (group g, frames [f0, f0 + 256) of the group's cell).  Wave w
+// One workgroup per tile (group g, frames [f0, f0 + 256) of its pack's list).  Wave w
 // owns frames f0 + 64 w .. + 63 (lane s expands frame s) over every band and both
 // rotation tiles, so the four waves read the same slice rows at about the same
 // time (one fetch from L2 serves the workgroup) and each wave writes its own
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(256) void cand_pwrite_kernel(
 
 // ------------------------------------------------------------------ M-step
 // One workgroup per (group g, 1024-pixel range); it runs over the whole frame list
-// of the group's cell in blocks of 32 frames.  Wave w owns the range's band pair
+// of the group's pack in blocks of 32 frames.  Wave w owns the range's band pair
 // w (256 pixels): it expands the block's frames there into LDS rows [pixel][frame]
 // (lanes s and s + 32 take the two bands of frame s), contracts them with the
 // block's P (B operand, read straight from its blocked layout) and clears the
@@ -802,16 +803,18 @@ __global__ void fill_zero16_kernel(u4* __restrict__ p, int64_t n16) {
     p[e] = u4{0u, 0u, 0u, 0u};
 }
 
-// groups of 32 rotations: count per cell
-__global__ void cell_group_count_kernel(const int64_t* __restrict__ cell_ptr, int n_cells, int32_t* __restrict__ cnt) {
+// groups of up to 32 rotations: count per pack (cell_ptr: the packs' first pack-order
+// rotation, n_cells + 1 entries; packs past the last hold none)
+__global__ void pack_group_count_kernel(const int64_t* __restrict__ cell_ptr, int n_cells, int32_t* __restrict__ cnt) {
   const int c = blockIdx.x * 256 + threadIdx.x;
   if (c >= n_cells) return;
   const int64_t R = cell_ptr[c + 1] - cell_ptr[c];
   cnt[c] = (int32_t)((R + kGR - 1) / kGR);
 }
 
-// group table and storage sizes (Fp * 32 elements, Fp = frame list rounded up to 32)
-__global__ void cell_group_fill_kernel(const int64_t* __restrict__ cell_ptr, const int64_t* __restrict__ cf_ptr,
+// group table and storage sizes (Fp * 32 elements, Fp = the pack's frame list
+// rounded up to 32)
+__global__ void pack_group_fill_kernel(const int64_t* __restrict__ cell_ptr, const int64_t* __restrict__ cf_ptr,
                                        const int64_t* __restrict__ cg_ptr, int n_cells, int4* __restrict__ groups,
                                        int64_t* __restrict__ gsize) {
   const int c = blockIdx.x * 256 + threadIdx.x;
@@ -1019,18 +1022,18 @@ hipError_t launch_fill_zero_bytes(void* p, int64_t bytes, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_cell_groups(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int32_t* cnt,
+hipError_t launch_pack_groups(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int32_t* cnt,
                               int64_t* cg_ptr, int4* groups, int64_t* gsize, int64_t* grp_off, int64_t g_max,
                               hipStream_t st) {
   const unsigned nb = (unsigned)((n_cells + 255) / 256);
-  cell_group_count_kernel<<<nb, 256, 0, st>>>(cell_ptr, n_cells, cnt);
+  pack_group_count_kernel<<<nb, 256, 0, st>>>(cell_ptr, n_cells, cnt);
   hipError_t e = launch_scan(cnt, n_cells, cg_ptr, st);
   if (e != hipSuccess) return e;
   // every group's size; sizes past the last group stay zero so the scan of g_max
   // entries gives the offsets of the real groups
   e = launch_fill_i32((int32_t*)gsize, 2 * g_max, 0, st);
   if (e != hipSuccess) return e;
-  cell_group_fill_kernel<<<nb, 256, 0, st>>>(cell_ptr, cf_ptr, cg_ptr, n_cells, groups, gsize);
+  pack_group_fill_kernel<<<nb, 256, 0, st>>>(cell_ptr, cf_ptr, cg_ptr, n_cells, groups, gsize);
   return launch_scan64(gsize, g_max, grp_off, st);
 }
 

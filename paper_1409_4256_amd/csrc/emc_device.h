@@ -185,8 +185,6 @@ hipError_t launch_cand_mask(const int32_t* topk, int k_top, const int32_t* frame
                             uint32_t* mask, hipStream_t st);
 hipError_t launch_cand_cells(const int32_t* topk, int k_top, const int32_t* frames, int64_t n_frames, int n_cells,
                              int32_t* cells, int32_t* keys, hipStream_t st);
-hipError_t launch_pair_columns(const int32_t* order, int64_t n_pairs, int k_top, const int32_t* keys,
-                               const int64_t* cf_ptr, int32_t* cf_frame, int32_t* pair_col, hipStream_t st);
 // packs of neighbouring cells (at most kPackRot rotations in all; a cell with more is a pack of its own)
 constexpr int kPackRot = 16;  // the packing cap: one 16-row MFMA tile (<= the candidate kernels' group of 32)
 hipError_t launch_packs(const float* coarse, int n_cells, const int64_t* cell_ptr, const int32_t* cell_of,
@@ -240,7 +238,7 @@ int run_count(int nbands);
 hipError_t launch_run_table(const int64_t* ptr, int64_t n_frames, int nbands, void* runs, hipStream_t st);
 hipError_t launch_band_dot(const void* runs, int nbands, const void* chunks, int64_t n_frames, const double* c,
                            double* b, hipStream_t st);
-hipError_t launch_cell_groups(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int32_t* cnt,
+hipError_t launch_pack_groups(const int64_t* cell_ptr, const int64_t* cf_ptr, int n_cells, int32_t* cnt,
                               int64_t* cg_ptr, int4* groups, int64_t* gsize, int64_t* grp_off, int64_t g_max,
                               hipStream_t st);
 hipError_t launch_group_tiles(const int4* groups, const int64_t* cg_ptr, int n_cells, const int64_t* cf_ptr,

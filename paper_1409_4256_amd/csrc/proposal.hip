@@ -1,7 +1,8 @@
-// Plan of the learned-proposal form: coarse cells of the fine rotations, the
-// candidate frames grouped by their best cell and the (frame, proposed cell)
-// pairs grouped by cell.  The candidate E- and M-steps and the candidate frames'
-// sparse band format are in cand.hip.
+// Plan of the learned-proposal form: coarse cells of the fine rotations, packs
+// of neighbouring cells, the candidate frames grouped by their best cell and
+// the union frame lists of each pack with one bit per proposed cell.  The
+// candidate E- and M-steps and the candidate frames' sparse band format are in
+// cand.hip.
 #include "emc_device.h"
 
 namespace emc {
@@ -203,18 +204,6 @@ __global__ __launch_bounds__(256) void dup_check_kernel(const int32_t* __restric
     }
   }
   if (__ballot(dup) != 0ull && lane == 0) atomicOr(flag, 2);
-}
-
-// pairs sorted by cell (order = pair indices): frame of each pair in cell order and
-// the column of each pair inside its cell's frame list
-__global__ void pair_columns_kernel(const int32_t* __restrict__ order, int64_t n_pairs, int k_top,
-                                    const int32_t* __restrict__ keys, const int64_t* __restrict__ cf_ptr,
-                                    int32_t* __restrict__ cf_frame, int32_t* __restrict__ pair_col) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n_pairs) return;
-  const int32_t pr = order[e];
-  cf_frame[e] = pr / k_top;
-  pair_col[pr] = (int32_t)(e - cf_ptr[keys[pr]]);
 }
 
 // ------------------------------------------------------------------ packs of cells
@@ -515,14 +504,6 @@ hipError_t launch_dup_check(const int32_t* cells, int k_top, int64_t n_frames, i
   if (n_frames <= 0) return hipSuccess;
   const size_t shm = (size_t)4 * ((n_cells + 31) / 32) * sizeof(uint32_t);
   dup_check_kernel<<<(unsigned)((n_frames + 3) / 4), 256, shm, st>>>(cells, k_top, n_frames, n_cells, flag);
-  return hipGetLastError();
-}
-
-hipError_t launch_pair_columns(const int32_t* order, int64_t n_pairs, int k_top, const int32_t* keys,
-                               const int64_t* cf_ptr, int32_t* cf_frame, int32_t* pair_col, hipStream_t st) {
-  if (n_pairs > 0)
-    pair_columns_kernel<<<(unsigned)((n_pairs + 255) / 256), 256, 0, st>>>(order, n_pairs, k_top, keys, cf_ptr,
-                                                                           cf_frame, pair_col);
   return hipGetLastError();
 }
 
