@@ -30,6 +30,7 @@
 //   P  bf16  [Fp/32][32][32]     blocks of 32 frames, rotation-major inside a block,
 //                                which is the MFMA operand layout of the M-step.
 #include "emc_device.h"
+#include "lse.h"
 
 namespace emc {
 
@@ -286,16 +287,6 @@ __global__ __launch_bounds__(256, 2) void cand_loglik_kernel(
 // FP64 rounding of the sum).  Responsibilities keep every term; a - L is formed in
 // FP64 and its exponential evaluated in FP32 (P is stored in BF16), skipped only
 // below -110, where its FP32 value is 0.
-constexpr double kLseDrop = 64.0;
-__device__ __forceinline__ void lse_push(double& mx, double& s, double a) {
-  if (!(a > mx - kLseDrop)) return;  // zero prior weight, or negligible against the maximum
-  if (a > mx) {
-    s = s * exp(mx - a) + 1.0;
-    mx = a;
-  } else {
-    s += exp(a - mx);
-  }
-}
 
 // The rotation term of a, log w_j - S_j, in the packs' rotation order (entry t
 // belongs to rotation pack_rot[t]), so that a group's terms are contiguous.
@@ -331,6 +322,7 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
   if (f >= n_frames) return;  // uniform per wave
   const double bk = b[f];
   double mx = -INFINITY, sum = 0.0;
+  const ExpCoef ec = exp_coef();
   for (int t = lane; t < k_top; t += 64) {
     const int c = cells[f * k_top + t];
     if (c < 0) continue;
@@ -348,18 +340,12 @@ __global__ __launch_bounds__(256) void cand_estep_kernel(
       for (int q = 0; q < kGR / 4; ++q)
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-          if (4 * q + u >= a && 4 * q + u < z) lse_push(mx, sum, ((double)v[q][u] + bk) + cr[4 * q + u]);
+          if (4 * q + u >= a && 4 * q + u < z) lse_push(mx, sum, ((double)v[q][u] + bk) + cr[4 * q + u], ec);
     }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    const double m2 = __shfl_xor(mx, o, 64), s2 = __shfl_xor(sum, o, 64);
-    if (m2 > mx) {
-      sum = sum * exp(mx - m2) + s2;
-      mx = m2;
-    } else if (m2 > -INFINITY) {
-      sum += s2 * exp(m2 - mx);
-    }
+    lse_merge(mx, sum, __shfl_xor(mx, o, 64), __shfl_xor(sum, o, 64));
   }
   if (lane == 0) L[f] = mx + log(sum);
 }

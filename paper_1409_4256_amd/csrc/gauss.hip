@@ -12,6 +12,7 @@
 // P_jk / phi_jk with the frames (the same GEMM as the Poisson M-step), and the
 // c-step's weight stays rho_j = sum_k P_jk (eq. (2.12)).
 #include "emc_device.h"
+#include "lse.h"
 
 namespace emc {
 
@@ -124,31 +125,18 @@ __global__ __launch_bounds__(256) void gauss_stats_kernel(const float* __restric
   const double bk = live ? b[k] : 0.0, k2k = live ? k2[k] : 0.0;
   double m = -INFINITY, s = 0.0;
   if (live) {
+    const ExpCoef ec = exp_coef();
     for (int j = wave; j < n_rot; j += 4) {
       const int64_t e = (int64_t)j * ld + k;
       const GaussTerm t = gauss_term(Gd[e], bk, k2k, s2[j], log_w[j], own ? 1.0f : phi[e], own, inv2s2);
-      if (!(t.a > -INFINITY)) continue;  // zero prior weight: no contribution
-      if (t.a > m) {
-        s = s * exp(m - t.a) + 1.0;
-        m = t.a;
-      } else {
-        s += exp(t.a - m);
-      }
+      lse_push(m, s, t.a, ec);  // zero prior weight (a = -inf): no contribution
     }
   }
   sm[wave][lane] = m;
   ss[wave][lane] = s;
   __syncthreads();
   if (wave == 0 && live) {
-    for (int w = 1; w < 4; ++w) {
-      const double m2 = sm[w][lane], s2v = ss[w][lane];
-      if (m2 > m) {
-        s = s * exp(m - m2) + s2v;
-        m = m2;
-      } else if (m2 > -INFINITY) {
-        s += s2v * exp(m2 - m);
-      }
-    }
+    for (int w = 1; w < 4; ++w) lse_merge(m, s, sm[w][lane], ss[w][lane]);
     stats[2 * k] = m;
     stats[2 * k + 1] = s;
   }
