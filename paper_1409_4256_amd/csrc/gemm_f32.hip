@@ -7,8 +7,11 @@
 // per SIMD, so that one issues MFMAs while the other waits at the stage barrier or
 // on LDS), each wave 128 x 64 built from 8 x 4 v_mfma_f32_16x16x4_f32 tiles
 // (the proposal network's small products: 256 x 128 with 4 waves).  Operands
-// are staged through double-buffered LDS laid out [row][k] with a 4-float pad;
-// every lane reads 4 consecutive k of one row with a single 128-bit LDS read
+// are staged through double-buffered LDS laid out [row][k], 128-byte rows with
+// their 16-byte chunks swizzled (chunk c of row r at c ^ ((r >> 1) & 7), so that
+// neither the 16-byte stores nor the reads of 16 rows at one k collide in a
+// bank; a 16-byte pad per row instead measured 1.5e10 bank-conflict cycles per
+// launch); every lane reads 4 consecutive k of one row with a single 128-bit LDS read
 // and feeds them to 4 successive MFMAs (the k order inside a 16-wide chunk is
 // permuted identically for both operands, which leaves the sum unchanged).
 #include "emc_device.h"
@@ -17,7 +20,8 @@ namespace emc {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 256, BK = 32, LDK = BK + 4;
+constexpr int BM = 256, BK = 32;
+__device__ __forceinline__ int lds_at(int r, int c) { return r * BK + 4 * (c ^ ((r >> 1) & 7)); }
 constexpr int GROUP_M = 8;  // M tiles per schedule group: blocks sharing an M tile land on one XCD
 
 // USE only names the instantiation (0: the iteration's contractions, 1: the proposal
@@ -31,8 +35,8 @@ __global__ __launch_bounds__(128 * NWN) void gemm_f32_kernel(const float* __rest
   constexpr int LA = BM * BK / 4 / NT, LB = BN * BK / 4 / NT;  // 16-byte loads per thread and stage
   // two waves per SIMD (NWN = 4) fit their 256 registers only with one 16-deep k step live
   constexpr int KU = NWN == 2 ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) float As[2][BM * LDK];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BN * LDK];
+  __shared__ __attribute__((aligned(16))) float As[2][BM * BK];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BN * BK];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / NWN, wn = wave % NWN;
@@ -71,12 +75,12 @@ __global__ __launch_bounds__(128 * NWN) void gemm_f32_kernel(const float* __rest
 #pragma unroll
     for (int u = 0; u < LA; ++u) {
       const int f = tid + NT * u, r = f >> 3, c4 = f & 7;
-      *reinterpret_cast<f4*>(as + r * LDK + 4 * c4) = ra[u];
+      *reinterpret_cast<f4*>(as + lds_at(r, c4)) = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < LB; ++u) {
       const int f = tid + NT * u, r = f >> 3, c4 = f & 7;
-      *reinterpret_cast<f4*>(bs + r * LDK + 4 * c4) = rb[u];
+      *reinterpret_cast<f4*>(bs + lds_at(r, c4)) = rb[u];
     }
   };
 
@@ -91,19 +95,19 @@ __global__ __launch_bounds__(128 * NWN) void gemm_f32_kernel(const float* __rest
   store_stage(0);
   __syncthreads();
 
-  const int arow = wm * 128 + (lane & 15), brow = wn * 64 + (lane & 15), kofs = 4 * (lane >> 4);
+  const int arow = wm * 128 + (lane & 15), brow = wn * 64 + (lane & 15), kc = lane >> 4;
   for (int64_t s = 0; s < nk; ++s) {
     const int buf = (int)(s & 1);
     if (s + 1 < nk) load_stage((s + 1) * BK);
-    const float* as = As[buf] + arow * LDK + kofs;
-    const float* bs = Bs[buf] + brow * LDK + kofs;
+    const float* as = As[buf];
+    const float* bs = Bs[buf];
 #pragma unroll KU
     for (int kk = 0; kk < BK; kk += 16) {
       f4 a[8], b[4];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) a[i] = *reinterpret_cast<const f4*>(as + i * 16 * LDK + kk);
+      for (int i = 0; i < 8; ++i) a[i] = *reinterpret_cast<const f4*>(as + lds_at(arow + 16 * i, (kk >> 2) + kc));
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const f4*>(bs + j * 16 * LDK + kk);
+      for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const f4*>(bs + lds_at(brow + 16 * j, (kk >> 2) + kc));
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
