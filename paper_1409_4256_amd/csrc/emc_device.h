@@ -31,6 +31,23 @@ __device__ __forceinline__ Rot quat_rot(const float* __restrict__ qv) {
   return r;
 }
 
+// Grid cell of a rotated pixel: the lowest corner (bx, by, bz) of its 2 x 2 x 2
+// neighbourhood and the fractional offsets (tx, ty, tz) of grid-frame position p.
+struct Cell {
+  int bx, by, bz;
+  double tx, ty, tz;
+};
+
+__device__ __forceinline__ Cell cell_at(const Rot& r, const float* __restrict__ qi, int N) {
+  const double qx = qi[0], qy = qi[1], qz = qi[2];
+  const double h = 0.5 * N;
+  const double px = r.m[0] * qx + r.m[1] * qy + r.m[2] * qz + h;
+  const double py = r.m[3] * qx + r.m[4] * qy + r.m[5] * qz + h;
+  const double pz = r.m[6] * qx + r.m[7] * qy + r.m[8] * qz + h;
+  const double fx0 = floor(px), fy0 = floor(py), fz0 = floor(pz);
+  return Cell{(int)fx0, (int)fy0, (int)fz0, px - fx0, py - fy0, pz - fz0};
+}
+
 // Trilinear stencil of grid-frame position p: the up to 8 grid points with
 // non-zero tent weight.  Points outside the N^3 box get weight 0 (index 0).
 struct Stencil {
@@ -40,28 +57,49 @@ struct Stencil {
 };
 
 __device__ __forceinline__ Stencil stencil_at(const Rot& r, const float* __restrict__ qi, int N) {
-  const double qx = qi[0], qy = qi[1], qz = qi[2];
-  const double h = 0.5 * N;
-  const double px = r.m[0] * qx + r.m[1] * qy + r.m[2] * qz + h;
-  const double py = r.m[3] * qx + r.m[4] * qy + r.m[5] * qz + h;
-  const double pz = r.m[6] * qx + r.m[7] * qy + r.m[8] * qz + h;
-  const double fx0 = floor(px), fy0 = floor(py), fz0 = floor(pz);
-  const int bx = (int)fx0, by = (int)fy0, bz = (int)fz0;
-  const double tx = px - fx0, ty = py - fy0, tz = pz - fz0;
+  const Cell c = cell_at(r, qi, N);
   Stencil s;
-  s.bx = bx;
-  s.by = by;
-  s.bz = bz;
+  s.bx = c.bx;
+  s.by = c.by;
+  s.bz = c.bz;
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
     const int dx = t >> 2, dy = (t >> 1) & 1, dz = t & 1;
-    const int vx = bx + dx, vy = by + dy, vz = bz + dz;
+    const int vx = c.bx + dx, vy = c.by + dy, vz = c.bz + dz;
     const bool in = (unsigned)vx < (unsigned)N && (unsigned)vy < (unsigned)N && (unsigned)vz < (unsigned)N;
-    const double w = (dx ? tx : 1.0 - tx) * (dy ? ty : 1.0 - ty) * (dz ? tz : 1.0 - tz);
+    const double w = (dx ? c.tx : 1.0 - c.tx) * (dy ? c.ty : 1.0 - c.ty) * (dz ? c.tz : 1.0 - c.tz);
     s.idx[t] = in ? (vx * N + vy) * N + vz : 0;
     s.w[t] = in ? w : 0.0;
   }
   return s;
+}
+
+// The trilinear value sum_t w_t model[idx_t] of stencil_at, its terms added in the
+// same corner order (the same bits), with the model read as four z-pairs: one
+// 8-byte load per (dx, dy), starting at z0 = bz clamped to [0, N - 2] so that the
+// pair stays inside its row (N >= 2); a corner outside the grid adds 0, its pair
+// read from an in-grid address.
+__device__ __forceinline__ double trilinear_at(const float* __restrict__ model, int N, const Rot& r,
+                                               const float* __restrict__ qi) {
+  const Cell c = cell_at(r, qi, N);
+  const int z0 = c.bz < 0 ? 0 : (c.bz > N - 2 ? N - 2 : c.bz);
+  double W = 0.0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int dx = p >> 1, dy = p & 1;
+    const int vx = c.bx + dx, vy = c.by + dy;
+    const bool inxy = (unsigned)vx < (unsigned)N && (unsigned)vy < (unsigned)N;
+    float v[2];
+    __builtin_memcpy(v, model + (inxy ? ((int64_t)vx * N + vy) * N + z0 : 0), sizeof(v));
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz) {
+      const int vz = c.bz + dz;
+      const bool in = inxy && (unsigned)vz < (unsigned)N;
+      const double w = (dx ? c.tx : 1.0 - c.tx) * (dy ? c.ty : 1.0 - c.ty) * (dz ? c.tz : 1.0 - c.tz);
+      W += (in ? w : 0.0) * (double)v[vz == z0 ? 0 : 1];
+    }
+  }
+  return W;
 }
 
 template <typename T>

@@ -21,22 +21,14 @@ __global__ __launch_bounds__(256) void centre_kernel(const float* __restrict__ m
   for (int t = 0; t < nc; ++t) {
     const int j = (int)(((int64_t)t * n_rot) / nc);
     const Rot r = quat_rot(quat + 4 * (int64_t)j);
-    const Stencil s = stencil_at(r, q + 3 * i, N);
-    double W = 0.0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) W += s.w[k] * (double)model[s.idx[k]];
-    acc += log(fmax(W, kFloor));
+    acc += log(fmax(trilinear_at(model, N, r, q + 3 * i), kFloor));
   }
   c[i] = acc / nc;
 }
 
 __device__ __forceinline__ double slice_value(const float* __restrict__ model, int N, const Rot& r,
                                               const float* __restrict__ qi) {
-  const Stencil s = stencil_at(r, qi, N);
-  double W = 0.0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) W += s.w[k] * (double)model[s.idx[k]];
-  return fmax(W, kFloor);
+  return fmax(trilinear_at(model, N, r, qi), kFloor);
 }
 
 __device__ __forceinline__ double block_sum4(double v, double* red) {
