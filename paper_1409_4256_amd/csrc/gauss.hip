@@ -33,11 +33,7 @@ __global__ __launch_bounds__(256) void gauss_centre_kernel(const float* __restri
   for (int t = 0; t < nc; ++t) {
     const int j = (int)(((int64_t)t * n_rot) / nc);
     const Rot r = quat_rot(quat + 4 * (int64_t)j);
-    const Stencil s = stencil_at(r, q + 3 * i, N);
-    double W = 0.0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) W += s.w[k] * (double)model[s.idx[k]];
-    acc += W;
+    acc += trilinear_at(model, N, r, q + 3 * i);
   }
   c[i] = acc / nc;
 }
@@ -58,10 +54,7 @@ __global__ __launch_bounds__(256) void gauss_expand_kernel(const float* __restri
   for (int64_t i = threadIdx.x; i < stride; i += 256) {
     float out = 0.0f;
     if (i < n_pix && mask[i]) {
-      const Stencil s = stencil_at(r, q + 3 * i, N);
-      double W = 0.0;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) W += s.w[k] * (double)model[s.idx[k]];
+      const double W = trilinear_at(model, N, r, q + 3 * i);
       sum += W * W;
       out = (float)(W - c[i]);
     }
