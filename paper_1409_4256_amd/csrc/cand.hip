@@ -43,7 +43,8 @@ static_assert(kPackRot <= kGR, "a pack of cells fits one group");
 constexpr int kFT = 64;             // frames per log-likelihood wave (four 16-column tiles)
 constexpr int kTileF = 4 * kFT;     // frames per log-likelihood workgroup (tile)
 constexpr int kBand = 128;          // pixels per band (granularity of the entry-offset table)
-constexpr int kLRow = kBand + 8;    // LDS row of one frame's band, bf16 (272 bytes: conflict-free 16-byte reads)
+constexpr int kLRow = kBand + 8;    // LDS row of one frame's band, bf16 (272 bytes; 288, which spreads the
+                                     // MFMA operand reads over all banks, measured the same)
 constexpr int kFB = 32;             // frames per M-step block (one MFMA reduction step)
 constexpr int kKRow = kFB + 8;      // LDS row of one pixel's frames, bf16 (80 bytes)
 
