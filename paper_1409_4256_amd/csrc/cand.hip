@@ -11,7 +11,8 @@
 //     W'_r,i = sum_frames P[r][frame] K_i,frame                         (eq. 2.11)
 // Frames are stored sparsely, band-blocked: for every 128-pixel band a frame's
 // non-zero pixels are 16-bit words (pixel in band << 9 | count) packed in 16-byte
-// chunks of 8 (the last one padded with 0xffff).  Bands come in runs of 8 (1024
+// chunks of 8 (the last one padded with count-0 words at a pixel of the band
+// without photons, so that expanding a word never needs a test).  Bands come in runs of 8 (1024
 // pixels, the M-step's pixel range); inside a run a frame's chunks of the 8 bands
 // are contiguous, frame after frame (run 0 of every frame, then run 1, ...).  A
 // lane that streams one frame band after band thus reads whole cache lines of its
@@ -53,7 +54,6 @@ __device__ __forceinline__ uint16_t count_bf16(uint32_t e) {
   return (uint16_t)(__float_as_uint((float)(e & 0xffffu)) >> 16);
 }
 
-constexpr uint32_t kPad = 0xffffu;  // padding word of a chunk
 constexpr int kRun = 8;             // bands per run of the chunk layout (the M-step's 1024-pixel range)
 
 // Chunks [x, y) of band i (0..kRun-1) of a run record {first chunk, offsets of
@@ -79,35 +79,32 @@ __device__ __forceinline__ u4 load_chunk(const u4* __restrict__ p) {
 constexpr int kWin = 2;              // chunks per band held in registers (16 pixels)
 
 // Writes (CLEAR = false) or zeroes one chunk's pixels: word e goes to
-// base[(e >> 9) * stride] as the BF16 count (e & 511); a padding word goes to
-// base[junk], a slot of the lane's own that no MFMA reads (a select, not a branch).
+// base[(e >> 9) * stride] as the BF16 count (e & 511).  No word needs a test: a
+// chunk's padding words carry count 0 at a pixel whose count is 0, and the
+// callers' filler chunks either come before every real word of the band (count 0
+// anywhere) or repeat a real chunk (the same values again).
 template <bool CLEAR>
-__device__ __forceinline__ void put_chunk(uint16_t* base, int stride, int junk, u4 ch) {
+__device__ __forceinline__ void put_chunk(uint16_t* base, int stride, u4 ch) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const uint32_t e = h ? (ch[u] >> 16) : (ch[u] & 0xffffu);
-      const int off = e == kPad ? junk : (int)(e >> 9) * stride;
-      base[off] = CLEAR ? (uint16_t)0 : count_bf16(e & 511u);
+      base[(int)(e >> 9) * stride] = CLEAR ? (uint16_t)0 : count_bf16(e & 511u);
     }
   }
 }
 
-// chunks first, first + step, ... < c1 of a band beyond the register window
-// (step 1: one lane per frame; 2: two lanes per frame taking alternate chunks),
-// loaded four at a time
-// (chunks from `mid` on belong to the next band: their pixels go `next` further)
+// chunks first, first + 1, ... < c1 of a band beyond the register window, loaded
+// four at a time; slots past c1 repeat chunk c1 - 1
 template <bool CLEAR, bool NT>
-__device__ __forceinline__ void put_rest(uint16_t* base, int stride, int junk, const u4* __restrict__ src, int first,
-                                         int c1, int step, int mid = INT_MAX, int next = 0) {
-  const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
-  for (int c = first; c < c1; c += 4 * step) {
+__device__ __forceinline__ void put_rest(uint16_t* base, int stride, const u4* __restrict__ src, int first, int c1) {
+  for (int c = first; c < c1; c += 4) {
     u4 v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = c + u * step < c1 ? load_chunk<NT>(src + c + u * step) : pad;
+    for (int u = 0; u < 4; ++u) v[u] = load_chunk<NT>(src + (c + u < c1 ? c + u : c1 - 1));
 #pragma unroll
-    for (int u = 0; u < 4; ++u) put_chunk<CLEAR>(base + (c + u * step >= mid ? next : 0), stride, junk, v[u]);
+    for (int u = 0; u < 4; ++u) put_chunk<CLEAR>(base, stride, v[u]);
   }
 }
 
@@ -149,9 +146,6 @@ __device__ __forceinline__ void cand_loglik_tile(
 
   uint16_t* rows = lds + wave * kFT * kLRow;
   uint16_t* frow = rows + lane * kLRow;
-  // padding words go to column kBand + 2 (lane / 16) of the lane's row: past the
-  // MFMA's 128 columns, and in a different bank for each lane of the wave
-  const int junk = kBand + 2 * (lane >> 4);
   for (int e = lane; e < kFT * kLRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = u4{0u, 0u, 0u, 0u};
 
   f4 acc[NT][4];
@@ -161,7 +155,8 @@ __device__ __forceinline__ void cand_loglik_tile(
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
   const u4 zero = {0u, 0u, 0u, 0u};
-  const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+  // window slots past a band's chunks hold zero chunks (count 0 at the row's first
+  // pixel), written before the band's real chunks
   // pipeline: chunks of the current band in registers, the next band's chunk range;
   // the records of the current run and the next one (loaded on entering a run)
   u4 rc = zero, rcn = zero;
@@ -173,7 +168,7 @@ __device__ __forceinline__ void cand_loglik_tile(
   if (has) r0c = run_band(rc, 0);
   u4 w0[kWin];
 #pragma unroll
-  for (int u = 0; u < kWin; ++u) w0[u] = r0c.x + u < r0c.y ? load_chunk<false>(fb + r0c.x + u) : pad;
+  for (int u = 0; u < kWin; ++u) w0[u] = r0c.x + u < r0c.y ? load_chunk<false>(fb + r0c.x + u) : zero;
   if (has && 1 < nbands) r1c = run_band(rc, 1);
   // A fragments (slice rows, hi and lo, of each row tile) of a band, 4 k-steps
   auto load_a = [&](int band, u4 (&h)[4][NT], u4 (&l)[4][NT]) {
@@ -197,7 +192,7 @@ __device__ __forceinline__ void cand_loglik_tile(
     // have been issued
     u4 w1[kWin];
 #pragma unroll
-    for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? load_chunk<false>(fb + r1c.x + u) : pad;
+    for (int u = 0; u < kWin; ++u) w1[u] = r1c.x + u < r1c.y ? load_chunk<false>(fb + r1c.x + u) : zero;
     if (band > 0 && band % kRun == 0) {  // entering run band / kRun (uniform)
       rc = rcn;
       rcn = has && band / kRun + 1 < n_runs ? rec_of[band / kRun + 1] : zero;
@@ -208,12 +203,12 @@ __device__ __forceinline__ void cand_loglik_tile(
     // bands hold at most 8 photon pixels per frame)
     const bool more = __ballot(r0c.y - r0c.x > 1) != 0;
     if (has) {
-      put_chunk<false>(frow, 1, junk, w0[0]);
-      if (more) {
+      if (more) {  // the window's later slots first: zero fillers precede the real words
 #pragma unroll
-        for (int u = 1; u < kWin; ++u) put_chunk<false>(frow, 1, junk, w0[u]);
-        put_rest<false, false>(frow, 1, junk, fb, r0c.x + kWin, r0c.y, 1);
+        for (int u = kWin - 1; u >= 1; --u) put_chunk<false>(frow, 1, w0[u]);
       }
+      put_chunk<false>(frow, 1, w0[0]);
+      if (more) put_rest<false, false>(frow, 1, fb, r0c.x + kWin, r0c.y);
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
@@ -236,10 +231,10 @@ __device__ __forceinline__ void cand_loglik_tile(
     // in order, so the MFMA operand reads above are done)
     if (has) {
       if (r0c.y - r0c.x <= kWin) {
-        put_chunk<true>(frow, 1, junk, w0[0]);
+        put_chunk<true>(frow, 1, w0[0]);
         if (more) {
 #pragma unroll
-          for (int u = 1; u < kWin; ++u) put_chunk<true>(frow, 1, junk, w0[u]);
+          for (int u = 1; u < kWin; ++u) put_chunk<true>(frow, 1, w0[u]);
         }
       } else {
 #pragma unroll
@@ -445,7 +440,6 @@ __device__ __forceinline__ void cand_mstep_range(
     for (int t = 0; t < NT; ++t) acc[i][t] = f4{0.f, 0.f, 0.f, 0.f};
   double rs0 = 0.0, rs1 = 0.0;
   const u4 zero = {0u, 0u, 0u, 0u};
-  const u4 pad = {0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
   constexpr int kNext = kBand * kKRow;  // LDS offset of the pair's second band
 
   // this lane's band of the pair (band 2 w + par of run pr, the workgroup's pixel
@@ -455,9 +449,10 @@ __device__ __forceinline__ void cand_mstep_range(
   const u4* run_pr = runs + (int64_t)n_list * n_runs + (int64_t)pr * n_list;
   const bool sparse = dense_band[band + par] < 0;
   uint16_t* fcol_b = fcol + par * kNext;
-  // padding words go to column kFB + 2 (lane / 16) of pixel row `slot` (never an
-  // MFMA operand; a different bank for each lane of the wave)
-  const int junk = slot * kKRow + kFB + 2 * (lane >> 4) - slot - par * kNext;
+  // window slots past a band's chunks hold filler chunks of count-0 words at pixel
+  // row `slot` (a different bank for each lane), written before the real chunks
+  const uint32_t fw = (uint32_t)slot << 9;
+  const u4 fill = {fw | fw << 16, fw | fw << 16, fw | fw << 16, fw | fw << 16};
   // a frame's record (a zero record: no chunks); decoded one block after its load
   auto record_of = [&](int32_t fr) -> u4 { return fr < 0 || !sparse ? u4{0u, 0u, 0u, 0u} : run_pr[fr]; };
   auto frame_at = [&](int64_t f0) -> int32_t { return f0 + slot < F ? cf[f0 + slot] : -1; };
@@ -473,7 +468,7 @@ __device__ __forceinline__ void cand_mstep_range(
   int32_t fr2 = frame_at(2 * kFB);
   u4 w0[kWin];
 #pragma unroll
-  for (int u = 0; u < kWin; ++u) w0[u] = q0.x + u < q0.y ? load_chunk<true>(fb + q0.x + u) : pad;
+  for (int u = 0; u < kWin; ++u) w0[u] = q0.x + u < q0.y ? load_chunk<true>(fb + q0.x + u) : fill;
   u4 e1 = record_of(fr1);
   u4 b0, b1;
   load_p(0, b0, b1);
@@ -487,12 +482,12 @@ __device__ __forceinline__ void cand_mstep_range(
     const int2 q1 = run_band(e1, bi);
     u4 w1[kWin];
 #pragma unroll
-    for (int u = 0; u < kWin; ++u) w1[u] = q1.x + u < q1.y ? load_chunk<true>(fb + q1.x + u) : pad;
+    for (int u = 0; u < kWin; ++u) w1[u] = q1.x + u < q1.y ? load_chunk<true>(fb + q1.x + u) : fill;
     const u4 e2 = record_of(fr2);
     const int32_t fr3 = frame_at(f0 + 3 * kFB);
 #pragma unroll
-    for (int u = 0; u < kWin; ++u) put_chunk<false>(fcol_b, kKRow, junk, w0[u]);
-    put_rest<false, true>(fcol_b, kKRow, junk, fb, q0.x + kWin, q0.y, 1);
+    for (int u = kWin - 1; u >= 0; --u) put_chunk<false>(fcol_b, kKRow, w0[u]);  // fillers before real words
+    put_rest<false, true>(fcol_b, kKRow, fb, q0.x + kWin, q0.y);
     if (nf < kFB) {  // frames past the list end hold no responsibility
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -529,7 +524,7 @@ __device__ __forceinline__ void cand_mstep_range(
     // otherwise all of them with contiguous 16-byte stores
     if (__ballot(q0.y - q0.x > kWin) == 0) {
 #pragma unroll
-      for (int u = 0; u < kWin; ++u) put_chunk<true>(fcol_b, kKRow, junk, w0[u]);
+      for (int u = 0; u < kWin; ++u) put_chunk<true>(fcol_b, kKRow, w0[u]);
     } else {
       for (int e = lane; e < kPair * kKRow / 8; e += 64) reinterpret_cast<u4*>(rows)[e] = zero;
     }
@@ -658,6 +653,7 @@ __global__ void run_table_kernel(const int64_t* __restrict__ ptr, int64_t n_fram
 }
 
 // Fill: words (pixel in band << 9 | count) in pixel order, chunk tails padded
+// with count 0 at the band's first pixel without photons
 __global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restrict__ counts,
                                                         const uint8_t* __restrict__ mask, int n_pix,
                                                         const int32_t* __restrict__ frames, int64_t n_frames, int nb,
@@ -675,6 +671,7 @@ __global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restri
     if (r.x == r.y) continue;  // uniform: empty band
     uint16_t* out = words + (int64_t)r.x * 8;
     int n = 0;
+    unsigned long long bal0 = 0, bal1 = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int i = b * kBand + 64 * h + lane;
@@ -682,8 +679,13 @@ __global__ __launch_bounds__(256) void band_fill_kernel(const uint16_t* __restri
       const unsigned long long bal = __ballot(v != 0u);
       if (v != 0u) out[n + __popcll(bal & below)] = (uint16_t)(((uint32_t)(64 * h + lane) << 9) | v);
       n += __popcll(bal);
+      (h ? bal1 : bal0) = bal;
     }
-    for (int t = n + lane; t < 8 * (r.y - r.x); t += 64) out[t] = (uint16_t)kPad;
+    // padding words: count 0 at the band's first pixel without photons (one exists:
+    // a band of 128 counted pixels fills its 16 chunks exactly)
+    const unsigned long long z0 = ~bal0, z1 = ~bal1;
+    const int zp = z0 ? __builtin_ctzll(z0) : (z1 ? 64 + __builtin_ctzll(z1) : 0);
+    for (int t = n + lane; t < 8 * (r.y - r.x); t += 64) out[t] = (uint16_t)(zp << 9);
   }
 }
 
@@ -709,7 +711,7 @@ __global__ __launch_bounds__(256) void band_dot_kernel(const u4* __restrict__ ru
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const uint32_t e = h ? (w[u] >> 16) : (w[u] & 0xffffu);
-            if (e != kPad) acc += (double)(e & 511u) * cb[e >> 9];
+            acc += (double)(e & 511u) * cb[e >> 9];  // padding words: count 0
           }
         }
       }
