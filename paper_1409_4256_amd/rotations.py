@@ -17,6 +17,7 @@ volume by h / |p|^4, so w_j is proportional to |p_j|^-4 (normalised to sum 1).
 """
 from __future__ import annotations
 
+import functools
 import itertools
 import math
 
@@ -81,28 +82,59 @@ def cells_600cell(V: np.ndarray) -> np.ndarray:
     return out
 
 
-def rotation_set(d: int):
-    """(quat [Mrot(d)][4] float64 unit quaternions, log_w [Mrot(d)] float64) of refinement d >= 1."""
-    if d < 1:
-        raise ValueError("refinement d must be >= 1")
+def _compositions(d: int) -> np.ndarray:
+    """The (i, j, k, l) >= 0 with i + j + k + l = d, in lexicographic order."""
+    return np.array([c for c in itertools.product(range(d + 1), repeat=4) if sum(c) == d], dtype=np.int64)
+
+
+@functools.lru_cache(maxsize=None)
+def _cells():
     V = vertices_600cell()
     C = cells_600cell(V)
     # antipode of each vertex: the 600-cell is centrally symmetric
     anti = np.array([int(np.argmin(np.abs(V + V[a]).sum(axis=1))) for a in range(len(V))])
-    comps = [c for c in itertools.product(range(d + 1), repeat=4) if sum(c) == d]
-    points = {}
-    for cell in C:
-        for comp in comps:
-            key = tuple(sorted((int(cell[t]), comp[t]) for t in range(4) if comp[t] > 0))
-            if key in points:
-                continue
-            # one of each pair (p, -p): keep the combination that is lexicographically smaller
-            akey = tuple(sorted((int(anti[v]), k) for v, k in key))
-            if akey < key:
-                key = akey
-            if key not in points:
-                points[key] = sum(k * V[v] for v, k in key) / d
-    P = np.array([points[k] for k in sorted(points)])
+    return V, C, anti
+
+
+def rotation_set(d: int):
+    """(quat [Mrot(d)][4] float64 unit quaternions, log_w [Mrot(d)] float64) of refinement d >= 1.
+
+    Every (cell, composition) names a point by its key, the (vertex, weight) pairs
+    of its non-zero weights in ascending vertex order; a pair (p, -p) is kept once,
+    under the lexicographically smaller of the key and its antipode's key.  Keys
+    are packed into integers (base-B digits, one per pair, missing pairs 0, so that
+    integer order is the tuples' lexicographic order), so the merge is one sort."""
+    if d < 1:
+        raise ValueError("refinement d must be >= 1")
+    V, C, anti = _cells()
+    comps = _compositions(d)
+    B = 121 * (d + 1) + 1               # pair code 1 + v (d + 1) + k < B
+    v = np.repeat(C, len(comps), axis=0).reshape(len(C), len(comps), 4)   # [cell][comp][t]
+    k = np.broadcast_to(comps[None, :, :], v.shape)
+
+    def pack(vv, kk):
+        # pairs with k > 0 in ascending vertex order, then empty digits
+        code = np.where(kk > 0, 1 + vv * (d + 1) + kk, 0)
+        order = np.argsort(np.where(kk > 0, vv, 1 << 20), axis=-1, kind="stable")
+        code = np.take_along_axis(code, order, axis=-1)
+        key = np.zeros(code.shape[:-1], dtype=np.int64)
+        for t in range(4):
+            key = key * B + code[..., t]
+        return key, np.take_along_axis(vv, order, axis=-1), np.take_along_axis(kk, order, axis=-1)
+
+    key, vs, ks = pack(v, k)
+    akey, avs, aks = pack(anti[v], k)
+    use_anti = akey < key
+    key = np.where(use_anti, akey, key).reshape(-1)
+    vs = np.where(use_anti[..., None], avs, vs).reshape(-1, 4)
+    ks = np.where(use_anti[..., None], aks, ks).reshape(-1, 4)
+    uniq, first = np.unique(key, return_index=True)      # sorted keys: the order of the set
+    vs, ks = vs[first], ks[first]
+    # sum of k V[v] over the key's pairs in order, then / d (empty pairs add exact zeros last)
+    P = ks[:, 0, None] * V[vs[:, 0]]
+    for t in range(1, 4):
+        P = P + np.where(ks[:, t, None] > 0, ks[:, t, None] * V[vs[:, t]], 0.0)
+    P = P / d
     r = np.linalg.norm(P, axis=1)
     quat = P / r[:, None]
     w = r ** -4.0

@@ -102,3 +102,35 @@ def test_adaptive_rule():
     assert R.next_refinement(-100.0, -98.0, 3, 8) == 3        # change 2 > 0.98
     assert R.next_refinement(-100.0, -99.5, 8, 8) == 8        # at d_max
     assert R.next_refinement(-100.0, -100.0, 5, 8, tol=0.0) == 6
+
+
+def _rotation_set_by_loops(d):
+    """The rotation set written as plain loops over cells and compositions (a dict
+    of points keyed by their (vertex, weight) pairs): the vectorised builder must
+    reproduce it bit for bit, order and signs included."""
+    import itertools
+
+    V = R.vertices_600cell()
+    C = R.cells_600cell(V)
+    anti = np.array([int(np.argmin(np.abs(V + V[a]).sum(axis=1))) for a in range(len(V))])
+    comps = [c for c in itertools.product(range(d + 1), repeat=4) if sum(c) == d]
+    points = {}
+    for cell in C:
+        for comp in comps:
+            key = tuple(sorted((int(cell[t]), comp[t]) for t in range(4) if comp[t] > 0))
+            akey = tuple(sorted((int(anti[v]), k) for v, k in key))
+            if akey < key:
+                key = akey
+            if key not in points:
+                points[key] = sum(k * V[v] for v, k in key) / d
+    P = np.array([points[k] for k in sorted(points)])
+    r = np.linalg.norm(P, axis=1)
+    w = r ** -4.0
+    return P / r[:, None], np.log(w / w.sum())
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5])
+def test_vectorised_builder_equals_the_loops(d):
+    q, lw = R.rotation_set(d)
+    q0, lw0 = _rotation_set_by_loops(d)
+    assert np.array_equal(q, q0) and np.array_equal(lw, lw0)
