@@ -110,45 +110,102 @@ __device__ __forceinline__ int wmax(int v) {
   return v;
 }
 
-// One wave per (rotation j, pixel group t): the bricks its used pixels reach.
-// FILL = false counts visits per brick; FILL = true writes j * n_groups + t into
-// the brick's list at off[brick] + the next slot of cursor[brick].
+// The bricks the used pixels of visit (rotation j, pixel group t) reach; a wave
+// takes kVisitItems consecutive visits.  FILL = false counts visits per brick;
+// FILL = true writes j * n_groups + t into the brick's list at off[brick] + the
+// next slot of cursor[brick].  A workgroup first tallies its own hits per brick in
+// LDS and then touches each brick's global counter once: the central bricks are
+// reached by every rotation, and one device-scope atomic per hit on those few
+// counters serialised the pass.  (FILL: the workgroup lists its hits in LDS,
+// reserves each brick's range with one atomic and writes the visits into it; hits
+// past the list's capacity, and grids of more than kVisitLdsBricks bricks, take
+// one global atomic each.)
+constexpr int kVisitItems = 8;
+constexpr int kVisitLdsBricks = 4096;  // bricks tallied in LDS (grids up to 256^3)
+constexpr int kVisitListCap = 1024;    // hits a workgroup lists in LDS (FILL)
 template <bool FILL>
 __global__ __launch_bounds__(256) void brick_visit_kernel(const float* __restrict__ q, const uint8_t* __restrict__ mask,
                                                           const double* __restrict__ rot, int n_pix, int n_rot,
                                                           int n_groups, int N, int nb, int* __restrict__ cnt,
                                                           const int64_t* __restrict__ off, int* __restrict__ visits) {
-  const int64_t wv = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  __shared__ int tally[kVisitLdsBricks];            // this workgroup's hits per brick (FILL: then its cursors)
+  __shared__ int base[FILL ? kVisitLdsBricks : 1];  // FILL: first slot of this workgroup's hits of each brick
+  __shared__ int2 hits[FILL ? kVisitListCap : 1];   // FILL: (brick, visit)
+  __shared__ int n_hits;
+  const int n_bricks = nb * nb * nb;
+  const bool local = n_bricks <= kVisitLdsBricks;
+  if (local)
+    for (int b = threadIdx.x; b < n_bricks; b += 256) tally[b] = 0;
+  if (threadIdx.x == 0) n_hits = 0;
+  __syncthreads();
+  auto direct = [&](int brick, int id) {  // one global atomic for this hit
+    const int slot = atomicAdd(cnt + brick, 1);
+    if constexpr (FILL)  // the counting pass found the same visits; the guard only bounds the write
+      if (off[brick] + slot < off[brick + 1]) visits[off[brick] + slot] = id;
+  };
+  const int64_t w0 = ((int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) * kVisitItems;
   const int lane = threadIdx.x & 63;
-  if (wv >= (int64_t)n_rot * n_groups) return;  // whole waves leave together
-  const int j = (int)(wv / n_groups), t = (int)(wv - (int64_t)j * n_groups);
-  const int i = t * kVisitPx + lane;
-  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
-  if (i < n_pix && mask[i]) {
-    double m[9];
-    load_rot(rot, j, m);
-    const Corner c = brick_corner(m, q[3 * (int64_t)i], q[3 * (int64_t)i + 1], q[3 * (int64_t)i + 2], 0.5 * N);
-    axis_bricks(c.bx, N, lo[0], hi[0]);
-    axis_bricks(c.by, N, lo[1], hi[1]);
-    axis_bricks(c.bz, N, lo[2], hi[2]);
-    if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2])  // no corner inside the grid
-      lo[0] = lo[1] = lo[2] = INT_MAX, hi[0] = hi[1] = hi[2] = INT_MIN;
-  }
-  const int x0 = wmin(lo[0]), y0 = wmin(lo[1]), z0 = wmin(lo[2]);
-  const int x1 = wmax(hi[0]), y1 = wmax(hi[1]), z1 = wmax(hi[2]);
-  if (x0 > x1) return;  // uniform: no used pixel reaches the grid
-  for (int bx = x0; bx <= x1; ++bx)
-    for (int by = y0; by <= y1; ++by)
-      for (int bz = z0; bz <= z1; ++bz) {
-        const bool hit = bx >= lo[0] && bx <= hi[0] && by >= lo[1] && by <= hi[1] && bz >= lo[2] && bz <= hi[2];
-        if (__ballot(hit) == 0) continue;
-        if (lane == 0) {
-          const int brick = (bx * nb + by) * nb + bz;
-          const int slot = atomicAdd(cnt + brick, 1);
-          if constexpr (FILL)  // the counting pass found the same visits; the guard only bounds the write
-            if (off[brick] + slot < off[brick + 1]) visits[off[brick] + slot] = j * n_groups + t;
+  const int64_t n_visits = (int64_t)n_rot * n_groups;
+  for (int u = 0; u < kVisitItems; ++u) {
+    const int64_t wv = w0 + u;
+    if (wv >= n_visits) break;  // whole waves leave the loop together
+    const int j = (int)(wv / n_groups), t = (int)(wv - (int64_t)j * n_groups);
+    const int i = t * kVisitPx + lane;
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+    if (i < n_pix && mask[i]) {
+      double m[9];
+      load_rot(rot, j, m);
+      const Corner c = brick_corner(m, q[3 * (int64_t)i], q[3 * (int64_t)i + 1], q[3 * (int64_t)i + 2], 0.5 * N);
+      axis_bricks(c.bx, N, lo[0], hi[0]);
+      axis_bricks(c.by, N, lo[1], hi[1]);
+      axis_bricks(c.bz, N, lo[2], hi[2]);
+      if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2])  // no corner inside the grid
+        lo[0] = lo[1] = lo[2] = INT_MAX, hi[0] = hi[1] = hi[2] = INT_MIN;
+    }
+    const int x0 = wmin(lo[0]), y0 = wmin(lo[1]), z0 = wmin(lo[2]);
+    const int x1 = wmax(hi[0]), y1 = wmax(hi[1]), z1 = wmax(hi[2]);
+    if (x0 > x1) continue;  // uniform: no used pixel reaches the grid
+    for (int bx = x0; bx <= x1; ++bx)
+      for (int by = y0; by <= y1; ++by)
+        for (int bz = z0; bz <= z1; ++bz) {
+          const bool hit = bx >= lo[0] && bx <= hi[0] && by >= lo[1] && by <= hi[1] && bz >= lo[2] && bz <= hi[2];
+          if (__ballot(hit) == 0) continue;
+          if (lane == 0) {
+            const int brick = (bx * nb + by) * nb + bz, id = j * n_groups + t;
+            if (!local) {
+              direct(brick, id);
+            } else if constexpr (!FILL) {
+              atomicAdd(&tally[brick], 1);
+            } else {
+              const int h = atomicAdd(&n_hits, 1);
+              if (h < kVisitListCap) {
+                hits[h] = make_int2(brick, id);
+                atomicAdd(&tally[brick], 1);
+              } else {
+                direct(brick, id);
+              }
+            }
+          }
         }
-      }
+  }
+  __syncthreads();
+  if (!local) return;  // uniform
+  if constexpr (!FILL) {
+    for (int b = threadIdx.x; b < n_bricks; b += 256)
+      if (tally[b] > 0) atomicAdd(cnt + b, tally[b]);
+  } else {
+    for (int b = threadIdx.x; b < n_bricks; b += 256) {
+      base[b] = tally[b] > 0 ? atomicAdd(cnt + b, tally[b]) : 0;
+      tally[b] = 0;  // the same thread read it: now this brick's local cursor
+    }
+    __syncthreads();
+    const int nh = n_hits < kVisitListCap ? n_hits : kVisitListCap;
+    for (int h = threadIdx.x; h < nh; h += 256) {
+      const int brick = hits[h].x;
+      const int slot = base[brick] + atomicAdd(&tally[brick], 1);
+      if (off[brick] + slot < off[brick + 1]) visits[off[brick] + slot] = hits[h].y;
+    }
+  }
 }
 
 // One workgroup per work item (brick, first visit, end visit).  Waves take the
@@ -262,7 +319,7 @@ hipError_t launch_brick_rot(const float* quat, int n_rot, double* rot, hipStream
 
 hipError_t launch_brick_visits(const float* q, const uint8_t* mask, const double* rot, int n_pix, int n_rot,
                                int n_groups, int N, int nb, int* cnt, const int64_t* off, int* visits, hipStream_t st) {
-  const int64_t waves = (int64_t)n_rot * n_groups;
+  const int64_t waves = ((int64_t)n_rot * n_groups + kVisitItems - 1) / kVisitItems;
   const unsigned blocks = (unsigned)((waves + 3) / 4);
   if (off)
     brick_visit_kernel<true><<<blocks, 256, 0, st>>>(q, mask, rot, n_pix, n_rot, n_groups, N, nb, cnt, off, visits);
