@@ -133,7 +133,7 @@ class Run:
         self.cur = 1 - self.cur
 
 
-def cpu_baseline(inp, n_rot_s=600, n_data_s=2000):
+def cpu_baseline(inp, n_rot_s=900, n_data_s=2000):
     """The FP64 oracle, as it stands, on a bounded sample of the same workload,
     scaled per stage to the full iteration (expansion and compression scale with
     Mrot, the contractions and the E-step with Mrot x Mdata)."""
