@@ -279,19 +279,34 @@ __global__ __launch_bounds__(kBrickWaves * 64) void brick_scatter_kernel(const i
         const Corner c = brick_corner(m, cur.qx, cur.qy, cur.qz, h);
         const double wn = cur.w;
         const int lx = c.bx - X0, ly = c.by - Y0, lz = c.bz - Z0;
+        // Each axis's two corners: inside this brick and inside the grid (a partial
+        // brick ends at N), and their weights.  A corner's weight is (wx * wy) * wz,
+        // the x-y products formed once for both z corners; its LDS slot is
+        // lds_slot(lx + dx, ly + dy, lz + dz) with the row and the z rotation split
+        // into a per-pixel part and compile-time corner offsets.  Corners of zero
+        // weight add zeros (the plan lists their brick all the same).
+        const bool vx[2] = {(unsigned)lx < (unsigned)kBrick && c.bx < N,
+                            (unsigned)(lx + 1) < (unsigned)kBrick && c.bx + 1 < N};
+        const bool vy[2] = {(unsigned)ly < (unsigned)kBrick && c.by < N,
+                            (unsigned)(ly + 1) < (unsigned)kBrick && c.by + 1 < N};
+        const bool vz[2] = {(unsigned)lz < (unsigned)kBrick && c.bz < N,
+                            (unsigned)(lz + 1) < (unsigned)kBrick && c.bz + 1 < N};
+        const double wx[2] = {1.0 - c.tx, c.tx}, wy[2] = {1.0 - c.ty, c.ty}, wz[2] = {1.0 - c.tz, c.tz};
+        const int rz = __mul24(lx, 13) + __mul24(ly, 7) + lz, par = lx & 1;
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int dx = t >> 2, dy = (t >> 1) & 1, dz = t & 1;
-          const int ex = lx + dx, ey = ly + dy, ez = lz + dz;
-          if ((unsigned)ex >= (unsigned)kBrick || (unsigned)ey >= (unsigned)kBrick ||
-              (unsigned)ez >= (unsigned)kBrick)
-            continue;
-          if (X0 + ex >= N || Y0 + ey >= N || Z0 + ez >= N) continue;  // past the grid in a partial brick
-          const double f = (dx ? c.tx : 1.0 - c.tx) * (dy ? c.ty : 1.0 - c.ty) * (dz ? c.tz : 1.0 - c.tz);
-          if (f == 0.0) continue;
-          const int e = lds_slot(ex, ey, ez);
-          atomicAdd(s_num + e, f * wn);
-          atomicAdd(s_den + e, f * rj);
+        for (int a = 0; a < 4; ++a) {
+          const int dx = a >> 1, dy = a & 1;
+          if (!(vx[dx] && vy[dy])) continue;
+          const double wxy = wx[dx] * wy[dy];
+          const int row = ((lx + dx) * kBrick + ((ly + dy) ^ par ^ dx)) * kBrick;
+#pragma unroll
+          for (int dz = 0; dz < 2; ++dz) {
+            if (!vz[dz]) continue;
+            const double f = wxy * wz[dz];
+            const int e = row + ((rz + 13 * dx + 7 * dy + dz) & (kBrick - 1));
+            atomicAdd(s_num + e, f * wn);
+            atomicAdd(s_den + e, f * rj);
+          }
         }
       }
       cur = nxt;
